@@ -1,0 +1,254 @@
+"""CPU oracle for the SKIS hot path -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of ``bench.py``
+may import this package.  The product library (``paper_1709_03565_amd``) never imports,
+links or executes anything here, and this package never imports the product library.
+
+Contents
+  * ``skis_oracle.c``  plain C: Philox4x32-10, validation, prefix products (Eq. gamma_v),
+    integer root weights and alias table (Eq. probu), IIS sampling (Alg. 1), the CSR
+    sketch (Alg. 2), the node->samples transpose, the estimator (Eq. eq21) and the greedy
+    (Alg. 3).  Loaded here through ctypes.
+  * ``philox.py``      a pure-Python Philox4x32-10 (independent of the C one).
+  * ``tiny.py``        exact enumeration of live-edge graphs for graphs of <= 12 edges:
+    I(S) by its definition (Sec. 2.1) and the exact IIS sample distribution (Lemma 2).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "skis_oracle.c")
+_LIB = os.path.join(_HERE, "libskis_oracle.so")
+
+OK, EINVAL, ENOMEM, WDEGENERATE = 0, -1, -2, 1
+
+
+def build(force: bool = False) -> str:
+    """Compile the C oracle with gcc (no fast-math, no FP contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.run(
+            ["gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+             "-shared", "-pthread", "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"],
+            check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        L = ctypes.CDLL(build())
+        P = ctypes.c_void_p
+        i32, i64, u64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
+        L.ora_philox4x32_10.argtypes = [P, P, P]
+        L.ora_philox4x32_10.restype = None
+        L.ora_edge_coin.argtypes = [u64, u64, i64, ctypes.c_float]
+        L.ora_edge_coin.restype = ctypes.c_int
+        L.ora_validate.argtypes = [i32, i64, P, P, P]
+        L.ora_validate.restype = ctypes.c_int
+        L.ora_row_prefix.argtypes = [i32, P, P, P, P]
+        L.ora_row_prefix.restype = None
+        L.ora_gamma_total.argtypes = [i32, P]
+        L.ora_gamma_total.restype = f64
+        L.ora_root_shift.argtypes = [i32]
+        L.ora_root_shift.restype = ctypes.c_int
+        L.ora_root_weights.argtypes = [i32, P, P]
+        L.ora_root_weights.restype = u64
+        L.ora_alias_build.argtypes = [i32, P, u64, P, P]
+        L.ora_alias_build.restype = ctypes.c_int
+        L.ora_build.argtypes = [i32, i64, P, P, P, u64, u64, u64, ctypes.c_int, ctypes.c_int]
+        L.ora_build.restype = P
+        L.ora_sketch_status.argtypes = [P]
+        L.ora_sketch_status.restype = ctypes.c_int
+        L.ora_sketch_info.argtypes = [P, P, P, P, P, P]
+        L.ora_sketch_info.restype = None
+        L.ora_sketch_copy.argtypes = [P, P, P, P, P]
+        L.ora_sketch_copy.restype = None
+        L.ora_sketch_free.argtypes = [P]
+        L.ora_sketch_free.restype = None
+        L.ora_inverse.argtypes = [i32, u64, P, P, P, P]
+        L.ora_inverse.restype = None
+        L.ora_estimate.argtypes = [i32, u64, P, P, P, f64, i32, P, P, P, P]
+        L.ora_estimate.restype = ctypes.c_int
+        L.ora_greedy.argtypes = [i32, u64, P, P, P, f64, i32, P, P, P, P]
+        L.ora_greedy.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code):
+        super().__init__("oracle error %d" % code)
+        self.code = code
+
+
+# --------------------------------------------------------------------------------------
+# Thin wrappers.  Graphs are in-CSR: row_ptr[n+1] (int32), col[m] (int32, source u of
+# the edge u->v in row v), w[m] (float32).
+# --------------------------------------------------------------------------------------
+
+def philox4x32_10(ctr, key):
+    c = _c(ctr, np.uint32)
+    k = _c(key, np.uint32)
+    out = np.zeros(4, np.uint32)
+    lib().ora_philox4x32_10(_p(c), _p(k), _p(out))
+    return out
+
+
+def edge_coin(seed: int, j: int, e: int, w: float) -> bool:
+    return bool(lib().ora_edge_coin(seed, j, e, float(np.float32(w))))
+
+
+def validate(row_ptr, col, w) -> int:
+    row_ptr, col, w = _c(row_ptr, np.int32), _c(col, np.int32), _c(w, np.float32)
+    return lib().ora_validate(len(row_ptr) - 1, len(col), _p(row_ptr), _p(col), _p(w))
+
+
+def row_prefix(row_ptr, w):
+    """(P[m], q[n]) of Eq. (gamma_v) / Eq. (probn), sequential per row."""
+    row_ptr, w = _c(row_ptr, np.int32), _c(w, np.float32)
+    n = len(row_ptr) - 1
+    P = np.zeros(max(len(w), 1), np.float64)
+    q = np.zeros(n, np.float64)
+    lib().ora_row_prefix(n, _p(row_ptr), _p(w), _p(P), _p(q))
+    return P[:len(w)], q
+
+
+def gamma_total(q) -> float:
+    q = _c(q, np.float64)
+    return lib().ora_gamma_total(len(q), _p(q))
+
+
+def root_weights(q):
+    """(W[n] uint64, C, s): integer root weights ceil(gamma * 2^s)."""
+    q = _c(q, np.float64)
+    W = np.zeros(len(q), np.uint64)
+    C = lib().ora_root_weights(len(q), _p(q), _p(W))
+    return W, int(C), lib().ora_root_shift(len(q))
+
+
+def alias_build(W, C: int):
+    W = _c(W, np.uint64)
+    n = len(W)
+    thr = np.zeros(n, np.uint64)
+    alias = np.zeros(n, np.int32)
+    st = lib().ora_alias_build(n, _p(W), C, _p(thr), _p(alias))
+    if st:
+        raise OracleError(st)
+    return thr, alias
+
+
+class Sketch:
+    """Samples [j0, j1) of the SKIS sketch as a CSR hypergraph (plus per-sample root and
+    edges-probed count), with Gamma and the integer weight total C."""
+
+    def __init__(self, status, sample_ptr, nodes, roots, probed, Gamma, C, j0):
+        self.status = status
+        self.sample_ptr = sample_ptr
+        self.nodes = nodes
+        self.roots = roots
+        self.probed = probed
+        self.Gamma = Gamma
+        self.C = C
+        self.j0 = j0
+
+    @property
+    def T(self) -> int:
+        return len(self.sample_ptr) - 1
+
+    def sample(self, i: int) -> np.ndarray:
+        return self.nodes[self.sample_ptr[i]:self.sample_ptr[i + 1]]
+
+
+def build_sketch(row_ptr, col, w, seed: int, j0: int, j1: int, nthreads: int = 1,
+                 ris_mode: bool = False) -> Sketch:
+    row_ptr, col, w = _c(row_ptr, np.int32), _c(col, np.int32), _c(w, np.float32)
+    n, m = len(row_ptr) - 1, len(col)
+    L = lib()
+    h = L.ora_build(n, m, _p(row_ptr), _p(col), _p(w), seed, j0, j1, nthreads, int(ris_mode))
+    if not h:
+        raise OracleError(ENOMEM)
+    try:
+        st = L.ora_sketch_status(h)
+        if st < 0:
+            raise OracleError(st)
+        cnt, ent, ptot = ctypes.c_uint64(), ctypes.c_int64(), ctypes.c_uint64()
+        G, C = ctypes.c_double(), ctypes.c_uint64()
+        L.ora_sketch_info(h, ctypes.byref(cnt), ctypes.byref(ent), ctypes.byref(ptot),
+                          ctypes.byref(G), ctypes.byref(C))
+        sp = np.zeros(cnt.value + 1, np.int64)
+        nodes = np.zeros(max(ent.value, 1), np.int32)
+        roots = np.zeros(max(cnt.value, 1), np.int32)
+        probed = np.zeros(max(cnt.value, 1), np.uint64)
+        L.ora_sketch_copy(h, _p(sp), _p(nodes), _p(roots), _p(probed))
+        return Sketch(st, sp, nodes[:ent.value], roots[:cnt.value], probed[:cnt.value],
+                      G.value, C.value, j0)
+    finally:
+        L.ora_sketch_free(h)
+
+
+def inverse(n: int, sample_ptr, nodes):
+    sample_ptr, nodes = _c(sample_ptr, np.int64), _c(nodes, np.int32)
+    T = len(sample_ptr) - 1
+    node_ptr = np.zeros(n + 1, np.int64)
+    ns = np.zeros(max(len(nodes), 1), np.int32)
+    lib().ora_inverse(n, T, _p(sample_ptr), _p(nodes), _p(node_ptr), _p(ns))
+    return node_ptr, ns[:len(nodes)]
+
+
+def _sets_csr(sets):
+    set_ptr = np.zeros(len(sets) + 1, np.int64)
+    for i, s in enumerate(sets):
+        set_ptr[i + 1] = set_ptr[i] + len(s)
+    flat = np.concatenate([np.asarray(s, np.int32) for s in sets]) if sets else np.zeros(0, np.int32)
+    return set_ptr, flat.astype(np.int32)
+
+
+def estimate(n: int, sample_ptr, nodes, q, Gamma: float, sets=None, set_ptr=None, set_nodes=None):
+    """(cov[Q] uint64, est[Q] float64) by Eq. (eq21)."""
+    if sets is not None:
+        set_ptr, set_nodes = _sets_csr(sets)
+    set_ptr, set_nodes = _c(set_ptr, np.int64), _c(set_nodes, np.int32)
+    sample_ptr, nodes, q = _c(sample_ptr, np.int64), _c(nodes, np.int32), _c(q, np.float64)
+    Q = len(set_ptr) - 1
+    cov = np.zeros(max(Q, 1), np.uint64)
+    est = np.zeros(max(Q, 1), np.float64)
+    if len(set_nodes) == 0:
+        set_nodes = np.zeros(1, np.int32)
+    st = lib().ora_estimate(n, len(sample_ptr) - 1, _p(sample_ptr), _p(nodes), _p(q), Gamma, Q,
+                            _p(set_ptr), _p(set_nodes), _p(cov), _p(est))
+    if st:
+        raise OracleError(st)
+    return cov[:Q], est[:Q]
+
+
+def greedy(n: int, sample_ptr, nodes, q, Gamma: float, k: int):
+    """(seeds[k], marginal_cov[k], cov, est) of Alg. 3."""
+    sample_ptr, nodes, q = _c(sample_ptr, np.int64), _c(nodes, np.int32), _c(q, np.float64)
+    if len(nodes) == 0:
+        nodes = np.zeros(1, np.int32)
+    seeds = np.zeros(max(k, 1), np.int32)
+    marg = np.zeros(max(k, 1), np.uint64)
+    cov, est = ctypes.c_uint64(), ctypes.c_double()
+    st = lib().ora_greedy(n, len(sample_ptr) - 1, _p(sample_ptr), _p(nodes), _p(q), Gamma, k,
+                          _p(seeds), _p(marg), ctypes.byref(cov), ctypes.byref(est))
+    if st:
+        raise OracleError(st)
+    return seeds[:k], marg[:k], cov.value, est.value

@@ -1,0 +1,78 @@
+"""Pins of the canonical Philox4x32-10 stream (Salmon et al., SC'11): the pure-Python and
+C oracle implementations agree with each other and with rocRAND's host-callable engine,
+an implementation this project did not write."""
+import os
+import shutil
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import philox as pyphilox
+
+
+def _vectors(count, seed, c1_max=(1 << 30) - 1):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    v = rng.integers(0, 1 << 32, size=(count, 6), dtype=np.uint64)
+    v[:, 1] %= (c1_max + 1)
+    # structured corners: zero counter/key, all-ones words, small counters
+    extra = np.array([[0, 0, 0, 0, 0, 0],
+                      [0xFFFFFFFF, 0, 0xFFFFFFFF, 0xFFFFFFFF, 0xFFFFFFFF, 0xFFFFFFFF],
+                      [1, 0, 0, 2, 1, 0],
+                      [7, 5, 0, 1, 1, 0]], np.uint64)
+    return np.concatenate([extra, v])
+
+
+def test_python_matches_c_oracle():
+    for row in _vectors(3000, 11, c1_max=0xFFFFFFFF):
+        ctr, key = [int(x) for x in row[:4]], [int(x) for x in row[4:]]
+        assert tuple(int(x) for x in oracle.philox4x32_10(ctr, key)) == pyphilox.philox4x32_10(ctr, key)
+
+
+@pytest.mark.skipif(shutil.which("hipcc") is None, reason="hipcc not available")
+def test_matches_rocrand_engine():
+    vec = _vectors(2000, 12)
+    src = os.path.join(os.path.dirname(__file__), "rocrand_philox_check.cpp")
+    with tempfile.TemporaryDirectory() as d:
+        exe = os.path.join(d, "chk")
+        subprocess.run(["hipcc", "-O1", "-o", exe, src], check=True, capture_output=True)
+        inp = "\n".join(" ".join(str(int(x)) for x in r) for r in vec) + "\n"
+        out = subprocess.run([exe], input=inp, capture_output=True, text=True, check=True).stdout
+    got = [tuple(int(t) for t in line.split()) for line in out.strip().splitlines()]
+    assert len(got) == len(vec)
+    for row, g in zip(vec, got):
+        ctr, key = [int(x) for x in row[:4]], [int(x) for x in row[4:]]
+        assert pyphilox.philox4x32_10(ctr, key) == g
+        assert tuple(int(x) for x in oracle.philox4x32_10(ctr, key)) == g
+
+
+def test_output_words_look_uniform():
+    # 2^14 calls -> 65536 words; byte histogram chi-square (255 dof) and bit balance.
+    words = []
+    for i in range(1 << 14):
+        words.extend(oracle.philox4x32_10([i, 3, 0, 2], [1, 0]))
+    w = np.array(words, np.uint32)
+    b = np.frombuffer(w.tobytes(), np.uint8)
+    h = np.bincount(b, minlength=256)
+    e = len(b) / 256
+    chi2 = ((h - e) ** 2 / e).sum()
+    assert chi2 < 255 + 6 * np.sqrt(2 * 255)
+    bits = np.unpackbits(b).mean()
+    assert abs(bits - 0.5) < 5 * 0.5 / np.sqrt(len(b) * 8)
+
+
+def test_edge_coin_definition():
+    # live iff w >= 1 or the 64-bit word (X for even e, Y for odd e) < floor(w * 2^64)
+    rng = np.random.Generator(np.random.PCG64(5))
+    for _ in range(500):
+        seed, j, e = int(rng.integers(0, 1 << 40)), int(rng.integers(0, 1 << 33)), int(rng.integers(0, 1 << 31))
+        w = float(np.float32(rng.choice([0.0, 1.0, rng.random(), 1e-9, 0.5])))
+        word = pyphilox.edge_coin_word(seed, j, e)
+        want = w >= 1.0 or word < int(np.float64(w) * 2.0 ** 64)
+        assert oracle.edge_coin(seed, j, e, w) == want
+    # P(live) = w: frequency over many (j, e) for w = 0.3
+    hits = sum(oracle.edge_coin(1, j, 0, 0.3) for j in range(40000))
+    p = float(np.float32(0.3))
+    assert abs(hits / 40000 - p) < 5 * np.sqrt(p * (1 - p) / 40000)
