@@ -1,0 +1,198 @@
+"""Benchmark of the SKIS hot path on one MI355X.
+
+One step = the whole path over one synthetic workload with the graph already in HBM:
+build_sketch (preprocessing, roots, persistent sampler, compaction, inverse index), then
+estimates for 100 seed sets and a greedy max-cover with k = 100 on the sketch.
+value = samples per second over the timed steps (T samples per step).
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(T: int, entries: int, probed: int) -> int:
+    """Bytes the sampler must move: per sample the root record (20 B) and its result meta
+    (size 4 + offset 8 + probed 8 B); per node of R_j its row bounds (8 B) and its staged
+    id (4 B); per probed in-edge its (col, w) record (8 B)."""
+    return 40 * T + 12 * entries + 8 * probed
+
+
+def cpu_baseline(g, wl, sets, k, T):
+    import numpy as np
+
+    import oracle
+    threads = len(os.sched_getaffinity(0))
+    log("cpu baseline: oracle with %d threads" % threads)
+    t = time.perf_counter()
+    oracle.build_sketch(g.row_ptr, g.col, g.w, seed=1, j0=0, j1=1, nthreads=threads)
+    t_fixed = time.perf_counter() - t
+    # size the sample for roughly 15 s of sampling
+    n0 = 1 << 12
+    t = time.perf_counter()
+    oracle.build_sketch(g.row_ptr, g.col, g.w, seed=1, j0=0, j1=n0, nthreads=threads)
+    rate = n0 / max(time.perf_counter() - t - t_fixed, 1e-3)
+    Ns = int(min(max(rate * 15.0, 1 << 14), T))
+    Ns = 1 << int(math.log2(Ns))
+    t = time.perf_counter()
+    sk = oracle.build_sketch(g.row_ptr, g.col, g.w, seed=1, j0=0, j1=Ns, nthreads=threads)
+    t_build = time.perf_counter() - t
+    _, q = oracle.row_prefix(g.row_ptr, g.w)
+    set_ptr, set_nodes = sets
+    t = time.perf_counter()
+    oracle.inverse(g.n, sk.sample_ptr, sk.nodes)
+    oracle.estimate(g.n, sk.sample_ptr, sk.nodes, q, sk.Gamma, set_ptr=set_ptr, set_nodes=set_nodes)
+    oracle.greedy(g.n, sk.sample_ptr, sk.nodes, q, sk.Gamma, k)
+    t_query = time.perf_counter() - t
+    per_sample = max(t_build - t_fixed, 1e-9) / Ns
+    t_full = t_fixed + per_sample * T + t_query * (T / Ns)
+    log("cpu baseline: Ns=%d build %.2fs (fixed %.2fs) queries %.2fs -> %.3g samples/s" %
+        (Ns, t_build, t_fixed, t_query, T / t_full))
+    return {
+        "value": T / t_full,
+        "unit": "samples/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": ("oracle (C, %d threads) on sample ids [0, %d) of the same workload: preprocessing "
+                   "%.2f s once + %.3g s/sample sampling, plus inverse index, the 100 estimates and greedy "
+                   "k=%d on that sketch (%.2f s) scaled by T/%d; extrapolated to T=%d" %
+                   (threads, Ns, t_fixed, per_sample, k, t_query, Ns, T)),
+        "sampling_only_samples_per_s": 1.0 / per_sample,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="cl1m_wc")
+    ap.add_argument("--samples", type=int, default=0, help="override T (default: the workload's)")
+    ap.add_argument("--queries", type=int, default=100)
+    ap.add_argument("--k", type=int, default=100)
+    ap.add_argument("--slots", type=int, default=0)
+    ap.add_argument("--visited", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the sketch shards by sample id with no communication, "
+              "and this build runs and reports a single GPU (got --gpus %d)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1709_03565_amd import inputs, skis
+
+    wl = inputs.WORKLOADS[args.workload]
+    T = args.samples or wl["T"]
+    log("workload", args.workload, wl, "T", T)
+    t = time.perf_counter()
+    g = inputs.workload_graph(args.workload)
+    log("graph ready in %.1fs: n=%d m=%d" % (time.perf_counter() - t, g.n, g.m))
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    rp = torch.from_numpy(g.row_ptr).to(dev)
+    col = torch.from_numpy(g.col).to(dev)
+    w = torch.from_numpy(g.w).to(dev)
+    sets = inputs.random_sets(g.n, args.queries, 50, seed=7)
+    set_ptr_np, set_nodes_np = inputs.sets_to_csr(sets)
+    set_ptr = torch.from_numpy(set_ptr_np).to(dev)
+    set_nodes = torch.from_numpy(set_nodes_np).to(dev)
+    opts = {}
+    if args.slots:
+        opts["slots_per_block"] = args.slots
+    if args.visited:
+        opts["visited_threshold"] = args.visited
+    torch.cuda.synchronize()
+
+    def step():
+        sk = skis.build_sketch(rp, col, w, T, inputs.SAMPLE_SEED, **opts)
+        sk.estimate(set_ptr, set_nodes)
+        seeds, marg, cov, est = sk.greedy(args.k)
+        inf = sk.info()
+        sk.free()
+        return inf, cov, est
+
+    for i in range(args.warmup):
+        inf, cov, est = step()
+        log("warmup %d: %s" % (i, inf))
+    torch.cuda.synchronize()
+    infos = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        infos.append(step())
+        log("step %d done" % i)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    inf = infos[-1][0]
+    ms_step = elapsed * 1000.0 / args.steps
+    value = T * args.steps / elapsed
+    sampler_ms = sum(x[0].ms_tier0 + x[0].ms_tier1 for x in infos) / len(infos)
+    tier0_ms = sum(x[0].ms_tier0 for x in infos) / len(infos)
+    b_alg = algorithmic_bytes(T, inf.entries, inf.probed_total)
+    achieved = b_alg / (sampler_ms * 1e-3) / 1e9
+    stages = {k: round(sum(getattr(x[0], k) for x in infos) / len(infos), 3) for k in
+              ["ms_preprocess", "ms_roots", "ms_sample", "ms_tier0", "ms_tier1", "ms_compact", "ms_inverse"]}
+    line = {
+        "metric": "SKIS samples/s",
+        "value": value,
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64/f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "%s: directed Chung-Lu n=%d m=%d beta=%g, %s weights fp32, T=%d IIS samples, Philox seed %d; "
+                        "step = build_sketch + inverse index + %d estimates (|S| 1-50) + greedy k=%d"
+                        % (args.workload, g.n, g.m, wl["beta"], wl["model"].upper(), T, inputs.SAMPLE_SEED,
+                           args.queries, args.k),
+            "T": T, "n": g.n, "m": g.m,
+        },
+        "edges_probed_per_s": inf.probed_total * args.steps / elapsed,
+        "sampler_samples_per_s": T / (sampler_ms * 1e-3),
+        "entries": inf.entries,
+        "probed_total": inf.probed_total,
+        "deferred": inf.deferred,
+        "stages_ms": stages,
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_sample (LDS tier + global tier launches)",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "alg_bytes_per_launch": b_alg,
+            "launch_ms": sampler_ms,
+            "tier0_ms": tier0_ms,
+        },
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(g, wl, (set_ptr_np, set_nodes_np), args.k, T)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,167 @@
+/*
+ * skis.h -- C ABI of libskis: the SKIS hot path (importance sketching of influence
+ * dynamics; Nguyen, Thai, Dinh, ICDM 2017) on AMD Instinct MI355X (gfx950).
+ *
+ * Problem statement (Sec. 2, Definitions 1 and 2): given a probabilistic graph G=(V,E,w)
+ * under the independent cascade model, estimate the influence I(S) of seed sets S
+ * (influence estimation) and find k seeds of large influence (influence maximisation).
+ * The library builds a sketch R = {R_1..R_T} of non-singular reverse-reachable samples
+ * drawn by IIS (Alg. 1), keeps it on the device as a CSR hypergraph plus its transpose
+ * (Alg. 2, preprocessing), and answers estimate queries by Eq. (eq21) and k-seed queries
+ * by the greedy of Alg. 3.
+ *
+ * Conventions for every entry point
+ *   - Pointers are DEVICE pointers unless the comment says "host".
+ *   - Every call takes a hipStream_t and is ordered on it.  Calls that return results in
+ *     host memory (marked "blocking") synchronise that stream before returning.
+ *   - Return value: SKIS_OK (0), a positive warning, or a negative error code.  On error
+ *     nothing is allocated or leaked, output buffers may be partly written, and
+ *     skis_last_error() returns a message (thread-local, valid until the next call on
+ *     the same thread).
+ *   - Graph layout (in-CSR): row v lists the in-edges u->v of v.  row_ptr[n+1] int32,
+ *     row_ptr[0] = 0, row_ptr[n] = m, nondecreasing; col[m] int32 holds the source u of
+ *     each in-edge, u in [0,n), u != v; w[m] float32 in [0,1] is the edge probability.
+ *     The order of edges within a row is the "fixed order" of N_in(v) in Sec. 3.1
+ *     (component 3); it changes which sample a given seed produces, not the distribution.
+ *     Repeated (u,v) pairs are independent edges.  The edge id of an in-edge is its
+ *     position in col.
+ *   - Randomness: sample j of a sketch is a pure function of (graph, seed, j) through a
+ *     counter-based Philox4x32-10 stream (Salmon et al., SC'11), so results do not depend
+ *     on launch shape, scheduling or the form of the sampler.
+ */
+#ifndef SKIS_H
+#define SKIS_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SKIS_OK 0
+#define SKIS_WDEGENERATE 1 /* warning: Gamma = 0, no non-singular sample exists; empty sketch */
+#define SKIS_EINVAL (-1)   /* invalid argument or malformed graph */
+#define SKIS_ENOMEM (-2)   /* device allocation failed or max_device_bytes exceeded */
+#define SKIS_EHIP (-3)     /* a HIP runtime call failed */
+
+typedef struct skis_sketch skis_sketch; /* opaque; owns every device buffer it allocates */
+
+/* Sampler and memory knobs.  Zero fields mean "default"; skis_default_options fills them. */
+typedef struct skis_options {
+    uint32_t form;                /* 0: persistent sampler (default); 1: plain form, one launch per BFS level */
+    uint32_t slots_per_block;     /* samples in flight per workgroup of the persistent sampler: 8, 16 or 32 */
+    uint32_t visited_threshold;   /* nodes per sample kept in LDS before the sample moves to the
+                                     global-memory tier: 128, 256 or 512 */
+    uint32_t big_row;             /* in-degree above which a sample moves to the global tier */
+    uint32_t build_inverse_index; /* 1 (default): build node->samples for estimate / greedy; 0: build only */
+    uint32_t reserved0;
+    uint64_t max_device_bytes;    /* 0 = unlimited; larger total allocation -> SKIS_ENOMEM */
+    uint64_t staging_entries;     /* initial staging capacity in node entries (0 = auto) */
+} skis_options;
+
+/* Fills *opt with the defaults. */
+void skis_default_options(skis_options *opt);
+
+/*
+ * Preprocessing alone (rows a1-a3 of the hot path), into caller buffers:
+ *   Eq. (gamma_v):  P[e] = prod of (1 - w) over row v up to and including edge e, in row
+ *                   order, fp64, one rounding per product (the bucket masses of
+ *                   Eq. probn are P[e-1] - P[e] / gamma_v);  q[v] = P of the last edge of
+ *                   row v (1 for an empty row) = 1 - gamma_v.
+ *   Eq. (probu):    root weights W[v] = ceil(gamma_v * 2^s), s = 62 - ceil(log2 n), so the
+ *                   root is v with probability W[v]/C, C = sum W (*C_out, host);
+ *                   Gamma = sum_v gamma_v, exactly rounded (*Gamma_out, host);
+ *                   alias table (thr[v] uint64, alias[v] int32): a bucket b drawn
+ *                   uniformly and r uniform in [0,C) give v = (r < thr[b]) ? b : alias[b].
+ *                   The table is the unique one produced by the sequential sweep: light
+ *                   nodes (n*W <= C) in id order are filled from the current heavy node
+ *                   (heavy nodes in id order), and a heavy node whose remainder falls to
+ *                   <= C becomes a bucket at once, filled from the next heavy node.
+ * Any output pointer may be NULL.  Blocking.  Errors: SKIS_EINVAL for a malformed graph.
+ */
+int skis_preprocess(int32_t n, int64_t m, const int32_t *row_ptr, const int32_t *col, const float *w,
+                    double *P, double *q, uint64_t *W, uint64_t *thr, int32_t *alias,
+                    uint64_t *C_out /* host */, double *Gamma_out /* host */, hipStream_t stream);
+
+/*
+ * Builds the sketch of num_samples IIS samples (Alg. 1 repeated, Alg. 2 preprocessing).
+ * Sample j (0 <= j < num_samples) draws its root by the alias table, its first live
+ * in-edge i* by Eq. (probn) (theta = U * gamma_root, i* = first edge with 1-P[e] > theta),
+ * flips independent coins for the root's later in-edges (earlier ones are dead by the
+ * bucket definition), then runs the reverse BFS of Alg. 1 lines 7-11.  Each R_j is stored
+ * sorted ascending; the sketch also keeps root[j], probed[j] = sum_{x in R_j} indeg(x),
+ * q[v] and Gamma.  Inputs are borrowed for the duration of the call only.
+ * opt (host) may be NULL.  Blocking.  *out (host) receives the sketch.
+ * Errors: SKIS_EINVAL (malformed graph, num_samples = 0, n <= 0, m < 0 or m >= 2^31),
+ * SKIS_ENOMEM, SKIS_EHIP.  Returns SKIS_WDEGENERATE (and an empty sketch) when Gamma = 0.
+ */
+int skis_build_sketch(int32_t n, int64_t m, const int32_t *row_ptr, const int32_t *col, const float *w,
+                      uint64_t num_samples, uint64_t seed, const skis_options *opt, hipStream_t stream,
+                      skis_sketch **out);
+
+typedef struct skis_info {
+    int32_t n;
+    int32_t reserved;
+    uint64_t T;                  /* samples in the sketch (0 when degenerate) */
+    uint64_t entries;            /* sum_j |R_j| */
+    uint64_t probed_total;       /* sum_j probed[j] (edges probed) */
+    uint64_t deferred;           /* samples that ran in the global-memory tier */
+    uint64_t C;                  /* integer root-weight total */
+    double Gamma;                /* sum of gamma_v */
+    uint64_t device_bytes;       /* bytes the sketch holds on the device */
+    double ms_preprocess, ms_roots, ms_sample, ms_compact, ms_inverse; /* stage times (events) */
+    double ms_tier0, ms_tier1;   /* the LDS-tier and global-tier sampler launches alone */
+} skis_info;
+
+/* Sketch facts (host out-param). */
+int skis_sketch_info(const skis_sketch *sk, skis_info *info /* host */);
+
+/*
+ * Estimates of Eq. (eq21) for Q seed sets given in CSR form: set i is
+ * set_nodes[set_ptr[i] .. set_ptr[i+1]) (device buffers; set_ptr int64[Q+1]).
+ * Duplicate ids in a set count once; an empty set gives cov 0 and est 0.
+ *   cov[i] = Cov(S_i) = #{ j : R_j meets S_i }                     (uint64, exact)
+ *   est[i] = fl(fl(cov * Gamma) / T) + sum_{v in S_i} q_v            (fp64; the sum is
+ *            compensated, so est agrees with an exactly rounded sum to ~1e-15 relative)
+ * For a degenerate sketch (T = 0) the first term is 0.  A set may hold at most 4096
+ * entries (duplicates included).  Blocking.
+ * Errors: SKIS_EINVAL (node id out of range, set_ptr not nondecreasing, a set above 4096
+ * entries, Q < 0, sketch built without the inverse index).
+ */
+int skis_estimate(const skis_sketch *sk, int32_t num_sets, const int64_t *set_ptr, const int32_t *set_nodes,
+                  uint64_t *cov, double *est, hipStream_t stream);
+
+/*
+ * Greedy max-cover of Alg. 3: k rounds, each adding the node v outside the current set
+ * with the largest gain fl(fl(Delta(v) * Gamma) / T) + q_v (Eq. margin), Delta(v) being
+ * the number of samples containing v not yet covered; ties go to the smallest id.
+ * seeds[k] int32 and marg[k] uint64 (Delta of each pick) are device buffers; *cov_out
+ * and *est_out (host) receive Cov and I_hat of the final set (Eq. eq21).  Blocking.
+ * Errors: SKIS_EINVAL (k < 1 or k > n, sketch built without the inverse index).
+ */
+int skis_greedy_max_cover(const skis_sketch *sk, int32_t k, int32_t *seeds, uint64_t *marg,
+                          uint64_t *cov_out /* host */, double *est_out /* host */, hipStream_t stream);
+
+/* Copies the sketch into caller buffers: sample_ptr int64[T+1], nodes int32[entries],
+ * roots int32[T], probed uint64[T].  Any pointer may be NULL. */
+int skis_sketch_export(const skis_sketch *sk, int64_t *sample_ptr, int32_t *nodes, int32_t *roots,
+                       uint64_t *probed, hipStream_t stream);
+
+/* Copies the node->samples transpose: node_ptr int64[n+1] and node_samples int32[entries]
+ * (each list holds the ids j with v in R_j, in no particular order).  Either may be NULL. */
+int skis_inverse_export(const skis_sketch *sk, int64_t *node_ptr, int32_t *node_samples, hipStream_t stream);
+
+/* Copies q[v] = 1 - gamma_v (fp64, n entries). */
+int skis_node_q(const skis_sketch *sk, double *q, hipStream_t stream);
+
+/* Frees the sketch and every device buffer it owns (NULL is a no-op). */
+void skis_sketch_free(skis_sketch *sk);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char *skis_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SKIS_H */

@@ -1,0 +1,323 @@
+// skis_api.cpp -- the extern "C" entry points of libskis (declared in include/skis.h):
+// argument checks, allocation accounting, error reporting and the order of the stages.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <new>
+
+#include "skis_internal.h"
+#include "skis_query.h"
+
+struct skis_sketch {
+    skis::Sketch core;
+    skis::QueryScratch qs;
+    std::mutex mu;
+};
+
+namespace skis {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+const std::string &get_error() { return g_err; }
+
+void *Arena::alloc(size_t bytes)
+{
+    if (cap && used + bytes > cap)
+        throw Error{SKIS_ENOMEM, "max_device_bytes exceeded: " + std::to_string(used + bytes) + " > " +
+                                     std::to_string(cap)};
+    void *p = nullptr;
+    const hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error{SKIS_ENOMEM, "hipMalloc(" + std::to_string(bytes) + ") failed: " + hipGetErrorString(e)};
+    }
+    used += bytes;
+    peak = std::max(peak, used);
+    return p;
+}
+
+void Arena::release(void *p, size_t bytes)
+{
+    (void)hipFree(p);
+    used -= bytes;
+}
+
+int device_cu_count()
+{
+    static thread_local int cached_dev = -1, cached_cus = 0;
+    int d = 0;
+    if (hipGetDevice(&d) != hipSuccess) return 1;
+    if (d != cached_dev) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, d) != hipSuccess || cus < 1) cus = 1;
+        cached_cus = cus;
+        cached_dev = d;
+    }
+    return cached_cus;
+}
+
+} // namespace skis
+
+template <class F>
+static int guarded(F &&f)
+{
+    try {
+        skis::set_error("");
+        return f();
+    } catch (const skis::Error &e) {
+        skis::set_error(e.msg);
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        skis::set_error("host allocation failed");
+        return SKIS_ENOMEM;
+    } catch (const std::exception &e) {
+        skis::set_error(e.what());
+        return SKIS_EHIP;
+    }
+}
+
+static void check_graph_args(int32_t n, int64_t m, const int32_t *row_ptr, const int32_t *col, const float *w)
+{
+    if (n <= 0) throw skis::Error{SKIS_EINVAL, "n must be positive"};
+    if (m < 0 || m > (int64_t)INT32_MAX) throw skis::Error{SKIS_EINVAL, "m must be in [0, 2^31)"};
+    if (!row_ptr || (m > 0 && (!col || !w))) throw skis::Error{SKIS_EINVAL, "graph pointers must not be NULL"};
+}
+
+extern "C" {
+
+void skis_default_options(skis_options *opt)
+{
+    if (!opt) return;
+    std::memset(opt, 0, sizeof(*opt));
+    opt->form = 0;
+    opt->slots_per_block = 32;
+    opt->visited_threshold = 128;
+    opt->big_row = 16384;
+    opt->build_inverse_index = 1;
+    opt->max_device_bytes = 0;
+    opt->staging_entries = 0;
+}
+
+int skis_preprocess(int32_t n, int64_t m, const int32_t *row_ptr, const int32_t *col, const float *w, double *P,
+                    double *q, uint64_t *W, uint64_t *thr, int32_t *alias, uint64_t *C_out, double *Gamma_out,
+                    hipStream_t stream)
+{
+    return guarded([&]() -> int {
+        check_graph_args(n, m, row_ptr, col, w);
+        skis::Arena arena;
+        skis::Prep prep;
+        skis::preprocess(arena, n, m, row_ptr, col, w, thr || alias, prep, stream);
+        if (P && m > 0)
+            SKIS_HIP_TRY(hipMemcpyAsync(P, prep.P.ptr, sizeof(double) * (size_t)m, hipMemcpyDeviceToDevice, stream));
+        if (q) SKIS_HIP_TRY(hipMemcpyAsync(q, prep.q.ptr, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, stream));
+        if (W) SKIS_HIP_TRY(hipMemcpyAsync(W, prep.W.ptr, sizeof(uint64_t) * (size_t)n, hipMemcpyDeviceToDevice, stream));
+        if (prep.C > 0) {
+            if (thr)
+                SKIS_HIP_TRY(hipMemcpy2DAsync(thr, sizeof(uint64_t), prep.alias.ptr, sizeof(skis::AliasEntry),
+                                              sizeof(uint64_t), (size_t)n, hipMemcpyDeviceToDevice, stream));
+            if (alias)
+                SKIS_HIP_TRY(hipMemcpy2DAsync(alias, sizeof(int32_t),
+                                              reinterpret_cast<const char *>(prep.alias.ptr) + sizeof(uint64_t),
+                                              sizeof(skis::AliasEntry), sizeof(int32_t), (size_t)n,
+                                              hipMemcpyDeviceToDevice, stream));
+        }
+        SKIS_HIP_TRY(hipStreamSynchronize(stream));
+        if (C_out) *C_out = prep.C;
+        if (Gamma_out) *Gamma_out = prep.Gamma;
+        return prep.C == 0 ? SKIS_WDEGENERATE : SKIS_OK;
+    });
+}
+
+int skis_build_sketch(int32_t n, int64_t m, const int32_t *row_ptr, const int32_t *col, const float *w,
+                      uint64_t num_samples, uint64_t seed, const skis_options *opt_in, hipStream_t stream,
+                      skis_sketch **out)
+{
+    return guarded([&]() -> int {
+        if (!out) throw skis::Error{SKIS_EINVAL, "out must not be NULL"};
+        *out = nullptr;
+        check_graph_args(n, m, row_ptr, col, w);
+        if (num_samples == 0) throw skis::Error{SKIS_EINVAL, "num_samples must be positive"};
+        skis_options opt;
+        skis_default_options(&opt);
+        if (opt_in) {
+            opt.form = opt_in->form;
+            if (opt_in->slots_per_block) opt.slots_per_block = opt_in->slots_per_block;
+            if (opt_in->visited_threshold) opt.visited_threshold = opt_in->visited_threshold;
+            if (opt_in->big_row) opt.big_row = opt_in->big_row;
+            opt.build_inverse_index = opt_in->build_inverse_index;
+            opt.max_device_bytes = opt_in->max_device_bytes;
+            opt.staging_entries = opt_in->staging_entries;
+        }
+        if (opt.form > 0) throw skis::Error{SKIS_EINVAL, "unknown sampler form"};
+        skis_sketch *h = new skis_sketch;
+        try {
+            skis::Sketch &sk = h->core;
+            sk.arena.cap = opt.max_device_bytes;
+            sk.n = n;
+            hipEvent_t e0, e1;
+            SKIS_HIP_TRY(hipEventCreate(&e0));
+            SKIS_HIP_TRY(hipEventCreate(&e1));
+            SKIS_HIP_TRY(hipEventRecord(e0, stream));
+            int status = SKIS_OK;
+            {
+                skis::Prep prep;
+                skis::preprocess(sk.arena, n, m, row_ptr, col, w, true, prep, stream);
+                SKIS_HIP_TRY(hipEventRecord(e1, stream));
+                SKIS_HIP_TRY(hipEventSynchronize(e1));
+                float ms = 0;
+                SKIS_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                sk.ms_preprocess = ms;
+                sk.Gamma = prep.Gamma;
+                sk.C = prep.C;
+                sk.q.swap(prep.q);
+                if (prep.C == 0) {
+                    status = SKIS_WDEGENERATE;
+                    sk.T = 0;
+                    sk.sample_ptr.alloc(sk.arena, 1);
+                    SKIS_HIP_TRY(hipMemsetAsync(sk.sample_ptr.ptr, 0, sizeof(int64_t), stream));
+                } else {
+                    skis::SampleConfig cfg;
+                    cfg.form = opt.form;
+                    cfg.slots = opt.slots_per_block;
+                    cfg.visited = opt.visited_threshold;
+                    cfg.big_row = opt.big_row;
+                    cfg.staging_entries = opt.staging_entries;
+                    skis::sample_and_compact(sk.arena, prep, n, m, num_samples, seed, cfg, sk, stream);
+                }
+            } // preprocessing buffers released here
+            if (opt.build_inverse_index) {
+                SKIS_HIP_TRY(hipEventRecord(e0, stream));
+                skis::build_inverse(sk, stream);
+                SKIS_HIP_TRY(hipEventRecord(e1, stream));
+                SKIS_HIP_TRY(hipEventSynchronize(e1));
+                float ms = 0;
+                SKIS_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                sk.ms_inverse = ms;
+            }
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            SKIS_HIP_TRY(hipStreamSynchronize(stream));
+            *out = h;
+            if (status == SKIS_WDEGENERATE) skis::set_error("Gamma = 0: no non-singular sample exists");
+            return status;
+        } catch (...) {
+            delete h;
+            throw;
+        }
+    });
+}
+
+int skis_sketch_info(const skis_sketch *h, skis_info *info)
+{
+    return guarded([&]() -> int {
+        if (!h || !info) throw skis::Error{SKIS_EINVAL, "NULL argument"};
+        const skis::Sketch &sk = h->core;
+        std::memset(info, 0, sizeof(*info));
+        info->n = sk.n;
+        info->T = sk.T;
+        info->entries = sk.entries;
+        info->probed_total = sk.probed_total;
+        info->deferred = sk.deferred;
+        info->C = sk.C;
+        info->Gamma = sk.Gamma;
+        info->device_bytes = sk.arena.used;
+        info->ms_preprocess = sk.ms_preprocess;
+        info->ms_roots = sk.ms_roots;
+        info->ms_sample = sk.ms_sample;
+        info->ms_compact = sk.ms_compact;
+        info->ms_inverse = sk.ms_inverse;
+        info->ms_tier0 = sk.ms_tier0;
+        info->ms_tier1 = sk.ms_tier1;
+        return SKIS_OK;
+    });
+}
+
+int skis_estimate(const skis_sketch *hc, int32_t num_sets, const int64_t *set_ptr, const int32_t *set_nodes,
+                  uint64_t *cov, double *est, hipStream_t stream)
+{
+    return guarded([&]() -> int {
+        if (!hc) throw skis::Error{SKIS_EINVAL, "NULL sketch"};
+        skis_sketch *h = const_cast<skis_sketch *>(hc);
+        if (num_sets < 0) throw skis::Error{SKIS_EINVAL, "num_sets must be >= 0"};
+        if (num_sets == 0) return SKIS_OK;
+        if (!set_ptr || !cov || !est) throw skis::Error{SKIS_EINVAL, "NULL argument"};
+        if (!h->core.has_inverse) throw skis::Error{SKIS_EINVAL, "sketch was built without the inverse index"};
+        std::lock_guard<std::mutex> lk(h->mu);
+        skis::estimate_batch(h->core, h->qs, num_sets, set_ptr, set_nodes, cov, est, stream);
+        return SKIS_OK;
+    });
+}
+
+int skis_greedy_max_cover(const skis_sketch *hc, int32_t k, int32_t *seeds, uint64_t *marg, uint64_t *cov_out,
+                          double *est_out, hipStream_t stream)
+{
+    return guarded([&]() -> int {
+        if (!hc) throw skis::Error{SKIS_EINVAL, "NULL sketch"};
+        skis_sketch *h = const_cast<skis_sketch *>(hc);
+        if (k < 1 || k > h->core.n) throw skis::Error{SKIS_EINVAL, "k must be in [1, n]"};
+        if (!seeds || !marg || !cov_out || !est_out) throw skis::Error{SKIS_EINVAL, "NULL argument"};
+        if (!h->core.has_inverse) throw skis::Error{SKIS_EINVAL, "sketch was built without the inverse index"};
+        std::lock_guard<std::mutex> lk(h->mu);
+        skis::greedy(h->core, h->qs, k, seeds, marg, cov_out, est_out, stream);
+        return SKIS_OK;
+    });
+}
+
+int skis_sketch_export(const skis_sketch *h, int64_t *sample_ptr, int32_t *nodes, int32_t *roots, uint64_t *probed,
+                       hipStream_t stream)
+{
+    return guarded([&]() -> int {
+        if (!h) throw skis::Error{SKIS_EINVAL, "NULL sketch"};
+        const skis::Sketch &sk = h->core;
+        if (sample_ptr)
+            SKIS_HIP_TRY(hipMemcpyAsync(sample_ptr, sk.sample_ptr.ptr, sizeof(int64_t) * (sk.T + 1),
+                                        hipMemcpyDeviceToDevice, stream));
+        if (nodes && sk.entries)
+            SKIS_HIP_TRY(hipMemcpyAsync(nodes, sk.nodes.ptr, sizeof(int32_t) * sk.entries, hipMemcpyDeviceToDevice,
+                                        stream));
+        if (roots && sk.T)
+            SKIS_HIP_TRY(hipMemcpyAsync(roots, sk.roots.ptr, sizeof(int32_t) * sk.T, hipMemcpyDeviceToDevice, stream));
+        if (probed && sk.T)
+            SKIS_HIP_TRY(hipMemcpyAsync(probed, sk.probed.ptr, sizeof(uint64_t) * sk.T, hipMemcpyDeviceToDevice,
+                                        stream));
+        SKIS_HIP_TRY(hipStreamSynchronize(stream));
+        return SKIS_OK;
+    });
+}
+
+int skis_inverse_export(const skis_sketch *h, int64_t *node_ptr, int32_t *node_samples, hipStream_t stream)
+{
+    return guarded([&]() -> int {
+        if (!h) throw skis::Error{SKIS_EINVAL, "NULL sketch"};
+        const skis::Sketch &sk = h->core;
+        if (!sk.has_inverse) throw skis::Error{SKIS_EINVAL, "sketch was built without the inverse index"};
+        if (node_ptr)
+            SKIS_HIP_TRY(hipMemcpyAsync(node_ptr, sk.node_ptr.ptr, sizeof(int64_t) * ((size_t)sk.n + 1),
+                                        hipMemcpyDeviceToDevice, stream));
+        if (node_samples && sk.entries)
+            SKIS_HIP_TRY(hipMemcpyAsync(node_samples, sk.node_samples.ptr, sizeof(int32_t) * sk.entries,
+                                        hipMemcpyDeviceToDevice, stream));
+        SKIS_HIP_TRY(hipStreamSynchronize(stream));
+        return SKIS_OK;
+    });
+}
+
+int skis_node_q(const skis_sketch *h, double *q, hipStream_t stream)
+{
+    return guarded([&]() -> int {
+        if (!h || !q) throw skis::Error{SKIS_EINVAL, "NULL argument"};
+        SKIS_HIP_TRY(hipMemcpyAsync(q, h->core.q.ptr, sizeof(double) * (size_t)h->core.n, hipMemcpyDeviceToDevice,
+                                    stream));
+        SKIS_HIP_TRY(hipStreamSynchronize(stream));
+        return SKIS_OK;
+    });
+}
+
+void skis_sketch_free(skis_sketch *h) { delete h; }
+
+const char *skis_last_error(void) { return skis::get_error().c_str(); }
+
+} // extern "C"

@@ -1,0 +1,132 @@
+// skis_device.h -- device helpers shared by the libskis HIP sources (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace skis {
+
+typedef unsigned __int128 u128;
+
+constexpr uint32_t TAG_ROOT = 0u;   // Philox tag: root draw
+constexpr uint32_t TAG_FIRST = 1u;  // Philox tag: first live in-edge of the root
+constexpr uint32_t TAG_EDGE = 2u;   // Philox tag: live-edge coins, two edges per call
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32->64-bit
+// multiplications with Weyl-bumped keys.  Returns the two 64-bit halves X = y1:y0 and
+// Y = y3:y2 of the output block for counter (c0, c1, c2, c3) and key (k0, k1).
+__device__ __forceinline__ void philox2x64(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                           uint32_t k0, uint32_t k1, uint64_t &X, uint64_t &Y)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    X = ((uint64_t)c1 << 32) | c0;
+    Y = ((uint64_t)c3 << 32) | c2;
+}
+
+// floor(w * 2^64) for a non-negative float w < 1 given by its bits, in integer arithmetic:
+// w = man * 2^(ex-150) for a normal number, so w * 2^64 = man * 2^(ex-86).
+__device__ __forceinline__ uint64_t coin_threshold(uint32_t wbits)
+{
+    const uint32_t ex = wbits >> 23;
+    if (ex == 0u) return 0ull; // zero or subnormal: below 2^-126, times 2^64 is < 1
+    const uint64_t man = (uint64_t)((wbits & 0x7FFFFFu) | 0x800000u);
+    if (ex >= 86u) return man << (ex - 86u);
+    const uint32_t sh = 86u - ex;
+    return sh >= 24u ? 0ull : (man >> sh);
+}
+
+// An edge of probability w (bits of a float in [0,1], +0 for zero) is live for a 64-bit
+// uniform word x iff w >= 1 or x < floor(w * 2^64): probability exactly w for w >= 2^-40.
+__device__ __forceinline__ bool coin_live(uint32_t wbits, uint64_t x)
+{
+    return wbits >= 0x3F800000u || x < coin_threshold(wbits);
+}
+
+// Alias-table entry: bucket b yields b when r < thr, else alias.
+struct __align__(16) AliasEntry {
+    uint64_t thr;
+    int32_t alias;
+    int32_t pad;
+};
+
+// Wave-level inclusive prefix sum over the 64 lanes.
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        T o = __shfl_up(v, d, 64);
+        if (lane >= d) v += o;
+    }
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v)
+{
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+// Block exclusive prefix sum of one value per thread.  `ws` is LDS scratch of at least
+// BLOCK/64 + 1 entries; the call contains two barriers and returns the block total in
+// *total.  Every thread of the block must call it.
+template <int BLOCK, typename T>
+__device__ __forceinline__ T block_excl_scan(T v, T *ws, T *total)
+{
+    constexpr int NW = BLOCK / 64;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    T inc = wave_incl_scan(v);
+    if (lane == 63) ws[wid] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        T acc = 0;
+        for (int i = 0; i < NW; ++i) {
+            T t = ws[i];
+            ws[i] = acc;
+            acc += t;
+        }
+        ws[NW] = acc;
+    }
+    __syncthreads();
+    *total = ws[NW];
+    return ws[wid] + inc - v;
+}
+
+// Round-to-nearest-even conversion of an unsigned 128-bit integer to binary64.
+__device__ __forceinline__ double u128_to_double(u128 x)
+{
+    if (x == 0) return 0.0;
+    const uint64_t hi = (uint64_t)(x >> 64);
+    const int lz = hi ? __clzll((long long)hi) : 64 + __clzll((long long)(uint64_t)x);
+    const int msb = 127 - lz;
+    if (msb <= 52) return (double)(uint64_t)x; // exact
+    const int sh = msb - 52;
+    uint64_t mant = (uint64_t)(x >> sh);
+    const u128 rem = x & (((u128)1 << sh) - 1);
+    const u128 half = (u128)1 << (sh - 1);
+    int e = sh;
+    if (rem > half || (rem == half && (mant & 1ull))) {
+        ++mant;
+        if (mant == (1ull << 53)) {
+            mant >>= 1;
+            ++e;
+        }
+    }
+    return ldexp((double)mant, e);
+}
+
+} // namespace skis

@@ -1,0 +1,150 @@
+// skis_internal.h -- host-side declarations shared by the libskis translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "skis.h"
+#include "skis_device.h"
+
+namespace skis {
+
+// ---------------------------------------------------------------------------------
+// Errors: every public entry point returns an int status and records a message.
+// ---------------------------------------------------------------------------------
+struct Error {
+    int code;
+    std::string msg;
+};
+
+void set_error(const std::string &msg);
+const std::string &get_error();
+
+#define SKIS_HIP_TRY(expr)                                                                        \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess)                                                                     \
+            throw ::skis::Error{SKIS_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)};    \
+    } while (0)
+
+// ---------------------------------------------------------------------------------
+// Device allocations, tracked against an optional byte cap.
+// ---------------------------------------------------------------------------------
+struct Arena {
+    uint64_t cap = 0;   // 0 = unlimited
+    uint64_t used = 0;  // bytes currently held
+    uint64_t peak = 0;
+    void *alloc(size_t bytes);
+    void release(void *p, size_t bytes);
+};
+
+template <typename T>
+struct DevBuf {
+    T *ptr = nullptr;
+    size_t count = 0;
+    Arena *arena = nullptr;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { reset(); }
+    void alloc(Arena &a, size_t n)
+    {
+        reset();
+        arena = &a;
+        count = n;
+        ptr = (T *)a.alloc(sizeof(T) * (n ? n : 1));
+    }
+    void reset()
+    {
+        if (ptr && arena) arena->release(ptr, sizeof(T) * (count ? count : 1));
+        ptr = nullptr;
+        count = 0;
+    }
+    size_t bytes() const { return sizeof(T) * count; }
+    void swap(DevBuf &o)
+    {
+        T *p = ptr;
+        size_t c = count;
+        Arena *a = arena;
+        ptr = o.ptr;
+        count = o.count;
+        arena = o.arena;
+        o.ptr = p;
+        o.count = c;
+        o.arena = a;
+    }
+};
+
+// ---------------------------------------------------------------------------------
+// The sketch object.
+// ---------------------------------------------------------------------------------
+struct Sketch {
+    Arena arena;
+    int32_t n = 0;
+    uint64_t T = 0;
+    uint64_t entries = 0;
+    uint64_t probed_total = 0;
+    uint64_t deferred = 0;
+    uint64_t C = 0;
+    double Gamma = 0.0;
+    bool has_inverse = false;
+    DevBuf<double> q;             // [n]
+    DevBuf<int64_t> sample_ptr;   // [T+1]
+    DevBuf<int32_t> nodes;        // [entries]
+    DevBuf<int32_t> roots;        // [T]
+    DevBuf<uint64_t> probed;      // [T]
+    DevBuf<int64_t> node_ptr;     // [n+1]
+    DevBuf<int32_t> node_samples; // [entries]
+    double ms_preprocess = 0, ms_roots = 0, ms_sample = 0, ms_compact = 0, ms_inverse = 0;
+    double ms_tier0 = 0, ms_tier1 = 0; // the two sampler launches alone
+};
+
+// ---------------------------------------------------------------------------------
+// Preprocessing (rows a1-a3).
+// ---------------------------------------------------------------------------------
+struct Prep {
+    DevBuf<int32_t> row_ptr;    // private copy [n+1]
+    DevBuf<uint2> edges;        // interleaved (col, w bits) per edge, padded to even length
+    DevBuf<double> P;           // [m]
+    DevBuf<double> q;           // [n]
+    DevBuf<uint64_t> W;         // [n]
+    DevBuf<AliasEntry> alias;   // [n]
+    uint64_t C = 0;
+    double Gamma = 0.0;
+};
+
+// Validates the graph, copies row_ptr, interleaves (col, w), computes P, q, W, C, Gamma and
+// (if build_alias) the alias table.  Throws Error on failure.
+void preprocess(Arena &arena, int32_t n, int64_t m, const int32_t *row_ptr, const int32_t *col,
+                const float *w, bool build_alias, Prep &out, hipStream_t s);
+
+// ---------------------------------------------------------------------------------
+// Sampling (rows a4-a7, a11) and compaction.
+// ---------------------------------------------------------------------------------
+struct SampleConfig {
+    uint32_t form = 0;
+    uint32_t slots = 32;
+    uint32_t visited = 256;
+    uint32_t big_row = 16384;
+    uint64_t staging_entries = 0;
+};
+
+void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, uint64_t T, uint64_t seed,
+                        const SampleConfig &cfg, Sketch &sk, hipStream_t s);
+
+void build_inverse(Sketch &sk, hipStream_t s);
+
+// ---------------------------------------------------------------------------------
+// Device-wide scans (exclusive), T in {uint32_t, uint64_t, int64_t, u128}.
+// ---------------------------------------------------------------------------------
+template <typename T>
+void excl_scan(Arena &arena, const T *in, T *out, int64_t n, T *d_total, hipStream_t s);
+void excl_scan_u32_to_i64(Arena &arena, const uint32_t *in, int64_t *out, int64_t n, int64_t *d_total,
+                          hipStream_t s);
+
+// Launch-shape helper: number of compute units of the current device.
+int device_cu_count();
+
+} // namespace skis

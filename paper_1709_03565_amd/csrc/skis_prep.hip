@@ -1,0 +1,302 @@
+// skis_prep.hip -- preprocessing for the root draw and the first live in-edge:
+// validation, per-row prefix products P and q (Eq. gamma_v / Eq. probn), integer root
+// weights W, the weight total C, Gamma (exactly rounded) and the alias table (Eq. probu).
+#include "skis_internal.h"
+
+namespace skis {
+
+enum : int { ERR_ROWPTR = 1, ERR_COL = 2, ERR_SELFLOOP = 4, ERR_WEIGHT = 8 };
+
+// One thread per row: validates the row, writes the interleaved (col, w) records and the
+// running products P[e] = P[e-1] * (1 - w[e]) in row order (one rounding each; the
+// build disables contraction, and __dmul_rn / __dsub_rn pin the operations), q[v] = last P.
+__global__ __launch_bounds__(256) void k_prep_rows(int32_t n, int64_t m, const int32_t *__restrict__ row_ptr,
+                                                   const int32_t *__restrict__ col, const float *__restrict__ w,
+                                                   int32_t *__restrict__ rp_copy, uint2 *__restrict__ edges,
+                                                   double *__restrict__ P, double *__restrict__ q, int *err)
+{
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t a = row_ptr[v], b = row_ptr[v + 1];
+        rp_copy[v] = a;
+        if (v == n - 1) rp_copy[n] = b;
+        int bad = 0;
+        if (v == 0 && a != 0) bad |= ERR_ROWPTR;
+        if (v == n - 1 && (int64_t)b != m) bad |= ERR_ROWPTR;
+        if (a < 0 || (int64_t)b > m || a > b) {
+            atomicOr(err, bad | ERR_ROWPTR);
+            q[v] = 1.0;
+            continue;
+        }
+        double prod = 1.0;
+        for (int32_t e = a; e < b; ++e) {
+            const int32_t u = col[e];
+            float wf = w[e];
+            if (u < 0 || u >= n) bad |= ERR_COL;
+            if (u == (int32_t)v) bad |= ERR_SELFLOOP;
+            if (!(wf >= 0.0f && wf <= 1.0f)) bad |= ERR_WEIGHT;
+            if (wf == 0.0f) wf = 0.0f; // -0 -> +0: the coin reads the bits
+            edges[e] = make_uint2((uint32_t)u, __float_as_uint(wf));
+            prod = __dmul_rn(prod, __dsub_rn(1.0, (double)wf));
+            P[e] = prod;
+        }
+        q[v] = prod;
+        if (bad) atomicOr(err, bad);
+    }
+}
+
+// W_v = ceil(gamma_v * 2^s) and k_v = gamma_v * 2^53 (an integer: gamma_v = 1 - q_v lies on
+// the grid 2^-53 Z because q_v is in [0,1]).  Per-block partial sums of W (u64) and k (u128).
+__global__ __launch_bounds__(256) void k_weights(int32_t n, int s_shift, const double *__restrict__ q,
+                                                 uint64_t *__restrict__ W, uint64_t *__restrict__ partW,
+                                                 u128 *__restrict__ partK)
+{
+    __shared__ uint64_t shW[4];
+    __shared__ uint64_t shKlo[4], shKhi[4];
+    uint64_t accW = 0;
+    u128 accK = 0;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const double g = __dsub_rn(1.0, q[v]);
+        const uint64_t k = (uint64_t)ldexp(g, 53);
+        uint64_t Wv;
+        if (k == 0) {
+            Wv = 0;
+        } else if (s_shift >= 53) {
+            Wv = k << (s_shift - 53);
+        } else {
+            const int d = 53 - s_shift;
+            Wv = (k + ((1ull << d) - 1)) >> d; // ceil(k / 2^d)
+        }
+        W[v] = Wv;
+        accW += Wv;
+        accK += (u128)k;
+    }
+    // block reduction (4 waves)
+    accW = wave_sum(accW);
+    uint64_t lo = (uint64_t)accK, hi = (uint64_t)(accK >> 64);
+    // 128-bit wave sum via two 64-bit halves with carry
+    for (int d = 32; d > 0; d >>= 1) {
+        uint64_t olo = __shfl_xor(lo, d, 64), ohi = __shfl_xor(hi, d, 64);
+        uint64_t nlo = lo + olo;
+        hi = hi + ohi + (nlo < lo ? 1ull : 0ull);
+        lo = nlo;
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+        shW[wid] = accW;
+        shKlo[wid] = lo;
+        shKhi[wid] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t sw = 0;
+        u128 sk = 0;
+        for (int i = 0; i < (int)(blockDim.x / 64); ++i) {
+            sw += shW[i];
+            sk += ((u128)shKhi[i] << 64) | shKlo[i];
+        }
+        partW[blockIdx.x] = sw;
+        partK[blockIdx.x] = sk;
+    }
+}
+
+struct PrepScalars {
+    uint64_t C;
+    double Gamma;
+};
+
+__global__ void k_weights_final(int nb, const uint64_t *partW, const u128 *partK, PrepScalars *out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    uint64_t C = 0;
+    u128 K = 0;
+    for (int i = 0; i < nb; ++i) {
+        C += partW[i];
+        K += partK[i];
+    }
+    out->C = C;
+    out->Gamma = ldexp(u128_to_double(K), -53);
+}
+
+// ---- alias table: the sequential sweep expressed by prefix sums -------------------------
+// Light nodes (a = n*W <= C) in id order have deficits d = C - a, heavy nodes surpluses
+// s = a - C.  With inclusive prefix sums D (over lights) and S (over heavies):
+//   light i:  thr = a, alias = heavy j with j = min{ j : S_j > D_{i-1} } (itself if none);
+//   heavy j:  thr = C + S_j - D_k with k = min{ k : D_k >= S_j }, alias = heavy j+1 (itself
+//             for the last heavy, whose thr is then C).
+// This reproduces the sweep exactly: the current heavy's remainder after light k is
+// C + S_j - D_k, and heavy j turns into a bucket at the first light that brings it to <= C.
+__global__ __launch_bounds__(256) void k_alias_flags(int32_t n, const uint64_t *__restrict__ W, uint64_t C,
+                                                     uint32_t *__restrict__ light)
+{
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        light[v] = ((uint64_t)n * W[v] <= C) ? 1u : 0u;
+}
+
+__global__ __launch_bounds__(256) void k_alias_split(int32_t n, const uint64_t *__restrict__ W, uint64_t C,
+                                                     const uint32_t *__restrict__ light,
+                                                     const uint32_t *__restrict__ lrank, int32_t *__restrict__ lid,
+                                                     int32_t *__restrict__ hid, u128 *__restrict__ dval,
+                                                     u128 *__restrict__ sval)
+{
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t a = (uint64_t)n * W[v];
+        const uint32_t lr = lrank[v];
+        if (light[v]) {
+            lid[lr] = (int32_t)v;
+            dval[lr] = (u128)(C - a);
+        } else {
+            const uint32_t hr = (uint32_t)v - lr;
+            hid[hr] = (int32_t)v;
+            sval[hr] = (u128)(a - C);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_add_inplace(int64_t len, u128 *__restrict__ excl, const u128 *__restrict__ val)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += (int64_t)gridDim.x * blockDim.x)
+        excl[i] += val[i];
+}
+
+__global__ __launch_bounds__(256) void k_alias_light(int32_t n, int64_t L, int64_t H, const uint64_t *__restrict__ W,
+                                                     const int32_t *__restrict__ lid, const int32_t *__restrict__ hid,
+                                                     const u128 *__restrict__ dval, const u128 *__restrict__ Dinc,
+                                                     const u128 *__restrict__ Sinc, AliasEntry *__restrict__ table)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < L; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t v = lid[i];
+        const u128 dex = Dinc[i] - dval[i];
+        int64_t lo = 0, hi = H; // first j with Sinc[j] > dex
+        while (lo < hi) {
+            int64_t mid = (lo + hi) >> 1;
+            if (Sinc[mid] > dex) hi = mid; else lo = mid + 1;
+        }
+        AliasEntry e;
+        e.thr = (uint64_t)n * W[v];
+        e.alias = lo < H ? hid[lo] : v;
+        e.pad = 0;
+        table[v] = e;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_alias_heavy(int64_t L, int64_t H, uint64_t C, const int32_t *__restrict__ hid,
+                                                     const u128 *__restrict__ Dinc, const u128 *__restrict__ Sinc,
+                                                     AliasEntry *__restrict__ table)
+{
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < H; j += (int64_t)gridDim.x * blockDim.x) {
+        const u128 Sj = Sinc[j];
+        int64_t lo = 0, hi = L; // first k with Dinc[k] >= Sj (exists: Sinc[H-1] == Dinc[L-1])
+        while (lo < hi) {
+            int64_t mid = (lo + hi) >> 1;
+            if (Dinc[mid] >= Sj) hi = mid; else lo = mid + 1;
+        }
+        const int64_t k = lo < L ? lo : L - 1;
+        AliasEntry e;
+        e.thr = (uint64_t)((u128)C + Sj - Dinc[k]);
+        e.alias = j + 1 < H ? hid[j + 1] : hid[j];
+        e.pad = 0;
+        table[hid[j]] = e;
+    }
+}
+
+static unsigned grid_for(int64_t items, int block = 256)
+{
+    int64_t g = (items + block - 1) / block;
+    int64_t cap = (int64_t)device_cu_count() * 16;
+    if (g > cap) g = cap;
+    return (unsigned)(g > 0 ? g : 1);
+}
+
+static int root_shift(int32_t n)
+{
+    int L = 0;
+    while ((1ll << L) < (int64_t)(n < 2 ? 2 : n)) ++L;
+    return 62 - L;
+}
+
+void preprocess(Arena &arena, int32_t n, int64_t m, const int32_t *row_ptr, const int32_t *col, const float *w,
+                bool build_alias, Prep &out, hipStream_t s)
+{
+    out.row_ptr.alloc(arena, (size_t)n + 1);
+    const size_t m_even = (size_t)(m + (m & 1));
+    out.edges.alloc(arena, m_even > 0 ? m_even : 2);
+    out.P.alloc(arena, (size_t)(m > 0 ? m : 1));
+    out.q.alloc(arena, (size_t)n);
+    out.W.alloc(arena, (size_t)n);
+    SKIS_HIP_TRY(hipMemsetAsync(out.edges.ptr, 0, out.edges.bytes(), s));
+    DevBuf<int> err;
+    err.alloc(arena, 1);
+    SKIS_HIP_TRY(hipMemsetAsync(err.ptr, 0, sizeof(int), s));
+    hipLaunchKernelGGL(k_prep_rows, dim3(grid_for(n)), dim3(256), 0, s, n, m, row_ptr, col, w, out.row_ptr.ptr,
+                       out.edges.ptr, out.P.ptr, out.q.ptr, err.ptr);
+    SKIS_HIP_TRY(hipGetLastError());
+    int herr = 0;
+    SKIS_HIP_TRY(hipMemcpyAsync(&herr, err.ptr, sizeof(int), hipMemcpyDeviceToHost, s));
+    SKIS_HIP_TRY(hipStreamSynchronize(s));
+    if (herr) {
+        std::string msg = "invalid graph:";
+        if (herr & ERR_ROWPTR) msg += " row_ptr must start at 0, end at m and be nondecreasing;";
+        if (herr & ERR_COL) msg += " col entries must lie in [0, n);";
+        if (herr & ERR_SELFLOOP) msg += " self-loops are not allowed;";
+        if (herr & ERR_WEIGHT) msg += " w must be in [0, 1] (no NaN);";
+        throw Error{SKIS_EINVAL, msg};
+    }
+    const unsigned gw = grid_for(n);
+    DevBuf<uint64_t> partW;
+    DevBuf<u128> partK;
+    DevBuf<PrepScalars> sc;
+    partW.alloc(arena, gw);
+    partK.alloc(arena, gw);
+    sc.alloc(arena, 1);
+    hipLaunchKernelGGL(k_weights, dim3(gw), dim3(256), 0, s, n, root_shift(n), out.q.ptr, out.W.ptr, partW.ptr,
+                       partK.ptr);
+    SKIS_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_weights_final, dim3(1), dim3(64), 0, s, (int)gw, partW.ptr, partK.ptr, sc.ptr);
+    SKIS_HIP_TRY(hipGetLastError());
+    PrepScalars hs;
+    SKIS_HIP_TRY(hipMemcpyAsync(&hs, sc.ptr, sizeof(hs), hipMemcpyDeviceToHost, s));
+    SKIS_HIP_TRY(hipStreamSynchronize(s));
+    out.C = hs.C;
+    out.Gamma = hs.Gamma;
+    if (!build_alias || out.C == 0) return;
+
+    out.alias.alloc(arena, (size_t)n);
+    DevBuf<uint32_t> light, lrank, Ltot;
+    DevBuf<int32_t> lid, hid;
+    DevBuf<u128> dval, sval, Dinc, Sinc;
+    light.alloc(arena, n);
+    lrank.alloc(arena, n);
+    Ltot.alloc(arena, 1);
+    lid.alloc(arena, n);
+    hid.alloc(arena, n);
+    dval.alloc(arena, n);
+    sval.alloc(arena, n);
+    Dinc.alloc(arena, n);
+    Sinc.alloc(arena, n);
+    hipLaunchKernelGGL(k_alias_flags, dim3(grid_for(n)), dim3(256), 0, s, n, out.W.ptr, out.C, light.ptr);
+    SKIS_HIP_TRY(hipGetLastError());
+    excl_scan<uint32_t>(arena, light.ptr, lrank.ptr, n, Ltot.ptr, s);
+    uint32_t hL = 0;
+    SKIS_HIP_TRY(hipMemcpyAsync(&hL, Ltot.ptr, sizeof(hL), hipMemcpyDeviceToHost, s));
+    SKIS_HIP_TRY(hipStreamSynchronize(s));
+    const int64_t L = hL, H = (int64_t)n - hL;
+    hipLaunchKernelGGL(k_alias_split, dim3(grid_for(n)), dim3(256), 0, s, n, out.W.ptr, out.C, light.ptr, lrank.ptr,
+                       lid.ptr, hid.ptr, dval.ptr, sval.ptr);
+    SKIS_HIP_TRY(hipGetLastError());
+    excl_scan<u128>(arena, dval.ptr, Dinc.ptr, L, nullptr, s);
+    excl_scan<u128>(arena, sval.ptr, Sinc.ptr, H, nullptr, s);
+    hipLaunchKernelGGL(k_add_inplace, dim3(grid_for(L)), dim3(256), 0, s, L, Dinc.ptr, dval.ptr);
+    hipLaunchKernelGGL(k_add_inplace, dim3(grid_for(H)), dim3(256), 0, s, H, Sinc.ptr, sval.ptr);
+    SKIS_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_alias_light, dim3(grid_for(L)), dim3(256), 0, s, n, L, H, out.W.ptr, lid.ptr, hid.ptr,
+                       dval.ptr, Dinc.ptr, Sinc.ptr, out.alias.ptr);
+    SKIS_HIP_TRY(hipGetLastError());
+    if (H > 0) {
+        hipLaunchKernelGGL(k_alias_heavy, dim3(grid_for(H)), dim3(256), 0, s, L, H, out.C, hid.ptr, Dinc.ptr,
+                           Sinc.ptr, out.alias.ptr);
+        SKIS_HIP_TRY(hipGetLastError());
+    }
+    SKIS_HIP_TRY(hipStreamSynchronize(s));
+}
+
+} // namespace skis

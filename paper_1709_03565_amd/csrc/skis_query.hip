@@ -1,0 +1,397 @@
+// skis_query.hip -- queries on the device-resident sketch:
+//   k_estimate   Eq. (eq21): Cov(S) by marking the samples of every v in S in a bitmap over
+//                the T samples (a sample counts once, when its bit first flips), and
+//                I_hat(S) = fl(fl(Cov * Gamma) / T) + sum_{v in S} q_v (compensated sum).
+//   k_argmax / k_cover_update   Alg. 3 with incremental Delta: pick the node of largest
+//                gain fl(fl(Delta * Gamma) / T) + q (Eq. margin), smallest id on ties, then
+//                lower Delta of every member of each sample the pick newly covers.
+#include "skis_internal.h"
+#include "skis_query.h"
+
+namespace skis {
+
+__device__ __forceinline__ void neumaier_add(double &s, double &c, double x)
+{
+    const double t = __dadd_rn(s, x);
+    if (fabs(s) >= fabs(x)) c = __dadd_rn(c, __dadd_rn(__dsub_rn(s, t), x));
+    else c = __dadd_rn(c, __dadd_rn(__dsub_rn(x, t), s));
+    s = t;
+}
+
+template <int NT>
+__device__ void bitonic_sort_lds(int32_t *buf, int P)
+{
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int d = k >> 1; d > 0; d >>= 1) {
+            for (int i = threadIdx.x; i < P; i += NT) {
+                const int ixj = i ^ d;
+                if (ixj > i) {
+                    const int32_t x = buf[i], y = buf[ixj];
+                    const bool asc = (i & k) == 0;
+                    if ((x > y) == asc) {
+                        buf[i] = y;
+                        buf[ixj] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// One workgroup per query of the batch [q0, q0 + gridDim.x).
+__global__ __launch_bounds__(EST_BLOCK) void k_estimate(int64_t q0, const int64_t *__restrict__ set_ptr,
+                                                        const int32_t *__restrict__ set_nodes, int32_t n, uint64_t T,
+                                                        double Gamma, const double *__restrict__ qv,
+                                                        const int64_t *__restrict__ node_ptr,
+                                                        const int32_t *__restrict__ node_samples,
+                                                        uint32_t *__restrict__ bitmaps, uint64_t wordsT,
+                                                        unsigned long long *__restrict__ cov_out,
+                                                        double *__restrict__ est_out, int *__restrict__ err)
+{
+    __shared__ int32_t buf[EST_MAX_SET];
+    __shared__ int64_t dbase[EST_MAX_SET + 1];
+    __shared__ int32_t s_scan[EST_BLOCK / 64 + 1];
+    __shared__ int64_t s_scan64[EST_BLOCK / 64 + 1];
+    __shared__ double ps[EST_BLOCK], pc[EST_BLOCK];
+    __shared__ unsigned long long s_cov[EST_BLOCK / 64];
+    __shared__ int s_bad;
+
+    const int64_t qi = q0 + blockIdx.x;
+    const int tid = threadIdx.x;
+    const int64_t a = set_ptr[qi], b = set_ptr[qi + 1];
+    const int64_t k = b - a;
+    if (tid == 0) s_bad = 0;
+    __syncthreads();
+    if (k < 0 || k > EST_MAX_SET) {
+        if (tid == 0) atomicOr(err, k < 0 ? 1 : 2);
+        return;
+    }
+    int P = 1;
+    while (P < k) P <<= 1;
+    for (int t = tid; t < P; t += EST_BLOCK) {
+        int32_t v = INT32_MAX;
+        if (t < k) {
+            v = set_nodes[a + t];
+            if (v < 0 || v >= n) {
+                s_bad = 1;
+                v = INT32_MAX;
+            }
+        }
+        buf[t] = v;
+    }
+    __syncthreads();
+    if (s_bad) {
+        if (tid == 0) atomicOr(err, 4);
+        return;
+    }
+    if (P > 1) bitonic_sort_lds<EST_BLOCK>(buf, P);
+
+    // distinct members, in ascending order, compacted to the front of buf
+    constexpr int IPT = EST_MAX_SET / EST_BLOCK;
+    int32_t mine[IPT];
+    int flags = 0, cntu = 0;
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+        const int t = tid * IPT + r;
+        const int32_t v = t < k ? buf[t] : INT32_MAX;
+        mine[r] = v;
+        const bool u = t < k && (t == 0 || buf[t - 1] != v);
+        flags |= (u ? 1 : 0) << r;
+        cntu += u ? 1 : 0;
+    }
+    int nu;
+    int pos = block_excl_scan<EST_BLOCK, int>(cntu, s_scan, &nu);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < IPT; ++r)
+        if (flags >> r & 1) buf[pos++] = mine[r];
+    __syncthreads();
+
+    // sum of q over distinct members: strided Neumaier, combined in thread order
+    double sq = 0.0, cq = 0.0;
+    for (int t = tid; t < nu; t += EST_BLOCK) neumaier_add(sq, cq, qv[buf[t]]);
+    ps[tid] = sq;
+    pc[tid] = cq;
+    // prefix of |H(v)| over distinct members
+    int64_t dl[IPT];
+    int64_t acc = 0;
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+        const int t = tid * IPT + r;
+        int64_t d = 0;
+        if (t < nu) {
+            const int32_t v = buf[t];
+            d = node_ptr[v + 1] - node_ptr[v];
+        }
+        dl[r] = acc;
+        acc += d;
+    }
+    int64_t E;
+    const int64_t ex = block_excl_scan<EST_BLOCK, int64_t>(acc, s_scan64, &E);
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+        const int t = tid * IPT + r;
+        if (t < nu) dbase[t] = ex + dl[r];
+    }
+    if (tid == 0) dbase[nu] = E;
+    __syncthreads();
+
+    uint32_t *bm = bitmaps + (uint64_t)blockIdx.x * wordsT;
+    unsigned long long local = 0;
+    for (int64_t idx = tid; idx < E; idx += EST_BLOCK) {
+        int lo = 0, hi = nu - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (dbase[mid] <= idx) lo = mid; else hi = mid - 1;
+        }
+        const int32_t v = buf[lo];
+        const int32_t j = node_samples[node_ptr[v] + (idx - dbase[lo])];
+        const uint32_t bit = 1u << (j & 31);
+        const uint32_t old = atomicOr(&bm[j >> 5], bit);
+        if (!(old & bit)) ++local;
+    }
+    local = wave_sum(local);
+    if ((tid & 63) == 0) s_cov[tid >> 6] = local;
+    __syncthreads();
+    if (tid == 0) {
+        unsigned long long c = 0;
+        for (int w = 0; w < EST_BLOCK / 64; ++w) c += s_cov[w];
+        double s = 0.0, cc = 0.0;
+        for (int t = 0; t < EST_BLOCK; ++t) {
+            neumaier_add(s, cc, ps[t]);
+            neumaier_add(s, cc, pc[t]);
+        }
+        const double first = T > 0 ? __ddiv_rn(__dmul_rn((double)c, Gamma), (double)T) : 0.0;
+        cov_out[qi] = c;
+        est_out[qi] = __dadd_rn(first, __dadd_rn(s, cc));
+    }
+    // leave the bitmap clear for the next query: walk the same entries again
+    __syncthreads();
+    for (int64_t idx = tid; idx < E; idx += EST_BLOCK) {
+        int lo = 0, hi = nu - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (dbase[mid] <= idx) lo = mid; else hi = mid - 1;
+        }
+        const int32_t v = buf[lo];
+        const int32_t j = node_samples[node_ptr[v] + (idx - dbase[lo])];
+        bm[j >> 5] = 0u;
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Greedy (Alg. 3).
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_greedy_init(int32_t n, const int64_t *__restrict__ node_ptr,
+                                                     int32_t *__restrict__ delta, uint8_t *__restrict__ chosen)
+{
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        delta[v] = (int32_t)(node_ptr[v + 1] - node_ptr[v]);
+        chosen[v] = 0;
+    }
+}
+
+__device__ __forceinline__ bool better(double g, int32_t v, double bg, int32_t bv)
+{
+    return bv < 0 || g > bg || (g == bg && v < bv);
+}
+
+__global__ __launch_bounds__(256) void k_argmax(int32_t n, uint64_t T, double Gamma, const int32_t *__restrict__ delta,
+                                                const double *__restrict__ qv, uint8_t *__restrict__ chosen,
+                                                double *__restrict__ part_g, int32_t *__restrict__ part_v,
+                                                GreedyState *__restrict__ st, int round, int32_t *__restrict__ seeds,
+                                                unsigned long long *__restrict__ marg)
+{
+    __shared__ double sg[256];
+    __shared__ int32_t sv[256];
+    __shared__ bool last;
+    double bg = 0.0;
+    int32_t bv = -1;
+    const double Td = (double)T;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        if (chosen[v]) continue;
+        const double g = __dadd_rn(T > 0 ? __ddiv_rn(__dmul_rn((double)delta[v], Gamma), Td) : 0.0, qv[v]);
+        if (better(g, (int32_t)v, bg, bv)) {
+            bg = g;
+            bv = (int32_t)v;
+        }
+    }
+    sg[threadIdx.x] = bg;
+    sv[threadIdx.x] = bv;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            const int o = threadIdx.x + w;
+            if (sv[o] >= 0 && better(sg[o], sv[o], sg[threadIdx.x], sv[threadIdx.x])) {
+                sg[threadIdx.x] = sg[o];
+                sv[threadIdx.x] = sv[o];
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part_g[blockIdx.x] = sg[0];
+        part_v[blockIdx.x] = sv[0];
+        __threadfence();
+        const unsigned ticket = atomicAdd(&st->done, 1u);
+        last = ticket == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    if (threadIdx.x == 0) {
+        double g = 0.0;
+        int32_t v = -1;
+        for (unsigned b = 0; b < gridDim.x; ++b) {
+            const int32_t pv = __hip_atomic_load(&part_v[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const double pg = __longlong_as_double((long long)__hip_atomic_load(
+                reinterpret_cast<unsigned long long *>(&part_g[b]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            if (pv >= 0 && better(pg, pv, g, v)) {
+                g = pg;
+                v = pv;
+            }
+        }
+        st->done = 0u;
+        st->vstar = v;
+        const int32_t d = delta[v];
+        seeds[round] = v;
+        marg[round] = (unsigned long long)d;
+        chosen[v] = 1;
+        st->cov += (unsigned long long)d;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_cover_update(const GreedyState *__restrict__ st,
+                                                      const int64_t *__restrict__ node_ptr,
+                                                      const int32_t *__restrict__ node_samples,
+                                                      const int64_t *__restrict__ sptr,
+                                                      const int32_t *__restrict__ nodes,
+                                                      uint32_t *__restrict__ covered, int32_t *__restrict__ delta)
+{
+    const int32_t v = st->vstar;
+    const int64_t a = node_ptr[v], b = node_ptr[v + 1];
+    for (int64_t p = a + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < b; p += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t j = node_samples[p];
+        const uint32_t bit = 1u << (j & 31);
+        const uint32_t old = atomicOr(&covered[j >> 5], bit);
+        if (old & bit) continue;
+        for (int64_t t = sptr[j]; t < sptr[j + 1]; ++t) atomicSub(&delta[nodes[t]], 1);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_greedy_final(int32_t n, uint64_t T, double Gamma,
+                                                      const uint8_t *__restrict__ chosen, const double *__restrict__ qv,
+                                                      GreedyState *__restrict__ st)
+{
+    __shared__ double ps[256], pc[256];
+    double s = 0.0, c = 0.0;
+    for (int64_t v = threadIdx.x; v < n; v += 256)
+        if (chosen[v]) neumaier_add(s, c, qv[v]);
+    ps[threadIdx.x] = s;
+    pc[threadIdx.x] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double ts = 0.0, tc = 0.0;
+        for (int t = 0; t < 256; ++t) {
+            neumaier_add(ts, tc, ps[t]);
+            neumaier_add(ts, tc, pc[t]);
+        }
+        const double first = T > 0 ? __ddiv_rn(__dmul_rn((double)st->cov, Gamma), (double)T) : 0.0;
+        st->est = __dadd_rn(first, __dadd_rn(ts, tc));
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_fill_q(uint64_t count, T *__restrict__ p, T v)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+static unsigned gridq(uint64_t items, int block, int per_cu = 8)
+{
+    uint64_t g = (items + block - 1) / block;
+    const uint64_t cap = (uint64_t)device_cu_count() * per_cu;
+    if (g > cap) g = cap;
+    return (unsigned)(g > 0 ? g : 1);
+}
+
+void estimate_batch(const Sketch &sk, QueryScratch &qs, int32_t Q, const int64_t *set_ptr, const int32_t *set_nodes,
+                    uint64_t *cov, double *est, hipStream_t s)
+{
+    const uint64_t wordsT = (sk.T + 31) / 32;
+    const uint64_t per = wordsT ? wordsT : 1;
+    // bitmaps for up to `batch` queries at a time, about 256 MiB
+    uint64_t batch = (256ull << 20) / (per * 4);
+    if (batch < 1) batch = 1;
+    if (batch > 4096) batch = 4096;
+    if (batch > (uint64_t)Q) batch = (uint64_t)Q;
+    if (qs.bitmap_words < batch * per) {
+        qs.bitmaps.alloc(const_cast<Arena &>(sk.arena), batch * per);
+        qs.bitmap_words = batch * per;
+        hipLaunchKernelGGL(k_fill_q<uint32_t>, dim3(gridq(batch * per, 256)), dim3(256), 0, s, batch * per,
+                           qs.bitmaps.ptr, 0u);
+        SKIS_HIP_TRY(hipGetLastError());
+    }
+    if (!qs.err.ptr) qs.err.alloc(const_cast<Arena &>(sk.arena), 1);
+    hipLaunchKernelGGL(k_fill_q<int>, dim3(1), dim3(64), 0, s, (uint64_t)1, qs.err.ptr, 0);
+    for (int64_t q0 = 0; q0 < Q; q0 += (int64_t)batch) {
+        const int64_t nq = (Q - q0) < (int64_t)batch ? (Q - q0) : (int64_t)batch;
+        hipLaunchKernelGGL(k_estimate, dim3((unsigned)nq), dim3(EST_BLOCK), 0, s, q0, set_ptr, set_nodes, sk.n, sk.T,
+                           sk.Gamma, sk.q.ptr, sk.node_ptr.ptr, sk.node_samples.ptr, qs.bitmaps.ptr, per,
+                           reinterpret_cast<unsigned long long *>(cov), est, qs.err.ptr);
+        SKIS_HIP_TRY(hipGetLastError());
+    }
+    int herr = 0;
+    SKIS_HIP_TRY(hipMemcpyAsync(&herr, qs.err.ptr, sizeof(int), hipMemcpyDeviceToHost, s));
+    SKIS_HIP_TRY(hipStreamSynchronize(s));
+    if (herr & 1) throw Error{SKIS_EINVAL, "set_ptr must be nondecreasing"};
+    if (herr & 2) throw Error{SKIS_EINVAL, "a seed set has more than 4096 entries"};
+    if (herr & 4) throw Error{SKIS_EINVAL, "a seed set holds a node id outside [0, n)"};
+}
+
+void greedy(const Sketch &sk, QueryScratch &qs, int32_t k, int32_t *seeds, uint64_t *marg, uint64_t *cov_out,
+            double *est_out, hipStream_t s)
+{
+    Arena &arena = const_cast<Arena &>(sk.arena);
+    const int32_t n = sk.n;
+    const uint64_t wordsT = (sk.T + 31) / 32;
+    DevBuf<int32_t> delta;
+    DevBuf<uint8_t> chosen;
+    DevBuf<uint32_t> covered;
+    DevBuf<GreedyState> st;
+    const unsigned ga = gridq(n, 256, 4);
+    DevBuf<double> pg;
+    DevBuf<int32_t> pv;
+    delta.alloc(arena, n);
+    chosen.alloc(arena, n);
+    covered.alloc(arena, wordsT ? wordsT : 1);
+    st.alloc(arena, 1);
+    pg.alloc(arena, ga);
+    pv.alloc(arena, ga);
+    hipLaunchKernelGGL(k_greedy_init, dim3(gridq(n, 256)), dim3(256), 0, s, n, sk.node_ptr.ptr, delta.ptr, chosen.ptr);
+    hipLaunchKernelGGL(k_fill_q<uint32_t>, dim3(gridq(wordsT ? wordsT : 1, 256)), dim3(256), 0, s,
+                       wordsT ? wordsT : 1, covered.ptr, 0u);
+    hipLaunchKernelGGL(k_fill_q<unsigned char>, dim3(1), dim3(64), 0, s, (uint64_t)sizeof(GreedyState),
+                       reinterpret_cast<unsigned char *>(st.ptr), (unsigned char)0);
+    SKIS_HIP_TRY(hipGetLastError());
+    const unsigned gu = (unsigned)device_cu_count() * 4;
+    for (int32_t r = 0; r < k; ++r) {
+        hipLaunchKernelGGL(k_argmax, dim3(ga), dim3(256), 0, s, n, sk.T, sk.Gamma, delta.ptr, sk.q.ptr, chosen.ptr,
+                           pg.ptr, pv.ptr, st.ptr, (int)r, seeds, reinterpret_cast<unsigned long long *>(marg));
+        if (sk.T)
+            hipLaunchKernelGGL(k_cover_update, dim3(gu), dim3(256), 0, s, st.ptr, sk.node_ptr.ptr,
+                               sk.node_samples.ptr, sk.sample_ptr.ptr, sk.nodes.ptr, covered.ptr, delta.ptr);
+    }
+    SKIS_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_greedy_final, dim3(1), dim3(256), 0, s, n, sk.T, sk.Gamma, chosen.ptr, sk.q.ptr, st.ptr);
+    SKIS_HIP_TRY(hipGetLastError());
+    GreedyState hs;
+    SKIS_HIP_TRY(hipMemcpyAsync(&hs, st.ptr, sizeof(hs), hipMemcpyDeviceToHost, s));
+    SKIS_HIP_TRY(hipStreamSynchronize(s));
+    *cov_out = hs.cov;
+    *est_out = hs.est;
+}
+
+} // namespace skis

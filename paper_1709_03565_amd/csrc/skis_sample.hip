@@ -1,0 +1,810 @@
+// skis_sample.hip -- IIS sampling (Alg. 1) and compaction into the CSR sketch (Alg. 2).
+//
+//   k_roots        one thread per sample: root by the alias table (Eq. probu) and first
+//                  live in-edge i* by Eq. (probn) (binary search over the prefix products)
+//   k_sample<...>  persistent sampler: every workgroup keeps S samples in flight, each
+//                  with its visited set and node list; the unexpanded nodes of all slots
+//                  form one flat list of (slot, edge range) items, and the lanes sweep the
+//                  edges of all items two at a time (one 16-byte load and one Philox call
+//                  per aligned edge pair).  GLOBAL=false keeps the visited set in LDS (an
+//                  open-addressing hash) and hands a sample to the global tier when it
+//                  outgrows the hash or meets an in-degree above big_row; GLOBAL=true keeps
+//                  a bitmap of n bits and a node list of n entries per slot in HBM.
+//   k_gather_*     sorts each sample's nodes and writes the CSR in sample order.
+//
+// Sample j is a pure function of (graph, seed, j): the order in which a sample's nodes are
+// discovered changes nothing, because the coins are keyed by (j, edge id) and the sample
+// is the set of nodes that reach the root through live edges.
+#include <algorithm>
+
+#include "skis_internal.h"
+
+namespace skis {
+
+constexpr uint32_t DEFERRED = 0xFFFFFFFFu;
+constexpr int SMALL_SORT = 256;    // sizes up to this are sorted by one wave in k_gather_small
+constexpr int SORT_LDS_MAX = 8192; // sizes up to this are sorted in LDS by k_gather_medium;
+                                   // larger ones are written already sorted by the global tier
+constexpr int IDBATCH = 64;        // sample ids taken from the global counter at a time
+
+enum : int { F_ACTIVE = 1, F_ROOTPEND = 2, F_DEFER = 4, F_CLEAR = 8 };
+
+// ---------------------------------------------------------------------------------------
+// Root and first live in-edge of every sample.
+//   rec[i] = (root, i*, row begin, row end), u1[i] = col[i*], for sample j = j0 + i.
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_roots(uint64_t j0, uint32_t count, uint32_t seed_lo, uint32_t seed_hi,
+                                               int32_t n, uint64_t C, const AliasEntry *__restrict__ alias,
+                                               const int32_t *__restrict__ row_ptr, const double *__restrict__ q,
+                                               const double *__restrict__ P, const uint2 *__restrict__ edges,
+                                               int4 *__restrict__ rec, int32_t *__restrict__ u1)
+{
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+        const uint64_t j = j0 + i;
+        const uint32_t jl = (uint32_t)j, jh = (uint32_t)(j >> 32);
+        uint64_t X, Y;
+        philox2x64(0u, jl, jh, TAG_ROOT, seed_lo, seed_hi, X, Y);
+        const uint64_t b = __umul64hi(X, (uint64_t)n);
+        const uint64_t r = __umul64hi(Y, C);
+        const AliasEntry ae = alias[b];
+        const int32_t root = r < ae.thr ? (int32_t)b : ae.alias;
+        const int32_t rb = row_ptr[root], re = row_ptr[root + 1];
+        philox2x64(0u, jl, jh, TAG_FIRST, seed_lo, seed_hi, X, Y);
+        const double U = (double)(X >> 11) * 0x1p-53;
+        const double theta = __dmul_rn(U, __dsub_rn(1.0, q[root]));
+        // first e in the row with 1 - P[e] > theta (1 - P is nondecreasing along the row)
+        int32_t lo = rb, hi = re;
+        while (lo < hi) {
+            const int32_t mid = lo + ((hi - lo) >> 1);
+            if (__dsub_rn(1.0, P[mid]) > theta) hi = mid; else lo = mid + 1;
+        }
+        int32_t istar = lo;
+        if (istar >= re) { // theta rounded up to gamma: last in-edge of positive probability
+            istar = re - 1;
+            while (istar > rb && edges[istar].y == 0u) --istar;
+        }
+        rec[i] = make_int4(root, istar, rb, re);
+        u1[i] = (int32_t)edges[istar].x;
+    }
+}
+
+struct SampleArgs {
+    int32_t n;
+    const int32_t *row_ptr;
+    const uint4 *pairs;         // edges as aligned pairs (col[2p], w[2p], col[2p+1], w[2p+1])
+    const int4 *rec;
+    const int32_t *u1;
+    uint64_t j0;
+    uint32_t seed_lo, seed_hi;
+    unsigned long long *next;   // id counter
+    const uint32_t *id_list;    // nullptr: ids 0..id_count-1; else id_list[0..id_count)
+    uint64_t id_count;
+    uint32_t big_row;
+    int32_t *staging;
+    unsigned long long stage_cap;
+    unsigned long long *stage_used;
+    uint32_t *out_size;
+    unsigned long long *out_off;
+    unsigned long long *out_probed;
+    uint32_t *deferred;
+    unsigned long long *n_deferred;
+    uint32_t *medium;
+    unsigned long long *n_medium;
+    int *overflow;
+    uint32_t *gbits;            // global tier: [slots][words]
+    int32_t *glist;             // global tier: [slots][n]
+    uint64_t words;
+};
+
+template <int BLOCK, int S, int HBITS, int ICAP, bool GLOBAL>
+__global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
+{
+    constexpr int HCAP = 1 << HBITS;
+    constexpr int RCAP = HCAP / 2;
+    constexpr int HSZ = GLOBAL ? 1 : S * HCAP;
+    constexpr int LSZ = GLOBAL ? 1 : S * RCAP;
+    constexpr int IPT = (ICAP + BLOCK - 1) / BLOCK;
+    static_assert(S <= 64, "slots are owned by the lanes of wave 0");
+    static_assert(IDBATCH >= S, "one refill must cover every empty slot");
+
+    __shared__ int32_t sh_hash[HSZ];
+    __shared__ int32_t sh_list[LSZ];
+    __shared__ uint32_t s_idx[S];
+    __shared__ int32_t s_count[S], s_cursor[S], s_flags[S], s_rib[S], s_rie[S];
+    __shared__ unsigned long long s_probed[S];
+    __shared__ int32_t s_wo_cnt[S];
+    __shared__ unsigned long long s_wo_off[S];
+    __shared__ int32_t s_ibase[S + 1], s_ifirst[S], s_irp[S];
+    __shared__ int32_t it_beg[ICAP], it_end[ICAP], it_pb[ICAP + 1];
+    __shared__ uint8_t it_slot[ICAP];
+    __shared__ int32_t s_nitems, s_alive;
+    __shared__ unsigned long long s_idnext, s_idend;
+    __shared__ int32_t s_scan[BLOCK / 64 + 1];
+
+    const int tid = threadIdx.x;
+    const int32_t n = a.n;
+
+    auto list_ptr = [&](int s) -> int32_t * {
+        if constexpr (GLOBAL) return a.glist + ((size_t)blockIdx.x * S + s) * (size_t)n;
+        else return sh_list + s * RCAP;
+    };
+    auto bits_ptr = [&](int s) -> uint32_t * { return a.gbits + ((size_t)blockIdx.x * S + s) * a.words; };
+
+    // Adds u to slot s's sample if it is not there yet.
+    auto visit = [&](int s, int32_t u) {
+        if constexpr (GLOBAL) {
+            const uint32_t bit = 1u << (u & 31);
+            const uint32_t old = atomicOr(bits_ptr(s) + (u >> 5), bit);
+            if (!(old & bit)) {
+                const int pos = atomicAdd(&s_count[s], 1);
+                list_ptr(s)[pos] = u;
+            }
+        } else {
+            int32_t *H = sh_hash + s * HCAP;
+            uint32_t h = ((uint32_t)u * 0x9E3779B1u) >> (32 - HBITS);
+            for (int k = 0; k < HCAP; ++k) {
+                const int32_t old = atomicCAS(&H[h], -1, u);
+                if (old == -1) {
+                    const int pos = atomicAdd(&s_count[s], 1);
+                    if (pos < RCAP) sh_list[s * RCAP + pos] = u;
+                    else atomicOr(&s_flags[s], F_DEFER);
+                    return;
+                }
+                if (old == u) return;
+                h = (h + 1) & (HCAP - 1);
+            }
+            atomicOr(&s_flags[s], F_DEFER);
+        }
+    };
+
+    if constexpr (!GLOBAL)
+        for (int i = tid; i < HSZ; i += BLOCK) sh_hash[i] = -1;
+    if (tid < S) {
+        s_flags[tid] = 0;
+        s_wo_cnt[tid] = 0;
+    }
+    if (tid == 0) {
+        s_idnext = 0;
+        s_idend = 0;
+    }
+    __syncthreads();
+
+    for (;;) {
+        // ---- A: wave 0, lane s owns slot s: finish, admit, hand out items -----------------
+        if (tid < 64) {
+            const int s = tid;
+            const bool own = s < S;
+            int f = own ? s_flags[s] : 0;
+            if (own && (f & F_ACTIVE)) {
+                if (!GLOBAL && (f & F_DEFER)) {
+                    const uint32_t i = s_idx[s];
+                    const unsigned long long k = atomicAdd(a.n_deferred, 1ull);
+                    a.deferred[k] = i;
+                    a.out_size[i] = DEFERRED;
+                    s_wo_cnt[s] = 0;
+                    f = F_CLEAR;
+                    s_flags[s] = f;
+                } else if (!(f & F_ROOTPEND) && s_cursor[s] >= s_count[s]) {
+                    const uint32_t i = s_idx[s];
+                    const int cnt = s_count[s];
+                    const unsigned long long off = atomicAdd(a.stage_used, (unsigned long long)cnt);
+                    a.out_size[i] = (uint32_t)cnt;
+                    a.out_off[i] = off;
+                    a.out_probed[i] = s_probed[s];
+                    if (cnt > SMALL_SORT) {
+                        const unsigned long long k = atomicAdd(a.n_medium, 1ull);
+                        a.medium[k] = i;
+                    }
+                    if (off + (unsigned long long)cnt <= a.stage_cap) {
+                        s_wo_cnt[s] = cnt;
+                        s_wo_off[s] = off;
+                    } else {
+                        s_wo_cnt[s] = 0;
+                        atomicOr(a.overflow, 1);
+                    }
+                    f = F_CLEAR;
+                    s_flags[s] = f;
+                }
+            }
+            // admission into slots that were already empty when this pass began
+            const bool want = own && f == 0;
+            const unsigned long long wmask = __ballot(want);
+            const int nwant = __popcll(wmask);
+            if (nwant > 0) {
+                const int rank = __popcll(wmask & ((1ull << s) - 1ull));
+                const unsigned long long idnext = s_idnext, idend = s_idend;
+                const unsigned long long avail = idend - idnext;
+                unsigned long long nb = 0;
+                if (avail < (unsigned long long)nwant) {
+                    if (s == 0) nb = atomicAdd(a.next, (unsigned long long)IDBATCH);
+                    nb = __shfl(nb, 0, 64);
+                }
+                const unsigned long long myid =
+                    (unsigned long long)rank < avail ? idnext + rank : nb + (rank - avail);
+                if (s == 0) {
+                    if (avail >= (unsigned long long)nwant) {
+                        s_idnext = idnext + nwant;
+                    } else {
+                        s_idnext = nb + (nwant - avail);
+                        s_idend = nb + IDBATCH;
+                    }
+                }
+                if (want && myid < a.id_count) {
+                    const uint32_t i = a.id_list ? a.id_list[myid] : (uint32_t)myid;
+                    const int4 r = a.rec[i];
+                    const int32_t u = a.u1[i];
+                    s_idx[s] = i;
+                    s_rib[s] = r.y + 1;
+                    s_rie[s] = r.w;
+                    s_probed[s] = (unsigned long long)(r.w - r.z);
+                    s_count[s] = 2;
+                    s_cursor[s] = 1;
+                    int nf = F_ACTIVE | (r.y + 1 < r.w ? F_ROOTPEND : 0);
+                    if (!GLOBAL && (uint32_t)(r.w - r.z) > a.big_row) nf |= F_DEFER;
+                    int32_t *L = list_ptr(s);
+                    L[0] = r.x;
+                    L[1] = u;
+                    if constexpr (GLOBAL) {
+                        uint32_t *B = bits_ptr(s);
+                        atomicOr(B + (r.x >> 5), 1u << (r.x & 31));
+                        atomicOr(B + (u >> 5), 1u << (u & 31));
+                    } else {
+                        int32_t *H = sh_hash + s * HCAP;
+                        const int32_t keys[2] = {r.x, u};
+                        for (int t = 0; t < 2; ++t) {
+                            uint32_t h = ((uint32_t)keys[t] * 0x9E3779B1u) >> (32 - HBITS);
+                            while (H[h] != -1) h = (h + 1) & (HCAP - 1);
+                            H[h] = keys[t];
+                        }
+                    }
+                    f = nf;
+                    s_flags[s] = f;
+                }
+            }
+            // items: the root item (edges after i*) and then unexpanded nodes, slot by slot
+            int pend = 0, rp = 0;
+            if (own && (f & F_ACTIVE) && !(f & F_DEFER)) {
+                rp = (f & F_ROOTPEND) ? 1 : 0;
+                int lim = s_count[s];
+                if (!GLOBAL && lim > RCAP) lim = RCAP;
+                const int rest = lim - s_cursor[s];
+                pend = rp + (rest > 0 ? rest : 0);
+            }
+            const int incl = wave_incl_scan(pend);
+            const int base = incl - pend;
+            int take = ICAP - base;
+            take = take < 0 ? 0 : (take > pend ? pend : take);
+            const int tincl = wave_incl_scan(take);
+            if (own) {
+                s_ibase[s] = tincl - take;
+                s_ifirst[s] = s_cursor[s];
+                const int trp = take > 0 ? rp : 0;
+                s_irp[s] = trp;
+                if (take > 0) {
+                    s_cursor[s] += take - trp;
+                    if (trp) {
+                        f &= ~F_ROOTPEND;
+                        s_flags[s] = f;
+                    }
+                }
+            }
+            const int total = __shfl(tincl, 63, 64);
+            const unsigned long long amask = __ballot(own && (f & F_ACTIVE));
+            if (s == 0) {
+                s_ibase[S] = total;
+                s_nitems = total;
+                s_alive = amask != 0ull;
+            }
+        }
+        __syncthreads();
+
+        // ---- B1: write out finished samples, clear their visited sets ----------------------
+        for (int s = 0; s < S; ++s) {
+            if (s_flags[s] != F_CLEAR) continue;
+            const int cnt = s_wo_cnt[s];
+            const unsigned long long off = s_wo_off[s];
+            if constexpr (!GLOBAL) {
+                for (int t = tid; t < cnt; t += BLOCK) a.staging[off + t] = sh_list[s * RCAP + t];
+                for (int t = tid; t < HCAP; t += BLOCK) sh_hash[s * HCAP + t] = -1;
+            } else {
+                int32_t *L = list_ptr(s);
+                uint32_t *B = bits_ptr(s);
+                if (cnt > SORT_LDS_MAX) {
+                    // a very large sample: write it sorted straight from the bitmap
+                    unsigned long long run = off;
+                    for (uint64_t w0 = 0; w0 < a.words; w0 += BLOCK) {
+                        const uint64_t wi = w0 + tid;
+                        const uint32_t word = wi < a.words ? B[wi] : 0u;
+                        int tot;
+                        const int ex = block_excl_scan<BLOCK, int>(__popc(word), s_scan, &tot);
+                        if (word) {
+                            uint32_t x = word;
+                            int k = 0;
+                            while (x) {
+                                const int b = __ffs(x) - 1;
+                                x &= x - 1u;
+                                a.staging[run + ex + k] = (int32_t)(wi * 32u + (uint64_t)b);
+                                ++k;
+                            }
+                            B[wi] = 0u;
+                        }
+                        run += (unsigned long long)tot;
+                    }
+                } else {
+                    for (int t = tid; t < cnt; t += BLOCK) a.staging[off + t] = L[t];
+                    const int rc = s_count[s];
+                    for (int t = tid; t < rc; t += BLOCK) B[L[t] >> 5] = 0u;
+                }
+            }
+        }
+        __syncthreads();
+        if (tid < S && s_flags[tid] == F_CLEAR) {
+            s_flags[tid] = 0;
+            s_wo_cnt[tid] = 0;
+        }
+
+        // ---- B2: item edge ranges ----------------------------------------------------------
+        const int nitems = s_nitems;
+        for (int it = tid; it < nitems; it += BLOCK) {
+            int lo = 0, hi = S;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (s_ibase[mid] <= it) lo = mid + 1; else hi = mid;
+            }
+            const int s = lo - 1;
+            const int t = it - s_ibase[s];
+            int beg, end;
+            if (s_irp[s] && t == 0) {
+                beg = s_rib[s];
+                end = s_rie[s];
+            } else {
+                const int32_t x = list_ptr(s)[s_ifirst[s] + t - s_irp[s]];
+                beg = a.row_ptr[x];
+                end = a.row_ptr[x + 1];
+                atomicAdd(&s_probed[s], (unsigned long long)(end - beg));
+                if (!GLOBAL && (uint32_t)(end - beg) > a.big_row) {
+                    atomicOr(&s_flags[s], F_DEFER);
+                    end = beg;
+                }
+            }
+            it_slot[it] = (uint8_t)s;
+            it_beg[it] = beg;
+            it_end[it] = end;
+            it_pb[it] = end > beg ? ((end - 1) >> 1) - (beg >> 1) + 1 : 0;
+        }
+        __syncthreads();
+
+        // ---- B3: prefix sum of edge pairs over the items -----------------------------------
+        {
+            int loc[IPT];
+            int acc = 0;
+#pragma unroll
+            for (int k = 0; k < IPT; ++k) {
+                const int idx = tid * IPT + k;
+                const int v = idx < nitems ? it_pb[idx] : 0;
+                loc[k] = acc;
+                acc += v;
+            }
+            int tot;
+            const int ex = block_excl_scan<BLOCK, int>(acc, s_scan, &tot);
+#pragma unroll
+            for (int k = 0; k < IPT; ++k) {
+                const int idx = tid * IPT + k;
+                if (idx < nitems) it_pb[idx] = ex + loc[k];
+            }
+            if (tid == 0) it_pb[nitems] = tot;
+        }
+        __syncthreads();
+
+        // ---- B4: live-edge coins for every edge pair, visits ------------------------------
+        const int total = it_pb[nitems];
+        for (int idx = tid; idx < total; idx += BLOCK) {
+            int lo = 0, hi = nitems - 1; // last item whose first pair index is <= idx
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (it_pb[mid] <= idx) lo = mid; else hi = mid - 1;
+            }
+            const int s = it_slot[lo];
+            if (!GLOBAL && (s_flags[s] & F_DEFER)) continue;
+            const int beg = it_beg[lo], end = it_end[lo];
+            const int p = (beg >> 1) + (idx - it_pb[lo]);
+            const uint4 pr = a.pairs[p];
+            const uint64_t j = a.j0 + s_idx[s];
+            uint64_t X, Y;
+            philox2x64((uint32_t)p, (uint32_t)j, (uint32_t)(j >> 32), TAG_EDGE, a.seed_lo, a.seed_hi, X, Y);
+            const int e0 = 2 * p;
+            if (e0 >= beg && coin_live(pr.y, X)) visit(s, (int32_t)pr.x);
+            if (e0 + 1 < end && coin_live(pr.w, Y)) visit(s, (int32_t)pr.z);
+        }
+        __syncthreads();
+        if (!s_alive) break;
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Compaction: sort each sample and write it at sample_ptr[i].
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ int32_t bitonic64(int32_t v)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+        for (int d = k >> 1; d > 0; d >>= 1) {
+            const int32_t o = __shfl_xor(v, d, 64);
+            const bool asc = (lane & k) == 0;
+            const bool low = (lane & d) == 0;
+            v = (low == asc) ? min(v, o) : max(v, o);
+        }
+    }
+    return v;
+}
+
+template <int NT>
+__device__ void bitonic_lds(int32_t *buf, int P)
+{
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int d = k >> 1; d > 0; d >>= 1) {
+            for (int i = threadIdx.x; i < P; i += NT) {
+                const int ixj = i ^ d;
+                if (ixj > i) {
+                    const int32_t x = buf[i], y = buf[ixj];
+                    const bool asc = (i & k) == 0;
+                    if ((x > y) == asc) {
+                        buf[i] = y;
+                        buf[ixj] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// 64-thread workgroups, one sample at a time; sizes above SMALL_SORT are left to
+// k_gather_medium.
+__global__ __launch_bounds__(64) void k_gather_small(uint64_t T, const uint32_t *__restrict__ size,
+                                                     const unsigned long long *__restrict__ off,
+                                                     const int64_t *__restrict__ sptr,
+                                                     const int32_t *__restrict__ staging, int32_t *__restrict__ nodes)
+{
+    __shared__ int32_t buf[SMALL_SORT];
+    const int lane = threadIdx.x;
+    for (uint64_t i = blockIdx.x; i < T; i += gridDim.x) {
+        const int sz = (int)size[i];
+        if (sz > SMALL_SORT) continue;
+        const int32_t *src = staging + off[i];
+        int32_t *dst = nodes + sptr[i];
+        if (sz <= 64) {
+            int32_t v = lane < sz ? src[lane] : INT32_MAX;
+            v = bitonic64(v);
+            if (lane < sz) dst[lane] = v;
+        } else {
+            int P = 128;
+            while (P < sz) P <<= 1;
+            for (int t = lane; t < P; t += 64) buf[t] = t < sz ? src[t] : INT32_MAX;
+            __syncthreads();
+            bitonic_lds<64>(buf, P);
+            for (int t = lane; t < sz; t += 64) dst[t] = buf[t];
+            __syncthreads();
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_gather_medium(uint64_t count, const uint32_t *__restrict__ list,
+                                                       const uint32_t *__restrict__ size,
+                                                       const unsigned long long *__restrict__ off,
+                                                       const int64_t *__restrict__ sptr,
+                                                       const int32_t *__restrict__ staging,
+                                                       int32_t *__restrict__ nodes)
+{
+    __shared__ int32_t buf[SORT_LDS_MAX];
+    for (uint64_t k = blockIdx.x; k < count; k += gridDim.x) {
+        const uint32_t i = list[k];
+        const int sz = (int)size[i];
+        const int32_t *src = staging + off[i];
+        int32_t *dst = nodes + sptr[i];
+        if (sz > SORT_LDS_MAX) { // written sorted by the global tier
+            for (int t = threadIdx.x; t < sz; t += 256) dst[t] = src[t];
+            continue;
+        }
+        int P = 512;
+        while (P < sz) P <<= 1;
+        for (int t = threadIdx.x; t < P; t += 256) buf[t] = t < sz ? src[t] : INT32_MAX;
+        __syncthreads();
+        bitonic_lds<256>(buf, P);
+        for (int t = threadIdx.x; t < sz; t += 256) dst[t] = buf[t];
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_roots_out(uint32_t count, const int4 *__restrict__ rec, int32_t *__restrict__ roots)
+{
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x)
+        roots[i] = rec[i].x;
+}
+
+__global__ __launch_bounds__(256) void k_sum_u64(uint64_t count, const unsigned long long *__restrict__ x,
+                                                 unsigned long long *__restrict__ out)
+{
+    unsigned long long acc = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (uint64_t)gridDim.x * blockDim.x)
+        acc += x[i];
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0 && acc) atomicAdd(out, acc);
+}
+
+// ---------------------------------------------------------------------------------------
+// Inverse index: node -> samples.
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_count_nodes(uint64_t entries, const int32_t *__restrict__ nodes,
+                                                     uint32_t *__restrict__ cnt)
+{
+    for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < entries; p += (uint64_t)gridDim.x * blockDim.x)
+        atomicAdd(&cnt[nodes[p]], 1u);
+}
+
+__global__ __launch_bounds__(64) void k_scatter_inverse(uint64_t T, const int64_t *__restrict__ sptr,
+                                                        const int32_t *__restrict__ nodes,
+                                                        const int64_t *__restrict__ node_ptr,
+                                                        uint32_t *__restrict__ fill, int32_t *__restrict__ ns)
+{
+    for (uint64_t j = blockIdx.x; j < T; j += gridDim.x) {
+        const int64_t a = sptr[j], b = sptr[j + 1];
+        for (int64_t p = a + threadIdx.x; p < b; p += 64) {
+            const int32_t v = nodes[p];
+            const uint32_t pos = atomicAdd(&fill[v], 1u);
+            ns[node_ptr[v] + pos] = (int32_t)j;
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_fill(uint64_t count, T *__restrict__ p, T v)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// ---------------------------------------------------------------------------------------
+// Host orchestration.
+// ---------------------------------------------------------------------------------------
+static unsigned grid_cap(uint64_t items, int block, int per_cu = 16)
+{
+    uint64_t g = (items + block - 1) / block;
+    const uint64_t cap = (uint64_t)device_cu_count() * per_cu;
+    if (g > cap) g = cap;
+    return (unsigned)(g > 0 ? g : 1);
+}
+
+struct Counters {
+    unsigned long long next;
+    unsigned long long stage_used;
+    unsigned long long n_deferred;
+    unsigned long long n_medium;
+    int overflow;
+    int pad;
+};
+
+typedef void (*SampleKernel)(SampleArgs);
+
+struct Variant {
+    uint32_t slots, visited;
+    SampleKernel fn;
+};
+
+// LDS tier variants: (slots per workgroup, LDS visited capacity)
+static const Variant kTier0[] = {
+    {32, 128, k_sample<256, 32, 8, 1024, false>},
+    {16, 256, k_sample<256, 16, 9, 1024, false>},
+    {32, 256, k_sample<256, 32, 9, 1024, false>},
+    {8, 512, k_sample<256, 8, 10, 1024, false>},
+    {16, 128, k_sample<256, 16, 8, 1024, false>},
+};
+constexpr int TIER1_SLOTS = 4;
+static SampleKernel const kTier1 = k_sample<256, TIER1_SLOTS, 1, 1024, true>;
+
+static SampleKernel pick_tier0(uint32_t slots, uint32_t visited)
+{
+    for (const Variant &v : kTier0)
+        if (v.slots == slots && v.visited == visited) return v.fn;
+    throw Error{SKIS_EINVAL, "unsupported (slots_per_block, visited_threshold) pair"};
+}
+
+static int occupancy_blocks(SampleKernel fn, int block)
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(fn), block, 0) != hipSuccess ||
+        nb < 1)
+        nb = 1;
+    return nb;
+}
+
+void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, uint64_t T, uint64_t seed,
+                        const SampleConfig &cfg, Sketch &sk, hipStream_t s)
+{
+    (void)m;
+    if (T >= (1ull << 31)) throw Error{SKIS_EINVAL, "num_samples must be below 2^31"};
+    const uint32_t count = (uint32_t)T;
+    const uint32_t seed_lo = (uint32_t)seed, seed_hi = (uint32_t)(seed >> 32);
+    constexpr int NEV = 8;
+    hipEvent_t ev[NEV];
+    for (auto &e : ev) SKIS_HIP_TRY(hipEventCreate(&e));
+    struct EvGuard {
+        hipEvent_t *e;
+        ~EvGuard()
+        {
+            for (int i = 0; i < NEV; ++i) (void)hipEventDestroy(e[i]);
+        }
+    } evg{ev};
+    bool ran_tier1 = false;
+
+    DevBuf<int4> rec;
+    DevBuf<int32_t> u1;
+    rec.alloc(arena, count);
+    u1.alloc(arena, count);
+    SKIS_HIP_TRY(hipEventRecord(ev[0], s));
+    hipLaunchKernelGGL(k_roots, dim3(grid_cap(count, 256, 64)), dim3(256), 0, s, (uint64_t)0, count, seed_lo, seed_hi,
+                       n, prep.C, prep.alias.ptr, prep.row_ptr.ptr, prep.q.ptr, prep.P.ptr, prep.edges.ptr, rec.ptr,
+                       u1.ptr);
+    SKIS_HIP_TRY(hipGetLastError());
+    SKIS_HIP_TRY(hipEventRecord(ev[1], s));
+
+    DevBuf<uint32_t> out_size, deferred, medium;
+    DevBuf<unsigned long long> out_off;
+    out_size.alloc(arena, count);
+    out_off.alloc(arena, count);
+    sk.probed.alloc(arena, count);
+    deferred.alloc(arena, count);
+    medium.alloc(arena, count);
+    DevBuf<Counters> ctr;
+    ctr.alloc(arena, 1);
+
+    uint64_t cap = cfg.staging_entries ? cfg.staging_entries : (uint64_t)count * 48ull + (1ull << 20);
+    DevBuf<int32_t> staging;
+    Counters hc{};
+    SampleKernel t0 = pick_tier0(cfg.slots, cfg.visited);
+    const int cus = device_cu_count();
+    const int nb0 = occupancy_blocks(t0, 256) * cus;
+    const uint64_t words = ((uint64_t)n + 31) / 32;
+    // global tier: every slot holds a bitmap of n bits and a node list of n entries; keep
+    // all slots within about 4 GiB
+    const uint64_t slot_bytes = (uint64_t)n * 4ull + words * 4ull;
+    uint64_t nb1_mem = (4ull << 30) / (slot_bytes * TIER1_SLOTS);
+    if (nb1_mem < 1) nb1_mem = 1;
+    const int nb1 = (int)std::min<uint64_t>((uint64_t)2 * cus, nb1_mem);
+
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        staging.alloc(arena, cap);
+        hipLaunchKernelGGL(k_fill<unsigned char>, dim3(1), dim3(64), 0, s, (uint64_t)sizeof(Counters),
+                           reinterpret_cast<unsigned char *>(ctr.ptr), (unsigned char)0);
+        SampleArgs A{};
+        A.n = n;
+        A.row_ptr = prep.row_ptr.ptr;
+        A.pairs = reinterpret_cast<const uint4 *>(prep.edges.ptr);
+        A.rec = rec.ptr;
+        A.u1 = u1.ptr;
+        A.j0 = 0;
+        A.seed_lo = seed_lo;
+        A.seed_hi = seed_hi;
+        A.next = &ctr.ptr->next;
+        A.id_list = nullptr;
+        A.id_count = count;
+        A.big_row = cfg.big_row;
+        A.staging = staging.ptr;
+        A.stage_cap = cap;
+        A.stage_used = &ctr.ptr->stage_used;
+        A.out_size = out_size.ptr;
+        A.out_off = out_off.ptr;
+        A.out_probed = reinterpret_cast<unsigned long long *>(sk.probed.ptr);
+        A.deferred = deferred.ptr;
+        A.n_deferred = &ctr.ptr->n_deferred;
+        A.medium = medium.ptr;
+        A.n_medium = &ctr.ptr->n_medium;
+        A.overflow = &ctr.ptr->overflow;
+        A.words = words;
+        SKIS_HIP_TRY(hipEventRecord(ev[4], s));
+        hipLaunchKernelGGL(t0, dim3(nb0), dim3(256), 0, s, A);
+        SKIS_HIP_TRY(hipGetLastError());
+        SKIS_HIP_TRY(hipEventRecord(ev[5], s));
+        SKIS_HIP_TRY(hipMemcpyAsync(&hc, ctr.ptr, sizeof(hc), hipMemcpyDeviceToHost, s));
+        SKIS_HIP_TRY(hipStreamSynchronize(s));
+        sk.deferred = hc.n_deferred;
+        if (hc.n_deferred > 0) {
+            const uint64_t slots = (uint64_t)nb1 * TIER1_SLOTS;
+            DevBuf<uint32_t> gbits;
+            DevBuf<int32_t> glist;
+            gbits.alloc(arena, slots * words);
+            glist.alloc(arena, slots * (uint64_t)n);
+            hipLaunchKernelGGL(k_fill<uint32_t>, dim3(grid_cap(slots * words, 256)), dim3(256), 0, s, slots * words,
+                               gbits.ptr, 0u);
+            hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(1), dim3(64), 0, s, (uint64_t)1, &ctr.ptr->next, 0ull);
+            A.id_list = deferred.ptr;
+            A.id_count = hc.n_deferred;
+            A.gbits = gbits.ptr;
+            A.glist = glist.ptr;
+            SKIS_HIP_TRY(hipEventRecord(ev[6], s));
+            hipLaunchKernelGGL(kTier1, dim3(nb1), dim3(256), 0, s, A);
+            SKIS_HIP_TRY(hipGetLastError());
+            SKIS_HIP_TRY(hipEventRecord(ev[7], s));
+            ran_tier1 = true;
+            SKIS_HIP_TRY(hipMemcpyAsync(&hc, ctr.ptr, sizeof(hc), hipMemcpyDeviceToHost, s));
+            SKIS_HIP_TRY(hipStreamSynchronize(s));
+        }
+        if (!hc.overflow) break;
+        cap = hc.stage_used + 1024; // every size is known now: exact retry
+        staging.reset();
+        if (attempt == 1) throw Error{SKIS_ENOMEM, "staging overflow after resize"};
+    }
+    SKIS_HIP_TRY(hipEventRecord(ev[2], s));
+
+    // CSR: sample_ptr = exclusive scan of sizes, then sorted copies
+    sk.T = count;
+    sk.sample_ptr.alloc(arena, (size_t)count + 1);
+    excl_scan_u32_to_i64(arena, out_size.ptr, sk.sample_ptr.ptr, count, sk.sample_ptr.ptr + count, s);
+    int64_t total = 0;
+    SKIS_HIP_TRY(hipMemcpyAsync(&total, sk.sample_ptr.ptr + count, sizeof(total), hipMemcpyDeviceToHost, s));
+    SKIS_HIP_TRY(hipStreamSynchronize(s));
+    sk.entries = (uint64_t)total;
+    sk.nodes.alloc(arena, (size_t)total);
+    hipLaunchKernelGGL(k_gather_small, dim3(grid_cap(count, 1, 64)), dim3(64), 0, s, (uint64_t)count, out_size.ptr,
+                       out_off.ptr, sk.sample_ptr.ptr, staging.ptr, sk.nodes.ptr);
+    SKIS_HIP_TRY(hipGetLastError());
+    if (hc.n_medium > 0) {
+        hipLaunchKernelGGL(k_gather_medium, dim3(grid_cap(hc.n_medium, 1, 4)), dim3(256), 0, s,
+                           (uint64_t)hc.n_medium, medium.ptr, out_size.ptr, out_off.ptr, sk.sample_ptr.ptr,
+                           staging.ptr, sk.nodes.ptr);
+        SKIS_HIP_TRY(hipGetLastError());
+    }
+    sk.roots.alloc(arena, count);
+    hipLaunchKernelGGL(k_roots_out, dim3(grid_cap(count, 256)), dim3(256), 0, s, count, rec.ptr, sk.roots.ptr);
+    SKIS_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(1), dim3(64), 0, s, (uint64_t)1, &ctr.ptr->next, 0ull);
+    hipLaunchKernelGGL(k_sum_u64, dim3(grid_cap(count, 256)), dim3(256), 0, s, (uint64_t)count,
+                       reinterpret_cast<const unsigned long long *>(sk.probed.ptr), &ctr.ptr->next);
+    SKIS_HIP_TRY(hipGetLastError());
+    unsigned long long ptot = 0;
+    SKIS_HIP_TRY(hipMemcpyAsync(&ptot, &ctr.ptr->next, sizeof(ptot), hipMemcpyDeviceToHost, s));
+    SKIS_HIP_TRY(hipEventRecord(ev[3], s));
+    SKIS_HIP_TRY(hipStreamSynchronize(s));
+    sk.probed_total = ptot;
+    float ms = 0;
+    SKIS_HIP_TRY(hipEventElapsedTime(&ms, ev[0], ev[1]));
+    sk.ms_roots = ms;
+    SKIS_HIP_TRY(hipEventElapsedTime(&ms, ev[1], ev[2]));
+    sk.ms_sample = ms;
+    SKIS_HIP_TRY(hipEventElapsedTime(&ms, ev[2], ev[3]));
+    sk.ms_compact = ms;
+    SKIS_HIP_TRY(hipEventElapsedTime(&ms, ev[4], ev[5]));
+    sk.ms_tier0 = ms;
+    sk.ms_tier1 = 0;
+    if (ran_tier1) {
+        SKIS_HIP_TRY(hipEventElapsedTime(&ms, ev[6], ev[7]));
+        sk.ms_tier1 = ms;
+    }
+}
+
+void build_inverse(Sketch &sk, hipStream_t s)
+{
+    Arena &arena = sk.arena;
+    const int32_t n = sk.n;
+    sk.node_ptr.alloc(arena, (size_t)n + 1);
+    sk.node_samples.alloc(arena, (size_t)sk.entries);
+    DevBuf<uint32_t> cnt;
+    cnt.alloc(arena, (size_t)n);
+    hipLaunchKernelGGL(k_fill<uint32_t>, dim3(grid_cap(n, 256)), dim3(256), 0, s, (uint64_t)n, cnt.ptr, 0u);
+    if (sk.entries)
+        hipLaunchKernelGGL(k_count_nodes, dim3(grid_cap(sk.entries, 256)), dim3(256), 0, s, sk.entries, sk.nodes.ptr,
+                           cnt.ptr);
+    SKIS_HIP_TRY(hipGetLastError());
+    excl_scan_u32_to_i64(arena, cnt.ptr, sk.node_ptr.ptr, n, sk.node_ptr.ptr + n, s);
+    hipLaunchKernelGGL(k_fill<uint32_t>, dim3(grid_cap(n, 256)), dim3(256), 0, s, (uint64_t)n, cnt.ptr, 0u);
+    if (sk.T)
+        hipLaunchKernelGGL(k_scatter_inverse, dim3(grid_cap(sk.T, 1, 64)), dim3(64), 0, s, sk.T, sk.sample_ptr.ptr,
+                           sk.nodes.ptr, sk.node_ptr.ptr, cnt.ptr, sk.node_samples.ptr);
+    SKIS_HIP_TRY(hipGetLastError());
+    SKIS_HIP_TRY(hipStreamSynchronize(s));
+    sk.has_inverse = true;
+}
+
+} // namespace skis

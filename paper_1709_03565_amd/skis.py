@@ -1,0 +1,226 @@
+"""ctypes binding of libskis.so (argument marshalling only).
+
+Every computation runs in the library's HIP kernels; this module passes device pointers of
+torch tensors and the current HIP stream.  torch supplies device memory and streams only.
+If libskis.so is missing or cannot be loaded, every call raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libskis.so")
+
+SKIS_OK, SKIS_WDEGENERATE, SKIS_EINVAL, SKIS_ENOMEM, SKIS_EHIP = 0, 1, -1, -2, -3
+
+EXPORTED = ("skis_default_options", "skis_preprocess", "skis_build_sketch", "skis_sketch_info",
+            "skis_estimate", "skis_greedy_max_cover", "skis_sketch_export", "skis_inverse_export",
+            "skis_node_q", "skis_sketch_free", "skis_last_error")
+
+
+class SkisError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("libskis error %d: %s" % (code, msg))
+        self.code = code
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("form", ctypes.c_uint32), ("slots_per_block", ctypes.c_uint32),
+                ("visited_threshold", ctypes.c_uint32), ("big_row", ctypes.c_uint32),
+                ("build_inverse_index", ctypes.c_uint32), ("reserved0", ctypes.c_uint32),
+                ("max_device_bytes", ctypes.c_uint64), ("staging_entries", ctypes.c_uint64)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("reserved", ctypes.c_int32), ("T", ctypes.c_uint64),
+                ("entries", ctypes.c_uint64), ("probed_total", ctypes.c_uint64),
+                ("deferred", ctypes.c_uint64), ("C", ctypes.c_uint64), ("Gamma", ctypes.c_double),
+                ("device_bytes", ctypes.c_uint64), ("ms_preprocess", ctypes.c_double),
+                ("ms_roots", ctypes.c_double), ("ms_sample", ctypes.c_double),
+                ("ms_compact", ctypes.c_double), ("ms_inverse", ctypes.c_double),
+                ("ms_tier0", ctypes.c_double), ("ms_tier1", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Loads libskis.so (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libskis.so is not built (%s); run python -m paper_1709_03565_amd.build" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        P, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+        L.skis_default_options.argtypes = [ctypes.POINTER(Options)]
+        L.skis_default_options.restype = None
+        L.skis_preprocess.argtypes = [i32, i64, P, P, P, P, P, P, P, P, P, P, P]
+        L.skis_preprocess.restype = ctypes.c_int
+        L.skis_build_sketch.argtypes = [i32, i64, P, P, P, u64, u64, ctypes.POINTER(Options), P,
+                                        ctypes.POINTER(P)]
+        L.skis_build_sketch.restype = ctypes.c_int
+        L.skis_sketch_info.argtypes = [P, ctypes.POINTER(Info)]
+        L.skis_sketch_info.restype = ctypes.c_int
+        L.skis_estimate.argtypes = [P, i32, P, P, P, P, P]
+        L.skis_estimate.restype = ctypes.c_int
+        L.skis_greedy_max_cover.argtypes = [P, i32, P, P, P, P, P]
+        L.skis_greedy_max_cover.restype = ctypes.c_int
+        L.skis_sketch_export.argtypes = [P, P, P, P, P, P]
+        L.skis_sketch_export.restype = ctypes.c_int
+        L.skis_inverse_export.argtypes = [P, P, P, P]
+        L.skis_inverse_export.restype = ctypes.c_int
+        L.skis_node_q.argtypes = [P, P, P]
+        L.skis_node_q.restype = ctypes.c_int
+        L.skis_sketch_free.argtypes = [P]
+        L.skis_sketch_free.restype = None
+        L.skis_last_error.argtypes = []
+        L.skis_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(code: int) -> int:
+    if code < 0:
+        raise SkisError(code, lib().skis_last_error().decode())
+    return code
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, dtype):
+    if not isinstance(t, torch.Tensor):
+        t = torch.as_tensor(t)
+    return t.to(device="cuda", dtype=dtype).contiguous()
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() else ctypes.c_void_p(0)
+
+
+def default_options(**kw) -> Options:
+    o = Options()
+    lib().skis_default_options(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def preprocess(row_ptr, col, w):
+    """Rows a1-a3 into new device tensors: dict(P, q, W, thr, alias, C, Gamma, status)."""
+    row_ptr, col, w = _dev(row_ptr, torch.int32), _dev(col, torch.int32), _dev(w, torch.float32)
+    n, m = row_ptr.numel() - 1, col.numel()
+    P = torch.empty(max(m, 1), dtype=torch.float64, device="cuda")
+    q = torch.empty(n, dtype=torch.float64, device="cuda")
+    W = torch.empty(n, dtype=torch.int64, device="cuda")
+    thr = torch.empty(n, dtype=torch.int64, device="cuda")
+    alias = torch.empty(n, dtype=torch.int32, device="cuda")
+    C = ctypes.c_uint64()
+    G = ctypes.c_double()
+    st = _check(lib().skis_preprocess(n, m, _ptr(row_ptr), _ptr(col), _ptr(w), _ptr(P), _ptr(q), _ptr(W),
+                                      _ptr(thr), _ptr(alias), ctypes.byref(C), ctypes.byref(G), _stream()))
+    return dict(P=P[:m], q=q, W=W, thr=thr, alias=alias, C=C.value, Gamma=G.value, status=st)
+
+
+@dataclass
+class SketchInfo:
+    n: int
+    T: int
+    entries: int
+    probed_total: int
+    deferred: int
+    C: int
+    Gamma: float
+    device_bytes: int
+    ms_preprocess: float
+    ms_roots: float
+    ms_sample: float
+    ms_compact: float
+    ms_inverse: float
+    ms_tier0: float
+    ms_tier1: float
+
+
+class Sketch:
+    """A device-resident SKIS sketch (owned by libskis; freed by free() or on GC)."""
+
+    def __init__(self, handle, status):
+        self._h = handle
+        self.status = status
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def free(self):
+        if self._h:
+            lib().skis_sketch_free(self._h)
+            self._h = None
+
+    def info(self) -> SketchInfo:
+        i = Info()
+        _check(lib().skis_sketch_info(self._h, ctypes.byref(i)))
+        return SketchInfo(i.n, i.T, i.entries, i.probed_total, i.deferred, i.C, i.Gamma, i.device_bytes,
+                          i.ms_preprocess, i.ms_roots, i.ms_sample, i.ms_compact, i.ms_inverse,
+                          i.ms_tier0, i.ms_tier1)
+
+    def estimate(self, set_ptr, set_nodes):
+        """(cov uint64[Q], est float64[Q]) device tensors for seed sets in CSR form."""
+        set_ptr, set_nodes = _dev(set_ptr, torch.int64), _dev(set_nodes, torch.int32)
+        Q = set_ptr.numel() - 1
+        cov = torch.empty(max(Q, 1), dtype=torch.int64, device="cuda")
+        est = torch.empty(max(Q, 1), dtype=torch.float64, device="cuda")
+        _check(lib().skis_estimate(self._h, Q, _ptr(set_ptr), _ptr(set_nodes), _ptr(cov), _ptr(est), _stream()))
+        return cov[:Q], est[:Q]
+
+    def greedy(self, k: int):
+        """(seeds int32[k], marginal uint64[k], cov, est) of Alg. 3."""
+        seeds = torch.empty(max(k, 1), dtype=torch.int32, device="cuda")
+        marg = torch.empty(max(k, 1), dtype=torch.int64, device="cuda")
+        cov, est = ctypes.c_uint64(), ctypes.c_double()
+        _check(lib().skis_greedy_max_cover(self._h, k, _ptr(seeds), _ptr(marg), ctypes.byref(cov),
+                                           ctypes.byref(est), _stream()))
+        return seeds[:k], marg[:k], cov.value, est.value
+
+    def export(self):
+        """(sample_ptr int64[T+1], nodes int32[entries], roots int32[T], probed uint64[T])."""
+        inf = self.info()
+        sp = torch.empty(inf.T + 1, dtype=torch.int64, device="cuda")
+        nodes = torch.empty(max(inf.entries, 1), dtype=torch.int32, device="cuda")
+        roots = torch.empty(max(inf.T, 1), dtype=torch.int32, device="cuda")
+        probed = torch.empty(max(inf.T, 1), dtype=torch.int64, device="cuda")
+        _check(lib().skis_sketch_export(self._h, _ptr(sp), _ptr(nodes), _ptr(roots), _ptr(probed), _stream()))
+        return sp, nodes[:inf.entries], roots[:inf.T], probed[:inf.T]
+
+    def inverse(self):
+        inf = self.info()
+        node_ptr = torch.empty(inf.n + 1, dtype=torch.int64, device="cuda")
+        ns = torch.empty(max(inf.entries, 1), dtype=torch.int32, device="cuda")
+        _check(lib().skis_inverse_export(self._h, _ptr(node_ptr), _ptr(ns), _stream()))
+        return node_ptr, ns[:inf.entries]
+
+    def q(self):
+        inf = self.info()
+        q = torch.empty(inf.n, dtype=torch.float64, device="cuda")
+        _check(lib().skis_node_q(self._h, _ptr(q), _stream()))
+        return q
+
+
+def build_sketch(row_ptr, col, w, num_samples: int, seed: int, options: Options | None = None, **kw) -> Sketch:
+    """Builds a sketch of num_samples IIS samples on the current device and stream."""
+    row_ptr, col, w = _dev(row_ptr, torch.int32), _dev(col, torch.int32), _dev(w, torch.float32)
+    n, m = row_ptr.numel() - 1, col.numel()
+    opt = options if options is not None else default_options(**kw)
+    h = ctypes.c_void_p()
+    st = _check(lib().skis_build_sketch(n, m, _ptr(row_ptr), _ptr(col), _ptr(w), num_samples, seed,
+                                        ctypes.byref(opt), _stream(), ctypes.byref(h)))
+    return Sketch(h, st)

@@ -1,0 +1,302 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle on the same seeded
+inputs: bit-exact for every integer array (prefix products and gamma included, since both
+sides compute them in the same order), FP64 estimates within 1e-12 relative."""
+import os
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1709_03565_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-12
+
+
+def _say(*a):
+    print("[gpu-parity]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def skis():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1709_03565_amd import skis as s
+    s.lib()
+    return s
+
+
+def _np(t):
+    return t.cpu().numpy()
+
+
+def _assert_sketch_equal(sk_gpu, ora, j0=0):
+    sp, nodes, roots, probed = (_np(x) for x in sk_gpu.export())
+    T = ora.T
+    assert np.array_equal(sp[j0:j0 + T + 1] - sp[j0], ora.sample_ptr)
+    assert np.array_equal(nodes[sp[j0]:sp[j0 + T]], ora.nodes)
+    assert np.array_equal(roots[j0:j0 + T], ora.roots)
+    assert np.array_equal(probed[j0:j0 + T].astype(np.uint64), ora.probed)
+
+
+# ---------------------------------------------------------------------------------------
+# a1-a3: preprocessing
+# ---------------------------------------------------------------------------------------
+def _special_graph(seed=3, n=400, m=3000):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    src = rng.integers(0, n, m)
+    dst = rng.integers(0, n, m)
+    keep = src != dst
+    vals = np.array([0.0, 1.0, 0.5, 0.25, 0.1, 0.01, 0.001, 1e-7, 0.999], np.float32)
+    w = vals[rng.integers(0, len(vals), keep.sum())]
+    w = np.where(rng.random(keep.sum()) < 0.5, rng.random(keep.sum()).astype(np.float32), w)
+    return inputs.edges_to_in_csr(n, src[keep], dst[keep], w)
+
+
+@pytest.mark.parametrize("which", ["cl15k_wc", "special", "tri_small"])
+def test_preprocess_bit_exact(skis, which):
+    _say("preprocess", which)
+    if which == "cl15k_wc":
+        g = inputs.workload_graph("cl15k_wc")
+        row_ptr, col, w = g.row_ptr, g.col, g.w
+    elif which == "special":
+        row_ptr, col, w = _special_graph()
+    else:
+        g = inputs.chung_lu_graph(20000, 200000, 2.0, 9, "tri", cache=False)
+        row_ptr, col, w = g.row_ptr, g.col, g.w
+    out = skis.preprocess(row_ptr, col, w)
+    P, q = oracle.row_prefix(row_ptr, w)
+    assert np.array_equal(_np(out["P"]), P)
+    assert np.array_equal(_np(out["q"]), q)
+    W, C, _ = oracle.root_weights(q)
+    assert np.array_equal(_np(out["W"]).astype(np.uint64), W)
+    assert out["C"] == C
+    assert out["Gamma"] == oracle.gamma_total(q)
+    thr, alias = oracle.alias_build(W, C)
+    assert np.array_equal(_np(out["thr"]).astype(np.uint64), thr)
+    assert np.array_equal(_np(out["alias"]), alias)
+
+
+# ---------------------------------------------------------------------------------------
+# a4-a7: the sketch
+# ---------------------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def cl15k(skis):
+    g = inputs.workload_graph("cl15k_wc")
+    T = inputs.WORKLOADS["cl15k_wc"]["T"]
+    _say("oracle cl15k T=%d" % T)
+    ora = oracle.build_sketch(g.row_ptr, g.col, g.w, seed=1, j0=0, j1=T, nthreads=8)
+    _say("gpu cl15k T=%d" % T)
+    sk = skis.build_sketch(g.row_ptr, g.col, g.w, T, 1)
+    return g, ora, sk
+
+
+def test_sketch_bit_exact_cl15k(cl15k):
+    g, ora, sk = cl15k
+    inf = sk.info()
+    _say("cl15k info", inf)
+    assert inf.T == ora.T and inf.entries == len(ora.nodes)
+    assert inf.probed_total == int(ora.probed.sum())
+    assert inf.Gamma == ora.Gamma and inf.C == ora.C
+    _assert_sketch_equal(sk, ora)
+    assert np.array_equal(_np(sk.q()), oracle.row_prefix(g.row_ptr, g.w)[1])
+
+
+@pytest.mark.parametrize("slots,visited,big_row", [(32, 128, 16384), (16, 256, 16384), (32, 256, 16384),
+                                                   (8, 512, 16384), (16, 128, 16384), (32, 128, 8),
+                                                   (16, 128, 100)])
+def test_sketch_identical_across_sampler_shapes(skis, slots, visited, big_row):
+    # big_row = 8 sends most samples through the global-memory tier
+    g = inputs.workload_graph("cl15k_wc")
+    T = 30000
+    _say("shape", slots, visited, big_row)
+    ora = oracle.build_sketch(g.row_ptr, g.col, g.w, seed=11, j0=0, j1=T, nthreads=8)
+    sk = skis.build_sketch(g.row_ptr, g.col, g.w, T, 11, slots_per_block=slots, visited_threshold=visited,
+                           big_row=big_row)
+    inf = sk.info()
+    if big_row == 8:
+        assert inf.deferred > T // 4
+    _assert_sketch_equal(sk, ora)
+
+
+@pytest.mark.parametrize("scale", [2.5, 4.0])
+def test_large_cascades_global_tier(skis, scale):
+    # heavier weights give samples of thousands of nodes: LDS overflow -> global tier;
+    # at scale 4 nearly every sample exceeds the LDS sort limit and is written sorted
+    # straight from its bitmap
+    g = inputs.chung_lu_graph(30000, 300000, 2.1, 77, "wc", cache=False)
+    w = np.minimum(g.w * scale, 1.0).astype(np.float32)
+    T = 2000
+    _say("large cascades", scale)
+    ora = oracle.build_sketch(g.row_ptr, g.col, w, seed=5, j0=0, j1=T, nthreads=8)
+    sizes = np.diff(ora.sample_ptr)
+    if scale > 3:
+        assert (sizes > 8192).mean() > 0.5
+    else:
+        assert (sizes > 256).mean() > 0.5 and sizes.max() <= 8192
+    sk = skis.build_sketch(g.row_ptr, g.col, w, T, 5)
+    assert sk.info().deferred > 0
+    _assert_sketch_equal(sk, ora)
+
+
+def test_tiny_and_degenerate_shapes(skis):
+    cases = []
+    # two-edge star, single edge, deterministic weights, multi-edges, empty rows
+    cases.append((np.array([0, 2, 2, 2], np.int32), np.array([1, 2], np.int32), np.array([0.5, 0.5], np.float32)))
+    cases.append((np.array([0, 0, 1], np.int32), np.array([0], np.int32), np.array([0.25], np.float32)))
+    cases.append((np.array([0, 3, 3, 4, 4], np.int32), np.array([1, 1, 2, 0], np.int32),
+                  np.array([0.3, 0.3, 1.0, 1.0], np.float32)))
+    cases.append((np.array([0, 0, 0, 1], np.int32), np.array([0], np.int32), np.array([1.0], np.float32)))
+    rng = np.random.Generator(np.random.PCG64(12))
+    for _ in range(6):
+        g = inputs.random_tiny_graph(rng, n=int(rng.integers(3, 9)), m=int(rng.integers(2, 12)))
+        cases.append((g.row_ptr, g.col, g.w))
+    for i, (rp, c, w) in enumerate(cases):
+        for T in [1, 7, 1000]:
+            _say("tiny case", i, "T", T)
+            ora = oracle.build_sketch(rp, c, w, seed=3, j0=0, j1=T)
+            sk = skis.build_sketch(rp, c, w, T, 3)
+            _assert_sketch_equal(sk, ora)
+
+
+def test_staging_overflow_retry(skis):
+    g = inputs.workload_graph("cl15k_wc")
+    T = 20000
+    ora = oracle.build_sketch(g.row_ptr, g.col, g.w, seed=2, j0=0, j1=T, nthreads=8)
+    sk = skis.build_sketch(g.row_ptr, g.col, g.w, T, 2, staging_entries=1000)
+    _assert_sketch_equal(sk, ora)
+
+
+def test_deterministic_repeat(skis):
+    g = inputs.workload_graph("cl15k_wc")
+    a = skis.build_sketch(g.row_ptr, g.col, g.w, 50000, 9)
+    b = skis.build_sketch(g.row_ptr, g.col, g.w, 50000, 9)
+    for x, y in zip(a.export(), b.export()):
+        assert torch.equal(x, y)
+    na, sa = a.inverse()
+    nb, sb = b.inverse()
+    assert torch.equal(na, nb)
+
+
+# ---------------------------------------------------------------------------------------
+# a8-a10: inverse index, estimate, greedy
+# ---------------------------------------------------------------------------------------
+def test_inverse_index(cl15k):
+    g, ora, sk = cl15k
+    node_ptr, ns = (_np(x) for x in sk.inverse())
+    onp, ons = oracle.inverse(g.n, ora.sample_ptr, ora.nodes)
+    assert np.array_equal(node_ptr, onp)
+    for v in range(g.n):
+        a, b = onp[v], onp[v + 1]
+        if b - a:
+            assert np.array_equal(np.sort(ns[a:b]), ons[a:b])
+
+
+def test_estimate_parity_config_sets(cl15k):
+    g, ora, sk = cl15k
+    sets = inputs.random_sets(g.n, 100, 50, seed=7)
+    sets += [np.array([], np.int32), np.array([3, 3, 3, 9, 9], np.int32), np.arange(g.n, dtype=np.int32),
+             np.array([g.n - 1, 0], np.int32)]
+    set_ptr, set_nodes = inputs.sets_to_csr(sets)
+    cov, est = sk.estimate(set_ptr, set_nodes)
+    _, q = oracle.row_prefix(g.row_ptr, g.w)
+    ocov, oest = oracle.estimate(g.n, ora.sample_ptr, ora.nodes, q, ora.Gamma, set_ptr=set_ptr, set_nodes=set_nodes)
+    assert np.array_equal(_np(cov).astype(np.uint64), ocov)
+    e = _np(est)
+    assert np.all(np.abs(e - oest) <= REL * np.maximum(np.abs(oest), 1e-300)), np.max(np.abs(e - oest) / np.abs(oest))
+    # repeated calls reuse cleared scratch
+    cov2, est2 = sk.estimate(set_ptr, set_nodes)
+    assert torch.equal(cov, cov2) and torch.equal(est, est2)
+
+
+def test_greedy_parity(cl15k):
+    g, ora, sk = cl15k
+    _, q = oracle.row_prefix(g.row_ptr, g.w)
+    for k in [1, 50]:
+        seeds, marg, cov, est = sk.greedy(k)
+        oseeds, omarg, ocov, oest = oracle.greedy(g.n, ora.sample_ptr, ora.nodes, q, ora.Gamma, k)
+        assert np.array_equal(_np(seeds), oseeds)
+        assert np.array_equal(_np(marg).astype(np.uint64), omarg)
+        assert cov == ocov
+        assert abs(est - oest) <= REL * abs(oest)
+
+
+def test_errors_and_degenerate(skis):
+    g = inputs.workload_graph("cl15k_wc")
+    bad_col = g.col.copy()
+    bad_col[5] = g.n
+    with pytest.raises(skis.SkisError) as ei:
+        skis.build_sketch(g.row_ptr, bad_col, g.w, 10, 1)
+    assert ei.value.code == skis.SKIS_EINVAL
+    bad_w = g.w.copy()
+    bad_w[7] = np.nan
+    with pytest.raises(skis.SkisError):
+        skis.build_sketch(g.row_ptr, g.col, bad_w, 10, 1)
+    loop = g.col.copy()
+    v = int(np.argmax(np.diff(g.row_ptr) > 0))
+    loop[g.row_ptr[v]] = v
+    with pytest.raises(skis.SkisError):
+        skis.build_sketch(g.row_ptr, loop, g.w, 10, 1)
+    with pytest.raises(skis.SkisError):
+        skis.build_sketch(g.row_ptr, g.col, g.w, 0, 1)
+    with pytest.raises(skis.SkisError) as ei:
+        skis.build_sketch(g.row_ptr, g.col, g.w, 1000, 1, max_device_bytes=1 << 16)
+    assert ei.value.code == skis.SKIS_ENOMEM
+    sk = skis.build_sketch(g.row_ptr, g.col, g.w, 1000, 1)
+    with pytest.raises(skis.SkisError):
+        sk.greedy(0)
+    with pytest.raises(skis.SkisError):
+        sk.greedy(g.n + 1)
+    with pytest.raises(skis.SkisError):
+        sk.estimate(np.array([0, 1]), np.array([g.n], np.int32))
+    nb = skis.build_sketch(g.row_ptr, g.col, g.w, 1000, 1, build_inverse_index=0)
+    with pytest.raises(skis.SkisError):
+        nb.estimate(np.array([0, 1]), np.array([0], np.int32))
+    # Gamma = 0: empty sketch, warning status, I_hat(S) = |S|
+    rp = np.array([0, 1, 2, 2], np.int32)
+    c = np.array([1, 2], np.int32)
+    w0 = np.zeros(2, np.float32)
+    d = skis.build_sketch(rp, c, w0, 100, 1)
+    assert d.status == skis.SKIS_WDEGENERATE and d.info().T == 0
+    cov, est = d.estimate(np.array([0, 2, 3]), np.array([0, 1, 2], np.int32))
+    assert _np(cov).tolist() == [0, 0] and _np(est).tolist() == [2.0, 1.0]
+    seeds, marg, cov, est = d.greedy(2)
+    assert _np(seeds).tolist() == [0, 1] and cov == 0 and est == 2.0
+
+
+# ---------------------------------------------------------------------------------------
+# Full-size workload (1M nodes, 20M edges, 2^24 samples): sampled windows bit-exact
+# ---------------------------------------------------------------------------------------
+def test_full_size_windows_cl1m(skis):
+    name = "cl1m_wc"
+    g = inputs.workload_graph(name)
+    T = inputs.WORKLOADS[name]["T"]
+    _say("full-size build", name, T)
+    sk = skis.build_sketch(g.row_ptr, g.col, g.w, T, inputs.SAMPLE_SEED)
+    inf = sk.info()
+    _say("info", inf)
+    sp, nodes, roots, probed = (_np(x) for x in sk.export())
+    rng = np.random.Generator(np.random.PCG64(2024))
+    windows = [(0, 1 << 13), (T - 512, T)] + [(int(s), int(s) + 512) for s in rng.integers(0, T - 512, 12)]
+    for j0, j1 in windows:
+        ora = oracle.build_sketch(g.row_ptr, g.col, g.w, seed=inputs.SAMPLE_SEED, j0=j0, j1=j1, nthreads=8)
+        assert np.array_equal(sp[j0:j1 + 1] - sp[j0], ora.sample_ptr)
+        assert np.array_equal(nodes[sp[j0]:sp[j1]], ora.nodes)
+        assert np.array_equal(roots[j0:j1], ora.roots)
+        assert np.array_equal(probed[j0:j1].astype(np.uint64), ora.probed)
+    # properties at any size
+    assert sp[-1] == inf.entries and int(probed.sum()) == inf.probed_total
+    sizes = np.diff(sp)
+    assert sizes.min() >= 2
+    # coverage of a few sets equals a brute-force count over the exported sketch
+    sets = inputs.random_sets(g.n, 4, 30, seed=5)
+    set_ptr, set_nodes = inputs.sets_to_csr(sets)
+    cov, est = sk.estimate(set_ptr, set_nodes)
+    owner = np.repeat(np.arange(T), sizes)
+    for i, S in enumerate(sets):
+        hit = np.isin(nodes, S)
+        assert int(_np(cov)[i]) == len(np.unique(owner[hit]))
