@@ -172,7 +172,6 @@ int skis_build_sketch(int32_t n, int64_t m, const int32_t *row_ptr, const int32_
                 sk.ms_preprocess = ms;
                 sk.Gamma = prep.Gamma;
                 sk.C = prep.C;
-                sk.q.swap(prep.q);
                 if (prep.C == 0) {
                     status = SKIS_WDEGENERATE;
                     sk.T = 0;
@@ -187,6 +186,8 @@ int skis_build_sketch(int32_t n, int64_t m, const int32_t *row_ptr, const int32_
                     cfg.staging_entries = opt.staging_entries;
                     skis::sample_and_compact(sk.arena, prep, n, m, num_samples, seed, cfg, sk, stream);
                 }
+                // q moves into the sketch only after every kernel that reads prep.q has run
+                sk.q.swap(prep.q);
             } // preprocessing buffers released here
             if (opt.build_inverse_index) {
                 SKIS_HIP_TRY(hipEventRecord(e0, stream));

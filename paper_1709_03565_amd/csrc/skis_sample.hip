@@ -37,7 +37,7 @@ __global__ __launch_bounds__(256) void k_roots(uint64_t j0, uint32_t count, uint
                                                int32_t n, uint64_t C, const AliasEntry *__restrict__ alias,
                                                const int32_t *__restrict__ row_ptr, const double *__restrict__ q,
                                                const double *__restrict__ P, const uint2 *__restrict__ edges,
-                                               int4 *__restrict__ rec, int32_t *__restrict__ u1)
+                                               int4 *__restrict__ rec, int32_t *__restrict__ u1, int *__restrict__ err)
 {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
         const uint64_t j = j0 + i;
@@ -48,7 +48,19 @@ __global__ __launch_bounds__(256) void k_roots(uint64_t j0, uint32_t count, uint
         const uint64_t r = __umul64hi(Y, C);
         const AliasEntry ae = alias[b];
         const int32_t root = r < ae.thr ? (int32_t)b : ae.alias;
+        if (root < 0 || root >= n) { // cannot happen for a valid table; never index with it
+            atomicOr(err, 8);
+            rec[i] = make_int4(0, 0, 0, 0);
+            u1[i] = 0;
+            continue;
+        }
         const int32_t rb = row_ptr[root], re = row_ptr[root + 1];
+        if (re <= rb) { // a root has gamma > 0, hence an in-edge
+            atomicOr(err, 8);
+            rec[i] = make_int4(root, rb, rb, rb);
+            u1[i] = root;
+            continue;
+        }
         philox2x64(0u, jl, jh, TAG_FIRST, seed_lo, seed_hi, X, Y);
         const double U = (double)(X >> 11) * 0x1p-53;
         const double theta = __dmul_rn(U, __dsub_rn(1.0, q[root]));
@@ -72,6 +84,7 @@ struct SampleArgs {
     int32_t n;
     const int32_t *row_ptr;
     const uint4 *pairs;         // edges as aligned pairs (col[2p], w[2p], col[2p+1], w[2p+1])
+    int64_t npairs;
     const int4 *rec;
     const int32_t *u1;
     uint64_t j0;
@@ -231,6 +244,11 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                 }
                 if (want && myid < a.id_count) {
                     const uint32_t i = a.id_list ? a.id_list[myid] : (uint32_t)myid;
+                    const int4 rr = a.rec[i];
+                    if ((uint32_t)rr.x >= (uint32_t)n || (uint32_t)a.u1[i] >= (uint32_t)n || rr.y < rr.z ||
+                        rr.w <= rr.y || (int64_t)rr.w > 2 * a.npairs) {
+                        atomicOr(a.overflow, 8); // bounds guard: the sample is left out
+                    } else {
                     const int4 r = a.rec[i];
                     const int32_t u = a.u1[i];
                     s_idx[s] = i;
@@ -259,6 +277,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                     }
                     f = nf;
                     s_flags[s] = f;
+                    }
                 }
             }
             // items: the root item (edges after i*) and then unexpanded nodes, slot by slot
@@ -359,8 +378,13 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                 end = s_rie[s];
             } else {
                 const int32_t x = list_ptr(s)[s_ifirst[s] + t - s_irp[s]];
-                beg = a.row_ptr[x];
-                end = a.row_ptr[x + 1];
+                if ((uint32_t)x >= (uint32_t)n) { // bounds guard: report, never index
+                    atomicOr(a.overflow, 4);
+                    beg = end = 0;
+                } else {
+                    beg = a.row_ptr[x];
+                    end = a.row_ptr[x + 1];
+                }
                 atomicAdd(&s_probed[s], (unsigned long long)(end - beg));
                 if (!GLOBAL && (uint32_t)(end - beg) > a.big_row) {
                     atomicOr(&s_flags[s], F_DEFER);
@@ -408,6 +432,10 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
             if (!GLOBAL && (s_flags[s] & F_DEFER)) continue;
             const int beg = it_beg[lo], end = it_end[lo];
             const int p = (beg >> 1) + (idx - it_pb[lo]);
+            if (p < 0 || (int64_t)p >= a.npairs) { // bounds guard: report, never index
+                atomicOr(a.overflow, 2);
+                continue;
+            }
             const uint4 pr = a.pairs[p];
             const uint64_t j = a.j0 + s_idx[s];
             uint64_t X, Y;
@@ -639,14 +667,27 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
     } evg{ev};
     bool ran_tier1 = false;
 
+    // every device buffer a kernel below dereferences must exist (checked on the host)
+    auto need = [](const void *p, const char *what) {
+        if (!p) throw Error{SKIS_EHIP, std::string("internal error: null device buffer ") + what};
+    };
+    need(prep.alias.ptr, "alias");
+    need(prep.row_ptr.ptr, "row_ptr");
+    need(prep.q.ptr, "q");
+    need(prep.P.ptr, "P");
+    need(prep.edges.ptr, "edges");
+
     DevBuf<int4> rec;
     DevBuf<int32_t> u1;
     rec.alloc(arena, count);
     u1.alloc(arena, count);
+    DevBuf<int> rerr;
+    rerr.alloc(arena, 1);
+    hipLaunchKernelGGL(k_fill<int>, dim3(1), dim3(64), 0, s, (uint64_t)1, rerr.ptr, 0);
     SKIS_HIP_TRY(hipEventRecord(ev[0], s));
     hipLaunchKernelGGL(k_roots, dim3(grid_cap(count, 256, 64)), dim3(256), 0, s, (uint64_t)0, count, seed_lo, seed_hi,
                        n, prep.C, prep.alias.ptr, prep.row_ptr.ptr, prep.q.ptr, prep.P.ptr, prep.edges.ptr, rec.ptr,
-                       u1.ptr);
+                       u1.ptr, rerr.ptr);
     SKIS_HIP_TRY(hipGetLastError());
     SKIS_HIP_TRY(hipEventRecord(ev[1], s));
 
@@ -682,6 +723,7 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
         A.n = n;
         A.row_ptr = prep.row_ptr.ptr;
         A.pairs = reinterpret_cast<const uint4 *>(prep.edges.ptr);
+        A.npairs = (int64_t)(prep.edges.count / 2);
         A.rec = rec.ptr;
         A.u1 = u1.ptr;
         A.j0 = 0;
@@ -703,6 +745,12 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
         A.n_medium = &ctr.ptr->n_medium;
         A.overflow = &ctr.ptr->overflow;
         A.words = words;
+        for (const void *p : {(const void *)A.row_ptr, (const void *)A.pairs, (const void *)A.rec, (const void *)A.u1,
+                              (const void *)A.next, (const void *)A.staging, (const void *)A.stage_used,
+                              (const void *)A.out_size, (const void *)A.out_off, (const void *)A.out_probed,
+                              (const void *)A.deferred, (const void *)A.n_deferred, (const void *)A.medium,
+                              (const void *)A.n_medium, (const void *)A.overflow})
+            need(p, "sampler argument");
         SKIS_HIP_TRY(hipEventRecord(ev[4], s));
         hipLaunchKernelGGL(t0, dim3(nb0), dim3(256), 0, s, A);
         SKIS_HIP_TRY(hipGetLastError());
@@ -723,6 +771,9 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
             A.id_count = hc.n_deferred;
             A.gbits = gbits.ptr;
             A.glist = glist.ptr;
+            need(A.gbits, "gbits");
+            need(A.glist, "glist");
+            need(A.id_list, "deferred list");
             SKIS_HIP_TRY(hipEventRecord(ev[6], s));
             hipLaunchKernelGGL(kTier1, dim3(nb1), dim3(256), 0, s, A);
             SKIS_HIP_TRY(hipGetLastError());
@@ -731,6 +782,12 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
             SKIS_HIP_TRY(hipMemcpyAsync(&hc, ctr.ptr, sizeof(hc), hipMemcpyDeviceToHost, s));
             SKIS_HIP_TRY(hipStreamSynchronize(s));
         }
+        int herr = 0;
+        SKIS_HIP_TRY(hipMemcpyAsync(&herr, rerr.ptr, sizeof(int), hipMemcpyDeviceToHost, s));
+        SKIS_HIP_TRY(hipStreamSynchronize(s));
+        if ((hc.overflow & ~1) || herr)
+            throw Error{SKIS_EHIP, "internal bounds check failed in the sampler (flags " +
+                                       std::to_string(hc.overflow | herr) + ")"};
         if (!hc.overflow) break;
         cap = hc.stage_used + 1024; // every size is known now: exact retry
         staging.reset();
