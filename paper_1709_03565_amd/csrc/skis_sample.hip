@@ -308,7 +308,10 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                 }
             }
             const int total = __shfl(tincl, 63, 64);
-            const unsigned long long amask = __ballot(own && (f & F_ACTIVE));
+            // the workgroup stays while a slot is active or was just finished: a finished
+            // slot takes a new sample only in the next pass, and the ids already taken
+            // from the global counter must not be dropped
+            const unsigned long long amask = __ballot(own && ((f & F_ACTIVE) || f == F_CLEAR));
             if (s == 0) {
                 s_ibase[S] = total;
                 s_nitems = total;
@@ -544,6 +547,16 @@ __global__ __launch_bounds__(256) void k_gather_medium(uint64_t count, const uin
         for (int t = threadIdx.x; t < sz; t += 256) dst[t] = buf[t];
         __syncthreads();
     }
+}
+
+__global__ __launch_bounds__(256) void k_count_value(uint64_t count, const uint32_t *__restrict__ x, uint32_t v,
+                                                     unsigned long long *__restrict__ out)
+{
+    unsigned long long acc = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (uint64_t)gridDim.x * blockDim.x)
+        acc += x[i] == v ? 1ull : 0ull;
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0 && acc) atomicAdd(out, acc);
 }
 
 __global__ __launch_bounds__(256) void k_roots_out(uint32_t count, const int4 *__restrict__ rec, int32_t *__restrict__ roots)
@@ -794,6 +807,17 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
         if (attempt == 1) throw Error{SKIS_ENOMEM, "staging overflow after resize"};
     }
     SKIS_HIP_TRY(hipEventRecord(ev[2], s));
+
+    // every sample must have finished in one of the two tiers
+    hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(1), dim3(64), 0, s, (uint64_t)1, &ctr.ptr->next, 0ull);
+    hipLaunchKernelGGL(k_count_value, dim3(grid_cap(count, 256)), dim3(256), 0, s, (uint64_t)count, out_size.ptr,
+                       DEFERRED, &ctr.ptr->next);
+    SKIS_HIP_TRY(hipGetLastError());
+    unsigned long long unfinished = 0;
+    SKIS_HIP_TRY(hipMemcpyAsync(&unfinished, &ctr.ptr->next, sizeof(unfinished), hipMemcpyDeviceToHost, s));
+    SKIS_HIP_TRY(hipStreamSynchronize(s));
+    if (unfinished)
+        throw Error{SKIS_EHIP, "internal error: " + std::to_string(unfinished) + " samples did not finish"};
 
     // CSR: sample_ptr = exclusive scan of sizes, then sorted copies
     sk.T = count;
