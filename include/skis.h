@@ -124,10 +124,10 @@ int skis_sketch_info(const skis_sketch *sk, skis_info *info /* host */);
  *   cov[i] = Cov(S_i) = #{ j : R_j meets S_i }                     (uint64, exact)
  *   est[i] = fl(fl(cov * Gamma) / T) + sum_{v in S_i} q_v            (fp64; the sum is
  *            compensated, so est agrees with an exactly rounded sum to ~1e-15 relative)
- * For a degenerate sketch (T = 0) the first term is 0.  A set may hold at most 4096
- * entries (duplicates included).  Blocking.
- * Errors: SKIS_EINVAL (node id out of range, set_ptr not nondecreasing, a set above 4096
- * entries, Q < 0, sketch built without the inverse index).
+ * For a degenerate sketch (T = 0) the first term is 0.  Sets of any size are accepted
+ * (sets above 4096 entries take a slower chunked path).  Blocking.
+ * Errors: SKIS_EINVAL (node id out of range, set_ptr not nondecreasing from 0, Q < 0,
+ * sketch built without the inverse index).
  */
 int skis_estimate(const skis_sketch *sk, int32_t num_sets, const int64_t *set_ptr, const int32_t *set_nodes,
                   uint64_t *cov, double *est, hipStream_t stream);

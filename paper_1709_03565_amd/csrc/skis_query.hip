@@ -8,6 +8,9 @@
 #include "skis_internal.h"
 #include "skis_query.h"
 
+#include <algorithm>
+#include <vector>
+
 namespace skis {
 
 __device__ __forceinline__ void neumaier_add(double &s, double &c, double x)
@@ -39,13 +42,21 @@ __device__ void bitonic_sort_lds(int32_t *buf, int P)
     }
 }
 
-// One workgroup per query of the batch [q0, q0 + gridDim.x).
-__global__ __launch_bounds__(EST_BLOCK) void k_estimate(int64_t q0, const int64_t *__restrict__ set_ptr,
+// One workgroup per query.  The set is taken in chunks of EST_MAX_SET entries; each chunk is
+// sorted and deduplicated in LDS.  LARGE workgroups (sets above one chunk) also keep a
+// bitmap of n bits that drops ids already met in an earlier chunk.  The distinct members'
+// q values are summed (compensated, in a fixed order) and their sample lists H(v) are
+// walked flat across the workgroup, flipping one bit per sample in a bitmap of T bits;
+// Cov(S) is the number of flips.
+template <bool LARGE>
+__global__ __launch_bounds__(EST_BLOCK) void k_estimate(const int64_t *__restrict__ qlist, int64_t q0,
+                                                        const int64_t *__restrict__ set_ptr,
                                                         const int32_t *__restrict__ set_nodes, int32_t n, uint64_t T,
                                                         double Gamma, const double *__restrict__ qv,
                                                         const int64_t *__restrict__ node_ptr,
                                                         const int32_t *__restrict__ node_samples,
                                                         uint32_t *__restrict__ bitmaps, uint64_t wordsT,
+                                                        uint32_t *__restrict__ nodebits, uint64_t wordsN,
                                                         unsigned long long *__restrict__ cov_out,
                                                         double *__restrict__ est_out, int *__restrict__ err)
 {
@@ -57,100 +68,109 @@ __global__ __launch_bounds__(EST_BLOCK) void k_estimate(int64_t q0, const int64_
     __shared__ unsigned long long s_cov[EST_BLOCK / 64];
     __shared__ int s_bad;
 
-    const int64_t qi = q0 + blockIdx.x;
+    const int64_t qi = LARGE ? qlist[q0 + blockIdx.x] : q0 + blockIdx.x;
     const int tid = threadIdx.x;
     const int64_t a = set_ptr[qi], b = set_ptr[qi + 1];
     const int64_t k = b - a;
-    if (tid == 0) s_bad = 0;
-    __syncthreads();
-    if (k < 0 || k > EST_MAX_SET) {
-        if (tid == 0) atomicOr(err, k < 0 ? 1 : 2);
+    if (k < 0) {
+        if (tid == 0) atomicOr(err, 1);
         return;
     }
-    int P = 1;
-    while (P < k) P <<= 1;
-    for (int t = tid; t < P; t += EST_BLOCK) {
-        int32_t v = INT32_MAX;
-        if (t < k) {
-            v = set_nodes[a + t];
-            if (v < 0 || v >= n) {
-                s_bad = 1;
-                v = INT32_MAX;
-            }
-        }
-        buf[t] = v;
-    }
-    __syncthreads();
-    if (s_bad) {
-        if (tid == 0) atomicOr(err, 4);
-        return;
-    }
-    if (P > 1) bitonic_sort_lds<EST_BLOCK>(buf, P);
-
-    // distinct members, in ascending order, compacted to the front of buf
+    if (!LARGE && k > EST_MAX_SET) return; // taken by the LARGE launch
+    uint32_t *bm = bitmaps + (uint64_t)blockIdx.x * wordsT;
+    uint32_t *nb = LARGE ? nodebits + (uint64_t)blockIdx.x * wordsN : nullptr;
     constexpr int IPT = EST_MAX_SET / EST_BLOCK;
-    int32_t mine[IPT];
-    int flags = 0, cntu = 0;
-#pragma unroll
-    for (int r = 0; r < IPT; ++r) {
-        const int t = tid * IPT + r;
-        const int32_t v = t < k ? buf[t] : INT32_MAX;
-        mine[r] = v;
-        const bool u = t < k && (t == 0 || buf[t - 1] != v);
-        flags |= (u ? 1 : 0) << r;
-        cntu += u ? 1 : 0;
-    }
-    int nu;
-    int pos = block_excl_scan<EST_BLOCK, int>(cntu, s_scan, &nu);
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < IPT; ++r)
-        if (flags >> r & 1) buf[pos++] = mine[r];
-    __syncthreads();
 
-    // sum of q over distinct members: strided Neumaier, combined in thread order
     double sq = 0.0, cq = 0.0;
-    for (int t = tid; t < nu; t += EST_BLOCK) neumaier_add(sq, cq, qv[buf[t]]);
+    unsigned long long local = 0;
+    int nu = 0;
+    int64_t E = 0;
+    for (int64_t c0 = a; c0 < b; c0 += EST_MAX_SET) {
+        const int kc = (int)((b - c0) < EST_MAX_SET ? (b - c0) : EST_MAX_SET);
+        if (tid == 0) s_bad = 0;
+        __syncthreads();
+        int P = 1;
+        while (P < kc) P <<= 1;
+        for (int t = tid; t < P; t += EST_BLOCK) {
+            int32_t v = INT32_MAX;
+            if (t < kc) {
+                v = set_nodes[c0 + t];
+                if (v < 0 || v >= n) {
+                    s_bad = 1;
+                    v = INT32_MAX;
+                }
+            }
+            buf[t] = v;
+        }
+        __syncthreads();
+        if (s_bad) {
+            if (tid == 0) atomicOr(err, 4);
+            return;
+        }
+        if (P > 1) bitonic_sort_lds<EST_BLOCK>(buf, P);
+
+        // distinct members of the chunk (and, for LARGE, not met before), compacted in order
+        int32_t mine[IPT];
+        int flags = 0, cntu = 0;
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) {
+            const int t = tid * IPT + r;
+            const int32_t v = t < kc ? buf[t] : INT32_MAX;
+            mine[r] = v;
+            bool u = t < kc && (t == 0 || buf[t - 1] != v);
+            if (LARGE && u) {
+                const uint32_t bit = 1u << (v & 31);
+                u = !(atomicOr(&nb[v >> 5], bit) & bit);
+            }
+            flags |= (u ? 1 : 0) << r;
+            cntu += u ? 1 : 0;
+        }
+        int pos = block_excl_scan<EST_BLOCK, int>(cntu, s_scan, &nu);
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < IPT; ++r)
+            if (flags >> r & 1) buf[pos++] = mine[r];
+        __syncthreads();
+
+        for (int t = tid; t < nu; t += EST_BLOCK) neumaier_add(sq, cq, qv[buf[t]]);
+        int64_t dl[IPT];
+        int64_t acc = 0;
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) {
+            const int t = tid * IPT + r;
+            int64_t d = 0;
+            if (t < nu) {
+                const int32_t v = buf[t];
+                d = node_ptr[v + 1] - node_ptr[v];
+            }
+            dl[r] = acc;
+            acc += d;
+        }
+        const int64_t ex = block_excl_scan<EST_BLOCK, int64_t>(acc, s_scan64, &E);
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) {
+            const int t = tid * IPT + r;
+            if (t < nu) dbase[t] = ex + dl[r];
+        }
+        if (tid == 0) dbase[nu] = E;
+        __syncthreads();
+        for (int64_t idx = tid; idx < E; idx += EST_BLOCK) {
+            int lo = 0, hi = nu - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (dbase[mid] <= idx) lo = mid; else hi = mid - 1;
+            }
+            const int32_t v = buf[lo];
+            const int32_t j = node_samples[node_ptr[v] + (idx - dbase[lo])];
+            const uint32_t bit = 1u << (j & 31);
+            const uint32_t old = atomicOr(&bm[j >> 5], bit);
+            if (!(old & bit)) ++local;
+        }
+        __syncthreads();
+    }
+
     ps[tid] = sq;
     pc[tid] = cq;
-    // prefix of |H(v)| over distinct members
-    int64_t dl[IPT];
-    int64_t acc = 0;
-#pragma unroll
-    for (int r = 0; r < IPT; ++r) {
-        const int t = tid * IPT + r;
-        int64_t d = 0;
-        if (t < nu) {
-            const int32_t v = buf[t];
-            d = node_ptr[v + 1] - node_ptr[v];
-        }
-        dl[r] = acc;
-        acc += d;
-    }
-    int64_t E;
-    const int64_t ex = block_excl_scan<EST_BLOCK, int64_t>(acc, s_scan64, &E);
-#pragma unroll
-    for (int r = 0; r < IPT; ++r) {
-        const int t = tid * IPT + r;
-        if (t < nu) dbase[t] = ex + dl[r];
-    }
-    if (tid == 0) dbase[nu] = E;
-    __syncthreads();
-
-    uint32_t *bm = bitmaps + (uint64_t)blockIdx.x * wordsT;
-    unsigned long long local = 0;
-    for (int64_t idx = tid; idx < E; idx += EST_BLOCK) {
-        int lo = 0, hi = nu - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (dbase[mid] <= idx) lo = mid; else hi = mid - 1;
-        }
-        const int32_t v = buf[lo];
-        const int32_t j = node_samples[node_ptr[v] + (idx - dbase[lo])];
-        const uint32_t bit = 1u << (j & 31);
-        const uint32_t old = atomicOr(&bm[j >> 5], bit);
-        if (!(old & bit)) ++local;
-    }
     local = wave_sum(local);
     if ((tid & 63) == 0) s_cov[tid >> 6] = local;
     __syncthreads();
@@ -166,17 +186,21 @@ __global__ __launch_bounds__(EST_BLOCK) void k_estimate(int64_t q0, const int64_
         cov_out[qi] = c;
         est_out[qi] = __dadd_rn(first, __dadd_rn(s, cc));
     }
-    // leave the bitmap clear for the next query: walk the same entries again
-    __syncthreads();
-    for (int64_t idx = tid; idx < E; idx += EST_BLOCK) {
-        int lo = 0, hi = nu - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (dbase[mid] <= idx) lo = mid; else hi = mid - 1;
+    // leave the bitmaps clear for the next query
+    if (LARGE) {
+        for (uint64_t w = tid; w < wordsT; w += EST_BLOCK) bm[w] = 0u;
+        for (int64_t t = a + tid; t < b; t += EST_BLOCK) nb[set_nodes[t] >> 5] = 0u;
+    } else {
+        for (int64_t idx = tid; idx < E; idx += EST_BLOCK) { // one chunk: buf and dbase still hold it
+            int lo = 0, hi = nu - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (dbase[mid] <= idx) lo = mid; else hi = mid - 1;
+            }
+            const int32_t v = buf[lo];
+            const int32_t j = node_samples[node_ptr[v] + (idx - dbase[lo])];
+            bm[j >> 5] = 0u;
         }
-        const int32_t v = buf[lo];
-        const int32_t j = node_samples[node_ptr[v] + (idx - dbase[lo])];
-        bm[j >> 5] = 0u;
     }
 }
 
@@ -320,6 +344,19 @@ static unsigned gridq(uint64_t items, int block, int per_cu = 8)
 void estimate_batch(const Sketch &sk, QueryScratch &qs, int32_t Q, const int64_t *set_ptr, const int32_t *set_nodes,
                     uint64_t *cov, double *est, hipStream_t s)
 {
+    Arena &arena = const_cast<Arena &>(sk.arena);
+    // set sizes on the host: argument checks and the list of sets above one LDS chunk
+    std::vector<int64_t> hptr((size_t)Q + 1);
+    SKIS_HIP_TRY(hipMemcpyAsync(hptr.data(), set_ptr, sizeof(int64_t) * ((size_t)Q + 1), hipMemcpyDeviceToHost, s));
+    SKIS_HIP_TRY(hipStreamSynchronize(s));
+    std::vector<int64_t> large;
+    for (int32_t i = 0; i < Q; ++i) {
+        const int64_t k = hptr[i + 1] - hptr[i];
+        if (k < 0 || hptr[i] < 0) throw Error{SKIS_EINVAL, "set_ptr must be nondecreasing from 0"};
+        if (k > EST_MAX_SET) large.push_back(i);
+    }
+    if (hptr[Q] > 0 && !set_nodes) throw Error{SKIS_EINVAL, "set_nodes must not be NULL"};
+
     const uint64_t wordsT = (sk.T + 31) / 32;
     const uint64_t per = wordsT ? wordsT : 1;
     // bitmaps for up to `batch` queries at a time, about 256 MiB
@@ -328,26 +365,52 @@ void estimate_batch(const Sketch &sk, QueryScratch &qs, int32_t Q, const int64_t
     if (batch > 4096) batch = 4096;
     if (batch > (uint64_t)Q) batch = (uint64_t)Q;
     if (qs.bitmap_words < batch * per) {
-        qs.bitmaps.alloc(const_cast<Arena &>(sk.arena), batch * per);
+        qs.bitmaps.alloc(arena, batch * per);
         qs.bitmap_words = batch * per;
         hipLaunchKernelGGL(k_fill_q<uint32_t>, dim3(gridq(batch * per, 256)), dim3(256), 0, s, batch * per,
                            qs.bitmaps.ptr, 0u);
         SKIS_HIP_TRY(hipGetLastError());
     }
-    if (!qs.err.ptr) qs.err.alloc(const_cast<Arena &>(sk.arena), 1);
+    if (!qs.err.ptr) qs.err.alloc(arena, 1);
     hipLaunchKernelGGL(k_fill_q<int>, dim3(1), dim3(64), 0, s, (uint64_t)1, qs.err.ptr, 0);
     for (int64_t q0 = 0; q0 < Q; q0 += (int64_t)batch) {
         const int64_t nq = (Q - q0) < (int64_t)batch ? (Q - q0) : (int64_t)batch;
-        hipLaunchKernelGGL(k_estimate, dim3((unsigned)nq), dim3(EST_BLOCK), 0, s, q0, set_ptr, set_nodes, sk.n, sk.T,
-                           sk.Gamma, sk.q.ptr, sk.node_ptr.ptr, sk.node_samples.ptr, qs.bitmaps.ptr, per,
+        hipLaunchKernelGGL(k_estimate<false>, dim3((unsigned)nq), dim3(EST_BLOCK), 0, s, (const int64_t *)nullptr, q0,
+                           set_ptr, set_nodes, sk.n, sk.T, sk.Gamma, sk.q.ptr, sk.node_ptr.ptr, sk.node_samples.ptr,
+                           qs.bitmaps.ptr, per, (uint32_t *)nullptr, (uint64_t)0,
                            reinterpret_cast<unsigned long long *>(cov), est, qs.err.ptr);
         SKIS_HIP_TRY(hipGetLastError());
+    }
+    if (!large.empty()) {
+        const uint64_t wordsN = ((uint64_t)sk.n + 31) / 32;
+        const uint64_t group = std::min<uint64_t>(std::min<uint64_t>(batch, 64), large.size());
+        DevBuf<int64_t> qlist;
+        DevBuf<uint32_t> nodebits;
+        qlist.alloc(arena, large.size());
+        nodebits.alloc(arena, group * wordsN);
+        SKIS_HIP_TRY(hipMemcpyAsync(qlist.ptr, large.data(), sizeof(int64_t) * large.size(), hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_fill_q<uint32_t>, dim3(gridq(group * wordsN, 256)), dim3(256), 0, s, group * wordsN,
+                           nodebits.ptr, 0u);
+        for (uint64_t g0 = 0; g0 < large.size(); g0 += group) {
+            const uint64_t ng = std::min<uint64_t>(group, large.size() - g0);
+            hipLaunchKernelGGL(k_estimate<true>, dim3((unsigned)ng), dim3(EST_BLOCK), 0, s,
+                               (const int64_t *)qlist.ptr, (int64_t)g0, set_ptr, set_nodes, sk.n, sk.T, sk.Gamma,
+                               sk.q.ptr, sk.node_ptr.ptr, sk.node_samples.ptr, qs.bitmaps.ptr, per, nodebits.ptr,
+                               wordsN, reinterpret_cast<unsigned long long *>(cov), est, qs.err.ptr);
+            SKIS_HIP_TRY(hipGetLastError());
+        }
+        SKIS_HIP_TRY(hipStreamSynchronize(s));
     }
     int herr = 0;
     SKIS_HIP_TRY(hipMemcpyAsync(&herr, qs.err.ptr, sizeof(int), hipMemcpyDeviceToHost, s));
     SKIS_HIP_TRY(hipStreamSynchronize(s));
+    if (herr) {
+        // a workgroup that stopped early may have left bits set: clear all scratch
+        hipLaunchKernelGGL(k_fill_q<uint32_t>, dim3(gridq(qs.bitmap_words, 256)), dim3(256), 0, s, qs.bitmap_words,
+                           qs.bitmaps.ptr, 0u);
+        SKIS_HIP_TRY(hipStreamSynchronize(s));
+    }
     if (herr & 1) throw Error{SKIS_EINVAL, "set_ptr must be nondecreasing"};
-    if (herr & 2) throw Error{SKIS_EINVAL, "a seed set has more than 4096 entries"};
     if (herr & 4) throw Error{SKIS_EINVAL, "a seed set holds a node id outside [0, n)"};
 }
 
