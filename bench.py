@@ -158,12 +158,12 @@ def main():
     inf = infos[-1][0]
     ms_step = elapsed * 1000.0 / args.steps
     value = T * args.steps / elapsed
-    sampler_ms = sum(x[0].ms_tier0 + x[0].ms_tier1 for x in infos) / len(infos)
+    sampler_ms = sum(x[0].ms_tier0 + x[0].ms_tier1 + x[0].ms_tier2 for x in infos) / len(infos)
     tier0_ms = sum(x[0].ms_tier0 for x in infos) / len(infos)
     b_alg = algorithmic_bytes(T, inf.entries, inf.probed_total)
     achieved = b_alg / (sampler_ms * 1e-3) / 1e9
     stages = {k: round(sum(getattr(x[0], k) for x in infos) / len(infos), 3) for k in
-              ["ms_preprocess", "ms_roots", "ms_sample", "ms_tier0", "ms_tier1", "ms_compact", "ms_inverse"]}
+              ["ms_preprocess", "ms_roots", "ms_sample", "ms_tier0", "ms_tier1", "ms_tier2", "ms_compact", "ms_inverse"]}
     line = {
         "metric": "SKIS samples/s",
         "value": value,
@@ -189,10 +189,11 @@ def main():
         "entries": inf.entries,
         "probed_total": inf.probed_total,
         "deferred": inf.deferred,
+        "deferred_global": inf.deferred_global,
         "stages_ms": stages,
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_sample (LDS tier + global tier launches)",
+            "kernel": "k_sample (all three tier launches)",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

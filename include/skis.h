@@ -106,12 +106,13 @@ typedef struct skis_info {
     uint64_t T;                  /* samples in the sketch (0 when degenerate) */
     uint64_t entries;            /* sum_j |R_j| */
     uint64_t probed_total;       /* sum_j probed[j] (edges probed) */
-    uint64_t deferred;           /* samples that ran in the global-memory tier */
+    uint64_t deferred;           /* samples that outgrew the first sampler tier */
     uint64_t C;                  /* integer root-weight total */
     double Gamma;                /* sum of gamma_v */
     uint64_t device_bytes;       /* bytes the sketch holds on the device */
     double ms_preprocess, ms_roots, ms_sample, ms_compact, ms_inverse; /* stage times (events) */
-    double ms_tier0, ms_tier1;   /* the LDS-tier and global-tier sampler launches alone */
+    double ms_tier0, ms_tier1, ms_tier2; /* the three sampler tiers' launches alone */
+    uint64_t deferred_global;    /* samples that reached the HBM tier */
 } skis_info;
 
 /* Sketch facts (host out-param). */

@@ -232,6 +232,8 @@ int skis_sketch_info(const skis_sketch *h, skis_info *info)
         info->ms_inverse = sk.ms_inverse;
         info->ms_tier0 = sk.ms_tier0;
         info->ms_tier1 = sk.ms_tier1;
+        info->ms_tier2 = sk.ms_tier2;
+        info->deferred_global = sk.deferred_global;
         return SKIS_OK;
     });
 }

@@ -98,7 +98,8 @@ struct Sketch {
     DevBuf<int64_t> node_ptr;     // [n+1]
     DevBuf<int32_t> node_samples; // [entries]
     double ms_preprocess = 0, ms_roots = 0, ms_sample = 0, ms_compact = 0, ms_inverse = 0;
-    double ms_tier0 = 0, ms_tier1 = 0; // the two sampler launches alone
+    double ms_tier0 = 0, ms_tier1 = 0, ms_tier2 = 0; // the sampler launches alone
+    uint64_t deferred_global = 0;                    // samples that reached the HBM tier
 };
 
 // ---------------------------------------------------------------------------------

@@ -8,9 +8,12 @@ constexpr int EST_BLOCK = 256;    // threads per query in k_estimate
 constexpr int EST_MAX_SET = 4096; // largest seed set one estimate workgroup holds in LDS
 
 struct GreedyState {
-    unsigned done;        // blocks of k_argmax that have finished this round
-    int32_t vstar;        // the pick of the current round
-    unsigned long long cov;
+    unsigned done;            // blocks of the current kernel that have finished
+    int32_t vstar;            // the node of the current iteration
+    int32_t round;            // picks made so far
+    int32_t phase;            // what k_greedy_step does with vstar (recount or select)
+    unsigned long long acc;   // recount accumulator
+    unsigned long long cov;   // coverage of the picks so far
     double est;
 };
 

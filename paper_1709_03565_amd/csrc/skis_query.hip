@@ -2,9 +2,8 @@
 //   k_estimate   Eq. (eq21): Cov(S) by marking the samples of every v in S in a bitmap over
 //                the T samples (a sample counts once, when its bit first flips), and
 //                I_hat(S) = fl(fl(Cov * Gamma) / T) + sum_{v in S} q_v (compensated sum).
-//   k_argmax / k_cover_update   Alg. 3 with incremental Delta: pick the node of largest
-//                gain fl(fl(Delta * Gamma) / T) + q (Eq. margin), smallest id on ties, then
-//                lower Delta of every member of each sample the pick newly covers.
+//   k_greedy_*   Alg. 3: the node of largest gain fl(fl(Delta * Gamma) / T) + q (Eq. margin),
+//                smallest id on ties, with Delta recounted lazily against a covered bitmap.
 #include "skis_internal.h"
 #include "skis_query.h"
 
@@ -205,15 +204,17 @@ __global__ __launch_bounds__(EST_BLOCK) void k_estimate(const int64_t *__restric
 }
 
 // ---------------------------------------------------------------------------------------
-// Greedy (Alg. 3).
+// Greedy (Alg. 3), evaluated lazily.  ub[v] is an upper bound on Delta(v), the number of
+// samples holding v not yet covered (it starts at |H(v)| and only falls, Lemma 8); gain[v]
+// caches fl(fl(ub * Gamma) / T) + q_v, a bound on v's gain because the rounding is
+// monotone.  Each iteration takes the node of largest bound gain (smallest id on ties):
+// if its bound was made exact in this round it is the round's pick, since every other
+// node's exact gain is at most its bound; otherwise its Delta is recounted against the
+// covered bitmap and the iteration repeats.  The picks are those of the plain greedy.
 // ---------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_greedy_init(int32_t n, const int64_t *__restrict__ node_ptr,
-                                                     int32_t *__restrict__ delta, uint8_t *__restrict__ chosen)
+__device__ __forceinline__ double gain_of(uint64_t d, uint64_t T, double Gamma, double q)
 {
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-        delta[v] = (int32_t)(node_ptr[v + 1] - node_ptr[v]);
-        chosen[v] = 0;
-    }
+    return __dadd_rn(T > 0 ? __ddiv_rn(__dmul_rn((double)d, Gamma), (double)T) : 0.0, q);
 }
 
 __device__ __forceinline__ bool better(double g, int32_t v, double bg, int32_t bv)
@@ -221,28 +222,28 @@ __device__ __forceinline__ bool better(double g, int32_t v, double bg, int32_t b
     return bv < 0 || g > bg || (g == bg && v < bv);
 }
 
-__global__ __launch_bounds__(256) void k_argmax(int32_t n, uint64_t T, double Gamma, const int32_t *__restrict__ delta,
-                                                const double *__restrict__ qv, uint8_t *__restrict__ chosen,
-                                                double *__restrict__ part_g, int32_t *__restrict__ part_v,
-                                                GreedyState *__restrict__ st, int round, int32_t *__restrict__ seeds,
-                                                unsigned long long *__restrict__ marg)
+__global__ __launch_bounds__(256) void k_greedy_init(int32_t n, uint64_t T, double Gamma,
+                                                     const int64_t *__restrict__ node_ptr,
+                                                     const double *__restrict__ qv, int64_t *__restrict__ ub,
+                                                     double *__restrict__ gain, int32_t *__restrict__ stamp,
+                                                     uint8_t *__restrict__ chosen)
 {
-    __shared__ double sg[256];
-    __shared__ int32_t sv[256];
-    __shared__ bool last;
-    double bg = 0.0;
-    int32_t bv = -1;
-    const double Td = (double)T;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-        if (chosen[v]) continue;
-        const double g = __dadd_rn(T > 0 ? __ddiv_rn(__dmul_rn((double)delta[v], Gamma), Td) : 0.0, qv[v]);
-        if (better(g, (int32_t)v, bg, bv)) {
-            bg = g;
-            bv = (int32_t)v;
-        }
+        const int64_t d = node_ptr[v + 1] - node_ptr[v];
+        ub[v] = d;
+        gain[v] = gain_of((uint64_t)d, T, Gamma, qv[v]);
+        stamp[v] = -1;
+        chosen[v] = 0;
     }
-    sg[threadIdx.x] = bg;
-    sv[threadIdx.x] = bv;
+}
+
+enum : int { GR_ARGMAX = 0, GR_RECOUNT = 1, GR_SELECT = 2 };
+
+// Block-wide (g, v) reduction in LDS; returns the winner in thread 0.
+__device__ __forceinline__ void block_best(double &g, int32_t &v, double *sg, int32_t *sv)
+{
+    sg[threadIdx.x] = g;
+    sv[threadIdx.x] = v;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if (threadIdx.x < w) {
@@ -254,54 +255,120 @@ __global__ __launch_bounds__(256) void k_argmax(int32_t n, uint64_t T, double Ga
         }
         __syncthreads();
     }
+    g = sg[0];
+    v = sv[0];
+}
+
+__global__ __launch_bounds__(256) void k_greedy_argmax(int32_t n, int32_t k, const double *__restrict__ gain,
+                                                       const uint8_t *__restrict__ chosen,
+                                                       const int32_t *__restrict__ stamp, double *__restrict__ part_g,
+                                                       int32_t *__restrict__ part_v, GreedyState *__restrict__ st)
+{
+    __shared__ double sg[256];
+    __shared__ int32_t sv[256];
+    __shared__ bool last;
+    if (st->round >= k) return;
+    double bg = 0.0;
+    int32_t bv = -1;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        if (chosen[v]) continue;
+        const double g = gain[v];
+        if (better(g, (int32_t)v, bg, bv)) {
+            bg = g;
+            bv = (int32_t)v;
+        }
+    }
+    block_best(bg, bv, sg, sv);
     if (threadIdx.x == 0) {
-        part_g[blockIdx.x] = sg[0];
-        part_v[blockIdx.x] = sv[0];
+        part_g[blockIdx.x] = bg;
+        part_v[blockIdx.x] = bv;
         __threadfence();
-        const unsigned ticket = atomicAdd(&st->done, 1u);
-        last = ticket == gridDim.x - 1;
+        last = atomicAdd(&st->done, 1u) == gridDim.x - 1;
     }
     __syncthreads();
     if (!last) return;
     __threadfence();
-    if (threadIdx.x == 0) {
-        double g = 0.0;
-        int32_t v = -1;
-        for (unsigned b = 0; b < gridDim.x; ++b) {
-            const int32_t pv = __hip_atomic_load(&part_v[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const double pg = __longlong_as_double((long long)__hip_atomic_load(
-                reinterpret_cast<unsigned long long *>(&part_g[b]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-            if (pv >= 0 && better(pg, pv, g, v)) {
-                g = pg;
-                v = pv;
-            }
+    bg = 0.0;
+    bv = -1;
+    for (unsigned b = threadIdx.x; b < gridDim.x; b += 256) {
+        const int32_t pv = __hip_atomic_load(&part_v[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const double pg = __longlong_as_double((long long)__hip_atomic_load(
+            reinterpret_cast<unsigned long long *>(&part_g[b]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        if (pv >= 0 && better(pg, pv, bg, bv)) {
+            bg = pg;
+            bv = pv;
         }
+    }
+    block_best(bg, bv, sg, sv);
+    if (threadIdx.x == 0) {
         st->done = 0u;
-        st->vstar = v;
-        const int32_t d = delta[v];
-        seeds[round] = v;
-        marg[round] = (unsigned long long)d;
-        chosen[v] = 1;
-        st->cov += (unsigned long long)d;
+        if (bv < 0) { // nothing left to pick (cannot happen for k <= n): stop
+            st->round = k;
+            return;
+        }
+        st->vstar = bv;
+        st->phase = stamp[bv] == st->round ? GR_SELECT : GR_RECOUNT;
     }
 }
 
-__global__ __launch_bounds__(256) void k_cover_update(const GreedyState *__restrict__ st,
-                                                      const int64_t *__restrict__ node_ptr,
-                                                      const int32_t *__restrict__ node_samples,
-                                                      const int64_t *__restrict__ sptr,
-                                                      const int32_t *__restrict__ nodes,
-                                                      uint32_t *__restrict__ covered, int32_t *__restrict__ delta)
+// RECOUNT: Delta(v) = #{ j in H(v) : not covered }.  SELECT: cover H(v) and record the pick.
+__global__ __launch_bounds__(256) void k_greedy_step(int32_t k, uint64_t T, double Gamma,
+                                                     const int64_t *__restrict__ node_ptr,
+                                                     const int32_t *__restrict__ node_samples,
+                                                     const double *__restrict__ qv, uint32_t *__restrict__ covered,
+                                                     int64_t *__restrict__ ub, double *__restrict__ gain,
+                                                     int32_t *__restrict__ stamp, uint8_t *__restrict__ chosen,
+                                                     GreedyState *__restrict__ st, int32_t *__restrict__ seeds,
+                                                     unsigned long long *__restrict__ marg)
 {
+    __shared__ unsigned long long s_cnt[4];
+    __shared__ bool last;
+    const int round = st->round;
+    if (round >= k) return;
+    const int phase = st->phase;
     const int32_t v = st->vstar;
     const int64_t a = node_ptr[v], b = node_ptr[v + 1];
+    unsigned long long cnt = 0;
     for (int64_t p = a + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < b; p += (int64_t)gridDim.x * blockDim.x) {
         const int32_t j = node_samples[p];
         const uint32_t bit = 1u << (j & 31);
-        const uint32_t old = atomicOr(&covered[j >> 5], bit);
-        if (old & bit) continue;
-        for (int64_t t = sptr[j]; t < sptr[j + 1]; ++t) atomicSub(&delta[nodes[t]], 1);
+        if (phase == GR_RECOUNT) {
+            cnt += (covered[j >> 5] & bit) ? 0ull : 1ull;
+        } else {
+            atomicOr(&covered[j >> 5], bit);
+        }
     }
+    if (phase == GR_RECOUNT) {
+        cnt = wave_sum(cnt);
+        if ((threadIdx.x & 63) == 0) s_cnt[threadIdx.x >> 6] = cnt;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const unsigned long long c = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+            if (c) atomicAdd(&st->acc, c);
+        }
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        last = atomicAdd(&st->done, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!last || threadIdx.x != 0) return;
+    __threadfence();
+    if (phase == GR_RECOUNT) {
+        const unsigned long long d = __hip_atomic_load(&st->acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ub[v] = (int64_t)d;
+        gain[v] = gain_of(d, T, Gamma, qv[v]);
+        stamp[v] = round;
+    } else {
+        seeds[round] = v;
+        marg[round] = (unsigned long long)ub[v];
+        chosen[v] = 1;
+        st->cov += (unsigned long long)ub[v];
+        st->round = round + 1;
+    }
+    st->acc = 0ull;
+    st->done = 0u;
+    st->phase = GR_ARGMAX;
 }
 
 __global__ __launch_bounds__(256) void k_greedy_final(int32_t n, uint64_t T, double Gamma,
@@ -417,40 +484,56 @@ void estimate_batch(const Sketch &sk, QueryScratch &qs, int32_t Q, const int64_t
 void greedy(const Sketch &sk, QueryScratch &qs, int32_t k, int32_t *seeds, uint64_t *marg, uint64_t *cov_out,
             double *est_out, hipStream_t s)
 {
+    (void)qs;
     Arena &arena = const_cast<Arena &>(sk.arena);
     const int32_t n = sk.n;
     const uint64_t wordsT = (sk.T + 31) / 32;
-    DevBuf<int32_t> delta;
+    DevBuf<int64_t> ub;
+    DevBuf<double> gain;
+    DevBuf<int32_t> stamp;
     DevBuf<uint8_t> chosen;
     DevBuf<uint32_t> covered;
     DevBuf<GreedyState> st;
     const unsigned ga = gridq(n, 256, 4);
     DevBuf<double> pg;
     DevBuf<int32_t> pv;
-    delta.alloc(arena, n);
+    ub.alloc(arena, n);
+    gain.alloc(arena, n);
+    stamp.alloc(arena, n);
     chosen.alloc(arena, n);
     covered.alloc(arena, wordsT ? wordsT : 1);
     st.alloc(arena, 1);
     pg.alloc(arena, ga);
     pv.alloc(arena, ga);
-    hipLaunchKernelGGL(k_greedy_init, dim3(gridq(n, 256)), dim3(256), 0, s, n, sk.node_ptr.ptr, delta.ptr, chosen.ptr);
+    hipLaunchKernelGGL(k_greedy_init, dim3(gridq(n, 256)), dim3(256), 0, s, n, sk.T, sk.Gamma, sk.node_ptr.ptr,
+                       sk.q.ptr, ub.ptr, gain.ptr, stamp.ptr, chosen.ptr);
     hipLaunchKernelGGL(k_fill_q<uint32_t>, dim3(gridq(wordsT ? wordsT : 1, 256)), dim3(256), 0, s,
                        wordsT ? wordsT : 1, covered.ptr, 0u);
     hipLaunchKernelGGL(k_fill_q<unsigned char>, dim3(1), dim3(64), 0, s, (uint64_t)sizeof(GreedyState),
                        reinterpret_cast<unsigned char *>(st.ptr), (unsigned char)0);
     SKIS_HIP_TRY(hipGetLastError());
-    const unsigned gu = (unsigned)device_cu_count() * 4;
-    for (int32_t r = 0; r < k; ++r) {
-        hipLaunchKernelGGL(k_argmax, dim3(ga), dim3(256), 0, s, n, sk.T, sk.Gamma, delta.ptr, sk.q.ptr, chosen.ptr,
-                           pg.ptr, pv.ptr, st.ptr, (int)r, seeds, reinterpret_cast<unsigned long long *>(marg));
-        if (sk.T)
-            hipLaunchKernelGGL(k_cover_update, dim3(gu), dim3(256), 0, s, st.ptr, sk.node_ptr.ptr,
-                               sk.node_samples.ptr, sk.sample_ptr.ptr, sk.nodes.ptr, covered.ptr, delta.ptr);
+    const unsigned gs = (unsigned)device_cu_count() * 4;
+    // Every pick takes at least one (argmax, step) pair; recounts add pairs.  Launch in
+    // batches and stop once the device reports k picks (extra pairs return at once).
+    GreedyState hs{};
+    int batch = k + 8;
+    for (int guard = 0; guard < 1 + 4 * n; ++guard) {
+        for (int i = 0; i < batch; ++i) {
+            hipLaunchKernelGGL(k_greedy_argmax, dim3(ga), dim3(256), 0, s, n, k, gain.ptr, chosen.ptr, stamp.ptr,
+                               pg.ptr, pv.ptr, st.ptr);
+            hipLaunchKernelGGL(k_greedy_step, dim3(gs), dim3(256), 0, s, k, sk.T, sk.Gamma, sk.node_ptr.ptr,
+                               sk.node_samples.ptr, sk.q.ptr, covered.ptr, ub.ptr, gain.ptr, stamp.ptr, chosen.ptr,
+                               st.ptr, seeds, reinterpret_cast<unsigned long long *>(marg));
+        }
+        SKIS_HIP_TRY(hipGetLastError());
+        SKIS_HIP_TRY(hipMemcpyAsync(&hs, st.ptr, sizeof(hs), hipMemcpyDeviceToHost, s));
+        SKIS_HIP_TRY(hipStreamSynchronize(s));
+        if (hs.round >= k) break;
+        batch = std::max(16, (k - hs.round) + 8);
     }
-    SKIS_HIP_TRY(hipGetLastError());
+    if (hs.round < k) throw Error{SKIS_EHIP, "internal error: greedy did not finish"};
     hipLaunchKernelGGL(k_greedy_final, dim3(1), dim3(256), 0, s, n, sk.T, sk.Gamma, chosen.ptr, sk.q.ptr, st.ptr);
     SKIS_HIP_TRY(hipGetLastError());
-    GreedyState hs;
     SKIS_HIP_TRY(hipMemcpyAsync(&hs, st.ptr, sizeof(hs), hipMemcpyDeviceToHost, s));
     SKIS_HIP_TRY(hipStreamSynchronize(s));
     *cov_out = hs.cov;

@@ -117,6 +117,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
     constexpr int HSZ = GLOBAL ? 1 : S * HCAP;
     constexpr int LSZ = GLOBAL ? 1 : S * RCAP;
     constexpr int IPT = (ICAP + BLOCK - 1) / BLOCK;
+    constexpr int PPL = 4; // edge pairs per lane per sweep
     static_assert(S <= 64, "slots are owned by the lanes of wave 0");
     static_assert(IDBATCH >= S, "one refill must cover every empty slot");
 
@@ -188,6 +189,15 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
             const int s = tid;
             const bool own = s < S;
             int f = own ? s_flags[s] : 0;
+            // finished samples of this pass reserve their staging space with one atomic
+            const bool fin = own && (f & F_ACTIVE) && !(!GLOBAL && (f & F_DEFER)) && !(f & F_ROOTPEND) &&
+                             s_cursor[s] >= s_count[s];
+            const unsigned long long fcnt = fin ? (unsigned long long)s_count[s] : 0ull;
+            const unsigned long long fincl = wave_incl_scan(fcnt);
+            const unsigned long long ftot = __shfl(fincl, 63, 64);
+            unsigned long long fbase = 0;
+            if (s == 0 && ftot) fbase = atomicAdd(a.stage_used, ftot);
+            fbase = __shfl(fbase, 0, 64);
             if (own && (f & F_ACTIVE)) {
                 if (!GLOBAL && (f & F_DEFER)) {
                     const uint32_t i = s_idx[s];
@@ -197,10 +207,10 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                     s_wo_cnt[s] = 0;
                     f = F_CLEAR;
                     s_flags[s] = f;
-                } else if (!(f & F_ROOTPEND) && s_cursor[s] >= s_count[s]) {
+                } else if (fin) {
                     const uint32_t i = s_idx[s];
                     const int cnt = s_count[s];
-                    const unsigned long long off = atomicAdd(a.stage_used, (unsigned long long)cnt);
+                    const unsigned long long off = fbase + fincl - fcnt;
                     a.out_size[i] = (uint32_t)cnt;
                     a.out_off[i] = off;
                     a.out_probed[i] = s_probed[s];
@@ -424,28 +434,48 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
         __syncthreads();
 
         // ---- B4: live-edge coins for every edge pair, visits ------------------------------
+        // Each lane takes PPL consecutive pairs: one search for the first pair's item, the
+        // next ones by stepping across item boundaries; all loads are issued before the
+        // coins are drawn.
         const int total = it_pb[nitems];
-        for (int idx = tid; idx < total; idx += BLOCK) {
-            int lo = 0, hi = nitems - 1; // last item whose first pair index is <= idx
+        for (int base = tid * PPL; base < total; base += BLOCK * PPL) {
+            int lo = 0, hi = nitems - 1; // last item whose first pair index is <= base
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
-                if (it_pb[mid] <= idx) lo = mid; else hi = mid - 1;
+                if (it_pb[mid] <= base) lo = mid; else hi = mid - 1;
             }
-            const int s = it_slot[lo];
-            if (!GLOBAL && (s_flags[s] & F_DEFER)) continue;
-            const int beg = it_beg[lo], end = it_end[lo];
-            const int p = (beg >> 1) + (idx - it_pb[lo]);
-            if (p < 0 || (int64_t)p >= a.npairs) { // bounds guard: report, never index
-                atomicOr(a.overflow, 2);
-                continue;
+            uint4 pr[PPL];
+            int pp[PPL], ps[PPL], pbeg[PPL], pend[PPL];
+#pragma unroll
+            for (int g = 0; g < PPL; ++g) {
+                const int idx = base + g;
+                ps[g] = -1;
+                if (idx >= total) continue;
+                while (it_pb[lo + 1] <= idx) ++lo; // it_pb[nitems] = total > idx
+                const int sl = it_slot[lo];
+                if (!GLOBAL && (s_flags[sl] & F_DEFER)) continue;
+                const int p = (it_beg[lo] >> 1) + (idx - it_pb[lo]);
+                if (p < 0 || (int64_t)p >= a.npairs) { // bounds guard: report, never index
+                    atomicOr(a.overflow, 2);
+                    continue;
+                }
+                ps[g] = sl;
+                pp[g] = p;
+                pbeg[g] = it_beg[lo];
+                pend[g] = it_end[lo];
+                pr[g] = a.pairs[p];
             }
-            const uint4 pr = a.pairs[p];
-            const uint64_t j = a.j0 + s_idx[s];
-            uint64_t X, Y;
-            philox2x64((uint32_t)p, (uint32_t)j, (uint32_t)(j >> 32), TAG_EDGE, a.seed_lo, a.seed_hi, X, Y);
-            const int e0 = 2 * p;
-            if (e0 >= beg && coin_live(pr.y, X)) visit(s, (int32_t)pr.x);
-            if (e0 + 1 < end && coin_live(pr.w, Y)) visit(s, (int32_t)pr.z);
+#pragma unroll
+            for (int g = 0; g < PPL; ++g) {
+                if (ps[g] < 0) continue;
+                const int sl = ps[g];
+                const uint64_t j = a.j0 + s_idx[sl];
+                uint64_t X, Y;
+                philox2x64((uint32_t)pp[g], (uint32_t)j, (uint32_t)(j >> 32), TAG_EDGE, a.seed_lo, a.seed_hi, X, Y);
+                const int e0 = 2 * pp[g];
+                if (e0 >= pbeg[g] && coin_live(pr[g].y, X)) visit(sl, (int32_t)pr[g].x);
+                if (e0 + 1 < pend[g] && coin_live(pr[g].w, Y)) visit(sl, (int32_t)pr[g].z);
+            }
         }
         __syncthreads();
         if (!s_alive) break;
@@ -575,31 +605,6 @@ __global__ __launch_bounds__(256) void k_sum_u64(uint64_t count, const unsigned 
     if ((threadIdx.x & 63) == 0 && acc) atomicAdd(out, acc);
 }
 
-// ---------------------------------------------------------------------------------------
-// Inverse index: node -> samples.
-// ---------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_count_nodes(uint64_t entries, const int32_t *__restrict__ nodes,
-                                                     uint32_t *__restrict__ cnt)
-{
-    for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < entries; p += (uint64_t)gridDim.x * blockDim.x)
-        atomicAdd(&cnt[nodes[p]], 1u);
-}
-
-__global__ __launch_bounds__(64) void k_scatter_inverse(uint64_t T, const int64_t *__restrict__ sptr,
-                                                        const int32_t *__restrict__ nodes,
-                                                        const int64_t *__restrict__ node_ptr,
-                                                        uint32_t *__restrict__ fill, int32_t *__restrict__ ns)
-{
-    for (uint64_t j = blockIdx.x; j < T; j += gridDim.x) {
-        const int64_t a = sptr[j], b = sptr[j + 1];
-        for (int64_t p = a + threadIdx.x; p < b; p += 64) {
-            const int32_t v = nodes[p];
-            const uint32_t pos = atomicAdd(&fill[v], 1u);
-            ns[node_ptr[v] + pos] = (int32_t)j;
-        }
-    }
-}
-
 template <typename T>
 __global__ __launch_bounds__(256) void k_fill(uint64_t count, T *__restrict__ p, T v)
 {
@@ -634,7 +639,7 @@ struct Variant {
     SampleKernel fn;
 };
 
-// LDS tier variants: (slots per workgroup, LDS visited capacity)
+// first (LDS) tier variants: (slots per workgroup, LDS visited capacity)
 static const Variant kTier0[] = {
     {32, 128, k_sample<256, 32, 8, 1024, false>},
     {16, 256, k_sample<256, 16, 9, 1024, false>},
@@ -642,8 +647,11 @@ static const Variant kTier0[] = {
     {8, 512, k_sample<256, 8, 10, 1024, false>},
     {16, 128, k_sample<256, 16, 8, 1024, false>},
 };
-constexpr int TIER1_SLOTS = 4;
-static SampleKernel const kTier1 = k_sample<256, TIER1_SLOTS, 1, 1024, true>;
+// second tier: samples that outgrew the first, 8 slots of 1024 nodes in LDS
+static SampleKernel const kTierMid = k_sample<256, 8, 11, 1024, false>;
+// last tier: a bitmap of n bits and a node list of n entries per slot in HBM
+constexpr int TIERG_SLOTS = 4;
+static SampleKernel const kTierGlobal = k_sample<256, TIERG_SLOTS, 1, 1024, true>;
 
 static SampleKernel pick_tier0(uint32_t slots, uint32_t visited)
 {
@@ -668,7 +676,7 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
     if (T >= (1ull << 31)) throw Error{SKIS_EINVAL, "num_samples must be below 2^31"};
     const uint32_t count = (uint32_t)T;
     const uint32_t seed_lo = (uint32_t)seed, seed_hi = (uint32_t)(seed >> 32);
-    constexpr int NEV = 8;
+    constexpr int NEV = 10;
     hipEvent_t ev[NEV];
     for (auto &e : ev) SKIS_HIP_TRY(hipEventCreate(&e));
     struct EvGuard {
@@ -678,7 +686,7 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
             for (int i = 0; i < NEV; ++i) (void)hipEventDestroy(e[i]);
         }
     } evg{ev};
-    bool ran_tier1 = false;
+    bool ran_mid = false, ran_global = false;
 
     // every device buffer a kernel below dereferences must exist (checked on the host)
     auto need = [](const void *p, const char *what) {
@@ -720,13 +728,25 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
     SampleKernel t0 = pick_tier0(cfg.slots, cfg.visited);
     const int cus = device_cu_count();
     const int nb0 = occupancy_blocks(t0, 256) * cus;
+    const int nbm = occupancy_blocks(kTierMid, 256) * cus;
     const uint64_t words = ((uint64_t)n + 31) / 32;
     // global tier: every slot holds a bitmap of n bits and a node list of n entries; keep
     // all slots within about 4 GiB
     const uint64_t slot_bytes = (uint64_t)n * 4ull + words * 4ull;
-    uint64_t nb1_mem = (4ull << 30) / (slot_bytes * TIER1_SLOTS);
-    if (nb1_mem < 1) nb1_mem = 1;
-    const int nb1 = (int)std::min<uint64_t>((uint64_t)2 * cus, nb1_mem);
+    uint64_t nbg_mem = (4ull << 30) / (slot_bytes * TIERG_SLOTS);
+    if (nbg_mem < 1) nbg_mem = 1;
+    const int nbg = (int)std::min<uint64_t>((uint64_t)2 * cus, nbg_mem);
+    DevBuf<uint32_t> deferred2;
+    deferred2.alloc(arena, count);
+
+    auto read_counters = [&]() {
+        SKIS_HIP_TRY(hipMemcpyAsync(&hc, ctr.ptr, sizeof(hc), hipMemcpyDeviceToHost, s));
+        SKIS_HIP_TRY(hipStreamSynchronize(s));
+    };
+    auto reset_ids = [&]() {
+        hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(1), dim3(64), 0, s, (uint64_t)1, &ctr.ptr->next, 0ull);
+        hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(1), dim3(64), 0, s, (uint64_t)1, &ctr.ptr->n_deferred, 0ull);
+    };
 
     for (int attempt = 0; attempt < 2; ++attempt) {
         staging.alloc(arena, cap);
@@ -762,38 +782,57 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
                               (const void *)A.next, (const void *)A.staging, (const void *)A.stage_used,
                               (const void *)A.out_size, (const void *)A.out_off, (const void *)A.out_probed,
                               (const void *)A.deferred, (const void *)A.n_deferred, (const void *)A.medium,
-                              (const void *)A.n_medium, (const void *)A.overflow})
+                              (const void *)A.n_medium, (const void *)A.overflow, (const void *)deferred2.ptr})
             need(p, "sampler argument");
+        // tier 0: every sample, LDS visited sets of cfg.visited nodes
         SKIS_HIP_TRY(hipEventRecord(ev[4], s));
         hipLaunchKernelGGL(t0, dim3(nb0), dim3(256), 0, s, A);
         SKIS_HIP_TRY(hipGetLastError());
         SKIS_HIP_TRY(hipEventRecord(ev[5], s));
-        SKIS_HIP_TRY(hipMemcpyAsync(&hc, ctr.ptr, sizeof(hc), hipMemcpyDeviceToHost, s));
-        SKIS_HIP_TRY(hipStreamSynchronize(s));
+        read_counters();
         sk.deferred = hc.n_deferred;
+        sk.deferred_global = 0;
+        ran_mid = ran_global = false;
         if (hc.n_deferred > 0) {
-            const uint64_t slots = (uint64_t)nb1 * TIER1_SLOTS;
+            // tier 1: the samples that outgrew tier 0, LDS visited sets of 1024 nodes
+            const uint64_t nd = hc.n_deferred;
+            reset_ids();
+            A.id_list = deferred.ptr;
+            A.id_count = nd;
+            A.deferred = deferred2.ptr;
+            A.big_row = std::max<uint32_t>(cfg.big_row, 1u << 20);
+            SKIS_HIP_TRY(hipEventRecord(ev[6], s));
+            hipLaunchKernelGGL(kTierMid, dim3(nbm), dim3(256), 0, s, A);
+            SKIS_HIP_TRY(hipGetLastError());
+            SKIS_HIP_TRY(hipEventRecord(ev[7], s));
+            ran_mid = true;
+            read_counters();
+        }
+        if (ran_mid && hc.n_deferred > 0) {
+            // tier 2: what is left, a bitmap and a node list of n entries per slot in HBM
+            const uint64_t nd = hc.n_deferred;
+            sk.deferred_global = nd;
+            const uint64_t slots = (uint64_t)nbg * TIERG_SLOTS;
             DevBuf<uint32_t> gbits;
             DevBuf<int32_t> glist;
             gbits.alloc(arena, slots * words);
             glist.alloc(arena, slots * (uint64_t)n);
             hipLaunchKernelGGL(k_fill<uint32_t>, dim3(grid_cap(slots * words, 256)), dim3(256), 0, s, slots * words,
                                gbits.ptr, 0u);
-            hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(1), dim3(64), 0, s, (uint64_t)1, &ctr.ptr->next, 0ull);
-            A.id_list = deferred.ptr;
-            A.id_count = hc.n_deferred;
+            reset_ids();
+            A.id_list = deferred2.ptr;
+            A.id_count = nd;
+            A.deferred = deferred.ptr; // unused: the global tier finishes every sample
             A.gbits = gbits.ptr;
             A.glist = glist.ptr;
             need(A.gbits, "gbits");
             need(A.glist, "glist");
-            need(A.id_list, "deferred list");
-            SKIS_HIP_TRY(hipEventRecord(ev[6], s));
-            hipLaunchKernelGGL(kTier1, dim3(nb1), dim3(256), 0, s, A);
+            SKIS_HIP_TRY(hipEventRecord(ev[8], s));
+            hipLaunchKernelGGL(kTierGlobal, dim3(nbg), dim3(256), 0, s, A);
             SKIS_HIP_TRY(hipGetLastError());
-            SKIS_HIP_TRY(hipEventRecord(ev[7], s));
-            ran_tier1 = true;
-            SKIS_HIP_TRY(hipMemcpyAsync(&hc, ctr.ptr, sizeof(hc), hipMemcpyDeviceToHost, s));
-            SKIS_HIP_TRY(hipStreamSynchronize(s));
+            SKIS_HIP_TRY(hipEventRecord(ev[9], s));
+            ran_global = true;
+            read_counters();
         }
         int herr = 0;
         SKIS_HIP_TRY(hipMemcpyAsync(&herr, rerr.ptr, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -808,7 +847,7 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
     }
     SKIS_HIP_TRY(hipEventRecord(ev[2], s));
 
-    // every sample must have finished in one of the two tiers
+    // every sample must have finished in one of the tiers
     hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(1), dim3(64), 0, s, (uint64_t)1, &ctr.ptr->next, 0ull);
     hipLaunchKernelGGL(k_count_value, dim3(grid_cap(count, 256)), dim3(256), 0, s, (uint64_t)count, out_size.ptr,
                        DEFERRED, &ctr.ptr->next);
@@ -859,33 +898,15 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
     SKIS_HIP_TRY(hipEventElapsedTime(&ms, ev[4], ev[5]));
     sk.ms_tier0 = ms;
     sk.ms_tier1 = 0;
-    if (ran_tier1) {
+    sk.ms_tier2 = 0;
+    if (ran_mid) {
         SKIS_HIP_TRY(hipEventElapsedTime(&ms, ev[6], ev[7]));
         sk.ms_tier1 = ms;
     }
-}
-
-void build_inverse(Sketch &sk, hipStream_t s)
-{
-    Arena &arena = sk.arena;
-    const int32_t n = sk.n;
-    sk.node_ptr.alloc(arena, (size_t)n + 1);
-    sk.node_samples.alloc(arena, (size_t)sk.entries);
-    DevBuf<uint32_t> cnt;
-    cnt.alloc(arena, (size_t)n);
-    hipLaunchKernelGGL(k_fill<uint32_t>, dim3(grid_cap(n, 256)), dim3(256), 0, s, (uint64_t)n, cnt.ptr, 0u);
-    if (sk.entries)
-        hipLaunchKernelGGL(k_count_nodes, dim3(grid_cap(sk.entries, 256)), dim3(256), 0, s, sk.entries, sk.nodes.ptr,
-                           cnt.ptr);
-    SKIS_HIP_TRY(hipGetLastError());
-    excl_scan_u32_to_i64(arena, cnt.ptr, sk.node_ptr.ptr, n, sk.node_ptr.ptr + n, s);
-    hipLaunchKernelGGL(k_fill<uint32_t>, dim3(grid_cap(n, 256)), dim3(256), 0, s, (uint64_t)n, cnt.ptr, 0u);
-    if (sk.T)
-        hipLaunchKernelGGL(k_scatter_inverse, dim3(grid_cap(sk.T, 1, 64)), dim3(64), 0, s, sk.T, sk.sample_ptr.ptr,
-                           sk.nodes.ptr, sk.node_ptr.ptr, cnt.ptr, sk.node_samples.ptr);
-    SKIS_HIP_TRY(hipGetLastError());
-    SKIS_HIP_TRY(hipStreamSynchronize(s));
-    sk.has_inverse = true;
+    if (ran_global) {
+        SKIS_HIP_TRY(hipEventElapsedTime(&ms, ev[8], ev[9]));
+        sk.ms_tier2 = ms;
+    }
 }
 
 } // namespace skis
