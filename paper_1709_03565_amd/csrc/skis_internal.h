@@ -97,6 +97,9 @@ struct Sketch {
     DevBuf<uint64_t> probed;      // [T]
     DevBuf<int64_t> node_ptr;     // [n+1]
     DevBuf<int32_t> node_samples; // [entries]
+    DevBuf<int32_t> hot_id;       // [n] index in hot_node, or -1 (frequent nodes of the sketch)
+    DevBuf<int32_t> hot_node;     // [nhot]
+    int nhot = 0;
     double ms_preprocess = 0, ms_roots = 0, ms_sample = 0, ms_compact = 0, ms_inverse = 0;
     double ms_tier0 = 0, ms_tier1 = 0, ms_tier2 = 0; // the sampler launches alone
     uint64_t deferred_global = 0;                    // samples that reached the HBM tier

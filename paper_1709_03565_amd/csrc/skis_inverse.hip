@@ -203,7 +203,7 @@ void build_inverse(Sketch &sk, hipStream_t s)
     }
     const uint32_t thr = bsel >= 32 ? 0xFFFFFFFFu : (1u << bsel);
     DevBuf<uint32_t> flag, rank, ntot;
-    DevBuf<int32_t> hot_id, hot_node;
+    DevBuf<int32_t> &hot_id = sk.hot_id, &hot_node = sk.hot_node; // kept: the greedy uses them too
     flag.alloc(arena, n);
     rank.alloc(arena, n);
     ntot.alloc(arena, 1);
@@ -219,6 +219,7 @@ void build_inverse(Sketch &sk, hipStream_t s)
     SKIS_HIP_TRY(hipStreamSynchronize(s));
     const int nhot = (int)std::min<uint32_t>(nhot_u, INV_HOT);
     if ((uint32_t)nhot != nhot_u) throw Error{SKIS_EHIP, "internal error: too many hot nodes"};
+    sk.nhot = nhot;
 
     // 2. counts
     const uint32_t nchunks = (uint32_t)((T + INV_CHUNK - 1) / INV_CHUNK);

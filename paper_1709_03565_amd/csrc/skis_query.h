@@ -7,13 +7,13 @@ namespace skis {
 constexpr int EST_BLOCK = 256;    // threads per query in k_estimate
 constexpr int EST_MAX_SET = 4096; // largest seed set one estimate workgroup holds in LDS
 
+constexpr int GREEDY_HOT = 2048;  // hot nodes decremented in LDS
+
 struct GreedyState {
-    unsigned done;            // blocks of the current kernel that have finished
-    int32_t vstar;            // the node of the current iteration
-    int32_t round;            // picks made so far
-    int32_t phase;            // what k_greedy_step does with vstar (recount or select)
-    unsigned long long acc;   // recount accumulator
-    unsigned long long cov;   // coverage of the picks so far
+    unsigned done;              // blocks of k_greedy_argmax that have finished
+    int32_t vstar;              // this round's pick (-1: none left)
+    unsigned long long listed;  // samples newly covered this round
+    unsigned long long cov;     // coverage of the picks so far
     double est;
 };
 

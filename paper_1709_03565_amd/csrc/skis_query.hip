@@ -3,7 +3,8 @@
 //                the T samples (a sample counts once, when its bit first flips), and
 //                I_hat(S) = fl(fl(Cov * Gamma) / T) + sum_{v in S} q_v (compensated sum).
 //   k_greedy_*   Alg. 3: the node of largest gain fl(fl(Delta * Gamma) / T) + q (Eq. margin),
-//                smallest id on ties, with Delta recounted lazily against a covered bitmap.
+//                smallest id on ties; Delta kept exact by decrementing the members of every
+//                newly covered sample.
 #include "skis_internal.h"
 #include "skis_query.h"
 
@@ -204,15 +205,15 @@ __global__ __launch_bounds__(EST_BLOCK) void k_estimate(const int64_t *__restric
 }
 
 // ---------------------------------------------------------------------------------------
-// Greedy (Alg. 3), evaluated lazily.  ub[v] is an upper bound on Delta(v), the number of
-// samples holding v not yet covered (it starts at |H(v)| and only falls, Lemma 8); gain[v]
-// caches fl(fl(ub * Gamma) / T) + q_v, a bound on v's gain because the rounding is
-// monotone.  Each iteration takes the node of largest bound gain (smallest id on ties):
-// if its bound was made exact in this round it is the round's pick, since every other
-// node's exact gain is at most its bound; otherwise its Delta is recounted against the
-// covered bitmap and the iteration repeats.  The picks are those of the plain greedy.
+// Greedy (Alg. 3) with exact marginal coverage.  delta[v] = #{ j in H(v) : j not covered }.
+// Each round: k_greedy_argmax picks the node of largest gain fl(fl(delta * Gamma) / T) + q_v
+// (Eq. margin; smallest id on ties); k_greedy_mark sets the covered bits of H(v*) and lists
+// the samples it newly covers; k_greedy_decrement lowers delta of every member of those
+// samples.  The most frequent nodes (the transpose's hot list) are decremented in LDS per
+// workgroup and flushed once, so hubs do not serialise on one counter.  Integer updates
+// commute, so delta and the picks are exact.
 // ---------------------------------------------------------------------------------------
-__device__ __forceinline__ double gain_of(uint64_t d, uint64_t T, double Gamma, double q)
+__device__ __forceinline__ double gain_of(int64_t d, uint64_t T, double Gamma, double q)
 {
     return __dadd_rn(T > 0 ? __ddiv_rn(__dmul_rn((double)d, Gamma), (double)T) : 0.0, q);
 }
@@ -222,24 +223,16 @@ __device__ __forceinline__ bool better(double g, int32_t v, double bg, int32_t b
     return bv < 0 || g > bg || (g == bg && v < bv);
 }
 
-__global__ __launch_bounds__(256) void k_greedy_init(int32_t n, uint64_t T, double Gamma,
-                                                     const int64_t *__restrict__ node_ptr,
-                                                     const double *__restrict__ qv, int64_t *__restrict__ ub,
-                                                     double *__restrict__ gain, int32_t *__restrict__ stamp,
-                                                     uint8_t *__restrict__ chosen)
+__global__ __launch_bounds__(256) void k_greedy_init(int32_t n, const int64_t *__restrict__ node_ptr,
+                                                     int32_t *__restrict__ delta, uint8_t *__restrict__ chosen)
 {
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t d = node_ptr[v + 1] - node_ptr[v];
-        ub[v] = d;
-        gain[v] = gain_of((uint64_t)d, T, Gamma, qv[v]);
-        stamp[v] = -1;
+        delta[v] = (int32_t)(node_ptr[v + 1] - node_ptr[v]);
         chosen[v] = 0;
     }
 }
 
-enum : int { GR_ARGMAX = 0, GR_RECOUNT = 1, GR_SELECT = 2 };
-
-// Block-wide (g, v) reduction in LDS; returns the winner in thread 0.
+// Block-wide (g, v) reduction in LDS; every thread gets the winner.
 __device__ __forceinline__ void block_best(double &g, int32_t &v, double *sg, int32_t *sv)
 {
     sg[threadIdx.x] = g;
@@ -259,20 +252,21 @@ __device__ __forceinline__ void block_best(double &g, int32_t &v, double *sg, in
     v = sv[0];
 }
 
-__global__ __launch_bounds__(256) void k_greedy_argmax(int32_t n, int32_t k, const double *__restrict__ gain,
-                                                       const uint8_t *__restrict__ chosen,
-                                                       const int32_t *__restrict__ stamp, double *__restrict__ part_g,
-                                                       int32_t *__restrict__ part_v, GreedyState *__restrict__ st)
+__global__ __launch_bounds__(256) void k_greedy_argmax(int32_t n, int round, uint64_t T, double Gamma,
+                                                       const int32_t *__restrict__ delta, const double *__restrict__ qv,
+                                                       uint8_t *__restrict__ chosen, double *__restrict__ part_g,
+                                                       int32_t *__restrict__ part_v, GreedyState *__restrict__ st,
+                                                       int32_t *__restrict__ seeds,
+                                                       unsigned long long *__restrict__ marg)
 {
     __shared__ double sg[256];
     __shared__ int32_t sv[256];
     __shared__ bool last;
-    if (st->round >= k) return;
     double bg = 0.0;
     int32_t bv = -1;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
         if (chosen[v]) continue;
-        const double g = gain[v];
+        const double g = gain_of(delta[v], T, Gamma, qv[v]);
         if (better(g, (int32_t)v, bg, bv)) {
             bg = g;
             bv = (int32_t)v;
@@ -302,73 +296,78 @@ __global__ __launch_bounds__(256) void k_greedy_argmax(int32_t n, int32_t k, con
     block_best(bg, bv, sg, sv);
     if (threadIdx.x == 0) {
         st->done = 0u;
-        if (bv < 0) { // nothing left to pick (cannot happen for k <= n): stop
-            st->round = k;
+        st->listed = 0ull;
+        if (bv < 0) { // nothing left to pick (cannot happen for k <= n)
+            st->vstar = -1;
             return;
         }
         st->vstar = bv;
-        st->phase = stamp[bv] == st->round ? GR_SELECT : GR_RECOUNT;
+        const int32_t d = delta[bv];
+        seeds[round] = bv;
+        marg[round] = (unsigned long long)d;
+        chosen[bv] = 1;
+        st->cov += (unsigned long long)d;
     }
 }
 
-// RECOUNT: Delta(v) = #{ j in H(v) : not covered }.  SELECT: cover H(v) and record the pick.
-__global__ __launch_bounds__(256) void k_greedy_step(int32_t k, uint64_t T, double Gamma,
+// Covers H(v*): lists every sample whose covered bit flips (one list append per wave).
+__global__ __launch_bounds__(256) void k_greedy_mark(const GreedyState *__restrict__ st,
                                                      const int64_t *__restrict__ node_ptr,
                                                      const int32_t *__restrict__ node_samples,
-                                                     const double *__restrict__ qv, uint32_t *__restrict__ covered,
-                                                     int64_t *__restrict__ ub, double *__restrict__ gain,
-                                                     int32_t *__restrict__ stamp, uint8_t *__restrict__ chosen,
-                                                     GreedyState *__restrict__ st, int32_t *__restrict__ seeds,
-                                                     unsigned long long *__restrict__ marg)
+                                                     uint32_t *__restrict__ covered, uint32_t *__restrict__ list,
+                                                     unsigned long long *__restrict__ listed)
 {
-    __shared__ unsigned long long s_cnt[4];
-    __shared__ bool last;
-    const int round = st->round;
-    if (round >= k) return;
-    const int phase = st->phase;
     const int32_t v = st->vstar;
+    if (v < 0) return;
     const int64_t a = node_ptr[v], b = node_ptr[v + 1];
-    unsigned long long cnt = 0;
-    for (int64_t p = a + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < b; p += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t j = node_samples[p];
-        const uint32_t bit = 1u << (j & 31);
-        if (phase == GR_RECOUNT) {
-            cnt += (covered[j >> 5] & bit) ? 0ull : 1ull;
-        } else {
-            atomicOr(&covered[j >> 5], bit);
+    const int lane = threadIdx.x & 63;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p0 = a + (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); p0 < b; p0 += stride) {
+        const int64_t p = p0 + lane;
+        bool fresh = false;
+        int32_t j = 0;
+        if (p < b) {
+            j = node_samples[p];
+            const uint32_t bit = 1u << (j & 31);
+            fresh = !(atomicOr(&covered[j >> 5], bit) & bit);
         }
+        const unsigned long long m = __ballot(fresh);
+        if (!m) continue;
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(listed, (unsigned long long)__popcll(m));
+        base = __shfl(base, 0, 64);
+        if (fresh) list[base + __popcll(m & ((1ull << lane) - 1ull))] = (uint32_t)j;
     }
-    if (phase == GR_RECOUNT) {
-        cnt = wave_sum(cnt);
-        if ((threadIdx.x & 63) == 0) s_cnt[threadIdx.x >> 6] = cnt;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            const unsigned long long c = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
-            if (c) atomicAdd(&st->acc, c);
+}
+
+// Lowers delta of every member of every newly covered sample.
+__global__ __launch_bounds__(256) void k_greedy_decrement(const GreedyState *__restrict__ st,
+                                                          const uint32_t *__restrict__ list,
+                                                          const int64_t *__restrict__ sptr,
+                                                          const int32_t *__restrict__ nodes,
+                                                          const int32_t *__restrict__ hot_id,
+                                                          const int32_t *__restrict__ hot_node, int nhot,
+                                                          int32_t *__restrict__ delta)
+{
+    __shared__ int32_t hd[GREEDY_HOT];
+    if (st->vstar < 0) return;
+    const uint64_t cnt = st->listed;
+    for (int h = threadIdx.x; h < nhot; h += 256) hd[h] = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & 15, sub = threadIdx.x >> 4; // 16 lanes per sample
+    for (uint64_t i = (uint64_t)blockIdx.x * 16 + sub; i < cnt; i += (uint64_t)gridDim.x * 16) {
+        const uint32_t j = list[i];
+        const int64_t a = sptr[j], b = sptr[j + 1];
+        for (int64_t t = a + lane; t < b; t += 16) {
+            const int32_t u = nodes[t];
+            const int32_t h = hot_id ? hot_id[u] : -1;
+            if (h >= 0) atomicSub(&hd[h], 1);
+            else atomicSub(&delta[u], 1);
         }
-    }
-    if (threadIdx.x == 0) {
-        __threadfence();
-        last = atomicAdd(&st->done, 1u) == gridDim.x - 1;
     }
     __syncthreads();
-    if (!last || threadIdx.x != 0) return;
-    __threadfence();
-    if (phase == GR_RECOUNT) {
-        const unsigned long long d = __hip_atomic_load(&st->acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        ub[v] = (int64_t)d;
-        gain[v] = gain_of(d, T, Gamma, qv[v]);
-        stamp[v] = round;
-    } else {
-        seeds[round] = v;
-        marg[round] = (unsigned long long)ub[v];
-        chosen[v] = 1;
-        st->cov += (unsigned long long)ub[v];
-        st->round = round + 1;
-    }
-    st->acc = 0ull;
-    st->done = 0u;
-    st->phase = GR_ARGMAX;
+    for (int h = threadIdx.x; h < nhot; h += 256)
+        if (hd[h]) atomicAdd(&delta[hot_node[h]], hd[h]);
 }
 
 __global__ __launch_bounds__(256) void k_greedy_final(int32_t n, uint64_t T, double Gamma,
@@ -488,54 +487,46 @@ void greedy(const Sketch &sk, QueryScratch &qs, int32_t k, int32_t *seeds, uint6
     Arena &arena = const_cast<Arena &>(sk.arena);
     const int32_t n = sk.n;
     const uint64_t wordsT = (sk.T + 31) / 32;
-    DevBuf<int64_t> ub;
-    DevBuf<double> gain;
-    DevBuf<int32_t> stamp;
+    DevBuf<int32_t> delta;
     DevBuf<uint8_t> chosen;
-    DevBuf<uint32_t> covered;
+    DevBuf<uint32_t> covered, list;
     DevBuf<GreedyState> st;
     const unsigned ga = gridq(n, 256, 4);
     DevBuf<double> pg;
     DevBuf<int32_t> pv;
-    ub.alloc(arena, n);
-    gain.alloc(arena, n);
-    stamp.alloc(arena, n);
+    delta.alloc(arena, n);
     chosen.alloc(arena, n);
     covered.alloc(arena, wordsT ? wordsT : 1);
+    list.alloc(arena, sk.T ? sk.T : 1);
     st.alloc(arena, 1);
     pg.alloc(arena, ga);
     pv.alloc(arena, ga);
-    hipLaunchKernelGGL(k_greedy_init, dim3(gridq(n, 256)), dim3(256), 0, s, n, sk.T, sk.Gamma, sk.node_ptr.ptr,
-                       sk.q.ptr, ub.ptr, gain.ptr, stamp.ptr, chosen.ptr);
+    hipLaunchKernelGGL(k_greedy_init, dim3(gridq(n, 256)), dim3(256), 0, s, n, sk.node_ptr.ptr, delta.ptr, chosen.ptr);
     hipLaunchKernelGGL(k_fill_q<uint32_t>, dim3(gridq(wordsT ? wordsT : 1, 256)), dim3(256), 0, s,
                        wordsT ? wordsT : 1, covered.ptr, 0u);
     hipLaunchKernelGGL(k_fill_q<unsigned char>, dim3(1), dim3(64), 0, s, (uint64_t)sizeof(GreedyState),
                        reinterpret_cast<unsigned char *>(st.ptr), (unsigned char)0);
     SKIS_HIP_TRY(hipGetLastError());
-    const unsigned gs = (unsigned)device_cu_count() * 4;
-    // Every pick takes at least one (argmax, step) pair; recounts add pairs.  Launch in
-    // batches and stop once the device reports k picks (extra pairs return at once).
-    GreedyState hs{};
-    int batch = k + 8;
-    for (int guard = 0; guard < 1 + 4 * n; ++guard) {
-        for (int i = 0; i < batch; ++i) {
-            hipLaunchKernelGGL(k_greedy_argmax, dim3(ga), dim3(256), 0, s, n, k, gain.ptr, chosen.ptr, stamp.ptr,
-                               pg.ptr, pv.ptr, st.ptr);
-            hipLaunchKernelGGL(k_greedy_step, dim3(gs), dim3(256), 0, s, k, sk.T, sk.Gamma, sk.node_ptr.ptr,
-                               sk.node_samples.ptr, sk.q.ptr, covered.ptr, ub.ptr, gain.ptr, stamp.ptr, chosen.ptr,
-                               st.ptr, seeds, reinterpret_cast<unsigned long long *>(marg));
+    const unsigned gu = (unsigned)device_cu_count() * 4;
+    const int nhot = std::min<int>(sk.nhot, GREEDY_HOT);
+    const int32_t *hot_id = nhot > 0 ? sk.hot_id.ptr : nullptr;
+    for (int32_t r = 0; r < k; ++r) {
+        hipLaunchKernelGGL(k_greedy_argmax, dim3(ga), dim3(256), 0, s, n, (int)r, sk.T, sk.Gamma, delta.ptr, sk.q.ptr,
+                           chosen.ptr, pg.ptr, pv.ptr, st.ptr, seeds, reinterpret_cast<unsigned long long *>(marg));
+        if (sk.T) {
+            hipLaunchKernelGGL(k_greedy_mark, dim3(gu), dim3(256), 0, s, st.ptr, sk.node_ptr.ptr, sk.node_samples.ptr,
+                               covered.ptr, list.ptr, &st.ptr->listed);
+            hipLaunchKernelGGL(k_greedy_decrement, dim3(gu), dim3(256), 0, s, st.ptr, list.ptr, sk.sample_ptr.ptr,
+                               sk.nodes.ptr, hot_id, sk.hot_node.ptr, nhot, delta.ptr);
         }
-        SKIS_HIP_TRY(hipGetLastError());
-        SKIS_HIP_TRY(hipMemcpyAsync(&hs, st.ptr, sizeof(hs), hipMemcpyDeviceToHost, s));
-        SKIS_HIP_TRY(hipStreamSynchronize(s));
-        if (hs.round >= k) break;
-        batch = std::max(16, (k - hs.round) + 8);
     }
-    if (hs.round < k) throw Error{SKIS_EHIP, "internal error: greedy did not finish"};
+    SKIS_HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_greedy_final, dim3(1), dim3(256), 0, s, n, sk.T, sk.Gamma, chosen.ptr, sk.q.ptr, st.ptr);
     SKIS_HIP_TRY(hipGetLastError());
+    GreedyState hs;
     SKIS_HIP_TRY(hipMemcpyAsync(&hs, st.ptr, sizeof(hs), hipMemcpyDeviceToHost, s));
     SKIS_HIP_TRY(hipStreamSynchronize(s));
+    if (hs.vstar < 0) throw Error{SKIS_EHIP, "internal error: greedy ran out of candidates"};
     *cov_out = hs.cov;
     *est_out = hs.est;
 }
