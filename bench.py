@@ -87,6 +87,7 @@ def main():
     ap.add_argument("--k", type=int, default=100)
     ap.add_argument("--slots", type=int, default=0)
     ap.add_argument("--visited", type=int, default=0)
+    ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (for scaling HBM byte counters) and exit")
@@ -134,6 +135,8 @@ def main():
         opts["slots_per_block"] = args.slots
     if args.visited:
         opts["visited_threshold"] = args.visited
+    if args.threads:
+        opts["threads_per_block"] = args.threads
     torch.cuda.synchronize()
 
     def step():

@@ -50,12 +50,15 @@ typedef struct skis_sketch skis_sketch; /* opaque; owns every device buffer it a
 /* Sampler and memory knobs.  Zero fields mean "default"; skis_default_options fills them. */
 typedef struct skis_options {
     uint32_t form;                /* 0: persistent sampler (default); 1: plain form, one launch per BFS level */
-    uint32_t slots_per_block;     /* samples in flight per workgroup of the persistent sampler: 8, 16 or 32 */
-    uint32_t visited_threshold;   /* nodes per sample kept in LDS before the sample moves to the
-                                     global-memory tier: 128, 256 or 512 */
-    uint32_t big_row;             /* in-degree above which a sample moves to the global tier */
+    uint32_t slots_per_block;     /* samples in flight per workgroup of the first sampler tier */
+    uint32_t visited_threshold;   /* nodes per sample kept in LDS by the first tier before the sample
+                                     moves to the next tier */
+    uint32_t big_row;             /* in-degree above which the first tier hands a sample on */
     uint32_t build_inverse_index; /* 1 (default): build node->samples for estimate / greedy; 0: build only */
-    uint32_t reserved0;
+    uint32_t threads_per_block;   /* 64 (default: one wave per workgroup) or 256.  Supported
+                                     (threads, slots, visited): (64,8,128) default, (64,8,64),
+                                     (64,16,128), (64,4,256), (64,16,64), (256,32,128),
+                                     (256,16,256), (256,32,256), (256,8,512), (256,16,128) */
     uint64_t max_device_bytes;    /* 0 = unlimited; larger total allocation -> SKIS_ENOMEM */
     uint64_t staging_entries;     /* initial staging capacity in node entries (0 = auto) */
 } skis_options;

@@ -93,8 +93,9 @@ void skis_default_options(skis_options *opt)
     if (!opt) return;
     std::memset(opt, 0, sizeof(*opt));
     opt->form = 0;
-    opt->slots_per_block = 32;
+    opt->slots_per_block = 8;
     opt->visited_threshold = 128;
+    opt->threads_per_block = 64;
     opt->big_row = 16384;
     opt->build_inverse_index = 1;
     opt->max_device_bytes = 0;
@@ -147,6 +148,7 @@ int skis_build_sketch(int32_t n, int64_t m, const int32_t *row_ptr, const int32_
             if (opt_in->slots_per_block) opt.slots_per_block = opt_in->slots_per_block;
             if (opt_in->visited_threshold) opt.visited_threshold = opt_in->visited_threshold;
             if (opt_in->big_row) opt.big_row = opt_in->big_row;
+            if (opt_in->threads_per_block) opt.threads_per_block = opt_in->threads_per_block;
             opt.build_inverse_index = opt_in->build_inverse_index;
             opt.max_device_bytes = opt_in->max_device_bytes;
             opt.staging_entries = opt_in->staging_entries;
@@ -180,6 +182,7 @@ int skis_build_sketch(int32_t n, int64_t m, const int32_t *row_ptr, const int32_
                 } else {
                     skis::SampleConfig cfg;
                     cfg.form = opt.form;
+                    cfg.threads = opt.threads_per_block;
                     cfg.slots = opt.slots_per_block;
                     cfg.visited = opt.visited_threshold;
                     cfg.big_row = opt.big_row;

@@ -7,13 +7,26 @@ namespace skis {
 
 enum : int { ERR_ROWPTR = 1, ERR_COL = 2, ERR_SELFLOOP = 4, ERR_WEIGHT = 8 };
 
+constexpr int32_t LONG_ROW = 256; // rows above this length are taken by a whole wave
+
+__device__ __forceinline__ int check_edge(int32_t u, float wf, int64_t v, int32_t n)
+{
+    int bad = 0;
+    if (u < 0 || u >= n) bad |= ERR_COL;
+    if (u == (int32_t)v) bad |= ERR_SELFLOOP;
+    if (!(wf >= 0.0f && wf <= 1.0f)) bad |= ERR_WEIGHT;
+    return bad;
+}
+
 // One thread per row: validates the row, writes the interleaved (col, w) records and the
 // running products P[e] = P[e-1] * (1 - w[e]) in row order (one rounding each; the
 // build disables contraction, and __dmul_rn / __dsub_rn pin the operations), q[v] = last P.
+// Rows longer than LONG_ROW are listed for k_prep_long.
 __global__ __launch_bounds__(256) void k_prep_rows(int32_t n, int64_t m, const int32_t *__restrict__ row_ptr,
                                                    const int32_t *__restrict__ col, const float *__restrict__ w,
                                                    int32_t *__restrict__ rp_copy, uint2 *__restrict__ edges,
-                                                   double *__restrict__ P, double *__restrict__ q, int *err)
+                                                   double *__restrict__ P, double *__restrict__ q, int *err,
+                                                   int32_t *__restrict__ long_rows, unsigned int *__restrict__ n_long)
 {
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
         const int32_t a = row_ptr[v], b = row_ptr[v + 1];
@@ -27,13 +40,16 @@ __global__ __launch_bounds__(256) void k_prep_rows(int32_t n, int64_t m, const i
             q[v] = 1.0;
             continue;
         }
+        if (b - a > LONG_ROW) {
+            long_rows[atomicAdd(n_long, 1u)] = (int32_t)v;
+            if (bad) atomicOr(err, bad);
+            continue;
+        }
         double prod = 1.0;
         for (int32_t e = a; e < b; ++e) {
             const int32_t u = col[e];
             float wf = w[e];
-            if (u < 0 || u >= n) bad |= ERR_COL;
-            if (u == (int32_t)v) bad |= ERR_SELFLOOP;
-            if (!(wf >= 0.0f && wf <= 1.0f)) bad |= ERR_WEIGHT;
+            bad |= check_edge(u, wf, v, n);
             if (wf == 0.0f) wf = 0.0f; // -0 -> +0: the coin reads the bits
             edges[e] = make_uint2((uint32_t)u, __float_as_uint(wf));
             prod = __dmul_rn(prod, __dsub_rn(1.0, (double)wf));
@@ -41,6 +57,58 @@ __global__ __launch_bounds__(256) void k_prep_rows(int32_t n, int64_t m, const i
         }
         q[v] = prod;
         if (bad) atomicOr(err, bad);
+    }
+}
+
+// One wave per long row: the lanes load and validate 64 edges at a time and stage the
+// factors (1 - w) in LDS; lane 0 extends the running product through them in row order
+// (the same sequence of roundings as one thread would do), then all lanes store P.
+__global__ __launch_bounds__(256) void k_prep_long(int32_t n, const int32_t *__restrict__ row_ptr,
+                                                   const int32_t *__restrict__ col, const float *__restrict__ w,
+                                                   uint2 *__restrict__ edges, double *__restrict__ P,
+                                                   double *__restrict__ q, int *err,
+                                                   const int32_t *__restrict__ long_rows,
+                                                   const unsigned int *__restrict__ n_long)
+{
+    __shared__ double fac[4][64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const unsigned int cnt = *n_long;
+    for (unsigned int r = blockIdx.x * 4 + wid; r < cnt; r += gridDim.x * 4) {
+        const int32_t v = long_rows[r];
+        const int32_t a = row_ptr[v], b = row_ptr[v + 1];
+        double prod = 1.0; // meaningful in lane 0
+        int bad = 0;
+        for (int32_t c0 = a; c0 < b; c0 += 64) {
+            const int32_t e = c0 + lane;
+            if (e < b) {
+                const int32_t u = col[e];
+                float wf = w[e];
+                bad |= check_edge(u, wf, v, n);
+                if (wf == 0.0f) wf = 0.0f;
+                edges[e] = make_uint2((uint32_t)u, __float_as_uint(wf));
+                fac[wid][lane] = __dsub_rn(1.0, (double)wf);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int len = (b - c0) < 64 ? (b - c0) : 64;
+            if (lane == 0) {
+                for (int i = 0; i < len; ++i) {
+                    prod = __dmul_rn(prod, fac[wid][i]);
+                    fac[wid][i] = prod;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (e < b) P[e] = fac[wid][lane];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        if (lane == 0) q[v] = prod;
+        bad = __reduce_or_sync(~0ull, bad);
+        if (lane == 0 && bad) atomicOr(err, bad);
     }
 }
 
@@ -225,10 +293,16 @@ void preprocess(Arena &arena, int32_t n, int64_t m, const int32_t *row_ptr, cons
     out.W.alloc(arena, (size_t)n);
     SKIS_HIP_TRY(hipMemsetAsync(out.edges.ptr, 0, out.edges.bytes(), s));
     DevBuf<int> err;
-    err.alloc(arena, 1);
-    SKIS_HIP_TRY(hipMemsetAsync(err.ptr, 0, sizeof(int), s));
+    err.alloc(arena, 2);
+    SKIS_HIP_TRY(hipMemsetAsync(err.ptr, 0, 2 * sizeof(int), s));
+    DevBuf<int32_t> long_rows;
+    long_rows.alloc(arena, (size_t)n);
+    unsigned int *n_long = reinterpret_cast<unsigned int *>(err.ptr + 1);
     hipLaunchKernelGGL(k_prep_rows, dim3(grid_for(n)), dim3(256), 0, s, n, m, row_ptr, col, w, out.row_ptr.ptr,
-                       out.edges.ptr, out.P.ptr, out.q.ptr, err.ptr);
+                       out.edges.ptr, out.P.ptr, out.q.ptr, err.ptr, long_rows.ptr, n_long);
+    SKIS_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_prep_long, dim3((unsigned)device_cu_count() * 4), dim3(256), 0, s, n, row_ptr, col, w,
+                       out.edges.ptr, out.P.ptr, out.q.ptr, err.ptr, long_rows.ptr, n_long);
     SKIS_HIP_TRY(hipGetLastError());
     int herr = 0;
     SKIS_HIP_TRY(hipMemcpyAsync(&herr, err.ptr, sizeof(int), hipMemcpyDeviceToHost, s));

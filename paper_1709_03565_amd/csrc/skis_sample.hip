@@ -635,29 +635,39 @@ struct Counters {
 typedef void (*SampleKernel)(SampleArgs);
 
 struct Variant {
-    uint32_t slots, visited;
+    uint32_t threads, slots, visited;
     SampleKernel fn;
 };
 
-// first (LDS) tier variants: (slots per workgroup, LDS visited capacity)
+// LDS-tier variants: (threads per workgroup, slots per workgroup, LDS visited capacity).
+// With 64 threads a workgroup is one wave that owns its slots and LDS and never waits for
+// another wave; with 256 threads four waves share the slots and meet at barriers.
 static const Variant kTier0[] = {
-    {32, 128, k_sample<256, 32, 8, 1024, false>},
-    {16, 256, k_sample<256, 16, 9, 1024, false>},
-    {32, 256, k_sample<256, 32, 9, 1024, false>},
-    {8, 512, k_sample<256, 8, 10, 1024, false>},
-    {16, 128, k_sample<256, 16, 8, 1024, false>},
+    {64, 8, 128, k_sample<64, 8, 8, 256, false>},
+    {64, 8, 64, k_sample<64, 8, 7, 256, false>},
+    {64, 16, 128, k_sample<64, 16, 8, 512, false>},
+    {64, 4, 256, k_sample<64, 4, 9, 256, false>},
+    {64, 16, 64, k_sample<64, 16, 7, 512, false>},
+    {256, 32, 128, k_sample<256, 32, 8, 1024, false>},
+    {256, 16, 256, k_sample<256, 16, 9, 1024, false>},
+    {256, 32, 256, k_sample<256, 32, 9, 1024, false>},
+    {256, 8, 512, k_sample<256, 8, 10, 1024, false>},
+    {256, 16, 128, k_sample<256, 16, 8, 1024, false>},
 };
-// second tier: samples that outgrew the first, 8 slots of 1024 nodes in LDS
-static SampleKernel const kTierMid = k_sample<256, 8, 11, 1024, false>;
+// second tier: samples that outgrew the first, slots of 1024 nodes in LDS
+static const Variant kTierMidV[] = {
+    {64, 2, 1024, k_sample<64, 2, 11, 256, false>},
+    {256, 8, 1024, k_sample<256, 8, 11, 1024, false>},
+};
 // last tier: a bitmap of n bits and a node list of n entries per slot in HBM
 constexpr int TIERG_SLOTS = 4;
 static SampleKernel const kTierGlobal = k_sample<256, TIERG_SLOTS, 1, 1024, true>;
 
-static SampleKernel pick_tier0(uint32_t slots, uint32_t visited)
+static const Variant &pick_variant(const Variant *vs, size_t nv, uint32_t threads, uint32_t slots, uint32_t visited)
 {
-    for (const Variant &v : kTier0)
-        if (v.slots == slots && v.visited == visited) return v.fn;
-    throw Error{SKIS_EINVAL, "unsupported (slots_per_block, visited_threshold) pair"};
+    for (size_t i = 0; i < nv; ++i)
+        if (vs[i].threads == threads && vs[i].slots == slots && vs[i].visited == visited) return vs[i];
+    throw Error{SKIS_EINVAL, "unsupported (threads_per_block, slots_per_block, visited_threshold) combination"};
 }
 
 static int occupancy_blocks(SampleKernel fn, int block)
@@ -725,10 +735,11 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
     uint64_t cap = cfg.staging_entries ? cfg.staging_entries : (uint64_t)count * 48ull + (1ull << 20);
     DevBuf<int32_t> staging;
     Counters hc{};
-    SampleKernel t0 = pick_tier0(cfg.slots, cfg.visited);
+    const Variant &v0 = pick_variant(kTier0, sizeof(kTier0) / sizeof(kTier0[0]), cfg.threads, cfg.slots, cfg.visited);
+    const Variant &vm = kTierMidV[cfg.threads == 64 ? 0 : 1];
     const int cus = device_cu_count();
-    const int nb0 = occupancy_blocks(t0, 256) * cus;
-    const int nbm = occupancy_blocks(kTierMid, 256) * cus;
+    const int nb0 = occupancy_blocks(v0.fn, (int)v0.threads) * cus;
+    const int nbm = occupancy_blocks(vm.fn, (int)vm.threads) * cus;
     const uint64_t words = ((uint64_t)n + 31) / 32;
     // global tier: every slot holds a bitmap of n bits and a node list of n entries; keep
     // all slots within about 4 GiB
@@ -786,7 +797,7 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
             need(p, "sampler argument");
         // tier 0: every sample, LDS visited sets of cfg.visited nodes
         SKIS_HIP_TRY(hipEventRecord(ev[4], s));
-        hipLaunchKernelGGL(t0, dim3(nb0), dim3(256), 0, s, A);
+        hipLaunchKernelGGL(v0.fn, dim3(nb0), dim3(v0.threads), 0, s, A);
         SKIS_HIP_TRY(hipGetLastError());
         SKIS_HIP_TRY(hipEventRecord(ev[5], s));
         read_counters();
@@ -802,7 +813,7 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
             A.deferred = deferred2.ptr;
             A.big_row = std::max<uint32_t>(cfg.big_row, 1u << 20);
             SKIS_HIP_TRY(hipEventRecord(ev[6], s));
-            hipLaunchKernelGGL(kTierMid, dim3(nbm), dim3(256), 0, s, A);
+            hipLaunchKernelGGL(vm.fn, dim3(nbm), dim3(vm.threads), 0, s, A);
             SKIS_HIP_TRY(hipGetLastError());
             SKIS_HIP_TRY(hipEventRecord(ev[7], s));
             ran_mid = true;

@@ -31,7 +31,7 @@ class SkisError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("form", ctypes.c_uint32), ("slots_per_block", ctypes.c_uint32),
                 ("visited_threshold", ctypes.c_uint32), ("big_row", ctypes.c_uint32),
-                ("build_inverse_index", ctypes.c_uint32), ("reserved0", ctypes.c_uint32),
+                ("build_inverse_index", ctypes.c_uint32), ("threads_per_block", ctypes.c_uint32),
                 ("max_device_bytes", ctypes.c_uint64), ("staging_entries", ctypes.c_uint64)]
 
 
