@@ -81,15 +81,36 @@ __device__ __forceinline__ T wave_sum(T v)
     return v;
 }
 
+// Workgroup barrier.  A one-wave workgroup only needs its LDS operations ordered: the
+// wavefront-scope fences keep the compiler from moving LDS accesses across the call and
+// the wave issues its LDS instructions in order, so no wait for outstanding global memory
+// operations is forced (s_barrier with a full waitcnt would be).
+template <int BLOCK>
+__device__ __forceinline__ void block_sync()
+{
+    if constexpr (BLOCK == 64) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
 // Block exclusive prefix sum of one value per thread.  `ws` is LDS scratch of at least
-// BLOCK/64 + 1 entries; the call contains two barriers and returns the block total in
-// *total.  Every thread of the block must call it.
+// BLOCK/64 + 1 entries; for more than one wave the call contains two barriers.  Returns
+// the block total in *total.  Every thread of the block must call it.
 template <int BLOCK, typename T>
 __device__ __forceinline__ T block_excl_scan(T v, T *ws, T *total)
 {
     constexpr int NW = BLOCK / 64;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     T inc = wave_incl_scan(v);
+    if constexpr (NW == 1) {
+        (void)ws;
+        *total = __shfl(inc, 63, 64);
+        return inc - v;
+    }
     if (lane == 63) ws[wid] = inc;
     __syncthreads();
     if (threadIdx.x == 0) {

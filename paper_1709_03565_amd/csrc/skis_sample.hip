@@ -181,7 +181,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
         s_idnext = 0;
         s_idend = 0;
     }
-    __syncthreads();
+    block_sync<BLOCK>();
 
     for (;;) {
         // ---- A: wave 0, lane s owns slot s: finish, admit, hand out items -----------------
@@ -328,7 +328,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                 s_alive = amask != 0ull;
             }
         }
-        __syncthreads();
+        block_sync<BLOCK>();
 
         // ---- B1: write out finished samples, clear their visited sets ----------------------
         for (int s = 0; s < S; ++s) {
@@ -369,7 +369,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                 }
             }
         }
-        __syncthreads();
+        block_sync<BLOCK>();
         if (tid < S && s_flags[tid] == F_CLEAR) {
             s_flags[tid] = 0;
             s_wo_cnt[tid] = 0;
@@ -409,7 +409,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
             it_end[it] = end;
             it_pb[it] = end > beg ? ((end - 1) >> 1) - (beg >> 1) + 1 : 0;
         }
-        __syncthreads();
+        block_sync<BLOCK>();
 
         // ---- B3: prefix sum of edge pairs over the items -----------------------------------
         {
@@ -431,7 +431,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
             }
             if (tid == 0) it_pb[nitems] = tot;
         }
-        __syncthreads();
+        block_sync<BLOCK>();
 
         // ---- B4: live-edge coins for every edge pair, visits ------------------------------
         // Each lane takes PPL consecutive pairs: one search for the first pair's item, the
@@ -477,7 +477,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                 if (e0 + 1 < pend[g] && coin_live(pr[g].w, Y)) visit(sl, (int32_t)pr[g].z);
             }
         }
-        __syncthreads();
+        block_sync<BLOCK>();
         if (!s_alive) break;
     }
 }
