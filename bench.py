@@ -88,6 +88,7 @@ def main():
     ap.add_argument("--slots", type=int, default=0)
     ap.add_argument("--visited", type=int, default=0)
     ap.add_argument("--threads", type=int, default=0)
+    ap.add_argument("--form", type=int, default=0, help="0: persistent sampler, 1: plain (one launch per level)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (for scaling HBM byte counters) and exit")
@@ -137,6 +138,8 @@ def main():
         opts["visited_threshold"] = args.visited
     if args.threads:
         opts["threads_per_block"] = args.threads
+    if args.form:
+        opts["form"] = args.form
     torch.cuda.synchronize()
 
     def step():

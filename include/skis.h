@@ -116,6 +116,8 @@ typedef struct skis_info {
     double ms_preprocess, ms_roots, ms_sample, ms_compact, ms_inverse; /* stage times (events) */
     double ms_tier0, ms_tier1, ms_tier2; /* the three sampler tiers' launches alone */
     uint64_t deferred_global;    /* samples that reached the HBM tier */
+    uint32_t plain_levels;       /* plain form: BFS level launches (0 for the persistent form) */
+    uint32_t reserved1;
 } skis_info;
 
 /* Sketch facts (host out-param). */

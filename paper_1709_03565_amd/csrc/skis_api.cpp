@@ -153,7 +153,7 @@ int skis_build_sketch(int32_t n, int64_t m, const int32_t *row_ptr, const int32_
             opt.max_device_bytes = opt_in->max_device_bytes;
             opt.staging_entries = opt_in->staging_entries;
         }
-        if (opt.form > 0) throw skis::Error{SKIS_EINVAL, "unknown sampler form"};
+        if (opt.form > 1) throw skis::Error{SKIS_EINVAL, "unknown sampler form"};
         skis_sketch *h = new skis_sketch;
         try {
             skis::Sketch &sk = h->core;
@@ -237,6 +237,7 @@ int skis_sketch_info(const skis_sketch *h, skis_info *info)
         info->ms_tier1 = sk.ms_tier1;
         info->ms_tier2 = sk.ms_tier2;
         info->deferred_global = sk.deferred_global;
+        info->plain_levels = sk.plain_levels;
         return SKIS_OK;
     });
 }

@@ -103,6 +103,7 @@ struct Sketch {
     double ms_preprocess = 0, ms_roots = 0, ms_sample = 0, ms_compact = 0, ms_inverse = 0;
     double ms_tier0 = 0, ms_tier1 = 0, ms_tier2 = 0; // the sampler launches alone
     uint64_t deferred_global = 0;                    // samples that reached the HBM tier
+    uint32_t plain_levels = 0;                       // BFS level launches of the plain form
 };
 
 // ---------------------------------------------------------------------------------

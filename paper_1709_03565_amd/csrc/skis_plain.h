@@ -1,0 +1,33 @@
+// skis_plain.h -- the plain (one launch per BFS level) form of the sampler.
+#pragma once
+#include "skis_internal.h"
+
+namespace skis {
+
+struct PlainInputs {
+    uint32_t count;                 // samples 0..count-1
+    const int32_t *row_ptr;
+    const uint4 *pairs;
+    int64_t npairs;
+    const int4 *rec;
+    const int32_t *u1;
+    uint32_t seed_lo, seed_hi;
+    uint64_t expected_size;         // expected |R_j|, sizes the chunk buffers
+    int32_t *staging;
+    uint64_t stage_cap;
+    uint32_t *out_size;
+    unsigned long long *out_off;
+    unsigned long long *out_probed;
+    uint32_t *medium;
+    unsigned long long *n_medium;
+    int small_sort;
+};
+
+struct PlainOutputs {
+    uint64_t entries = 0;
+    uint32_t levels = 0;            // BFS levels launched, over all chunks
+};
+
+void sample_plain(Arena &arena, const PlainInputs &in, PlainOutputs &out, hipStream_t s);
+
+} // namespace skis

@@ -18,6 +18,7 @@
 #include <algorithm>
 
 #include "skis_internal.h"
+#include "skis_plain.h"
 
 namespace skis {
 
@@ -759,7 +760,39 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
         hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(1), dim3(64), 0, s, (uint64_t)1, &ctr.ptr->n_deferred, 0ull);
     };
 
-    for (int attempt = 0; attempt < 2; ++attempt) {
+    if (cfg.form == 1) {
+        // plain form: one launch per BFS level over all samples of a chunk
+        staging.alloc(arena, cap);
+        hipLaunchKernelGGL(k_fill<unsigned char>, dim3(1), dim3(64), 0, s, (uint64_t)sizeof(Counters),
+                           reinterpret_cast<unsigned char *>(ctr.ptr), (unsigned char)0);
+        PlainInputs in{};
+        in.count = count;
+        in.row_ptr = prep.row_ptr.ptr;
+        in.pairs = reinterpret_cast<const uint4 *>(prep.edges.ptr);
+        in.npairs = (int64_t)(prep.edges.count / 2);
+        in.rec = rec.ptr;
+        in.u1 = u1.ptr;
+        in.seed_lo = seed_lo;
+        in.seed_hi = seed_hi;
+        in.expected_size = 48;
+        in.staging = staging.ptr;
+        in.stage_cap = cap;
+        in.out_size = out_size.ptr;
+        in.out_off = out_off.ptr;
+        in.out_probed = reinterpret_cast<unsigned long long *>(sk.probed.ptr);
+        in.medium = medium.ptr;
+        in.n_medium = &ctr.ptr->n_medium;
+        in.small_sort = SMALL_SORT;
+        PlainOutputs po;
+        SKIS_HIP_TRY(hipEventRecord(ev[4], s));
+        sample_plain(arena, in, po, s);
+        SKIS_HIP_TRY(hipEventRecord(ev[5], s));
+        read_counters();
+        sk.deferred = 0;
+        sk.deferred_global = 0;
+        sk.plain_levels = po.levels;
+    }
+    for (int attempt = 0; attempt < 2 && cfg.form == 0; ++attempt) {
         staging.alloc(arena, cap);
         hipLaunchKernelGGL(k_fill<unsigned char>, dim3(1), dim3(64), 0, s, (uint64_t)sizeof(Counters),
                            reinterpret_cast<unsigned char *>(ctr.ptr), (unsigned char)0);

@@ -43,7 +43,8 @@ class Info(ctypes.Structure):
                 ("ms_roots", ctypes.c_double), ("ms_sample", ctypes.c_double),
                 ("ms_compact", ctypes.c_double), ("ms_inverse", ctypes.c_double),
                 ("ms_tier0", ctypes.c_double), ("ms_tier1", ctypes.c_double),
-                ("ms_tier2", ctypes.c_double), ("deferred_global", ctypes.c_uint64)]
+                ("ms_tier2", ctypes.c_double), ("deferred_global", ctypes.c_uint64),
+                ("plain_levels", ctypes.c_uint32), ("reserved1", ctypes.c_uint32)]
 
 
 _lib = None
@@ -149,6 +150,7 @@ class SketchInfo:
     ms_tier1: float
     ms_tier2: float
     deferred_global: int
+    plain_levels: int
 
 
 class Sketch:
@@ -174,7 +176,8 @@ class Sketch:
         _check(lib().skis_sketch_info(self._h, ctypes.byref(i)))
         return SketchInfo(i.n, i.T, i.entries, i.probed_total, i.deferred, i.C, i.Gamma, i.device_bytes,
                           i.ms_preprocess, i.ms_roots, i.ms_sample, i.ms_compact, i.ms_inverse,
-                          i.ms_tier0, i.ms_tier1, i.ms_tier2, i.deferred_global)
+                          i.ms_tier0, i.ms_tier1, i.ms_tier2, i.deferred_global,
+                          i.plain_levels)
 
     def estimate(self, set_ptr, set_nodes):
         """(cov uint64[Q], est float64[Q]) device tensors for seed sets in CSR form."""

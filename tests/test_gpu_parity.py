@@ -146,6 +146,25 @@ def test_large_cascades_global_tier(skis, scale):
     _assert_sketch_equal(sk, ora)
 
 
+@pytest.mark.parametrize("which", ["cl15k", "large"])
+def test_plain_form_matches_oracle_and_persistent(skis, which):
+    # the one-launch-per-level form gives the same sketch, bit for bit
+    if which == "cl15k":
+        g = inputs.workload_graph("cl15k_wc")
+        rp, c, w, T = g.row_ptr, g.col, g.w, 30000
+    else:
+        g = inputs.chung_lu_graph(30000, 300000, 2.1, 77, "wc", cache=False)
+        rp, c, w, T = g.row_ptr, g.col, np.minimum(g.w * 2.5, 1.0).astype(np.float32), 2000
+    _say("plain form", which)
+    ora = oracle.build_sketch(rp, c, w, seed=13, j0=0, j1=T, nthreads=8)
+    plain = skis.build_sketch(rp, c, w, T, 13, form=1)
+    assert plain.info().plain_levels > 0
+    _assert_sketch_equal(plain, ora)
+    pers = skis.build_sketch(rp, c, w, T, 13)
+    for x, y in zip(plain.export(), pers.export()):
+        assert torch.equal(x, y)
+
+
 def test_tiny_and_degenerate_shapes(skis):
     cases = []
     # two-edge star, single edge, deterministic weights, multi-edges, empty rows
@@ -164,6 +183,7 @@ def test_tiny_and_degenerate_shapes(skis):
             ora = oracle.build_sketch(rp, c, w, seed=3, j0=0, j1=T)
             sk = skis.build_sketch(rp, c, w, T, 3)
             _assert_sketch_equal(sk, ora)
+            _assert_sketch_equal(skis.build_sketch(rp, c, w, T, 3, form=1), ora)
 
 
 def test_staging_overflow_retry(skis):
