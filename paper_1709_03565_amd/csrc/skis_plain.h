@@ -13,8 +13,7 @@ struct PlainInputs {
     const int32_t *u1;
     uint32_t seed_lo, seed_hi;
     uint64_t expected_size;         // expected |R_j|, sizes the chunk buffers
-    int32_t *staging;
-    uint64_t stage_cap;
+    DevBuf<int32_t> *staging;       // grown (contents kept) when a chunk does not fit
     uint32_t *out_size;
     unsigned long long *out_off;
     unsigned long long *out_probed;

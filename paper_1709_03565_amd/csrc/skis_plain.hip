@@ -15,6 +15,7 @@ constexpr unsigned long long HASH_EMPTY = ~0ull;
 constexpr int PLAIN_BLOCK = 256;
 constexpr int PLAIN_PPT = 4;                              // edge pairs per thread per launch window
 constexpr int PLAIN_WINDOW = PLAIN_BLOCK * PLAIN_PPT;     // pairs per workgroup window
+constexpr uint64_t PLAIN_MAX_PROBE = 4096;                // longest probe run before a resize
 
 struct PlainCtx {
     const int32_t *row_ptr;
@@ -43,7 +44,7 @@ __device__ __forceinline__ void plain_visit(const PlainCtx &c, uint32_t i, int32
 {
     const unsigned long long key = ((unsigned long long)i << 32) | (uint32_t)u;
     uint64_t h = (key * 0x9E3779B97F4A7C15ull) >> 20;
-    for (uint64_t probe = 0; probe <= c.hmask; ++probe) {
+    for (uint64_t probe = 0; probe < PLAIN_MAX_PROBE; ++probe) {
         h &= c.hmask;
         const unsigned long long old = atomicCAS(&c.hash[h], HASH_EMPTY, key);
         if (old == HASH_EMPTY) {
@@ -64,7 +65,7 @@ __device__ __forceinline__ void plain_visit(const PlainCtx &c, uint32_t i, int32
         if (old == key) return;
         ++h;
     }
-    atomicOr(c.err, 4); // table full
+    atomicOr(c.err, 4); // probe run too long: the chunk is redone with a larger table
 }
 
 // Level 0: root and first live in-edge of every sample; the root's later in-edges and the
@@ -81,7 +82,7 @@ __global__ __launch_bounds__(PLAIN_BLOCK) void k_plain_init(uint32_t count, uint
             const unsigned long long key = ((unsigned long long)t << 32) | (uint32_t)r.x;
             uint64_t h = (key * 0x9E3779B97F4A7C15ull) >> 20;
             bool done = false;
-            for (uint64_t probe = 0; probe <= c.hmask && !done; ++probe) {
+            for (uint64_t probe = 0; probe < PLAIN_MAX_PROBE && !done; ++probe) {
                 h &= c.hmask;
                 const unsigned long long old = atomicCAS(&c.hash[h], HASH_EMPTY, key);
                 if (old == HASH_EMPTY || old == key) done = true;
@@ -214,11 +215,8 @@ static unsigned gridp(uint64_t items, int per_cu = 16)
 void sample_plain(Arena &arena, const PlainInputs &in, PlainOutputs &out, hipStream_t s)
 {
     const uint32_t T = in.count;
-    // chunks of samples: the hash holds about 2.5x the chunk's expected entries
     const uint32_t chunk = std::min<uint32_t>(T, 1u << 21);
-    const uint64_t exp_entries = (uint64_t)chunk * std::max<uint64_t>(in.expected_size, 8);
-    uint64_t hcap = 1;
-    while (hcap < exp_entries * 5 / 2) hcap <<= 1;
+    uint64_t exp_size = std::max<uint64_t>(in.expected_size, 8);
     DevBuf<unsigned long long> hash;
     DevBuf<uint32_t> sizes, fill;
     DevBuf<unsigned long long> probed;
@@ -226,85 +224,120 @@ void sample_plain(Arena &arena, const PlainInputs &in, PlainOutputs &out, hipStr
     DevBuf<int4> itA, itB;
     DevBuf<uint32_t> np;
     DevBuf<int64_t> pbase, off;
-    DevBuf<unsigned long long> ctr; // n_entries, n_items_out, scratch
+    DevBuf<unsigned long long> ctr; // n_entries, n_items_out
     DevBuf<int> err;
-    hash.alloc(arena, hcap);
     sizes.alloc(arena, chunk);
     fill.alloc(arena, chunk);
     probed.alloc(arena, chunk);
-    const uint64_t ecap = exp_entries * 2 + (1u << 20);
-    entries.alloc(arena, ecap);
-    itA.alloc(arena, ecap);
-    itB.alloc(arena, ecap);
-    np.alloc(arena, ecap);
-    pbase.alloc(arena, ecap + 1);
     off.alloc(arena, (size_t)chunk + 1);
     ctr.alloc(arena, 4);
     err.alloc(arena, 1);
-    hipLaunchKernelGGL(k_plain_fill<int>, dim3(1), dim3(64), 0, s, (uint64_t)1, err.ptr, 0);
+    uint64_t hcap = 0, ecap = 0;
+    auto size_buffers = [&](uint64_t exp_entries, uint64_t min_hcap) {
+        uint64_t want_h = 1;
+        while (want_h < std::max<uint64_t>(exp_entries * 5 / 2, min_hcap)) want_h <<= 1;
+        const uint64_t want_e = exp_entries * 2 + (1u << 20);
+        if (want_h > hcap) {
+            hash.alloc(arena, want_h);
+            hcap = want_h;
+        }
+        if (want_e > ecap) {
+            entries.alloc(arena, want_e);
+            itA.alloc(arena, want_e);
+            itB.alloc(arena, want_e);
+            np.alloc(arena, want_e);
+            pbase.alloc(arena, want_e + 1);
+            ecap = want_e;
+        }
+    };
+    size_buffers((uint64_t)chunk * exp_size, 0);
 
     int64_t base = 0;
     out.levels = 0;
     for (uint32_t i0 = 0; i0 < T; i0 += chunk) {
         const uint32_t cn = std::min<uint32_t>(chunk, T - i0);
-        hipLaunchKernelGGL(k_plain_fill<unsigned long long>, dim3(gridp(hcap)), dim3(PLAIN_BLOCK), 0, s, hcap, hash.ptr,
-                           HASH_EMPTY);
-        hipLaunchKernelGGL(k_plain_fill<unsigned long long>, dim3(1), dim3(64), 0, s, (uint64_t)4, ctr.ptr, 0ull);
-        PlainCtx c;
-        c.row_ptr = in.row_ptr;
-        c.pairs = in.pairs;
-        c.npairs = in.npairs;
-        c.hash = hash.ptr;
-        c.hmask = hcap - 1;
-        c.sizes = sizes.ptr;
-        c.probed = probed.ptr;
-        c.entries = entries.ptr;
-        c.n_entries = ctr.ptr + 0;
-        c.entries_cap = ecap;
-        c.items_out = itA.ptr;
-        c.n_items_out = ctr.ptr + 1;
-        c.items_cap = ecap;
-        c.err = err.ptr;
-        hipLaunchKernelGGL(k_plain_init, dim3(gridp(cn)), dim3(PLAIN_BLOCK), 0, s, cn, i0, in.rec, in.u1, c);
-        SKIS_HIP_TRY(hipGetLastError());
-        int4 *cur = itA.ptr, *nxt = itB.ptr;
-        for (;;) {
-            unsigned long long hv[2];
-            SKIS_HIP_TRY(hipMemcpyAsync(hv, ctr.ptr, sizeof(hv), hipMemcpyDeviceToHost, s));
-            SKIS_HIP_TRY(hipStreamSynchronize(s));
-            const uint64_t n_items = hv[1];
-            if (n_items == 0) break;
-            if (n_items > ecap) throw Error{SKIS_EHIP, "plain sampler: frontier buffer too small"};
-            ++out.levels;
-            hipLaunchKernelGGL(k_plain_pairs, dim3(gridp(n_items)), dim3(PLAIN_BLOCK), 0, s, (uint64_t)n_items, cur,
-                               np.ptr);
-            excl_scan_u32_to_i64(arena, np.ptr, pbase.ptr, (int64_t)n_items, pbase.ptr + n_items, s);
-            int64_t total = 0;
-            SKIS_HIP_TRY(hipMemcpyAsync(&total, pbase.ptr + n_items, sizeof(total), hipMemcpyDeviceToHost, s));
-            hipLaunchKernelGGL(k_plain_fill<unsigned long long>, dim3(1), dim3(64), 0, s, (uint64_t)1, ctr.ptr + 1, 0ull);
-            SKIS_HIP_TRY(hipStreamSynchronize(s));
-            c.items_out = nxt;
-            const uint64_t wins = ((uint64_t)total + PLAIN_WINDOW - 1) / PLAIN_WINDOW;
-            const unsigned ge = (unsigned)std::min<uint64_t>(std::max<uint64_t>(wins, 1), (uint64_t)device_cu_count() * 16);
-            hipLaunchKernelGGL(k_plain_expand, dim3(ge), dim3(PLAIN_BLOCK), 0, s, (uint64_t)n_items, cur, pbase.ptr,
-                               total, in.seed_lo, in.seed_hi, (uint64_t)i0, c);
-            SKIS_HIP_TRY(hipGetLastError());
-            std::swap(cur, nxt);
-        }
-        int herr = 0;
-        SKIS_HIP_TRY(hipMemcpyAsync(&herr, err.ptr, sizeof(int), hipMemcpyDeviceToHost, s));
         unsigned long long ne = 0;
-        SKIS_HIP_TRY(hipMemcpyAsync(&ne, ctr.ptr, sizeof(ne), hipMemcpyDeviceToHost, s));
-        SKIS_HIP_TRY(hipStreamSynchronize(s));
-        if (herr) throw Error{SKIS_EHIP, "plain sampler: capacity or bounds check failed (flags " + std::to_string(herr) + ")"};
-        // chunk compaction
+        for (int attempt = 0;; ++attempt) {
+            hipLaunchKernelGGL(k_plain_fill<int>, dim3(1), dim3(64), 0, s, (uint64_t)1, err.ptr, 0);
+            hipLaunchKernelGGL(k_plain_fill<unsigned long long>, dim3(gridp(hcap)), dim3(PLAIN_BLOCK), 0, s, hcap,
+                               hash.ptr, HASH_EMPTY);
+            hipLaunchKernelGGL(k_plain_fill<unsigned long long>, dim3(1), dim3(64), 0, s, (uint64_t)4, ctr.ptr, 0ull);
+            PlainCtx c;
+            c.row_ptr = in.row_ptr;
+            c.pairs = in.pairs;
+            c.npairs = in.npairs;
+            c.hash = hash.ptr;
+            c.hmask = hcap - 1;
+            c.sizes = sizes.ptr;
+            c.probed = probed.ptr;
+            c.entries = entries.ptr;
+            c.n_entries = ctr.ptr + 0;
+            c.entries_cap = ecap;
+            c.items_out = itA.ptr;
+            c.n_items_out = ctr.ptr + 1;
+            c.items_cap = ecap;
+            c.err = err.ptr;
+            hipLaunchKernelGGL(k_plain_init, dim3(gridp(cn)), dim3(PLAIN_BLOCK), 0, s, cn, i0, in.rec, in.u1, c);
+            SKIS_HIP_TRY(hipGetLastError());
+            int4 *cur = itA.ptr, *nxt = itB.ptr;
+            bool overflow = false;
+            for (;;) {
+                unsigned long long hv[2];
+                int herr = 0;
+                SKIS_HIP_TRY(hipMemcpyAsync(hv, ctr.ptr, sizeof(hv), hipMemcpyDeviceToHost, s));
+                SKIS_HIP_TRY(hipMemcpyAsync(&herr, err.ptr, sizeof(int), hipMemcpyDeviceToHost, s));
+                SKIS_HIP_TRY(hipStreamSynchronize(s));
+                if (herr & 8) throw Error{SKIS_EHIP, "plain sampler: bounds check failed"};
+                if (herr || hv[1] > ecap) {
+                    overflow = true;
+                    break;
+                }
+                const uint64_t n_items = hv[1];
+                if (n_items == 0) break;
+                ++out.levels;
+                hipLaunchKernelGGL(k_plain_pairs, dim3(gridp(n_items)), dim3(PLAIN_BLOCK), 0, s, (uint64_t)n_items, cur,
+                                   np.ptr);
+                excl_scan_u32_to_i64(arena, np.ptr, pbase.ptr, (int64_t)n_items, pbase.ptr + n_items, s);
+                int64_t total = 0;
+                SKIS_HIP_TRY(hipMemcpyAsync(&total, pbase.ptr + n_items, sizeof(total), hipMemcpyDeviceToHost, s));
+                hipLaunchKernelGGL(k_plain_fill<unsigned long long>, dim3(1), dim3(64), 0, s, (uint64_t)1, ctr.ptr + 1,
+                                   0ull);
+                SKIS_HIP_TRY(hipStreamSynchronize(s));
+                c.items_out = nxt;
+                const uint64_t wins = ((uint64_t)total + PLAIN_WINDOW - 1) / PLAIN_WINDOW;
+                const unsigned ge =
+                    (unsigned)std::min<uint64_t>(std::max<uint64_t>(wins, 1), (uint64_t)device_cu_count() * 16);
+                hipLaunchKernelGGL(k_plain_expand, dim3(ge), dim3(PLAIN_BLOCK), 0, s, (uint64_t)n_items, cur,
+                                   pbase.ptr, total, in.seed_lo, in.seed_hi, (uint64_t)i0, c);
+                SKIS_HIP_TRY(hipGetLastError());
+                std::swap(cur, nxt);
+            }
+            SKIS_HIP_TRY(hipMemcpyAsync(&ne, ctr.ptr, sizeof(ne), hipMemcpyDeviceToHost, s));
+            SKIS_HIP_TRY(hipStreamSynchronize(s));
+            if (!overflow) break;
+            if (attempt == 6) throw Error{SKIS_ENOMEM, "plain sampler: chunk buffers kept overflowing"};
+            // the chunk is a pure function of its sample ids: grow and run it again
+            exp_size *= 4;
+            size_buffers(std::max<uint64_t>((uint64_t)cn * exp_size, ne * 2), hcap * 2);
+        }
+        // chunk compaction (staging grows, keeping what earlier chunks wrote)
+        if ((uint64_t)base + ne > in.staging->count) {
+            DevBuf<int32_t> bigger;
+            bigger.alloc(arena, std::max<uint64_t>(in.staging->count * 2, (uint64_t)base + ne + (1u << 20)));
+            if (base > 0)
+                SKIS_HIP_TRY(hipMemcpyAsync(bigger.ptr, in.staging->ptr, sizeof(int32_t) * (size_t)base,
+                                            hipMemcpyDeviceToDevice, s));
+            SKIS_HIP_TRY(hipStreamSynchronize(s));
+            in.staging->swap(bigger);
+        }
         excl_scan_u32_to_i64(arena, sizes.ptr, off.ptr, cn, off.ptr + cn, s);
         hipLaunchKernelGGL(k_plain_fill<uint32_t>, dim3(gridp(cn)), dim3(PLAIN_BLOCK), 0, s, (uint64_t)cn, fill.ptr, 0u);
         hipLaunchKernelGGL(k_plain_scatter, dim3(gridp(ne)), dim3(PLAIN_BLOCK), 0, s, (uint64_t)ne, entries.ptr, off.ptr,
-                           base, fill.ptr, in.staging, in.stage_cap, err.ptr);
+                           base, fill.ptr, in.staging->ptr, (uint64_t)in.staging->count, err.ptr);
         hipLaunchKernelGGL(k_plain_meta, dim3(gridp(cn)), dim3(PLAIN_BLOCK), 0, s, cn, i0, sizes.ptr, probed.ptr, off.ptr,
                            base, in.out_size, in.out_off, in.out_probed, in.medium, in.n_medium, in.small_sort);
         SKIS_HIP_TRY(hipGetLastError());
+        int herr = 0;
         SKIS_HIP_TRY(hipMemcpyAsync(&herr, err.ptr, sizeof(int), hipMemcpyDeviceToHost, s));
         SKIS_HIP_TRY(hipStreamSynchronize(s));
         if (herr) throw Error{SKIS_ENOMEM, "plain sampler: staging too small"};

@@ -775,8 +775,7 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
         in.seed_lo = seed_lo;
         in.seed_hi = seed_hi;
         in.expected_size = 48;
-        in.staging = staging.ptr;
-        in.stage_cap = cap;
+        in.staging = &staging;
         in.out_size = out_size.ptr;
         in.out_off = out_off.ptr;
         in.out_probed = reinterpret_cast<unsigned long long *>(sk.probed.ptr);
