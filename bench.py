@@ -89,6 +89,9 @@ def main():
     ap.add_argument("--visited", type=int, default=0)
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--form", type=int, default=0, help="0: persistent sampler, 1: plain (one launch per level)")
+    ap.add_argument("--no-autotune", action="store_true", help="use the library's default sampler shape")
+    ap.add_argument("--no-plain-compare", action="store_true",
+                    help="skip the untimed plain-form build that is reported beside the persistent sampler")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (for scaling HBM byte counters) and exit")
@@ -140,6 +143,12 @@ def main():
         opts["threads_per_block"] = args.threads
     if args.form:
         opts["form"] = args.form
+    tuned = None
+    if not args.no_autotune and args.form == 0 and not (args.slots or args.visited or args.threads):
+        from paper_1709_03565_amd import autotune
+        tuned = autotune.autotune(rp, col, w, pilot_samples=min(T, 1 << 21), log=log)
+        opts.update(autotune.options_from(tuned))
+        log("autotuned options: %s (%.2f ms on the pilot)" % (autotune.options_from(tuned), tuned["ms"]))
     torch.cuda.synchronize()
 
     def step():
@@ -210,6 +219,17 @@ def main():
             "tier0_ms": tier0_ms,
         },
     }
+    if tuned is not None:
+        line["config"]["sampler_options"] = autotune.options_from(tuned)
+    if not args.no_plain_compare and args.form == 0:
+        sk = skis.build_sketch(rp, col, w, T, inputs.SAMPLE_SEED, form=1, build_inverse_index=0)
+        pinf = sk.info()
+        sk.free()
+        line["plain_form"] = {"sampler_ms": pinf.ms_tier0, "levels": pinf.plain_levels,
+                              "persistent_sampler_ms": sampler_ms,
+                              "speedup_persistent_over_plain": pinf.ms_tier0 / sampler_ms}
+        log("plain form: sampler %.1f ms over %d level launches; persistent %.1f ms" %
+            (pinf.ms_tier0, pinf.plain_levels, sampler_ms))
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(g, wl, (set_ptr_np, set_nodes_np), args.k, T)
     print(json.dumps(line), flush=True)

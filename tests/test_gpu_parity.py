@@ -292,10 +292,11 @@ def test_errors_and_degenerate(skis):
 
 
 # ---------------------------------------------------------------------------------------
-# Full-size workload (1M nodes, 20M edges, 2^24 samples): sampled windows bit-exact
+# Full-size workloads (1M nodes / 20M edges / 2^24 samples, WC; 4M nodes / 70M edges / 2^25
+# samples, TRI): sampled windows bit-exact, properties at any size
 # ---------------------------------------------------------------------------------------
-def test_full_size_windows_cl1m(skis):
-    name = "cl1m_wc"
+@pytest.mark.parametrize("name", ["cl1m_wc", "cl4m_tri"])
+def test_full_size_windows(skis, name):
     g = inputs.workload_graph(name)
     T = inputs.WORKLOADS[name]["T"]
     _say("full-size build", name, T)
