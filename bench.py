@@ -146,7 +146,7 @@ def main():
     tuned = None
     if not args.no_autotune and args.form == 0 and not (args.slots or args.visited or args.threads):
         from paper_1709_03565_amd import autotune
-        tuned = autotune.autotune(rp, col, w, pilot_samples=min(T, 1 << 21), log=log)
+        tuned = autotune.autotune(rp, col, w, pilot_samples=T, log=log)
         opts.update(autotune.options_from(tuned))
         log("autotuned options: %s (%.2f ms on the pilot)" % (autotune.options_from(tuned), tuned["ms"]))
     torch.cuda.synchronize()
@@ -230,6 +230,20 @@ def main():
                               "speedup_persistent_over_plain": pinf.ms_tier0 / sampler_ms}
         log("plain form: sampler %.1f ms over %d level launches; persistent %.1f ms" %
             (pinf.ms_tier0, pinf.plain_levels, sampler_ms))
+    if not args.no_plain_compare and args.form == 0:
+        # the captured form: the same chain captured into a HIP graph, replayed per chunk
+        cinfs = []
+        for _ in range(2):
+            sk = skis.build_sketch(rp, col, w, T, inputs.SAMPLE_SEED, form=2, build_inverse_index=0,
+                                   **{k: v for k, v in opts.items() if k != "form"})
+            cinfs.append(sk.info())
+            sk.free()
+        cinf = min(cinfs, key=lambda x: x.ms_tier0)
+        line["captured_form"] = {"sampler_ms": cinf.ms_tier0, "graph_replays": cinf.graph_replays,
+                                 "chunk_samples": -(-T // cinf.graph_replays),
+                                 "persistent_sampler_ms": sampler_ms}
+        log("captured form: sampler %.1f ms over %d graph replays; persistent %.1f ms" %
+            (cinf.ms_tier0, cinf.graph_replays, sampler_ms))
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(g, wl, (set_ptr_np, set_nodes_np), args.k, T)
     print(json.dumps(line), flush=True)

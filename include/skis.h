@@ -49,7 +49,10 @@ typedef struct skis_sketch skis_sketch; /* opaque; owns every device buffer it a
 
 /* Sampler and memory knobs.  Zero fields mean "default"; skis_default_options fills them. */
 typedef struct skis_options {
-    uint32_t form;                /* 0: persistent sampler (default); 1: plain form, one launch per BFS level */
+    uint32_t form;                /* 0: persistent sampler (default); 1: plain form, one launch per BFS
+                                     level; 2: captured form, the persistent sampler's whole chain
+                                     (roots and the three tiers, with device-side work counts) captured
+                                     once into a HIP graph and replayed per chunk of chunk_samples ids */
     uint32_t slots_per_block;     /* samples in flight per workgroup of the first sampler tier */
     uint32_t visited_threshold;   /* nodes per sample kept in LDS by the first tier before the sample
                                      moves to the next tier */
@@ -61,6 +64,7 @@ typedef struct skis_options {
                                      (256,16,256), (256,32,256), (256,8,512), (256,16,128) */
     uint64_t max_device_bytes;    /* 0 = unlimited; larger total allocation -> SKIS_ENOMEM */
     uint64_t staging_entries;     /* initial staging capacity in node entries (0 = auto) */
+    uint64_t chunk_samples;       /* captured form: sample ids per graph replay (0 = 2^22) */
 } skis_options;
 
 /* Fills *opt with the defaults. */
@@ -114,10 +118,12 @@ typedef struct skis_info {
     double Gamma;                /* sum of gamma_v */
     uint64_t device_bytes;       /* bytes the sketch holds on the device */
     double ms_preprocess, ms_roots, ms_sample, ms_compact, ms_inverse; /* stage times (events) */
-    double ms_tier0, ms_tier1, ms_tier2; /* the three sampler tiers' launches alone */
+    double ms_tier0, ms_tier1, ms_tier2; /* the three sampler tiers' launches alone; the plain
+                                            and the captured form report their whole sampler
+                                            in ms_tier0 */
     uint64_t deferred_global;    /* samples that reached the HBM tier */
     uint32_t plain_levels;       /* plain form: BFS level launches (0 for the persistent form) */
-    uint32_t reserved1;
+    uint32_t graph_replays;      /* captured form: replays of the captured chain (0 otherwise) */
 } skis_info;
 
 /* Sketch facts (host out-param). */

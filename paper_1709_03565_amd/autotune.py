@@ -9,6 +9,12 @@ workgroup can be held by one sample.  autotune() times every candidate on a pilo
 of the real graph (sampling only, measured with the library's own HIP events) and returns
 the fastest; results are cached in a JSON file keyed by device, graph shape and a
 fingerprint of the edge probabilities.
+
+The pilot has to be about as large as the real build: a persistent launch ends with a tail
+in which a few large cascades hold the last workgroups, and that tail is a fixed cost, so
+on a small pilot shapes with short tails win even when they are slower per sample.  A
+first pass times every shape once; the three fastest are timed again and the best of those
+is refined over big_row.
 """
 from __future__ import annotations
 
@@ -45,7 +51,7 @@ def _device_key() -> str:
     return "%s/%d" % (getattr(p, "gcnArchName", p.name), p.multi_processor_count)
 
 
-def autotune(row_ptr, col, w, pilot_samples: int = 1 << 20, seed: int = 1, shapes=None, big_rows=None,
+def autotune(row_ptr, col, w, pilot_samples: int = 1 << 24, seed: int = 1, shapes=None, big_rows=None,
              repeats: int = 2, cache_path: str | None = _DEFAULT_CACHE, log=None) -> dict:
     """Returns the fastest options as a dict of skis_options field values, plus the timings."""
     key = "%s|%s|T=%d" % (_device_key(), _fingerprint(row_ptr, w), pilot_samples)
@@ -61,9 +67,9 @@ def autotune(row_ptr, col, w, pilot_samples: int = 1 << 20, seed: int = 1, shape
     big_rows = big_rows or BIG_ROWS
     results = []
 
-    def trial(opts):
+    def trial(opts, reps):
         best = None
-        for _ in range(repeats):
+        for _ in range(reps):
             sk = skis.build_sketch(row_ptr, col, w, pilot_samples, seed, build_inverse_index=0, **opts)
             inf = sk.info()
             sk.free()
@@ -74,15 +80,19 @@ def autotune(row_ptr, col, w, pilot_samples: int = 1 << 20, seed: int = 1, shape
             log("autotune %s: %.2f ms" % (opts, best))
         return best
 
-    best_opts, best_ms = None, None
+    first = []
     for (th, sl, vi) in shapes:
         o = dict(threads_per_block=th, slots_per_block=sl, visited_threshold=vi)
-        t = trial(o)
+        first.append((trial(o, 1), o))
+    first.sort(key=lambda x: x[0])
+    best_opts, best_ms = None, None
+    for _, o in first[:3]:
+        t = trial(o, repeats)
         if best_ms is None or t < best_ms:
             best_opts, best_ms = o, t
     for br in big_rows:
         o = dict(best_opts, big_row=br)
-        t = trial(o)
+        t = trial(o, repeats)
         if t < best_ms:
             best_opts, best_ms = o, t
     out = dict(best_opts, ms=best_ms, pilot_samples=pilot_samples, trials=results)

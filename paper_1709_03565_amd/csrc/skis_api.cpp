@@ -100,6 +100,7 @@ void skis_default_options(skis_options *opt)
     opt->build_inverse_index = 1;
     opt->max_device_bytes = 0;
     opt->staging_entries = 0;
+    opt->chunk_samples = 0;
 }
 
 int skis_preprocess(int32_t n, int64_t m, const int32_t *row_ptr, const int32_t *col, const float *w, double *P,
@@ -152,8 +153,9 @@ int skis_build_sketch(int32_t n, int64_t m, const int32_t *row_ptr, const int32_
             opt.build_inverse_index = opt_in->build_inverse_index;
             opt.max_device_bytes = opt_in->max_device_bytes;
             opt.staging_entries = opt_in->staging_entries;
+            opt.chunk_samples = opt_in->chunk_samples;
         }
-        if (opt.form > 1) throw skis::Error{SKIS_EINVAL, "unknown sampler form"};
+        if (opt.form > 2) throw skis::Error{SKIS_EINVAL, "unknown sampler form"};
         skis_sketch *h = new skis_sketch;
         try {
             skis::Sketch &sk = h->core;
@@ -187,6 +189,7 @@ int skis_build_sketch(int32_t n, int64_t m, const int32_t *row_ptr, const int32_
                     cfg.visited = opt.visited_threshold;
                     cfg.big_row = opt.big_row;
                     cfg.staging_entries = opt.staging_entries;
+                    cfg.chunk = opt.chunk_samples;
                     skis::sample_and_compact(sk.arena, prep, n, m, num_samples, seed, cfg, sk, stream);
                 }
                 // q moves into the sketch only after every kernel that reads prep.q has run
@@ -238,6 +241,7 @@ int skis_sketch_info(const skis_sketch *h, skis_info *info)
         info->ms_tier2 = sk.ms_tier2;
         info->deferred_global = sk.deferred_global;
         info->plain_levels = sk.plain_levels;
+        info->graph_replays = sk.graph_replays;
         return SKIS_OK;
     });
 }

@@ -104,6 +104,7 @@ struct Sketch {
     double ms_tier0 = 0, ms_tier1 = 0, ms_tier2 = 0; // the sampler launches alone
     uint64_t deferred_global = 0;                    // samples that reached the HBM tier
     uint32_t plain_levels = 0;                       // BFS level launches of the plain form
+    uint32_t graph_replays = 0;                      // replays of the captured chain (captured form)
 };
 
 // ---------------------------------------------------------------------------------
@@ -135,6 +136,7 @@ struct SampleConfig {
     uint32_t visited = 256;
     uint32_t big_row = 16384;
     uint64_t staging_entries = 0;
+    uint64_t chunk = 0; // captured form: samples per replay of the chain (0: 2^22)
 };
 
 void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, uint64_t T, uint64_t seed,

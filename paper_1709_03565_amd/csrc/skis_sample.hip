@@ -34,13 +34,19 @@ enum : int { F_ACTIVE = 1, F_ROOTPEND = 2, F_DEFER = 4, F_CLEAR = 8 };
 // Root and first live in-edge of every sample.
 //   rec[i] = (root, i*, row begin, row end), u1[i] = col[i*], for sample j = j0 + i.
 // ---------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_roots(uint64_t j0, uint32_t count, uint32_t seed_lo, uint32_t seed_hi,
+//   range (device, may be null): {base, count} of a chunk read at launch; the thread then
+//   covers i = base .. base+count-1 instead of 0 .. count-1.
+__global__ __launch_bounds__(256) void k_roots(uint64_t j0, uint32_t count, const unsigned long long *range,
+                                               uint32_t seed_lo, uint32_t seed_hi,
                                                int32_t n, uint64_t C, const AliasEntry *__restrict__ alias,
                                                const int32_t *__restrict__ row_ptr, const double *__restrict__ q,
                                                const double *__restrict__ P, const uint2 *__restrict__ edges,
                                                int4 *__restrict__ rec, int32_t *__restrict__ u1, int *__restrict__ err)
 {
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+    const uint32_t base = range ? (uint32_t)range[0] : 0u;
+    const uint32_t cnt = range ? (uint32_t)range[1] : count;
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < cnt; t += gridDim.x * blockDim.x) {
+        const uint32_t i = base + t;
         const uint64_t j = j0 + i;
         const uint32_t jl = (uint32_t)j, jh = (uint32_t)(j >> 32);
         uint64_t X, Y;
@@ -91,8 +97,10 @@ struct SampleArgs {
     uint64_t j0;
     uint32_t seed_lo, seed_hi;
     unsigned long long *next;   // id counter
-    const uint32_t *id_list;    // nullptr: ids 0..id_count-1; else id_list[0..id_count)
+    const uint32_t *id_list;    // nullptr: ids id_base..id_base+id_count-1; else id_list[0..id_count)
     uint64_t id_count;
+    const unsigned long long *id_count_dev; // when set, id_count is read from here at launch
+    const unsigned long long *id_base_dev;  // when set, id_base is read from here (else 0)
     uint32_t big_row;
     int32_t *staging;
     unsigned long long stage_cap;
@@ -138,6 +146,9 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
 
     const int tid = threadIdx.x;
     const int32_t n = a.n;
+    // the work of this launch; in a captured chain the previous kernel has written it
+    const unsigned long long id_count = a.id_count_dev ? *a.id_count_dev : a.id_count;
+    const unsigned long long id_base = a.id_base_dev ? *a.id_base_dev : 0ull;
 
     auto list_ptr = [&](int s) -> int32_t * {
         if constexpr (GLOBAL) return a.glist + ((size_t)blockIdx.x * S + s) * (size_t)n;
@@ -253,8 +264,8 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                         s_idend = nb + IDBATCH;
                     }
                 }
-                if (want && myid < a.id_count) {
-                    const uint32_t i = a.id_list ? a.id_list[myid] : (uint32_t)myid;
+                if (want && myid < id_count) {
+                    const uint32_t i = a.id_list ? a.id_list[myid] : (uint32_t)(id_base + myid);
                     const int4 rr = a.rec[i];
                     if ((uint32_t)rr.x >= (uint32_t)n || (uint32_t)a.u1[i] >= (uint32_t)n || rr.y < rr.z ||
                         rr.w <= rr.y || (int64_t)rr.w > 2 * a.npairs) {
@@ -614,6 +625,43 @@ __global__ __launch_bounds__(256) void k_fill(uint64_t count, T *__restrict__ p,
 }
 
 // ---------------------------------------------------------------------------------------
+// Chain control for the captured form: the graph [begin, roots, tier 0, tier 1, tier 2,
+// end] is replayed once per chunk of sample ids, and everything that changes between
+// replays lives in this record, so a replay needs nothing from the host.
+// ---------------------------------------------------------------------------------------
+struct ChainCtl {
+    unsigned long long cursor;            // first sample id not yet handed to a chunk
+    unsigned long long base, count;       // the current chunk: ids [base, base + count)
+    unsigned long long next0, next1, next2; // id counters of the three tiers
+    unsigned long long nd0, nd1;          // samples handed on by tier 0 / tier 1 in this chunk
+    unsigned long long tot0, tot1;        // the same, summed over chunks
+    unsigned long long replays;
+};
+
+__global__ __launch_bounds__(64) void k_chain_begin(ChainCtl *c, uint64_t T, uint64_t chunk)
+{
+    if (threadIdx.x != 0) return;
+    const unsigned long long cur = c->cursor;
+    const unsigned long long cnt = cur < T ? (T - cur < chunk ? T - cur : chunk) : 0ull;
+    c->base = cur;
+    c->count = cnt;
+    c->cursor = cur + cnt;
+    c->next0 = 0;
+    c->next1 = 0;
+    c->next2 = 0;
+    c->nd0 = 0;
+    c->nd1 = 0;
+}
+
+__global__ __launch_bounds__(64) void k_chain_end(ChainCtl *c)
+{
+    if (threadIdx.x != 0) return;
+    c->tot0 += c->nd0;
+    c->tot1 += c->nd1;
+    c->replays += 1;
+}
+
+// ---------------------------------------------------------------------------------------
 // Host orchestration.
 // ---------------------------------------------------------------------------------------
 static unsigned grid_cap(uint64_t items, int block, int per_cu = 16)
@@ -717,10 +765,12 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
     rerr.alloc(arena, 1);
     hipLaunchKernelGGL(k_fill<int>, dim3(1), dim3(64), 0, s, (uint64_t)1, rerr.ptr, 0);
     SKIS_HIP_TRY(hipEventRecord(ev[0], s));
-    hipLaunchKernelGGL(k_roots, dim3(grid_cap(count, 256, 64)), dim3(256), 0, s, (uint64_t)0, count, seed_lo, seed_hi,
-                       n, prep.C, prep.alias.ptr, prep.row_ptr.ptr, prep.q.ptr, prep.P.ptr, prep.edges.ptr, rec.ptr,
-                       u1.ptr, rerr.ptr);
-    SKIS_HIP_TRY(hipGetLastError());
+    if (cfg.form != 2) { // the captured form draws the roots inside its chain, chunk by chunk
+        hipLaunchKernelGGL(k_roots, dim3(grid_cap(count, 256, 64)), dim3(256), 0, s, (uint64_t)0, count,
+                           (const unsigned long long *)nullptr, seed_lo, seed_hi, n, prep.C, prep.alias.ptr,
+                           prep.row_ptr.ptr, prep.q.ptr, prep.P.ptr, prep.edges.ptr, rec.ptr, u1.ptr, rerr.ptr);
+        SKIS_HIP_TRY(hipGetLastError());
+    }
     SKIS_HIP_TRY(hipEventRecord(ev[1], s));
 
     DevBuf<uint32_t> out_size, deferred, medium;
@@ -760,6 +810,142 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
         hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(1), dim3(64), 0, s, (uint64_t)1, &ctr.ptr->n_deferred, 0ull);
     };
 
+    // Captured form: the whole chain for one chunk of ids -- chunk bounds, roots, the three
+    // tiers, each reading its work count from device memory -- is captured once into a HIP
+    // graph on a private stream and replayed ceil(T / chunk) times on s with no host
+    // round trip in between.  The HBM tier cannot be skipped on the host's word here, so
+    // its buffers are always allocated (at most about 1 GiB; each slot clears its own bits
+    // when its sample finishes, so they stay zero across replays).
+    auto sample_chain_graph = [&]() {
+        const uint64_t chunk = std::min<uint64_t>(count, cfg.chunk ? cfg.chunk : (1ull << 22));
+        const uint64_t replays = (count + chunk - 1) / chunk;
+        DevBuf<ChainCtl> gc;
+        gc.alloc(arena, 1);
+        const uint64_t nbg_g = std::max<uint64_t>(
+            1, std::min<uint64_t>((uint64_t)nbg, (1ull << 30) / (slot_bytes * TIERG_SLOTS)));
+        const uint64_t gslots = nbg_g * TIERG_SLOTS;
+        DevBuf<uint32_t> gbits;
+        DevBuf<int32_t> glist;
+        gbits.alloc(arena, gslots * words);
+        glist.alloc(arena, gslots * (uint64_t)n);
+        hipLaunchKernelGGL(k_fill<uint32_t>, dim3(grid_cap(gslots * words, 256)), dim3(256), 0, s, gslots * words,
+                           gbits.ptr, 0u);
+        need(gc.ptr, "chain control");
+        need(gbits.ptr, "gbits");
+        need(glist.ptr, "glist");
+        struct GraphGuard {
+            hipStream_t cs = nullptr;
+            hipGraph_t g = nullptr;
+            hipGraphExec_t x = nullptr;
+            bool capturing = false;
+            ~GraphGuard()
+            {
+                if (capturing) {
+                    hipGraph_t tmp = nullptr;
+                    (void)hipStreamEndCapture(cs, &tmp);
+                    if (tmp) (void)hipGraphDestroy(tmp);
+                }
+                if (x) (void)hipGraphExecDestroy(x);
+                if (g) (void)hipGraphDestroy(g);
+                if (cs) (void)hipStreamDestroy(cs);
+            }
+        } gg;
+        SKIS_HIP_TRY(hipStreamCreateWithFlags(&gg.cs, hipStreamNonBlocking));
+        for (int attempt = 0; attempt < 2; ++attempt) {
+            staging.alloc(arena, cap);
+            hipLaunchKernelGGL(k_fill<unsigned char>, dim3(1), dim3(64), 0, s, (uint64_t)sizeof(Counters),
+                               reinterpret_cast<unsigned char *>(ctr.ptr), (unsigned char)0);
+            hipLaunchKernelGGL(k_fill<unsigned char>, dim3(1), dim3(64), 0, s, (uint64_t)sizeof(ChainCtl),
+                               reinterpret_cast<unsigned char *>(gc.ptr), (unsigned char)0);
+            SKIS_HIP_TRY(hipGetLastError());
+            SampleArgs A{};
+            A.n = n;
+            A.row_ptr = prep.row_ptr.ptr;
+            A.pairs = reinterpret_cast<const uint4 *>(prep.edges.ptr);
+            A.npairs = (int64_t)(prep.edges.count / 2);
+            A.rec = rec.ptr;
+            A.u1 = u1.ptr;
+            A.j0 = 0;
+            A.seed_lo = seed_lo;
+            A.seed_hi = seed_hi;
+            A.staging = staging.ptr;
+            A.stage_cap = cap;
+            A.stage_used = &ctr.ptr->stage_used;
+            A.out_size = out_size.ptr;
+            A.out_off = out_off.ptr;
+            A.out_probed = reinterpret_cast<unsigned long long *>(sk.probed.ptr);
+            A.medium = medium.ptr;
+            A.n_medium = &ctr.ptr->n_medium;
+            A.overflow = &ctr.ptr->overflow;
+            A.words = words;
+            need(A.staging, "staging");
+            SampleArgs A0 = A, A1 = A, A2 = A;
+            A0.next = &gc.ptr->next0;
+            A0.id_list = nullptr;
+            A0.id_count_dev = &gc.ptr->count;
+            A0.id_base_dev = &gc.ptr->base;
+            A0.big_row = cfg.big_row;
+            A0.deferred = deferred.ptr;
+            A0.n_deferred = &gc.ptr->nd0;
+            A1.next = &gc.ptr->next1;
+            A1.id_list = deferred.ptr;
+            A1.id_count_dev = &gc.ptr->nd0;
+            A1.big_row = std::max<uint32_t>(cfg.big_row, 1u << 20);
+            A1.deferred = deferred2.ptr;
+            A1.n_deferred = &gc.ptr->nd1;
+            A2.next = &gc.ptr->next2;
+            A2.id_list = deferred2.ptr;
+            A2.id_count_dev = &gc.ptr->nd1;
+            A2.deferred = deferred.ptr; // unused: the HBM tier finishes every sample
+            A2.n_deferred = &ctr.ptr->n_deferred; // unused for the same reason
+            A2.gbits = gbits.ptr;
+            A2.glist = glist.ptr;
+
+            SKIS_HIP_TRY(hipStreamBeginCapture(gg.cs, hipStreamCaptureModeThreadLocal));
+            gg.capturing = true;
+            hipLaunchKernelGGL(k_chain_begin, dim3(1), dim3(64), 0, gg.cs, gc.ptr, (uint64_t)count, chunk);
+            hipLaunchKernelGGL(k_roots, dim3(grid_cap(chunk, 256, 64)), dim3(256), 0, gg.cs, (uint64_t)0, 0u,
+                               (const unsigned long long *)&gc.ptr->base, seed_lo, seed_hi, n, prep.C,
+                               prep.alias.ptr, prep.row_ptr.ptr, prep.q.ptr, prep.P.ptr, prep.edges.ptr, rec.ptr,
+                               u1.ptr, rerr.ptr);
+            hipLaunchKernelGGL(v0.fn, dim3(nb0), dim3(v0.threads), 0, gg.cs, A0);
+            hipLaunchKernelGGL(vm.fn, dim3(nbm), dim3(vm.threads), 0, gg.cs, A1);
+            hipLaunchKernelGGL(kTierGlobal, dim3((unsigned)nbg_g), dim3(256), 0, gg.cs, A2);
+            hipLaunchKernelGGL(k_chain_end, dim3(1), dim3(64), 0, gg.cs, gc.ptr);
+            const hipError_t launch_err = hipGetLastError();
+            gg.capturing = false;
+            SKIS_HIP_TRY(hipStreamEndCapture(gg.cs, &gg.g));
+            SKIS_HIP_TRY(launch_err);
+            SKIS_HIP_TRY(hipGraphInstantiate(&gg.x, gg.g, nullptr, nullptr, 0));
+            SKIS_HIP_TRY(hipEventRecord(ev[4], s));
+            for (uint64_t r = 0; r < replays; ++r) SKIS_HIP_TRY(hipGraphLaunch(gg.x, s));
+            SKIS_HIP_TRY(hipEventRecord(ev[5], s));
+            ChainCtl hg{};
+            SKIS_HIP_TRY(hipMemcpyAsync(&hg, gc.ptr, sizeof(hg), hipMemcpyDeviceToHost, s));
+            read_counters();
+            int herr = 0;
+            SKIS_HIP_TRY(hipMemcpyAsync(&herr, rerr.ptr, sizeof(int), hipMemcpyDeviceToHost, s));
+            SKIS_HIP_TRY(hipStreamSynchronize(s));
+            if ((hc.overflow & ~1) || herr)
+                throw Error{SKIS_EHIP, "internal bounds check failed in the sampler (flags " +
+                                           std::to_string(hc.overflow | herr) + ")"};
+            if (hg.replays != replays || hg.cursor != count)
+                throw Error{SKIS_EHIP, "internal error: the captured chain covered " + std::to_string(hg.cursor) +
+                                           " of " + std::to_string(count) + " samples"};
+            sk.deferred = hg.tot0;
+            sk.deferred_global = hg.tot1;
+            sk.graph_replays = (uint32_t)replays;
+            (void)hipGraphExecDestroy(gg.x);
+            (void)hipGraphDestroy(gg.g);
+            gg.x = nullptr;
+            gg.g = nullptr;
+            if (!hc.overflow) return;
+            cap = hc.stage_used + 1024; // every size is known now: exact retry
+            staging.reset();
+            if (attempt == 1) throw Error{SKIS_ENOMEM, "staging overflow after resize"};
+        }
+    };
+
     if (cfg.form == 1) {
         // plain form: one launch per BFS level over all samples of a chunk
         staging.alloc(arena, cap);
@@ -791,6 +977,7 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
         sk.deferred_global = 0;
         sk.plain_levels = po.levels;
     }
+    if (cfg.form == 2) sample_chain_graph();
     for (int attempt = 0; attempt < 2 && cfg.form == 0; ++attempt) {
         staging.alloc(arena, cap);
         hipLaunchKernelGGL(k_fill<unsigned char>, dim3(1), dim3(64), 0, s, (uint64_t)sizeof(Counters),

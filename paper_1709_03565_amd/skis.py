@@ -32,7 +32,8 @@ class Options(ctypes.Structure):
     _fields_ = [("form", ctypes.c_uint32), ("slots_per_block", ctypes.c_uint32),
                 ("visited_threshold", ctypes.c_uint32), ("big_row", ctypes.c_uint32),
                 ("build_inverse_index", ctypes.c_uint32), ("threads_per_block", ctypes.c_uint32),
-                ("max_device_bytes", ctypes.c_uint64), ("staging_entries", ctypes.c_uint64)]
+                ("max_device_bytes", ctypes.c_uint64), ("staging_entries", ctypes.c_uint64),
+                ("chunk_samples", ctypes.c_uint64)]
 
 
 class Info(ctypes.Structure):
@@ -44,7 +45,7 @@ class Info(ctypes.Structure):
                 ("ms_compact", ctypes.c_double), ("ms_inverse", ctypes.c_double),
                 ("ms_tier0", ctypes.c_double), ("ms_tier1", ctypes.c_double),
                 ("ms_tier2", ctypes.c_double), ("deferred_global", ctypes.c_uint64),
-                ("plain_levels", ctypes.c_uint32), ("reserved1", ctypes.c_uint32)]
+                ("plain_levels", ctypes.c_uint32), ("graph_replays", ctypes.c_uint32)]
 
 
 _lib = None
@@ -151,6 +152,7 @@ class SketchInfo:
     ms_tier2: float
     deferred_global: int
     plain_levels: int
+    graph_replays: int
 
 
 class Sketch:
@@ -177,7 +179,7 @@ class Sketch:
         return SketchInfo(i.n, i.T, i.entries, i.probed_total, i.deferred, i.C, i.Gamma, i.device_bytes,
                           i.ms_preprocess, i.ms_roots, i.ms_sample, i.ms_compact, i.ms_inverse,
                           i.ms_tier0, i.ms_tier1, i.ms_tier2, i.deferred_global,
-                          i.plain_levels)
+                          i.plain_levels, i.graph_replays)
 
     def estimate(self, set_ptr, set_nodes):
         """(cov uint64[Q], est float64[Q]) device tensors for seed sets in CSR form."""

@@ -165,6 +165,34 @@ def test_plain_form_matches_oracle_and_persistent(skis, which):
         assert torch.equal(x, y)
 
 
+@pytest.mark.parametrize("which,chunk", [("cl15k", 0), ("cl15k", 4096), ("cl15k", 1000), ("large", 300)])
+def test_captured_form_matches_oracle_and_persistent(skis, which, chunk):
+    # the captured chain (chunk bounds, roots, three tiers) replayed once per chunk of ids,
+    # the last chunk ragged, gives the same sketch bit for bit; two builds in a row
+    # instantiate and replay two graphs over the same kind of buffers
+    if which == "cl15k":
+        g = inputs.workload_graph("cl15k_wc")
+        rp, c, w, T = g.row_ptr, g.col, g.w, 30000
+    else:
+        g = inputs.chung_lu_graph(30000, 300000, 2.1, 77, "wc", cache=False)
+        rp, c, w, T = g.row_ptr, g.col, np.minimum(g.w * 2.5, 1.0).astype(np.float32), 2000
+    _say("captured form", which, chunk)
+    ora = oracle.build_sketch(rp, c, w, seed=13, j0=0, j1=T, nthreads=8)
+    pers = skis.build_sketch(rp, c, w, T, 13)
+    for rep in range(2):
+        cap = skis.build_sketch(rp, c, w, T, 13, form=2, chunk_samples=chunk)
+        inf = cap.info()
+        _say("captured info", rep, inf)
+        eff = min(chunk or (1 << 22), T)
+        assert inf.graph_replays == (T + eff - 1) // eff
+        _assert_sketch_equal(cap, ora)
+        for x, y in zip(cap.export(), pers.export()):
+            assert torch.equal(x, y)
+        assert inf.deferred == pers.info().deferred
+        if which == "large":
+            assert inf.deferred_global > 0
+
+
 def test_tiny_and_degenerate_shapes(skis):
     cases = []
     # two-edge star, single edge, deterministic weights, multi-edges, empty rows
@@ -184,6 +212,7 @@ def test_tiny_and_degenerate_shapes(skis):
             sk = skis.build_sketch(rp, c, w, T, 3)
             _assert_sketch_equal(sk, ora)
             _assert_sketch_equal(skis.build_sketch(rp, c, w, T, 3, form=1), ora)
+            _assert_sketch_equal(skis.build_sketch(rp, c, w, T, 3, form=2, chunk_samples=3), ora)
 
 
 def test_staging_overflow_retry(skis):
@@ -191,6 +220,8 @@ def test_staging_overflow_retry(skis):
     T = 20000
     ora = oracle.build_sketch(g.row_ptr, g.col, g.w, seed=2, j0=0, j1=T, nthreads=8)
     sk = skis.build_sketch(g.row_ptr, g.col, g.w, T, 2, staging_entries=1000)
+    _assert_sketch_equal(sk, ora)
+    sk = skis.build_sketch(g.row_ptr, g.col, g.w, T, 2, staging_entries=1000, form=2, chunk_samples=3000)
     _assert_sketch_equal(sk, ora)
 
 
@@ -316,6 +347,14 @@ def test_full_size_windows(skis, name):
     assert sp[-1] == inf.entries and int(probed.sum()) == inf.probed_total
     sizes = np.diff(sp)
     assert sizes.min() >= 2
+    # the captured form (four replays of its chain) writes the same sketch
+    cap = skis.build_sketch(g.row_ptr, g.col, g.w, T, inputs.SAMPLE_SEED, form=2, chunk_samples=T // 4 + 1,
+                            build_inverse_index=0)
+    _say("captured info", cap.info())
+    assert cap.info().graph_replays == 4
+    for x, y in zip(cap.export(), (torch.from_numpy(a) for a in (sp, nodes, roots, probed))):
+        assert torch.equal(x.cpu(), y)
+    cap.free()
     # coverage of a few sets equals a brute-force count over the exported sketch
     sets = inputs.random_sets(g.n, 4, 30, seed=5)
     set_ptr, set_nodes = inputs.sets_to_csr(sets)
