@@ -59,9 +59,10 @@ typedef struct skis_options {
     uint32_t big_row;             /* in-degree above which the first tier hands a sample on */
     uint32_t build_inverse_index; /* 1 (default): build node->samples for estimate / greedy; 0: build only */
     uint32_t threads_per_block;   /* 64 (default: one wave per workgroup) or 256.  Supported
-                                     (threads, slots, visited): (64,4,256) default, (64,8,128),
-                                     (64,8,64), (64,16,128), (64,16,64), (256,32,128),
-                                     (256,16,256), (256,32,256), (256,8,512), (256,16,128) */
+                                     (threads, slots, visited): (64,16,128) default, (64,4,256),
+                                     (64,8,128), (64,8,64), (64,8,192), (64,8,256), (64,12,192),
+                                     (64,16,64), (256,32,128), (256,16,256), (256,32,256),
+                                     (256,8,512), (256,16,128) */
     uint64_t max_device_bytes;    /* 0 = unlimited; larger total allocation -> SKIS_ENOMEM */
     uint64_t staging_entries;     /* initial staging capacity in node entries (0 = auto) */
     uint64_t chunk_samples;       /* captured form: sample ids per graph replay (0 = 2^22) */

@@ -93,8 +93,8 @@ void skis_default_options(skis_options *opt)
     if (!opt) return;
     std::memset(opt, 0, sizeof(*opt));
     opt->form = 0;
-    opt->slots_per_block = 4;
-    opt->visited_threshold = 256;
+    opt->slots_per_block = 16;
+    opt->visited_threshold = 128;
     opt->threads_per_block = 64;
     opt->big_row = 16384;
     opt->build_inverse_index = 1;

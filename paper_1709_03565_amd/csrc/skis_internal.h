@@ -132,8 +132,8 @@ void preprocess(Arena &arena, int32_t n, int64_t m, const int32_t *row_ptr, cons
 struct SampleConfig {
     uint32_t form = 0;
     uint32_t threads = 64;
-    uint32_t slots = 4;
-    uint32_t visited = 256;
+    uint32_t slots = 16;
+    uint32_t visited = 128;
     uint32_t big_row = 16384;
     uint64_t staging_entries = 0;
     uint64_t chunk = 0; // captured form: samples per replay of the chain (0: 2^22)

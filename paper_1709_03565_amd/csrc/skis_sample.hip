@@ -118,11 +118,13 @@ struct SampleArgs {
     uint64_t words;
 };
 
-template <int BLOCK, int S, int HBITS, int ICAP, bool GLOBAL>
+// RCAP: nodes a slot holds before its sample moves on (the visited threshold); HCAP: size
+// of the slot's open-addressing hash, any size above RCAP (3/2 RCAP keeps the load factor
+// at most 2/3 while leaving LDS for more slots).
+template <int BLOCK, int S, int RCAP, int HCAP, int ICAP, bool GLOBAL>
 __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
 {
-    constexpr int HCAP = 1 << HBITS;
-    constexpr int RCAP = HCAP / 2;
+    static_assert(GLOBAL || HCAP > RCAP, "the hash must be larger than the node list");
     constexpr int HSZ = GLOBAL ? 1 : S * HCAP;
     constexpr int LSZ = GLOBAL ? 1 : S * RCAP;
     constexpr int IPT = (ICAP + BLOCK - 1) / BLOCK;
@@ -156,6 +158,12 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
     };
     auto bits_ptr = [&](int s) -> uint32_t * { return a.gbits + ((size_t)blockIdx.x * S + s) * a.words; };
 
+    // Home slot of node u in an HCAP-entry hash: multiplicative hashing, then the high
+    // half of the product with HCAP maps the 32-bit hash onto [0, HCAP).
+    auto hash_slot = [](int32_t u) -> uint32_t {
+        return (uint32_t)(((uint64_t)((uint32_t)u * 0x9E3779B1u) * (uint64_t)HCAP) >> 32);
+    };
+
     // Adds u to slot s's sample if it is not there yet.
     auto visit = [&](int s, int32_t u) {
         if constexpr (GLOBAL) {
@@ -167,7 +175,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
             }
         } else {
             int32_t *H = sh_hash + s * HCAP;
-            uint32_t h = ((uint32_t)u * 0x9E3779B1u) >> (32 - HBITS);
+            uint32_t h = hash_slot(u);
             for (int k = 0; k < HCAP; ++k) {
                 const int32_t old = atomicCAS(&H[h], -1, u);
                 if (old == -1) {
@@ -177,7 +185,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                     return;
                 }
                 if (old == u) return;
-                h = (h + 1) & (HCAP - 1);
+                h = h + 1 == (uint32_t)HCAP ? 0u : h + 1;
             }
             atomicOr(&s_flags[s], F_DEFER);
         }
@@ -292,8 +300,8 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                         int32_t *H = sh_hash + s * HCAP;
                         const int32_t keys[2] = {r.x, u};
                         for (int t = 0; t < 2; ++t) {
-                            uint32_t h = ((uint32_t)keys[t] * 0x9E3779B1u) >> (32 - HBITS);
-                            while (H[h] != -1) h = (h + 1) & (HCAP - 1);
+                            uint32_t h = hash_slot(keys[t]);
+                            while (H[h] != -1) h = h + 1 == (uint32_t)HCAP ? 0u : h + 1;
                             H[h] = keys[t];
                         }
                     }
@@ -446,11 +454,13 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
         block_sync<BLOCK>();
 
         // ---- B4: live-edge coins for every edge pair, visits ------------------------------
-        // Each lane takes PPL consecutive pairs: one search for the first pair's item, the
-        // next ones by stepping across item boundaries; all loads are issued before the
-        // coins are drawn.
+        // Each lane takes ppl consecutive pairs (ppl = the fewest, up to PPL, that cover the
+        // pass in one sweep; uniform over the workgroup): one search for the first pair's
+        // item, the next ones by stepping across item boundaries; all loads are issued
+        // before the coins are drawn.
         const int total = it_pb[nitems];
-        for (int base = tid * PPL; base < total; base += BLOCK * PPL) {
+        const int ppl = total >= BLOCK * PPL ? PPL : (total + BLOCK - 1) / BLOCK;
+        for (int base = tid * ppl; base < total; base += BLOCK * ppl) {
             int lo = 0, hi = nitems - 1; // last item whose first pair index is <= base
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
@@ -462,7 +472,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
             for (int g = 0; g < PPL; ++g) {
                 const int idx = base + g;
                 ps[g] = -1;
-                if (idx >= total) continue;
+                if (g >= ppl || idx >= total) continue;
                 while (it_pb[lo + 1] <= idx) ++lo; // it_pb[nitems] = total > idx
                 const int sl = it_slot[lo];
                 if (!GLOBAL && (s_flags[sl] & F_DEFER)) continue;
@@ -479,6 +489,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
             }
 #pragma unroll
             for (int g = 0; g < PPL; ++g) {
+                if (g >= ppl) break;
                 if (ps[g] < 0) continue;
                 const int sl = ps[g];
                 const uint64_t j = a.j0 + s_idx[sl];
@@ -692,25 +703,31 @@ struct Variant {
 // With 64 threads a workgroup is one wave that owns its slots and LDS and never waits for
 // another wave; with 256 threads four waves share the slots and meet at barriers.
 static const Variant kTier0[] = {
-    {64, 8, 128, k_sample<64, 8, 8, 256, false>},
-    {64, 8, 64, k_sample<64, 8, 7, 256, false>},
-    {64, 16, 128, k_sample<64, 16, 8, 512, false>},
-    {64, 4, 256, k_sample<64, 4, 9, 256, false>},
-    {64, 16, 64, k_sample<64, 16, 7, 512, false>},
-    {256, 32, 128, k_sample<256, 32, 8, 1024, false>},
-    {256, 16, 256, k_sample<256, 16, 9, 1024, false>},
-    {256, 32, 256, k_sample<256, 32, 9, 1024, false>},
-    {256, 8, 512, k_sample<256, 8, 10, 1024, false>},
-    {256, 16, 128, k_sample<256, 16, 8, 1024, false>},
+    {64, 4, 256, k_sample<64, 4, 256, 384, 256, false>},
+    {64, 8, 128, k_sample<64, 8, 128, 192, 256, false>},
+    {64, 8, 64, k_sample<64, 8, 64, 96, 256, false>},
+    {64, 8, 192, k_sample<64, 8, 192, 288, 256, false>},
+    {64, 8, 256, k_sample<64, 8, 256, 384, 256, false>},
+    {64, 12, 192, k_sample<64, 12, 192, 288, 384, false>},
+    {64, 16, 128, k_sample<64, 16, 128, 192, 512, false>},
+    {64, 16, 64, k_sample<64, 16, 64, 96, 512, false>},
+    {256, 32, 128, k_sample<256, 32, 128, 192, 1024, false>},
+    {256, 16, 256, k_sample<256, 16, 256, 384, 1024, false>},
+    {256, 32, 256, k_sample<256, 32, 256, 384, 1024, false>},
+    {256, 8, 512, k_sample<256, 8, 512, 768, 1024, false>},
+    {256, 16, 128, k_sample<256, 16, 128, 192, 1024, false>},
 };
 // second tier: samples that outgrew the first, slots of 1024 nodes in LDS
 static const Variant kTierMidV[] = {
-    {64, 2, 1024, k_sample<64, 2, 11, 256, false>},
-    {256, 8, 1024, k_sample<256, 8, 11, 1024, false>},
+    {64, 2, 1024, k_sample<64, 2, 1024, 1536, 256, false>},
+    {256, 8, 1024, k_sample<256, 8, 1024, 1536, 1024, false>},
 };
-// last tier: a bitmap of n bits and a node list of n entries per slot in HBM
-constexpr int TIERG_SLOTS = 4;
-static SampleKernel const kTierGlobal = k_sample<256, TIERG_SLOTS, 1, 1024, true>;
+// One sample per workgroup: the samples that reach this tier are few and large, so the
+// chip is filled with workgroups rather than slots; the HBM buffers of all slots are kept
+// within TIERG_BUDGET bytes.
+constexpr int TIERG_SLOTS = 1;
+constexpr uint64_t TIERG_BUDGET = 8ull << 30;
+static SampleKernel const kTierGlobal = k_sample<256, TIERG_SLOTS, 1, 1, 1024, true>;
 
 static const Variant &pick_variant(const Variant *vs, size_t nv, uint32_t threads, uint32_t slots, uint32_t visited)
 {
@@ -792,10 +809,9 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
     const int nb0 = occupancy_blocks(v0.fn, (int)v0.threads) * cus;
     const int nbm = occupancy_blocks(vm.fn, (int)vm.threads) * cus;
     const uint64_t words = ((uint64_t)n + 31) / 32;
-    // global tier: every slot holds a bitmap of n bits and a node list of n entries; keep
-    // all slots within about 4 GiB
+    // global tier: every slot holds a bitmap of n bits and a node list of n entries
     const uint64_t slot_bytes = (uint64_t)n * 4ull + words * 4ull;
-    uint64_t nbg_mem = (4ull << 30) / (slot_bytes * TIERG_SLOTS);
+    uint64_t nbg_mem = TIERG_BUDGET / (slot_bytes * TIERG_SLOTS);
     if (nbg_mem < 1) nbg_mem = 1;
     const int nbg = (int)std::min<uint64_t>((uint64_t)2 * cus, nbg_mem);
     DevBuf<uint32_t> deferred2;
@@ -814,15 +830,14 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
     // tiers, each reading its work count from device memory -- is captured once into a HIP
     // graph on a private stream and replayed ceil(T / chunk) times on s with no host
     // round trip in between.  The HBM tier cannot be skipped on the host's word here, so
-    // its buffers are always allocated (at most about 1 GiB; each slot clears its own bits
-    // when its sample finishes, so they stay zero across replays).
+    // its buffers are always allocated (each slot clears its own bits when its sample
+    // finishes, so they stay zero across replays).
     auto sample_chain_graph = [&]() {
         const uint64_t chunk = std::min<uint64_t>(count, cfg.chunk ? cfg.chunk : (1ull << 22));
         const uint64_t replays = (count + chunk - 1) / chunk;
         DevBuf<ChainCtl> gc;
         gc.alloc(arena, 1);
-        const uint64_t nbg_g = std::max<uint64_t>(
-            1, std::min<uint64_t>((uint64_t)nbg, (1ull << 30) / (slot_bytes * TIERG_SLOTS)));
+        const uint64_t nbg_g = (uint64_t)nbg;
         const uint64_t gslots = nbg_g * TIERG_SLOTS;
         DevBuf<uint32_t> gbits;
         DevBuf<int32_t> glist;

@@ -52,7 +52,7 @@ def test_library_targets_gfx950(libpath):
 def test_default_options_and_errors_without_gpu(libpath):
     from paper_1709_03565_amd import skis
     o = skis.default_options()
-    assert o.slots_per_block == 4 and o.visited_threshold == 256 and o.threads_per_block == 64
+    assert o.slots_per_block == 16 and o.visited_threshold == 128 and o.threads_per_block == 64
     assert o.build_inverse_index == 1
     L = skis.lib()
     h = ctypes.c_void_p()
