@@ -76,6 +76,88 @@ def cpu_baseline(g, wl, sets, k, T):
     }
 
 
+def serve(args):
+    """Open-loop serving over the resident 4M-node TRI sketch (2^25 samples): Poisson
+    arrivals, Zipf(1.5) set sizes in 1..1000, latency from scheduled arrival to the result
+    in host memory; the first second is warm-up."""
+    import numpy as np
+    import torch
+
+    from paper_1709_03565_amd import inputs, skis
+    name = "cl4m_tri" if args.workload == "cl1m_wc" else args.workload
+    wl = inputs.WORKLOADS[name]
+    T = args.samples or wl["T"]
+    g = inputs.workload_graph(name)
+    log("serve: graph %s n=%d m=%d, T=%d" % (name, g.n, g.m, T))
+    torch.cuda.set_device(0)
+    rp, col, w = (torch.from_numpy(x).cuda() for x in (g.row_ptr, g.col, g.w))
+    sk = skis.build_sketch(rp, col, w, T, inputs.SAMPLE_SEED)
+    inf = sk.info()
+    warm_s = 1.0
+    nq = int(round(args.rate * (warm_s + args.duration)))
+    set_ptr, set_nodes, arrival = inputs.serving_trace(g.n, nq, args.rate, seed=11)
+    log("serve: %d queries over %.1f s, mean |S| %.2f" % (nq, arrival[-1] / 1e6, set_ptr[-1] / nq))
+    srv = skis.Server(sk)
+    t = time.perf_counter()
+    cov, est, lat = srv.replay(set_ptr, set_nodes, arrival)
+    wall = time.perf_counter() - t
+    st = srv.stats()
+    srv.close()
+    meas = arrival >= warm_s * 1e6
+    lm = lat[meas]
+    t_first = arrival[meas][0]
+    t_last_done = np.max(arrival[meas] + lm)
+    achieved = meas.sum() / ((t_last_done - t_first) * 1e-6)
+    # alone vs mix: the same sets estimated in one plain batch call
+    acov, aest = sk.estimate(torch.from_numpy(set_ptr).cuda(), torch.from_numpy(set_nodes).cuda())
+    acov = acov.cpu().numpy().astype(np.uint64)
+    aest = aest.cpu().numpy()
+    same = bool(np.array_equal(acov, cov) and np.array_equal(aest, est))
+    # work per query: entries of H(v) walked, sum of deg_H over the set
+    node_ptr = sk.inverse()[0].cpu().numpy()
+    degH = np.diff(node_ptr)
+    work = np.add.reduceat(degH[set_nodes], set_ptr[:-1]) if len(set_nodes) else np.zeros(nq, np.int64)
+    wm = work[meas]
+    heavy = wm >= np.percentile(wm, 99)
+    line = {
+        "metric": "SKIS serving latency p99",
+        "value": float(np.percentile(lm, 99)),
+        "unit": "us",
+        "n_gpus": 1,
+        "higher_is_better": False,
+        "vs_baseline": None,
+        "dtype": "u64/f64",
+        "data": "synthetic",
+        "config": {"workload": "%s: n=%d m=%d, resident sketch of T=%d samples; open-loop Poisson %.0f q/s, "
+                               "Zipf(1.5) set sizes in 1..1000, members uniform; %.0f s warm-up + %.0f s measured"
+                               % (name, g.n, g.m, T, args.rate, warm_s, args.duration)},
+        "p50_us": float(np.percentile(lm, 50)),
+        "p90_us": float(np.percentile(lm, 90)),
+        "p99_us": float(np.percentile(lm, 99)),
+        "p999_us": float(np.percentile(lm, 99.9)),
+        "max_us": float(lm.max()),
+        "offered_qps": args.rate,
+        "achieved_qps": float(achieved),
+        "queries_measured": int(meas.sum()),
+        "replay_wall_s": wall,
+        "batches": st["batches"],
+        "mean_batch": st["queries"] / max(st["batches"], 1),
+        "max_batch": st["max_batch"],
+        "batch_hist_pow2": st["batch_hist"],
+        "server_device_bytes": st["device_bytes"],
+        "sketch_entries": inf.entries,
+        "alone_vs_mix_identical": same,
+        "work_entries_p50": float(np.percentile(wm, 50)),
+        "work_entries_p99": float(np.percentile(wm, 99)),
+        "work_entries_max": int(wm.max()),
+        "p50_us_heaviest_1pct": float(np.percentile(lm[heavy], 50)),
+        "p99_us_rest": float(np.percentile(lm[~heavy], 99)),
+    }
+    log("serve: p50 %.1f us p99 %.1f us achieved %.0f q/s, %d batches (mean %.2f), identical alone/mix: %s" %
+        (line["p50_us"], line["p99_us"], achieved, st["batches"], line["mean_batch"], same))
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +175,10 @@ def main():
     ap.add_argument("--no-plain-compare", action="store_true",
                     help="skip the untimed plain-form build that is reported beside the persistent sampler")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve", action="store_true",
+                    help="serving benchmark instead: open-loop Poisson query stream against a resident sketch")
+    ap.add_argument("--rate", type=float, default=50000.0, help="--serve: offered queries per second")
+    ap.add_argument("--duration", type=float, default=10.0, help="--serve: measured seconds (after 1 s warm-up)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (for scaling HBM byte counters) and exit")
     args = ap.parse_args()
@@ -118,6 +204,10 @@ def main():
     import torch
 
     from paper_1709_03565_amd import inputs, skis
+
+    if args.serve:
+        serve(args)
+        return
 
     wl = inputs.WORKLOADS[args.workload]
     T = args.samples or wl["T"]

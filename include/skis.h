@@ -174,6 +174,73 @@ void skis_sketch_free(skis_sketch *sk);
 /* Message for the last failing call on this thread ("" if none). */
 const char *skis_last_error(void);
 
+/*
+ * Estimate service over a resident sketch: Alg. 2 answers any seed set from the one
+ * sketch (Eq. eq21), so a stream of influence queries is served without touching the
+ * graph.  One worker thread per server batches waiting queries continuously: whenever one
+ * of pipeline_depth batch slots is free, every waiting query it admits (by count, by total
+ * entries, and by sets above 4096 entries) is packed into pinned host memory and sent
+ * through copy-in, the estimate kernels and copy-out on the slot's own HIP stream, while
+ * the next batch is being formed.  Results are identical to skis_estimate's for the same
+ * set, alone or in any mix: every set has its own workgroup, bitmap and summation order.
+ * The sketch must outlive the server; the server does not lock it, and other calls on
+ * the sketch (estimate, greedy, export) may run at the same time.  Memory: each slot holds
+ * max_batch_queries bitmaps of T bits and max_large_sets bitmaps of n bits on the device.
+ */
+typedef struct skis_server skis_server;
+
+typedef struct skis_server_options {
+    uint32_t pipeline_depth;    /* batches in flight (default 4, one per hardware queue; at most 16) */
+    uint32_t max_batch_queries; /* queries per batch (default 256) */
+    uint32_t max_batch_entries; /* seed-set entries per batch; also the largest set accepted (default 2^20) */
+    uint32_t max_large_sets;    /* sets above 4096 entries per batch (default 4) */
+    uint64_t max_device_bytes;  /* 0 = unlimited; larger total allocation -> SKIS_ENOMEM */
+} skis_server_options;
+
+typedef struct skis_server_stats {
+    uint64_t batches;           /* batches completed */
+    uint64_t queries;           /* queries completed */
+    uint64_t max_batch;         /* largest batch */
+    uint64_t device_bytes;      /* device memory the server holds */
+    uint64_t batch_hist[16];    /* batches by size: bucket b counts sizes in [2^b, 2^(b+1)) (b = 15: >= 2^15) */
+} skis_server_stats;
+
+/* Fills *opt with the defaults. */
+void skis_server_default_options(skis_server_options *opt);
+
+/* Starts a server on the current device over sk (built with the inverse index).
+ * Errors: SKIS_EINVAL (NULL arguments, no inverse index, depth > 16), SKIS_ENOMEM. */
+int skis_server_create(const skis_sketch *sk, const skis_server_options *opt /* host, may be NULL */,
+                       skis_server **out /* host */);
+
+/* Queues one seed set (host array of count node ids, copied before the call returns) and
+ * returns its ticket.  Thread-safe.  Errors: SKIS_EINVAL (an id outside [0, n), count < 0
+ * or above max_batch_entries), SKIS_EHIP if the worker has stopped on a device error. */
+int skis_server_submit(skis_server *sv, const int32_t *nodes /* host */, int32_t count,
+                       uint64_t *ticket /* host */);
+
+/* Blocks until the ticket's result is in host memory; returns Cov and I_hat as
+ * skis_estimate would, and the time from submission to completion in microseconds.  A
+ * ticket can be waited for once.  Thread-safe. */
+int skis_server_wait(skis_server *sv, uint64_t ticket, uint64_t *cov /* host */, double *est /* host */,
+                     double *latency_us /* host */);
+
+/* Open-loop replay of a query trace (all host arrays): query i (set_nodes[set_ptr[i] ..
+ * set_ptr[i+1])) is submitted at arrival_us[i] microseconds after the call starts
+ * (nondecreasing), whatever is still in flight; then every result is collected.
+ * latency_us[i] runs from the scheduled arrival to the result in host memory, so a
+ * submitter that falls behind is charged to the latency.  Output pointers may be NULL. */
+int skis_server_replay(skis_server *sv, int32_t num_queries, const int64_t *set_ptr /* [Q+1] */,
+                       const int32_t *set_nodes, const double *arrival_us /* [Q] */, uint64_t *cov /* [Q] */,
+                       double *est /* [Q] */, double *latency_us /* [Q] */);
+
+/* Counters since creation. */
+int skis_server_get_stats(skis_server *sv, skis_server_stats *stats /* host */);
+
+/* Drains the queued queries, stops the worker and frees the server (NULL is a no-op).
+ * Results not yet waited for are dropped. */
+void skis_server_destroy(skis_server *sv);
+
 #ifdef __cplusplus
 }
 #endif

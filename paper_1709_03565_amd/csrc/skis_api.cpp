@@ -10,11 +10,6 @@
 #include "skis_internal.h"
 #include "skis_query.h"
 
-struct skis_sketch {
-    skis::Sketch core;
-    skis::QueryScratch qs;
-    std::mutex mu;
-};
 
 namespace skis {
 

@@ -1,5 +1,7 @@
 // skis_query.h -- declarations of the query kernels' host launchers.
 #pragma once
+#include <mutex>
+
 #include "skis_internal.h"
 
 namespace skis {
@@ -26,7 +28,25 @@ struct QueryScratch {
 
 void estimate_batch(const Sketch &sk, QueryScratch &qs, int32_t Q, const int64_t *set_ptr, const int32_t *set_nodes,
                     uint64_t *cov, double *est, hipStream_t s);
+// One launch pair for nq sets in CSR form on the device (set_ptr from 0): the sets of at
+// most EST_MAX_SET entries take a workgroup each; the nlarge sets listed in large[] (device
+// indexes into the CSR) take the chunked path with one node bitmap of n bits each in
+// nodebits.  bitmaps holds a zeroed bitmap of bitmap_words words for every workgroup
+// (max(nq, nlarge) of them) and is left zeroed.  Stream-ordered; no host synchronisation.
+void estimate_launch(const Sketch &sk, int32_t nq, const int64_t *set_ptr, const int32_t *set_nodes,
+                     const int64_t *large, int32_t nlarge, uint32_t *bitmaps, uint64_t bitmap_words,
+                     uint32_t *nodebits, unsigned long long *cov, double *est, int *err, hipStream_t s);
+// Zero-fills count words with a kernel (capturable, unlike a memset node).
+void fill_u32(uint32_t *p, uint64_t count, hipStream_t s);
 void greedy(const Sketch &sk, QueryScratch &qs, int32_t k, int32_t *seeds, uint64_t *marg, uint64_t *cov_out,
             double *est_out, hipStream_t s);
 
 } // namespace skis
+
+// The opaque handle of the C ABI: the sketch, its estimate scratch, and a lock that
+// serialises the calls that use that scratch.
+struct skis_sketch {
+    skis::Sketch core;
+    skis::QueryScratch qs;
+    std::mutex mu;
+};

@@ -480,6 +480,32 @@ void estimate_batch(const Sketch &sk, QueryScratch &qs, int32_t Q, const int64_t
     if (herr & 4) throw Error{SKIS_EINVAL, "a seed set holds a node id outside [0, n)"};
 }
 
+void estimate_launch(const Sketch &sk, int32_t nq, const int64_t *set_ptr, const int32_t *set_nodes,
+                     const int64_t *large, int32_t nlarge, uint32_t *bitmaps, uint64_t bitmap_words,
+                     uint32_t *nodebits, unsigned long long *cov, double *est, int *err, hipStream_t s)
+{
+    const uint64_t per = bitmap_words;
+    if (nq > 0) {
+        hipLaunchKernelGGL(k_estimate<false>, dim3((unsigned)nq), dim3(EST_BLOCK), 0, s, (const int64_t *)nullptr,
+                           (int64_t)0, set_ptr, set_nodes, sk.n, sk.T, sk.Gamma, sk.q.ptr, sk.node_ptr.ptr,
+                           sk.node_samples.ptr, bitmaps, per, (uint32_t *)nullptr, (uint64_t)0, cov, est, err);
+        SKIS_HIP_TRY(hipGetLastError());
+    }
+    if (nlarge > 0) {
+        const uint64_t wordsN = ((uint64_t)sk.n + 31) / 32;
+        hipLaunchKernelGGL(k_estimate<true>, dim3((unsigned)nlarge), dim3(EST_BLOCK), 0, s, large, (int64_t)0,
+                           set_ptr, set_nodes, sk.n, sk.T, sk.Gamma, sk.q.ptr, sk.node_ptr.ptr, sk.node_samples.ptr,
+                           bitmaps, per, nodebits, wordsN, cov, est, err);
+        SKIS_HIP_TRY(hipGetLastError());
+    }
+}
+
+void fill_u32(uint32_t *p, uint64_t count, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill_q<uint32_t>, dim3(gridq(count, 256)), dim3(256), 0, s, count, p, 0u);
+    SKIS_HIP_TRY(hipGetLastError());
+}
+
 void greedy(const Sketch &sk, QueryScratch &qs, int32_t k, int32_t *seeds, uint64_t *marg, uint64_t *cov_out,
             double *est_out, hipStream_t s)
 {

@@ -171,6 +171,24 @@ def zipf_sizes(count: int, a: float, lo: int, hi: int, rng) -> np.ndarray:
     return rng.choice(k.astype(np.int64), size=count, p=p)
 
 
+def serving_trace(n: int, num_queries: int, rate_per_s: float, seed: int = 11, zipf_a: float = 1.5,
+                  max_size: int = 1000):
+    """An open-loop query stream: arrival gaps exponential with mean 1/rate (a Poisson
+    process), set sizes from a Zipf law of exponent zipf_a truncated to {1..max_size},
+    members uniform over the n nodes without replacement.  Returns (set_ptr int64[Q+1],
+    set_nodes int32, arrival_us float64[Q])."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    gaps = rng.exponential(1e6 / rate_per_s, size=num_queries)
+    arrival = np.cumsum(gaps) - gaps[0]
+    sizes = zipf_sizes(num_queries, zipf_a, 1, max_size, rng)
+    set_ptr = np.zeros(num_queries + 1, np.int64)
+    np.cumsum(sizes, out=set_ptr[1:])
+    nodes = np.empty(int(set_ptr[-1]), np.int32)
+    for i, k in enumerate(sizes):
+        nodes[set_ptr[i]:set_ptr[i + 1]] = rng.choice(n, size=int(k), replace=False)
+    return set_ptr, nodes, arrival
+
+
 def random_tiny_graph(rng, n: int, m: int, wset=None):
     """A random graph on n nodes with m distinct non-loop edges (for exact tests)."""
     pairs = [(u, v) for u in range(n) for v in range(n) if u != v]

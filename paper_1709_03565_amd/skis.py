@@ -10,6 +10,8 @@ import ctypes
 import os
 from dataclasses import dataclass
 
+import numpy as np
+
 import torch
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
@@ -19,7 +21,9 @@ SKIS_OK, SKIS_WDEGENERATE, SKIS_EINVAL, SKIS_ENOMEM, SKIS_EHIP = 0, 1, -1, -2, -
 
 EXPORTED = ("skis_default_options", "skis_preprocess", "skis_build_sketch", "skis_sketch_info",
             "skis_estimate", "skis_greedy_max_cover", "skis_sketch_export", "skis_inverse_export",
-            "skis_node_q", "skis_sketch_free", "skis_last_error")
+            "skis_node_q", "skis_sketch_free", "skis_last_error", "skis_server_default_options",
+            "skis_server_create", "skis_server_submit", "skis_server_wait", "skis_server_replay",
+            "skis_server_get_stats", "skis_server_destroy")
 
 
 class SkisError(RuntimeError):
@@ -34,6 +38,17 @@ class Options(ctypes.Structure):
                 ("build_inverse_index", ctypes.c_uint32), ("threads_per_block", ctypes.c_uint32),
                 ("max_device_bytes", ctypes.c_uint64), ("staging_entries", ctypes.c_uint64),
                 ("chunk_samples", ctypes.c_uint64)]
+
+
+class ServerOptions(ctypes.Structure):
+    _fields_ = [("pipeline_depth", ctypes.c_uint32), ("max_batch_queries", ctypes.c_uint32),
+                ("max_batch_entries", ctypes.c_uint32), ("max_large_sets", ctypes.c_uint32),
+                ("max_device_bytes", ctypes.c_uint64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("batches", ctypes.c_uint64), ("queries", ctypes.c_uint64), ("max_batch", ctypes.c_uint64),
+                ("device_bytes", ctypes.c_uint64), ("batch_hist", ctypes.c_uint64 * 16)]
 
 
 class Info(ctypes.Structure):
@@ -82,6 +97,21 @@ def lib():
         L.skis_sketch_free.restype = None
         L.skis_last_error.argtypes = []
         L.skis_last_error.restype = ctypes.c_char_p
+        L.skis_server_default_options.argtypes = [ctypes.POINTER(ServerOptions)]
+        L.skis_server_default_options.restype = None
+        L.skis_server_create.argtypes = [P, ctypes.POINTER(ServerOptions), ctypes.POINTER(P)]
+        L.skis_server_create.restype = ctypes.c_int
+        L.skis_server_submit.argtypes = [P, P, i32, ctypes.POINTER(u64)]
+        L.skis_server_submit.restype = ctypes.c_int
+        L.skis_server_wait.argtypes = [P, u64, ctypes.POINTER(u64), ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_double)]
+        L.skis_server_wait.restype = ctypes.c_int
+        L.skis_server_replay.argtypes = [P, i32, P, P, P, P, P, P]
+        L.skis_server_replay.restype = ctypes.c_int
+        L.skis_server_get_stats.argtypes = [P, ctypes.POINTER(ServerStats)]
+        L.skis_server_get_stats.restype = ctypes.c_int
+        L.skis_server_destroy.argtypes = [P]
+        L.skis_server_destroy.restype = None
         _lib = L
     return _lib
 
@@ -232,3 +262,65 @@ def build_sketch(row_ptr, col, w, num_samples: int, seed: int, options: Options 
     st = _check(lib().skis_build_sketch(n, m, _ptr(row_ptr), _ptr(col), _ptr(w), num_samples, seed,
                                         ctypes.byref(opt), _stream(), ctypes.byref(h)))
     return Sketch(h, st)
+
+
+class Server:
+    """Continuous-batching estimate service over a resident sketch (skis_server_*).
+
+    Host-side API: sets are numpy int32 arrays of node ids; results come back in host memory.
+    The sketch must stay alive while the server runs."""
+
+    def __init__(self, sketch: Sketch, **kw):
+        o = ServerOptions()
+        lib().skis_server_default_options(ctypes.byref(o))
+        for k, v in kw.items():
+            if not hasattr(o, k):
+                raise KeyError(k)
+            setattr(o, k, v)
+        h = ctypes.c_void_p()
+        _check(lib().skis_server_create(sketch._h, ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self._sketch = sketch
+
+    def submit(self, nodes) -> int:
+        a = np.ascontiguousarray(nodes, dtype=np.int32)
+        t = ctypes.c_uint64()
+        _check(lib().skis_server_submit(self._h, a.ctypes.data_as(ctypes.c_void_p), a.size, ctypes.byref(t)))
+        return t.value
+
+    def wait(self, ticket: int):
+        """(cov, est, latency_us) of a submitted set."""
+        c, e, l = ctypes.c_uint64(), ctypes.c_double(), ctypes.c_double()
+        _check(lib().skis_server_wait(self._h, ticket, ctypes.byref(c), ctypes.byref(e), ctypes.byref(l)))
+        return c.value, e.value, l.value
+
+    def replay(self, set_ptr, set_nodes, arrival_us):
+        """Open-loop replay: (cov uint64[Q], est float64[Q], latency_us float64[Q]) numpy arrays."""
+        sp = np.ascontiguousarray(set_ptr, dtype=np.int64)
+        sn = np.ascontiguousarray(set_nodes, dtype=np.int32)
+        at = np.ascontiguousarray(arrival_us, dtype=np.float64)
+        Q = sp.size - 1
+        cov = np.zeros(max(Q, 1), np.uint64)
+        est = np.zeros(max(Q, 1), np.float64)
+        lat = np.zeros(max(Q, 1), np.float64)
+        vp = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        _check(lib().skis_server_replay(self._h, Q, vp(sp), vp(sn) if sn.size else None, vp(at), vp(cov), vp(est),
+                                        vp(lat)))
+        return cov[:Q], est[:Q], lat[:Q]
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib().skis_server_get_stats(self._h, ctypes.byref(st)))
+        return {"batches": st.batches, "queries": st.queries, "max_batch": st.max_batch,
+                "device_bytes": st.device_bytes, "batch_hist": list(st.batch_hist)}
+
+    def close(self):
+        if self._h:
+            lib().skis_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,136 @@
+"""The estimate service (skis_server_*) through the C ABI: every result equals the oracle's
+estimate of Eq. (eq21) for the same set (Cov exact, I_hat within 1e-12 relative) and is
+bit-identical to skis_estimate of the set alone, whatever batch it was served in."""
+import sys
+import threading
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1709_03565_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-12
+
+
+def _say(*a):
+    print("[gpu-serve]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def skis():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1709_03565_amd import skis as s
+    s.lib()
+    return s
+
+
+@pytest.fixture(scope="module")
+def sketch(skis):
+    g = inputs.workload_graph("cl15k_wc")
+    T = 100000
+    _say("build cl15k T=%d" % T)
+    sk = skis.build_sketch(g.row_ptr, g.col, g.w, T, 1)
+    ora = oracle.build_sketch(g.row_ptr, g.col, g.w, seed=1, j0=0, j1=T, nthreads=8)
+    _, q = oracle.row_prefix(g.row_ptr, g.w)
+    return g, sk, ora, q
+
+
+def _alone(sk, set_ptr, set_nodes):
+    cov, est = sk.estimate(set_ptr, set_nodes)
+    return cov.cpu().numpy().astype(np.uint64), est.cpu().numpy()
+
+
+def test_server_matches_oracle_and_estimate(skis, sketch):
+    g, sk, ora, q = sketch
+    sets = inputs.random_sets(g.n, 60, 50, seed=7)
+    rng = np.random.Generator(np.random.PCG64(3))
+    sets += [np.array([], np.int32), np.array([5, 5, 5, 17], np.int32), np.arange(g.n, dtype=np.int32),
+             rng.choice(g.n, 5000, replace=False).astype(np.int32), np.array([g.n - 1], np.int32)]
+    set_ptr, set_nodes = inputs.sets_to_csr(sets)
+    srv = skis.Server(sk, pipeline_depth=2, max_batch_queries=16)
+    tickets = [srv.submit(s) for s in sets]
+    got = [srv.wait(t) for t in tickets]
+    st = srv.stats()
+    _say("stats", st)
+    srv.close()
+    cov = np.array([x[0] for x in got], np.uint64)
+    est = np.array([x[1] for x in got])
+    ocov, oest = oracle.estimate(g.n, ora.sample_ptr, ora.nodes, q, ora.Gamma, set_ptr=set_ptr, set_nodes=set_nodes)
+    assert np.array_equal(cov, ocov)
+    assert np.all(np.abs(est - oest) <= REL * np.maximum(np.abs(oest), 1e-300))
+    acov, aest = _alone(sk, set_ptr, set_nodes)
+    assert np.array_equal(cov, acov) and np.array_equal(est, aest)
+    assert st["queries"] == len(sets) and sum(st["batch_hist"]) == st["batches"]
+    assert all(x[2] > 0 for x in got)
+
+
+def test_replay_mix_equals_alone(skis, sketch):
+    # an open-loop stream fast enough that batches form: each result must not depend on
+    # the batch it ran in
+    g, sk, ora, q = sketch
+    set_ptr, set_nodes, arrival = inputs.serving_trace(g.n, 4000, 200000.0, seed=11, max_size=300)
+    srv = skis.Server(sk)
+    cov, est, lat = srv.replay(set_ptr, set_nodes, arrival)
+    st = srv.stats()
+    srv.close()
+    _say("replay stats", st, "p50 %.1f us p99 %.1f us" % (np.percentile(lat, 50), np.percentile(lat, 99)))
+    assert st["queries"] == 4000 and st["batches"] < 4000 and st["max_batch"] > 1
+    acov, aest = _alone(sk, set_ptr, set_nodes)
+    assert np.array_equal(cov, acov) and np.array_equal(est, aest)
+    # and the oracle agrees on a sample of them
+    idx = np.arange(0, 4000, 37)
+    sub = [set_nodes[set_ptr[i]:set_ptr[i + 1]] for i in idx]
+    sp2, sn2 = inputs.sets_to_csr(sub)
+    ocov, oest = oracle.estimate(g.n, ora.sample_ptr, ora.nodes, q, ora.Gamma, set_ptr=sp2, set_nodes=sn2)
+    assert np.array_equal(cov[idx], ocov)
+    assert np.all(np.abs(est[idx] - oest) <= REL * np.abs(oest))
+    assert np.all(lat > 0)
+
+
+def test_threads_submit_concurrently(skis, sketch):
+    g, sk, ora, q = sketch
+    sets = inputs.random_sets(g.n, 400, 40, seed=21)
+    srv = skis.Server(sk, pipeline_depth=4, max_batch_queries=32)
+    out = [None] * len(sets)
+
+    def worker(lo, hi):
+        ts = [(i, srv.submit(sets[i])) for i in range(lo, hi)]
+        for i, t in ts:
+            out[i] = srv.wait(t)
+
+    th = [threading.Thread(target=worker, args=(k * 100, (k + 1) * 100)) for k in range(4)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    srv.close()
+    set_ptr, set_nodes = inputs.sets_to_csr(sets)
+    acov, aest = _alone(sk, set_ptr, set_nodes)
+    assert np.array_equal(np.array([x[0] for x in out], np.uint64), acov)
+    assert np.array_equal(np.array([x[1] for x in out]), aest)
+
+
+def test_server_errors(skis, sketch):
+    g, sk, ora, q = sketch
+    srv = skis.Server(sk, max_batch_entries=100)
+    with pytest.raises(skis.SkisError) as ei:
+        srv.submit(np.array([g.n], np.int32))
+    assert ei.value.code == skis.SKIS_EINVAL
+    with pytest.raises(skis.SkisError):
+        srv.submit(np.arange(101, dtype=np.int32))  # larger than one batch
+    with pytest.raises(skis.SkisError):
+        srv.wait(12345)
+    t = srv.submit(np.array([1, 2], np.int32))
+    c, e, _ = srv.wait(t)
+    with pytest.raises(skis.SkisError):
+        srv.wait(t)  # a ticket is collected once
+    srv.close()
+    nb = skis.build_sketch(g.row_ptr, g.col, g.w, 1000, 1, build_inverse_index=0)
+    with pytest.raises(skis.SkisError):
+        skis.Server(nb)
