@@ -268,6 +268,36 @@ def test_estimate_parity_config_sets(cl15k):
     assert torch.equal(cov, cov2) and torch.equal(est, est2)
 
 
+def test_estimate_heavy_sets(cl15k):
+    # sets whose sample lists hold more than 32768 entries (hubs), 80 of them in one call
+    g, ora, sk = cl15k
+    node_ptr, _ = (_np(x) for x in sk.inverse())
+    deg = np.diff(node_ptr)
+    order = np.argsort(-deg, kind="stable").astype(np.int32)
+    rng = np.random.Generator(np.random.PCG64(31))
+    sets = [order[:k] for k in (1, 2, 3, 5, 10, 50, 300, 4096)]
+    for _ in range(80):
+        hub = np.concatenate([order[:2], order[rng.integers(2, 20, size=2)]])
+        sets.append(np.concatenate([hub, rng.choice(g.n, 30, replace=False).astype(np.int32)]))
+    heavy = sum(int(deg[np.unique(S)].sum()) > 32768 for S in sets)
+    _say("heavy sets", heavy, "top deg", int(deg[order[0]]))
+    assert heavy > 64
+    set_ptr, set_nodes = inputs.sets_to_csr(sets)
+    cov, est = sk.estimate(set_ptr, set_nodes)
+    _, q = oracle.row_prefix(g.row_ptr, g.w)
+    ocov, oest = oracle.estimate(g.n, ora.sample_ptr, ora.nodes, q, ora.Gamma, set_ptr=set_ptr, set_nodes=set_nodes)
+    assert np.array_equal(_np(cov).astype(np.uint64), ocov)
+    e = _np(est)
+    assert np.all(np.abs(e - oest) <= REL * np.abs(oest))
+    # the parked sets leave their bitmaps clear: a second call gives the same
+    cov2, est2 = sk.estimate(set_ptr, set_nodes)
+    assert torch.equal(cov, cov2) and torch.equal(est, est2)
+    # and each set alone gives the same bits as in the batch
+    for i in (0, 5, 7, 40):
+        c1, e1 = sk.estimate(np.array([0, len(sets[i])]), sets[i])
+        assert int(c1[0]) == int(cov[i]) and float(e1[0]) == float(est[i])
+
+
 def test_greedy_parity(cl15k):
     g, ora, sk = cl15k
     _, q = oracle.row_prefix(g.row_ptr, g.w)
