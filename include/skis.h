@@ -125,6 +125,10 @@ typedef struct skis_info {
     uint64_t deferred_global;    /* samples that reached the HBM tier */
     uint32_t plain_levels;       /* plain form: BFS level launches (0 for the persistent form) */
     uint32_t graph_replays;      /* captured form: replays of the captured chain (0 otherwise) */
+    uint64_t tier_samples[3];    /* samples finished by each sampler tier (LDS, LDS 1024, HBM); the
+                                    plain form counts everything in tier 0 */
+    uint64_t tier_entries[3];    /* sum of |R_j| over those samples */
+    uint64_t tier_probed[3];     /* edges probed for those samples */
 } skis_info;
 
 /* Sketch facts (host out-param). */

@@ -237,6 +237,11 @@ int skis_sketch_info(const skis_sketch *h, skis_info *info)
         info->deferred_global = sk.deferred_global;
         info->plain_levels = sk.plain_levels;
         info->graph_replays = sk.graph_replays;
+        for (int t = 0; t < 3; ++t) {
+            info->tier_samples[t] = sk.tier_stats[t][0];
+            info->tier_entries[t] = sk.tier_stats[t][1];
+            info->tier_probed[t] = sk.tier_stats[t][2];
+        }
         return SKIS_OK;
     });
 }

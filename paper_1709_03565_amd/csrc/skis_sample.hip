@@ -113,6 +113,7 @@ struct SampleArgs {
     uint32_t *medium;
     unsigned long long *n_medium;
     int *overflow;
+    unsigned long long *tier_stats; // [3]: samples finished by this launch, their entries, edges probed
     uint32_t *gbits;            // global tier: [slots][words]
     int32_t *glist;             // global tier: [slots][n]
     uint64_t words;
@@ -191,6 +192,8 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
         }
     };
 
+    // lane s of wave 0 counts what slot s finishes; summed once when the workgroup exits
+    unsigned long long st_fin = 0, st_ent = 0, st_prb = 0;
     if constexpr (!GLOBAL)
         for (int i = tid; i < HSZ; i += BLOCK) sh_hash[i] = -1;
     if (tid < S) {
@@ -234,6 +237,9 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                     a.out_size[i] = (uint32_t)cnt;
                     a.out_off[i] = off;
                     a.out_probed[i] = s_probed[s];
+                    st_fin += 1;
+                    st_ent += (unsigned long long)cnt;
+                    st_prb += s_probed[s];
                     if (cnt > SMALL_SORT) {
                         const unsigned long long k = atomicAdd(a.n_medium, 1ull);
                         a.medium[k] = i;
@@ -503,6 +509,16 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
         block_sync<BLOCK>();
         if (!s_alive) break;
     }
+    if (tid < 64 && a.tier_stats) {
+        st_fin = wave_sum(st_fin);
+        st_ent = wave_sum(st_ent);
+        st_prb = wave_sum(st_prb);
+        if (tid == 0 && st_fin) {
+            atomicAdd(a.tier_stats + 0, st_fin);
+            atomicAdd(a.tier_stats + 1, st_ent);
+            atomicAdd(a.tier_stats + 2, st_prb);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -690,6 +706,7 @@ struct Counters {
     unsigned long long n_medium;
     int overflow;
     int pad;
+    unsigned long long tier[3][3]; // per tier: samples finished, their entries, edges probed
 };
 
 typedef void (*SampleKernel)(SampleArgs);
@@ -895,6 +912,9 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
             A.words = words;
             need(A.staging, "staging");
             SampleArgs A0 = A, A1 = A, A2 = A;
+            A0.tier_stats = ctr.ptr->tier[0];
+            A1.tier_stats = ctr.ptr->tier[1];
+            A2.tier_stats = ctr.ptr->tier[2];
             A0.next = &gc.ptr->next0;
             A0.id_list = nullptr;
             A0.id_count_dev = &gc.ptr->count;
@@ -1023,6 +1043,7 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
         A.n_medium = &ctr.ptr->n_medium;
         A.overflow = &ctr.ptr->overflow;
         A.words = words;
+        A.tier_stats = ctr.ptr->tier[0];
         for (const void *p : {(const void *)A.row_ptr, (const void *)A.pairs, (const void *)A.rec, (const void *)A.u1,
                               (const void *)A.next, (const void *)A.staging, (const void *)A.stage_used,
                               (const void *)A.out_size, (const void *)A.out_off, (const void *)A.out_probed,
@@ -1046,6 +1067,7 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
             A.id_count = nd;
             A.deferred = deferred2.ptr;
             A.big_row = std::max<uint32_t>(cfg.big_row, 1u << 20);
+            A.tier_stats = ctr.ptr->tier[1];
             SKIS_HIP_TRY(hipEventRecord(ev[6], s));
             hipLaunchKernelGGL(vm.fn, dim3(nbm), dim3(vm.threads), 0, s, A);
             SKIS_HIP_TRY(hipGetLastError());
@@ -1070,6 +1092,7 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
             A.deferred = deferred.ptr; // unused: the global tier finishes every sample
             A.gbits = gbits.ptr;
             A.glist = glist.ptr;
+            A.tier_stats = ctr.ptr->tier[2];
             need(A.gbits, "gbits");
             need(A.glist, "glist");
             SKIS_HIP_TRY(hipEventRecord(ev[8], s));
@@ -1091,6 +1114,8 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
         if (attempt == 1) throw Error{SKIS_ENOMEM, "staging overflow after resize"};
     }
     SKIS_HIP_TRY(hipEventRecord(ev[2], s));
+    for (int t = 0; t < 3; ++t)
+        for (int k = 0; k < 3; ++k) sk.tier_stats[t][k] = hc.tier[t][k];
 
     // every sample must have finished in one of the tiers
     hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(1), dim3(64), 0, s, (uint64_t)1, &ctr.ptr->next, 0ull);
@@ -1133,6 +1158,11 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
     SKIS_HIP_TRY(hipEventRecord(ev[3], s));
     SKIS_HIP_TRY(hipStreamSynchronize(s));
     sk.probed_total = ptot;
+    if (cfg.form == 1) { // the plain form is one stage
+        sk.tier_stats[0][0] = count;
+        sk.tier_stats[0][1] = (uint64_t)total;
+        sk.tier_stats[0][2] = ptot;
+    }
     float ms = 0;
     SKIS_HIP_TRY(hipEventElapsedTime(&ms, ev[0], ev[1]));
     sk.ms_roots = ms;

@@ -60,7 +60,9 @@ class Info(ctypes.Structure):
                 ("ms_compact", ctypes.c_double), ("ms_inverse", ctypes.c_double),
                 ("ms_tier0", ctypes.c_double), ("ms_tier1", ctypes.c_double),
                 ("ms_tier2", ctypes.c_double), ("deferred_global", ctypes.c_uint64),
-                ("plain_levels", ctypes.c_uint32), ("graph_replays", ctypes.c_uint32)]
+                ("plain_levels", ctypes.c_uint32), ("graph_replays", ctypes.c_uint32),
+                ("tier_samples", ctypes.c_uint64 * 3), ("tier_entries", ctypes.c_uint64 * 3),
+                ("tier_probed", ctypes.c_uint64 * 3)]
 
 
 _lib = None
@@ -183,6 +185,9 @@ class SketchInfo:
     deferred_global: int
     plain_levels: int
     graph_replays: int
+    tier_samples: tuple = (0, 0, 0)
+    tier_entries: tuple = (0, 0, 0)
+    tier_probed: tuple = (0, 0, 0)
 
 
 class Sketch:
@@ -209,7 +214,8 @@ class Sketch:
         return SketchInfo(i.n, i.T, i.entries, i.probed_total, i.deferred, i.C, i.Gamma, i.device_bytes,
                           i.ms_preprocess, i.ms_roots, i.ms_sample, i.ms_compact, i.ms_inverse,
                           i.ms_tier0, i.ms_tier1, i.ms_tier2, i.deferred_global,
-                          i.plain_levels, i.graph_replays)
+                          i.plain_levels, i.graph_replays, tuple(i.tier_samples), tuple(i.tier_entries),
+                          tuple(i.tier_probed))
 
     def estimate(self, set_ptr, set_nodes):
         """(cov uint64[Q], est float64[Q]) device tensors for seed sets in CSR form."""

@@ -34,6 +34,12 @@ def _np(t):
     return t.cpu().numpy()
 
 
+def _assert_tiers_add_up(inf):
+    assert sum(inf.tier_samples) == inf.T
+    assert sum(inf.tier_entries) == inf.entries
+    assert sum(inf.tier_probed) == inf.probed_total
+
+
 def _assert_sketch_equal(sk_gpu, ora, j0=0):
     sp, nodes, roots, probed = (_np(x) for x in sk_gpu.export())
     T = ora.T
@@ -102,6 +108,7 @@ def test_sketch_bit_exact_cl15k(cl15k):
     assert inf.T == ora.T and inf.entries == len(ora.nodes)
     assert inf.probed_total == int(ora.probed.sum())
     assert inf.Gamma == ora.Gamma and inf.C == ora.C
+    _assert_tiers_add_up(inf)
     _assert_sketch_equal(sk, ora)
     assert np.array_equal(_np(sk.q()), oracle.row_prefix(g.row_ptr, g.w)[1])
 
@@ -120,6 +127,7 @@ def test_sketch_identical_across_sampler_shapes(skis, threads, slots, visited, b
     sk = skis.build_sketch(g.row_ptr, g.col, g.w, T, 11, threads_per_block=threads, slots_per_block=slots,
                            visited_threshold=visited, big_row=big_row)
     inf = sk.info()
+    _assert_tiers_add_up(inf)
     if big_row == 8:
         assert inf.deferred > T // 4
     _assert_sketch_equal(sk, ora)
@@ -144,6 +152,8 @@ def test_large_cascades_global_tier(skis, scale):
     inf = sk.info()
     _say("large cascades info", inf)
     assert inf.deferred > 0 and inf.deferred_global > 0  # samples above 1024 nodes reach the HBM tier
+    _assert_tiers_add_up(inf)
+    assert inf.tier_samples[2] == inf.deferred_global
     _assert_sketch_equal(sk, ora)
 
 
@@ -160,6 +170,7 @@ def test_plain_form_matches_oracle_and_persistent(skis, which):
     ora = oracle.build_sketch(rp, c, w, seed=13, j0=0, j1=T, nthreads=8)
     plain = skis.build_sketch(rp, c, w, T, 13, form=1)
     assert plain.info().plain_levels > 0
+    _assert_tiers_add_up(plain.info())
     _assert_sketch_equal(plain, ora)
     pers = skis.build_sketch(rp, c, w, T, 13)
     for x, y in zip(plain.export(), pers.export()):
@@ -186,6 +197,8 @@ def test_captured_form_matches_oracle_and_persistent(skis, which, chunk):
         _say("captured info", rep, inf)
         eff = min(chunk or (1 << 22), T)
         assert inf.graph_replays == (T + eff - 1) // eff
+        _assert_tiers_add_up(inf)
+        assert list(inf.tier_samples) == list(pers.info().tier_samples)
         _assert_sketch_equal(cap, ora)
         for x, y in zip(cap.export(), pers.export()):
             assert torch.equal(x, y)

@@ -72,3 +72,19 @@ def test_product_code_does_not_use_the_oracle():
                 text = open(os.path.join(dirpath, f), errors="ignore").read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "skis_oracle" not in text and "ora_" not in text, f
+
+
+def test_bench_kernel_names_match_the_library_table():
+    # bench.py names the first-tier kernel (for the roofline and the counter lookup) from
+    # its own copy of the (threads, slots, visited) -> (hash size, item capacity) table
+    import re
+    import bench
+    src = open(os.path.join(ROOT, "paper_1709_03565_amd", "csrc", "skis_sample.hip")).read()
+    table = src[src.index("kTier0[] = {"):src.index("};", src.index("kTier0[] = {"))]
+    rows = re.findall(r"\{(\d+), (\d+), (\d+), k_sample<(\d+), (\d+), (\d+), (\d+), (\d+), false>\}", table)
+    assert len(rows) >= 10
+    for r in rows:
+        th, sl, vi, th2, sl2, vi2, hcap, icap = map(int, r)
+        assert (th, sl, vi) == (th2, sl2, vi2)
+        name = bench.tier0_kernel_name(dict(threads_per_block=th, slots_per_block=sl, visited_threshold=vi))
+        assert name == "k_sample<%d, %d, %d, %d, %d, false>" % (th, sl, vi, hcap, icap)
