@@ -34,9 +34,9 @@ def algorithmic_bytes(T: int, entries: int, probed: int) -> int:
 
 
 # (threads, slots, visited) -> the LDS hash size the library compiles for that shape
-_HCAP = {(64, 4, 256): 384, (64, 8, 128): 192, (64, 8, 64): 96, (64, 8, 192): 288, (64, 8, 256): 384,
-         (64, 12, 192): 288, (64, 16, 128): 192, (64, 16, 64): 96, (256, 32, 128): 192, (256, 16, 256): 384,
-         (256, 32, 256): 384, (256, 8, 512): 768, (256, 16, 128): 192}
+_HCAP = {(64, 4, 256): 344, (64, 8, 128): 172, (64, 8, 64): 88, (64, 8, 192): 256, (64, 8, 256): 344,
+         (64, 12, 192): 256, (64, 12, 256): 344, (64, 16, 128): 172, (64, 16, 192): 256, (64, 16, 64): 88,
+         (256, 32, 128): 172, (256, 16, 256): 344, (256, 32, 256): 344, (256, 8, 512): 688, (256, 16, 128): 172}
 _ICAP = {64: {4: 256, 8: 256, 12: 384, 16: 512}, 256: {}}
 
 

@@ -61,8 +61,8 @@ typedef struct skis_options {
     uint32_t threads_per_block;   /* 64 (default: one wave per workgroup) or 256.  Supported
                                      (threads, slots, visited): (64,16,128) default, (64,4,256),
                                      (64,8,128), (64,8,64), (64,8,192), (64,8,256), (64,12,192),
-                                     (64,16,64), (256,32,128), (256,16,256), (256,32,256),
-                                     (256,8,512), (256,16,128) */
+                                     (64,12,256), (64,16,192), (64,16,64), (256,32,128),
+                                     (256,16,256), (256,32,256), (256,8,512), (256,16,128) */
     uint64_t max_device_bytes;    /* 0 = unlimited; larger total allocation -> SKIS_ENOMEM */
     uint64_t staging_entries;     /* initial staging capacity in node entries (0 = auto) */
     uint64_t chunk_samples;       /* captured form: sample ids per graph replay (0 = 2^22) */

@@ -28,8 +28,9 @@ import torch
 from . import skis
 
 # (threads_per_block, slots_per_block, visited_threshold) the library is compiled for
-SHAPES = [(64, 4, 256), (64, 8, 128), (64, 8, 64), (64, 8, 192), (64, 8, 256), (64, 12, 192), (64, 16, 128),
-          (64, 16, 64), (256, 32, 128), (256, 16, 256), (256, 32, 256), (256, 8, 512), (256, 16, 128)]
+SHAPES = [(64, 4, 256), (64, 8, 128), (64, 8, 64), (64, 8, 192), (64, 8, 256), (64, 12, 192), (64, 12, 256),
+          (64, 16, 128), (64, 16, 192), (64, 16, 64), (256, 32, 128), (256, 16, 256), (256, 32, 256), (256, 8, 512),
+          (256, 16, 128)]
 BIG_ROWS = [4096, 16384, 65536]
 
 _DEFAULT_CACHE = os.path.join(os.environ.get("SKIS_TUNE_CACHE", "/tmp"), "skis_autotune.json")

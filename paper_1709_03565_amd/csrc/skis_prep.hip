@@ -60,9 +60,11 @@ __global__ __launch_bounds__(256) void k_prep_rows(int32_t n, int64_t m, const i
     }
 }
 
-// One wave per long row: the lanes load and validate 64 edges at a time and stage the
-// factors (1 - w) in LDS; lane 0 extends the running product through them in row order
-// (the same sequence of roundings as one thread would do), then all lanes store P.
+// One wave per long row: the lanes load and validate 64 edges at a time, each holding its
+// factor (1 - w) in a register.  The running product is carried through the 64 factors in
+// row order by every lane at once (factor i read from lane i with readlane, one rounding per
+// product: the same sequence one thread would do), and lane i keeps the product that ends
+// at its edge, so the dependent chain is one fp64 multiply per edge.
 __global__ __launch_bounds__(256) void k_prep_long(int32_t n, const int32_t *__restrict__ row_ptr,
                                                    const int32_t *__restrict__ col, const float *__restrict__ w,
                                                    uint2 *__restrict__ edges, double *__restrict__ P,
@@ -70,41 +72,45 @@ __global__ __launch_bounds__(256) void k_prep_long(int32_t n, const int32_t *__r
                                                    const int32_t *__restrict__ long_rows,
                                                    const unsigned int *__restrict__ n_long)
 {
-    __shared__ double fac[4][64];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const unsigned int cnt = *n_long;
     for (unsigned int r = blockIdx.x * 4 + wid; r < cnt; r += gridDim.x * 4) {
         const int32_t v = long_rows[r];
         const int32_t a = row_ptr[v], b = row_ptr[v + 1];
-        double prod = 1.0; // meaningful in lane 0
+        double prod = 1.0; // the same in every lane
         int bad = 0;
         for (int32_t c0 = a; c0 < b; c0 += 64) {
             const int32_t e = c0 + lane;
+            double f = 1.0;
             if (e < b) {
                 const int32_t u = col[e];
                 float wf = w[e];
                 bad |= check_edge(u, wf, v, n);
                 if (wf == 0.0f) wf = 0.0f;
                 edges[e] = make_uint2((uint32_t)u, __float_as_uint(wf));
-                fac[wid][lane] = __dsub_rn(1.0, (double)wf);
+                f = __dsub_rn(1.0, (double)wf);
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const long long fb = __double_as_longlong(f);
+            const int flo = (int)(unsigned)fb, fhi = (int)(unsigned)(fb >> 32);
             const int len = (b - c0) < 64 ? (b - c0) : 64;
-            if (lane == 0) {
+            double mine = 0.0;
+            if (len == 64) {
+#pragma unroll 16
+                for (int i = 0; i < 64; ++i) {
+                    const unsigned lo = (unsigned)__builtin_amdgcn_readlane(flo, i);
+                    const unsigned hi = (unsigned)__builtin_amdgcn_readlane(fhi, i);
+                    prod = __dmul_rn(prod, __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo)));
+                    if (lane == i) mine = prod;
+                }
+            } else {
                 for (int i = 0; i < len; ++i) {
-                    prod = __dmul_rn(prod, fac[wid][i]);
-                    fac[wid][i] = prod;
+                    const unsigned lo = (unsigned)__builtin_amdgcn_readlane(flo, i);
+                    const unsigned hi = (unsigned)__builtin_amdgcn_readlane(fhi, i);
+                    prod = __dmul_rn(prod, __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo)));
+                    if (lane == i) mine = prod;
                 }
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            if (e < b) P[e] = fac[wid][lane];
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (e < b) P[e] = mine;
         }
         if (lane == 0) q[v] = prod;
         bad = __reduce_or_sync(~0ull, bad);

@@ -26,7 +26,7 @@ constexpr uint32_t DEFERRED = 0xFFFFFFFFu;
 constexpr int SMALL_SORT = 256;    // sizes up to this are sorted by one wave in k_gather_small
 constexpr int SORT_LDS_MAX = 8192; // sizes up to this are sorted in LDS by k_gather_medium;
                                    // larger ones are written already sorted by the global tier
-constexpr int IDBATCH = 64;        // sample ids taken from the global counter at a time
+constexpr int IDBATCH = 32;        // sample ids taken from the global counter at a time
 
 enum : int { F_ACTIVE = 1, F_ROOTPEND = 2, F_DEFER = 4, F_CLEAR = 8 };
 
@@ -120,12 +120,13 @@ struct SampleArgs {
 };
 
 // RCAP: nodes a slot holds before its sample moves on (the visited threshold); HCAP: size
-// of the slot's open-addressing hash, any size above RCAP (3/2 RCAP keeps the load factor
-// at most 2/3 while leaving LDS for more slots).
+// of the slot's open-addressing hash, any size above RCAP (about 4/3 RCAP keeps the load
+// factor at most 3/4 while leaving LDS for more slots).
 template <int BLOCK, int S, int RCAP, int HCAP, int ICAP, bool GLOBAL>
 __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
 {
     static_assert(GLOBAL || HCAP > RCAP, "the hash must be larger than the node list");
+    static_assert(GLOBAL || HCAP <= 65535, "list entries are 16-bit hash slot indexes");
     constexpr int HSZ = GLOBAL ? 1 : S * HCAP;
     constexpr int LSZ = GLOBAL ? 1 : S * RCAP;
     constexpr int IPT = (ICAP + BLOCK - 1) / BLOCK;
@@ -134,7 +135,9 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
     static_assert(IDBATCH >= S, "one refill must cover every empty slot");
 
     __shared__ int32_t sh_hash[HSZ];
-    __shared__ int32_t sh_list[LSZ];
+    // LDS tiers: the node list holds the hash slot of each node in discovery order (the
+    // slot holds the node id), half the bytes of a list of ids
+    __shared__ uint16_t sh_lidx[LSZ];
     __shared__ uint32_t s_idx[S];
     __shared__ int32_t s_count[S], s_cursor[S], s_flags[S], s_rib[S], s_rie[S];
     __shared__ unsigned long long s_probed[S];
@@ -145,6 +148,13 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
     __shared__ uint8_t it_slot[ICAP];
     __shared__ int32_t s_nitems, s_alive;
     __shared__ unsigned long long s_idnext, s_idend;
+    // the root records of the last two id batches, loaded when a batch is taken, so that
+    // admitting a sample costs no global round trip: [buffer][id - base]
+    __shared__ int4 s_crec[2][IDBATCH];
+    __shared__ int32_t s_cu1[2][IDBATCH];
+    __shared__ uint32_t s_cidx[2][IDBATCH];
+    __shared__ unsigned long long s_cbase[2];
+    __shared__ int s_ccur;
     __shared__ int32_t s_scan[BLOCK / 64 + 1];
 
     const int tid = threadIdx.x;
@@ -153,9 +163,11 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
     const unsigned long long id_count = a.id_count_dev ? *a.id_count_dev : a.id_count;
     const unsigned long long id_base = a.id_base_dev ? *a.id_base_dev : 0ull;
 
-    auto list_ptr = [&](int s) -> int32_t * {
-        if constexpr (GLOBAL) return a.glist + ((size_t)blockIdx.x * S + s) * (size_t)n;
-        else return sh_list + s * RCAP;
+    auto list_ptr = [&](int s) -> int32_t * { return a.glist + ((size_t)blockIdx.x * S + s) * (size_t)n; };
+    // node at position t of slot s's list
+    auto list_node = [&](int s, int t) -> int32_t {
+        if constexpr (GLOBAL) return list_ptr(s)[t];
+        else return sh_hash[s * HCAP + sh_lidx[s * RCAP + t]];
     };
     auto bits_ptr = [&](int s) -> uint32_t * { return a.gbits + ((size_t)blockIdx.x * S + s) * a.words; };
 
@@ -181,7 +193,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                 const int32_t old = atomicCAS(&H[h], -1, u);
                 if (old == -1) {
                     const int pos = atomicAdd(&s_count[s], 1);
-                    if (pos < RCAP) sh_list[s * RCAP + pos] = u;
+                    if (pos < RCAP) sh_lidx[s * RCAP + pos] = (uint16_t)h;
                     else atomicOr(&s_flags[s], F_DEFER);
                     return;
                 }
@@ -203,7 +215,13 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
     if (tid == 0) {
         s_idnext = 0;
         s_idend = 0;
+        s_cbase[0] = s_cbase[1] = ~0ull;
+        s_ccur = 0;
     }
+    // staging space is reserved STAGE_CHUNK entries at a time per workgroup (lane 0 of
+    // wave 0 keeps the open chunk [st_base, st_end)); the HBM tier reserves exactly
+    constexpr unsigned long long STAGE_CHUNK = GLOBAL ? 0ull : 8ull * S * RCAP;
+    unsigned long long st_base = 0, st_end = 0;
     block_sync<BLOCK>();
 
     for (;;) {
@@ -212,14 +230,23 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
             const int s = tid;
             const bool own = s < S;
             int f = own ? s_flags[s] : 0;
-            // finished samples of this pass reserve their staging space with one atomic
+            // finished samples of this pass take their staging space from the workgroup's
+            // open chunk, which is refilled with one atomic when it runs short
             const bool fin = own && (f & F_ACTIVE) && !(!GLOBAL && (f & F_DEFER)) && !(f & F_ROOTPEND) &&
                              s_cursor[s] >= s_count[s];
             const unsigned long long fcnt = fin ? (unsigned long long)s_count[s] : 0ull;
             const unsigned long long fincl = wave_incl_scan(fcnt);
             const unsigned long long ftot = __shfl(fincl, 63, 64);
             unsigned long long fbase = 0;
-            if (s == 0 && ftot) fbase = atomicAdd(a.stage_used, ftot);
+            if (s == 0 && ftot) {
+                if (st_base + ftot > st_end) {
+                    const unsigned long long want = ftot > STAGE_CHUNK ? ftot : STAGE_CHUNK;
+                    st_base = atomicAdd(a.stage_used, want);
+                    st_end = st_base + want;
+                }
+                fbase = st_base;
+                st_base += ftot;
+            }
             fbase = __shfl(fbase, 0, 64);
             if (own && (f & F_ACTIVE)) {
                 if (!GLOBAL && (f & F_DEFER)) {
@@ -264,9 +291,28 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                 const unsigned long long idnext = s_idnext, idend = s_idend;
                 const unsigned long long avail = idend - idnext;
                 unsigned long long nb = 0;
+                int cur = s_ccur;
                 if (avail < (unsigned long long)nwant) {
                     if (s == 0) nb = atomicAdd(a.next, (unsigned long long)IDBATCH);
                     nb = __shfl(nb, 0, 64);
+                    // load the new batch's records into the other buffer (lane l: id nb + l)
+                    cur ^= 1;
+                    if (s < IDBATCH) {
+                        const unsigned long long id = nb + (unsigned long long)s;
+                        if (id < id_count) {
+                            const uint32_t i = a.id_list ? a.id_list[id] : (uint32_t)(id_base + id);
+                            s_cidx[cur][s] = i;
+                            s_crec[cur][s] = a.rec[i];
+                            s_cu1[cur][s] = a.u1[i];
+                        }
+                    }
+                    if (s == 0) {
+                        s_cbase[cur] = nb;
+                        s_ccur = cur;
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                 }
                 const unsigned long long myid =
                     (unsigned long long)rank < avail ? idnext + rank : nb + (rank - avail);
@@ -279,14 +325,18 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                     }
                 }
                 if (want && myid < id_count) {
-                    const uint32_t i = a.id_list ? a.id_list[myid] : (uint32_t)(id_base + myid);
-                    const int4 rr = a.rec[i];
-                    if ((uint32_t)rr.x >= (uint32_t)n || (uint32_t)a.u1[i] >= (uint32_t)n || rr.y < rr.z ||
-                        rr.w <= rr.y || (int64_t)rr.w > 2 * a.npairs) {
+                    // the id is in the newest batch or in the remainder of the one before
+                    const int b = (myid - s_cbase[cur] < (unsigned long long)IDBATCH) ? cur : (cur ^ 1);
+                    const unsigned long long cd = myid - s_cbase[b];
+                    const int c = cd < (unsigned long long)IDBATCH ? (int)cd : 0;
+                    const uint32_t i = s_cidx[b][c];
+                    const int4 r = s_crec[b][c];
+                    const int32_t u = s_cu1[b][c];
+                    if (cd >= (unsigned long long)IDBATCH || i >= (uint32_t)(id_base + (a.id_list ? 0x7FFFFFFFull : id_count)) ||
+                        (uint32_t)r.x >= (uint32_t)n || (uint32_t)u >= (uint32_t)n || r.y < r.z || r.w <= r.y ||
+                        (int64_t)r.w > 2 * a.npairs) {
                         atomicOr(a.overflow, 8); // bounds guard: the sample is left out
                     } else {
-                    const int4 r = a.rec[i];
-                    const int32_t u = a.u1[i];
                     s_idx[s] = i;
                     s_rib[s] = r.y + 1;
                     s_rie[s] = r.w;
@@ -295,20 +345,22 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                     s_cursor[s] = 1;
                     int nf = F_ACTIVE | (r.y + 1 < r.w ? F_ROOTPEND : 0);
                     if (!GLOBAL && (uint32_t)(r.w - r.z) > a.big_row) nf |= F_DEFER;
-                    int32_t *L = list_ptr(s);
-                    L[0] = r.x;
-                    L[1] = u;
                     if constexpr (GLOBAL) {
+                        int32_t *L = list_ptr(s);
+                        L[0] = r.x;
+                        L[1] = u;
                         uint32_t *B = bits_ptr(s);
                         atomicOr(B + (r.x >> 5), 1u << (r.x & 31));
                         atomicOr(B + (u >> 5), 1u << (u & 31));
                     } else {
+                        // root and u1 differ (no self-loops), so they take two slots
                         int32_t *H = sh_hash + s * HCAP;
                         const int32_t keys[2] = {r.x, u};
                         for (int t = 0; t < 2; ++t) {
                             uint32_t h = hash_slot(keys[t]);
                             while (H[h] != -1) h = h + 1 == (uint32_t)HCAP ? 0u : h + 1;
                             H[h] = keys[t];
+                            sh_lidx[s * RCAP + t] = (uint16_t)h;
                         }
                     }
                     f = nf;
@@ -362,7 +414,8 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
             const int cnt = s_wo_cnt[s];
             const unsigned long long off = s_wo_off[s];
             if constexpr (!GLOBAL) {
-                for (int t = tid; t < cnt; t += BLOCK) a.staging[off + t] = sh_list[s * RCAP + t];
+                for (int t = tid; t < cnt; t += BLOCK) a.staging[off + t] = list_node(s, t);
+                block_sync<BLOCK>(); // every read of the hash above precedes its clearing
                 for (int t = tid; t < HCAP; t += BLOCK) sh_hash[s * HCAP + t] = -1;
             } else {
                 int32_t *L = list_ptr(s);
@@ -416,7 +469,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                 beg = s_rib[s];
                 end = s_rie[s];
             } else {
-                const int32_t x = list_ptr(s)[s_ifirst[s] + t - s_irp[s]];
+                const int32_t x = list_node(s, s_ifirst[s] + t - s_irp[s]);
                 if ((uint32_t)x >= (uint32_t)n) { // bounds guard: report, never index
                     atomicOr(a.overflow, 4);
                     beg = end = 0;
@@ -720,24 +773,26 @@ struct Variant {
 // With 64 threads a workgroup is one wave that owns its slots and LDS and never waits for
 // another wave; with 256 threads four waves share the slots and meet at barriers.
 static const Variant kTier0[] = {
-    {64, 4, 256, k_sample<64, 4, 256, 384, 256, false>},
-    {64, 8, 128, k_sample<64, 8, 128, 192, 256, false>},
-    {64, 8, 64, k_sample<64, 8, 64, 96, 256, false>},
-    {64, 8, 192, k_sample<64, 8, 192, 288, 256, false>},
-    {64, 8, 256, k_sample<64, 8, 256, 384, 256, false>},
-    {64, 12, 192, k_sample<64, 12, 192, 288, 384, false>},
-    {64, 16, 128, k_sample<64, 16, 128, 192, 512, false>},
-    {64, 16, 64, k_sample<64, 16, 64, 96, 512, false>},
-    {256, 32, 128, k_sample<256, 32, 128, 192, 1024, false>},
-    {256, 16, 256, k_sample<256, 16, 256, 384, 1024, false>},
-    {256, 32, 256, k_sample<256, 32, 256, 384, 1024, false>},
-    {256, 8, 512, k_sample<256, 8, 512, 768, 1024, false>},
-    {256, 16, 128, k_sample<256, 16, 128, 192, 1024, false>},
+    {64, 4, 256, k_sample<64, 4, 256, 344, 256, false>},
+    {64, 8, 128, k_sample<64, 8, 128, 172, 256, false>},
+    {64, 8, 64, k_sample<64, 8, 64, 88, 256, false>},
+    {64, 8, 192, k_sample<64, 8, 192, 256, 256, false>},
+    {64, 8, 256, k_sample<64, 8, 256, 344, 256, false>},
+    {64, 12, 192, k_sample<64, 12, 192, 256, 384, false>},
+    {64, 12, 256, k_sample<64, 12, 256, 344, 384, false>},
+    {64, 16, 128, k_sample<64, 16, 128, 172, 512, false>},
+    {64, 16, 192, k_sample<64, 16, 192, 256, 512, false>},
+    {64, 16, 64, k_sample<64, 16, 64, 88, 512, false>},
+    {256, 32, 128, k_sample<256, 32, 128, 172, 1024, false>},
+    {256, 16, 256, k_sample<256, 16, 256, 344, 1024, false>},
+    {256, 32, 256, k_sample<256, 32, 256, 344, 1024, false>},
+    {256, 8, 512, k_sample<256, 8, 512, 688, 1024, false>},
+    {256, 16, 128, k_sample<256, 16, 128, 172, 1024, false>},
 };
 // second tier: samples that outgrew the first, slots of 1024 nodes in LDS
 static const Variant kTierMidV[] = {
-    {64, 2, 1024, k_sample<64, 2, 1024, 1536, 256, false>},
-    {256, 8, 1024, k_sample<256, 8, 1024, 1536, 1024, false>},
+    {64, 2, 1024, k_sample<64, 2, 1024, 1368, 256, false>},
+    {256, 8, 1024, k_sample<256, 8, 1024, 1368, 1024, false>},
 };
 // One sample per workgroup: the samples that reach this tier are few and large, so the
 // chip is filled with workgroups rather than slots; the HBM buffers of all slots are kept
@@ -817,7 +872,6 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
     DevBuf<Counters> ctr;
     ctr.alloc(arena, 1);
 
-    uint64_t cap = cfg.staging_entries ? cfg.staging_entries : (uint64_t)count * 48ull + (1ull << 20);
     DevBuf<int32_t> staging;
     Counters hc{};
     const Variant &v0 = pick_variant(kTier0, sizeof(kTier0) / sizeof(kTier0[0]), cfg.threads, cfg.slots, cfg.visited);
@@ -825,6 +879,16 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
     const int cus = device_cu_count();
     const int nb0 = occupancy_blocks(v0.fn, (int)v0.threads) * cus;
     const int nbm = occupancy_blocks(vm.fn, (int)vm.threads) * cus;
+    // Staging: each LDS-tier workgroup reserves 8 * slots * visited entries at a time and
+    // wastes less than one finished pass (slots * visited) per reservation plus its last
+    // open chunk, so sum|R| * 8/7 + 2 chunks per workgroup bounds what a launch reserves.
+    const uint64_t ch0 = 8ull * v0.slots * v0.visited, chm = 8ull * vm.slots * vm.visited;
+    const uint64_t slack = (uint64_t)std::min<uint64_t>(nb0, count) * 2 * ch0 +
+                           (uint64_t)std::min<uint64_t>(nbm, count) * 2 * chm;
+    auto staging_bound = [&](uint64_t entries, uint64_t launches) {
+        return entries + entries / 7 + 1 + launches * slack + (1ull << 20);
+    };
+    uint64_t cap = cfg.staging_entries ? cfg.staging_entries : staging_bound((uint64_t)count * 48ull, 1);
     const uint64_t words = ((uint64_t)n + 31) / 32;
     // global tier: every slot holds a bitmap of n bits and a node list of n entries
     const uint64_t slot_bytes = (uint64_t)n * 4ull + words * 4ull;
@@ -852,6 +916,7 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
     auto sample_chain_graph = [&]() {
         const uint64_t chunk = std::min<uint64_t>(count, cfg.chunk ? cfg.chunk : (1ull << 22));
         const uint64_t replays = (count + chunk - 1) / chunk;
+        if (!cfg.staging_entries) cap = staging_bound((uint64_t)count * 48ull, replays);
         DevBuf<ChainCtl> gc;
         gc.alloc(arena, 1);
         const uint64_t nbg_g = (uint64_t)nbg;
@@ -975,7 +1040,8 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
             gg.x = nullptr;
             gg.g = nullptr;
             if (!hc.overflow) return;
-            cap = hc.stage_used + 1024; // every size is known now: exact retry
+            // every size is known now: a bound that holds whatever order the chunks took
+            cap = staging_bound(hc.tier[0][1] + hc.tier[1][1] + hc.tier[2][1], replays);
             staging.reset();
             if (attempt == 1) throw Error{SKIS_ENOMEM, "staging overflow after resize"};
         }
@@ -1109,7 +1175,8 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
             throw Error{SKIS_EHIP, "internal bounds check failed in the sampler (flags " +
                                        std::to_string(hc.overflow | herr) + ")"};
         if (!hc.overflow) break;
-        cap = hc.stage_used + 1024; // every size is known now: exact retry
+        // every size is known now: a bound that holds whatever order the chunks took
+        cap = staging_bound(hc.tier[0][1] + hc.tier[1][1] + hc.tier[2][1], 1);
         staging.reset();
         if (attempt == 1) throw Error{SKIS_ENOMEM, "staging overflow after resize"};
     }

@@ -115,7 +115,7 @@ def test_sketch_bit_exact_cl15k(cl15k):
 
 @pytest.mark.parametrize("threads,slots,visited,big_row", [
     (64, 8, 128, 16384), (64, 8, 64, 16384), (64, 16, 128, 16384), (64, 4, 256, 16384), (64, 16, 64, 16384),
-    (64, 8, 192, 16384), (64, 8, 256, 16384), (64, 12, 192, 16384),
+    (64, 8, 192, 16384), (64, 8, 256, 16384), (64, 12, 192, 16384), (64, 12, 256, 16384), (64, 16, 192, 16384),
     (256, 32, 128, 16384), (256, 16, 256, 16384), (256, 32, 256, 16384), (256, 8, 512, 16384),
     (256, 16, 128, 16384), (64, 8, 128, 8), (256, 32, 128, 8), (64, 16, 64, 100)])
 def test_sketch_identical_across_sampler_shapes(skis, threads, slots, visited, big_row):
