@@ -88,14 +88,15 @@ void skis_default_options(skis_options *opt)
     if (!opt) return;
     std::memset(opt, 0, sizeof(*opt));
     opt->form = 0;
-    opt->slots_per_block = 16;
-    opt->visited_threshold = 128;
+    opt->slots_per_block = 4;
+    opt->visited_threshold = 192;
     opt->threads_per_block = 64;
     opt->big_row = 16384;
     opt->build_inverse_index = 1;
     opt->max_device_bytes = 0;
     opt->staging_entries = 0;
     opt->chunk_samples = 0;
+    opt->pairs_per_lane = 2;
 }
 
 int skis_preprocess(int32_t n, int64_t m, const int32_t *row_ptr, const int32_t *col, const float *w, double *P,
@@ -149,6 +150,7 @@ int skis_build_sketch(int32_t n, int64_t m, const int32_t *row_ptr, const int32_
             opt.max_device_bytes = opt_in->max_device_bytes;
             opt.staging_entries = opt_in->staging_entries;
             opt.chunk_samples = opt_in->chunk_samples;
+            if (opt_in->pairs_per_lane) opt.pairs_per_lane = opt_in->pairs_per_lane;
         }
         if (opt.form > 2) throw skis::Error{SKIS_EINVAL, "unknown sampler form"};
         skis_sketch *h = new skis_sketch;
@@ -185,6 +187,7 @@ int skis_build_sketch(int32_t n, int64_t m, const int32_t *row_ptr, const int32_
                     cfg.big_row = opt.big_row;
                     cfg.staging_entries = opt.staging_entries;
                     cfg.chunk = opt.chunk_samples;
+                    cfg.ppl = opt.pairs_per_lane;
                     skis::sample_and_compact(sk.arena, prep, n, m, num_samples, seed, cfg, sk, stream);
                 }
                 // q moves into the sketch only after every kernel that reads prep.q has run

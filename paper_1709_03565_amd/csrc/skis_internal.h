@@ -133,11 +133,12 @@ void preprocess(Arena &arena, int32_t n, int64_t m, const int32_t *row_ptr, cons
 struct SampleConfig {
     uint32_t form = 0;
     uint32_t threads = 64;
-    uint32_t slots = 16;
-    uint32_t visited = 128;
+    uint32_t slots = 4;
+    uint32_t visited = 192;
     uint32_t big_row = 16384;
     uint64_t staging_entries = 0;
     uint64_t chunk = 0; // captured form: samples per replay of the chain (0: 2^22)
+    uint32_t ppl = 2;   // edge pairs per lane per sweep in the first tier
 };
 
 void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, uint64_t T, uint64_t seed,

@@ -26,7 +26,9 @@ constexpr uint32_t DEFERRED = 0xFFFFFFFFu;
 constexpr int SMALL_SORT = 256;    // sizes up to this are sorted by one wave in k_gather_small
 constexpr int SORT_LDS_MAX = 8192; // sizes up to this are sorted in LDS by k_gather_medium;
                                    // larger ones are written already sorted by the global tier
-constexpr int IDBATCH = 32;        // sample ids taken from the global counter at a time
+// sample ids taken from the global counter at a time: at least the slots of a workgroup
+template <int S>
+constexpr int id_batch() { return S <= 16 ? 16 : 32; }
 
 enum : int { F_ACTIVE = 1, F_ROOTPEND = 2, F_DEFER = 4, F_CLEAR = 8 };
 
@@ -122,15 +124,17 @@ struct SampleArgs {
 // RCAP: nodes a slot holds before its sample moves on (the visited threshold); HCAP: size
 // of the slot's open-addressing hash, any size above RCAP (about 4/3 RCAP keeps the load
 // factor at most 3/4 while leaving LDS for more slots).
-template <int BLOCK, int S, int RCAP, int HCAP, int ICAP, bool GLOBAL>
+// ICAP: items (pending nodes over all slots) expanded per pass; PPL: most edge pairs a lane
+// takes per sweep (4 keeps more loads in flight, 2 needs fewer registers).
+template <int BLOCK, int S, int RCAP, int HCAP, int ICAP, int PPL, bool GLOBAL>
 __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
 {
+    constexpr int IDBATCH = id_batch<S>();
     static_assert(GLOBAL || HCAP > RCAP, "the hash must be larger than the node list");
     static_assert(GLOBAL || HCAP <= 65535, "list entries are 16-bit hash slot indexes");
     constexpr int HSZ = GLOBAL ? 1 : S * HCAP;
     constexpr int LSZ = GLOBAL ? 1 : S * RCAP;
     constexpr int IPT = (ICAP + BLOCK - 1) / BLOCK;
-    constexpr int PPL = 4; // edge pairs per lane per sweep
     static_assert(S <= 64, "slots are owned by the lanes of wave 0");
     static_assert(IDBATCH >= S, "one refill must cover every empty slot");
 
@@ -254,7 +258,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                     const unsigned long long k = atomicAdd(a.n_deferred, 1ull);
                     a.deferred[k] = i;
                     a.out_size[i] = DEFERRED;
-                    s_wo_cnt[s] = 0;
+                    s_wo_cnt[s] = -1; // nothing to write; its hash may hold keys past the list
                     f = F_CLEAR;
                     s_flags[s] = f;
                 } else if (fin) {
@@ -414,9 +418,18 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
             const int cnt = s_wo_cnt[s];
             const unsigned long long off = s_wo_off[s];
             if constexpr (!GLOBAL) {
-                for (int t = tid; t < cnt; t += BLOCK) a.staging[off + t] = list_node(s, t);
-                block_sync<BLOCK>(); // every read of the hash above precedes its clearing
-                for (int t = tid; t < HCAP; t += BLOCK) sh_hash[s * HCAP + t] = -1;
+                if (cnt < 0) { // a sample handed on: clear the whole table
+                    for (int t = tid; t < HCAP; t += BLOCK) sh_hash[s * HCAP + t] = -1;
+                } else {
+                    // a finished sample has every key in its list: write the first cnt
+                    // (all, unless staging overflowed) and clear exactly the slots it used
+                    const int rc = s_count[s];
+                    for (int t = tid; t < rc; t += BLOCK) {
+                        const int h = sh_lidx[s * RCAP + t];
+                        if (t < cnt) a.staging[off + t] = sh_hash[s * HCAP + h];
+                        sh_hash[s * HCAP + h] = -1;
+                    }
+                }
             } else {
                 int32_t *L = list_ptr(s);
                 uint32_t *B = bits_ptr(s);
@@ -765,7 +778,7 @@ struct Counters {
 typedef void (*SampleKernel)(SampleArgs);
 
 struct Variant {
-    uint32_t threads, slots, visited;
+    uint32_t threads, slots, visited, ppl;
     SampleKernel fn;
 };
 
@@ -773,39 +786,45 @@ struct Variant {
 // With 64 threads a workgroup is one wave that owns its slots and LDS and never waits for
 // another wave; with 256 threads four waves share the slots and meet at barriers.
 static const Variant kTier0[] = {
-    {64, 4, 256, k_sample<64, 4, 256, 344, 256, false>},
-    {64, 8, 128, k_sample<64, 8, 128, 172, 256, false>},
-    {64, 8, 64, k_sample<64, 8, 64, 88, 256, false>},
-    {64, 8, 192, k_sample<64, 8, 192, 256, 256, false>},
-    {64, 8, 256, k_sample<64, 8, 256, 344, 256, false>},
-    {64, 12, 192, k_sample<64, 12, 192, 256, 384, false>},
-    {64, 12, 256, k_sample<64, 12, 256, 344, 384, false>},
-    {64, 16, 128, k_sample<64, 16, 128, 172, 512, false>},
-    {64, 16, 192, k_sample<64, 16, 192, 256, 512, false>},
-    {64, 16, 64, k_sample<64, 16, 64, 88, 512, false>},
-    {256, 32, 128, k_sample<256, 32, 128, 172, 1024, false>},
-    {256, 16, 256, k_sample<256, 16, 256, 344, 1024, false>},
-    {256, 32, 256, k_sample<256, 32, 256, 344, 1024, false>},
-    {256, 8, 512, k_sample<256, 8, 512, 688, 1024, false>},
-    {256, 16, 128, k_sample<256, 16, 128, 172, 1024, false>},
+    {64, 4, 192, 4, k_sample<64, 4, 192, 256, 128, 4, false>},
+    {64, 4, 192, 2, k_sample<64, 4, 192, 256, 64, 2, false>},
+    {64, 4, 256, 4, k_sample<64, 4, 256, 320, 128, 4, false>},
+    {64, 4, 256, 2, k_sample<64, 4, 256, 320, 64, 2, false>},
+    {64, 2, 256, 2, k_sample<64, 2, 256, 320, 64, 2, false>},
+    {64, 3, 256, 2, k_sample<64, 3, 256, 320, 64, 2, false>},
+    {64, 2, 384, 2, k_sample<64, 2, 384, 512, 64, 2, false>},
+    {64, 6, 256, 4, k_sample<64, 6, 256, 320, 192, 4, false>},
+    {64, 8, 128, 4, k_sample<64, 8, 128, 172, 256, 4, false>},
+    {64, 8, 192, 4, k_sample<64, 8, 192, 256, 256, 4, false>},
+    {64, 8, 192, 2, k_sample<64, 8, 192, 256, 256, 2, false>},
+    {64, 8, 256, 4, k_sample<64, 8, 256, 344, 256, 4, false>},
+    {64, 12, 192, 4, k_sample<64, 12, 192, 256, 384, 4, false>},
+    {64, 16, 128, 4, k_sample<64, 16, 128, 172, 512, 4, false>},
+    {64, 16, 64, 4, k_sample<64, 16, 64, 88, 512, 4, false>},
+    {256, 16, 128, 4, k_sample<256, 16, 128, 172, 1024, 4, false>},
+    {256, 32, 128, 4, k_sample<256, 32, 128, 172, 1024, 4, false>},
+    {256, 16, 256, 4, k_sample<256, 16, 256, 344, 1024, 4, false>},
 };
 // second tier: samples that outgrew the first, slots of 1024 nodes in LDS
 static const Variant kTierMidV[] = {
-    {64, 2, 1024, k_sample<64, 2, 1024, 1368, 256, false>},
-    {256, 8, 1024, k_sample<256, 8, 1024, 1368, 1024, false>},
+    {64, 2, 1024, 2, k_sample<64, 2, 1024, 1368, 128, 2, false>},
+    {256, 8, 1024, 4, k_sample<256, 8, 1024, 1368, 1024, 4, false>},
 };
 // One sample per workgroup: the samples that reach this tier are few and large, so the
 // chip is filled with workgroups rather than slots; the HBM buffers of all slots are kept
 // within TIERG_BUDGET bytes.
 constexpr int TIERG_SLOTS = 1;
 constexpr uint64_t TIERG_BUDGET = 8ull << 30;
-static SampleKernel const kTierGlobal = k_sample<256, TIERG_SLOTS, 1, 1, 1024, true>;
+static SampleKernel const kTierGlobal = k_sample<256, TIERG_SLOTS, 1, 1, 1024, 4, true>;
 
-static const Variant &pick_variant(const Variant *vs, size_t nv, uint32_t threads, uint32_t slots, uint32_t visited)
+static const Variant &pick_variant(const Variant *vs, size_t nv, uint32_t threads, uint32_t slots, uint32_t visited,
+                                   uint32_t ppl)
 {
     for (size_t i = 0; i < nv; ++i)
-        if (vs[i].threads == threads && vs[i].slots == slots && vs[i].visited == visited) return vs[i];
-    throw Error{SKIS_EINVAL, "unsupported (threads_per_block, slots_per_block, visited_threshold) combination"};
+        if (vs[i].threads == threads && vs[i].slots == slots && vs[i].visited == visited && vs[i].ppl == ppl)
+            return vs[i];
+    throw Error{SKIS_EINVAL,
+                "unsupported (threads_per_block, slots_per_block, visited_threshold, pairs_per_lane) combination"};
 }
 
 static int occupancy_blocks(SampleKernel fn, int block)
@@ -874,7 +893,8 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
 
     DevBuf<int32_t> staging;
     Counters hc{};
-    const Variant &v0 = pick_variant(kTier0, sizeof(kTier0) / sizeof(kTier0[0]), cfg.threads, cfg.slots, cfg.visited);
+    const Variant &v0 =
+        pick_variant(kTier0, sizeof(kTier0) / sizeof(kTier0[0]), cfg.threads, cfg.slots, cfg.visited, cfg.ppl);
     const Variant &vm = kTierMidV[cfg.threads == 64 ? 0 : 1];
     const int cus = device_cu_count();
     const int nb0 = occupancy_blocks(v0.fn, (int)v0.threads) * cus;

@@ -113,19 +113,21 @@ def test_sketch_bit_exact_cl15k(cl15k):
     assert np.array_equal(_np(sk.q()), oracle.row_prefix(g.row_ptr, g.w)[1])
 
 
-@pytest.mark.parametrize("threads,slots,visited,big_row", [
-    (64, 8, 128, 16384), (64, 8, 64, 16384), (64, 16, 128, 16384), (64, 4, 256, 16384), (64, 16, 64, 16384),
-    (64, 8, 192, 16384), (64, 8, 256, 16384), (64, 12, 192, 16384), (64, 12, 256, 16384), (64, 16, 192, 16384),
-    (256, 32, 128, 16384), (256, 16, 256, 16384), (256, 32, 256, 16384), (256, 8, 512, 16384),
-    (256, 16, 128, 16384), (64, 8, 128, 8), (256, 32, 128, 8), (64, 16, 64, 100)])
-def test_sketch_identical_across_sampler_shapes(skis, threads, slots, visited, big_row):
+@pytest.mark.parametrize("threads,slots,visited,ppl,big_row", [
+    (64, 4, 192, 4, 16384), (64, 4, 192, 2, 16384), (64, 4, 256, 4, 16384), (64, 4, 256, 2, 16384),
+    (64, 2, 256, 2, 16384), (64, 3, 256, 2, 16384), (64, 2, 384, 2, 16384),
+    (64, 6, 256, 4, 16384), (64, 8, 128, 4, 16384), (64, 8, 192, 4, 16384), (64, 8, 192, 2, 16384),
+    (64, 8, 256, 4, 16384), (64, 12, 192, 4, 16384), (64, 16, 128, 4, 16384), (64, 16, 64, 4, 16384),
+    (256, 16, 128, 4, 16384), (256, 32, 128, 4, 16384), (256, 16, 256, 4, 16384),
+    (64, 8, 128, 4, 8), (256, 32, 128, 4, 8), (64, 16, 64, 4, 100), (64, 4, 192, 2, 8)])
+def test_sketch_identical_across_sampler_shapes(skis, threads, slots, visited, ppl, big_row):
     # big_row = 8 sends most samples through the second tier
     g = inputs.workload_graph("cl15k_wc")
     T = 30000
     _say("shape", threads, slots, visited, big_row)
     ora = oracle.build_sketch(g.row_ptr, g.col, g.w, seed=11, j0=0, j1=T, nthreads=8)
     sk = skis.build_sketch(g.row_ptr, g.col, g.w, T, 11, threads_per_block=threads, slots_per_block=slots,
-                           visited_threshold=visited, big_row=big_row)
+                           visited_threshold=visited, pairs_per_lane=ppl, big_row=big_row)
     inf = sk.info()
     _assert_tiers_add_up(inf)
     if big_row == 8:

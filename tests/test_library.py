@@ -52,7 +52,8 @@ def test_library_targets_gfx950(libpath):
 def test_default_options_and_errors_without_gpu(libpath):
     from paper_1709_03565_amd import skis
     o = skis.default_options()
-    assert o.slots_per_block == 16 and o.visited_threshold == 128 and o.threads_per_block == 64
+    assert o.slots_per_block == 4 and o.visited_threshold == 192 and o.threads_per_block == 64
+    assert o.pairs_per_lane == 2
     assert o.build_inverse_index == 1
     L = skis.lib()
     h = ctypes.c_void_p()
@@ -81,10 +82,12 @@ def test_bench_kernel_names_match_the_library_table():
     import bench
     src = open(os.path.join(ROOT, "paper_1709_03565_amd", "csrc", "skis_sample.hip")).read()
     table = src[src.index("kTier0[] = {"):src.index("};", src.index("kTier0[] = {"))]
-    rows = re.findall(r"\{(\d+), (\d+), (\d+), k_sample<(\d+), (\d+), (\d+), (\d+), (\d+), false>\}", table)
+    rows = re.findall(r"\{(\d+), (\d+), (\d+), (\d+), k_sample<(\d+), (\d+), (\d+), (\d+), (\d+), (\d+), false>\}",
+                      table)
     assert len(rows) >= 10
     for r in rows:
-        th, sl, vi, th2, sl2, vi2, hcap, icap = map(int, r)
-        assert (th, sl, vi) == (th2, sl2, vi2)
-        name = bench.tier0_kernel_name(dict(threads_per_block=th, slots_per_block=sl, visited_threshold=vi))
-        assert name == "k_sample<%d, %d, %d, %d, %d, false>" % (th, sl, vi, hcap, icap)
+        th, sl, vi, pl, th2, sl2, vi2, hcap, icap, pl2 = map(int, r)
+        assert (th, sl, vi, pl) == (th2, sl2, vi2, pl2)
+        name = bench.tier0_kernel_name(dict(threads_per_block=th, slots_per_block=sl, visited_threshold=vi,
+                                            pairs_per_lane=pl))
+        assert name == "k_sample<%d, %d, %d, %d, %d, %d, false>" % (th, sl, vi, hcap, icap, pl)
