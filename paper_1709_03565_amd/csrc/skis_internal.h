@@ -146,6 +146,10 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
 
 void build_inverse(Sketch &sk, hipStream_t s);
 
+// node_ptr[n+1] and node_samples[N] (each list ascending) of the N-entry sketch.
+void radix_transpose(Arena &arena, const int64_t *sample_ptr, const int32_t *nodes, uint64_t T, uint64_t N,
+                     int32_t n, int64_t *node_ptr, int32_t *node_samples, hipStream_t s);
+
 // ---------------------------------------------------------------------------------
 // Device-wide scans (exclusive), T in {uint32_t, uint64_t, int64_t, u128}.
 // ---------------------------------------------------------------------------------

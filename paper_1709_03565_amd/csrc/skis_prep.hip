@@ -60,11 +60,14 @@ __global__ __launch_bounds__(256) void k_prep_rows(int32_t n, int64_t m, const i
     }
 }
 
-// One wave per long row: the lanes load and validate 64 edges at a time, each holding its
-// factor (1 - w) in a register.  The running product is carried through the 64 factors in
-// row order by every lane at once (factor i read from lane i with readlane, one rounding per
-// product: the same sequence one thread would do), and lane i keeps the product that ends
-// at its edge, so the dependent chain is one fp64 multiply per edge.
+// One wave per long row, 512 edges per step.  The lanes load, validate and interleave the
+// step's edges (8 each) and put the factors (1 - w) in LDS; the loads of the next step are
+// already in flight.  Lane 0 then carries the running product through the 512 factors in
+// row order, 64 at a time held in registers, so the dependent chain is one fp64 multiply
+// per edge with one rounding each (the same sequence a single thread would do), and writes
+// the products back to LDS for all lanes to store P.
+constexpr int LONG_STEP = 512;
+
 __global__ __launch_bounds__(256) void k_prep_long(int32_t n, const int32_t *__restrict__ row_ptr,
                                                    const int32_t *__restrict__ col, const float *__restrict__ w,
                                                    uint2 *__restrict__ edges, double *__restrict__ P,
@@ -72,45 +75,86 @@ __global__ __launch_bounds__(256) void k_prep_long(int32_t n, const int32_t *__r
                                                    const int32_t *__restrict__ long_rows,
                                                    const unsigned int *__restrict__ n_long)
 {
+    constexpr int PER = LONG_STEP / 64;
+    __shared__ double fac_all[4][LONG_STEP];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    double *fac = fac_all[wid];
     const unsigned int cnt = *n_long;
+    auto wave_sync = []() {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
     for (unsigned int r = blockIdx.x * 4 + wid; r < cnt; r += gridDim.x * 4) {
         const int32_t v = long_rows[r];
         const int32_t a = row_ptr[v], b = row_ptr[v + 1];
-        double prod = 1.0; // the same in every lane
+        double prod = 1.0; // meaningful in lane 0
         int bad = 0;
-        for (int32_t c0 = a; c0 < b; c0 += 64) {
-            const int32_t e = c0 + lane;
-            double f = 1.0;
-            if (e < b) {
-                const int32_t u = col[e];
-                float wf = w[e];
-                bad |= check_edge(u, wf, v, n);
-                if (wf == 0.0f) wf = 0.0f;
-                edges[e] = make_uint2((uint32_t)u, __float_as_uint(wf));
-                f = __dsub_rn(1.0, (double)wf);
+        // element k of a step is edge c0 + k*64 + lane for this lane (coalesced per k)
+        int32_t uc[PER];
+        float wc[PER];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int32_t e = a + k * 64 + lane;
+            uc[k] = e < b ? col[e] : 0;
+            wc[k] = e < b ? w[e] : 0.0f;
+        }
+        for (int32_t c0 = a; c0 < b; c0 += LONG_STEP) {
+            // next step's loads first
+            int32_t un[PER];
+            float wn[PER];
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                const int32_t e = c0 + LONG_STEP + k * 64 + lane;
+                un[k] = e < b ? col[e] : 0;
+                wn[k] = e < b ? w[e] : 0.0f;
             }
-            const long long fb = __double_as_longlong(f);
-            const int flo = (int)(unsigned)fb, fhi = (int)(unsigned)(fb >> 32);
-            const int len = (b - c0) < 64 ? (b - c0) : 64;
-            double mine = 0.0;
-            if (len == 64) {
-#pragma unroll 16
-                for (int i = 0; i < 64; ++i) {
-                    const unsigned lo = (unsigned)__builtin_amdgcn_readlane(flo, i);
-                    const unsigned hi = (unsigned)__builtin_amdgcn_readlane(fhi, i);
-                    prod = __dmul_rn(prod, __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo)));
-                    if (lane == i) mine = prod;
-                }
-            } else {
-                for (int i = 0; i < len; ++i) {
-                    const unsigned lo = (unsigned)__builtin_amdgcn_readlane(flo, i);
-                    const unsigned hi = (unsigned)__builtin_amdgcn_readlane(fhi, i);
-                    prod = __dmul_rn(prod, __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo)));
-                    if (lane == i) mine = prod;
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                const int32_t e = c0 + k * 64 + lane;
+                if (e < b) {
+                    float wf = wc[k];
+                    bad |= check_edge(uc[k], wf, v, n);
+                    if (wf == 0.0f) wf = 0.0f;
+                    edges[e] = make_uint2((uint32_t)uc[k], __float_as_uint(wf));
+                    fac[k * 64 + lane] = __dsub_rn(1.0, (double)wf);
                 }
             }
-            if (e < b) P[e] = mine;
+            wave_sync();
+            const int len = (b - c0) < LONG_STEP ? (b - c0) : LONG_STEP;
+            if (lane == 0) {
+                if (len == LONG_STEP) {
+                    for (int g = 0; g < LONG_STEP; g += 64) {
+                        double f[64];
+#pragma unroll
+                        for (int i = 0; i < 64; ++i) f[i] = fac[g + i];
+#pragma unroll
+                        for (int i = 0; i < 64; ++i) {
+                            prod = __dmul_rn(prod, f[i]);
+                            f[i] = prod;
+                        }
+#pragma unroll
+                        for (int i = 0; i < 64; ++i) fac[g + i] = f[i];
+                    }
+                } else {
+                    for (int i = 0; i < len; ++i) {
+                        prod = __dmul_rn(prod, fac[i]);
+                        fac[i] = prod;
+                    }
+                }
+            }
+            wave_sync();
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                const int32_t e = c0 + k * 64 + lane;
+                if (e < b) P[e] = fac[k * 64 + lane];
+            }
+            wave_sync();
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                uc[k] = un[k];
+                wc[k] = wn[k];
+            }
         }
         if (lane == 0) q[v] = prod;
         bad = __reduce_or_sync(~0ull, bad);
