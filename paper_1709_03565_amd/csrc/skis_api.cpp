@@ -18,17 +18,68 @@ static thread_local std::string g_err;
 void set_error(const std::string &msg) { g_err = msg; }
 const std::string &get_error() { return g_err; }
 
+// Stream-ordered allocation from the device's default memory pool, which keeps up to
+// POOL_KEEP bytes of released memory for reuse: a build then takes its buffers from what the
+// previous one released instead of going back to the driver.  Buffers are released on the
+// arena's stream, after the work queued there that uses them.
+constexpr uint64_t POOL_KEEP = 64ull << 30;
+
+static bool pool_ready()
+{
+    static thread_local int ready_dev = -1;
+    static thread_local bool ok = false;
+    int d = 0;
+    if (hipGetDevice(&d) != hipSuccess) return false;
+    if (d != ready_dev) {
+        ready_dev = d;
+        int supported = 0;
+        ok = hipDeviceGetAttribute(&supported, hipDeviceAttributeMemoryPoolsSupported, d) == hipSuccess && supported;
+        if (ok) {
+            hipMemPool_t pool = nullptr;
+            uint64_t keep = POOL_KEEP;
+            ok = hipDeviceGetDefaultMemPool(&pool, d) == hipSuccess &&
+                 hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep) == hipSuccess;
+        }
+        (void)hipGetLastError();
+    }
+    return ok;
+}
+
+// A released block is kept and handed to a later request of at least half its size: the
+// stages of one build (sampler, compaction, transpose) allocate and release buffers of a few
+// GB each, and reusing them avoids a driver call per buffer.  Kept blocks go back to the
+// pool when the build ends (trim) and when the arena dies.
 void *Arena::alloc(size_t bytes)
 {
-    if (cap && used + bytes > cap)
-        throw Error{SKIS_ENOMEM, "max_device_bytes exceeded: " + std::to_string(used + bytes) + " > " +
+    const size_t need = bytes ? bytes : 1;
+    auto it = free_blocks.lower_bound(need);
+    if (it != free_blocks.end() && it->first <= 2 * need) {
+        void *p = it->second;
+        kept -= it->first;
+        free_blocks.erase(it);
+        used += bytes;
+        peak = std::max(peak, used);
+        return p;
+    }
+    if (cap && used + kept + need > cap) trim();
+    if (cap && used + need > cap)
+        throw Error{SKIS_ENOMEM, "max_device_bytes exceeded: " + std::to_string(used + need) + " > " +
                                      std::to_string(cap)};
     void *p = nullptr;
-    const hipError_t e = hipMalloc(&p, bytes);
+    const bool pooled = pool_ready();
+    hipError_t e = pooled ? hipMallocAsync(&p, need, stream) : hipMalloc(&p, need);
+    if (e != hipSuccess && !free_blocks.empty()) { // give the kept blocks back and try once more
+        (void)hipGetLastError();
+        trim();
+        e = pooled ? hipMallocAsync(&p, need, stream) : hipMalloc(&p, need);
+    }
     if (e != hipSuccess) {
         (void)hipGetLastError();
-        throw Error{SKIS_ENOMEM, "hipMalloc(" + std::to_string(bytes) + ") failed: " + hipGetErrorString(e)};
+        throw Error{SKIS_ENOMEM, "device allocation of " + std::to_string(need) + " bytes failed: " +
+                                     hipGetErrorString(e)};
     }
+    if (pooled) pooled_ptrs.insert(p);
+    blocks[p] = need;
     used += bytes;
     peak = std::max(peak, used);
     return p;
@@ -36,8 +87,23 @@ void *Arena::alloc(size_t bytes)
 
 void Arena::release(void *p, size_t bytes)
 {
-    (void)hipFree(p);
     used -= bytes;
+    auto it = blocks.find(p);
+    if (it == blocks.end()) return;
+    free_blocks.emplace(it->second, p);
+    kept += it->second;
+}
+
+void Arena::trim()
+{
+    for (auto &fb : free_blocks) {
+        void *p = fb.second;
+        if (pooled_ptrs.erase(p)) (void)hipFreeAsync(p, stream);
+        else (void)hipFree(p);
+        blocks.erase(p);
+    }
+    free_blocks.clear();
+    kept = 0;
 }
 
 int device_cu_count()
@@ -106,6 +172,7 @@ int skis_preprocess(int32_t n, int64_t m, const int32_t *row_ptr, const int32_t 
     return guarded([&]() -> int {
         check_graph_args(n, m, row_ptr, col, w);
         skis::Arena arena;
+        arena.stream = stream;
         skis::Prep prep;
         skis::preprocess(arena, n, m, row_ptr, col, w, thr || alias, prep, stream);
         if (P && m > 0)
@@ -157,6 +224,7 @@ int skis_build_sketch(int32_t n, int64_t m, const int32_t *row_ptr, const int32_
         try {
             skis::Sketch &sk = h->core;
             sk.arena.cap = opt.max_device_bytes;
+            sk.arena.stream = stream;
             sk.n = n;
             hipEvent_t e0, e1;
             SKIS_HIP_TRY(hipEventCreate(&e0));
@@ -204,6 +272,7 @@ int skis_build_sketch(int32_t n, int64_t m, const int32_t *row_ptr, const int32_
             }
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);
+            sk.arena.trim(); // the stages' temporaries go back to the device pool
             SKIS_HIP_TRY(hipStreamSynchronize(stream));
             *out = h;
             if (status == SKIS_WDEGENERATE) skis::set_error("Gamma = 0: no non-singular sample exists");
@@ -260,7 +329,9 @@ int skis_estimate(const skis_sketch *hc, int32_t num_sets, const int64_t *set_pt
         if (!set_ptr || !cov || !est) throw skis::Error{SKIS_EINVAL, "NULL argument"};
         if (!h->core.has_inverse) throw skis::Error{SKIS_EINVAL, "sketch was built without the inverse index"};
         std::lock_guard<std::mutex> lk(h->mu);
+        h->core.arena.stream = stream; // this call's scratch is allocated and released in its order
         skis::estimate_batch(h->core, h->qs, num_sets, set_ptr, set_nodes, cov, est, stream);
+        h->core.arena.trim();
         return SKIS_OK;
     });
 }
@@ -275,7 +346,9 @@ int skis_greedy_max_cover(const skis_sketch *hc, int32_t k, int32_t *seeds, uint
         if (!seeds || !marg || !cov_out || !est_out) throw skis::Error{SKIS_EINVAL, "NULL argument"};
         if (!h->core.has_inverse) throw skis::Error{SKIS_EINVAL, "sketch was built without the inverse index"};
         std::lock_guard<std::mutex> lk(h->mu);
+        h->core.arena.stream = stream;
         skis::greedy(h->core, h->qs, k, seeds, marg, cov_out, est_out, stream);
+        h->core.arena.trim();
         return SKIS_OK;
     });
 }
@@ -330,7 +403,15 @@ int skis_node_q(const skis_sketch *h, double *q, hipStream_t stream)
     });
 }
 
-void skis_sketch_free(skis_sketch *h) { delete h; }
+void skis_sketch_free(skis_sketch *h)
+{
+    if (!h) return;
+    // every call on the sketch has returned, but its buffers may have been used on any
+    // stream: release them in order behind all work on the device
+    (void)hipDeviceSynchronize();
+    h->core.arena.stream = nullptr;
+    delete h;
+}
 
 const char *skis_last_error(void) { return skis::get_error().c_str(); }
 

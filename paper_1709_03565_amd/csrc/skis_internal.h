@@ -3,7 +3,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
 #include <string>
+#include <unordered_map>
+#include <unordered_set>
 #include <vector>
 
 #include "skis.h"
@@ -33,11 +36,18 @@ const std::string &get_error();
 // Device allocations, tracked against an optional byte cap.
 // ---------------------------------------------------------------------------------
 struct Arena {
-    uint64_t cap = 0;   // 0 = unlimited
-    uint64_t used = 0;  // bytes currently held
+    uint64_t cap = 0;   // 0 = unlimited (counts live and kept blocks)
+    uint64_t used = 0;  // bytes currently held by live buffers
     uint64_t peak = 0;
+    uint64_t kept = 0;  // bytes of released blocks kept for reuse
+    hipStream_t stream = nullptr;              // allocations and releases are ordered on this stream
+    std::unordered_map<void *, size_t> blocks; // every block the arena owns -> its size
+    std::multimap<size_t, void *> free_blocks; // released blocks kept for reuse, by size
+    std::unordered_set<void *> pooled_ptrs;    // blocks from the stream-ordered pool
     void *alloc(size_t bytes);
     void release(void *p, size_t bytes);
+    void trim(); // returns the kept blocks to the device pool
+    ~Arena() { trim(); }
 };
 
 template <typename T>

@@ -23,7 +23,7 @@
 namespace skis {
 
 constexpr uint32_t DEFERRED = 0xFFFFFFFFu;
-constexpr int SMALL_SORT = 256;    // sizes up to this are sorted by one wave in k_gather_small
+constexpr int SMALL_SORT = 256;    // sizes up to this are sorted by one wave (k_gather_seg / k_gather_small)
 constexpr int SORT_LDS_MAX = 8192; // sizes up to this are sorted in LDS by k_gather_medium;
                                    // larger ones are written already sorted by the global tier
 // sample ids taken from the global counter at a time: at least the slots of a workgroup
@@ -590,22 +590,6 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
 // ---------------------------------------------------------------------------------------
 // Compaction: sort each sample and write it at sample_ptr[i].
 // ---------------------------------------------------------------------------------------
-__device__ __forceinline__ int32_t bitonic64(int32_t v)
-{
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int k = 2; k <= 64; k <<= 1) {
-#pragma unroll
-        for (int d = k >> 1; d > 0; d >>= 1) {
-            const int32_t o = __shfl_xor(v, d, 64);
-            const bool asc = (lane & k) == 0;
-            const bool low = (lane & d) == 0;
-            v = (low == asc) ? min(v, o) : max(v, o);
-        }
-    }
-    return v;
-}
-
 template <int NT>
 __device__ void bitonic_lds(int32_t *buf, int P)
 {
@@ -627,33 +611,140 @@ __device__ void bitonic_lds(int32_t *buf, int P)
     }
 }
 
-// 64-thread workgroups, one sample at a time; sizes above SMALL_SORT are left to
-// k_gather_medium.
-__global__ __launch_bounds__(64) void k_gather_small(uint64_t T, const uint32_t *__restrict__ size,
+// 64-thread workgroups, one sample of 65 .. SMALL_SORT nodes at a time (from the class
+// list); larger sizes are left to k_gather_medium.
+__global__ __launch_bounds__(64) void k_gather_small(const unsigned long long *__restrict__ counts,
+                                                     const uint32_t *__restrict__ lists,
+                                                     const uint32_t *__restrict__ size,
                                                      const unsigned long long *__restrict__ off,
                                                      const int64_t *__restrict__ sptr,
                                                      const int32_t *__restrict__ staging, int32_t *__restrict__ nodes)
 {
     __shared__ int32_t buf[SMALL_SORT];
     const int lane = threadIdx.x;
-    for (uint64_t i = blockIdx.x; i < T; i += gridDim.x) {
+    unsigned long long base = 0;
+    for (int k = 0; k < 4; ++k) base += counts[k];
+    const unsigned long long T = counts[4]; // the class of sizes 65 .. SMALL_SORT
+    for (uint64_t q = blockIdx.x; q < T; q += gridDim.x) {
+        const uint32_t i = lists[base + q];
         const int sz = (int)size[i];
         if (sz > SMALL_SORT) continue;
         const int32_t *src = staging + off[i];
         int32_t *dst = nodes + sptr[i];
-        if (sz <= 64) {
-            int32_t v = lane < sz ? src[lane] : INT32_MAX;
-            v = bitonic64(v);
-            if (lane < sz) dst[lane] = v;
-        } else {
-            int P = 128;
-            while (P < sz) P <<= 1;
-            for (int t = lane; t < P; t += 64) buf[t] = t < sz ? src[t] : INT32_MAX;
-            __syncthreads();
-            bitonic_lds<64>(buf, P);
-            for (int t = lane; t < sz; t += 64) dst[t] = buf[t];
-            __syncthreads();
+        int P = 128;
+        while (P < sz) P <<= 1;
+        for (int t = lane; t < P; t += 64) buf[t] = t < sz ? src[t] : INT32_MAX;
+        __syncthreads();
+        bitonic_lds<64>(buf, P);
+        for (int t = lane; t < sz; t += 64) dst[t] = buf[t];
+        __syncthreads();
+    }
+}
+
+// Size classes for the segmented sorts: class c < 3 holds sizes up to 8 << c (segments of
+// 8, 16 or 32 lanes), class 3 sizes up to 64 (a whole wave), class 4 sizes up to SMALL_SORT.
+constexpr int GATHER_CLASSES = 5;
+
+__device__ __forceinline__ int size_class(uint32_t sz)
+{
+    return sz <= 8 ? 0 : sz <= 16 ? 1 : sz <= 32 ? 2 : sz <= 64 ? 3 : 4;
+}
+
+// counts[c] = samples of class c (samples above SMALL_SORT are listed by the sampler)
+__global__ __launch_bounds__(256) void k_class_count(uint64_t T, const uint32_t *__restrict__ size,
+                                                     unsigned long long *__restrict__ counts)
+{
+    unsigned long long c[GATHER_CLASSES] = {};
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < T; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t sz = size[i];
+        if (sz <= SMALL_SORT) c[size_class(sz)] += 1;
+    }
+#pragma unroll
+    for (int k = 0; k < GATHER_CLASSES; ++k) {
+        const unsigned long long t = wave_sum(c[k]);
+        if ((threadIdx.x & 63) == 0 && t) atomicAdd(&counts[k], t);
+    }
+}
+
+// lists[base(c) + ...] = the samples of class c, base(c) = counts of the classes before c.
+// Each workgroup takes CLASS_CHUNK consecutive samples, counts their classes in LDS,
+// reserves its range of every class list with one atomic per class, then places them.
+constexpr int CLASS_CHUNK = 4096;
+
+__global__ __launch_bounds__(256) void k_class_fill(uint64_t T, const uint32_t *__restrict__ size,
+                                                    const unsigned long long *__restrict__ counts,
+                                                    unsigned long long *__restrict__ cursor,
+                                                    uint32_t *__restrict__ lists)
+{
+    __shared__ uint32_t lc[GATHER_CLASSES];
+    __shared__ unsigned long long lb[GATHER_CLASSES];
+    unsigned long long base[GATHER_CLASSES];
+    unsigned long long acc = 0;
+#pragma unroll
+    for (int k = 0; k < GATHER_CLASSES; ++k) {
+        base[k] = acc;
+        acc += counts[k];
+    }
+    for (uint64_t c0 = (uint64_t)blockIdx.x * CLASS_CHUNK; c0 < T; c0 += (uint64_t)gridDim.x * CLASS_CHUNK) {
+        const uint64_t c1 = min(c0 + CLASS_CHUNK, T);
+        if (threadIdx.x < GATHER_CLASSES) lc[threadIdx.x] = 0u;
+        __syncthreads();
+        for (uint64_t i = c0 + threadIdx.x; i < c1; i += 256) {
+            const uint32_t sz = size[i];
+            if (sz <= SMALL_SORT) atomicAdd(&lc[size_class(sz)], 1u);
         }
+        __syncthreads();
+        if (threadIdx.x < GATHER_CLASSES) {
+            const uint32_t x = lc[threadIdx.x];
+            lb[threadIdx.x] = x ? atomicAdd(&cursor[threadIdx.x], (unsigned long long)x) : 0ull;
+            lc[threadIdx.x] = 0u;
+        }
+        __syncthreads();
+        for (uint64_t i = c0 + threadIdx.x; i < c1; i += 256) {
+            const uint32_t sz = size[i];
+            if (sz <= SMALL_SORT) {
+                const int c = size_class(sz);
+                lists[base[c] + lb[c] + atomicAdd(&lc[c], 1u)] = (uint32_t)i;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// W-lane segments of one wave each sort one sample of class W (64 / W samples per step):
+// bitonic network within the segment, padded with INT32_MAX.
+template <int W>
+__global__ __launch_bounds__(64) void k_gather_seg(int cls, const unsigned long long *__restrict__ counts,
+                                                   const uint32_t *__restrict__ lists,
+                                                   const uint32_t *__restrict__ size,
+                                                   const unsigned long long *__restrict__ off,
+                                                   const int64_t *__restrict__ sptr,
+                                                   const int32_t *__restrict__ staging, int32_t *__restrict__ nodes)
+{
+    constexpr int G = 64 / W;
+    const int lane = threadIdx.x, seg = lane / W, t = lane % W;
+    unsigned long long base = 0;
+    for (int k = 0; k < cls; ++k) base += counts[k];
+    const unsigned long long cnt = counts[cls];
+    for (unsigned long long g0 = (unsigned long long)blockIdx.x * G; g0 < cnt; g0 += (unsigned long long)gridDim.x * G) {
+        const unsigned long long gi = g0 + seg;
+        uint32_t i = 0, sz = 0;
+        if (gi < cnt) {
+            i = lists[base + gi];
+            sz = size[i];
+        }
+        int32_t v = (t < (int)sz) ? staging[off[i] + t] : INT32_MAX;
+#pragma unroll
+        for (int k = 2; k <= W; k <<= 1) {
+#pragma unroll
+            for (int d = k >> 1; d > 0; d >>= 1) {
+                const int32_t o = __shfl_xor(v, d, 64);
+                const bool asc = (t & k) == 0;
+                const bool low = (t & d) == 0;
+                v = (low == asc) ? min(v, o) : max(v, o);
+            }
+        }
+        if (t < (int)sz) nodes[sptr[i] + t] = v;
     }
 }
 
@@ -1224,9 +1315,31 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
     SKIS_HIP_TRY(hipStreamSynchronize(s));
     sk.entries = (uint64_t)total;
     sk.nodes.alloc(arena, (size_t)total);
-    hipLaunchKernelGGL(k_gather_small, dim3(grid_cap(count, 1, 64)), dim3(64), 0, s, (uint64_t)count, out_size.ptr,
-                       out_off.ptr, sk.sample_ptr.ptr, staging.ptr, sk.nodes.ptr);
-    SKIS_HIP_TRY(hipGetLastError());
+    {
+        // samples by size class, then one segmented sort per class
+        DevBuf<unsigned long long> cls;
+        DevBuf<uint32_t> lists;
+        cls.alloc(arena, 2 * GATHER_CLASSES);
+        lists.alloc(arena, count);
+        hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(1), dim3(64), 0, s, (uint64_t)(2 * GATHER_CLASSES),
+                           cls.ptr, 0ull);
+        hipLaunchKernelGGL(k_class_count, dim3(grid_cap(count, 256)), dim3(256), 0, s, (uint64_t)count, out_size.ptr,
+                           cls.ptr);
+        hipLaunchKernelGGL(k_class_fill, dim3(grid_cap(count, CLASS_CHUNK, 8)), dim3(256), 0, s, (uint64_t)count,
+                           out_size.ptr, cls.ptr, cls.ptr + GATHER_CLASSES, lists.ptr);
+        const unsigned gg = grid_cap(count, 8, 64);
+        hipLaunchKernelGGL(k_gather_seg<8>, dim3(gg), dim3(64), 0, s, 0, cls.ptr, lists.ptr, out_size.ptr, out_off.ptr,
+                           sk.sample_ptr.ptr, staging.ptr, sk.nodes.ptr);
+        hipLaunchKernelGGL(k_gather_seg<16>, dim3(gg), dim3(64), 0, s, 1, cls.ptr, lists.ptr, out_size.ptr,
+                           out_off.ptr, sk.sample_ptr.ptr, staging.ptr, sk.nodes.ptr);
+        hipLaunchKernelGGL(k_gather_seg<32>, dim3(gg), dim3(64), 0, s, 2, cls.ptr, lists.ptr, out_size.ptr,
+                           out_off.ptr, sk.sample_ptr.ptr, staging.ptr, sk.nodes.ptr);
+        hipLaunchKernelGGL(k_gather_seg<64>, dim3(gg), dim3(64), 0, s, 3, cls.ptr, lists.ptr, out_size.ptr,
+                           out_off.ptr, sk.sample_ptr.ptr, staging.ptr, sk.nodes.ptr);
+        hipLaunchKernelGGL(k_gather_small, dim3(grid_cap(count, 1, 64)), dim3(64), 0, s, cls.ptr, lists.ptr,
+                           out_size.ptr, out_off.ptr, sk.sample_ptr.ptr, staging.ptr, sk.nodes.ptr);
+        SKIS_HIP_TRY(hipGetLastError());
+    }
     if (hc.n_medium > 0) {
         hipLaunchKernelGGL(k_gather_medium, dim3(grid_cap(hc.n_medium, 1, 4)), dim3(256), 0, s,
                            (uint64_t)hc.n_medium, medium.ptr, out_size.ptr, out_off.ptr, sk.sample_ptr.ptr,

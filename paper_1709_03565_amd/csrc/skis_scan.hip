@@ -124,8 +124,8 @@ static void scan_impl(Arena &arena, const S *in, D *out, int64_t n, T *d_total, 
                            part.ptr);
         SKIS_HIP_TRY(hipGetLastError());
     }
-    // `part` is released on return; hipFree synchronises the device first, so the
-    // kernels queued above have finished with it.
+    // `part` is released on return, ordered on the arena's stream after the kernels above
+    // (or by a synchronising free when the device has no memory pool).
 }
 
 template <typename T>

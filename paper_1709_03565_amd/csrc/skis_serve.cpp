@@ -361,6 +361,7 @@ int skis_server_create(const skis_sketch *sk, const skis_server_options *opt_in,
                                    hipMemcpyDeviceToHost));
         }
         const uint64_t nb = std::max<uint64_t>(opt.max_batch_queries, opt.max_large_sets);
+        sv->arena.stream = nullptr; // allocations complete before any slot stream uses them (below)
         for (uint32_t i = 0; i < opt.pipeline_depth; ++i) {
             sv->slots.push_back(std::make_unique<Slot>());
             Slot &s = *sv->slots.back();
@@ -380,6 +381,7 @@ int skis_server_create(const skis_sketch *sk, const skis_server_options *opt_in,
             s.d_err.alloc(sv->arena, 1);
             s.bitmaps.alloc(sv->arena, nb * sv->wordsT);
             s.nodebits.alloc(sv->arena, (uint64_t)opt.max_large_sets * sv->wordsN);
+            SKIS_HIP_TRY(hipDeviceSynchronize());
             skis::fill_u32(s.bitmaps.ptr, nb * sv->wordsT, s.stream);
             skis::fill_u32(s.nodebits.ptr, (uint64_t)opt.max_large_sets * sv->wordsN, s.stream);
             skis::fill_u32(reinterpret_cast<uint32_t *>(s.d_err.ptr), 1, s.stream);
