@@ -442,7 +442,11 @@ __global__ __launch_bounds__(256) void k_greedy_argmax(int32_t n, int round, uin
     }
 }
 
-// Covers H(v*): lists every sample whose covered bit flips (one list append per wave).
+// Covers H(v*): lists every sample whose covered bit flips.  H(v*) is in ascending sample
+// order, so each lane takes a run of MARK_RUN consecutive entries and sets the bits of one
+// bitmap word with one atomicOr; the newly covered samples are appended once per wave.
+constexpr int MARK_RUN = 8;
+
 __global__ __launch_bounds__(256) void k_greedy_mark(const GreedyState *__restrict__ st,
                                                      const int64_t *__restrict__ node_ptr,
                                                      const int32_t *__restrict__ node_samples,
@@ -453,27 +457,106 @@ __global__ __launch_bounds__(256) void k_greedy_mark(const GreedyState *__restri
     if (v < 0) return;
     const int64_t a = node_ptr[v], b = node_ptr[v + 1];
     const int lane = threadIdx.x & 63;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t p0 = a + (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); p0 < b; p0 += stride) {
-        const int64_t p = p0 + lane;
-        bool fresh = false;
-        int32_t j = 0;
-        if (p < b) {
-            j = node_samples[p];
-            const uint32_t bit = 1u << (j & 31);
-            fresh = !(atomicOr(&covered[j >> 5], bit) & bit);
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t c0 = a + wave * 64 * MARK_RUN; c0 < b; c0 += nwaves * 64 * MARK_RUN) {
+        const int64_t r0 = c0 + (int64_t)lane * MARK_RUN;
+        int32_t js[MARK_RUN];
+        int n = 0;
+#pragma unroll
+        for (int k = 0; k < MARK_RUN; ++k) {
+            js[k] = r0 + k < b ? node_samples[r0 + k] : -1;
+            n += js[k] >= 0 ? 1 : 0;
         }
-        const unsigned long long m = __ballot(fresh);
-        if (!m) continue;
+        uint32_t fresh = 0; // bit k: js[k] newly covered
+        int k = 0;
+        while (k < n) { // one word at a time
+            const int32_t word = js[k] >> 5;
+            uint32_t bits = 0;
+            int k1 = k;
+            while (k1 < n && (js[k1] >> 5) == word) bits |= 1u << (js[k1++] & 31);
+            const uint32_t newb = bits & ~atomicOr(&covered[word], bits);
+            for (int t = k; t < k1; ++t)
+                if (newb & (1u << (js[t] & 31))) fresh |= 1u << t;
+            k = k1;
+        }
+        const int cnt = __popc(fresh);
+        const int incl = wave_incl_scan(cnt);
+        const int tot = __shfl(incl, 63, 64);
+        if (!tot) continue;
         unsigned long long base = 0;
-        if (lane == 0) base = atomicAdd(listed, (unsigned long long)__popcll(m));
-        base = __shfl(base, 0, 64);
-        if (fresh) list[base + __popcll(m & ((1ull << lane) - 1ull))] = (uint32_t)j;
+        if (lane == 0) base = atomicAdd(listed, (unsigned long long)tot);
+        base = __shfl(base, 0, 64) + (unsigned long long)(incl - cnt);
+#pragma unroll
+        for (int t = 0; t < MARK_RUN; ++t)
+            if (fresh & (1u << t)) list[base++] = (uint32_t)js[t];
+    }
+}
+
+// A round that covers more than T / RECOUNT_DIV samples recounts Delta of every node from
+// its list instead of decrementing the members of each newly covered sample.
+constexpr uint64_t RECOUNT_DIV = 32;
+constexpr int RECOUNT_SPAN = 2048; // list entries per recount work item
+
+__device__ __forceinline__ bool heavy_round(const GreedyState *st, uint64_t T)
+{
+    return st->vstar >= 0 && st->listed > T / RECOUNT_DIV;
+}
+
+// Work items for the recount: each node's list cut into spans of RECOUNT_SPAN entries.
+__global__ __launch_bounds__(256) void k_recount_items_count(int32_t n, const int64_t *__restrict__ node_ptr,
+                                                             uint32_t *__restrict__ nitems)
+{
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t d = node_ptr[v + 1] - node_ptr[v];
+        nitems[v] = (uint32_t)((d + RECOUNT_SPAN - 1) / RECOUNT_SPAN);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_recount_items_fill(int32_t n, const uint32_t *__restrict__ nitems,
+                                                            const int64_t *__restrict__ ioff, int2 *__restrict__ items)
+{
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        for (uint32_t c = 0; c < nitems[v]; ++c) items[ioff[v] + c] = make_int2((int32_t)v, (int32_t)c);
+}
+
+__global__ __launch_bounds__(256) void k_recount_zero(const GreedyState *__restrict__ st, uint64_t T, int32_t n,
+                                                      int32_t *__restrict__ delta)
+{
+    if (!heavy_round(st, T)) return;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        delta[v] = 0;
+}
+
+// delta[v] += #{ j in span : j not covered }, one wave per span
+__global__ __launch_bounds__(256) void k_greedy_recount(const GreedyState *__restrict__ st, uint64_t T,
+                                                        uint64_t nitems, const int2 *__restrict__ items,
+                                                        const int64_t *__restrict__ node_ptr,
+                                                        const int32_t *__restrict__ node_samples,
+                                                        const uint32_t *__restrict__ covered,
+                                                        int32_t *__restrict__ delta)
+{
+    if (!heavy_round(st, T)) return;
+    const int lane = threadIdx.x & 63;
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    for (uint64_t it = wave; it < nitems; it += nwaves) {
+        const int2 w = items[it];
+        const int64_t e = node_ptr[w.x + 1];
+        const int64_t p0 = node_ptr[w.x] + (int64_t)w.y * RECOUNT_SPAN;
+        const int64_t p1 = min(e, p0 + (int64_t)RECOUNT_SPAN);
+        int c = 0;
+        for (int64_t p = p0 + lane; p < p1; p += 64) {
+            const int32_t j = node_samples[p];
+            c += (covered[j >> 5] >> (j & 31)) & 1u ? 0 : 1;
+        }
+        c = wave_sum(c);
+        if (lane == 0 && c) atomicAdd(&delta[w.x], c);
     }
 }
 
 // Lowers delta of every member of every newly covered sample.
-__global__ __launch_bounds__(256) void k_greedy_decrement(const GreedyState *__restrict__ st,
+__global__ __launch_bounds__(256) void k_greedy_decrement(const GreedyState *__restrict__ st, uint64_t T,
                                                           const uint32_t *__restrict__ list,
                                                           const int64_t *__restrict__ sptr,
                                                           const int32_t *__restrict__ nodes,
@@ -482,7 +565,7 @@ __global__ __launch_bounds__(256) void k_greedy_decrement(const GreedyState *__r
                                                           int32_t *__restrict__ delta)
 {
     __shared__ int32_t hd[GREEDY_HOT];
-    if (st->vstar < 0) return;
+    if (st->vstar < 0 || heavy_round(st, T)) return;
     const uint64_t cnt = st->listed;
     for (int h = threadIdx.x; h < nhot; h += 256) hd[h] = 0;
     __syncthreads();
@@ -701,14 +784,39 @@ void greedy(const Sketch &sk, QueryScratch &qs, int32_t k, int32_t *seeds, uint6
     const unsigned gu = (unsigned)device_cu_count() * 4;
     const int nhot = std::min<int>(sk.nhot, GREEDY_HOT);
     const int32_t *hot_id = nhot > 0 ? sk.hot_id.ptr : nullptr;
+    // recount work items (used by the rounds that cover many samples)
+    DevBuf<uint32_t> nitems;
+    DevBuf<int64_t> ioff;
+    DevBuf<int2> items;
+    uint64_t nit = 0;
+    if (sk.T) {
+        nitems.alloc(arena, n);
+        ioff.alloc(arena, (size_t)n + 1);
+        hipLaunchKernelGGL(k_recount_items_count, dim3(gridq(n, 256)), dim3(256), 0, s, n, sk.node_ptr.ptr,
+                           nitems.ptr);
+        excl_scan_u32_to_i64(arena, nitems.ptr, ioff.ptr, n, ioff.ptr + n, s);
+        int64_t hn = 0;
+        SKIS_HIP_TRY(hipMemcpyAsync(&hn, ioff.ptr + n, sizeof(hn), hipMemcpyDeviceToHost, s));
+        SKIS_HIP_TRY(hipStreamSynchronize(s));
+        nit = (uint64_t)hn;
+        items.alloc(arena, nit ? nit : 1);
+        hipLaunchKernelGGL(k_recount_items_fill, dim3(gridq(n, 256)), dim3(256), 0, s, n, nitems.ptr, ioff.ptr,
+                           items.ptr);
+        SKIS_HIP_TRY(hipGetLastError());
+    }
+    const unsigned gr = gridq(nit * 64, 256, 8);
     for (int32_t r = 0; r < k; ++r) {
         hipLaunchKernelGGL(k_greedy_argmax, dim3(ga), dim3(256), 0, s, n, (int)r, sk.T, sk.Gamma, delta.ptr, sk.q.ptr,
                            chosen.ptr, pg.ptr, pv.ptr, st.ptr, seeds, reinterpret_cast<unsigned long long *>(marg));
         if (sk.T) {
             hipLaunchKernelGGL(k_greedy_mark, dim3(gu), dim3(256), 0, s, st.ptr, sk.node_ptr.ptr, sk.node_samples.ptr,
                                covered.ptr, list.ptr, &st.ptr->listed);
-            hipLaunchKernelGGL(k_greedy_decrement, dim3(gu), dim3(256), 0, s, st.ptr, list.ptr, sk.sample_ptr.ptr,
-                               sk.nodes.ptr, hot_id, sk.hot_node.ptr, nhot, delta.ptr);
+            // exactly one of the two updates does work, decided on the device from the count
+            hipLaunchKernelGGL(k_greedy_decrement, dim3(gu), dim3(256), 0, s, st.ptr, sk.T, list.ptr,
+                               sk.sample_ptr.ptr, sk.nodes.ptr, hot_id, sk.hot_node.ptr, nhot, delta.ptr);
+            hipLaunchKernelGGL(k_recount_zero, dim3(gridq(n, 256)), dim3(256), 0, s, st.ptr, sk.T, n, delta.ptr);
+            hipLaunchKernelGGL(k_greedy_recount, dim3(gr), dim3(256), 0, s, st.ptr, sk.T, nit, items.ptr,
+                               sk.node_ptr.ptr, sk.node_samples.ptr, covered.ptr, delta.ptr);
         }
     }
     SKIS_HIP_TRY(hipGetLastError());
