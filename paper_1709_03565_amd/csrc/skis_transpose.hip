@@ -7,8 +7,9 @@
 //   k_rs_hist     digit counts per tile, stored digit-major (H[d * ntiles + tile]), so one
 //                 exclusive scan of H gives every (tile, digit) its output offset;
 //   k_rs_scatter  each wave ranks its entries among equal digits with 8 ballots (lanes in
-//                 order), the waves of a tile are ordered by a prefix of their counts, and
-//                 every entry is written at its offset: the sort is stable.
+//                 order), the waves of a tile are ordered by a prefix of their counts, the
+//                 tile is sorted by digit in LDS (stable) and written out in order, so each
+//                 digit's run of the tile goes to its offset with consecutive lanes.
 // The input is in sample order, so every list H(v) comes out sorted by sample id.
 // k_rs_bounds then finds where each node's run starts.
 #include <algorithm>
@@ -77,16 +78,20 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(uint64_t N, const int32
                                                          int32_t *__restrict__ vout, int shift, uint64_t ntiles,
                                                          const int64_t *__restrict__ OFF)
 {
-    __shared__ long long base[256];
-    __shared__ uint32_t cnt[RS_WAVES][256]; // phase 1: counts; then the running write index
-    __shared__ int32_t sk[RS_WAVES][RS_SPAN], sv[RS_WAVES][RS_SPAN]; // each wave's span
+    __shared__ long long base[256];        // output offset of each digit for this tile
+    __shared__ uint32_t tstart[256 + 1];   // first tile-local position of each digit
+    __shared__ uint32_t cnt[RS_WAVES][256]; // per-wave digit counts, then each wave's running index
+    __shared__ int32_t sk[RS_TILE], sv[RS_TILE]; // the tile, then the tile sorted by digit
+    __shared__ uint32_t s_scan[RS_WAVES + 1];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const unsigned long long lt = (1ull << lane) - 1ull;
     constexpr int R = RS_SPAN / 64;
     for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         base[threadIdx.x] = OFF[(uint64_t)threadIdx.x * ntiles + tile];
         for (int i = threadIdx.x; i < RS_WAVES * 256; i += RS_BLOCK) (&cnt[0][0])[i] = 0u;
-        const uint64_t s0 = tile * RS_TILE + (uint64_t)w * RS_SPAN;
+        const uint64_t t0 = tile * RS_TILE;
+        const uint64_t s0 = t0 + (uint64_t)w * RS_SPAN;
+        const int nvalid = (int)min((uint64_t)RS_TILE, N - t0);
         {
             // the wave's span: all loads in flight at once, then staged in LDS
             int32_t kr[R], vr[R];
@@ -98,15 +103,15 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(uint64_t N, const int32
             }
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                sk[w][r * 64 + lane] = kr[r];
-                sv[w][r * 64 + lane] = vr[r];
+                sk[w * RS_SPAN + r * 64 + lane] = kr[r];
+                sv[w * RS_SPAN + r * 64 + lane] = vr[r];
             }
         }
         __syncthreads();
         // phase 1: this wave's digit counts (one leader per digit and round adds)
         for (int r = 0; r < R; ++r) {
             const bool valid = s0 + (uint64_t)r * 64 + lane < N;
-            const uint32_t d = valid ? (((uint32_t)sk[w][r * 64 + lane] >> shift) & 255u) : 0u;
+            const uint32_t d = valid ? (((uint32_t)sk[w * RS_SPAN + r * 64 + lane] >> shift) & 255u) : 0u;
             const unsigned long long m = same_digit_mask(valid, d);
             if (valid && !(m & lt)) cnt[w][d] += (uint32_t)__popcll(m);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -114,7 +119,7 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(uint64_t N, const int32
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
         __syncthreads();
-        // waves in order: wave w starts each digit after the entries of waves < w
+        // digit d of the tile: its waves in order, after the digits below d
         {
             const int d = threadIdx.x;
             uint32_t acc = 0;
@@ -123,19 +128,23 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(uint64_t N, const int32
                 cnt[k][d] = acc;
                 acc += x;
             }
+            uint32_t tot;
+            const uint32_t ex = block_excl_scan<RS_BLOCK, uint32_t>(acc, s_scan, &tot);
+            tstart[d] = ex;
+            if (d == 255) tstart[256] = tot;
+            for (int k = 0; k < RS_WAVES; ++k) cnt[k][d] += ex;
         }
         __syncthreads();
-        // phase 2: ranks in lane order, writes
+        // phase 2: tile-local positions (stable), kept in registers until every wave has read
+        int32_t kr[R], vr[R];
+        uint32_t lp[R];
         for (int r = 0; r < R; ++r) {
             const bool valid = s0 + (uint64_t)r * 64 + lane < N;
-            const int32_t key = sk[w][r * 64 + lane];
-            const uint32_t d = valid ? (((uint32_t)key >> shift) & 255u) : 0u;
+            kr[r] = sk[w * RS_SPAN + r * 64 + lane];
+            vr[r] = sv[w * RS_SPAN + r * 64 + lane];
+            const uint32_t d = valid ? (((uint32_t)kr[r] >> shift) & 255u) : 0u;
             const unsigned long long m = same_digit_mask(valid, d);
-            if (valid) {
-                const long long pos = base[d] + (long long)cnt[w][d] + __popcll(m & lt);
-                kout[pos] = key;
-                vout[pos] = sv[w][r * 64 + lane];
-            }
+            lp[r] = valid ? cnt[w][d] + (uint32_t)__popcll(m & lt) : 0xFFFFFFFFu;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -143,6 +152,21 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(uint64_t N, const int32
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        __syncthreads();
+        for (int r = 0; r < R; ++r)
+            if (lp[r] != 0xFFFFFFFFu) {
+                sk[lp[r]] = kr[r];
+                sv[lp[r]] = vr[r];
+            }
+        __syncthreads();
+        // phase 3: the sorted tile goes out in order, each digit's run to its offset
+        for (int i = threadIdx.x; i < nvalid; i += RS_BLOCK) {
+            const int32_t key = sk[i];
+            const uint32_t d = ((uint32_t)key >> shift) & 255u;
+            const long long pos = base[d] + (long long)(i - (int)tstart[d]);
+            kout[pos] = key;
+            vout[pos] = sv[i];
         }
         __syncthreads();
     }
