@@ -48,9 +48,17 @@ struct SplitScratch {
 struct GreedyState {
     unsigned done;              // blocks of k_greedy_argmax that have finished
     int32_t vstar;              // this round's pick (-1: none left)
+    unsigned shrunk;            // a heavy round has cut the lists down (they are in the work copy)
     unsigned long long listed;  // samples newly covered this round
     unsigned long long cov;     // coverage of the picks so far
     double est;
+};
+
+// One recount work item: entries [p0, p0 + len) of node v's list.
+struct RecountItem {
+    int64_t p0;
+    int32_t len;
+    int32_t v;
 };
 
 // Per-sketch scratch for estimate: one bitmap of T bits per query in flight.

@@ -345,6 +345,18 @@ __global__ __launch_bounds__(256) void k_est_split_finish(EstSplit *__restrict__
 // workgroup and flushed once, so hubs do not serialise on one counter.  Integer updates
 // commute, so delta and the picks are exact.
 // ---------------------------------------------------------------------------------------
+// A round that covers more than T / RECOUNT_DIV samples recounts Delta of every node from
+// its list instead of decrementing the members of each newly covered sample.
+constexpr uint64_t RECOUNT_DIV = 32;
+constexpr int RECOUNT_SPAN = 1024; // list entries per recount work item
+constexpr int RECOUNT_LANES = 16;  // lanes per work item
+constexpr int RECOUNT_UNROLL = 8;  // loads in flight per lane
+
+__device__ __forceinline__ bool heavy_round(const GreedyState *st, uint64_t T)
+{
+    return st->vstar >= 0 && st->listed > T / RECOUNT_DIV;
+}
+
 __device__ __forceinline__ double gain_of(int64_t d, uint64_t T, double Gamma, double q)
 {
     return __dadd_rn(T > 0 ? __ddiv_rn(__dmul_rn((double)d, Gamma), (double)T) : 0.0, q);
@@ -364,25 +376,44 @@ __global__ __launch_bounds__(256) void k_greedy_init(int32_t n, const int64_t *_
     }
 }
 
-// Block-wide (g, v) reduction in LDS; every thread gets the winner.
+// (g, v) maximum under the order "larger gain, then smaller id" (a total order on the
+// valid pairs, so any reduction tree gives the same winner); v < 0 marks an empty slot.
+__device__ __forceinline__ void wave_best(double &g, int32_t &v)
+{
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+        const double og = __shfl_xor(g, d, 64);
+        const int32_t ov = __shfl_xor(v, d, 64);
+        if (ov >= 0 && better(og, ov, g, v)) {
+            g = og;
+            v = ov;
+        }
+    }
+}
+
+// Workgroup-wide winner of 256 threads; every thread gets it.
 __device__ __forceinline__ void block_best(double &g, int32_t &v, double *sg, int32_t *sv)
 {
-    sg[threadIdx.x] = g;
-    sv[threadIdx.x] = v;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) {
-            const int o = threadIdx.x + w;
-            if (sv[o] >= 0 && better(sg[o], sv[o], sg[threadIdx.x], sv[threadIdx.x])) {
-                sg[threadIdx.x] = sg[o];
-                sv[threadIdx.x] = sv[o];
-            }
-        }
-        __syncthreads();
+    wave_best(g, v);
+    if ((threadIdx.x & 63) == 0) {
+        sg[threadIdx.x >> 6] = g;
+        sv[threadIdx.x >> 6] = v;
     }
+    __syncthreads();
     g = sg[0];
     v = sv[0];
+#pragma unroll
+    for (int w = 1; w < 4; ++w)
+        if (sv[w] >= 0 && better(sg[w], sv[w], g, v)) {
+            g = sg[w];
+            v = sv[w];
+        }
+    __syncthreads();
 }
+
+// Each thread scans ARGMAX_PER nodes of its workgroup's tile, all loads issued before the
+// gains are formed; the last workgroup to finish reduces the per-workgroup winners.
+constexpr int ARGMAX_PER = 16;
 
 __global__ __launch_bounds__(256) void k_greedy_argmax(int32_t n, int round, uint64_t T, double Gamma,
                                                        const int32_t *__restrict__ delta, const double *__restrict__ qv,
@@ -391,17 +422,33 @@ __global__ __launch_bounds__(256) void k_greedy_argmax(int32_t n, int round, uin
                                                        int32_t *__restrict__ seeds,
                                                        unsigned long long *__restrict__ marg)
 {
-    __shared__ double sg[256];
-    __shared__ int32_t sv[256];
+    __shared__ double sg[4];
+    __shared__ int32_t sv[4];
     __shared__ bool last;
     double bg = 0.0;
     int32_t bv = -1;
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-        if (chosen[v]) continue;
-        const double g = gain_of(delta[v], T, Gamma, qv[v]);
-        if (better(g, (int32_t)v, bg, bv)) {
-            bg = g;
-            bv = (int32_t)v;
+    for (int64_t v0 = (int64_t)blockIdx.x * 256 * ARGMAX_PER + threadIdx.x; v0 < n;
+         v0 += (int64_t)gridDim.x * 256 * ARGMAX_PER) {
+        int32_t d[ARGMAX_PER];
+        double q[ARGMAX_PER];
+        uint8_t c[ARGMAX_PER];
+#pragma unroll
+        for (int u = 0; u < ARGMAX_PER; ++u) {
+            const int64_t v = v0 + (int64_t)u * 256;
+            const bool in = v < n;
+            c[u] = in ? chosen[v] : (uint8_t)1;
+            d[u] = in ? delta[v] : 0;
+            q[u] = in ? qv[v] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < ARGMAX_PER; ++u) {
+            if (c[u]) continue;
+            const int32_t v = (int32_t)(v0 + (int64_t)u * 256);
+            const double g = gain_of(d[u], T, Gamma, q[u]);
+            if (better(g, v, bg, bv)) {
+                bg = g;
+                bv = v;
+            }
         }
     }
     block_best(bg, bv, sg, sv);
@@ -428,6 +475,7 @@ __global__ __launch_bounds__(256) void k_greedy_argmax(int32_t n, int round, uin
     block_best(bg, bv, sg, sv);
     if (threadIdx.x == 0) {
         st->done = 0u;
+        if (heavy_round(st, T)) st->shrunk = 1u; // the previous round rewrote the spans
         st->listed = 0ull;
         if (bv < 0) { // nothing left to pick (cannot happen for k <= n)
             st->vstar = -1;
@@ -493,16 +541,6 @@ __global__ __launch_bounds__(256) void k_greedy_mark(const GreedyState *__restri
     }
 }
 
-// A round that covers more than T / RECOUNT_DIV samples recounts Delta of every node from
-// its list instead of decrementing the members of each newly covered sample.
-constexpr uint64_t RECOUNT_DIV = 32;
-constexpr int RECOUNT_SPAN = 2048; // list entries per recount work item
-
-__device__ __forceinline__ bool heavy_round(const GreedyState *st, uint64_t T)
-{
-    return st->vstar >= 0 && st->listed > T / RECOUNT_DIV;
-}
-
 // Work items for the recount: each node's list cut into spans of RECOUNT_SPAN entries.
 __global__ __launch_bounds__(256) void k_recount_items_count(int32_t n, const int64_t *__restrict__ node_ptr,
                                                              uint32_t *__restrict__ nitems)
@@ -513,11 +551,21 @@ __global__ __launch_bounds__(256) void k_recount_items_count(int32_t n, const in
     }
 }
 
-__global__ __launch_bounds__(256) void k_recount_items_fill(int32_t n, const uint32_t *__restrict__ nitems,
-                                                            const int64_t *__restrict__ ioff, int2 *__restrict__ items)
+__global__ __launch_bounds__(256) void k_recount_items_fill(int32_t n, const int64_t *__restrict__ node_ptr,
+                                                            const uint32_t *__restrict__ nitems,
+                                                            const int64_t *__restrict__ ioff,
+                                                            RecountItem *__restrict__ items)
 {
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
-        for (uint32_t c = 0; c < nitems[v]; ++c) items[ioff[v] + c] = make_int2((int32_t)v, (int32_t)c);
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t a = node_ptr[v], d = node_ptr[v + 1] - a;
+        for (uint32_t c = 0; c < nitems[v]; ++c) {
+            RecountItem w;
+            w.p0 = a + (int64_t)c * RECOUNT_SPAN;
+            w.len = (int32_t)min<int64_t>(RECOUNT_SPAN, d - (int64_t)c * RECOUNT_SPAN);
+            w.v = (int32_t)v;
+            items[ioff[v] + c] = w;
+        }
+    }
 }
 
 __global__ __launch_bounds__(256) void k_recount_zero(const GreedyState *__restrict__ st, uint64_t T, int32_t n,
@@ -528,30 +576,55 @@ __global__ __launch_bounds__(256) void k_recount_zero(const GreedyState *__restr
         delta[v] = 0;
 }
 
-// delta[v] += #{ j in span : j not covered }, one wave per span
+// delta[v] += #{ j in span : j not covered }, and the span is cut down to those samples:
+// the first heavy round reads node v's list from the sketch and writes the uncovered part
+// to the same offsets of `work`; later heavy rounds read and rewrite `work` in place (a kept
+// entry only moves to a lower position, after every load of its batch).  The order within
+// a span stays ascending.  RECOUNT_LANES lanes per span, RECOUNT_UNROLL list loads and then
+// as many bitmap loads in flight per lane.
 __global__ __launch_bounds__(256) void k_greedy_recount(const GreedyState *__restrict__ st, uint64_t T,
-                                                        uint64_t nitems, const int2 *__restrict__ items,
-                                                        const int64_t *__restrict__ node_ptr,
-                                                        const int32_t *__restrict__ node_samples,
+                                                        uint64_t nitems, RecountItem *__restrict__ items,
+                                                        const int32_t *node_samples, int32_t *work,
                                                         const uint32_t *__restrict__ covered,
                                                         int32_t *__restrict__ delta)
 {
     if (!heavy_round(st, T)) return;
-    const int lane = threadIdx.x & 63;
+    const int32_t *src = st->shrunk ? work : node_samples;
+    constexpr int G = 64 / RECOUNT_LANES;
+    const int lane = threadIdx.x & 63, grp = lane / RECOUNT_LANES, t = lane % RECOUNT_LANES;
+    const uint64_t below = (1ull << t) - 1ull;
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-    for (uint64_t it = wave; it < nitems; it += nwaves) {
-        const int2 w = items[it];
-        const int64_t e = node_ptr[w.x + 1];
-        const int64_t p0 = node_ptr[w.x] + (int64_t)w.y * RECOUNT_SPAN;
-        const int64_t p1 = min(e, p0 + (int64_t)RECOUNT_SPAN);
-        int c = 0;
-        for (int64_t p = p0 + lane; p < p1; p += 64) {
-            const int32_t j = node_samples[p];
-            c += (covered[j >> 5] >> (j & 31)) & 1u ? 0 : 1;
+    for (uint64_t b0 = wave * G; b0 < nitems; b0 += nwaves * G) { // uniform over the wave
+        const uint64_t it = b0 + grp;
+        RecountItem w;
+        w.p0 = 0;
+        w.len = 0;
+        w.v = -1;
+        if (it < nitems) w = items[it];
+        int kept = 0; // same in every lane of the group
+        for (int q0 = 0; q0 < w.len; q0 += RECOUNT_LANES * RECOUNT_UNROLL) {
+            int32_t js[RECOUNT_UNROLL];
+#pragma unroll
+            for (int u = 0; u < RECOUNT_UNROLL; ++u) {
+                const int q = q0 + u * RECOUNT_LANES + t;
+                js[u] = q < w.len ? src[w.p0 + q] : -1;
+            }
+            uint32_t wd[RECOUNT_UNROLL];
+#pragma unroll
+            for (int u = 0; u < RECOUNT_UNROLL; ++u) wd[u] = js[u] >= 0 ? covered[js[u] >> 5] : 0xffffffffu;
+#pragma unroll
+            for (int u = 0; u < RECOUNT_UNROLL; ++u) {
+                const bool keep = !((wd[u] >> (js[u] & 31)) & 1u);
+                const uint64_t m = (__ballot(keep) >> (grp * RECOUNT_LANES)) & 0xffffull;
+                if (keep) work[w.p0 + kept + __popcll(m & below)] = js[u];
+                kept += __popcll(m);
+            }
         }
-        c = wave_sum(c);
-        if (lane == 0 && c) atomicAdd(&delta[w.x], c);
+        if (t == 0 && it < nitems) {
+            items[it].len = kept;
+            if (kept) atomicAdd(&delta[w.v], kept);
+        }
     }
 }
 
@@ -585,14 +658,14 @@ __global__ __launch_bounds__(256) void k_greedy_decrement(const GreedyState *__r
         if (hd[h]) atomicAdd(&delta[hot_node[h]], hd[h]);
 }
 
-__global__ __launch_bounds__(256) void k_greedy_final(int32_t n, uint64_t T, double Gamma,
-                                                      const uint8_t *__restrict__ chosen, const double *__restrict__ qv,
+// second term of Eq. margin summed over the k picks (each node is picked at most once)
+__global__ __launch_bounds__(256) void k_greedy_final(int32_t k, uint64_t T, double Gamma,
+                                                      const int32_t *__restrict__ seeds, const double *__restrict__ qv,
                                                       GreedyState *__restrict__ st)
 {
     __shared__ double ps[256], pc[256];
     double s = 0.0, c = 0.0;
-    for (int64_t v = threadIdx.x; v < n; v += 256)
-        if (chosen[v]) neumaier_add(s, c, qv[v]);
+    for (int32_t r = threadIdx.x; r < k; r += 256) neumaier_add(s, c, qv[seeds[r]]);
     ps[threadIdx.x] = s;
     pc[threadIdx.x] = c;
     __syncthreads();
@@ -765,7 +838,7 @@ void greedy(const Sketch &sk, QueryScratch &qs, int32_t k, int32_t *seeds, uint6
     DevBuf<uint8_t> chosen;
     DevBuf<uint32_t> covered, list;
     DevBuf<GreedyState> st;
-    const unsigned ga = gridq(n, 256, 4);
+    const unsigned ga = gridq(((uint64_t)n + ARGMAX_PER - 1) / ARGMAX_PER, 256, 4);
     DevBuf<double> pg;
     DevBuf<int32_t> pv;
     delta.alloc(arena, n);
@@ -787,7 +860,8 @@ void greedy(const Sketch &sk, QueryScratch &qs, int32_t k, int32_t *seeds, uint6
     // recount work items (used by the rounds that cover many samples)
     DevBuf<uint32_t> nitems;
     DevBuf<int64_t> ioff;
-    DevBuf<int2> items;
+    DevBuf<RecountItem> items;
+    DevBuf<int32_t> work; // the lists cut down by the heavy rounds
     uint64_t nit = 0;
     if (sk.T) {
         nitems.alloc(arena, n);
@@ -800,11 +874,12 @@ void greedy(const Sketch &sk, QueryScratch &qs, int32_t k, int32_t *seeds, uint6
         SKIS_HIP_TRY(hipStreamSynchronize(s));
         nit = (uint64_t)hn;
         items.alloc(arena, nit ? nit : 1);
-        hipLaunchKernelGGL(k_recount_items_fill, dim3(gridq(n, 256)), dim3(256), 0, s, n, nitems.ptr, ioff.ptr,
-                           items.ptr);
+        work.alloc(arena, sk.entries ? sk.entries : 1);
+        hipLaunchKernelGGL(k_recount_items_fill, dim3(gridq(n, 256)), dim3(256), 0, s, n, sk.node_ptr.ptr,
+                           nitems.ptr, ioff.ptr, items.ptr);
         SKIS_HIP_TRY(hipGetLastError());
     }
-    const unsigned gr = gridq(nit * 64, 256, 8);
+    const unsigned gr = gridq(nit * RECOUNT_LANES, 256, 8);
     for (int32_t r = 0; r < k; ++r) {
         hipLaunchKernelGGL(k_greedy_argmax, dim3(ga), dim3(256), 0, s, n, (int)r, sk.T, sk.Gamma, delta.ptr, sk.q.ptr,
                            chosen.ptr, pg.ptr, pv.ptr, st.ptr, seeds, reinterpret_cast<unsigned long long *>(marg));
@@ -816,11 +891,11 @@ void greedy(const Sketch &sk, QueryScratch &qs, int32_t k, int32_t *seeds, uint6
                                sk.sample_ptr.ptr, sk.nodes.ptr, hot_id, sk.hot_node.ptr, nhot, delta.ptr);
             hipLaunchKernelGGL(k_recount_zero, dim3(gridq(n, 256)), dim3(256), 0, s, st.ptr, sk.T, n, delta.ptr);
             hipLaunchKernelGGL(k_greedy_recount, dim3(gr), dim3(256), 0, s, st.ptr, sk.T, nit, items.ptr,
-                               sk.node_ptr.ptr, sk.node_samples.ptr, covered.ptr, delta.ptr);
+                               sk.node_samples.ptr, work.ptr, covered.ptr, delta.ptr);
         }
     }
     SKIS_HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_greedy_final, dim3(1), dim3(256), 0, s, n, sk.T, sk.Gamma, chosen.ptr, sk.q.ptr, st.ptr);
+    hipLaunchKernelGGL(k_greedy_final, dim3(1), dim3(256), 0, s, k, sk.T, sk.Gamma, seeds, sk.q.ptr, st.ptr);
     SKIS_HIP_TRY(hipGetLastError());
     GreedyState hs;
     SKIS_HIP_TRY(hipMemcpyAsync(&hs, st.ptr, sizeof(hs), hipMemcpyDeviceToHost, s));

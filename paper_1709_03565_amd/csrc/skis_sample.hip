@@ -23,7 +23,7 @@
 namespace skis {
 
 constexpr uint32_t DEFERRED = 0xFFFFFFFFu;
-constexpr int SMALL_SORT = 256;    // sizes up to this are sorted by one wave (k_gather_seg / k_gather_small)
+constexpr int SMALL_SORT = 256;    // sizes up to this are sorted in registers by k_gather_sort
 constexpr int SORT_LDS_MAX = 8192; // sizes up to this are sorted in LDS by k_gather_medium;
                                    // larger ones are written already sorted by the global tier
 // sample ids taken from the global counter at a time: at least the slots of a workgroup
@@ -611,49 +611,23 @@ __device__ void bitonic_lds(int32_t *buf, int P)
     }
 }
 
-// 64-thread workgroups, one sample of 65 .. SMALL_SORT nodes at a time (from the class
-// list); larger sizes are left to k_gather_medium.
-__global__ __launch_bounds__(64) void k_gather_small(const unsigned long long *__restrict__ counts,
-                                                     const uint32_t *__restrict__ lists,
-                                                     const uint32_t *__restrict__ size,
-                                                     const unsigned long long *__restrict__ off,
-                                                     const int64_t *__restrict__ sptr,
-                                                     const int32_t *__restrict__ staging, int32_t *__restrict__ nodes)
-{
-    __shared__ int32_t buf[SMALL_SORT];
-    const int lane = threadIdx.x;
-    unsigned long long base = 0;
-    for (int k = 0; k < 4; ++k) base += counts[k];
-    const unsigned long long T = counts[4]; // the class of sizes 65 .. SMALL_SORT
-    for (uint64_t q = blockIdx.x; q < T; q += gridDim.x) {
-        const uint32_t i = lists[base + q];
-        const int sz = (int)size[i];
-        if (sz > SMALL_SORT) continue;
-        const int32_t *src = staging + off[i];
-        int32_t *dst = nodes + sptr[i];
-        int P = 128;
-        while (P < sz) P <<= 1;
-        for (int t = lane; t < P; t += 64) buf[t] = t < sz ? src[t] : INT32_MAX;
-        __syncthreads();
-        bitonic_lds<64>(buf, P);
-        for (int t = lane; t < sz; t += 64) dst[t] = buf[t];
-        __syncthreads();
-    }
-}
-
-// Size classes for the segmented sorts: class c < 3 holds sizes up to 8 << c (segments of
-// 8, 16 or 32 lanes), class 3 sizes up to 64 (a whole wave), class 4 sizes up to SMALL_SORT.
-constexpr int GATHER_CLASSES = 5;
+// Size classes for the segmented sorts: class c holds sizes up to 8 << c; classes 0 .. 3 use
+// segments of 8, 16, 32 or 64 lanes with one node per lane, classes 4 and 5 a whole wave
+// with 2 or 4 nodes per lane (up to SMALL_SORT).
+constexpr int GATHER_CLASSES = 6;
 
 __device__ __forceinline__ int size_class(uint32_t sz)
 {
-    return sz <= 8 ? 0 : sz <= 16 ? 1 : sz <= 32 ? 2 : sz <= 64 ? 3 : 4;
+    return sz <= 8 ? 0 : sz <= 16 ? 1 : sz <= 32 ? 2 : sz <= 64 ? 3 : sz <= 128 ? 4 : 5;
 }
 
 // counts[c] = samples of class c (samples above SMALL_SORT are listed by the sampler)
 __global__ __launch_bounds__(256) void k_class_count(uint64_t T, const uint32_t *__restrict__ size,
                                                      unsigned long long *__restrict__ counts)
 {
+    __shared__ unsigned long long bc[GATHER_CLASSES];
+    if (threadIdx.x < GATHER_CLASSES) bc[threadIdx.x] = 0ull;
+    __syncthreads();
     unsigned long long c[GATHER_CLASSES] = {};
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < T; i += (uint64_t)gridDim.x * blockDim.x) {
         const uint32_t sz = size[i];
@@ -662,8 +636,11 @@ __global__ __launch_bounds__(256) void k_class_count(uint64_t T, const uint32_t 
 #pragma unroll
     for (int k = 0; k < GATHER_CLASSES; ++k) {
         const unsigned long long t = wave_sum(c[k]);
-        if ((threadIdx.x & 63) == 0 && t) atomicAdd(&counts[k], t);
+        if ((threadIdx.x & 63) == 0 && t) atomicAdd(&bc[k], t);
     }
+    __syncthreads();
+    // one global atomic per class and workgroup: same-address atomics serialise in L2
+    if (threadIdx.x < GATHER_CLASSES && bc[threadIdx.x]) atomicAdd(&counts[threadIdx.x], bc[threadIdx.x]);
 }
 
 // lists[base(c) + ...] = the samples of class c, base(c) = counts of the classes before c.
@@ -711,40 +688,85 @@ __global__ __launch_bounds__(256) void k_class_fill(uint64_t T, const uint32_t *
     }
 }
 
-// W-lane segments of one wave each sort one sample of class W (64 / W samples per step):
-// bitonic network within the segment, padded with INT32_MAX.
-template <int W>
-__global__ __launch_bounds__(64) void k_gather_seg(int cls, const unsigned long long *__restrict__ counts,
-                                                   const uint32_t *__restrict__ lists,
-                                                   const uint32_t *__restrict__ size,
-                                                   const unsigned long long *__restrict__ off,
-                                                   const int64_t *__restrict__ sptr,
-                                                   const int32_t *__restrict__ staging, int32_t *__restrict__ nodes)
+// Segments of W lanes each sort one sample of up to W * R nodes in registers (64 / W samples
+// per wave and step).  Node slot r * W + t of the sample is loaded by lane t of the segment
+// into v[r] (coalesced; padding INT32_MAX), then a bitonic network sorts the W * R values
+// with element e = t * R + r living in v[r] of lane t: exchanges at distance d < R stay
+// in the lane, the others are shuffles at lane distance d / R within the segment.  The
+// next step's list entry and sample bounds are loaded before the current sort.
+template <int W, int R>
+__global__ __launch_bounds__(64) void k_gather_sort(int cls, const unsigned long long *__restrict__ counts,
+                                                    const uint32_t *__restrict__ lists,
+                                                    const uint32_t *__restrict__ size,
+                                                    const unsigned long long *__restrict__ off,
+                                                    const int64_t *__restrict__ sptr,
+                                                    const int32_t *__restrict__ staging, int32_t *__restrict__ nodes)
 {
-    constexpr int G = 64 / W;
+    constexpr int G = 64 / W, P = W * R;
     const int lane = threadIdx.x, seg = lane / W, t = lane % W;
     unsigned long long base = 0;
     for (int k = 0; k < cls; ++k) base += counts[k];
     const unsigned long long cnt = counts[cls];
-    for (unsigned long long g0 = (unsigned long long)blockIdx.x * G; g0 < cnt; g0 += (unsigned long long)gridDim.x * G) {
-        const unsigned long long gi = g0 + seg;
-        uint32_t i = 0, sz = 0;
-        if (gi < cnt) {
-            i = lists[base + gi];
-            sz = size[i];
+    const unsigned long long stride = (unsigned long long)gridDim.x * G;
+    uint32_t sz = 0;
+    unsigned long long o = 0;
+    int64_t dp = 0;
+    unsigned long long g0 = (unsigned long long)blockIdx.x * G;
+    if (g0 + seg < cnt) {
+        const uint32_t i = lists[base + g0 + seg];
+        sz = size[i];
+        o = off[i];
+        dp = sptr[i];
+    }
+    for (; g0 < cnt; g0 += stride) {
+        uint32_t nsz = 0;
+        unsigned long long no = 0;
+        int64_t ndp = 0;
+        if (g0 + stride + seg < cnt) {
+            const uint32_t i = lists[base + g0 + stride + seg];
+            nsz = size[i];
+            no = off[i];
+            ndp = sptr[i];
         }
-        int32_t v = (t < (int)sz) ? staging[off[i] + t] : INT32_MAX;
+        int32_t v[R];
 #pragma unroll
-        for (int k = 2; k <= W; k <<= 1) {
+        for (int r = 0; r < R; ++r) {
+            const int x = r * W + t;
+            v[r] = x < (int)sz ? staging[o + x] : INT32_MAX;
+        }
+#pragma unroll
+        for (int k = 2; k <= P; k <<= 1) {
 #pragma unroll
             for (int d = k >> 1; d > 0; d >>= 1) {
-                const int32_t o = __shfl_xor(v, d, 64);
-                const bool asc = (t & k) == 0;
-                const bool low = (t & d) == 0;
-                v = (low == asc) ? min(v, o) : max(v, o);
+                if (d < R) {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        if (r & d) continue;
+                        const bool asc = ((t * R + r) & k) == 0;
+                        const int32_t x = v[r], y = v[r | d];
+                        v[r] = asc ? min(x, y) : max(x, y);
+                        v[r | d] = asc ? max(x, y) : min(x, y);
+                    }
+                } else {
+                    const int ld = d / R;
+                    const bool low = (t & ld) == 0;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const bool asc = ((t * R + r) & k) == 0;
+                        const int32_t y = __shfl_xor(v[r], ld, 64);
+                        v[r] = (low == asc) ? min(v[r], y) : max(v[r], y);
+                    }
+                }
             }
         }
-        if (t < (int)sz) nodes[sptr[i] + t] = v;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int e = t * R + r;
+            if (e < (int)sz) nodes[dp + e] = v[r];
+        }
+        sz = nsz;
+        o = no;
+        dp = ndp;
     }
 }
 
@@ -775,14 +797,26 @@ __global__ __launch_bounds__(256) void k_gather_medium(uint64_t count, const uin
     }
 }
 
+// Adds the sum of v over a 256-thread workgroup to *out with one global atomic.
+__device__ __forceinline__ void block_add_to(unsigned long long v, unsigned long long *out)
+{
+    __shared__ unsigned long long part[4];
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long t = part[0] + part[1] + part[2] + part[3];
+        if (t) atomicAdd(out, t);
+    }
+}
+
 __global__ __launch_bounds__(256) void k_count_value(uint64_t count, const uint32_t *__restrict__ x, uint32_t v,
                                                      unsigned long long *__restrict__ out)
 {
     unsigned long long acc = 0;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (uint64_t)gridDim.x * blockDim.x)
         acc += x[i] == v ? 1ull : 0ull;
-    acc = wave_sum(acc);
-    if ((threadIdx.x & 63) == 0 && acc) atomicAdd(out, acc);
+    block_add_to(acc, out);
 }
 
 __global__ __launch_bounds__(256) void k_roots_out(uint32_t count, const int4 *__restrict__ rec, int32_t *__restrict__ roots)
@@ -797,8 +831,7 @@ __global__ __launch_bounds__(256) void k_sum_u64(uint64_t count, const unsigned 
     unsigned long long acc = 0;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (uint64_t)gridDim.x * blockDim.x)
         acc += x[i];
-    acc = wave_sum(acc);
-    if ((threadIdx.x & 63) == 0 && acc) atomicAdd(out, acc);
+    block_add_to(acc, out);
 }
 
 template <typename T>
@@ -1297,7 +1330,7 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
 
     // every sample must have finished in one of the tiers
     hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(1), dim3(64), 0, s, (uint64_t)1, &ctr.ptr->next, 0ull);
-    hipLaunchKernelGGL(k_count_value, dim3(grid_cap(count, 256)), dim3(256), 0, s, (uint64_t)count, out_size.ptr,
+    hipLaunchKernelGGL(k_count_value, dim3(grid_cap(count, 256, 1)), dim3(256), 0, s, (uint64_t)count, out_size.ptr,
                        DEFERRED, &ctr.ptr->next);
     SKIS_HIP_TRY(hipGetLastError());
     unsigned long long unfinished = 0;
@@ -1323,21 +1356,25 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
         lists.alloc(arena, count);
         hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(1), dim3(64), 0, s, (uint64_t)(2 * GATHER_CLASSES),
                            cls.ptr, 0ull);
-        hipLaunchKernelGGL(k_class_count, dim3(grid_cap(count, 256)), dim3(256), 0, s, (uint64_t)count, out_size.ptr,
+        hipLaunchKernelGGL(k_class_count, dim3(grid_cap(count, 256, 1)), dim3(256), 0, s, (uint64_t)count, out_size.ptr,
                            cls.ptr);
         hipLaunchKernelGGL(k_class_fill, dim3(grid_cap(count, CLASS_CHUNK, 8)), dim3(256), 0, s, (uint64_t)count,
                            out_size.ptr, cls.ptr, cls.ptr + GATHER_CLASSES, lists.ptr);
         const unsigned gg = grid_cap(count, 8, 64);
-        hipLaunchKernelGGL(k_gather_seg<8>, dim3(gg), dim3(64), 0, s, 0, cls.ptr, lists.ptr, out_size.ptr, out_off.ptr,
+        const uint32_t *const sz_p = out_size.ptr;
+        const unsigned long long *const off_p = out_off.ptr;
+        hipLaunchKernelGGL((k_gather_sort<8, 1>), dim3(gg), dim3(64), 0, s, 0, cls.ptr, lists.ptr, sz_p, off_p,
                            sk.sample_ptr.ptr, staging.ptr, sk.nodes.ptr);
-        hipLaunchKernelGGL(k_gather_seg<16>, dim3(gg), dim3(64), 0, s, 1, cls.ptr, lists.ptr, out_size.ptr,
-                           out_off.ptr, sk.sample_ptr.ptr, staging.ptr, sk.nodes.ptr);
-        hipLaunchKernelGGL(k_gather_seg<32>, dim3(gg), dim3(64), 0, s, 2, cls.ptr, lists.ptr, out_size.ptr,
-                           out_off.ptr, sk.sample_ptr.ptr, staging.ptr, sk.nodes.ptr);
-        hipLaunchKernelGGL(k_gather_seg<64>, dim3(gg), dim3(64), 0, s, 3, cls.ptr, lists.ptr, out_size.ptr,
-                           out_off.ptr, sk.sample_ptr.ptr, staging.ptr, sk.nodes.ptr);
-        hipLaunchKernelGGL(k_gather_small, dim3(grid_cap(count, 1, 64)), dim3(64), 0, s, cls.ptr, lists.ptr,
-                           out_size.ptr, out_off.ptr, sk.sample_ptr.ptr, staging.ptr, sk.nodes.ptr);
+        hipLaunchKernelGGL((k_gather_sort<16, 1>), dim3(gg), dim3(64), 0, s, 1, cls.ptr, lists.ptr, sz_p, off_p,
+                           sk.sample_ptr.ptr, staging.ptr, sk.nodes.ptr);
+        hipLaunchKernelGGL((k_gather_sort<32, 1>), dim3(gg), dim3(64), 0, s, 2, cls.ptr, lists.ptr, sz_p, off_p,
+                           sk.sample_ptr.ptr, staging.ptr, sk.nodes.ptr);
+        hipLaunchKernelGGL((k_gather_sort<64, 1>), dim3(gg), dim3(64), 0, s, 3, cls.ptr, lists.ptr, sz_p, off_p,
+                           sk.sample_ptr.ptr, staging.ptr, sk.nodes.ptr);
+        hipLaunchKernelGGL((k_gather_sort<64, 2>), dim3(gg), dim3(64), 0, s, 4, cls.ptr, lists.ptr, sz_p, off_p,
+                           sk.sample_ptr.ptr, staging.ptr, sk.nodes.ptr);
+        hipLaunchKernelGGL((k_gather_sort<64, 4>), dim3(gg), dim3(64), 0, s, 5, cls.ptr, lists.ptr, sz_p, off_p,
+                           sk.sample_ptr.ptr, staging.ptr, sk.nodes.ptr);
         SKIS_HIP_TRY(hipGetLastError());
     }
     if (hc.n_medium > 0) {
@@ -1350,7 +1387,7 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
     hipLaunchKernelGGL(k_roots_out, dim3(grid_cap(count, 256)), dim3(256), 0, s, count, rec.ptr, sk.roots.ptr);
     SKIS_HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(1), dim3(64), 0, s, (uint64_t)1, &ctr.ptr->next, 0ull);
-    hipLaunchKernelGGL(k_sum_u64, dim3(grid_cap(count, 256)), dim3(256), 0, s, (uint64_t)count,
+    hipLaunchKernelGGL(k_sum_u64, dim3(grid_cap(count, 256, 1)), dim3(256), 0, s, (uint64_t)count,
                        reinterpret_cast<const unsigned long long *>(sk.probed.ptr), &ctr.ptr->next);
     SKIS_HIP_TRY(hipGetLastError());
     unsigned long long ptot = 0;

@@ -409,3 +409,20 @@ def test_full_size_windows(skis, name):
     for i, S in enumerate(sets):
         hit = np.isin(nodes, S)
         assert int(_np(cov)[i]) == len(np.unique(owner[hit]))
+    # greedy (Alg. 3) at full size, where the first rounds each cover more than T/32 samples:
+    # every marginal equals the coverage its pick adds, measured by estimate over the
+    # prefixes of the pick list, and round 0 picks the exact argmax over the degrees
+    k = 100
+    seeds, marg, gcov, gest = sk.greedy(k)
+    seeds, marg = _np(seeds), _np(marg).astype(np.int64)
+    assert len(np.unique(seeds)) == k
+    pp, pn = inputs.sets_to_csr([seeds[:r + 1] for r in range(k)])
+    pc, pe = sk.estimate(pp, pn)
+    pc = _np(pc).astype(np.int64)
+    assert np.array_equal(np.diff(np.concatenate([[0], pc])), marg)
+    assert gcov == int(pc[-1]) and abs(gest - float(_np(pe)[-1])) <= REL * abs(gest)
+    deg = np.diff(_np(sk.inverse()[0]))
+    _, q = oracle.row_prefix(g.row_ptr, g.w)
+    gains = (deg.astype(np.float64) * inf.Gamma) / float(T) + q
+    assert int(seeds[0]) == int(np.argmax(gains)) and marg[0] == deg[seeds[0]]
+    _say("greedy", name, "first picks", seeds[:4].tolist(), "marg", marg[:4].tolist())
