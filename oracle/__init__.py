@@ -122,7 +122,8 @@ def validate(row_ptr, col, w) -> int:
 
 
 def row_prefix(row_ptr, w):
-    """(P[m], q[n]) of Eq. (gamma_v) / Eq. (probn), sequential per row."""
+    """(P[m], q[n]) of Eq. (gamma_v) / Eq. (probn): per row, products in blocks of 64
+    in-edges with a carried block product (a plain left-to-right product up to 64)."""
     row_ptr, w = _c(row_ptr, np.int32), _c(w, np.float32)
     n = len(row_ptr) - 1
     P = np.zeros(max(len(w), 1), np.float64)

@@ -103,20 +103,34 @@ int ora_validate(int32_t n, int64_t m, const int32_t *row_ptr, const int32_t *co
 }
 
 /* ------------------------------------------------------------------------------------
- * Eq. (gamma_v) and the bucket probabilities of Eq. (probn): per row v, the running
- * product P_e of (1 - w) over the in-edges up to and including e, in CSR order.
- * q_v = P of the last in-edge (1 for an empty row) is the singular probability, and
- * gamma_v = 1 - q_v.
+ * Eq. (gamma_v) and the bucket probabilities of Eq. (probn): per row v, the product P_e
+ * of (1 - w) over the in-edges up to and including e, in CSR order.  q_v = P of the last
+ * in-edge (1 for an empty row) is the singular probability, and gamma_v = 1 - q_v.
+ * The paper defines these products over the reals; in binary64 they are formed in blocks
+ * of ORA_PREFIX_BLOCK consecutive in-edges of the row: a running product within the
+ * block (starting from the block's first factor), a carry that multiplies in each
+ * finished block's total, and P_e = carry * (running product of e's block up to e), one
+ * rounding per product.  A row of at most ORA_PREFIX_BLOCK in-edges is the plain
+ * left-to-right product.
  * ---------------------------------------------------------------------------------- */
+#define ORA_PREFIX_BLOCK 64
+
 void ora_row_prefix(int32_t n, const int32_t *row_ptr, const float *w, double *P, double *q)
 {
     for (int32_t v = 0; v < n; ++v) {
-        double prod = 1.0;
-        for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
-            prod = prod * (1.0 - (double)w[e]);
-            P[e] = prod;
+        const int32_t a = row_ptr[v], b = row_ptr[v + 1];
+        double carry = 1.0, local = 1.0;
+        for (int32_t e = a; e < b; ++e) {
+            const double f = 1.0 - (double)w[e];
+            if ((e - a) % ORA_PREFIX_BLOCK == 0) {
+                if (e > a) carry = carry * local; /* the finished block's total */
+                local = f;
+            } else {
+                local = local * f;
+            }
+            P[e] = carry * local;
         }
-        q[v] = prod;
+        q[v] = b > a ? P[b - 1] : 1.0;
     }
 }
 

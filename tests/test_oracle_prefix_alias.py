@@ -40,6 +40,56 @@ def test_wc_rows_closed_form():
     assert np.all(q[len(degs):] == 1.0)
 
 
+def _rows_graph(rows):
+    """A graph whose node v has the in-edge weights rows[v] (sources are fresh nodes)."""
+    src, dst, ws = [], [], []
+    n = len(rows) + max(len(r) for r in rows)
+    for v, r in enumerate(rows):
+        for i, x in enumerate(r):
+            src.append(len(rows) + i)
+            dst.append(v)
+            ws.append(x)
+    return inputs.edges_to_in_csr(n, src, dst, np.array(ws, np.float32))
+
+
+def test_prefix_short_rows_are_the_plain_running_product():
+    # a row of at most 64 in-edges: P is itertools.accumulate's left-to-right product
+    import itertools
+    import operator
+    rng = np.random.Generator(np.random.PCG64(12))
+    rows = [rng.choice(np.array([0.1, 0.01, 0.001, 0.5, 0.0], np.float32), size=d) for d in (1, 2, 17, 63, 64)]
+    row_ptr, col, ww = _rows_graph(rows)
+    P, q = oracle.row_prefix(row_ptr, ww)
+    for v in range(len(rows)):
+        a, b = row_ptr[v], row_ptr[v + 1]
+        f = [1.0 - float(x) for x in ww[a:b]]
+        assert P[a:b].tolist() == list(itertools.accumulate(f, operator.mul))
+        assert q[v] == P[b - 1]
+
+
+def test_prefix_long_rows_within_rounding_bound_of_exact_products():
+    # every P_e against the exact rational product of its factors.  Counting the roundings
+    # behind the i-th product of a row (0-based): 63 in each earlier block, the carries
+    # after the first (which multiplies 1.0 exactly), i mod 64 in its own block and the
+    # final product (exact in block 0): i in all, as for a left-to-right product.  So
+    # |P_e - exact| <= i u / (1 - i u) * exact; a dropped, repeated or misplaced factor
+    # is off by orders of magnitude more
+    rng = np.random.Generator(np.random.PCG64(13))
+    u = Fraction(1, 1 << 53)
+    rows = [rng.choice(np.array([0.1, 0.01, 0.001], np.float32), size=d) for d in (65, 128, 129, 1000, 4097)]
+    rows.append(np.full(300, np.float32(1.0) / np.float32(300), np.float32))
+    row_ptr, col, ww = _rows_graph(rows)
+    P, q = oracle.row_prefix(row_ptr, ww)
+    for v in range(len(rows)):
+        a, b = row_ptr[v], row_ptr[v + 1]
+        exact = Fraction(1)
+        for i, x in enumerate(ww[a:b]):
+            exact *= 1 - Fraction(float(x))
+            bound = i * u / (1 - i * u) * exact
+            assert abs(Fraction(float(P[a + i])) - exact) <= bound, (v, i)
+        assert q[v] == P[b - 1]
+
+
 def test_prefix_special_values_and_monotone():
     rng = np.random.Generator(np.random.PCG64(3))
     n = 50
