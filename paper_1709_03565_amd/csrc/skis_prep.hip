@@ -18,9 +18,15 @@ __device__ __forceinline__ int check_edge(int32_t u, float wf, int64_t v, int32_
     return bad;
 }
 
-// One thread per row: validates the row, writes the interleaved (col, w) records and the
-// running products P[e] = P[e-1] * (1 - w[e]) in row order (one rounding each; the
-// build disables contraction, and __dmul_rn / __dsub_rn pin the operations), q[v] = last P.
+// The products of a row (Eq. gamma_v / Eq. probn) are formed in blocks of PREFIX_BLOCK
+// consecutive in-edges: a running product within the block starting from its first factor
+// (1 - w), a carry that multiplies in each finished block's total, and
+// P[e] = carry * (running product of e's block up to e), one rounding per product (the
+// build disables contraction; __dmul_rn / __dsub_rn pin the operations).  A row of at most
+// PREFIX_BLOCK in-edges is the plain left-to-right product.  q[v] = the row's last P.
+constexpr int PREFIX_BLOCK = 64;
+
+// One thread per row: validates the row, writes the interleaved (col, w) records, P and q.
 // Rows longer than LONG_ROW are listed for k_prep_long.
 __global__ __launch_bounds__(256) void k_prep_rows(int32_t n, int64_t m, const int32_t *__restrict__ row_ptr,
                                                    const int32_t *__restrict__ col, const float *__restrict__ w,
@@ -45,28 +51,40 @@ __global__ __launch_bounds__(256) void k_prep_rows(int32_t n, int64_t m, const i
             if (bad) atomicOr(err, bad);
             continue;
         }
-        double prod = 1.0;
+        double carry = 1.0, local = 1.0, last = 1.0;
         for (int32_t e = a; e < b; ++e) {
             const int32_t u = col[e];
             float wf = w[e];
             bad |= check_edge(u, wf, v, n);
             if (wf == 0.0f) wf = 0.0f; // -0 -> +0: the coin reads the bits
             edges[e] = make_uint2((uint32_t)u, __float_as_uint(wf));
-            prod = __dmul_rn(prod, __dsub_rn(1.0, (double)wf));
-            P[e] = prod;
+            const double f = __dsub_rn(1.0, (double)wf);
+            if ((e - a) % PREFIX_BLOCK == 0) {
+                if (e > a) carry = __dmul_rn(carry, local);
+                local = f;
+            } else {
+                local = __dmul_rn(local, f);
+            }
+            last = __dmul_rn(carry, local);
+            P[e] = last;
         }
-        q[v] = prod;
+        q[v] = last;
         if (bad) atomicOr(err, bad);
     }
 }
 
-// One wave per long row, 512 edges per step.  The lanes load, validate and interleave the
-// step's edges (8 each) and put the factors (1 - w) in LDS; the loads of the next step are
-// already in flight.  Lane 0 then carries the running product through the 512 factors in
-// row order, 64 at a time held in registers, so the dependent chain is one fp64 multiply
-// per edge with one rounding each (the same sequence a single thread would do), and writes
-// the products back to LDS for all lanes to store P.
-constexpr int LONG_STEP = 512;
+// One 256-thread workgroup per long row, LONG_CHUNK blocks of PREFIX_BLOCK in-edges (LONG_EDGES
+// edges) at a time, every global access coalesced: (1) each thread loads, validates and writes
+// LONG_PER edges and puts their factors (1 - w) in LDS; (2) thread b < LONG_CHUNK replaces the
+// factors of block b by the running product within the block; (3) thread 0 carries the product
+// through the chunk's block totals in row order; (4) each thread writes P = carry * running
+// product for its LONG_PER edges.  The carry after the last block is q[v].  LDS rows of
+// PREFIX_BLOCK doubles are padded by one so that the threads of (2) do not share banks.
+constexpr int LONG_CHUNK = 64;
+constexpr int LONG_EDGES = LONG_CHUNK * PREFIX_BLOCK; // 4096
+constexpr int LONG_PER = LONG_EDGES / 256;
+
+__device__ __forceinline__ int long_slot(int i) { return i + i / PREFIX_BLOCK; }
 
 __global__ __launch_bounds__(256) void k_prep_long(int32_t n, const int32_t *__restrict__ row_ptr,
                                                    const int32_t *__restrict__ col, const float *__restrict__ w,
@@ -75,90 +93,109 @@ __global__ __launch_bounds__(256) void k_prep_long(int32_t n, const int32_t *__r
                                                    const int32_t *__restrict__ long_rows,
                                                    const unsigned int *__restrict__ n_long)
 {
-    constexpr int PER = LONG_STEP / 64;
-    __shared__ double fac_all[4][LONG_STEP];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    double *fac = fac_all[wid];
+    __shared__ double s_f[LONG_EDGES + LONG_CHUNK];
+    __shared__ double s_tot[LONG_CHUNK], s_carry[LONG_CHUNK];
+    __shared__ double s_run;
+    const int t = threadIdx.x;
     const unsigned int cnt = *n_long;
-    auto wave_sync = []() {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    };
-    for (unsigned int r = blockIdx.x * 4 + wid; r < cnt; r += gridDim.x * 4) {
+    for (unsigned int r = blockIdx.x; r < cnt; r += gridDim.x) {
         const int32_t v = long_rows[r];
         const int32_t a = row_ptr[v], b = row_ptr[v + 1];
-        double prod = 1.0; // meaningful in lane 0
         int bad = 0;
-        // element k of a step is edge c0 + k*64 + lane for this lane (coalesced per k)
-        int32_t uc[PER];
-        float wc[PER];
+        if (t == 0) s_run = 1.0;
+        // element k of a thread's share of a chunk is edge c0 + k * 256 + t (coalesced per k);
+        // the loads are unconditional (an index past the row reads its last edge, unused), so
+        // that the compiler can keep the next chunk's loads in flight across a chunk
+        int32_t uc[LONG_PER];
+        float wc[LONG_PER];
 #pragma unroll
-        for (int k = 0; k < PER; ++k) {
-            const int32_t e = a + k * 64 + lane;
-            uc[k] = e < b ? col[e] : 0;
-            wc[k] = e < b ? w[e] : 0.0f;
+        for (int k = 0; k < LONG_PER; ++k) {
+            const int32_t e = min(a + k * 256 + t, b - 1);
+            uc[k] = col[e];
+            wc[k] = w[e];
         }
-        for (int32_t c0 = a; c0 < b; c0 += LONG_STEP) {
-            // next step's loads first
-            int32_t un[PER];
-            float wn[PER];
+        for (int32_t c0 = a; c0 < b; c0 += LONG_EDGES) {
+            // (1) this chunk's edges, then the next chunk's loads
+            int32_t un[LONG_PER];
+            float wn[LONG_PER];
 #pragma unroll
-            for (int k = 0; k < PER; ++k) {
-                const int32_t e = c0 + LONG_STEP + k * 64 + lane;
-                un[k] = e < b ? col[e] : 0;
-                wn[k] = e < b ? w[e] : 0.0f;
-            }
-#pragma unroll
-            for (int k = 0; k < PER; ++k) {
-                const int32_t e = c0 + k * 64 + lane;
+            for (int k = 0; k < LONG_PER; ++k) {
+                const int32_t e = c0 + k * 256 + t;
                 if (e < b) {
                     float wf = wc[k];
                     bad |= check_edge(uc[k], wf, v, n);
-                    if (wf == 0.0f) wf = 0.0f;
+                    if (wf == 0.0f) wf = 0.0f; // -0 -> +0: the coin reads the bits
                     edges[e] = make_uint2((uint32_t)uc[k], __float_as_uint(wf));
-                    fac[k * 64 + lane] = __dsub_rn(1.0, (double)wf);
+                    s_f[long_slot(k * 256 + t)] = __dsub_rn(1.0, (double)wf);
                 }
             }
-            wave_sync();
-            const int len = (b - c0) < LONG_STEP ? (b - c0) : LONG_STEP;
-            if (lane == 0) {
-                if (len == LONG_STEP) {
-                    for (int g = 0; g < LONG_STEP; g += 64) {
-                        double f[64];
 #pragma unroll
-                        for (int i = 0; i < 64; ++i) f[i] = fac[g + i];
+            for (int k = 0; k < LONG_PER; ++k) {
+                const int32_t e = min(c0 + LONG_EDGES + k * 256 + t, b - 1);
+                un[k] = col[e];
+                wn[k] = w[e];
+            }
+            __syncthreads();
+            const int len = min(b - c0, LONG_EDGES);
+            const int nb = (len + PREFIX_BLOCK - 1) / PREFIX_BLOCK;
+            // (2) running products within the blocks
+            if (t < nb) { // the block's factors go to registers first: only the multiplies chain
+                const int i0 = t * PREFIX_BLOCK, cntb = min(len - i0, PREFIX_BLOCK);
+                double f[PREFIX_BLOCK];
 #pragma unroll
-                        for (int i = 0; i < 64; ++i) {
-                            prod = __dmul_rn(prod, f[i]);
-                            f[i] = prod;
-                        }
+                for (int i = 0; i < PREFIX_BLOCK; ++i) f[i] = i < cntb ? s_f[long_slot(i0 + i)] : 1.0;
+                double local = f[0];
 #pragma unroll
-                        for (int i = 0; i < 64; ++i) fac[g + i] = f[i];
-                    }
-                } else {
-                    for (int i = 0; i < len; ++i) {
-                        prod = __dmul_rn(prod, fac[i]);
-                        fac[i] = prod;
+                for (int i = 1; i < PREFIX_BLOCK; ++i) {
+                    if (i < cntb) local = __dmul_rn(local, f[i]);
+                    f[i] = local;
+                }
+#pragma unroll
+                for (int i = 1; i < PREFIX_BLOCK; ++i)
+                    if (i < cntb) s_f[long_slot(i0 + i)] = f[i];
+                s_tot[t] = local;
+            }
+            __syncthreads();
+            // (3) carries; the row's block 0 has carry 1 (its products are final)
+            if (t == 0) {
+                double tot[LONG_CHUNK];
+#pragma unroll
+                for (int k = 0; k < LONG_CHUNK; ++k) tot[k] = k < nb ? s_tot[k] : 1.0;
+                double run = s_run;
+#pragma unroll
+                for (int k = 0; k < LONG_CHUNK; ++k) {
+                    if (k < nb) {
+                        const double c = run;
+                        run = (c0 == a && k == 0) ? tot[0] : __dmul_rn(run, tot[k]);
+                        tot[k] = c;
                     }
                 }
-            }
-            wave_sync();
 #pragma unroll
-            for (int k = 0; k < PER; ++k) {
-                const int32_t e = c0 + k * 64 + lane;
-                if (e < b) P[e] = fac[k * 64 + lane];
+                for (int k = 0; k < LONG_CHUNK; ++k)
+                    if (k < nb) s_carry[k] = tot[k];
+                s_run = run;
             }
-            wave_sync();
+            __syncthreads();
+            // (4) P = carry * running product
 #pragma unroll
-            for (int k = 0; k < PER; ++k) {
+            for (int k = 0; k < LONG_PER; ++k) {
+                const int i = k * 256 + t;
+                if (i < len) {
+                    const double l = s_f[long_slot(i)];
+                    const int blk = i / PREFIX_BLOCK;
+                    P[c0 + i] = (c0 == a && blk == 0) ? l : __dmul_rn(s_carry[blk], l);
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < LONG_PER; ++k) {
                 uc[k] = un[k];
                 wc[k] = wn[k];
             }
         }
-        if (lane == 0) q[v] = prod;
-        bad = __reduce_or_sync(~0ull, bad);
-        if (lane == 0 && bad) atomicOr(err, bad);
+        if (t == 0) q[v] = s_run;
+        if (bad) atomicOr(err, bad);
+        __syncthreads();
     }
 }
 

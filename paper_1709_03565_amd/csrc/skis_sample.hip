@@ -23,7 +23,7 @@
 namespace skis {
 
 constexpr uint32_t DEFERRED = 0xFFFFFFFFu;
-constexpr int SMALL_SORT = 256;    // sizes up to this are sorted in registers by k_gather_sort
+constexpr int SMALL_SORT = 1024;   // sizes up to this are sorted in registers by k_gather_sort
 constexpr int SORT_LDS_MAX = 8192; // sizes up to this are sorted in LDS by k_gather_medium;
                                    // larger ones are written already sorted by the global tier
 // sample ids taken from the global counter at a time: at least the slots of a workgroup
@@ -469,37 +469,70 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
 
         // ---- B2: item edge ranges ----------------------------------------------------------
         const int nitems = s_nitems;
-        for (int it = tid; it < nitems; it += BLOCK) {
-            int lo = 0, hi = S;
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (s_ibase[mid] <= it) lo = mid + 1; else hi = mid;
+        if (nitems > 0) {
+            // item it = k * BLOCK + tid (nitems <= ICAP <= IPT * BLOCK): first the node of each
+            // item, then all row-bound loads unconditionally (node 0 stands in where there is
+            // none), then the ranges
+            int xs[IPT], ss[IPT];
+            bool rootit[IPT];
+#pragma unroll
+            for (int k = 0; k < IPT; ++k) {
+                const int it = k * BLOCK + tid;
+                ss[k] = -1;
+                xs[k] = 0;
+                rootit[k] = false;
+                if (it < nitems) {
+                    int lo = 0, hi = S;
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        if (s_ibase[mid] <= it) lo = mid + 1; else hi = mid;
+                    }
+                    const int sl = lo - 1;
+                    const int t = it - s_ibase[sl];
+                    ss[k] = sl;
+                    if (s_irp[sl] && t == 0) {
+                        rootit[k] = true;
+                    } else {
+                        const int32_t x = list_node(sl, s_ifirst[sl] + t - s_irp[sl]);
+                        if ((uint32_t)x >= (uint32_t)n) { // bounds guard: report, never index
+                            atomicOr(a.overflow, 4);
+                            xs[k] = -1;
+                        } else {
+                            xs[k] = x;
+                        }
+                    }
+                }
             }
-            const int s = lo - 1;
-            const int t = it - s_ibase[s];
-            int beg, end;
-            if (s_irp[s] && t == 0) {
-                beg = s_rib[s];
-                end = s_rie[s];
-            } else {
-                const int32_t x = list_node(s, s_ifirst[s] + t - s_irp[s]);
-                if ((uint32_t)x >= (uint32_t)n) { // bounds guard: report, never index
-                    atomicOr(a.overflow, 4);
-                    beg = end = 0;
+            int rb[IPT], re[IPT];
+#pragma unroll
+            for (int k = 0; k < IPT; ++k) {
+                const int32_t xc = xs[k] >= 0 ? xs[k] : 0;
+                rb[k] = a.row_ptr[xc];
+                re[k] = a.row_ptr[xc + 1];
+            }
+#pragma unroll
+            for (int k = 0; k < IPT; ++k) {
+                const int it = k * BLOCK + tid;
+                const int sl = ss[k];
+                if (sl < 0) continue;
+                int beg, end;
+                if (rootit[k]) {
+                    beg = s_rib[sl];
+                    end = s_rie[sl];
                 } else {
-                    beg = a.row_ptr[x];
-                    end = a.row_ptr[x + 1];
+                    beg = xs[k] >= 0 ? rb[k] : 0;
+                    end = xs[k] >= 0 ? re[k] : 0;
+                    atomicAdd(&s_probed[sl], (unsigned long long)(end - beg));
+                    if (!GLOBAL && (uint32_t)(end - beg) > a.big_row) {
+                        atomicOr(&s_flags[sl], F_DEFER);
+                        end = beg;
+                    }
                 }
-                atomicAdd(&s_probed[s], (unsigned long long)(end - beg));
-                if (!GLOBAL && (uint32_t)(end - beg) > a.big_row) {
-                    atomicOr(&s_flags[s], F_DEFER);
-                    end = beg;
-                }
+                it_slot[it] = (uint8_t)sl;
+                it_beg[it] = beg;
+                it_end[it] = end;
+                it_pb[it] = end > beg ? ((end - 1) >> 1) - (beg >> 1) + 1 : 0;
             }
-            it_slot[it] = (uint8_t)s;
-            it_beg[it] = beg;
-            it_end[it] = end;
-            it_pb[it] = end > beg ? ((end - 1) >> 1) - (beg >> 1) + 1 : 0;
         }
         block_sync<BLOCK>();
 
@@ -538,12 +571,12 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                 const int mid = (lo + hi + 1) >> 1;
                 if (it_pb[mid] <= base) lo = mid; else hi = mid - 1;
             }
-            uint4 pr[PPL];
             int pp[PPL], ps[PPL], pbeg[PPL], pend[PPL];
 #pragma unroll
             for (int g = 0; g < PPL; ++g) {
                 const int idx = base + g;
                 ps[g] = -1;
+                pp[g] = 0;
                 if (g >= ppl || idx >= total) continue;
                 while (it_pb[lo + 1] <= idx) ++lo; // it_pb[nitems] = total > idx
                 const int sl = it_slot[lo];
@@ -557,8 +590,13 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                 pp[g] = p;
                 pbeg[g] = it_beg[lo];
                 pend[g] = it_end[lo];
-                pr[g] = a.pairs[p];
             }
+            // every load is issued, unconditionally (a lane without a pair reads pair 0, which
+            // exists whenever the pass has a pair at all), before any is used: a load under a
+            // branch would make the compiler wait for it before the next one
+            uint4 pr[PPL];
+#pragma unroll
+            for (int g = 0; g < PPL; ++g) pr[g] = a.pairs[pp[g]];
 #pragma unroll
             for (int g = 0; g < PPL; ++g) {
                 if (g >= ppl) break;
@@ -612,13 +650,13 @@ __device__ void bitonic_lds(int32_t *buf, int P)
 }
 
 // Size classes for the segmented sorts: class c holds sizes up to 8 << c; classes 0 .. 3 use
-// segments of 8, 16, 32 or 64 lanes with one node per lane, classes 4 and 5 a whole wave
-// with 2 or 4 nodes per lane (up to SMALL_SORT).
-constexpr int GATHER_CLASSES = 6;
+// segments of 8, 16, 32 or 64 lanes with one node per lane, classes 4 .. 7 a whole wave with
+// 2, 4, 8 or 16 nodes per lane (up to SMALL_SORT).
+constexpr int GATHER_CLASSES = 8;
 
 __device__ __forceinline__ int size_class(uint32_t sz)
 {
-    return sz <= 8 ? 0 : sz <= 16 ? 1 : sz <= 32 ? 2 : sz <= 64 ? 3 : sz <= 128 ? 4 : 5;
+    return sz <= 8 ? 0 : sz <= 16 ? 1 : sz <= 32 ? 2 : sz <= 64 ? 3 : sz <= 128 ? 4 : sz <= 256 ? 5 : sz <= 512 ? 6 : 7;
 }
 
 // counts[c] = samples of class c (samples above SMALL_SORT are listed by the sampler)
@@ -1374,6 +1412,10 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
         hipLaunchKernelGGL((k_gather_sort<64, 2>), dim3(gg), dim3(64), 0, s, 4, cls.ptr, lists.ptr, sz_p, off_p,
                            sk.sample_ptr.ptr, staging.ptr, sk.nodes.ptr);
         hipLaunchKernelGGL((k_gather_sort<64, 4>), dim3(gg), dim3(64), 0, s, 5, cls.ptr, lists.ptr, sz_p, off_p,
+                           sk.sample_ptr.ptr, staging.ptr, sk.nodes.ptr);
+        hipLaunchKernelGGL((k_gather_sort<64, 8>), dim3(gg), dim3(64), 0, s, 6, cls.ptr, lists.ptr, sz_p, off_p,
+                           sk.sample_ptr.ptr, staging.ptr, sk.nodes.ptr);
+        hipLaunchKernelGGL((k_gather_sort<64, 16>), dim3(gg), dim3(64), 0, s, 7, cls.ptr, lists.ptr, sz_p, off_p,
                            sk.sample_ptr.ptr, staging.ptr, sk.nodes.ptr);
         SKIS_HIP_TRY(hipGetLastError());
     }

@@ -63,14 +63,35 @@ def _special_graph(seed=3, n=400, m=3000):
     return inputs.edges_to_in_csr(n, src[keep], dst[keep], w)
 
 
-@pytest.mark.parametrize("which", ["cl15k_wc", "special", "tri_small"])
+def _long_rows_graph():
+    # rows on both sides of the one-thread limit (256 in-edges), of a block (64) and of a
+    # workgroup chunk (256 blocks = 16384 in-edges); one row holds w = 0 and w = 1 edges
+    rng = np.random.Generator(np.random.PCG64(17))
+    lens = [63, 64, 65, 256, 257, 1000, 16383, 16384, 16385, 2 * 16384 + 65, 40000]
+    vals = np.array([1e-3, 1e-4, 1e-5, 3e-4], np.float32) # the products stay well above 0
+    src, dst, ws = [], [], []
+    n = len(lens) + max(lens)
+    for v, d in enumerate(lens):
+        x = vals[rng.integers(0, len(vals), d)]
+        if d == 1000:
+            x[500] = 0.0
+            x[700] = 1.0
+        src += list(range(len(lens), len(lens) + d))
+        dst += [v] * d
+        ws.append(x)
+    return inputs.edges_to_in_csr(n, src, dst, np.concatenate(ws))
+
+
+@pytest.mark.parametrize("which", ["cl15k_wc", "special", "tri_small", "long_rows", "cl1m_wc", "cl4m_tri"])
 def test_preprocess_bit_exact(skis, which):
     _say("preprocess", which)
-    if which == "cl15k_wc":
-        g = inputs.workload_graph("cl15k_wc")
+    if which in ("cl15k_wc", "cl1m_wc", "cl4m_tri"):
+        g = inputs.workload_graph(which)
         row_ptr, col, w = g.row_ptr, g.col, g.w
     elif which == "special":
         row_ptr, col, w = _special_graph()
+    elif which == "long_rows":
+        row_ptr, col, w = _long_rows_graph()
     else:
         g = inputs.chung_lu_graph(20000, 200000, 2.0, 9, "tri", cache=False)
         row_ptr, col, w = g.row_ptr, g.col, g.w
