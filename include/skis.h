@@ -102,11 +102,11 @@ int skis_preprocess(int32_t n, int64_t m, const int32_t *row_ptr, const int32_t 
  * Sample j (0 <= j < num_samples) draws its root by the alias table, its first live
  * in-edge i* by Eq. (probn) (theta = U * gamma_root, i* = first edge with 1-P[e] > theta),
  * flips independent coins for the root's later in-edges (earlier ones are dead by the
- * bucket definition), then runs the reverse BFS of Alg. 1 lines 7-11.  Each R_j is stored
+ * bucket definition), then runs the reverse BFS of Alg. 1.  Each R_j is stored
  * sorted ascending; the sketch also keeps root[j], probed[j] = sum_{x in R_j} indeg(x),
  * q[v] and Gamma.  Inputs are borrowed for the duration of the call only.
  * opt (host) may be NULL.  Blocking.  *out (host) receives the sketch.
- * Errors: SKIS_EINVAL (malformed graph, num_samples = 0, n <= 0, m < 0 or m >= 2^31),
+ * Errors: SKIS_EINVAL (malformed graph, num_samples = 0 or >= 2^31, n <= 0, m < 0 or m >= 2^31),
  * SKIS_ENOMEM, SKIS_EHIP.  Returns SKIS_WDEGENERATE (and an empty sketch) when Gamma = 0.
  */
 int skis_build_sketch(int32_t n, int64_t m, const int32_t *row_ptr, const int32_t *col, const float *w,

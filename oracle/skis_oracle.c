@@ -265,7 +265,7 @@ static int64_t ora_one_sample(const ora_ctx *g, uint64_t j, unsigned char *mark,
     uint64_t X, Y;
     int32_t root;
 
-    /* Alg. 1 line 1: root with probability gamma_v / Gamma (Eq. probu), by the alias
+    /* Alg. 1, the root: drawn with probability gamma_v / Gamma (Eq. probu), by the alias
      * table over integer weights; in RIS mode a uniform root (Sec. 2.3.1 step 1). */
     draw2(g->seed, 0u, j, 0u, &X, &Y);
     uint64_t b = mulhi64(X, (uint64_t)g->n);
@@ -281,7 +281,7 @@ static int64_t ora_one_sample(const ora_ctx *g, uint64_t j, unsigned char *mark,
     const int32_t rs = g->row_ptr[root], re = g->row_ptr[root + 1];
     int32_t first_scan = rs; /* first in-edge of the root that still gets a coin */
     if (!g->ris_mode) {
-        /* Alg. 1 line 2, Eq. (probn): bucket B_i has probability
+        /* Alg. 1, the first live in-edge, Eq. (probn): bucket B_i has probability
          * prod_{t<i}(1-w_t) w_i / gamma = (P_{i-1} - P_i) / gamma.  With theta uniform in
          * [0, gamma), B_i is the first i whose cumulative mass 1 - P_i exceeds theta. */
         draw2(g->seed, 0u, j, 1u, &X, &Y);
@@ -296,13 +296,13 @@ static int64_t ora_one_sample(const ora_ctx *g, uint64_t j, unsigned char *mark,
             for (int32_t e = re - 1; e >= rs; --e)
                 if (g->w[e] > 0.0f) { istar = e; break; }
         }
-        /* Alg. 1 line 3: u_i joins R_j and the queue. */
+        /* Alg. 1: u_i joins R_j and the queue. */
         int32_t u = g->col[istar];
         if (!mark[u]) {
             mark[u] = 1;
             if (vec_push(out, u)) return ORA_ENOMEM;
         }
-        /* Alg. 1 lines 4-6 with the bucket reading: in-edges before u_i are dead (that is
+        /* Alg. 1, the root's other in-edges, with the bucket reading: in-edges before u_i are dead (that is
          * what B_i means), in-edges after it flip their own coins. */
         first_scan = istar + 1;
     }
@@ -313,7 +313,7 @@ static int64_t ora_one_sample(const ora_ctx *g, uint64_t j, unsigned char *mark,
             if (vec_push(out, u)) return ORA_ENOMEM;
         }
     }
-    /* Alg. 1 lines 7-11: FIFO reverse BFS; the root itself is not queued again. */
+    /* Alg. 1, the FIFO reverse BFS; the root itself is not queued again. */
     for (int64_t head = base + 1; head < out->len; ++head) {
         int32_t x = out->nodes[head];
         for (int32_t e = g->row_ptr[x]; e < g->row_ptr[x + 1]; ++e) {

@@ -205,6 +205,8 @@ int skis_build_sketch(int32_t n, int64_t m, const int32_t *row_ptr, const int32_
         *out = nullptr;
         check_graph_args(n, m, row_ptr, col, w);
         if (num_samples == 0) throw skis::Error{SKIS_EINVAL, "num_samples must be positive"};
+        if (num_samples > (uint64_t)INT32_MAX)
+            throw skis::Error{SKIS_EINVAL, "num_samples must be below 2^31 (sample ids are 32-bit)"};
         skis_options opt;
         skis_default_options(&opt);
         if (opt_in) {
@@ -256,6 +258,7 @@ int skis_build_sketch(int32_t n, int64_t m, const int32_t *row_ptr, const int32_
                     cfg.staging_entries = opt.staging_entries;
                     cfg.chunk = opt.chunk_samples;
                     cfg.ppl = opt.pairs_per_lane;
+                    cfg.owners = opt.build_inverse_index != 0;
                     skis::sample_and_compact(sk.arena, prep, n, m, num_samples, seed, cfg, sk, stream);
                 }
                 // q moves into the sketch only after every kernel that reads prep.q has run

@@ -107,6 +107,7 @@ struct Sketch {
     DevBuf<uint64_t> probed;      // [T]
     DevBuf<int64_t> node_ptr;     // [n+1]
     DevBuf<int32_t> node_samples; // [entries]
+    DevBuf<int32_t> owner;        // [entries] sample id of each entry; built for and consumed by the transpose
     DevBuf<int32_t> hot_id;       // [n] index in hot_node, or -1 (frequent nodes of the sketch)
     DevBuf<int32_t> hot_node;     // [nhot]
     int nhot = 0;
@@ -149,6 +150,7 @@ struct SampleConfig {
     uint64_t staging_entries = 0;
     uint64_t chunk = 0; // captured form: samples per replay of the chain (0: 2^22)
     uint32_t ppl = 2;   // edge pairs per lane per sweep in the first tier
+    bool owners = false; // also write the sample id of every entry (Sketch::owner) for the transpose
 };
 
 void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, uint64_t T, uint64_t seed,
@@ -157,8 +159,10 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
 void build_inverse(Sketch &sk, hipStream_t s);
 
 // node_ptr[n+1] and node_samples[N] (each list ascending) of the N-entry sketch.
-void radix_transpose(Arena &arena, const int64_t *sample_ptr, const int32_t *nodes, uint64_t T, uint64_t N,
-                     int32_t n, int64_t *node_ptr, int32_t *node_samples, hipStream_t s);
+// owner: the sample id of every entry (written by the compaction), or null to have them
+// computed here; its contents are overwritten.  deg[n] receives each node's entry count.
+void radix_transpose(Arena &arena, const int64_t *sample_ptr, const int32_t *nodes, int32_t *owner, uint64_t T,
+                     uint64_t N, int32_t n, int64_t *node_ptr, int32_t *node_samples, uint32_t *deg, hipStream_t s);
 
 // ---------------------------------------------------------------------------------
 // Device-wide scans (exclusive), T in {uint32_t, uint64_t, int64_t, u128}.

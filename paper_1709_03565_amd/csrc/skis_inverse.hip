@@ -47,16 +47,6 @@ __global__ __launch_bounds__(256) void k_inv_hot_ids(int32_t n, const uint32_t *
     }
 }
 
-// deg[v] = |H(v)| from the offsets (saturated to 32 bits)
-__global__ __launch_bounds__(256) void k_inv_degrees(int32_t n, const int64_t *__restrict__ node_ptr,
-                                                     uint32_t *__restrict__ deg)
-{
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t d = node_ptr[v + 1] - node_ptr[v];
-        deg[v] = d > 0xFFFFFFFFll ? 0xFFFFFFFFu : (uint32_t)d;
-    }
-}
-
 template <typename T>
 __global__ __launch_bounds__(256) void k_inv_fill(uint64_t count, T *__restrict__ p, T v)
 {
@@ -89,11 +79,13 @@ void build_inverse(Sketch &sk, hipStream_t s)
         sk.has_inverse = true;
         return;
     }
-    radix_transpose(arena, sk.sample_ptr.ptr, sk.nodes.ptr, T, sk.entries, n, sk.node_ptr.ptr, sk.node_samples.ptr, s);
+    radix_transpose(arena, sk.sample_ptr.ptr, sk.nodes.ptr, sk.owner.count == sk.entries ? sk.owner.ptr : nullptr, T,
+                    sk.entries, n, sk.node_ptr.ptr, sk.node_samples.ptr, cnt.ptr, s);
+    sk.owner.reset();
 
     // hot nodes from the exact degrees: the smallest power-of-two threshold (at least 16
     // samples) that keeps at most INV_HOT nodes
-    hipLaunchKernelGGL(k_inv_degrees, dim3(grid_inv(n, 256)), dim3(256), 0, s, n, sk.node_ptr.ptr, cnt.ptr);
+    // cnt holds the exact degrees (the transpose counted them)
     DevBuf<unsigned long long> hist;
     hist.alloc(arena, 33);
     hipLaunchKernelGGL(k_inv_fill<unsigned long long>, dim3(1), dim3(64), 0, s, (uint64_t)33, hist.ptr, 0ull);

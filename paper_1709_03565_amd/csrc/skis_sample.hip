@@ -131,7 +131,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
 {
     constexpr int IDBATCH = id_batch<S>();
     static_assert(GLOBAL || HCAP > RCAP, "the hash must be larger than the node list");
-    static_assert(GLOBAL || HCAP <= 65535, "list entries are 16-bit hash slot indexes");
+    static_assert(GLOBAL || HCAP <= 65535, "list entries are 8- or 16-bit hash slot indexes");
     constexpr int HSZ = GLOBAL ? 1 : S * HCAP;
     constexpr int LSZ = GLOBAL ? 1 : S * RCAP;
     constexpr int IPT = (ICAP + BLOCK - 1) / BLOCK;
@@ -140,8 +140,9 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
 
     __shared__ int32_t sh_hash[HSZ];
     // LDS tiers: the node list holds the hash slot of each node in discovery order (the
-    // slot holds the node id), half the bytes of a list of ids
-    __shared__ uint16_t sh_lidx[LSZ];
+    // slot holds the node id), a quarter or half the bytes of a list of ids
+    using LIdx = std::conditional_t<(HCAP <= 256), uint8_t, uint16_t>;
+    __shared__ LIdx sh_lidx[LSZ];
     __shared__ uint32_t s_idx[S];
     __shared__ int32_t s_count[S], s_cursor[S], s_flags[S], s_rib[S], s_rie[S];
     __shared__ unsigned long long s_probed[S];
@@ -193,11 +194,12 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
         } else {
             int32_t *H = sh_hash + s * HCAP;
             uint32_t h = hash_slot(u);
+#pragma unroll 1
             for (int k = 0; k < HCAP; ++k) {
                 const int32_t old = atomicCAS(&H[h], -1, u);
                 if (old == -1) {
                     const int pos = atomicAdd(&s_count[s], 1);
-                    if (pos < RCAP) sh_lidx[s * RCAP + pos] = (uint16_t)h;
+                    if (pos < RCAP) sh_lidx[s * RCAP + pos] = (LIdx)h;
                     else atomicOr(&s_flags[s], F_DEFER);
                     return;
                 }
@@ -364,7 +366,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                             uint32_t h = hash_slot(keys[t]);
                             while (H[h] != -1) h = h + 1 == (uint32_t)HCAP ? 0u : h + 1;
                             H[h] = keys[t];
-                            sh_lidx[s * RCAP + t] = (uint16_t)h;
+                            sh_lidx[s * RCAP + t] = (LIdx)h;
                         }
                     }
                     f = nf;
@@ -597,6 +599,9 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
             uint4 pr[PPL];
 #pragma unroll
             for (int g = 0; g < PPL; ++g) pr[g] = a.pairs[pp[g]];
+            // coins first; the live edges (bit 2g + h: edge h of pair g) are then visited
+            // through one call site, so the hash probing is not inlined 2 * PPL times
+            uint32_t live = 0u;
 #pragma unroll
             for (int g = 0; g < PPL; ++g) {
                 if (g >= ppl) break;
@@ -606,8 +611,23 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                 uint64_t X, Y;
                 philox2x64((uint32_t)pp[g], (uint32_t)j, (uint32_t)(j >> 32), TAG_EDGE, a.seed_lo, a.seed_hi, X, Y);
                 const int e0 = 2 * pp[g];
-                if (e0 >= pbeg[g] && coin_live(pr[g].y, X)) visit(sl, (int32_t)pr[g].x);
-                if (e0 + 1 < pend[g] && coin_live(pr[g].w, Y)) visit(sl, (int32_t)pr[g].z);
+                if (e0 >= pbeg[g] && coin_live(pr[g].y, X)) live |= 1u << (2 * g);
+                if (e0 + 1 < pend[g] && coin_live(pr[g].w, Y)) live |= 2u << (2 * g);
+            }
+            static_assert(PPL <= 4, "the live-edge switch covers up to 4 pairs per lane");
+            while (live) {
+                const int c = __ffs(live) - 1;
+                live &= live - 1u;
+                uint4 q;
+                int sl;
+                // a switch, not an index into pr[]: the arrays stay in registers
+                switch (c >> 1) {
+                case 0: q = pr[0]; sl = ps[0]; break;
+                case 1: q = pr[PPL > 1 ? 1 : 0]; sl = ps[PPL > 1 ? 1 : 0]; break;
+                case 2: q = pr[PPL > 2 ? 2 : 0]; sl = ps[PPL > 2 ? 2 : 0]; break;
+                default: q = pr[PPL > 3 ? 3 : 0]; sl = ps[PPL > 3 ? 3 : 0]; break;
+                }
+                visit(sl, (int32_t)((c & 1) ? q.z : q.x));
             }
         }
         block_sync<BLOCK>();
@@ -738,7 +758,8 @@ __global__ __launch_bounds__(64) void k_gather_sort(int cls, const unsigned long
                                                     const uint32_t *__restrict__ size,
                                                     const unsigned long long *__restrict__ off,
                                                     const int64_t *__restrict__ sptr,
-                                                    const int32_t *__restrict__ staging, int32_t *__restrict__ nodes)
+                                                    const int32_t *__restrict__ staging, int32_t *__restrict__ nodes,
+                                                    int32_t *__restrict__ owner)
 {
     constexpr int G = 64 / W, P = W * R;
     const int lane = threadIdx.x, seg = lane / W, t = lane % W;
@@ -746,25 +767,25 @@ __global__ __launch_bounds__(64) void k_gather_sort(int cls, const unsigned long
     for (int k = 0; k < cls; ++k) base += counts[k];
     const unsigned long long cnt = counts[cls];
     const unsigned long long stride = (unsigned long long)gridDim.x * G;
-    uint32_t sz = 0;
+    uint32_t sz = 0, id = 0;
     unsigned long long o = 0;
     int64_t dp = 0;
     unsigned long long g0 = (unsigned long long)blockIdx.x * G;
     if (g0 + seg < cnt) {
-        const uint32_t i = lists[base + g0 + seg];
-        sz = size[i];
-        o = off[i];
-        dp = sptr[i];
+        id = lists[base + g0 + seg];
+        sz = size[id];
+        o = off[id];
+        dp = sptr[id];
     }
     for (; g0 < cnt; g0 += stride) {
-        uint32_t nsz = 0;
+        uint32_t nsz = 0, nid = 0;
         unsigned long long no = 0;
         int64_t ndp = 0;
         if (g0 + stride + seg < cnt) {
-            const uint32_t i = lists[base + g0 + stride + seg];
-            nsz = size[i];
-            no = off[i];
-            ndp = sptr[i];
+            nid = lists[base + g0 + stride + seg];
+            nsz = size[nid];
+            no = off[nid];
+            ndp = sptr[nid];
         }
         int32_t v[R];
 #pragma unroll
@@ -800,9 +821,13 @@ __global__ __launch_bounds__(64) void k_gather_sort(int cls, const unsigned long
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int e = t * R + r;
-            if (e < (int)sz) nodes[dp + e] = v[r];
+            if (e < (int)sz) {
+                nodes[dp + e] = v[r];
+                if (owner) owner[dp + e] = (int32_t)id;
+            }
         }
         sz = nsz;
+        id = nid;
         o = no;
         dp = ndp;
     }
@@ -813,7 +838,7 @@ __global__ __launch_bounds__(256) void k_gather_medium(uint64_t count, const uin
                                                        const unsigned long long *__restrict__ off,
                                                        const int64_t *__restrict__ sptr,
                                                        const int32_t *__restrict__ staging,
-                                                       int32_t *__restrict__ nodes)
+                                                       int32_t *__restrict__ nodes, int32_t *__restrict__ owner)
 {
     __shared__ int32_t buf[SORT_LDS_MAX];
     for (uint64_t k = blockIdx.x; k < count; k += gridDim.x) {
@@ -821,6 +846,8 @@ __global__ __launch_bounds__(256) void k_gather_medium(uint64_t count, const uin
         const int sz = (int)size[i];
         const int32_t *src = staging + off[i];
         int32_t *dst = nodes + sptr[i];
+        if (owner)
+            for (int t = threadIdx.x; t < sz; t += 256) owner[sptr[i] + t] = (int32_t)i;
         if (sz > SORT_LDS_MAX) { // written sorted by the global tier
             for (int t = threadIdx.x; t < sz; t += 256) dst[t] = src[t];
             continue;
@@ -1386,6 +1413,9 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
     SKIS_HIP_TRY(hipStreamSynchronize(s));
     sk.entries = (uint64_t)total;
     sk.nodes.alloc(arena, (size_t)total);
+    if (cfg.owners) sk.owner.alloc(arena, (size_t)total);
+    else sk.owner.reset();
+    int32_t *const owner_p = cfg.owners ? sk.owner.ptr : nullptr;
     {
         // samples by size class, then one segmented sort per class
         DevBuf<unsigned long long> cls;
@@ -1402,27 +1432,27 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
         const uint32_t *const sz_p = out_size.ptr;
         const unsigned long long *const off_p = out_off.ptr;
         hipLaunchKernelGGL((k_gather_sort<8, 1>), dim3(gg), dim3(64), 0, s, 0, cls.ptr, lists.ptr, sz_p, off_p,
-                           sk.sample_ptr.ptr, staging.ptr, sk.nodes.ptr);
+                           sk.sample_ptr.ptr, staging.ptr, sk.nodes.ptr, owner_p);
         hipLaunchKernelGGL((k_gather_sort<16, 1>), dim3(gg), dim3(64), 0, s, 1, cls.ptr, lists.ptr, sz_p, off_p,
-                           sk.sample_ptr.ptr, staging.ptr, sk.nodes.ptr);
+                           sk.sample_ptr.ptr, staging.ptr, sk.nodes.ptr, owner_p);
         hipLaunchKernelGGL((k_gather_sort<32, 1>), dim3(gg), dim3(64), 0, s, 2, cls.ptr, lists.ptr, sz_p, off_p,
-                           sk.sample_ptr.ptr, staging.ptr, sk.nodes.ptr);
+                           sk.sample_ptr.ptr, staging.ptr, sk.nodes.ptr, owner_p);
         hipLaunchKernelGGL((k_gather_sort<64, 1>), dim3(gg), dim3(64), 0, s, 3, cls.ptr, lists.ptr, sz_p, off_p,
-                           sk.sample_ptr.ptr, staging.ptr, sk.nodes.ptr);
+                           sk.sample_ptr.ptr, staging.ptr, sk.nodes.ptr, owner_p);
         hipLaunchKernelGGL((k_gather_sort<64, 2>), dim3(gg), dim3(64), 0, s, 4, cls.ptr, lists.ptr, sz_p, off_p,
-                           sk.sample_ptr.ptr, staging.ptr, sk.nodes.ptr);
+                           sk.sample_ptr.ptr, staging.ptr, sk.nodes.ptr, owner_p);
         hipLaunchKernelGGL((k_gather_sort<64, 4>), dim3(gg), dim3(64), 0, s, 5, cls.ptr, lists.ptr, sz_p, off_p,
-                           sk.sample_ptr.ptr, staging.ptr, sk.nodes.ptr);
+                           sk.sample_ptr.ptr, staging.ptr, sk.nodes.ptr, owner_p);
         hipLaunchKernelGGL((k_gather_sort<64, 8>), dim3(gg), dim3(64), 0, s, 6, cls.ptr, lists.ptr, sz_p, off_p,
-                           sk.sample_ptr.ptr, staging.ptr, sk.nodes.ptr);
+                           sk.sample_ptr.ptr, staging.ptr, sk.nodes.ptr, owner_p);
         hipLaunchKernelGGL((k_gather_sort<64, 16>), dim3(gg), dim3(64), 0, s, 7, cls.ptr, lists.ptr, sz_p, off_p,
-                           sk.sample_ptr.ptr, staging.ptr, sk.nodes.ptr);
+                           sk.sample_ptr.ptr, staging.ptr, sk.nodes.ptr, owner_p);
         SKIS_HIP_TRY(hipGetLastError());
     }
     if (hc.n_medium > 0) {
         hipLaunchKernelGGL(k_gather_medium, dim3(grid_cap(hc.n_medium, 1, 4)), dim3(256), 0, s,
                            (uint64_t)hc.n_medium, medium.ptr, out_size.ptr, out_off.ptr, sk.sample_ptr.ptr,
-                           staging.ptr, sk.nodes.ptr);
+                           staging.ptr, sk.nodes.ptr, owner_p);
         SKIS_HIP_TRY(hipGetLastError());
     }
     sk.roots.alloc(arena, count);

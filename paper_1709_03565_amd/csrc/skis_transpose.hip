@@ -11,7 +11,8 @@
 //                 tile is sorted by digit in LDS (stable) and written out in order, so each
 //                 digit's run of the tile goes to its offset with consecutive lanes.
 // The input is in sample order, so every list H(v) comes out sorted by sample id.
-// k_rs_bounds then finds where each node's run starts.
+// The last pass writes only the sample ids and counts each node's entries; node_ptr is the
+// exclusive scan of those counts.
 #include <algorithm>
 
 #include "skis_internal.h"
@@ -60,12 +61,14 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_hist(uint64_t N, const int32_t 
     }
 }
 
-// Lanes of the wave holding the same digit d as this lane (among the valid ones).
-__device__ __forceinline__ unsigned long long same_digit_mask(bool valid, uint32_t d)
+// Lanes of the wave holding the same digit d as this lane (among the valid ones); digits
+// have `bits` significant bits (uniform), the others are zero.
+__device__ __forceinline__ unsigned long long same_digit_mask(bool valid, uint32_t d, int bits)
 {
     unsigned long long m = __ballot(valid);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
+        if (b >= bits) break;
         const bool bit = (d >> b) & 1u;
         const unsigned long long bb = __ballot(bit);
         m &= bit ? bb : ~bb;
@@ -75,8 +78,9 @@ __device__ __forceinline__ unsigned long long same_digit_mask(bool valid, uint32
 
 __global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(uint64_t N, const int32_t *__restrict__ kin,
                                                          const int32_t *__restrict__ vin, int32_t *__restrict__ kout,
-                                                         int32_t *__restrict__ vout, int shift, uint64_t ntiles,
-                                                         const int64_t *__restrict__ OFF)
+                                                         int32_t *__restrict__ vout, int shift, int bits,
+                                                         uint64_t ntiles, const int64_t *__restrict__ OFF,
+                                                         uint32_t *__restrict__ deg)
 {
     __shared__ long long base[256];        // output offset of each digit for this tile
     __shared__ uint32_t tstart[256 + 1];   // first tile-local position of each digit
@@ -86,33 +90,41 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(uint64_t N, const int32
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const unsigned long long lt = (1ull << lane) - 1ull;
     constexpr int R = RS_SPAN / 64;
-    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        base[threadIdx.x] = OFF[(uint64_t)threadIdx.x * ntiles + tile];
-        for (int i = threadIdx.x; i < RS_WAVES * 256; i += RS_BLOCK) (&cnt[0][0])[i] = 0u;
+    constexpr int PER = RS_TILE / RS_BLOCK;
+    // the next tile's entries and digit offsets are loaded while this one is sorted and
+    // written (unconditional loads: an index past the end reads the last entry, unused)
+    int32_t kr[R], vr[R];
+    long long bnext = 0;
+    uint64_t tile = blockIdx.x;
+    if (tile < ntiles) {
+        const uint64_t s0 = tile * RS_TILE + (uint64_t)w * RS_SPAN;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint64_t e = min(s0 + (uint64_t)r * 64 + lane, N - 1);
+            kr[r] = kin[e];
+            vr[r] = vin[e];
+        }
+        bnext = OFF[(uint64_t)threadIdx.x * ntiles + tile];
+    }
+    for (; tile < ntiles; tile += gridDim.x) {
         const uint64_t t0 = tile * RS_TILE;
         const uint64_t s0 = t0 + (uint64_t)w * RS_SPAN;
         const int nvalid = (int)min((uint64_t)RS_TILE, N - t0);
-        {
-            // the wave's span: all loads in flight at once, then staged in LDS
-            int32_t kr[R], vr[R];
+        base[threadIdx.x] = bnext;
+        for (int i = threadIdx.x; i < RS_WAVES * 256; i += RS_BLOCK) (&cnt[0][0])[i] = 0u;
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const uint64_t e = s0 + (uint64_t)r * 64 + lane;
-                kr[r] = e < N ? kin[e] : 0;
-                vr[r] = e < N ? vin[e] : 0;
-            }
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                sk[w * RS_SPAN + r * 64 + lane] = kr[r];
-                sv[w * RS_SPAN + r * 64 + lane] = vr[r];
-            }
+        for (int r = 0; r < R; ++r) {
+            sk[w * RS_SPAN + r * 64 + lane] = kr[r];
+            sv[w * RS_SPAN + r * 64 + lane] = vr[r];
         }
+        const uint64_t tn = tile + gridDim.x;
+        if (tn < ntiles) bnext = OFF[(uint64_t)threadIdx.x * ntiles + tn];
         __syncthreads();
         // phase 1: this wave's digit counts (one leader per digit and round adds)
         for (int r = 0; r < R; ++r) {
             const bool valid = s0 + (uint64_t)r * 64 + lane < N;
             const uint32_t d = valid ? (((uint32_t)sk[w * RS_SPAN + r * 64 + lane] >> shift) & 255u) : 0u;
-            const unsigned long long m = same_digit_mask(valid, d);
+            const unsigned long long m = same_digit_mask(valid, d, bits);
             if (valid && !(m & lt)) cnt[w][d] += (uint32_t)__popcll(m);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
@@ -136,14 +148,13 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(uint64_t N, const int32
         }
         __syncthreads();
         // phase 2: tile-local positions (stable), kept in registers until every wave has read
-        int32_t kr[R], vr[R];
         uint32_t lp[R];
         for (int r = 0; r < R; ++r) {
             const bool valid = s0 + (uint64_t)r * 64 + lane < N;
             kr[r] = sk[w * RS_SPAN + r * 64 + lane];
             vr[r] = sv[w * RS_SPAN + r * 64 + lane];
             const uint32_t d = valid ? (((uint32_t)kr[r] >> shift) & 255u) : 0u;
-            const unsigned long long m = same_digit_mask(valid, d);
+            const unsigned long long m = same_digit_mask(valid, d, bits);
             lp[r] = valid ? cnt[w][d] + (uint32_t)__popcll(m & lt) : 0xFFFFFFFFu;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
@@ -160,27 +171,46 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(uint64_t N, const int32
                 sv[lp[r]] = vr[r];
             }
         __syncthreads();
-        // phase 3: the sorted tile goes out in order, each digit's run to its offset
-        for (int i = threadIdx.x; i < nvalid; i += RS_BLOCK) {
-            const int32_t key = sk[i];
-            const uint32_t d = ((uint32_t)key >> shift) & 255u;
-            const long long pos = base[d] + (long long)(i - (int)tstart[d]);
-            kout[pos] = key;
-            vout[pos] = sv[i];
+        // the next tile's loads go out before this one is written
+        if (tn < ntiles) {
+            const uint64_t n0 = tn * RS_TILE + (uint64_t)w * RS_SPAN;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const uint64_t e = min(n0 + (uint64_t)r * 64 + lane, N - 1);
+                kr[r] = kin[e];
+                vr[r] = vin[e];
+            }
+        }
+        // phase 3: the sorted tile goes out in order, each digit's run to its offset.  In the
+        // last pass (deg set) the keys are not written: each run of equal keys within a
+        // digit's run adds its length to deg[key], as -first at its first element and
+        // last + 1 at its last one (the pass's keys are sorted within a digit's run).
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int i = k * RS_BLOCK + threadIdx.x;
+            if (i < nvalid) {
+                const int32_t key = sk[i];
+                const uint32_t d = ((uint32_t)key >> shift) & 255u;
+                const long long pos = base[d] + (long long)(i - (int)tstart[d]);
+                vout[pos] = sv[i];
+                if (!deg) {
+                    kout[pos] = key;
+                } else {
+                    const bool first = i == (int)tstart[d] || sk[i - 1] != key;
+                    const bool last = i + 1 == (int)tstart[d + 1] || sk[i + 1] != key;
+                    if (first) atomicAdd(&deg[key], (uint32_t)(-i));
+                    if (last) atomicAdd(&deg[key], (uint32_t)(i + 1));
+                }
+            }
         }
         __syncthreads();
     }
 }
 
-// node_ptr[v] = first position of key v in the sorted keys (N past the last), for all v.
-__global__ __launch_bounds__(256) void k_rs_bounds(uint64_t N, int32_t n, const int32_t *__restrict__ keys,
-                                                   int64_t *__restrict__ node_ptr)
+__global__ __launch_bounds__(256) void k_rs_fill_u32(uint64_t count, uint32_t *__restrict__ p, uint32_t v)
 {
-    for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p <= N; p += (uint64_t)gridDim.x * blockDim.x) {
-        const int32_t prev = p > 0 ? keys[p - 1] : -1;
-        const int32_t cur = p < N ? keys[p] : n;
-        for (int32_t v = prev + 1; v <= cur && v <= n; ++v) node_ptr[v] = (int64_t)p;
-    }
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
 }
 
 static unsigned grid_rs(uint64_t items, int block, int per_cu = 8)
@@ -191,8 +221,8 @@ static unsigned grid_rs(uint64_t items, int block, int per_cu = 8)
     return (unsigned)(g > 0 ? g : 1);
 }
 
-void radix_transpose(Arena &arena, const int64_t *sample_ptr, const int32_t *nodes, uint64_t T, uint64_t N,
-                     int32_t n, int64_t *node_ptr, int32_t *node_samples, hipStream_t s)
+void radix_transpose(Arena &arena, const int64_t *sample_ptr, const int32_t *nodes, int32_t *owner, uint64_t T,
+                     uint64_t N, int32_t n, int64_t *node_ptr, int32_t *node_samples, uint32_t *deg, hipStream_t s)
 {
     if (N == 0 || T == 0) throw Error{SKIS_EHIP, "internal error: empty transpose"};
     int bits = 1;
@@ -203,32 +233,40 @@ void radix_transpose(Arena &arena, const int64_t *sample_ptr, const int32_t *nod
     DevBuf<uint32_t> H;
     DevBuf<int64_t> OFF;
     ka.alloc(arena, N);
-    va.alloc(arena, N);
+    int32_t *vals = owner; // the sample id of every entry, scratch after the first pass
+    if (!vals) {
+        va.alloc(arena, N);
+        vals = va.ptr;
+    }
     if (passes > 1) vb.alloc(arena, N);
     kb.alloc(arena, N);
     H.alloc(arena, 256 * ntiles);
     OFF.alloc(arena, 256 * ntiles + 1);
-    hipLaunchKernelGGL(k_rs_vals, dim3(grid_rs(T * 64, 256, 16)), dim3(256), 0, s, T, sample_ptr, va.ptr);
-    SKIS_HIP_TRY(hipGetLastError());
+    if (!owner) {
+        hipLaunchKernelGGL(k_rs_vals, dim3(grid_rs(T * 64, 256, 16)), dim3(256), 0, s, T, sample_ptr, vals);
+        SKIS_HIP_TRY(hipGetLastError());
+    }
     const unsigned gt = (unsigned)std::min<uint64_t>(ntiles, (uint64_t)device_cu_count() * 8);
     // pass p reads (kin, vin) and writes (kout, vout); the sketch's nodes are the first keys,
     // the last pass writes the values straight into node_samples
     const int32_t *kin = nodes;
-    const int32_t *vin = va.ptr;
+    const int32_t *vin = vals;
+    // the last pass counts each node's entries instead of writing the sorted keys
+    hipLaunchKernelGGL(k_rs_fill_u32, dim3(grid_rs(n, 256, 4)), dim3(256), 0, s, (uint64_t)n, deg, 0u);
     for (int p = 0; p < passes; ++p) {
-        int32_t *kout = (p & 1) ? ka.ptr : kb.ptr;
-        int32_t *vout = (p == passes - 1) ? node_samples : ((p & 1) ? va.ptr : vb.ptr);
+        const bool lastp = p == passes - 1;
+        int32_t *kout = lastp ? nullptr : ((p & 1) ? ka.ptr : kb.ptr);
+        int32_t *vout = lastp ? node_samples : ((p & 1) ? vals : vb.ptr);
         hipLaunchKernelGGL(k_rs_hist, dim3(gt), dim3(RS_BLOCK), 0, s, N, kin, 8 * p, ntiles, H.ptr);
         SKIS_HIP_TRY(hipGetLastError());
         excl_scan_u32_to_i64(arena, H.ptr, OFF.ptr, (int64_t)(256 * ntiles), OFF.ptr + 256 * ntiles, s);
-        hipLaunchKernelGGL(k_rs_scatter, dim3(gt), dim3(RS_BLOCK), 0, s, N, kin, vin, kout, vout, 8 * p, ntiles,
-                           OFF.ptr);
+        hipLaunchKernelGGL(k_rs_scatter, dim3(gt), dim3(RS_BLOCK), 0, s, N, kin, vin, kout, vout, 8 * p,
+                           std::min(8, bits - 8 * p), ntiles, OFF.ptr, lastp ? deg : nullptr);
         SKIS_HIP_TRY(hipGetLastError());
         kin = kout;
         vin = vout;
     }
-    hipLaunchKernelGGL(k_rs_bounds, dim3(grid_rs(N + 1, 256, 16)), dim3(256), 0, s, N, n, kin, node_ptr);
-    SKIS_HIP_TRY(hipGetLastError());
+    excl_scan_u32_to_i64(arena, deg, node_ptr, n, node_ptr + n, s);
     SKIS_HIP_TRY(hipStreamSynchronize(s)); // the temporaries are released on return
 }
 

@@ -114,7 +114,7 @@ def test_single_edge_deterministic_estimates():
 
 def test_deterministic_weights_match_textbook_reverse_bfs():
     # w in {0, 1}: each sample is exactly the set of nodes that reach the root over
-    # certain edges (Alg. 1 lines 7-11 with every coin decided).
+    # certain edges (the reverse BFS of Alg. 1 with every coin decided).
     rng = np.random.Generator(np.random.PCG64(21))
     n, m = 300, 900
     src = rng.integers(0, n, m)
@@ -241,7 +241,7 @@ def test_invariants_and_thread_independence():
     deg = np.diff(g.row_ptr)
     for i in range(T):
         R = a.sample(i)
-        assert len(R) >= 2  # non-singular (Sec. 1, Alg. 1 line 3)
+        assert len(R) >= 2  # non-singular (Sec. 1, Alg. 1)
         assert np.all(np.diff(R) > 0)  # sorted, distinct
         assert a.roots[i] in R
         assert int(a.probed[i]) == int(deg[R].sum())
