@@ -45,6 +45,73 @@ static bool pool_ready()
     return ok;
 }
 
+// Idle device blocks shared by every arena of the process (per device, up to CACHE_KEEP
+// bytes): a block enters only when no queued work can use it any more (after a stream or
+// device synchronisation), so an arena on any stream may take it as it is.  Taking one costs
+// no driver call; the stream-ordered free and allocation cost tens to hundreds of microseconds
+// of host time each.
+constexpr uint64_t CACHE_KEEP = 32ull << 30;
+constexpr int CACHE_DEVICES = 64;
+
+struct CachedBlock {
+    void *p;
+    bool pooled;
+};
+
+struct BlockCache {
+    std::mutex mu;
+    std::multimap<size_t, CachedBlock> blocks; // by size
+    uint64_t bytes = 0;
+};
+
+static BlockCache &block_cache(int dev)
+{
+    static BlockCache caches[CACHE_DEVICES];
+    return caches[dev >= 0 && dev < CACHE_DEVICES ? dev : 0];
+}
+
+static void free_block(void *p, bool pooled)
+{
+    if (pooled) (void)hipFreeAsync(p, nullptr);
+    else (void)hipFree(p);
+}
+
+// an idle block of at least need and at most 2 * need bytes, or nullptr
+static void *cache_take(size_t need, size_t *size, bool *pooled)
+{
+    int d = 0;
+    if (hipGetDevice(&d) != hipSuccess || d < 0 || d >= CACHE_DEVICES) return nullptr;
+    BlockCache &c = block_cache(d);
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto it = c.blocks.lower_bound(need);
+    if (it == c.blocks.end() || it->first > 2 * need) return nullptr;
+    void *p = it->second.p;
+    *size = it->first;
+    *pooled = it->second.pooled;
+    c.bytes -= it->first;
+    c.blocks.erase(it);
+    return p;
+}
+
+static void cache_put(void *p, size_t size, bool pooled)
+{
+    int d = 0;
+    if (hipGetDevice(&d) != hipSuccess || d < 0 || d >= CACHE_DEVICES || size > CACHE_KEEP) {
+        free_block(p, pooled);
+        return;
+    }
+    BlockCache &c = block_cache(d);
+    std::lock_guard<std::mutex> lk(c.mu);
+    c.blocks.emplace(size, CachedBlock{p, pooled});
+    c.bytes += size;
+    while (c.bytes > CACHE_KEEP) { // the largest blocks leave first
+        auto it = std::prev(c.blocks.end());
+        c.bytes -= it->first;
+        free_block(it->second.p, it->second.pooled);
+        c.blocks.erase(it);
+    }
+}
+
 // A released block is kept and handed to a later request of at least half its size: the
 // stages of one build (sampler, compaction, transpose) allocate and release buffers of a few
 // GB each, and reusing them avoids a driver call per buffer.  Kept blocks go back to the
@@ -65,6 +132,17 @@ void *Arena::alloc(size_t bytes)
     if (cap && used + need > cap)
         throw Error{SKIS_ENOMEM, "max_device_bytes exceeded: " + std::to_string(used + need) + " > " +
                                      std::to_string(cap)};
+    {
+        size_t size = 0;
+        bool pooled = false;
+        if (void *p = cache_take(need, &size, &pooled)) {
+            if (pooled) pooled_ptrs.insert(p);
+            blocks[p] = size;
+            used += bytes;
+            peak = std::max(peak, used);
+            return p;
+        }
+    }
     void *p = nullptr;
     const bool pooled = pool_ready();
     hipError_t e = pooled ? hipMallocAsync(&p, need, stream) : hipMalloc(&p, need);
@@ -94,17 +172,21 @@ void Arena::release(void *p, size_t bytes)
     kept += it->second;
 }
 
-void Arena::trim()
+void Arena::trim(bool idle)
 {
     for (auto &fb : free_blocks) {
         void *p = fb.second;
-        if (pooled_ptrs.erase(p)) (void)hipFreeAsync(p, stream);
+        const bool pooled = pooled_ptrs.erase(p) > 0;
+        if (idle) cache_put(p, fb.first, pooled);
+        else if (pooled) (void)hipFreeAsync(p, stream);
         else (void)hipFree(p);
         blocks.erase(p);
     }
     free_blocks.clear();
     kept = 0;
 }
+
+Arena::~Arena() { trim(idle_on_destroy); }
 
 int device_cu_count()
 {
@@ -190,6 +272,7 @@ int skis_preprocess(int32_t n, int64_t m, const int32_t *row_ptr, const int32_t 
                                               hipMemcpyDeviceToDevice, stream));
         }
         SKIS_HIP_TRY(hipStreamSynchronize(stream));
+        arena.idle_on_destroy = true; // the synchronisation above ended every use of the blocks
         if (C_out) *C_out = prep.C;
         if (Gamma_out) *Gamma_out = prep.Gamma;
         return prep.C == 0 ? SKIS_WDEGENERATE : SKIS_OK;
@@ -275,8 +358,8 @@ int skis_build_sketch(int32_t n, int64_t m, const int32_t *row_ptr, const int32_
             }
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);
-            sk.arena.trim(); // the stages' temporaries go back to the device pool
             SKIS_HIP_TRY(hipStreamSynchronize(stream));
+            sk.arena.trim(true); // the stages' temporaries are idle: to the block cache
             *out = h;
             if (status == SKIS_WDEGENERATE) skis::set_error("Gamma = 0: no non-singular sample exists");
             return status;
@@ -351,7 +434,7 @@ int skis_greedy_max_cover(const skis_sketch *hc, int32_t k, int32_t *seeds, uint
         std::lock_guard<std::mutex> lk(h->mu);
         h->core.arena.stream = stream;
         skis::greedy(h->core, h->qs, k, seeds, marg, cov_out, est_out, stream);
-        h->core.arena.trim();
+        h->core.arena.trim(true); // greedy ends with a synchronisation of its stream
         return SKIS_OK;
     });
 }
@@ -413,6 +496,7 @@ void skis_sketch_free(skis_sketch *h)
     // stream: release them in order behind all work on the device
     (void)hipDeviceSynchronize();
     h->core.arena.stream = nullptr;
+    h->core.arena.idle_on_destroy = true; // nothing queued uses the blocks any more
     delete h;
 }
 

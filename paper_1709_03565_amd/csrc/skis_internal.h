@@ -44,10 +44,14 @@ struct Arena {
     std::unordered_map<void *, size_t> blocks; // every block the arena owns -> its size
     std::multimap<size_t, void *> free_blocks; // released blocks kept for reuse, by size
     std::unordered_set<void *> pooled_ptrs;    // blocks from the stream-ordered pool
+    bool idle_on_destroy = false;              // set when no queued work can still use the blocks
     void *alloc(size_t bytes);
     void release(void *p, size_t bytes);
-    void trim(); // returns the kept blocks to the device pool
-    ~Arena() { trim(); }
+    // Gives the kept blocks back: with idle (no queued work on any stream can still touch
+    // them) to the process-wide cache of idle device blocks, which later arenas reuse with no
+    // driver call; otherwise to the device pool, in order on the arena's stream.
+    void trim(bool idle = false);
+    ~Arena();
 };
 
 template <typename T>
