@@ -60,17 +60,81 @@ struct __align__(16) AliasEntry {
     int32_t pad;
 };
 
-// Wave-level inclusive prefix sum over the 64 lanes.
+// Adds lane (l - d) of the same row of 16 lanes to lane l (nothing where l mod 16 < d), d in
+// {1, 2, 4, 8}: one DPP-modified VALU add, no LDS traffic.
+template <int D>
+__device__ __forceinline__ uint32_t dpp_row_shr_add(uint32_t x)
+{
+    return x + (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x110 + D, 0xf, 0xf, true);
+}
+
+// Inclusive prefix sum of 32-bit values over the 64 lanes by DPP: a scan within each row of 16
+// (row_shr 1, 2, 4, 8), then lane 15 of rows 0 and 2 into rows 1 and 3 (row_bcast:15), then
+// lane 31 into rows 2 and 3 (row_bcast:31).  Every lane must be active.
+__device__ __forceinline__ uint32_t wave_incl_scan_dpp(uint32_t x)
+{
+    x = dpp_row_shr_add<1>(x);
+    x = dpp_row_shr_add<2>(x);
+    x = dpp_row_shr_add<4>(x);
+    x = dpp_row_shr_add<8>(x);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);
+    return x;
+}
+
+// Wave-level inclusive prefix sum over the 64 lanes (every lane active).
 template <typename T>
 __device__ __forceinline__ T wave_incl_scan(T v)
 {
-    const int lane = threadIdx.x & 63;
+    if constexpr (sizeof(T) == 4) {
+        return (T)wave_incl_scan_dpp((uint32_t)v);
+    } else {
+        const int lane = threadIdx.x & 63;
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        T o = __shfl_up(v, d, 64);
-        if (lane >= d) v += o;
+        for (int d = 1; d < 64; d <<= 1) {
+            T o = __shfl_up(v, d, 64);
+            if (lane >= d) v += o;
+        }
+        return v;
     }
-    return v;
+}
+
+// Value of lane `lane` (a constant) / of the first active lane, through a scalar register
+// (no LDS traffic, unlike a shuffle).
+__device__ __forceinline__ uint32_t lane_value(uint32_t v, int lane)
+{
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, lane);
+}
+
+__device__ __forceinline__ unsigned long long lane_value64(unsigned long long v, int lane)
+{
+    const uint32_t lo = lane_value((uint32_t)v, lane), hi = lane_value((uint32_t)(v >> 32), lane);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+__device__ __forceinline__ unsigned long long first_lane_value64(unsigned long long v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// Inclusive prefix sum over lanes 0 .. N-1 (exact there; lanes from N on hold partial sums),
+// 32-bit values, every lane active.
+template <int N, typename T>
+__device__ __forceinline__ T wave_incl_scan_n(T v)
+{
+    static_assert(sizeof(T) == 4, "32-bit scan");
+    if constexpr (N > 16) {
+        return (T)wave_incl_scan_dpp((uint32_t)v);
+    } else {
+        uint32_t x = (uint32_t)v;
+        if constexpr (N > 1) x = dpp_row_shr_add<1>(x);
+        if constexpr (N > 2) x = dpp_row_shr_add<2>(x);
+        if constexpr (N > 4) x = dpp_row_shr_add<4>(x);
+        if constexpr (N > 8) x = dpp_row_shr_add<8>(x);
+        return (T)x;
+    }
 }
 
 template <typename T>

@@ -240,9 +240,10 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
             // open chunk, which is refilled with one atomic when it runs short
             const bool fin = own && (f & F_ACTIVE) && !(!GLOBAL && (f & F_DEFER)) && !(f & F_ROOTPEND) &&
                              s_cursor[s] >= s_count[s];
-            const unsigned long long fcnt = fin ? (unsigned long long)s_count[s] : 0ull;
-            const unsigned long long fincl = wave_incl_scan(fcnt);
-            const unsigned long long ftot = __shfl(fincl, 63, 64);
+            // scans over the S slot lanes only (the others hold zeros); totals from lane S - 1
+            const uint32_t fcnt = fin ? (uint32_t)s_count[s] : 0u;
+            const uint32_t fincl = wave_incl_scan_n<S>(fcnt);
+            const unsigned long long ftot = lane_value(fincl, S - 1);
             unsigned long long fbase = 0;
             if (s == 0 && ftot) {
                 if (st_base + ftot > st_end) {
@@ -253,7 +254,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                 fbase = st_base;
                 st_base += ftot;
             }
-            fbase = __shfl(fbase, 0, 64);
+            fbase = first_lane_value64(fbase); // lane 0: every lane of the wave is active here
             if (own && (f & F_ACTIVE)) {
                 if (!GLOBAL && (f & F_DEFER)) {
                     const uint32_t i = s_idx[s];
@@ -266,7 +267,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                 } else if (fin) {
                     const uint32_t i = s_idx[s];
                     const int cnt = s_count[s];
-                    const unsigned long long off = fbase + fincl - fcnt;
+                    const unsigned long long off = fbase + (unsigned long long)(fincl - fcnt);
                     a.out_size[i] = (uint32_t)cnt;
                     a.out_off[i] = off;
                     a.out_probed[i] = s_probed[s];
@@ -300,7 +301,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                 int cur = s_ccur;
                 if (avail < (unsigned long long)nwant) {
                     if (s == 0) nb = atomicAdd(a.next, (unsigned long long)IDBATCH);
-                    nb = __shfl(nb, 0, 64);
+                    nb = first_lane_value64(nb);
                     // load the new batch's records into the other buffer (lane l: id nb + l)
                     cur ^= 1;
                     if (s < IDBATCH) {
@@ -383,11 +384,11 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                 const int rest = lim - s_cursor[s];
                 pend = rp + (rest > 0 ? rest : 0);
             }
-            const int incl = wave_incl_scan(pend);
+            const int incl = wave_incl_scan_n<S>(pend);
             const int base = incl - pend;
             int take = ICAP - base;
             take = take < 0 ? 0 : (take > pend ? pend : take);
-            const int tincl = wave_incl_scan(take);
+            const int tincl = wave_incl_scan_n<S>(take);
             if (own) {
                 s_ibase[s] = tincl - take;
                 s_ifirst[s] = s_cursor[s];
@@ -401,7 +402,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                     }
                 }
             }
-            const int total = __shfl(tincl, 63, 64);
+            const int total = (int)lane_value((uint32_t)tincl, S - 1);
             // the workgroup stays while a slot is active or was just finished: a finished
             // slot takes a new sample only in the next pass, and the ids already taken
             // from the global counter must not be dropped
