@@ -46,7 +46,7 @@ def tier0_kernel_name(opts) -> str:
     key = (opts.get("threads_per_block", 64), opts.get("slots_per_block", 4), opts.get("visited_threshold", 192),
            opts.get("pairs_per_lane", 2))
     hcap, icap = _TIER0[key]
-    return "k_sample<%d, %d, %d, %d, %d, %d, false>" % (key[0], key[1], key[2], hcap, icap, key[3])
+    return "k_sample<%d, %d, %d, %d, %d, %d, 0>" % (key[0], key[1], key[2], hcap, icap, key[3])
 
 
 def measured_traffic(kname: str, workload: str):

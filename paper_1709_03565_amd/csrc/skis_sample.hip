@@ -30,7 +30,8 @@ constexpr int SORT_LDS_MAX = 8192; // sizes up to this are sorted in LDS by k_ga
 template <int S>
 constexpr int id_batch() { return S <= 16 ? 16 : 32; }
 
-enum : int { F_ACTIVE = 1, F_ROOTPEND = 2, F_DEFER = 4, F_CLEAR = 8 };
+// F_RESUME: admitted this pass from a handover (its nodes are put back in phase B1)
+enum : int { F_ACTIVE = 1, F_ROOTPEND = 2, F_DEFER = 4, F_CLEAR = 8, F_RESUME = 16 };
 
 // ---------------------------------------------------------------------------------------
 // Root and first live in-edge of every sample.
@@ -89,6 +90,17 @@ __global__ __launch_bounds__(256) void k_roots(uint64_t j0, uint32_t count, cons
     }
 }
 
+// The state of a sample handed from one LDS tier to the next as of the start of the pass in
+// which it outgrew its slot: its first `count` nodes in discovery order (in the node buffer),
+// how many of them were expanded, whether the root's item was still pending, and the edges it
+// had probed.  The next tier resumes from there and repeats that pass (the coins depend only
+// on (sample, edge), so the set is the same).
+struct __align__(16) Handover {
+    int32_t count;
+    int32_t cursor_rp;        // cursor * 2 + (root item pending)
+    unsigned long long probed;
+};
+
 struct SampleArgs {
     int32_t n;
     const int32_t *row_ptr;
@@ -119,6 +131,16 @@ struct SampleArgs {
     uint32_t *gbits;            // global tier: [slots][words]
     int32_t *glist;             // global tier: [slots][n]
     uint64_t words;
+    // handover to the next tier: sample k of `deferred` (k < ho_cap_out) leaves its state in
+    // ho_state_out[k] and its nodes in ho_nodes_out[k * ho_stride ...]
+    Handover *ho_state_out;
+    int32_t *ho_nodes_out;
+    uint64_t ho_cap_out;
+    // handover from the previous tier: id k of id_list (k < ho_cap_in) resumes from it
+    const Handover *ho_state_in;
+    const int32_t *ho_nodes_in;
+    uint64_t ho_cap_in;
+    int32_t ho_stride;
 };
 
 // RCAP: nodes a slot holds before its sample moves on (the visited threshold); HCAP: size
@@ -126,9 +148,13 @@ struct SampleArgs {
 // factor at most 3/4 while leaving LDS for more slots).
 // ICAP: items (pending nodes over all slots) expanded per pass; PPL: most edge pairs a lane
 // takes per sweep (4 keeps more loads in flight, 2 needs fewer registers).
-template <int BLOCK, int S, int RCAP, int HCAP, int ICAP, int PPL, bool GLOBAL>
+// TIER: 0 the first LDS tier (hands its overflowing samples on with their state), 1 the
+// second LDS tier (resumes them), 2 the HBM tier (visited sets in global memory).
+template <int BLOCK, int S, int RCAP, int HCAP, int ICAP, int PPL, int TIER>
 __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
 {
+    constexpr bool GLOBAL = TIER == 2;
+    constexpr bool HO_OUT = TIER == 0, HO_IN = TIER == 1;
     constexpr int IDBATCH = id_batch<S>();
     static_assert(GLOBAL || HCAP > RCAP, "the hash must be larger than the node list");
     static_assert(GLOBAL || HCAP <= 65535, "list entries are 8- or 16-bit hash slot indexes");
@@ -146,8 +172,12 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
     __shared__ uint32_t s_idx[S];
     __shared__ int32_t s_count[S], s_cursor[S], s_flags[S], s_rib[S], s_rie[S];
     __shared__ unsigned long long s_probed[S];
+    // phase B1 work of a slot: s_wo_cnt >= 0 entries to write at s_wo_off, -1 a hand-on
+    // without handover, -2 a hand-on whose nodes go to handover s_wo_off; a slot flagged
+    // F_RESUME refills from handover s_wo_off
     __shared__ int32_t s_wo_cnt[S];
     __shared__ unsigned long long s_wo_off[S];
+    __shared__ Handover s_snap[HO_OUT ? S : 1]; // each slot's state at the start of the pass
     __shared__ int32_t s_ibase[S + 1], s_ifirst[S], s_irp[S];
     __shared__ int32_t it_beg[ICAP], it_end[ICAP], it_pb[ICAP + 1];
     __shared__ uint8_t it_slot[ICAP];
@@ -236,6 +266,12 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
             const int s = tid;
             const bool own = s < S;
             int f = own ? s_flags[s] : 0;
+            if constexpr (HO_IN) {
+                if (f & F_RESUME) { // refilled in the last pass's phase B1
+                    f &= ~F_RESUME;
+                    s_flags[s] = f;
+                }
+            }
             // finished samples of this pass take their staging space from the workgroup's
             // open chunk, which is refilled with one atomic when it runs short
             const bool fin = own && (f & F_ACTIVE) && !(!GLOBAL && (f & F_DEFER)) && !(f & F_ROOTPEND) &&
@@ -262,6 +298,13 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                     a.deferred[k] = i;
                     a.out_size[i] = DEFERRED;
                     s_wo_cnt[s] = -1; // nothing to write; its hash may hold keys past the list
+                    if constexpr (HO_OUT) {
+                        if (a.ho_state_out && k < a.ho_cap_out) {
+                            a.ho_state_out[k] = s_snap[s]; // its nodes follow in phase B1
+                            s_wo_cnt[s] = -2;
+                            s_wo_off[s] = k;
+                        }
+                    }
                     f = F_CLEAR;
                     s_flags[s] = f;
                 } else if (fin) {
@@ -352,7 +395,25 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                     s_cursor[s] = 1;
                     int nf = F_ACTIVE | (r.y + 1 < r.w ? F_ROOTPEND : 0);
                     if (!GLOBAL && (uint32_t)(r.w - r.z) > a.big_row) nf |= F_DEFER;
-                    if constexpr (GLOBAL) {
+                    bool resumed = false;
+                    if constexpr (HO_IN) {
+                        if (a.ho_state_in && myid < a.ho_cap_in) {
+                            const Handover h = a.ho_state_in[myid];
+                            const int cur = h.cursor_rp >> 1;
+                            if (h.count >= 2 && h.count <= RCAP && cur >= 1 && cur <= h.count) {
+                                // its nodes are put back into the hash and list in phase B1
+                                resumed = true;
+                                s_count[s] = h.count;
+                                s_cursor[s] = cur;
+                                s_probed[s] = h.probed;
+                                nf = F_ACTIVE | F_RESUME | ((h.cursor_rp & 1) ? F_ROOTPEND : 0);
+                                if ((uint32_t)(r.w - r.z) > a.big_row) nf |= F_DEFER;
+                                s_wo_off[s] = myid;
+                            }
+                        }
+                    }
+                    if (resumed) {
+                    } else if constexpr (GLOBAL) {
                         int32_t *L = list_ptr(s);
                         L[0] = r.x;
                         L[1] = u;
@@ -373,6 +434,16 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                     f = nf;
                     s_flags[s] = f;
                     }
+                }
+            }
+            // the state a handover would carry if this pass outgrows the slot
+            if constexpr (HO_OUT) {
+                if (a.ho_state_out && own && (f & F_ACTIVE)) {
+                    Handover h;
+                    h.count = s_count[s];
+                    h.cursor_rp = s_cursor[s] * 2 + ((f & F_ROOTPEND) ? 1 : 0);
+                    h.probed = s_probed[s];
+                    s_snap[s] = h;
                 }
             }
             // items: the root item (edges after i*) and then unexpanded nodes, slot by slot
@@ -417,11 +488,32 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
 
         // ---- B1: write out finished samples, clear their visited sets ----------------------
         for (int s = 0; s < S; ++s) {
-            if (s_flags[s] != F_CLEAR) continue;
+            const int fs = s_flags[s];
+            if constexpr (HO_IN) {
+                if (fs & F_RESUME) { // resumed from a handover: its nodes back into the hash and list
+                    const int c = s_count[s];
+                    const int32_t *src = a.ho_nodes_in + (size_t)s_wo_off[s] * (size_t)a.ho_stride;
+                    int32_t *H = sh_hash + s * HCAP;
+                    for (int t = tid; t < c; t += BLOCK) {
+                        const int32_t u = src[t];
+                        uint32_t h = hash_slot(u);
+                        for (int k = 0; k < HCAP && atomicCAS(&H[h], -1, u) != -1; ++k)
+                            h = h + 1 == (uint32_t)HCAP ? 0u : h + 1;
+                        sh_lidx[s * RCAP + t] = (LIdx)h;
+                    }
+                }
+            }
+            if (fs != F_CLEAR) continue;
             const int cnt = s_wo_cnt[s];
             const unsigned long long off = s_wo_off[s];
             if constexpr (!GLOBAL) {
-                if (cnt < 0) { // a sample handed on: clear the whole table
+                if (cnt < 0) { // a sample handed on: its nodes to the handover, then a full clear
+                    if (HO_OUT && cnt == -2) {
+                        const int c = s_snap[s].count;
+                        int32_t *dst = a.ho_nodes_out + (size_t)off * (size_t)a.ho_stride;
+                        for (int t = tid; t < c; t += BLOCK) dst[t] = sh_hash[s * HCAP + sh_lidx[s * RCAP + t]];
+                        block_sync<BLOCK>();
+                    }
                     for (int t = tid; t < HCAP; t += BLOCK) sh_hash[s * HCAP + t] = -1;
                 } else {
                     // a finished sample has every key in its list: write the first cnt
@@ -469,6 +561,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
             s_flags[tid] = 0;
             s_wo_cnt[tid] = 0;
         }
+
 
         // ---- B2: item edge ranges ----------------------------------------------------------
         const int nitems = s_nitems;
@@ -976,36 +1069,36 @@ struct Variant {
 // With 64 threads a workgroup is one wave that owns its slots and LDS and never waits for
 // another wave; with 256 threads four waves share the slots and meet at barriers.
 static const Variant kTier0[] = {
-    {64, 4, 192, 4, k_sample<64, 4, 192, 256, 128, 4, false>},
-    {64, 4, 192, 2, k_sample<64, 4, 192, 256, 64, 2, false>},
-    {64, 4, 256, 4, k_sample<64, 4, 256, 320, 128, 4, false>},
-    {64, 4, 256, 2, k_sample<64, 4, 256, 320, 64, 2, false>},
-    {64, 2, 256, 2, k_sample<64, 2, 256, 320, 64, 2, false>},
-    {64, 3, 256, 2, k_sample<64, 3, 256, 320, 64, 2, false>},
-    {64, 2, 384, 2, k_sample<64, 2, 384, 512, 64, 2, false>},
-    {64, 6, 256, 4, k_sample<64, 6, 256, 320, 192, 4, false>},
-    {64, 8, 128, 4, k_sample<64, 8, 128, 172, 256, 4, false>},
-    {64, 8, 192, 4, k_sample<64, 8, 192, 256, 256, 4, false>},
-    {64, 8, 192, 2, k_sample<64, 8, 192, 256, 256, 2, false>},
-    {64, 8, 256, 4, k_sample<64, 8, 256, 344, 256, 4, false>},
-    {64, 12, 192, 4, k_sample<64, 12, 192, 256, 384, 4, false>},
-    {64, 16, 128, 4, k_sample<64, 16, 128, 172, 512, 4, false>},
-    {64, 16, 64, 4, k_sample<64, 16, 64, 88, 512, 4, false>},
-    {256, 16, 128, 4, k_sample<256, 16, 128, 172, 1024, 4, false>},
-    {256, 32, 128, 4, k_sample<256, 32, 128, 172, 1024, 4, false>},
-    {256, 16, 256, 4, k_sample<256, 16, 256, 344, 1024, 4, false>},
+    {64, 4, 192, 4, k_sample<64, 4, 192, 256, 128, 4, 0>},
+    {64, 4, 192, 2, k_sample<64, 4, 192, 256, 64, 2, 0>},
+    {64, 4, 256, 4, k_sample<64, 4, 256, 320, 128, 4, 0>},
+    {64, 4, 256, 2, k_sample<64, 4, 256, 320, 64, 2, 0>},
+    {64, 2, 256, 2, k_sample<64, 2, 256, 320, 64, 2, 0>},
+    {64, 3, 256, 2, k_sample<64, 3, 256, 320, 64, 2, 0>},
+    {64, 2, 384, 2, k_sample<64, 2, 384, 512, 64, 2, 0>},
+    {64, 6, 256, 4, k_sample<64, 6, 256, 320, 192, 4, 0>},
+    {64, 8, 128, 4, k_sample<64, 8, 128, 172, 256, 4, 0>},
+    {64, 8, 192, 4, k_sample<64, 8, 192, 256, 256, 4, 0>},
+    {64, 8, 192, 2, k_sample<64, 8, 192, 256, 256, 2, 0>},
+    {64, 8, 256, 4, k_sample<64, 8, 256, 344, 256, 4, 0>},
+    {64, 12, 192, 4, k_sample<64, 12, 192, 256, 384, 4, 0>},
+    {64, 16, 128, 4, k_sample<64, 16, 128, 172, 512, 4, 0>},
+    {64, 16, 64, 4, k_sample<64, 16, 64, 88, 512, 4, 0>},
+    {256, 16, 128, 4, k_sample<256, 16, 128, 172, 1024, 4, 0>},
+    {256, 32, 128, 4, k_sample<256, 32, 128, 172, 1024, 4, 0>},
+    {256, 16, 256, 4, k_sample<256, 16, 256, 344, 1024, 4, 0>},
 };
 // second tier: samples that outgrew the first, slots of 1024 nodes in LDS
 static const Variant kTierMidV[] = {
-    {64, 2, 1024, 2, k_sample<64, 2, 1024, 1368, 128, 2, false>},
-    {256, 8, 1024, 4, k_sample<256, 8, 1024, 1368, 1024, 4, false>},
+    {64, 2, 1024, 2, k_sample<64, 2, 1024, 1368, 128, 2, 1>},
+    {256, 8, 1024, 4, k_sample<256, 8, 1024, 1368, 1024, 4, 1>},
 };
 // One sample per workgroup: the samples that reach this tier are few and large, so the
 // chip is filled with workgroups rather than slots; the HBM buffers of all slots are kept
 // within TIERG_BUDGET bytes.
 constexpr int TIERG_SLOTS = 1;
 constexpr uint64_t TIERG_BUDGET = 8ull << 30;
-static SampleKernel const kTierGlobal = k_sample<256, TIERG_SLOTS, 1, 1, 1024, 4, true>;
+static SampleKernel const kTierGlobal = k_sample<256, TIERG_SLOTS, 1, 1, 1024, 4, 2>;
 
 static const Variant &pick_variant(const Variant *vs, size_t nv, uint32_t threads, uint32_t slots, uint32_t visited,
                                    uint32_t ppl)
@@ -1086,6 +1179,15 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
     const Variant &v0 =
         pick_variant(kTier0, sizeof(kTier0) / sizeof(kTier0[0]), cfg.threads, cfg.slots, cfg.visited, cfg.ppl);
     const Variant &vm = kTierMidV[cfg.threads == 64 ? 0 : 1];
+    // handover from tier 0 to tier 1 for the first ho_cap samples a launch hands on (the rest
+    // start over in tier 1): about 3 % of the samples at the default shape
+    const uint64_t ho_cap = std::min<uint64_t>(count, std::max<uint64_t>(1024, count / 32));
+    const int ho_stride = (int)v0.visited;
+    if (v0.visited > vm.visited) throw Error{SKIS_EHIP, "internal error: tier 1 smaller than tier 0"};
+    DevBuf<Handover> ho_state;
+    DevBuf<int32_t> ho_nodes;
+    ho_state.alloc(arena, ho_cap);
+    ho_nodes.alloc(arena, ho_cap * (uint64_t)ho_stride);
     const int cus = device_cu_count();
     const int nb0 = occupancy_blocks(v0.fn, (int)v0.threads) * cus;
     const int nbm = occupancy_blocks(vm.fn, (int)vm.threads) * cus;
@@ -1210,6 +1312,13 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
             A2.n_deferred = &ctr.ptr->n_deferred; // unused for the same reason
             A2.gbits = gbits.ptr;
             A2.glist = glist.ptr;
+            A0.ho_state_out = ho_state.ptr; // tier 0 hands over, tier 1 resumes, tier 2 starts over
+            A0.ho_nodes_out = ho_nodes.ptr;
+            A0.ho_cap_out = ho_cap;
+            A1.ho_state_in = ho_state.ptr;
+            A1.ho_nodes_in = ho_nodes.ptr;
+            A1.ho_cap_in = ho_cap;
+            A0.ho_stride = A1.ho_stride = ho_stride;
 
             SKIS_HIP_TRY(hipStreamBeginCapture(gg.cs, hipStreamCaptureModeThreadLocal));
             gg.capturing = true;
@@ -1320,6 +1429,10 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
         A.overflow = &ctr.ptr->overflow;
         A.words = words;
         A.tier_stats = ctr.ptr->tier[0];
+        A.ho_state_out = ho_state.ptr;
+        A.ho_nodes_out = ho_nodes.ptr;
+        A.ho_cap_out = ho_cap;
+        A.ho_stride = ho_stride;
         for (const void *p : {(const void *)A.row_ptr, (const void *)A.pairs, (const void *)A.rec, (const void *)A.u1,
                               (const void *)A.next, (const void *)A.staging, (const void *)A.stage_used,
                               (const void *)A.out_size, (const void *)A.out_off, (const void *)A.out_probed,
@@ -1344,6 +1457,12 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
             A.deferred = deferred2.ptr;
             A.big_row = std::max<uint32_t>(cfg.big_row, 1u << 20);
             A.tier_stats = ctr.ptr->tier[1];
+            A.ho_state_out = nullptr;
+            A.ho_nodes_out = nullptr;
+            A.ho_cap_out = 0;
+            A.ho_state_in = ho_state.ptr;
+            A.ho_nodes_in = ho_nodes.ptr;
+            A.ho_cap_in = ho_cap;
             SKIS_HIP_TRY(hipEventRecord(ev[6], s));
             hipLaunchKernelGGL(vm.fn, dim3(nbm), dim3(vm.threads), 0, s, A);
             SKIS_HIP_TRY(hipGetLastError());
@@ -1369,6 +1488,9 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
             A.gbits = gbits.ptr;
             A.glist = glist.ptr;
             A.tier_stats = ctr.ptr->tier[2];
+            A.ho_state_in = nullptr; // the HBM tier starts its samples over
+            A.ho_nodes_in = nullptr;
+            A.ho_cap_in = 0;
             need(A.gbits, "gbits");
             need(A.glist, "glist");
             SKIS_HIP_TRY(hipEventRecord(ev[8], s));

@@ -82,7 +82,7 @@ def test_bench_kernel_names_match_the_library_table():
     import bench
     src = open(os.path.join(ROOT, "paper_1709_03565_amd", "csrc", "skis_sample.hip")).read()
     table = src[src.index("kTier0[] = {"):src.index("};", src.index("kTier0[] = {"))]
-    rows = re.findall(r"\{(\d+), (\d+), (\d+), (\d+), k_sample<(\d+), (\d+), (\d+), (\d+), (\d+), (\d+), false>\}",
+    rows = re.findall(r"\{(\d+), (\d+), (\d+), (\d+), k_sample<(\d+), (\d+), (\d+), (\d+), (\d+), (\d+), 0>\}",
                       table)
     assert len(rows) >= 10
     for r in rows:
@@ -90,4 +90,4 @@ def test_bench_kernel_names_match_the_library_table():
         assert (th, sl, vi, pl) == (th2, sl2, vi2, pl2)
         name = bench.tier0_kernel_name(dict(threads_per_block=th, slots_per_block=sl, visited_threshold=vi,
                                             pairs_per_lane=pl))
-        assert name == "k_sample<%d, %d, %d, %d, %d, %d, false>" % (th, sl, vi, hcap, icap, pl)
+        assert name == "k_sample<%d, %d, %d, %d, %d, %d, 0>" % (th, sl, vi, hcap, icap, pl)
