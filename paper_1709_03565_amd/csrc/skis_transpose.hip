@@ -4,12 +4,14 @@
 // A direct scatter from the sketch writes one 4-byte id per entry to a random place in HBM
 // (each write a partial-line update).  The sort instead writes every pass in runs: each
 // tile of RS_TILE entries sends its entries of one digit to one contiguous range.  Per pass:
-//   k_rs_hist     digit counts per tile, stored digit-major (H[d * ntiles + tile]), so one
-//                 exclusive scan of H gives every (tile, digit) its output offset;
-//   k_rs_scatter  each wave ranks its entries among equal digits with 8 ballots (lanes in
-//                 order), the waves of a tile are ordered by a prefix of their counts, the
-//                 tile is sorted by digit in LDS (stable) and written out in order, so each
-//                 digit's run of the tile goes to its offset with consecutive lanes.
+//   k_rs_hist     digit counts per tile, one contiguous row per tile; per-chunk digit sums,
+//                 one exclusive scan of those (digit-major) and a walk over each chunk's rows
+//                 give every (tile, digit) its output offset, again one row per tile;
+//   k_rs_scatter  each wave ranks its entries among equal digits with one ballot per digit
+//                 bit (lanes in order) in one pass that also counts the wave's digits, the
+//                 waves of a tile are ordered by a prefix of their counts, the tile is sorted
+//                 by digit in LDS (stable) and written out in order, so each digit's run of
+//                 the tile goes to its offset with consecutive lanes.
 // The input is in sample order, so every list H(v) comes out sorted by sample id.
 // The last pass writes only the sample ids and counts each node's entries; node_ptr is the
 // exclusive scan of those counts.
@@ -56,8 +58,41 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_hist(uint64_t N, const int32_t 
         for (int r = 0; r < R; ++r)
             if (kr[r] >= 0) atomicAdd(&h[((uint32_t)kr[r] >> shift) & 255u], 1u);
         __syncthreads();
-        H[(uint64_t)threadIdx.x * ntiles + tile] = h[threadIdx.x];
+        H[tile * 256 + threadIdx.x] = h[threadIdx.x]; // tile-major: one contiguous row per tile
         __syncthreads();
+    }
+}
+
+// Output offsets of every (tile, digit) from the tile-major histogram H[tile][digit]: the
+// entries of digit d go after those of every smaller digit and, within d, tile by tile.
+// k_rs_chunk_sums adds the rows of each chunk of RS_CHUNK tiles per digit into C[d][chunk]
+// (digit-major, so one exclusive scan of C gives every (digit, chunk) its base), and
+// k_rs_offsets walks the chunk's rows from that base, writing OFF[tile][digit].  Every access
+// to H and OFF is a contiguous row of 256 values.
+constexpr int RS_CHUNK = 64;
+
+__global__ __launch_bounds__(256) void k_rs_chunk_sums(uint64_t ntiles, const uint32_t *__restrict__ H,
+                                                       uint64_t nchunks, uint32_t *__restrict__ C)
+{
+    for (uint64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const uint64_t t0 = c * RS_CHUNK, t1 = min(t0 + RS_CHUNK, ntiles);
+        uint32_t acc = 0;
+        for (uint64_t t = t0; t < t1; ++t) acc += H[t * 256 + threadIdx.x];
+        C[(uint64_t)threadIdx.x * nchunks + c] = acc;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_rs_offsets(uint64_t ntiles, const uint32_t *__restrict__ H,
+                                                    uint64_t nchunks, const int64_t *__restrict__ CB,
+                                                    int64_t *__restrict__ OFF)
+{
+    for (uint64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const uint64_t t0 = c * RS_CHUNK, t1 = min(t0 + RS_CHUNK, ntiles);
+        int64_t acc = CB[(uint64_t)threadIdx.x * nchunks + c];
+        for (uint64_t t = t0; t < t1; ++t) {
+            OFF[t * 256 + threadIdx.x] = acc;
+            acc += H[t * 256 + threadIdx.x];
+        }
     }
 }
 
@@ -104,7 +139,7 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(uint64_t N, const int32
             kr[r] = kin[e];
             vr[r] = vin[e];
         }
-        bnext = OFF[(uint64_t)threadIdx.x * ntiles + tile];
+        bnext = OFF[tile * 256 + threadIdx.x];
     }
     for (; tile < ntiles; tile += gridDim.x) {
         const uint64_t t0 = tile * RS_TILE;
@@ -112,19 +147,22 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(uint64_t N, const int32
         const int nvalid = (int)min((uint64_t)RS_TILE, N - t0);
         base[threadIdx.x] = bnext;
         for (int i = threadIdx.x; i < RS_WAVES * 256; i += RS_BLOCK) (&cnt[0][0])[i] = 0u;
+        const uint64_t tn = tile + gridDim.x;
+        if (tn < ntiles) bnext = OFF[tn * 256 + threadIdx.x];
+        __syncthreads();
+        // one ranking pass over the wave's span (in registers, in order): the rank of each
+        // entry among the equal digits before it in the wave, while the leader of each digit
+        // and round advances the wave's count of that digit
+        uint32_t lp[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            sk[w * RS_SPAN + r * 64 + lane] = kr[r];
-            sv[w * RS_SPAN + r * 64 + lane] = vr[r];
-        }
-        const uint64_t tn = tile + gridDim.x;
-        if (tn < ntiles) bnext = OFF[(uint64_t)threadIdx.x * ntiles + tn];
-        __syncthreads();
-        // phase 1: this wave's digit counts (one leader per digit and round adds)
-        for (int r = 0; r < R; ++r) {
             const bool valid = s0 + (uint64_t)r * 64 + lane < N;
-            const uint32_t d = valid ? (((uint32_t)sk[w * RS_SPAN + r * 64 + lane] >> shift) & 255u) : 0u;
+            const uint32_t d = valid ? (((uint32_t)kr[r] >> shift) & 255u) : 0u;
             const unsigned long long m = same_digit_mask(valid, d, bits);
+            lp[r] = valid ? cnt[w][d] + (uint32_t)__popcll(m & lt) : 0xFFFFFFFFu;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             if (valid && !(m & lt)) cnt[w][d] += (uint32_t)__popcll(m);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
@@ -147,28 +185,14 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(uint64_t N, const int32
             for (int k = 0; k < RS_WAVES; ++k) cnt[k][d] += ex;
         }
         __syncthreads();
-        // phase 2: tile-local positions (stable), kept in registers until every wave has read
-        uint32_t lp[R];
-        for (int r = 0; r < R; ++r) {
-            const bool valid = s0 + (uint64_t)r * 64 + lane < N;
-            kr[r] = sk[w * RS_SPAN + r * 64 + lane];
-            vr[r] = sv[w * RS_SPAN + r * 64 + lane];
-            const uint32_t d = valid ? (((uint32_t)kr[r] >> shift) & 255u) : 0u;
-            const unsigned long long m = same_digit_mask(valid, d, bits);
-            lp[r] = valid ? cnt[w][d] + (uint32_t)__popcll(m & lt) : 0xFFFFFFFFu;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            if (valid && !(m & lt)) cnt[w][d] += (uint32_t)__popcll(m);
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        }
-        __syncthreads();
+        // the tile sorted by digit (stably) in LDS
+#pragma unroll
         for (int r = 0; r < R; ++r)
             if (lp[r] != 0xFFFFFFFFu) {
-                sk[lp[r]] = kr[r];
-                sv[lp[r]] = vr[r];
+                const uint32_t d = ((uint32_t)kr[r] >> shift) & 255u;
+                const uint32_t pos = cnt[w][d] + lp[r];
+                sk[pos] = kr[r];
+                sv[pos] = vr[r];
             }
         __syncthreads();
         // the next tile's loads go out before this one is written
@@ -240,8 +264,13 @@ void radix_transpose(Arena &arena, const int64_t *sample_ptr, const int32_t *nod
     }
     if (passes > 1) vb.alloc(arena, N);
     kb.alloc(arena, N);
+    const uint64_t nchunks = (ntiles + RS_CHUNK - 1) / RS_CHUNK;
     H.alloc(arena, 256 * ntiles);
-    OFF.alloc(arena, 256 * ntiles + 1);
+    OFF.alloc(arena, 256 * ntiles);
+    DevBuf<uint32_t> C;
+    DevBuf<int64_t> CB;
+    C.alloc(arena, 256 * nchunks);
+    CB.alloc(arena, 256 * nchunks + 1);
     if (!owner) {
         hipLaunchKernelGGL(k_rs_vals, dim3(grid_rs(T * 64, 256, 16)), dim3(256), 0, s, T, sample_ptr, vals);
         SKIS_HIP_TRY(hipGetLastError());
@@ -259,7 +288,12 @@ void radix_transpose(Arena &arena, const int64_t *sample_ptr, const int32_t *nod
         int32_t *vout = lastp ? node_samples : ((p & 1) ? vals : vb.ptr);
         hipLaunchKernelGGL(k_rs_hist, dim3(gt), dim3(RS_BLOCK), 0, s, N, kin, 8 * p, ntiles, H.ptr);
         SKIS_HIP_TRY(hipGetLastError());
-        excl_scan_u32_to_i64(arena, H.ptr, OFF.ptr, (int64_t)(256 * ntiles), OFF.ptr + 256 * ntiles, s);
+        hipLaunchKernelGGL(k_rs_chunk_sums, dim3(grid_rs(nchunks * 256, 256, 8)), dim3(256), 0, s, ntiles, H.ptr,
+                           nchunks, C.ptr);
+        excl_scan_u32_to_i64(arena, C.ptr, CB.ptr, (int64_t)(256 * nchunks), CB.ptr + 256 * nchunks, s);
+        hipLaunchKernelGGL(k_rs_offsets, dim3(grid_rs(nchunks * 256, 256, 8)), dim3(256), 0, s, ntiles, H.ptr,
+                           nchunks, CB.ptr, OFF.ptr);
+        SKIS_HIP_TRY(hipGetLastError());
         hipLaunchKernelGGL(k_rs_scatter, dim3(gt), dim3(RS_BLOCK), 0, s, N, kin, vin, kout, vout, 8 * p,
                            std::min(8, bits - 8 * p), ntiles, OFF.ptr, lastp ? deg : nullptr);
         SKIS_HIP_TRY(hipGetLastError());
