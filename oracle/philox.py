@@ -12,7 +12,7 @@ MASK32 = 0xFFFFFFFF
 M0, M1 = 0xD2511F53, 0xCD9E8D57
 W0, W1 = 0x9E3779B9, 0xBB67AE85
 
-TAG_ROOT, TAG_FIRST, TAG_EDGE = 0, 1, 2
+TAG_ROOT, TAG_FIRST, TAG_EDGE, TAG_EDGE_LOW = 0, 1, 2, 3
 
 
 def philox4x32_10(ctr, key):
@@ -37,5 +37,10 @@ def draw2(seed: int, sub: int, j: int, tag: int):
 
 
 def edge_coin_word(seed: int, j: int, e: int) -> int:
-    X, Y = draw2(seed, e >> 1, j, TAG_EDGE)
-    return Y if (e & 1) else X
+    """The 64-bit coin of edge e in sample j: high half = word e & 3 of the call with counter
+    (e >> 2, j, TAG_EDGE), low half = word 0 of the call with counter (e, j, TAG_EDGE_LOW)."""
+    key = (seed & MASK32, (seed >> 32) & MASK32)
+    jl, jh = j & MASK32, (j >> 32) & MASK32
+    hi = philox4x32_10((e >> 2, jl, jh, TAG_EDGE), key)[e & 3]
+    lo = philox4x32_10((e & MASK32, jl, jh, TAG_EDGE_LOW), key)[0]
+    return (hi << 32) | lo

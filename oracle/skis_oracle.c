@@ -17,8 +17,10 @@
  *   counter = (sub, j_lo, j_hi, tag) for sample id j.
  *     tag 0 (root draw):       sub = 0; X = y1:y0 picks the alias bucket, Y = y3:y2 its split
  *     tag 1 (first live edge): sub = 0; U = (X >> 11) * 2^-53
- *     tag 2 (edge coin):       sub = e >> 1; the coin of edge e is X if e is even, Y if odd;
- *                              live iff w >= 1 or coin < floor(w * 2^64)
+ *     tag 2 (edge coin, high): sub = e >> 2; word y[e & 3] is the high half of edge e's coin
+ *     tag 3 (edge coin, low):  sub = e;      word y0 is the low half of edge e's coin
+ *                              the coin is the 64-bit word high:low; the edge is live iff
+ *                              w >= 1 or coin < floor(w * 2^64)
  */
 #include <math.h>
 #include <pthread.h>
@@ -72,16 +74,23 @@ static uint64_t mulhi64(uint64_t a, uint64_t b)
 }
 
 /* Live-edge coin of edge e in sample j (Sec. 2.1: each edge is live independently with
- * probability w).  floor(w * 2^64) is exact for every fp32 w >= 2^-40, so the coin is
- * live with probability exactly w there. */
+ * probability w).  The coin is the 64-bit word high:low drawn as the randomness map above
+ * states; floor(w * 2^64) is exact for every fp32 w >= 2^-40, so the coin is live with
+ * probability exactly w there.  Two 64-bit words compare as their (high, low) pairs do
+ * lexicographically, so the low half is only drawn when the high halves are equal. */
 int ora_edge_coin(uint64_t seed, uint64_t j, int64_t e, float w)
 {
     if (w >= 1.0f) return 1;
-    uint64_t X, Y;
-    draw2(seed, (uint32_t)((uint64_t)e >> 1), j, 2u, &X, &Y);
-    uint64_t x = (e & 1) ? Y : X;
-    uint64_t thr = (uint64_t)((double)w * 0x1p64);
-    return x < thr;
+    const uint64_t thr = (uint64_t)((double)w * 0x1p64);
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t y[4];
+    const uint32_t hi_ctr[4] = {(uint32_t)((uint64_t)e >> 2), (uint32_t)j, (uint32_t)(j >> 32), 2u};
+    ora_philox4x32_10(hi_ctr, key, y);
+    const uint32_t hi = y[e & 3], thr_hi = (uint32_t)(thr >> 32);
+    if (hi != thr_hi) return hi < thr_hi;
+    const uint32_t lo_ctr[4] = {(uint32_t)e, (uint32_t)j, (uint32_t)(j >> 32), 3u};
+    ora_philox4x32_10(lo_ctr, key, y);
+    return y[0] < (uint32_t)thr;
 }
 
 /* ------------------------------------------------------------------------------------

@@ -64,7 +64,8 @@ def test_output_words_look_uniform():
 
 
 def test_edge_coin_definition():
-    # live iff w >= 1 or the 64-bit word (X for even e, Y for odd e) < floor(w * 2^64)
+    # live iff w >= 1 or the 64-bit coin (high half: word e & 3 of the tag-2 call at e >> 2;
+    # low half: word 0 of the tag-3 call at e) < floor(w * 2^64)
     rng = np.random.Generator(np.random.PCG64(5))
     for _ in range(500):
         seed, j, e = int(rng.integers(0, 1 << 40)), int(rng.integers(0, 1 << 33)), int(rng.integers(0, 1 << 31))
@@ -76,3 +77,51 @@ def test_edge_coin_definition():
     hits = sum(oracle.edge_coin(1, j, 0, 0.3) for j in range(40000))
     p = float(np.float32(0.3))
     assert abs(hits / 40000 - p) < 5 * np.sqrt(p * (1 - p) / 40000)
+
+
+def test_edge_coin_high_words_share_one_call():
+    # four consecutive edges 4c..4c+3 take their high halves from the four words of one call
+    seed, j = 0x1234_5678_9ABC, 77
+    for c in (0, 1, 12345, (1 << 29) - 1):
+        y = pyphilox.philox4x32_10((c, j, 0, pyphilox.TAG_EDGE), (seed & 0xFFFFFFFF, seed >> 32))
+        for h in range(4):
+            assert pyphilox.edge_coin_word(seed, j, 4 * c + h) >> 32 == y[h]
+
+
+def _tie_cases(seed, e, count):
+    # sample ids whose coin high half is below 2^23, so that a float32 w puts the threshold's
+    # high half exactly on it with a non-zero low half
+    out = []
+    j = 0
+    while len(out) < count:
+        hi = pyphilox.edge_coin_word(seed, j, e) >> 32
+        if hi < (1 << 23):
+            out.append((j, hi))
+        j += 1
+    return out
+
+
+def test_edge_coin_tie_of_high_halves_decided_by_low_half():
+    # w = (hi + 1/2) * 2^-32 is a float32 for hi < 2^23 and floor(w * 2^64) = hi:2^31, so the
+    # high halves tie and the edge is live iff the low half is below 2^31
+    seed = 99
+    live_seen = set()
+    for e in (0, 3, 6, 1001):
+        for j, hi in _tie_cases(seed, e, 4):
+            w = np.float32((hi + 0.5) * 2.0 ** -32)
+            assert float(w) == (hi + 0.5) * 2.0 ** -32
+            thr = int(np.float64(w) * 2.0 ** 64)
+            assert thr >> 32 == hi and thr & 0xFFFFFFFF == 1 << 31
+            lo = pyphilox.edge_coin_word(seed, j, e) & 0xFFFFFFFF
+            got = oracle.edge_coin(seed, j, e, float(w))
+            assert got == (lo < (1 << 31))
+            live_seen.add(got)
+            # the threshold's low half at zero: a tie of the high halves is never live
+            w0 = np.float32(hi * 2.0 ** -32)
+            if int(np.float64(w0) * 2.0 ** 64) == hi << 32:
+                assert not oracle.edge_coin(seed, j, e, float(w0))
+            # one more than the tie in the high half: always live
+            w1 = np.float32((hi + 1) * 2.0 ** -32)
+            if int(np.float64(w1) * 2.0 ** 64) >> 32 == hi + 1:
+                assert oracle.edge_coin(seed, j, e, float(w1))
+    assert live_seen == {False, True}
