@@ -49,7 +49,8 @@ struct GreedyState {
     unsigned done;              // blocks of k_greedy_argmax that have finished
     int32_t vstar;              // this round's pick (-1: none left)
     unsigned shrunk;            // a heavy round has cut the lists down (they are in the work copy)
-    unsigned long long listed;  // samples newly covered this round
+    int32_t cur;                // which of the two delta buffers holds the current counts
+    unsigned long long dstar;   // delta of this round's pick: the samples it newly covers
     unsigned long long cov;     // coverage of the picks so far
     double est;
 };

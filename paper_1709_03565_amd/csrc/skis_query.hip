@@ -339,11 +339,10 @@ __global__ __launch_bounds__(256) void k_est_split_finish(EstSplit *__restrict__
 // ---------------------------------------------------------------------------------------
 // Greedy (Alg. 3) with exact marginal coverage.  delta[v] = #{ j in H(v) : j not covered }.
 // Each round: k_greedy_argmax picks the node of largest gain fl(fl(delta * Gamma) / T) + q_v
-// (Eq. margin; smallest id on ties); k_greedy_mark sets the covered bits of H(v*) and lists
-// the samples it newly covers; k_greedy_decrement lowers delta of every member of those
-// samples.  The most frequent nodes (the transpose's hot list) are decremented in LDS per
-// workgroup and flushed once, so hubs do not serialise on one counter.  Integer updates
-// commute, so delta and the picks are exact.
+// (Eq. margin; smallest id on ties); k_greedy_cover sets the covered bits of H(v*) and lowers
+// delta of every member of the samples it newly covers, or, when they are many,
+// k_greedy_recount counts delta afresh from the lists.  Three launches per round and no host
+// synchronisation inside the k rounds.
 // ---------------------------------------------------------------------------------------
 // A round that covers more than T / RECOUNT_DIV samples recounts Delta of every node from
 // its list instead of decrementing the members of each newly covered sample.
@@ -354,7 +353,7 @@ constexpr int RECOUNT_UNROLL = 8;  // loads in flight per lane
 
 __device__ __forceinline__ bool heavy_round(const GreedyState *st, uint64_t T)
 {
-    return st->vstar >= 0 && st->listed > T / RECOUNT_DIV;
+    return st->vstar >= 0 && st->dstar > T / RECOUNT_DIV;
 }
 
 __device__ __forceinline__ double gain_of(int64_t d, uint64_t T, double Gamma, double q)
@@ -415,8 +414,11 @@ __device__ __forceinline__ void block_best(double &g, int32_t &v, double *sg, in
 // gains are formed; the last workgroup to finish reduces the per-workgroup winners.
 constexpr int ARGMAX_PER = 16;
 
+// delta lives in two buffers: a round that recounts writes the spare one (kept zero), and
+// the next argmax switches to it and zeroes the one it leaves as it scans.
 __global__ __launch_bounds__(256) void k_greedy_argmax(int32_t n, int round, uint64_t T, double Gamma,
-                                                       const int32_t *__restrict__ delta, const double *__restrict__ qv,
+                                                       int32_t *__restrict__ delta0, int32_t *__restrict__ delta1,
+                                                       const double *__restrict__ qv,
                                                        uint8_t *__restrict__ chosen, double *__restrict__ part_g,
                                                        int32_t *__restrict__ part_v, GreedyState *__restrict__ st,
                                                        int32_t *__restrict__ seeds,
@@ -425,6 +427,10 @@ __global__ __launch_bounds__(256) void k_greedy_argmax(int32_t n, int round, uin
     __shared__ double sg[4];
     __shared__ int32_t sv[4];
     __shared__ bool last;
+    const bool recounted = heavy_round(st, T); // the previous round (st is rewritten by the last block)
+    const int cur = st->cur ^ (recounted ? 1 : 0);
+    const int32_t *delta = cur ? delta1 : delta0;
+    int32_t *spare = cur ? delta0 : delta1;
     double bg = 0.0;
     int32_t bv = -1;
     for (int64_t v0 = (int64_t)blockIdx.x * 256 * ARGMAX_PER + threadIdx.x; v0 < n;
@@ -439,6 +445,7 @@ __global__ __launch_bounds__(256) void k_greedy_argmax(int32_t n, int round, uin
             c[u] = in ? chosen[v] : (uint8_t)1;
             d[u] = in ? delta[v] : 0;
             q[u] = in ? qv[v] : 0.0;
+            if (recounted && in) spare[v] = 0;
         }
 #pragma unroll
         for (int u = 0; u < ARGMAX_PER; ++u) {
@@ -475,14 +482,17 @@ __global__ __launch_bounds__(256) void k_greedy_argmax(int32_t n, int round, uin
     block_best(bg, bv, sg, sv);
     if (threadIdx.x == 0) {
         st->done = 0u;
-        if (heavy_round(st, T)) st->shrunk = 1u; // the previous round rewrote the spans
-        st->listed = 0ull;
+        if (recounted) {
+            st->shrunk = 1u; // the previous round rewrote the spans
+            st->cur = cur;
+        }
         if (bv < 0) { // nothing left to pick (cannot happen for k <= n)
             st->vstar = -1;
             return;
         }
         st->vstar = bv;
         const int32_t d = delta[bv];
+        st->dstar = (unsigned long long)d;
         seeds[round] = bv;
         marg[round] = (unsigned long long)d;
         chosen[bv] = 1;
@@ -490,24 +500,40 @@ __global__ __launch_bounds__(256) void k_greedy_argmax(int32_t n, int round, uin
     }
 }
 
-// Covers H(v*): lists every sample whose covered bit flips.  H(v*) is in ascending sample
-// order, so each lane takes a run of MARK_RUN consecutive entries and sets the bits of one
-// bitmap word with one atomicOr; the newly covered samples are appended once per wave.
+// Covers H(v*).  H(v*) is in ascending sample order, so each lane takes a run of MARK_RUN
+// consecutive entries and sets the bits of one bitmap word with one atomicOr.  In a round that
+// does not recount, each wave queues the samples it newly covered in LDS and lowers delta of
+// every member of each (16 lanes per sample); the most frequent nodes (the transpose's hot
+// list) are decremented in LDS per workgroup and flushed once, so hubs do not serialise on
+// one counter.  Integer updates commute, so delta and the picks are exact.  The number of
+// samples a round newly covers is delta of its pick, known before the round starts.
 constexpr int MARK_RUN = 8;
 
-__global__ __launch_bounds__(256) void k_greedy_mark(const GreedyState *__restrict__ st,
-                                                     const int64_t *__restrict__ node_ptr,
-                                                     const int32_t *__restrict__ node_samples,
-                                                     uint32_t *__restrict__ covered, uint32_t *__restrict__ list,
-                                                     unsigned long long *__restrict__ listed)
+__global__ __launch_bounds__(256) void k_greedy_cover(const GreedyState *__restrict__ st, uint64_t T,
+                                                      const int64_t *__restrict__ node_ptr,
+                                                      const int32_t *__restrict__ node_samples,
+                                                      uint32_t *__restrict__ covered,
+                                                      const int64_t *__restrict__ sptr,
+                                                      const int32_t *__restrict__ nodes,
+                                                      const int32_t *__restrict__ hot_id,
+                                                      const int32_t *__restrict__ hot_node, int nhot,
+                                                      int32_t *__restrict__ delta0, int32_t *__restrict__ delta1)
 {
+    __shared__ int32_t hd[GREEDY_HOT];
+    __shared__ uint32_t queue[4][64 * MARK_RUN];
     const int32_t v = st->vstar;
     if (v < 0) return;
+    const bool update = !heavy_round(st, T);
+    int32_t *delta = st->cur ? delta1 : delta0;
+    if (update)
+        for (int h = threadIdx.x; h < nhot; h += 256) hd[h] = 0;
+    __syncthreads();
     const int64_t a = node_ptr[v], b = node_ptr[v + 1];
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t c0 = a + wave * 64 * MARK_RUN; c0 < b; c0 += nwaves * 64 * MARK_RUN) {
+    uint32_t *q = queue[wid];
+    for (int64_t c0 = a + wave * 64 * MARK_RUN; c0 < b; c0 += nwaves * 64 * MARK_RUN) { // uniform per wave
         const int64_t r0 = c0 + (int64_t)lane * MARK_RUN;
         int32_t js[MARK_RUN];
         int n = 0;
@@ -528,17 +554,39 @@ __global__ __launch_bounds__(256) void k_greedy_mark(const GreedyState *__restri
                 if (newb & (1u << (js[t] & 31))) fresh |= 1u << t;
             k = k1;
         }
+        if (!update) continue;
         const int cnt = __popc(fresh);
         const int incl = wave_incl_scan(cnt);
-        const int tot = __shfl(incl, 63, 64);
+        const int tot = (int)lane_value((uint32_t)incl, 63);
         if (!tot) continue;
-        unsigned long long base = 0;
-        if (lane == 0) base = atomicAdd(listed, (unsigned long long)tot);
-        base = __shfl(base, 0, 64) + (unsigned long long)(incl - cnt);
+        int pos = incl - cnt;
 #pragma unroll
         for (int t = 0; t < MARK_RUN; ++t)
-            if (fresh & (1u << t)) list[base++] = (uint32_t)js[t];
+            if (fresh & (1u << t)) q[pos++] = (uint32_t)js[t];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int g = lane >> 4, gl = lane & 15; // 4 samples at a time, 16 lanes each
+        for (int i0 = 0; i0 < tot; i0 += 4) {
+            const int i = i0 + g;
+            if (i >= tot) continue;
+            const uint32_t j = q[i];
+            const int64_t sa = sptr[j], sb = sptr[j + 1];
+            for (int64_t t = sa + gl; t < sb; t += 16) {
+                const int32_t u = nodes[t];
+                const int32_t h = hot_id ? hot_id[u] : -1;
+                if (h >= 0) atomicSub(&hd[h], 1);
+                else atomicSub(&delta[u], 1);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront"); // the queue is reused next
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
+    if (!update) return;
+    __syncthreads();
+    for (int h = threadIdx.x; h < nhot; h += 256)
+        if (hd[h]) atomicAdd(&delta[hot_node[h]], hd[h]);
 }
 
 // Work items for the recount: each node's list cut into spans of RECOUNT_SPAN entries.
@@ -568,14 +616,6 @@ __global__ __launch_bounds__(256) void k_recount_items_fill(int32_t n, const int
     }
 }
 
-__global__ __launch_bounds__(256) void k_recount_zero(const GreedyState *__restrict__ st, uint64_t T, int32_t n,
-                                                      int32_t *__restrict__ delta)
-{
-    if (!heavy_round(st, T)) return;
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
-        delta[v] = 0;
-}
-
 // delta[v] += #{ j in span : j not covered }, and the span is cut down to those samples:
 // the first heavy round reads node v's list from the sketch and writes the uncovered part
 // to the same offsets of `work`; later heavy rounds read and rewrite `work` in place (a kept
@@ -586,9 +626,10 @@ __global__ __launch_bounds__(256) void k_greedy_recount(const GreedyState *__res
                                                         uint64_t nitems, RecountItem *__restrict__ items,
                                                         const int32_t *node_samples, int32_t *work,
                                                         const uint32_t *__restrict__ covered,
-                                                        int32_t *__restrict__ delta)
+                                                        int32_t *__restrict__ delta0, int32_t *__restrict__ delta1)
 {
     if (!heavy_round(st, T)) return;
+    int32_t *delta = st->cur ? delta0 : delta1; // the spare buffer, all zero; the next argmax switches
     const int32_t *src = st->shrunk ? work : node_samples;
     constexpr int G = 64 / RECOUNT_LANES;
     const int lane = threadIdx.x & 63, grp = lane / RECOUNT_LANES, t = lane % RECOUNT_LANES;
@@ -626,36 +667,6 @@ __global__ __launch_bounds__(256) void k_greedy_recount(const GreedyState *__res
             if (kept) atomicAdd(&delta[w.v], kept);
         }
     }
-}
-
-// Lowers delta of every member of every newly covered sample.
-__global__ __launch_bounds__(256) void k_greedy_decrement(const GreedyState *__restrict__ st, uint64_t T,
-                                                          const uint32_t *__restrict__ list,
-                                                          const int64_t *__restrict__ sptr,
-                                                          const int32_t *__restrict__ nodes,
-                                                          const int32_t *__restrict__ hot_id,
-                                                          const int32_t *__restrict__ hot_node, int nhot,
-                                                          int32_t *__restrict__ delta)
-{
-    __shared__ int32_t hd[GREEDY_HOT];
-    if (st->vstar < 0 || heavy_round(st, T)) return;
-    const uint64_t cnt = st->listed;
-    for (int h = threadIdx.x; h < nhot; h += 256) hd[h] = 0;
-    __syncthreads();
-    const int lane = threadIdx.x & 15, sub = threadIdx.x >> 4; // 16 lanes per sample
-    for (uint64_t i = (uint64_t)blockIdx.x * 16 + sub; i < cnt; i += (uint64_t)gridDim.x * 16) {
-        const uint32_t j = list[i];
-        const int64_t a = sptr[j], b = sptr[j + 1];
-        for (int64_t t = a + lane; t < b; t += 16) {
-            const int32_t u = nodes[t];
-            const int32_t h = hot_id ? hot_id[u] : -1;
-            if (h >= 0) atomicSub(&hd[h], 1);
-            else atomicSub(&delta[u], 1);
-        }
-    }
-    __syncthreads();
-    for (int h = threadIdx.x; h < nhot; h += 256)
-        if (hd[h]) atomicAdd(&delta[hot_node[h]], hd[h]);
 }
 
 // second term of Eq. margin summed over the k picks (each node is picked at most once)
@@ -834,23 +845,24 @@ void greedy(const Sketch &sk, QueryScratch &qs, int32_t k, int32_t *seeds, uint6
     Arena &arena = const_cast<Arena &>(sk.arena);
     const int32_t n = sk.n;
     const uint64_t wordsT = (sk.T + 31) / 32;
-    DevBuf<int32_t> delta;
+    DevBuf<int32_t> delta, delta_spare; // the counts and the buffer a recounting round fills
     DevBuf<uint8_t> chosen;
-    DevBuf<uint32_t> covered, list;
+    DevBuf<uint32_t> covered;
     DevBuf<GreedyState> st;
     const unsigned ga = gridq(((uint64_t)n + ARGMAX_PER - 1) / ARGMAX_PER, 256, 4);
     DevBuf<double> pg;
     DevBuf<int32_t> pv;
     delta.alloc(arena, n);
+    delta_spare.alloc(arena, n);
     chosen.alloc(arena, n);
     covered.alloc(arena, wordsT ? wordsT : 1);
-    list.alloc(arena, sk.T ? sk.T : 1);
     st.alloc(arena, 1);
     pg.alloc(arena, ga);
     pv.alloc(arena, ga);
     hipLaunchKernelGGL(k_greedy_init, dim3(gridq(n, 256)), dim3(256), 0, s, n, sk.node_ptr.ptr, delta.ptr, chosen.ptr);
     hipLaunchKernelGGL(k_fill_q<uint32_t>, dim3(gridq(wordsT ? wordsT : 1, 256)), dim3(256), 0, s,
                        wordsT ? wordsT : 1, covered.ptr, 0u);
+    hipLaunchKernelGGL(k_fill_q<int32_t>, dim3(gridq(n, 256)), dim3(256), 0, s, (uint64_t)n, delta_spare.ptr, 0);
     hipLaunchKernelGGL(k_fill_q<unsigned char>, dim3(1), dim3(64), 0, s, (uint64_t)sizeof(GreedyState),
                        reinterpret_cast<unsigned char *>(st.ptr), (unsigned char)0);
     SKIS_HIP_TRY(hipGetLastError());
@@ -881,17 +893,16 @@ void greedy(const Sketch &sk, QueryScratch &qs, int32_t k, int32_t *seeds, uint6
     }
     const unsigned gr = gridq(nit * RECOUNT_LANES, 256, 8);
     for (int32_t r = 0; r < k; ++r) {
-        hipLaunchKernelGGL(k_greedy_argmax, dim3(ga), dim3(256), 0, s, n, (int)r, sk.T, sk.Gamma, delta.ptr, sk.q.ptr,
-                           chosen.ptr, pg.ptr, pv.ptr, st.ptr, seeds, reinterpret_cast<unsigned long long *>(marg));
+        hipLaunchKernelGGL(k_greedy_argmax, dim3(ga), dim3(256), 0, s, n, (int)r, sk.T, sk.Gamma, delta.ptr,
+                           delta_spare.ptr, sk.q.ptr, chosen.ptr, pg.ptr, pv.ptr, st.ptr, seeds,
+                           reinterpret_cast<unsigned long long *>(marg));
         if (sk.T) {
-            hipLaunchKernelGGL(k_greedy_mark, dim3(gu), dim3(256), 0, s, st.ptr, sk.node_ptr.ptr, sk.node_samples.ptr,
-                               covered.ptr, list.ptr, &st.ptr->listed);
-            // exactly one of the two updates does work, decided on the device from the count
-            hipLaunchKernelGGL(k_greedy_decrement, dim3(gu), dim3(256), 0, s, st.ptr, sk.T, list.ptr,
-                               sk.sample_ptr.ptr, sk.nodes.ptr, hot_id, sk.hot_node.ptr, nhot, delta.ptr);
-            hipLaunchKernelGGL(k_recount_zero, dim3(gridq(n, 256)), dim3(256), 0, s, st.ptr, sk.T, n, delta.ptr);
+            // the cover lowers delta itself unless the round recounts, decided on the device
+            hipLaunchKernelGGL(k_greedy_cover, dim3(gu), dim3(256), 0, s, st.ptr, sk.T, sk.node_ptr.ptr,
+                               sk.node_samples.ptr, covered.ptr, sk.sample_ptr.ptr, sk.nodes.ptr, hot_id,
+                               sk.hot_node.ptr, nhot, delta.ptr, delta_spare.ptr);
             hipLaunchKernelGGL(k_greedy_recount, dim3(gr), dim3(256), 0, s, st.ptr, sk.T, nit, items.ptr,
-                               sk.node_samples.ptr, work.ptr, covered.ptr, delta.ptr);
+                               sk.node_samples.ptr, work.ptr, covered.ptr, delta.ptr, delta_spare.ptr);
         }
     }
     SKIS_HIP_TRY(hipGetLastError());
