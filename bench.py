@@ -33,18 +33,18 @@ def algorithmic_bytes(T: int, entries: int, probed: int) -> int:
     return 40 * T + 12 * entries + 8 * probed
 
 
-# (threads, slots, visited, pairs per lane) -> (hash size, items per pass) of the first-tier
+# (threads, slots, visited, quads per lane) -> (hash size, items per pass) of the first-tier
 # kernel the library compiles for that shape
-_TIER0 = {(64, 4, 192, 4): (256, 128), (64, 4, 192, 2): (256, 64), (64, 4, 256, 4): (320, 128),
-          (64, 4, 256, 2): (320, 64), (64, 2, 256, 2): (320, 64), (64, 3, 256, 2): (320, 64), (64, 2, 384, 2): (512, 64), (64, 6, 256, 4): (320, 192), (64, 8, 128, 4): (172, 256),
-          (64, 8, 192, 4): (256, 256), (64, 8, 192, 2): (256, 256), (64, 8, 256, 4): (344, 256),
-          (64, 12, 192, 4): (256, 384), (64, 16, 128, 4): (172, 512), (64, 16, 64, 4): (88, 512),
-          (256, 16, 128, 4): (172, 1024), (256, 32, 128, 4): (172, 1024), (256, 16, 256, 4): (344, 1024)}
+_TIER0 = {(64, 4, 192, 2): (256, 128), (64, 4, 192, 1): (256, 64), (64, 4, 256, 2): (320, 128),
+          (64, 4, 256, 1): (320, 64), (64, 2, 256, 1): (320, 64), (64, 3, 256, 1): (320, 64), (64, 2, 384, 1): (512, 64), (64, 6, 256, 2): (320, 192), (64, 8, 128, 2): (172, 256),
+          (64, 8, 192, 2): (256, 256), (64, 8, 192, 1): (256, 256), (64, 8, 256, 2): (344, 256),
+          (64, 12, 192, 2): (256, 384), (64, 16, 128, 2): (172, 512), (64, 16, 64, 2): (88, 512),
+          (256, 16, 128, 2): (172, 1024), (256, 32, 128, 2): (172, 1024), (256, 16, 256, 2): (344, 1024)}
 
 
 def tier0_kernel_name(opts) -> str:
     key = (opts.get("threads_per_block", 64), opts.get("slots_per_block", 4), opts.get("visited_threshold", 192),
-           opts.get("pairs_per_lane", 2))
+           opts.get("quads_per_lane", 1))
     hcap, icap = _TIER0[key]
     return "k_sample<%d, %d, %d, %d, %d, %d, 0>" % (key[0], key[1], key[2], hcap, icap, key[3])
 
@@ -207,7 +207,7 @@ def main():
     ap.add_argument("--visited", type=int, default=0)
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--big-row", type=int, default=0)
-    ap.add_argument("--ppl", type=int, default=0, help="edge pairs per lane per sweep in the first tier (2 or 4)")
+    ap.add_argument("--qpl", type=int, default=0, help="edge quads per lane per sweep in the first tier (1 or 2)")
     ap.add_argument("--form", type=int, default=0, help="0: persistent sampler, 1: plain (one launch per level)")
     ap.add_argument("--no-autotune", action="store_true", help="use the library's default sampler shape")
     ap.add_argument("--no-plain-compare", action="store_true",
@@ -271,13 +271,13 @@ def main():
         opts["threads_per_block"] = args.threads
     if args.big_row:
         opts["big_row"] = args.big_row
-    if args.ppl:
-        opts["pairs_per_lane"] = args.ppl
+    if args.qpl:
+        opts["quads_per_lane"] = args.qpl
     if args.form:
         opts["form"] = args.form
     tuned = None
     if not args.no_autotune and args.form == 0 and not (args.slots or args.visited or args.threads or args.big_row
-                                                         or args.ppl):
+                                                         or args.qpl):
         from paper_1709_03565_amd import autotune
         tuned = autotune.autotune(rp, col, w, pilot_samples=T, log=log)
         opts.update(autotune.options_from(tuned))

@@ -59,17 +59,18 @@ typedef struct skis_options {
     uint32_t big_row;             /* in-degree above which the first tier hands a sample on */
     uint32_t build_inverse_index; /* 1 (default): build node->samples for estimate / greedy; 0: build only */
     uint32_t threads_per_block;   /* 64 (default: one wave per workgroup) or 256.  Supported
-                                     (threads, slots, visited, pairs_per_lane):
-                                     (64,4,192,2) default, (64,4,192,4), (64,16,128,4),
-                                     (64,4,256,4), (64,4,256,2), (64,2,256,2), (64,3,256,2),
-                                     (64,2,384,2), (64,6,256,4), (64,8,128,4),
-                                     (64,8,192,4), (64,8,192,2), (64,8,256,4), (64,12,192,4),
-                                     (64,16,64,4), (256,16,128,4), (256,32,128,4), (256,16,256,4) */
+                                     (threads, slots, visited, quads_per_lane):
+                                     (64,4,192,1) default, (64,4,192,2), (64,16,128,2),
+                                     (64,4,256,2), (64,4,256,1), (64,2,256,1), (64,3,256,1),
+                                     (64,2,384,1), (64,6,256,2), (64,8,128,2),
+                                     (64,8,192,2), (64,8,192,1), (64,8,256,2), (64,12,192,2),
+                                     (64,16,64,2), (256,16,128,2), (256,32,128,2), (256,16,256,2) */
     uint64_t max_device_bytes;    /* 0 = unlimited; larger total allocation -> SKIS_ENOMEM */
     uint64_t staging_entries;     /* initial staging capacity in node entries (0 = auto) */
     uint64_t chunk_samples;       /* captured form: sample ids per graph replay (0 = 2^22) */
-    uint32_t pairs_per_lane;      /* first tier: most edge pairs a lane takes per sweep, 2 (default:
-                                     fewer registers, more workgroups resident) or 4 */
+    uint32_t quads_per_lane;      /* first tier: most edge quads (aligned groups of four edges)
+                                     a lane takes per sweep, 1 (default: fewer registers, more
+                                     workgroups resident) or 2 */
     uint32_t reserved_opt;
 } skis_options;
 

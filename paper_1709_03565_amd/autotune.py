@@ -27,11 +27,11 @@ import torch
 
 from . import skis
 
-# (threads_per_block, slots_per_block, visited_threshold, pairs_per_lane) the library is compiled for
-SHAPES = [(64, 4, 192, 4), (64, 4, 192, 2), (64, 4, 256, 4), (64, 4, 256, 2), (64, 2, 256, 2), (64, 3, 256, 2),
-          (64, 2, 384, 2), (64, 6, 256, 4), (64, 8, 128, 4),
-          (64, 8, 192, 4), (64, 8, 192, 2), (64, 8, 256, 4), (64, 12, 192, 4), (64, 16, 128, 4), (64, 16, 64, 4),
-          (256, 16, 128, 4), (256, 32, 128, 4), (256, 16, 256, 4)]
+# (threads_per_block, slots_per_block, visited_threshold, quads_per_lane) the library is compiled for
+SHAPES = [(64, 4, 192, 2), (64, 4, 192, 1), (64, 4, 256, 2), (64, 4, 256, 1), (64, 2, 256, 1), (64, 3, 256, 1),
+          (64, 2, 384, 1), (64, 6, 256, 2), (64, 8, 128, 2),
+          (64, 8, 192, 2), (64, 8, 192, 1), (64, 8, 256, 2), (64, 12, 192, 2), (64, 16, 128, 2), (64, 16, 64, 2),
+          (256, 16, 128, 2), (256, 32, 128, 2), (256, 16, 256, 2)]
 BIG_ROWS = [4096, 16384, 65536]
 
 _DEFAULT_CACHE = os.path.join(os.environ.get("SKIS_TUNE_CACHE", "/tmp"), "skis_autotune.json")
@@ -84,7 +84,7 @@ def autotune(row_ptr, col, w, pilot_samples: int = 1 << 24, seed: int = 1, shape
 
     first = []
     for (th, sl, vi, pl) in shapes:
-        o = dict(threads_per_block=th, slots_per_block=sl, visited_threshold=vi, pairs_per_lane=pl)
+        o = dict(threads_per_block=th, slots_per_block=sl, visited_threshold=vi, quads_per_lane=pl)
         first.append((trial(o, 1), o))
     first.sort(key=lambda x: x[0])
     best_opts, best_ms = None, None
@@ -110,4 +110,4 @@ def autotune(row_ptr, col, w, pilot_samples: int = 1 << 24, seed: int = 1, shape
 def options_from(tuned: dict) -> dict:
     """The skis_options fields of an autotune() result."""
     return {k: v for k, v in tuned.items() if k in ("threads_per_block", "slots_per_block", "visited_threshold",
-                                                    "pairs_per_lane", "big_row")}
+                                                    "quads_per_lane", "big_row")}

@@ -244,7 +244,7 @@ void skis_default_options(skis_options *opt)
     opt->max_device_bytes = 0;
     opt->staging_entries = 0;
     opt->chunk_samples = 0;
-    opt->pairs_per_lane = 2;
+    opt->quads_per_lane = 1;
 }
 
 int skis_preprocess(int32_t n, int64_t m, const int32_t *row_ptr, const int32_t *col, const float *w, double *P,
@@ -302,7 +302,7 @@ int skis_build_sketch(int32_t n, int64_t m, const int32_t *row_ptr, const int32_
             opt.max_device_bytes = opt_in->max_device_bytes;
             opt.staging_entries = opt_in->staging_entries;
             opt.chunk_samples = opt_in->chunk_samples;
-            if (opt_in->pairs_per_lane) opt.pairs_per_lane = opt_in->pairs_per_lane;
+            if (opt_in->quads_per_lane) opt.quads_per_lane = opt_in->quads_per_lane;
         }
         if (opt.form > 2) throw skis::Error{SKIS_EINVAL, "unknown sampler form"};
         skis_sketch *h = new skis_sketch;
@@ -340,7 +340,7 @@ int skis_build_sketch(int32_t n, int64_t m, const int32_t *row_ptr, const int32_
                     cfg.big_row = opt.big_row;
                     cfg.staging_entries = opt.staging_entries;
                     cfg.chunk = opt.chunk_samples;
-                    cfg.ppl = opt.pairs_per_lane;
+                    cfg.qpl = opt.quads_per_lane;
                     cfg.owners = opt.build_inverse_index != 0;
                     skis::sample_and_compact(sk.arena, prep, n, m, num_samples, seed, cfg, sk, stream);
                 }

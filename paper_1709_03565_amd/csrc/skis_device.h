@@ -9,7 +9,8 @@ typedef unsigned __int128 u128;
 
 constexpr uint32_t TAG_ROOT = 0u;   // Philox tag: root draw
 constexpr uint32_t TAG_FIRST = 1u;  // Philox tag: first live in-edge of the root
-constexpr uint32_t TAG_EDGE = 2u;   // Philox tag: live-edge coins, two edges per call
+constexpr uint32_t TAG_EDGE = 2u;   // Philox tag: high halves of the live-edge coins, four edges per call
+constexpr uint32_t TAG_EDGE_LOW = 3u; // Philox tag: low half of one edge's coin
 
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32->64-bit
 // multiplications with Weyl-bumped keys.  Returns the two 64-bit halves X = y1:y0 and
@@ -51,6 +52,25 @@ __device__ __forceinline__ uint64_t coin_threshold(uint32_t wbits)
 __device__ __forceinline__ bool coin_live(uint32_t wbits, uint64_t x)
 {
     return wbits >= 0x3F800000u || x < coin_threshold(wbits);
+}
+
+// The high half of the coin threshold floor(w * 2^64), or 0xFFFFFFFF for w >= 1.  An edge
+// whose coin has a high half below it is live, one above it is not, and one equal to it is
+// decided by coin_live on the whole coin (for w < 1 the threshold's high half is at most
+// 0xFFFFFF00, so 0xFFFFFFFF is free to mean "always live").
+__device__ __forceinline__ uint32_t coin_threshold_hi(uint32_t wbits)
+{
+    return wbits >= 0x3F800000u ? 0xFFFFFFFFu : (uint32_t)(coin_threshold(wbits) >> 32);
+}
+
+// The whole 64-bit coin of edge e in sample j given its high half: the low half is word 0
+// of the call with counter (e, j_lo, j_hi, TAG_EDGE_LOW).
+__device__ __forceinline__ uint64_t coin_with_low_half(uint32_t hi, uint32_t e, uint64_t j, uint32_t seed_lo,
+                                                       uint32_t seed_hi)
+{
+    uint64_t X, Y;
+    philox2x64(e, (uint32_t)j, (uint32_t)(j >> 32), TAG_EDGE_LOW, seed_lo, seed_hi, X, Y);
+    return ((uint64_t)hi << 32) | (uint32_t)X;
 }
 
 // Alias-table entry: bucket b yields b when r < thr, else alias.

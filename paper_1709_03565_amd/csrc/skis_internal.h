@@ -128,7 +128,9 @@ struct Sketch {
 // ---------------------------------------------------------------------------------
 struct Prep {
     DevBuf<int32_t> row_ptr;    // private copy [n+1]
-    DevBuf<uint2> edges;        // interleaved (col, w bits) per edge, padded to even length
+    DevBuf<uint2> edges;        // interleaved (col, coin_threshold_hi(w)) per edge, padded with
+                                // (0, 0) records to a multiple of four edges
+    DevBuf<uint32_t> wbits;     // [m] w bits per edge (+0 for -0): coin ties and the roots' fallback
     DevBuf<double> P;           // [m]
     DevBuf<double> q;           // [n]
     DevBuf<uint64_t> W;         // [n]
@@ -137,8 +139,8 @@ struct Prep {
     double Gamma = 0.0;
 };
 
-// Validates the graph, copies row_ptr, interleaves (col, w), computes P, q, W, C, Gamma and
-// (if build_alias) the alias table.  Throws Error on failure.
+// Validates the graph, copies row_ptr, interleaves (col, coin threshold), keeps the w bits,
+// computes P, q, W, C, Gamma and (if build_alias) the alias table.  Throws Error on failure.
 void preprocess(Arena &arena, int32_t n, int64_t m, const int32_t *row_ptr, const int32_t *col,
                 const float *w, bool build_alias, Prep &out, hipStream_t s);
 
@@ -153,7 +155,7 @@ struct SampleConfig {
     uint32_t big_row = 16384;
     uint64_t staging_entries = 0;
     uint64_t chunk = 0; // captured form: samples per replay of the chain (0: 2^22)
-    uint32_t ppl = 2;   // edge pairs per lane per sweep in the first tier
+    uint32_t qpl = 1;   // edge quads per lane per sweep in the first tier
     bool owners = false; // also write the sample id of every entry (Sketch::owner) for the transpose
 };
 

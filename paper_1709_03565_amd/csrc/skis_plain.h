@@ -7,8 +7,9 @@ namespace skis {
 struct PlainInputs {
     uint32_t count;                 // samples 0..count-1
     const int32_t *row_ptr;
-    const uint4 *pairs;
-    int64_t npairs;
+    const uint4 *pairs;             // edge records two at a time, padded to whole quads
+    int64_t nquads;
+    const uint32_t *wbits;          // w bits per edge
     const int4 *rec;
     const int32_t *u1;
     uint32_t seed_lo, seed_hi;

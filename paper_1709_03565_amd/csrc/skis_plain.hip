@@ -1,7 +1,7 @@
 // skis_plain.hip -- the plain form of the sampler: the reverse BFS of Alg. 1 advanced one
 // level per launch over every sample of a chunk at once.  Visited sets live in one global
 // open-addressing hash keyed by (sample, node); each level's frontier is a list of
-// (sample, edge range) items whose edges are swept two at a time with the same Philox
+// (sample, edge range) items whose edges are swept four at a time with the same Philox
 // coins as the persistent sampler, so both forms produce the same sets.  The host reads
 // the frontier size after every level.
 #include <algorithm>
@@ -13,14 +13,15 @@ namespace skis {
 
 constexpr unsigned long long HASH_EMPTY = ~0ull;
 constexpr int PLAIN_BLOCK = 256;
-constexpr int PLAIN_PPT = 4;                              // edge pairs per thread per launch window
-constexpr int PLAIN_WINDOW = PLAIN_BLOCK * PLAIN_PPT;     // pairs per workgroup window
+constexpr int PLAIN_PPT = 4;                              // edge quads per thread per launch window
+constexpr int PLAIN_WINDOW = PLAIN_BLOCK * PLAIN_PPT;     // quads per workgroup window
 constexpr uint64_t PLAIN_MAX_PROBE = 4096;                // longest probe run before a resize
 
 struct PlainCtx {
     const int32_t *row_ptr;
-    const uint4 *pairs;
-    int64_t npairs;
+    const uint4 *pairs;              // edge records two at a time, padded to whole quads
+    int64_t nquads;
+    const uint32_t *wbits;           // w bits per edge: coin ties
     unsigned long long *hash;
     uint64_t hmask;
     uint32_t *sizes;                 // per sample of the chunk
@@ -28,15 +29,15 @@ struct PlainCtx {
     uint2 *entries;                  // (sample in chunk, node)
     unsigned long long *n_entries;
     uint64_t entries_cap;
-    int4 *items_out;                 // (sample in chunk, edge begin, edge end, pairs)
+    int4 *items_out;                 // (sample in chunk, edge begin, edge end, quads)
     unsigned long long *n_items_out;
     uint64_t items_cap;
     int *err;
 };
 
-__device__ __forceinline__ uint32_t pair_count(int32_t beg, int32_t end)
+__device__ __forceinline__ uint32_t quad_count(int32_t beg, int32_t end)
 {
-    return end > beg ? (uint32_t)(((end - 1) >> 1) - (beg >> 1) + 1) : 0u;
+    return end > beg ? (uint32_t)(((end - 1) >> 2) - (beg >> 2) + 1) : 0u;
 }
 
 // Inserts (i, u); on success appends the entry and a frontier item for u's row.
@@ -54,7 +55,7 @@ __device__ __forceinline__ void plain_visit(const PlainCtx &c, uint32_t i, int32
             else atomicOr(c.err, 1);
             const int32_t rb = c.row_ptr[u], re = c.row_ptr[u + 1];
             atomicAdd(&c.probed[i], (unsigned long long)(re - rb));
-            const uint32_t np = pair_count(rb, re);
+            const uint32_t np = quad_count(rb, re);
             if (np) {
                 const unsigned long long k = atomicAdd(c.n_items_out, 1ull);
                 if (k < c.items_cap) c.items_out[k] = make_int4((int32_t)i, rb, re, (int32_t)np);
@@ -94,7 +95,7 @@ __global__ __launch_bounds__(PLAIN_BLOCK) void k_plain_init(uint32_t count, uint
             if (e < c.entries_cap) c.entries[e] = make_uint2(t, (uint32_t)r.x);
             else atomicOr(c.err, 1);
         }
-        const uint32_t np = pair_count(r.y + 1, r.w);
+        const uint32_t np = quad_count(r.y + 1, r.w);
         if (np) {
             const unsigned long long k = atomicAdd(c.n_items_out, 1ull);
             if (k < c.items_cap) c.items_out[k] = make_int4((int32_t)t, r.y + 1, r.w, (int32_t)np);
@@ -104,15 +105,15 @@ __global__ __launch_bounds__(PLAIN_BLOCK) void k_plain_init(uint32_t count, uint
     }
 }
 
-__global__ __launch_bounds__(PLAIN_BLOCK) void k_plain_pairs(uint64_t n_items, const int4 *__restrict__ items,
+__global__ __launch_bounds__(PLAIN_BLOCK) void k_plain_quads(uint64_t n_items, const int4 *__restrict__ items,
                                                              uint32_t *__restrict__ np)
 {
     for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n_items; k += (uint64_t)gridDim.x * blockDim.x)
         np[k] = (uint32_t)items[k].w;
 }
 
-// One level: every edge pair of every frontier item.  Workgroup b takes pairs
-// [b*W, (b+1)*W); the items it touches are found once and their pair offsets staged in LDS.
+// One level: every edge quad of every frontier item.  Workgroup b takes quads
+// [b*W, (b+1)*W); the items it touches are found once and their quad offsets staged in LDS.
 __global__ __launch_bounds__(PLAIN_BLOCK) void k_plain_expand(uint64_t n_items, const int4 *__restrict__ items,
                                                               const int64_t *__restrict__ pbase, int64_t total,
                                                               uint32_t seed_lo, uint32_t seed_hi, uint64_t j0,
@@ -122,7 +123,7 @@ __global__ __launch_bounds__(PLAIN_BLOCK) void k_plain_expand(uint64_t n_items, 
     __shared__ int64_t s_first;
     __shared__ int s_cnt;
     for (int64_t w0 = (int64_t)blockIdx.x * PLAIN_WINDOW; w0 < total; w0 += (int64_t)gridDim.x * PLAIN_WINDOW) {
-        if (threadIdx.x == 0) { // last item whose first pair is <= w0
+        if (threadIdx.x == 0) { // last item whose first quad is <= w0
             int64_t lo = 0, hi = (int64_t)n_items - 1;
             while (lo < hi) {
                 const int64_t mid = (lo + hi + 1) >> 1;
@@ -141,24 +142,31 @@ __global__ __launch_bounds__(PLAIN_BLOCK) void k_plain_expand(uint64_t n_items, 
         for (int g = 0; g < PLAIN_PPT; ++g) {
             const int64_t idx = w0 + (int64_t)g * PLAIN_BLOCK + threadIdx.x;
             if (idx >= total) break;
-            int lo = 0, hi = cnt - 1; // last window item whose first pair is <= idx
+            int lo = 0, hi = cnt - 1; // last window item whose first quad is <= idx
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
                 if (s_pb[mid] <= idx) lo = mid; else hi = mid - 1;
             }
             const int4 it = items[first + lo];
-            const int p = (it.y >> 1) + (int)(idx - s_pb[lo]);
-            if (p < 0 || (int64_t)p >= c.npairs) { // bounds guard: report, never index
+            const int qd = (it.y >> 2) + (int)(idx - s_pb[lo]);
+            if (qd < 0 || (int64_t)qd >= c.nquads) { // bounds guard: report, never index
                 atomicOr(c.err, 8);
                 continue;
             }
-            const uint4 pr = c.pairs[p];
+            const uint4 p0 = c.pairs[2 * qd], p1 = c.pairs[2 * qd + 1];
+            const uint32_t col[4] = {p0.x, p0.z, p1.x, p1.z}, th[4] = {p0.y, p0.w, p1.y, p1.w};
             const uint64_t j = j0 + (uint32_t)it.x;
             uint64_t X, Y;
-            philox2x64((uint32_t)p, (uint32_t)j, (uint32_t)(j >> 32), TAG_EDGE, seed_lo, seed_hi, X, Y);
-            const int e0 = 2 * p;
-            if (e0 >= it.y && coin_live(pr.y, X)) plain_visit(c, (uint32_t)it.x, (int32_t)pr.x);
-            if (e0 + 1 < it.z && coin_live(pr.w, Y)) plain_visit(c, (uint32_t)it.x, (int32_t)pr.z);
+            philox2x64((uint32_t)qd, (uint32_t)j, (uint32_t)(j >> 32), TAG_EDGE, seed_lo, seed_hi, X, Y);
+            const uint32_t hw[4] = {(uint32_t)X, (uint32_t)(X >> 32), (uint32_t)Y, (uint32_t)(Y >> 32)};
+            for (int h = 0; h < 4; ++h) {
+                const int e = 4 * qd + h;
+                if (e < it.y || e >= it.z) continue;
+                const bool live = hw[h] != th[h]
+                                      ? hw[h] < th[h]
+                                      : coin_live(c.wbits[e], coin_with_low_half(hw[h], (uint32_t)e, j, seed_lo, seed_hi));
+                if (live) plain_visit(c, (uint32_t)it.x, (int32_t)col[h]);
+            }
         }
         __syncthreads();
     }
@@ -265,7 +273,8 @@ void sample_plain(Arena &arena, const PlainInputs &in, PlainOutputs &out, hipStr
             PlainCtx c;
             c.row_ptr = in.row_ptr;
             c.pairs = in.pairs;
-            c.npairs = in.npairs;
+            c.nquads = in.nquads;
+            c.wbits = in.wbits;
             c.hash = hash.ptr;
             c.hmask = hcap - 1;
             c.sizes = sizes.ptr;
@@ -295,7 +304,7 @@ void sample_plain(Arena &arena, const PlainInputs &in, PlainOutputs &out, hipStr
                 const uint64_t n_items = hv[1];
                 if (n_items == 0) break;
                 ++out.levels;
-                hipLaunchKernelGGL(k_plain_pairs, dim3(gridp(n_items)), dim3(PLAIN_BLOCK), 0, s, (uint64_t)n_items, cur,
+                hipLaunchKernelGGL(k_plain_quads, dim3(gridp(n_items)), dim3(PLAIN_BLOCK), 0, s, (uint64_t)n_items, cur,
                                    np.ptr);
                 excl_scan_u32_to_i64(arena, np.ptr, pbase.ptr, (int64_t)n_items, pbase.ptr + n_items, s);
                 int64_t total = 0;

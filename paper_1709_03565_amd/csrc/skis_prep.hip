@@ -31,7 +31,8 @@ constexpr int PREFIX_BLOCK = 64;
 __global__ __launch_bounds__(256) void k_prep_rows(int32_t n, int64_t m, const int32_t *__restrict__ row_ptr,
                                                    const int32_t *__restrict__ col, const float *__restrict__ w,
                                                    int32_t *__restrict__ rp_copy, uint2 *__restrict__ edges,
-                                                   double *__restrict__ P, double *__restrict__ q, int *err,
+                                                   uint32_t *__restrict__ wbits, double *__restrict__ P,
+                                                   double *__restrict__ q, int *err,
                                                    int32_t *__restrict__ long_rows, unsigned int *__restrict__ n_long)
 {
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
@@ -57,7 +58,8 @@ __global__ __launch_bounds__(256) void k_prep_rows(int32_t n, int64_t m, const i
             float wf = w[e];
             bad |= check_edge(u, wf, v, n);
             if (wf == 0.0f) wf = 0.0f; // -0 -> +0: the coin reads the bits
-            edges[e] = make_uint2((uint32_t)u, __float_as_uint(wf));
+            edges[e] = make_uint2((uint32_t)u, coin_threshold_hi(__float_as_uint(wf)));
+            wbits[e] = __float_as_uint(wf);
             const double f = __dsub_rn(1.0, (double)wf);
             if ((e - a) % PREFIX_BLOCK == 0) {
                 if (e > a) carry = __dmul_rn(carry, local);
@@ -88,8 +90,8 @@ __device__ __forceinline__ int long_slot(int i) { return i + i / PREFIX_BLOCK; }
 
 __global__ __launch_bounds__(256) void k_prep_long(int32_t n, const int32_t *__restrict__ row_ptr,
                                                    const int32_t *__restrict__ col, const float *__restrict__ w,
-                                                   uint2 *__restrict__ edges, double *__restrict__ P,
-                                                   double *__restrict__ q, int *err,
+                                                   uint2 *__restrict__ edges, uint32_t *__restrict__ wbits,
+                                                   double *__restrict__ P, double *__restrict__ q, int *err,
                                                    const int32_t *__restrict__ long_rows,
                                                    const unsigned int *__restrict__ n_long)
 {
@@ -125,7 +127,8 @@ __global__ __launch_bounds__(256) void k_prep_long(int32_t n, const int32_t *__r
                     float wf = wc[k];
                     bad |= check_edge(uc[k], wf, v, n);
                     if (wf == 0.0f) wf = 0.0f; // -0 -> +0: the coin reads the bits
-                    edges[e] = make_uint2((uint32_t)uc[k], __float_as_uint(wf));
+                    edges[e] = make_uint2((uint32_t)uc[k], coin_threshold_hi(__float_as_uint(wf)));
+                    wbits[e] = __float_as_uint(wf);
                     s_f[long_slot(k * 256 + t)] = __dsub_rn(1.0, (double)wf);
                 }
             }
@@ -373,8 +376,9 @@ void preprocess(Arena &arena, int32_t n, int64_t m, const int32_t *row_ptr, cons
                 bool build_alias, Prep &out, hipStream_t s)
 {
     out.row_ptr.alloc(arena, (size_t)n + 1);
-    const size_t m_even = (size_t)(m + (m & 1));
-    out.edges.alloc(arena, m_even > 0 ? m_even : 2);
+    const size_t m_quad = (size_t)((m + 3) & ~(int64_t)3);
+    out.edges.alloc(arena, m_quad > 0 ? m_quad : 4);
+    out.wbits.alloc(arena, (size_t)(m > 0 ? m : 1));
     out.P.alloc(arena, (size_t)(m > 0 ? m : 1));
     out.q.alloc(arena, (size_t)n);
     out.W.alloc(arena, (size_t)n);
@@ -386,10 +390,10 @@ void preprocess(Arena &arena, int32_t n, int64_t m, const int32_t *row_ptr, cons
     long_rows.alloc(arena, (size_t)n);
     unsigned int *n_long = reinterpret_cast<unsigned int *>(err.ptr + 1);
     hipLaunchKernelGGL(k_prep_rows, dim3(grid_for(n)), dim3(256), 0, s, n, m, row_ptr, col, w, out.row_ptr.ptr,
-                       out.edges.ptr, out.P.ptr, out.q.ptr, err.ptr, long_rows.ptr, n_long);
+                       out.edges.ptr, out.wbits.ptr, out.P.ptr, out.q.ptr, err.ptr, long_rows.ptr, n_long);
     SKIS_HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_prep_long, dim3((unsigned)device_cu_count() * 4), dim3(256), 0, s, n, row_ptr, col, w,
-                       out.edges.ptr, out.P.ptr, out.q.ptr, err.ptr, long_rows.ptr, n_long);
+                       out.edges.ptr, out.wbits.ptr, out.P.ptr, out.q.ptr, err.ptr, long_rows.ptr, n_long);
     SKIS_HIP_TRY(hipGetLastError());
     int herr = 0;
     SKIS_HIP_TRY(hipMemcpyAsync(&herr, err.ptr, sizeof(int), hipMemcpyDeviceToHost, s));

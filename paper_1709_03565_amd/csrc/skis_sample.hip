@@ -5,8 +5,8 @@
 //   k_sample<...>  persistent sampler: every workgroup keeps S samples in flight, each
 //                  with its visited set and node list; the unexpanded nodes of all slots
 //                  form one flat list of (slot, edge range) items, and the lanes sweep the
-//                  edges of all items two at a time (one 16-byte load and one Philox call
-//                  per aligned edge pair).  GLOBAL=false keeps the visited set in LDS (an
+//                  edges of all items four at a time (two 16-byte loads and one Philox call
+//                  per aligned edge quad).  GLOBAL=false keeps the visited set in LDS (an
 //                  open-addressing hash) and hands a sample to the global tier when it
 //                  outgrows the hash or meets an in-degree above big_row; GLOBAL=true keeps
 //                  a bitmap of n bits and a node list of n entries per slot in HBM.
@@ -44,7 +44,7 @@ __global__ __launch_bounds__(256) void k_roots(uint64_t j0, uint32_t count, cons
                                                int32_t n, uint64_t C, const AliasEntry *__restrict__ alias,
                                                const int32_t *__restrict__ row_ptr, const double *__restrict__ q,
                                                const double *__restrict__ P, const uint2 *__restrict__ edges,
-                                               int4 *__restrict__ rec, int32_t *__restrict__ u1, int *__restrict__ err)
+                                               const uint32_t *__restrict__ wbits, int4 *__restrict__ rec, int32_t *__restrict__ u1, int *__restrict__ err)
 {
     const uint32_t base = range ? (uint32_t)range[0] : 0u;
     const uint32_t cnt = range ? (uint32_t)range[1] : count;
@@ -83,7 +83,7 @@ __global__ __launch_bounds__(256) void k_roots(uint64_t j0, uint32_t count, cons
         int32_t istar = lo;
         if (istar >= re) { // theta rounded up to gamma: last in-edge of positive probability
             istar = re - 1;
-            while (istar > rb && edges[istar].y == 0u) --istar;
+            while (istar > rb && wbits[istar] == 0u) --istar;
         }
         rec[i] = make_int4(root, istar, rb, re);
         u1[i] = (int32_t)edges[istar].x;
@@ -104,8 +104,10 @@ struct __align__(16) Handover {
 struct SampleArgs {
     int32_t n;
     const int32_t *row_ptr;
-    const uint4 *pairs;         // edges as aligned pairs (col[2p], w[2p], col[2p+1], w[2p+1])
-    int64_t npairs;
+    const uint4 *pairs;         // edge records two at a time: (col[2p], th[2p], col[2p+1], th[2p+1]),
+                                // th = coin_threshold_hi(w); padded to whole quads of edges
+    int64_t nquads;             // pairs holds 2 * nquads records
+    const uint32_t *wbits;      // w bits per edge, read when a coin's high half ties th
     const int4 *rec;
     const int32_t *u1;
     uint64_t j0;
@@ -146,11 +148,12 @@ struct SampleArgs {
 // RCAP: nodes a slot holds before its sample moves on (the visited threshold); HCAP: size
 // of the slot's open-addressing hash, any size above RCAP (about 4/3 RCAP keeps the load
 // factor at most 3/4 while leaving LDS for more slots).
-// ICAP: items (pending nodes over all slots) expanded per pass; PPL: most edge pairs a lane
-// takes per sweep (4 keeps more loads in flight, 2 needs fewer registers).
+// ICAP: items (pending nodes over all slots) expanded per pass; QPL: most edge quads (aligned
+// groups of four edges, one Philox call) a lane takes per sweep (2 keeps more loads in
+// flight, 1 needs fewer registers).
 // TIER: 0 the first LDS tier (hands its overflowing samples on with their state), 1 the
 // second LDS tier (resumes them), 2 the HBM tier (visited sets in global memory).
-template <int BLOCK, int S, int RCAP, int HCAP, int ICAP, int PPL, int TIER>
+template <int BLOCK, int S, int RCAP, int HCAP, int ICAP, int QPL, int TIER>
 __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
 {
     constexpr bool GLOBAL = TIER == 2;
@@ -384,7 +387,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                     const int32_t u = s_cu1[b][c];
                     if (cd >= (unsigned long long)IDBATCH || i >= (uint32_t)(id_base + (a.id_list ? 0x7FFFFFFFull : id_count)) ||
                         (uint32_t)r.x >= (uint32_t)n || (uint32_t)u >= (uint32_t)n || r.y < r.z || r.w <= r.y ||
-                        (int64_t)r.w > 2 * a.npairs) {
+                        (int64_t)r.w > 4 * a.nquads) {
                         atomicOr(a.overflow, 8); // bounds guard: the sample is left out
                     } else {
                     s_idx[s] = i;
@@ -627,12 +630,12 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                 it_slot[it] = (uint8_t)sl;
                 it_beg[it] = beg;
                 it_end[it] = end;
-                it_pb[it] = end > beg ? ((end - 1) >> 1) - (beg >> 1) + 1 : 0;
+                it_pb[it] = end > beg ? ((end - 1) >> 2) - (beg >> 2) + 1 : 0;
             }
         }
         block_sync<BLOCK>();
 
-        // ---- B3: prefix sum of edge pairs over the items -----------------------------------
+        // ---- B3: prefix sum of edge quads over the items -----------------------------------
         {
             int loc[IPT];
             int acc = 0;
@@ -654,61 +657,91 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
         }
         block_sync<BLOCK>();
 
-        // ---- B4: live-edge coins for every edge pair, visits ------------------------------
-        // Each lane takes ppl consecutive pairs (ppl = the fewest, up to PPL, that cover the
-        // pass in one sweep; uniform over the workgroup): one search for the first pair's
+        // ---- B4: live-edge coins for every edge quad, visits ------------------------------
+        // Each lane takes qpl consecutive quads (qpl = the fewest, up to QPL, that cover the
+        // pass in one sweep; uniform over the workgroup): one search for the first quad's
         // item, the next ones by stepping across item boundaries; all loads are issued
-        // before the coins are drawn.
+        // before the coins are drawn.  One Philox call gives the high halves of a quad's
+        // four coins; a high half equal to the edge's threshold (probability 2^-32) is
+        // settled on the whole coin after the sweep.
         const int total = it_pb[nitems];
-        const int ppl = total >= BLOCK * PPL ? PPL : (total + BLOCK - 1) / BLOCK;
-        for (int base = tid * ppl; base < total; base += BLOCK * ppl) {
-            int lo = 0, hi = nitems - 1; // last item whose first pair index is <= base
+        const int qpl = total >= BLOCK * QPL ? QPL : (total + BLOCK - 1) / BLOCK;
+        for (int base = tid * qpl; base < total; base += BLOCK * qpl) {
+            int lo = 0, hi = nitems - 1; // last item whose first quad index is <= base
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
                 if (it_pb[mid] <= base) lo = mid; else hi = mid - 1;
             }
-            int pp[PPL], ps[PPL], pbeg[PPL], pend[PPL];
+            int pq[QPL], ps[QPL];
+            uint32_t pin[QPL]; // edges of the quad inside the item's range, one bit each
 #pragma unroll
-            for (int g = 0; g < PPL; ++g) {
+            for (int g = 0; g < QPL; ++g) {
                 const int idx = base + g;
                 ps[g] = -1;
-                pp[g] = 0;
-                if (g >= ppl || idx >= total) continue;
+                pq[g] = 0;
+                pin[g] = 0u;
+                if (g >= qpl || idx >= total) continue;
                 while (it_pb[lo + 1] <= idx) ++lo; // it_pb[nitems] = total > idx
                 const int sl = it_slot[lo];
                 if (!GLOBAL && (s_flags[sl] & F_DEFER)) continue;
-                const int p = (it_beg[lo] >> 1) + (idx - it_pb[lo]);
-                if (p < 0 || (int64_t)p >= a.npairs) { // bounds guard: report, never index
+                const int q = (it_beg[lo] >> 2) + (idx - it_pb[lo]);
+                if (q < 0 || (int64_t)q >= a.nquads) { // bounds guard: report, never index
                     atomicOr(a.overflow, 2);
                     continue;
                 }
                 ps[g] = sl;
-                pp[g] = p;
-                pbeg[g] = it_beg[lo];
-                pend[g] = it_end[lo];
+                pq[g] = q;
+                const int lead = max(it_beg[lo] - 4 * q, 0), tail = max(4 * q + 4 - it_end[lo], 0);
+                pin[g] = (0xFu << lead) & (0xFu >> tail);
             }
-            // every load is issued, unconditionally (a lane without a pair reads pair 0, which
-            // exists whenever the pass has a pair at all), before any is used: a load under a
+            // every load is issued, unconditionally (a lane without a quad reads quad 0, which
+            // exists whenever the pass has a quad at all), before any is used: a load under a
             // branch would make the compiler wait for it before the next one
-            uint4 pr[PPL];
+            uint4 pr[2 * QPL];
 #pragma unroll
-            for (int g = 0; g < PPL; ++g) pr[g] = a.pairs[pp[g]];
-            // coins first; the live edges (bit 2g + h: edge h of pair g) are then visited
-            // through one call site, so the hash probing is not inlined 2 * PPL times
-            uint32_t live = 0u;
-#pragma unroll
-            for (int g = 0; g < PPL; ++g) {
-                if (g >= ppl) break;
-                if (ps[g] < 0) continue;
-                const int sl = ps[g];
-                const uint64_t j = a.j0 + s_idx[sl];
-                uint64_t X, Y;
-                philox2x64((uint32_t)pp[g], (uint32_t)j, (uint32_t)(j >> 32), TAG_EDGE, a.seed_lo, a.seed_hi, X, Y);
-                const int e0 = 2 * pp[g];
-                if (e0 >= pbeg[g] && coin_live(pr[g].y, X)) live |= 1u << (2 * g);
-                if (e0 + 1 < pend[g] && coin_live(pr[g].w, Y)) live |= 2u << (2 * g);
+            for (int g = 0; g < QPL; ++g) {
+                pr[2 * g] = a.pairs[2 * pq[g]];
+                pr[2 * g + 1] = a.pairs[2 * pq[g] + 1];
             }
-            static_assert(PPL <= 4, "the live-edge switch covers up to 4 pairs per lane");
+            // coins first; the live edges (bit 4g + h: edge h of quad g) are then visited
+            // through one call site, so the hash probing is not inlined 4 * QPL times
+            uint32_t live = 0u, tie = 0u;
+#pragma unroll
+            for (int g = 0; g < QPL; ++g) {
+                if (g >= qpl) break;
+                if (ps[g] < 0) continue;
+                const uint64_t j = a.j0 + s_idx[ps[g]];
+                uint64_t X, Y;
+                philox2x64((uint32_t)pq[g], (uint32_t)j, (uint32_t)(j >> 32), TAG_EDGE, a.seed_lo, a.seed_hi, X, Y);
+                const uint32_t hw[4] = {(uint32_t)X, (uint32_t)(X >> 32), (uint32_t)Y, (uint32_t)(Y >> 32)};
+                const uint32_t th[4] = {pr[2 * g].y, pr[2 * g].w, pr[2 * g + 1].y, pr[2 * g + 1].w};
+#pragma unroll
+                for (int h = 0; h < 4; ++h) {
+                    live |= (uint32_t)(hw[h] < th[h]) << (4 * g + h);
+                    tie |= (uint32_t)(hw[h] == th[h]) << (4 * g + h);
+                }
+                live &= ~(0xFu << (4 * g)) | (pin[g] << (4 * g));
+                tie &= ~(0xFu << (4 * g)) | (pin[g] << (4 * g));
+            }
+            static_assert(QPL <= 2, "the live-edge switch covers up to 2 quads per lane");
+            while (tie) { // almost never taken
+                const int c = __ffs(tie) - 1;
+                tie &= tie - 1u;
+                uint4 q;
+                switch (c >> 1) {
+                case 0: q = pr[0]; break;
+                case 1: q = pr[1]; break;
+                case 2: q = pr[QPL > 1 ? 2 : 0]; break;
+                default: q = pr[QPL > 1 ? 3 : 0]; break;
+                }
+                const bool g1 = QPL > 1 && c >= 4;
+                const int e = 4 * (g1 ? pq[QPL - 1] : pq[0]) + (c & 3);
+                const uint64_t j = a.j0 + s_idx[g1 ? ps[QPL - 1] : ps[0]];
+                // the coin's high half equals the threshold's
+                const uint32_t hw = (c & 1) ? q.w : q.y;
+                if (coin_live(a.wbits[e], coin_with_low_half(hw, (uint32_t)e, j, a.seed_lo, a.seed_hi)))
+                    live |= 1u << c;
+            }
             while (live) {
                 const int c = __ffs(live) - 1;
                 live &= live - 1u;
@@ -717,9 +750,9 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                 // a switch, not an index into pr[]: the arrays stay in registers
                 switch (c >> 1) {
                 case 0: q = pr[0]; sl = ps[0]; break;
-                case 1: q = pr[PPL > 1 ? 1 : 0]; sl = ps[PPL > 1 ? 1 : 0]; break;
-                case 2: q = pr[PPL > 2 ? 2 : 0]; sl = ps[PPL > 2 ? 2 : 0]; break;
-                default: q = pr[PPL > 3 ? 3 : 0]; sl = ps[PPL > 3 ? 3 : 0]; break;
+                case 1: q = pr[1]; sl = ps[0]; break;
+                case 2: q = pr[QPL > 1 ? 2 : 0]; sl = ps[QPL > 1 ? 1 : 0]; break;
+                default: q = pr[QPL > 1 ? 3 : 0]; sl = ps[QPL > 1 ? 1 : 0]; break;
                 }
                 visit(sl, (int32_t)((c & 1) ? q.z : q.x));
             }
@@ -1061,7 +1094,7 @@ struct Counters {
 typedef void (*SampleKernel)(SampleArgs);
 
 struct Variant {
-    uint32_t threads, slots, visited, ppl;
+    uint32_t threads, slots, visited, qpl;
     SampleKernel fn;
 };
 
@@ -1069,45 +1102,45 @@ struct Variant {
 // With 64 threads a workgroup is one wave that owns its slots and LDS and never waits for
 // another wave; with 256 threads four waves share the slots and meet at barriers.
 static const Variant kTier0[] = {
-    {64, 4, 192, 4, k_sample<64, 4, 192, 256, 128, 4, 0>},
-    {64, 4, 192, 2, k_sample<64, 4, 192, 256, 64, 2, 0>},
-    {64, 4, 256, 4, k_sample<64, 4, 256, 320, 128, 4, 0>},
-    {64, 4, 256, 2, k_sample<64, 4, 256, 320, 64, 2, 0>},
-    {64, 2, 256, 2, k_sample<64, 2, 256, 320, 64, 2, 0>},
-    {64, 3, 256, 2, k_sample<64, 3, 256, 320, 64, 2, 0>},
-    {64, 2, 384, 2, k_sample<64, 2, 384, 512, 64, 2, 0>},
-    {64, 6, 256, 4, k_sample<64, 6, 256, 320, 192, 4, 0>},
-    {64, 8, 128, 4, k_sample<64, 8, 128, 172, 256, 4, 0>},
-    {64, 8, 192, 4, k_sample<64, 8, 192, 256, 256, 4, 0>},
+    {64, 4, 192, 2, k_sample<64, 4, 192, 256, 128, 2, 0>},
+    {64, 4, 192, 1, k_sample<64, 4, 192, 256, 64, 1, 0>},
+    {64, 4, 256, 2, k_sample<64, 4, 256, 320, 128, 2, 0>},
+    {64, 4, 256, 1, k_sample<64, 4, 256, 320, 64, 1, 0>},
+    {64, 2, 256, 1, k_sample<64, 2, 256, 320, 64, 1, 0>},
+    {64, 3, 256, 1, k_sample<64, 3, 256, 320, 64, 1, 0>},
+    {64, 2, 384, 1, k_sample<64, 2, 384, 512, 64, 1, 0>},
+    {64, 6, 256, 2, k_sample<64, 6, 256, 320, 192, 2, 0>},
+    {64, 8, 128, 2, k_sample<64, 8, 128, 172, 256, 2, 0>},
     {64, 8, 192, 2, k_sample<64, 8, 192, 256, 256, 2, 0>},
-    {64, 8, 256, 4, k_sample<64, 8, 256, 344, 256, 4, 0>},
-    {64, 12, 192, 4, k_sample<64, 12, 192, 256, 384, 4, 0>},
-    {64, 16, 128, 4, k_sample<64, 16, 128, 172, 512, 4, 0>},
-    {64, 16, 64, 4, k_sample<64, 16, 64, 88, 512, 4, 0>},
-    {256, 16, 128, 4, k_sample<256, 16, 128, 172, 1024, 4, 0>},
-    {256, 32, 128, 4, k_sample<256, 32, 128, 172, 1024, 4, 0>},
-    {256, 16, 256, 4, k_sample<256, 16, 256, 344, 1024, 4, 0>},
+    {64, 8, 192, 1, k_sample<64, 8, 192, 256, 256, 1, 0>},
+    {64, 8, 256, 2, k_sample<64, 8, 256, 344, 256, 2, 0>},
+    {64, 12, 192, 2, k_sample<64, 12, 192, 256, 384, 2, 0>},
+    {64, 16, 128, 2, k_sample<64, 16, 128, 172, 512, 2, 0>},
+    {64, 16, 64, 2, k_sample<64, 16, 64, 88, 512, 2, 0>},
+    {256, 16, 128, 2, k_sample<256, 16, 128, 172, 1024, 2, 0>},
+    {256, 32, 128, 2, k_sample<256, 32, 128, 172, 1024, 2, 0>},
+    {256, 16, 256, 2, k_sample<256, 16, 256, 344, 1024, 2, 0>},
 };
 // second tier: samples that outgrew the first, slots of 1024 nodes in LDS
 static const Variant kTierMidV[] = {
-    {64, 2, 1024, 2, k_sample<64, 2, 1024, 1368, 128, 2, 1>},
-    {256, 8, 1024, 4, k_sample<256, 8, 1024, 1368, 1024, 4, 1>},
+    {64, 2, 1024, 1, k_sample<64, 2, 1024, 1368, 128, 1, 1>},
+    {256, 8, 1024, 2, k_sample<256, 8, 1024, 1368, 1024, 2, 1>},
 };
 // One sample per workgroup: the samples that reach this tier are few and large, so the
 // chip is filled with workgroups rather than slots; the HBM buffers of all slots are kept
 // within TIERG_BUDGET bytes.
 constexpr int TIERG_SLOTS = 1;
 constexpr uint64_t TIERG_BUDGET = 8ull << 30;
-static SampleKernel const kTierGlobal = k_sample<256, TIERG_SLOTS, 1, 1, 1024, 4, 2>;
+static SampleKernel const kTierGlobal = k_sample<256, TIERG_SLOTS, 1, 1, 1024, 2, 2>;
 
 static const Variant &pick_variant(const Variant *vs, size_t nv, uint32_t threads, uint32_t slots, uint32_t visited,
-                                   uint32_t ppl)
+                                   uint32_t qpl)
 {
     for (size_t i = 0; i < nv; ++i)
-        if (vs[i].threads == threads && vs[i].slots == slots && vs[i].visited == visited && vs[i].ppl == ppl)
+        if (vs[i].threads == threads && vs[i].slots == slots && vs[i].visited == visited && vs[i].qpl == qpl)
             return vs[i];
     throw Error{SKIS_EINVAL,
-                "unsupported (threads_per_block, slots_per_block, visited_threshold, pairs_per_lane) combination"};
+                "unsupported (threads_per_block, slots_per_block, visited_threshold, quads_per_lane) combination"};
 }
 
 static int occupancy_blocks(SampleKernel fn, int block)
@@ -1147,6 +1180,7 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
     need(prep.q.ptr, "q");
     need(prep.P.ptr, "P");
     need(prep.edges.ptr, "edges");
+    need(prep.wbits.ptr, "w bits");
 
     DevBuf<int4> rec;
     DevBuf<int32_t> u1;
@@ -1159,7 +1193,7 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
     if (cfg.form != 2) { // the captured form draws the roots inside its chain, chunk by chunk
         hipLaunchKernelGGL(k_roots, dim3(grid_cap(count, 256, 64)), dim3(256), 0, s, (uint64_t)0, count,
                            (const unsigned long long *)nullptr, seed_lo, seed_hi, n, prep.C, prep.alias.ptr,
-                           prep.row_ptr.ptr, prep.q.ptr, prep.P.ptr, prep.edges.ptr, rec.ptr, u1.ptr, rerr.ptr);
+                           prep.row_ptr.ptr, prep.q.ptr, prep.P.ptr, prep.edges.ptr, prep.wbits.ptr, rec.ptr, u1.ptr, rerr.ptr);
         SKIS_HIP_TRY(hipGetLastError());
     }
     SKIS_HIP_TRY(hipEventRecord(ev[1], s));
@@ -1177,7 +1211,7 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
     DevBuf<int32_t> staging;
     Counters hc{};
     const Variant &v0 =
-        pick_variant(kTier0, sizeof(kTier0) / sizeof(kTier0[0]), cfg.threads, cfg.slots, cfg.visited, cfg.ppl);
+        pick_variant(kTier0, sizeof(kTier0) / sizeof(kTier0[0]), cfg.threads, cfg.slots, cfg.visited, cfg.qpl);
     const Variant &vm = kTierMidV[cfg.threads == 64 ? 0 : 1];
     // handover from tier 0 to tier 1 for the first ho_cap samples a launch hands on (the rest
     // start over in tier 1): about 3 % of the samples at the default shape
@@ -1271,7 +1305,8 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
             A.n = n;
             A.row_ptr = prep.row_ptr.ptr;
             A.pairs = reinterpret_cast<const uint4 *>(prep.edges.ptr);
-            A.npairs = (int64_t)(prep.edges.count / 2);
+            A.nquads = (int64_t)(prep.edges.count / 4);
+            A.wbits = prep.wbits.ptr;
             A.rec = rec.ptr;
             A.u1 = u1.ptr;
             A.j0 = 0;
@@ -1325,7 +1360,7 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
             hipLaunchKernelGGL(k_chain_begin, dim3(1), dim3(64), 0, gg.cs, gc.ptr, (uint64_t)count, chunk);
             hipLaunchKernelGGL(k_roots, dim3(grid_cap(chunk, 256, 64)), dim3(256), 0, gg.cs, (uint64_t)0, 0u,
                                (const unsigned long long *)&gc.ptr->base, seed_lo, seed_hi, n, prep.C,
-                               prep.alias.ptr, prep.row_ptr.ptr, prep.q.ptr, prep.P.ptr, prep.edges.ptr, rec.ptr,
+                               prep.alias.ptr, prep.row_ptr.ptr, prep.q.ptr, prep.P.ptr, prep.edges.ptr, prep.wbits.ptr, rec.ptr,
                                u1.ptr, rerr.ptr);
             hipLaunchKernelGGL(v0.fn, dim3(nb0), dim3(v0.threads), 0, gg.cs, A0);
             hipLaunchKernelGGL(vm.fn, dim3(nbm), dim3(vm.threads), 0, gg.cs, A1);
@@ -1375,7 +1410,8 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
         in.count = count;
         in.row_ptr = prep.row_ptr.ptr;
         in.pairs = reinterpret_cast<const uint4 *>(prep.edges.ptr);
-        in.npairs = (int64_t)(prep.edges.count / 2);
+        in.nquads = (int64_t)(prep.edges.count / 4);
+        in.wbits = prep.wbits.ptr;
         in.rec = rec.ptr;
         in.u1 = u1.ptr;
         in.seed_lo = seed_lo;
@@ -1406,7 +1442,8 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
         A.n = n;
         A.row_ptr = prep.row_ptr.ptr;
         A.pairs = reinterpret_cast<const uint4 *>(prep.edges.ptr);
-        A.npairs = (int64_t)(prep.edges.count / 2);
+        A.nquads = (int64_t)(prep.edges.count / 4);
+        A.wbits = prep.wbits.ptr;
         A.rec = rec.ptr;
         A.u1 = u1.ptr;
         A.j0 = 0;

@@ -37,7 +37,7 @@ class Options(ctypes.Structure):
                 ("visited_threshold", ctypes.c_uint32), ("big_row", ctypes.c_uint32),
                 ("build_inverse_index", ctypes.c_uint32), ("threads_per_block", ctypes.c_uint32),
                 ("max_device_bytes", ctypes.c_uint64), ("staging_entries", ctypes.c_uint64),
-                ("chunk_samples", ctypes.c_uint64), ("pairs_per_lane", ctypes.c_uint32),
+                ("chunk_samples", ctypes.c_uint64), ("quads_per_lane", ctypes.c_uint32),
                 ("reserved_opt", ctypes.c_uint32)]
 
 

@@ -134,21 +134,21 @@ def test_sketch_bit_exact_cl15k(cl15k):
     assert np.array_equal(_np(sk.q()), oracle.row_prefix(g.row_ptr, g.w)[1])
 
 
-@pytest.mark.parametrize("threads,slots,visited,ppl,big_row", [
-    (64, 4, 192, 4, 16384), (64, 4, 192, 2, 16384), (64, 4, 256, 4, 16384), (64, 4, 256, 2, 16384),
-    (64, 2, 256, 2, 16384), (64, 3, 256, 2, 16384), (64, 2, 384, 2, 16384),
-    (64, 6, 256, 4, 16384), (64, 8, 128, 4, 16384), (64, 8, 192, 4, 16384), (64, 8, 192, 2, 16384),
-    (64, 8, 256, 4, 16384), (64, 12, 192, 4, 16384), (64, 16, 128, 4, 16384), (64, 16, 64, 4, 16384),
-    (256, 16, 128, 4, 16384), (256, 32, 128, 4, 16384), (256, 16, 256, 4, 16384),
-    (64, 8, 128, 4, 8), (256, 32, 128, 4, 8), (64, 16, 64, 4, 100), (64, 4, 192, 2, 8)])
-def test_sketch_identical_across_sampler_shapes(skis, threads, slots, visited, ppl, big_row):
+@pytest.mark.parametrize("threads,slots,visited,qpl,big_row", [
+    (64, 4, 192, 2, 16384), (64, 4, 192, 1, 16384), (64, 4, 256, 2, 16384), (64, 4, 256, 1, 16384),
+    (64, 2, 256, 1, 16384), (64, 3, 256, 1, 16384), (64, 2, 384, 1, 16384),
+    (64, 6, 256, 2, 16384), (64, 8, 128, 2, 16384), (64, 8, 192, 2, 16384), (64, 8, 192, 1, 16384),
+    (64, 8, 256, 2, 16384), (64, 12, 192, 2, 16384), (64, 16, 128, 2, 16384), (64, 16, 64, 2, 16384),
+    (256, 16, 128, 2, 16384), (256, 32, 128, 2, 16384), (256, 16, 256, 2, 16384),
+    (64, 8, 128, 2, 8), (256, 32, 128, 2, 8), (64, 16, 64, 2, 100), (64, 4, 192, 1, 8)])
+def test_sketch_identical_across_sampler_shapes(skis, threads, slots, visited, qpl, big_row):
     # big_row = 8 sends most samples through the second tier
     g = inputs.workload_graph("cl15k_wc")
     T = 30000
     _say("shape", threads, slots, visited, big_row)
     ora = oracle.build_sketch(g.row_ptr, g.col, g.w, seed=11, j0=0, j1=T, nthreads=8)
     sk = skis.build_sketch(g.row_ptr, g.col, g.w, T, 11, threads_per_block=threads, slots_per_block=slots,
-                           visited_threshold=visited, pairs_per_lane=ppl, big_row=big_row)
+                           visited_threshold=visited, quads_per_lane=qpl, big_row=big_row)
     inf = sk.info()
     _assert_tiers_add_up(inf)
     if big_row == 8:
@@ -250,6 +250,26 @@ def test_tiny_and_degenerate_shapes(skis):
             _assert_sketch_equal(sk, ora)
             _assert_sketch_equal(skis.build_sketch(rp, c, w, T, 3, form=1), ora)
             _assert_sketch_equal(skis.build_sketch(rp, c, w, T, 3, form=2, chunk_samples=3), ora)
+
+
+def test_coin_ties_of_the_high_halves(skis):
+    # edge weights that put the coin threshold's high half on the coin of one planted sample
+    # per edge: those samples take the low-half draw; all three forms match the oracle
+    import coin_ties
+    seed = 21
+    rp, c, w, planted = coin_ties.tie_star(seed)
+    T = 8192
+    _say("coin ties", len(planted), "planted, T", T)
+    ora = oracle.build_sketch(rp, c, w, seed=seed, j0=0, j1=T)
+    _assert_sketch_equal(skis.build_sketch(rp, c, w, T, seed), ora)
+    _assert_sketch_equal(skis.build_sketch(rp, c, w, T, seed, form=1), ora)
+    _assert_sketch_equal(skis.build_sketch(rp, c, w, T, seed, form=2, chunk_samples=1000), ora)
+    _assert_sketch_equal(skis.build_sketch(rp, c, w, T, seed, threads_per_block=256, slots_per_block=16,
+                                           visited_threshold=128, quads_per_lane=2), ora)
+    # in-degree 64 above big_row: every sample is handed on to the second tier
+    sk = skis.build_sketch(rp, c, w, T, seed, big_row=8)
+    assert sk.info().tier_samples[1] == T
+    _assert_sketch_equal(sk, ora)
 
 
 def test_staging_overflow_retry(skis):

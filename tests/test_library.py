@@ -53,7 +53,7 @@ def test_default_options_and_errors_without_gpu(libpath):
     from paper_1709_03565_amd import skis
     o = skis.default_options()
     assert o.slots_per_block == 4 and o.visited_threshold == 192 and o.threads_per_block == 64
-    assert o.pairs_per_lane == 2
+    assert o.quads_per_lane == 1
     assert o.build_inverse_index == 1
     L = skis.lib()
     h = ctypes.c_void_p()
@@ -89,5 +89,5 @@ def test_bench_kernel_names_match_the_library_table():
         th, sl, vi, pl, th2, sl2, vi2, hcap, icap, pl2 = map(int, r)
         assert (th, sl, vi, pl) == (th2, sl2, vi2, pl2)
         name = bench.tier0_kernel_name(dict(threads_per_block=th, slots_per_block=sl, visited_threshold=vi,
-                                            pairs_per_lane=pl))
+                                            quads_per_lane=pl))
         assert name == "k_sample<%d, %d, %d, %d, %d, %d, 0>" % (th, sl, vi, hcap, icap, pl)

@@ -125,3 +125,24 @@ def test_edge_coin_tie_of_high_halves_decided_by_low_half():
             if int(np.float64(w1) * 2.0 ** 64) >> 32 == hi + 1:
                 assert oracle.edge_coin(seed, j, e, float(w1))
     assert live_seen == {False, True}
+
+
+def test_planted_coin_ties_reach_the_oracle_both_ways():
+    # the tie graph used by the GPU parity test: the planted ties that lie after i* are
+    # decided by the low half (live iff below 2^31), and both outcomes occur
+    import coin_ties
+    seed = 21
+    row_ptr, col, w, planted = coin_ties.tie_star(seed)
+    assert len(planted) == 64
+    P, q = oracle.row_prefix(row_ptr, w)
+    T = max(j for j, _ in planted) + 1
+    sk = oracle.build_sketch(row_ptr, col, w, seed=seed, j0=0, j1=T)
+    outcomes = []
+    for j, e in planted:
+        istar = coin_ties.first_live_edge(seed, j, P[:row_ptr[1]], q[0])
+        members = set(sk.sample(j).tolist())
+        if e > istar:
+            lo = pyphilox.edge_coin_word(seed, j, e) & 0xFFFFFFFF
+            assert ((e + 1) in members) == (lo < (1 << 31))
+            outcomes.append(lo < (1 << 31))
+    assert len(outcomes) >= 10 and 0 < sum(outcomes) < len(outcomes)
