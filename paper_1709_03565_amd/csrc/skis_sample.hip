@@ -1130,8 +1130,10 @@ static const Variant kTierMidV[] = {
 // chip is filled with workgroups rather than slots; the HBM buffers of all slots are kept
 // within TIERG_BUDGET bytes.
 constexpr int TIERG_SLOTS = 1;
+constexpr int TIERG_BLOCK = 1024; // sixteen waves per sample: the largest samples bound the tier's time
+constexpr int TIERG_PER_CU = TIERG_BLOCK >= 512 ? 1 : 512 / TIERG_BLOCK;
 constexpr uint64_t TIERG_BUDGET = 8ull << 30;
-static SampleKernel const kTierGlobal = k_sample<256, TIERG_SLOTS, 1, 1, 1024, 2, 2>;
+static SampleKernel const kTierGlobal = k_sample<TIERG_BLOCK, TIERG_SLOTS, 1, 1, 4 * TIERG_BLOCK, 2, 2>;
 
 static const Variant &pick_variant(const Variant *vs, size_t nv, uint32_t threads, uint32_t slots, uint32_t visited,
                                    uint32_t qpl)
@@ -1240,7 +1242,7 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
     const uint64_t slot_bytes = (uint64_t)n * 4ull + words * 4ull;
     uint64_t nbg_mem = TIERG_BUDGET / (slot_bytes * TIERG_SLOTS);
     if (nbg_mem < 1) nbg_mem = 1;
-    const int nbg = (int)std::min<uint64_t>((uint64_t)2 * cus, nbg_mem);
+    const int nbg = (int)std::min<uint64_t>((uint64_t)TIERG_PER_CU * cus, nbg_mem);
     DevBuf<uint32_t> deferred2;
     deferred2.alloc(arena, count);
 
@@ -1364,7 +1366,7 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
                                u1.ptr, rerr.ptr);
             hipLaunchKernelGGL(v0.fn, dim3(nb0), dim3(v0.threads), 0, gg.cs, A0);
             hipLaunchKernelGGL(vm.fn, dim3(nbm), dim3(vm.threads), 0, gg.cs, A1);
-            hipLaunchKernelGGL(kTierGlobal, dim3((unsigned)nbg_g), dim3(256), 0, gg.cs, A2);
+            hipLaunchKernelGGL(kTierGlobal, dim3((unsigned)nbg_g), dim3(TIERG_BLOCK), 0, gg.cs, A2);
             hipLaunchKernelGGL(k_chain_end, dim3(1), dim3(64), 0, gg.cs, gc.ptr);
             const hipError_t launch_err = hipGetLastError();
             gg.capturing = false;
@@ -1531,7 +1533,7 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
             need(A.gbits, "gbits");
             need(A.glist, "glist");
             SKIS_HIP_TRY(hipEventRecord(ev[8], s));
-            hipLaunchKernelGGL(kTierGlobal, dim3(nbg), dim3(256), 0, s, A);
+            hipLaunchKernelGGL(kTierGlobal, dim3(nbg), dim3(TIERG_BLOCK), 0, s, A);
             SKIS_HIP_TRY(hipGetLastError());
             SKIS_HIP_TRY(hipEventRecord(ev[9], s));
             ran_global = true;
