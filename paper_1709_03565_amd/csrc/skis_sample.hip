@@ -1133,7 +1133,7 @@ constexpr int TIERG_SLOTS = 1;
 constexpr int TIERG_BLOCK = 1024; // sixteen waves per sample: the largest samples bound the tier's time
 constexpr int TIERG_PER_CU = TIERG_BLOCK >= 512 ? 1 : 512 / TIERG_BLOCK;
 constexpr uint64_t TIERG_BUDGET = 8ull << 30;
-static SampleKernel const kTierGlobal = k_sample<TIERG_BLOCK, TIERG_SLOTS, 1, 1, 4 * TIERG_BLOCK, 2, 2>;
+static SampleKernel const kTierGlobal = k_sample<TIERG_BLOCK, TIERG_SLOTS, 1, 1, 8 * TIERG_BLOCK, 2, 2>;
 
 static const Variant &pick_variant(const Variant *vs, size_t nv, uint32_t threads, uint32_t slots, uint32_t visited,
                                    uint32_t qpl)

@@ -21,9 +21,9 @@
 
 namespace skis {
 
-constexpr int RS_BLOCK = 256;
+constexpr int RS_BLOCK = 512;
 constexpr int RS_WAVES = RS_BLOCK / 64;
-constexpr int RS_TILE = 4096;                 // entries per tile
+constexpr int RS_TILE = 8192;                 // entries per tile (digit runs of ~32 entries)
 constexpr int RS_SPAN = RS_TILE / RS_WAVES;   // entries per wave, in rounds of 64
 
 // vals[p] = j for every entry p of sample j (one wave per sample)
@@ -44,7 +44,7 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_hist(uint64_t N, const int32_t 
 {
     __shared__ uint32_t h[256];
     for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        h[threadIdx.x] = 0u;
+        if (threadIdx.x < 256) h[threadIdx.x] = 0u;
         __syncthreads();
         const uint64_t e0 = tile * RS_TILE;
         constexpr int R = RS_TILE / RS_BLOCK;
@@ -58,7 +58,7 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_hist(uint64_t N, const int32_t 
         for (int r = 0; r < R; ++r)
             if (kr[r] >= 0) atomicAdd(&h[((uint32_t)kr[r] >> shift) & 255u], 1u);
         __syncthreads();
-        H[tile * 256 + threadIdx.x] = h[threadIdx.x]; // tile-major: one contiguous row per tile
+        if (threadIdx.x < 256) H[tile * 256 + threadIdx.x] = h[threadIdx.x]; // one contiguous row per tile
         __syncthreads();
     }
 }
@@ -111,7 +111,7 @@ __device__ __forceinline__ unsigned long long same_digit_mask(bool valid, uint32
     return m;
 }
 
-__global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(uint64_t N, const int32_t *__restrict__ kin,
+__global__ __launch_bounds__(RS_BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_rs_scatter(uint64_t N, const int32_t *__restrict__ kin,
                                                          const int32_t *__restrict__ vin, int32_t *__restrict__ kout,
                                                          int32_t *__restrict__ vout, int shift, int bits,
                                                          uint64_t ntiles, const int64_t *__restrict__ OFF,
@@ -139,16 +139,16 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(uint64_t N, const int32
             kr[r] = kin[e];
             vr[r] = vin[e];
         }
-        bnext = OFF[tile * 256 + threadIdx.x];
+        if (threadIdx.x < 256) bnext = OFF[tile * 256 + threadIdx.x];
     }
     for (; tile < ntiles; tile += gridDim.x) {
         const uint64_t t0 = tile * RS_TILE;
         const uint64_t s0 = t0 + (uint64_t)w * RS_SPAN;
         const int nvalid = (int)min((uint64_t)RS_TILE, N - t0);
-        base[threadIdx.x] = bnext;
+        if (threadIdx.x < 256) base[threadIdx.x] = bnext;
         for (int i = threadIdx.x; i < RS_WAVES * 256; i += RS_BLOCK) (&cnt[0][0])[i] = 0u;
         const uint64_t tn = tile + gridDim.x;
-        if (tn < ntiles) bnext = OFF[tn * 256 + threadIdx.x];
+        if (tn < ntiles && threadIdx.x < 256) bnext = OFF[tn * 256 + threadIdx.x];
         __syncthreads();
         // one ranking pass over the wave's span (in registers, in order): the rank of each
         // entry among the equal digits before it in the wave, while the leader of each digit
@@ -171,18 +171,21 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(uint64_t N, const int32
         __syncthreads();
         // digit d of the tile: its waves in order, after the digits below d
         {
-            const int d = threadIdx.x;
+            const int d = threadIdx.x; // digits 0..255; the other threads add nothing
             uint32_t acc = 0;
-            for (int k = 0; k < RS_WAVES; ++k) {
-                const uint32_t x = cnt[k][d];
-                cnt[k][d] = acc;
-                acc += x;
-            }
+            if (d < 256)
+                for (int k = 0; k < RS_WAVES; ++k) {
+                    const uint32_t x = cnt[k][d];
+                    cnt[k][d] = acc;
+                    acc += x;
+                }
             uint32_t tot;
             const uint32_t ex = block_excl_scan<RS_BLOCK, uint32_t>(acc, s_scan, &tot);
-            tstart[d] = ex;
-            if (d == 255) tstart[256] = tot;
-            for (int k = 0; k < RS_WAVES; ++k) cnt[k][d] += ex;
+            if (d < 256) {
+                tstart[d] = ex;
+                if (d == 255) tstart[256] = tot;
+                for (int k = 0; k < RS_WAVES; ++k) cnt[k][d] += ex;
+            }
         }
         __syncthreads();
         // the tile sorted by digit (stably) in LDS
