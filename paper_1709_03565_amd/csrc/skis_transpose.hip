@@ -21,9 +21,9 @@
 
 namespace skis {
 
-constexpr int RS_BLOCK = 512;
+constexpr int RS_BLOCK = 1024;
 constexpr int RS_WAVES = RS_BLOCK / 64;
-constexpr int RS_TILE = 8192;                 // entries per tile (digit runs of ~32 entries)
+constexpr int RS_TILE = 16384;                // entries per tile (digit runs of ~64 entries)
 constexpr int RS_SPAN = RS_TILE / RS_WAVES;   // entries per wave, in rounds of 64
 
 // vals[p] = j for every entry p of sample j (one wave per sample)
