@@ -30,7 +30,7 @@ constexpr int SORT_LDS_MAX = 8192; // sizes up to this are sorted in LDS by k_ga
 template <int S>
 constexpr int id_batch() { return S <= 16 ? 16 : 32; }
 
-// F_RESUME: admitted this pass from a handover (its nodes are put back in phase B1)
+// F_RESUME: admitted this pass from a handover (its nodes are put back in phase B1r)
 enum : int { F_ACTIVE = 1, F_ROOTPEND = 2, F_DEFER = 4, F_CLEAR = 8, F_RESUME = 16 };
 
 // ---------------------------------------------------------------------------------------
@@ -264,13 +264,13 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
     block_sync<BLOCK>();
 
     for (;;) {
-        // ---- A: wave 0, lane s owns slot s: finish, admit, hand out items -----------------
+        // ---- A1: wave 0, lane s owns slot s: finished and handed-on samples -----------------
         if (tid < 64) {
             const int s = tid;
             const bool own = s < S;
             int f = own ? s_flags[s] : 0;
             if constexpr (HO_IN) {
-                if (f & F_RESUME) { // refilled in the last pass's phase B1
+                if (f & F_RESUME) { // refilled in the last pass's phase B1r
                     f &= ~F_RESUME;
                     s_flags[s] = f;
                 }
@@ -335,7 +335,78 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                     s_flags[s] = f;
                 }
             }
-            // admission into slots that were already empty when this pass began
+        }
+        block_sync<BLOCK>();
+
+        // ---- B1: write out finished samples, clear their visited sets ----------------------
+        // (before admission, so that a slot finished in this pass takes its next sample now)
+        for (int s = 0; s < S; ++s) {
+            const int fs = s_flags[s];
+            if (fs != F_CLEAR) continue;
+            const int cnt = s_wo_cnt[s];
+            const unsigned long long off = s_wo_off[s];
+            if constexpr (!GLOBAL) {
+                if (cnt < 0) { // a sample handed on: its nodes to the handover, then a full clear
+                    if (HO_OUT && cnt == -2) {
+                        const int c = s_snap[s].count;
+                        int32_t *dst = a.ho_nodes_out + (size_t)off * (size_t)a.ho_stride;
+                        for (int t = tid; t < c; t += BLOCK) dst[t] = sh_hash[s * HCAP + sh_lidx[s * RCAP + t]];
+                        block_sync<BLOCK>();
+                    }
+                    for (int t = tid; t < HCAP; t += BLOCK) sh_hash[s * HCAP + t] = -1;
+                } else {
+                    // a finished sample has every key in its list: write the first cnt
+                    // (all, unless staging overflowed) and clear exactly the slots it used
+                    const int rc = s_count[s];
+                    for (int t = tid; t < rc; t += BLOCK) {
+                        const int h = sh_lidx[s * RCAP + t];
+                        if (t < cnt) a.staging[off + t] = sh_hash[s * HCAP + h];
+                        sh_hash[s * HCAP + h] = -1;
+                    }
+                }
+            } else {
+                int32_t *L = list_ptr(s);
+                uint32_t *B = bits_ptr(s);
+                if (cnt > SORT_LDS_MAX) {
+                    // a very large sample: write it sorted straight from the bitmap
+                    unsigned long long run = off;
+                    for (uint64_t w0 = 0; w0 < a.words; w0 += BLOCK) {
+                        const uint64_t wi = w0 + tid;
+                        const uint32_t word = wi < a.words ? B[wi] : 0u;
+                        int tot;
+                        const int ex = block_excl_scan<BLOCK, int>(__popc(word), s_scan, &tot);
+                        if (word) {
+                            uint32_t x = word;
+                            int k = 0;
+                            while (x) {
+                                const int b = __ffs(x) - 1;
+                                x &= x - 1u;
+                                a.staging[run + ex + k] = (int32_t)(wi * 32u + (uint64_t)b);
+                                ++k;
+                            }
+                            B[wi] = 0u;
+                        }
+                        run += (unsigned long long)tot;
+                    }
+                } else {
+                    for (int t = tid; t < cnt; t += BLOCK) a.staging[off + t] = L[t];
+                    const int rc = s_count[s];
+                    for (int t = tid; t < rc; t += BLOCK) B[L[t] >> 5] = 0u;
+                }
+            }
+        }
+        block_sync<BLOCK>();
+        if (tid < S && s_flags[tid] == F_CLEAR) {
+            s_flags[tid] = 0;
+            s_wo_cnt[tid] = 0;
+        }
+
+        // ---- A2: wave 0 again: admission, the handover snapshot, the pass's items -----------
+        if (tid < 64) {
+            const int s = tid;
+            const bool own = s < S;
+            int f = own ? s_flags[s] : 0;
+            // admission into every empty slot, those finished above included
             const bool want = own && f == 0;
             const unsigned long long wmask = __ballot(want);
             const int nwant = __popcll(wmask);
@@ -404,7 +475,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                             const Handover h = a.ho_state_in[myid];
                             const int cur = h.cursor_rp >> 1;
                             if (h.count >= 2 && h.count <= RCAP && cur >= 1 && cur <= h.count) {
-                                // its nodes are put back into the hash and list in phase B1
+                                // its nodes are put back into the hash and list in phase B1r
                                 resumed = true;
                                 s_count[s] = h.count;
                                 s_cursor[s] = cur;
@@ -477,10 +548,9 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                 }
             }
             const int total = (int)lane_value((uint32_t)tincl, S - 1);
-            // the workgroup stays while a slot is active or was just finished: a finished
-            // slot takes a new sample only in the next pass, and the ids already taken
-            // from the global counter must not be dropped
-            const unsigned long long amask = __ballot(own && ((f & F_ACTIVE) || f == F_CLEAR));
+            // the workgroup stays while a slot is active: admission has filled every empty
+            // slot while ids remain, so an idle workgroup holds no id taken from the counter
+            const unsigned long long amask = __ballot(own && (f & F_ACTIVE));
             if (s == 0) {
                 s_ibase[S] = total;
                 s_nitems = total;
@@ -489,82 +559,23 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
         }
         block_sync<BLOCK>();
 
-        // ---- B1: write out finished samples, clear their visited sets ----------------------
-        for (int s = 0; s < S; ++s) {
-            const int fs = s_flags[s];
-            if constexpr (HO_IN) {
-                if (fs & F_RESUME) { // resumed from a handover: its nodes back into the hash and list
-                    const int c = s_count[s];
-                    const int32_t *src = a.ho_nodes_in + (size_t)s_wo_off[s] * (size_t)a.ho_stride;
-                    int32_t *H = sh_hash + s * HCAP;
-                    for (int t = tid; t < c; t += BLOCK) {
-                        const int32_t u = src[t];
-                        uint32_t h = hash_slot(u);
-                        for (int k = 0; k < HCAP && atomicCAS(&H[h], -1, u) != -1; ++k)
-                            h = h + 1 == (uint32_t)HCAP ? 0u : h + 1;
-                        sh_lidx[s * RCAP + t] = (LIdx)h;
-                    }
+        // ---- B1r: resumed samples (admitted above) put their nodes back into hash and list ---
+        if constexpr (HO_IN) {
+            for (int s = 0; s < S; ++s) {
+                if (!(s_flags[s] & F_RESUME)) continue;
+                const int c = s_count[s];
+                const int32_t *src = a.ho_nodes_in + (size_t)s_wo_off[s] * (size_t)a.ho_stride;
+                int32_t *H = sh_hash + s * HCAP;
+                for (int t = tid; t < c; t += BLOCK) {
+                    const int32_t u = src[t];
+                    uint32_t h = hash_slot(u);
+                    for (int k = 0; k < HCAP && atomicCAS(&H[h], -1, u) != -1; ++k)
+                        h = h + 1 == (uint32_t)HCAP ? 0u : h + 1;
+                    sh_lidx[s * RCAP + t] = (LIdx)h;
                 }
             }
-            if (fs != F_CLEAR) continue;
-            const int cnt = s_wo_cnt[s];
-            const unsigned long long off = s_wo_off[s];
-            if constexpr (!GLOBAL) {
-                if (cnt < 0) { // a sample handed on: its nodes to the handover, then a full clear
-                    if (HO_OUT && cnt == -2) {
-                        const int c = s_snap[s].count;
-                        int32_t *dst = a.ho_nodes_out + (size_t)off * (size_t)a.ho_stride;
-                        for (int t = tid; t < c; t += BLOCK) dst[t] = sh_hash[s * HCAP + sh_lidx[s * RCAP + t]];
-                        block_sync<BLOCK>();
-                    }
-                    for (int t = tid; t < HCAP; t += BLOCK) sh_hash[s * HCAP + t] = -1;
-                } else {
-                    // a finished sample has every key in its list: write the first cnt
-                    // (all, unless staging overflowed) and clear exactly the slots it used
-                    const int rc = s_count[s];
-                    for (int t = tid; t < rc; t += BLOCK) {
-                        const int h = sh_lidx[s * RCAP + t];
-                        if (t < cnt) a.staging[off + t] = sh_hash[s * HCAP + h];
-                        sh_hash[s * HCAP + h] = -1;
-                    }
-                }
-            } else {
-                int32_t *L = list_ptr(s);
-                uint32_t *B = bits_ptr(s);
-                if (cnt > SORT_LDS_MAX) {
-                    // a very large sample: write it sorted straight from the bitmap
-                    unsigned long long run = off;
-                    for (uint64_t w0 = 0; w0 < a.words; w0 += BLOCK) {
-                        const uint64_t wi = w0 + tid;
-                        const uint32_t word = wi < a.words ? B[wi] : 0u;
-                        int tot;
-                        const int ex = block_excl_scan<BLOCK, int>(__popc(word), s_scan, &tot);
-                        if (word) {
-                            uint32_t x = word;
-                            int k = 0;
-                            while (x) {
-                                const int b = __ffs(x) - 1;
-                                x &= x - 1u;
-                                a.staging[run + ex + k] = (int32_t)(wi * 32u + (uint64_t)b);
-                                ++k;
-                            }
-                            B[wi] = 0u;
-                        }
-                        run += (unsigned long long)tot;
-                    }
-                } else {
-                    for (int t = tid; t < cnt; t += BLOCK) a.staging[off + t] = L[t];
-                    const int rc = s_count[s];
-                    for (int t = tid; t < rc; t += BLOCK) B[L[t] >> 5] = 0u;
-                }
-            }
+            block_sync<BLOCK>();
         }
-        block_sync<BLOCK>();
-        if (tid < S && s_flags[tid] == F_CLEAR) {
-            s_flags[tid] = 0;
-            s_wo_cnt[tid] = 0;
-        }
-
 
         // ---- B2: item edge ranges ----------------------------------------------------------
         const int nitems = s_nitems;
