@@ -102,6 +102,29 @@ __device__ __forceinline__ uint32_t wave_incl_scan_dpp(uint32_t x)
     return x;
 }
 
+// max(x, lane (l - d) of the same row of 16 lanes) in lane l (x where l mod 16 < d), d in
+// {1, 2, 4, 8}.
+template <int D>
+__device__ __forceinline__ uint32_t dpp_row_shr_max(uint32_t x)
+{
+    const uint32_t y = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x110 + D, 0xf, 0xf, true);
+    return x > y ? x : y;
+}
+
+// Inclusive prefix maximum over the 64 lanes (unsigned; every lane active): the same steps
+// as wave_incl_scan_dpp with max for +.
+__device__ __forceinline__ uint32_t wave_incl_max_dpp(uint32_t x)
+{
+    x = dpp_row_shr_max<1>(x);
+    x = dpp_row_shr_max<2>(x);
+    x = dpp_row_shr_max<4>(x);
+    x = dpp_row_shr_max<8>(x);
+    uint32_t y = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);
+    x = x > y ? x : y;
+    y = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);
+    return x > y ? x : y;
+}
+
 // Wave-level inclusive prefix sum over the 64 lanes (every lane active).
 template <typename T>
 __device__ __forceinline__ T wave_incl_scan(T v)

@@ -194,6 +194,14 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
     __shared__ unsigned long long s_cbase[2];
     __shared__ int s_ccur;
     __shared__ int32_t s_scan[BLOCK / 64 + 1];
+    // one-wave workgroups find an item's slot (one item per lane) and a lane's item in the
+    // first sweep (one quad per lane) by a prefix maximum over the lanes instead of a binary
+    // search: s_imap[i] = slot + 1 of the slot whose items start at i, s_qmap[p] = item + 1
+    // of the non-empty item whose quads start at p, 0 elsewhere
+    constexpr bool WMAP_SLOT = BLOCK == 64 && IPT == 1;
+    constexpr bool WMAP_QUAD = BLOCK == 64 && QPL == 1;
+    __shared__ uint32_t s_imap[WMAP_SLOT ? 64 : 1];
+    __shared__ uint32_t s_qmap[WMAP_QUAD ? 64 : 1];
 
     const int tid = threadIdx.x;
     const int32_t n = a.n;
@@ -534,6 +542,13 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
             int take = ICAP - base;
             take = take < 0 ? 0 : (take > pend ? pend : take);
             const int tincl = wave_incl_scan_n<S>(take);
+            if constexpr (WMAP_SLOT) {
+                s_imap[s] = 0u;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                if (own && take > 0) s_imap[tincl - take] = (uint32_t)s + 1u; // below nitems <= 64
+            }
             if (own) {
                 s_ibase[s] = tincl - take;
                 s_ifirst[s] = s_cursor[s];
@@ -583,6 +598,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
             // item it = k * BLOCK + tid (nitems <= ICAP <= IPT * BLOCK): first the node of each
             // item, then all row-bound loads unconditionally (node 0 stands in where there is
             // none), then the ranges
+            const int mapped_sl = WMAP_SLOT ? (int)wave_incl_max_dpp(s_imap[tid]) - 1 : 0;
             int xs[IPT], ss[IPT];
             bool rootit[IPT];
 #pragma unroll
@@ -592,12 +608,15 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                 xs[k] = 0;
                 rootit[k] = false;
                 if (it < nitems) {
-                    int lo = 0, hi = S;
-                    while (lo < hi) {
-                        const int mid = (lo + hi) >> 1;
-                        if (s_ibase[mid] <= it) lo = mid + 1; else hi = mid;
+                    int sl = mapped_sl;
+                    if constexpr (!WMAP_SLOT) {
+                        int lo = 0, hi = S;
+                        while (lo < hi) {
+                            const int mid = (lo + hi) >> 1;
+                            if (s_ibase[mid] <= it) lo = mid + 1; else hi = mid;
+                        }
+                        sl = lo - 1;
                     }
-                    const int sl = lo - 1;
                     const int t = it - s_ibase[sl];
                     ss[k] = sl;
                     if (s_irp[sl] && t == 0) {
@@ -648,13 +667,14 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
 
         // ---- B3: prefix sum of edge quads over the items -----------------------------------
         {
-            int loc[IPT];
+            int loc[IPT], cnt[IPT];
             int acc = 0;
 #pragma unroll
             for (int k = 0; k < IPT; ++k) {
                 const int idx = tid * IPT + k;
                 const int v = idx < nitems ? it_pb[idx] : 0;
                 loc[k] = acc;
+                cnt[k] = v;
                 acc += v;
             }
             int tot;
@@ -665,6 +685,18 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                 if (idx < nitems) it_pb[idx] = ex + loc[k];
             }
             if (tid == 0) it_pb[nitems] = tot;
+            if constexpr (WMAP_QUAD) {
+                s_qmap[tid] = 0u;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+                for (int k = 0; k < IPT; ++k) {
+                    const int idx = tid * IPT + k;
+                    const int st = ex + loc[k];
+                    if (idx < nitems && cnt[k] > 0 && st < 64) s_qmap[st] = (uint32_t)idx + 1u;
+                }
+            }
         }
         block_sync<BLOCK>();
 
@@ -677,11 +709,16 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
         // settled on the whole coin after the sweep.
         const int total = it_pb[nitems];
         const int qpl = total >= BLOCK * QPL ? QPL : (total + BLOCK - 1) / BLOCK;
+        const int first_item = WMAP_QUAD ? (int)wave_incl_max_dpp(s_qmap[tid]) - 1 : 0;
         for (int base = tid * qpl; base < total; base += BLOCK * qpl) {
             int lo = 0, hi = nitems - 1; // last item whose first quad index is <= base
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (it_pb[mid] <= base) lo = mid; else hi = mid - 1;
+            if (WMAP_QUAD && base < BLOCK) {
+                lo = first_item; // the first sweep: quad base = tid
+            } else {
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (it_pb[mid] <= base) lo = mid; else hi = mid - 1;
+                }
             }
             int pq[QPL], ps[QPL];
             uint32_t pin[QPL]; // edges of the quad inside the item's range, one bit each
