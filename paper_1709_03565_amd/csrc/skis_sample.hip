@@ -942,31 +942,31 @@ __global__ __launch_bounds__(64) void k_gather_sort(int cls, const unsigned long
     for (int k = 0; k < cls; ++k) base += counts[k];
     const unsigned long long cnt = counts[cls];
     const unsigned long long stride = (unsigned long long)gridDim.x * G;
-    uint32_t sz = 0, id = 0;
-    unsigned long long o = 0;
-    int64_t dp = 0;
+    // a two-stage pipeline over this segment's samples g0 + seg, g0 + stride + seg, ...: the
+    // list entry two samples ahead and the size, offset and position one sample ahead are
+    // loaded while the current one is sorted.  Loads are unconditional (an index past the
+    // class reads its last entry); a sample past the class has size 0 and writes nothing.
+    auto entry = [&](unsigned long long g) -> uint32_t { return lists[base + (g < cnt ? g : cnt - 1)]; };
     unsigned long long g0 = (unsigned long long)blockIdx.x * G;
-    if (g0 + seg < cnt) {
-        id = lists[base + g0 + seg];
-        sz = size[id];
-        o = off[id];
-        dp = sptr[id];
-    }
+    if (g0 >= cnt) return;
+    uint32_t id = entry(g0 + seg);
+    const uint32_t sz0 = size[id];
+    uint32_t sz = g0 + seg < cnt ? sz0 : 0u;
+    unsigned long long o = off[id];
+    int64_t dp = sptr[id];
+    uint32_t id1 = entry(g0 + stride + seg);
     for (; g0 < cnt; g0 += stride) {
-        uint32_t nsz = 0, nid = 0;
-        unsigned long long no = 0;
-        int64_t ndp = 0;
-        if (g0 + stride + seg < cnt) {
-            nid = lists[base + g0 + stride + seg];
-            nsz = size[nid];
-            no = off[nid];
-            ndp = sptr[nid];
-        }
+        const uint32_t id2 = entry(g0 + 2 * stride + seg);
+        const uint32_t sz1 = size[id1];
+        const uint32_t nsz = g0 + stride + seg < cnt ? sz1 : 0u;
+        const unsigned long long no = off[id1];
+        const int64_t ndp = sptr[id1];
         int32_t v[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int x = r * W + t;
-            v[r] = x < (int)sz ? staging[o + x] : INT32_MAX;
+            v[r] = staging[o + (x < (int)sz ? x : 0)];
+            if (x >= (int)sz) v[r] = INT32_MAX;
         }
 #pragma unroll
         for (int k = 2; k <= P; k <<= 1) {
@@ -1002,9 +1002,10 @@ __global__ __launch_bounds__(64) void k_gather_sort(int cls, const unsigned long
             }
         }
         sz = nsz;
-        id = nid;
+        id = id1;
         o = no;
         dp = ndp;
+        id1 = id2;
     }
 }
 
