@@ -1,6 +1,7 @@
 // skis_device.h -- device helpers shared by the libskis HIP sources (gfx950, wave64).
 #pragma once
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 namespace skis {
@@ -71,6 +72,20 @@ __device__ __forceinline__ uint64_t coin_with_low_half(uint32_t hi, uint32_t e, 
     uint64_t X, Y;
     philox2x64(e, (uint32_t)j, (uint32_t)(j >> 32), TAG_EDGE_LOW, seed_lo, seed_hi, X, Y);
     return ((uint64_t)hi << 32) | (uint32_t)X;
+}
+
+// Field at byte offset `off` of the kernel's argument segment, read with a scalar load at the
+// point of use.  The empty asm hides the segment's address from the optimiser, so the load is
+// not hoisted out of loops: an argument used once per pass or less then holds no scalar
+// register across a persistent kernel's loop (where it would be spilled to a VGPR lane and
+// reloaded with a VALU instruction at each use).
+template <typename T>
+__device__ __forceinline__ T karg_at(size_t off)
+{
+    const char __attribute__((address_space(4))) *base =
+        (const char __attribute__((address_space(4))) *)__builtin_amdgcn_kernarg_segment_ptr();
+    asm volatile("" : "+s"(base));
+    return *(const T __attribute__((address_space(4))) *)(base + off);
 }
 
 // Alias-table entry: bucket b yields b when r < thr, else alias.

@@ -16,6 +16,7 @@
 // discovered changes nothing, because the coins are keyed by (j, edge id) and the sample
 // is the set of nodes that reach the root through live edges.
 #include <algorithm>
+#include <type_traits>
 
 #include "skis_internal.h"
 #include "skis_plain.h"
@@ -153,6 +154,11 @@ struct SampleArgs {
 // flight, 1 needs fewer registers).
 // TIER: 0 the first LDS tier (hands its overflowing samples on with their state), 1 the
 // second LDS tier (resumes them), 2 the HBM tier (visited sets in global memory).
+// Arguments used once per pass or less are read from the argument segment where they are used
+// (see karg_at); the ones the edge sweep uses every pass stay in scalar registers.
+#define SKIS_KARG(f) karg_at<decltype(SampleArgs::f)>(offsetof(SampleArgs, f))
+static_assert(std::is_standard_layout<SampleArgs>::value, "argument offsets need a standard layout");
+
 template <int BLOCK, int S, int RCAP, int HCAP, int ICAP, int QPL, int TIER>
 __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
 {
@@ -206,8 +212,8 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
     const int tid = threadIdx.x;
     const int32_t n = a.n;
     // the work of this launch; in a captured chain the previous kernel has written it
-    const unsigned long long id_count = a.id_count_dev ? *a.id_count_dev : a.id_count;
-    const unsigned long long id_base = a.id_base_dev ? *a.id_base_dev : 0ull;
+    const unsigned long long id_count = SKIS_KARG(id_count_dev) ? *SKIS_KARG(id_count_dev) : SKIS_KARG(id_count);
+    const unsigned long long id_base = SKIS_KARG(id_base_dev) ? *SKIS_KARG(id_base_dev) : 0ull;
 
     auto list_ptr = [&](int s) -> int32_t * { return a.glist + ((size_t)blockIdx.x * S + s) * (size_t)n; };
     // node at position t of slot s's list
@@ -295,7 +301,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
             if (s == 0 && ftot) {
                 if (st_base + ftot > st_end) {
                     const unsigned long long want = ftot > STAGE_CHUNK ? ftot : STAGE_CHUNK;
-                    st_base = atomicAdd(a.stage_used, want);
+                    st_base = atomicAdd(SKIS_KARG(stage_used), want);
                     st_end = st_base + want;
                 }
                 fbase = st_base;
@@ -305,13 +311,13 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
             if (own && (f & F_ACTIVE)) {
                 if (!GLOBAL && (f & F_DEFER)) {
                     const uint32_t i = s_idx[s];
-                    const unsigned long long k = atomicAdd(a.n_deferred, 1ull);
-                    a.deferred[k] = i;
-                    a.out_size[i] = DEFERRED;
+                    const unsigned long long k = atomicAdd(SKIS_KARG(n_deferred), 1ull);
+                    SKIS_KARG(deferred)[k] = i;
+                    SKIS_KARG(out_size)[i] = DEFERRED;
                     s_wo_cnt[s] = -1; // nothing to write; its hash may hold keys past the list
                     if constexpr (HO_OUT) {
-                        if (a.ho_state_out && k < a.ho_cap_out) {
-                            a.ho_state_out[k] = s_snap[s]; // its nodes follow in phase B1
+                        if (SKIS_KARG(ho_state_out) && k < SKIS_KARG(ho_cap_out)) {
+                            SKIS_KARG(ho_state_out)[k] = s_snap[s]; // its nodes follow in phase B1
                             s_wo_cnt[s] = -2;
                             s_wo_off[s] = k;
                         }
@@ -322,22 +328,22 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                     const uint32_t i = s_idx[s];
                     const int cnt = s_count[s];
                     const unsigned long long off = fbase + (unsigned long long)(fincl - fcnt);
-                    a.out_size[i] = (uint32_t)cnt;
-                    a.out_off[i] = off;
-                    a.out_probed[i] = s_probed[s];
+                    SKIS_KARG(out_size)[i] = (uint32_t)cnt;
+                    SKIS_KARG(out_off)[i] = off;
+                    SKIS_KARG(out_probed)[i] = s_probed[s];
                     st_fin += 1;
                     st_ent += (unsigned long long)cnt;
                     st_prb += s_probed[s];
                     if (cnt > SMALL_SORT) {
-                        const unsigned long long k = atomicAdd(a.n_medium, 1ull);
-                        a.medium[k] = i;
+                        const unsigned long long k = atomicAdd(SKIS_KARG(n_medium), 1ull);
+                        SKIS_KARG(medium)[k] = i;
                     }
-                    if (off + (unsigned long long)cnt <= a.stage_cap) {
+                    if (off + (unsigned long long)cnt <= SKIS_KARG(stage_cap)) {
                         s_wo_cnt[s] = cnt;
                         s_wo_off[s] = off;
                     } else {
                         s_wo_cnt[s] = 0;
-                        atomicOr(a.overflow, 1);
+                        atomicOr(SKIS_KARG(overflow), 1);
                     }
                     f = F_CLEAR;
                     s_flags[s] = f;
@@ -357,7 +363,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                 if (cnt < 0) { // a sample handed on: its nodes to the handover, then a full clear
                     if (HO_OUT && cnt == -2) {
                         const int c = s_snap[s].count;
-                        int32_t *dst = a.ho_nodes_out + (size_t)off * (size_t)a.ho_stride;
+                        int32_t *dst = SKIS_KARG(ho_nodes_out) + (size_t)off * (size_t)SKIS_KARG(ho_stride);
                         for (int t = tid; t < c; t += BLOCK) dst[t] = sh_hash[s * HCAP + sh_lidx[s * RCAP + t]];
                         block_sync<BLOCK>();
                     }
@@ -368,7 +374,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                     const int rc = s_count[s];
                     for (int t = tid; t < rc; t += BLOCK) {
                         const int h = sh_lidx[s * RCAP + t];
-                        if (t < cnt) a.staging[off + t] = sh_hash[s * HCAP + h];
+                        if (t < cnt) SKIS_KARG(staging)[off + t] = sh_hash[s * HCAP + h];
                         sh_hash[s * HCAP + h] = -1;
                     }
                 }
@@ -389,7 +395,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                             while (x) {
                                 const int b = __ffs(x) - 1;
                                 x &= x - 1u;
-                                a.staging[run + ex + k] = (int32_t)(wi * 32u + (uint64_t)b);
+                                SKIS_KARG(staging)[run + ex + k] = (int32_t)(wi * 32u + (uint64_t)b);
                                 ++k;
                             }
                             B[wi] = 0u;
@@ -397,7 +403,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                         run += (unsigned long long)tot;
                     }
                 } else {
-                    for (int t = tid; t < cnt; t += BLOCK) a.staging[off + t] = L[t];
+                    for (int t = tid; t < cnt; t += BLOCK) SKIS_KARG(staging)[off + t] = L[t];
                     const int rc = s_count[s];
                     for (int t = tid; t < rc; t += BLOCK) B[L[t] >> 5] = 0u;
                 }
@@ -425,17 +431,17 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                 unsigned long long nb = 0;
                 int cur = s_ccur;
                 if (avail < (unsigned long long)nwant) {
-                    if (s == 0) nb = atomicAdd(a.next, (unsigned long long)IDBATCH);
+                    if (s == 0) nb = atomicAdd(SKIS_KARG(next), (unsigned long long)IDBATCH);
                     nb = first_lane_value64(nb);
                     // load the new batch's records into the other buffer (lane l: id nb + l)
                     cur ^= 1;
                     if (s < IDBATCH) {
                         const unsigned long long id = nb + (unsigned long long)s;
                         if (id < id_count) {
-                            const uint32_t i = a.id_list ? a.id_list[id] : (uint32_t)(id_base + id);
+                            const uint32_t i = SKIS_KARG(id_list) ? SKIS_KARG(id_list)[id] : (uint32_t)(id_base + id);
                             s_cidx[cur][s] = i;
-                            s_crec[cur][s] = a.rec[i];
-                            s_cu1[cur][s] = a.u1[i];
+                            s_crec[cur][s] = SKIS_KARG(rec)[i];
+                            s_cu1[cur][s] = SKIS_KARG(u1)[i];
                         }
                     }
                     if (s == 0) {
@@ -464,10 +470,10 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                     const uint32_t i = s_cidx[b][c];
                     const int4 r = s_crec[b][c];
                     const int32_t u = s_cu1[b][c];
-                    if (cd >= (unsigned long long)IDBATCH || i >= (uint32_t)(id_base + (a.id_list ? 0x7FFFFFFFull : id_count)) ||
+                    if (cd >= (unsigned long long)IDBATCH || i >= (uint32_t)(id_base + (SKIS_KARG(id_list) ? 0x7FFFFFFFull : id_count)) ||
                         (uint32_t)r.x >= (uint32_t)n || (uint32_t)u >= (uint32_t)n || r.y < r.z || r.w <= r.y ||
                         (int64_t)r.w > 4 * a.nquads) {
-                        atomicOr(a.overflow, 8); // bounds guard: the sample is left out
+                        atomicOr(SKIS_KARG(overflow), 8); // bounds guard: the sample is left out
                     } else {
                     s_idx[s] = i;
                     s_rib[s] = r.y + 1;
@@ -479,8 +485,8 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                     if (!GLOBAL && (uint32_t)(r.w - r.z) > a.big_row) nf |= F_DEFER;
                     bool resumed = false;
                     if constexpr (HO_IN) {
-                        if (a.ho_state_in && myid < a.ho_cap_in) {
-                            const Handover h = a.ho_state_in[myid];
+                        if (SKIS_KARG(ho_state_in) && myid < SKIS_KARG(ho_cap_in)) {
+                            const Handover h = SKIS_KARG(ho_state_in)[myid];
                             const int cur = h.cursor_rp >> 1;
                             if (h.count >= 2 && h.count <= RCAP && cur >= 1 && cur <= h.count) {
                                 // its nodes are put back into the hash and list in phase B1r
@@ -520,7 +526,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
             }
             // the state a handover would carry if this pass outgrows the slot
             if constexpr (HO_OUT) {
-                if (a.ho_state_out && own && (f & F_ACTIVE)) {
+                if (SKIS_KARG(ho_state_out) && own && (f & F_ACTIVE)) {
                     Handover h;
                     h.count = s_count[s];
                     h.cursor_rp = s_cursor[s] * 2 + ((f & F_ROOTPEND) ? 1 : 0);
@@ -579,7 +585,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
             for (int s = 0; s < S; ++s) {
                 if (!(s_flags[s] & F_RESUME)) continue;
                 const int c = s_count[s];
-                const int32_t *src = a.ho_nodes_in + (size_t)s_wo_off[s] * (size_t)a.ho_stride;
+                const int32_t *src = SKIS_KARG(ho_nodes_in) + (size_t)s_wo_off[s] * (size_t)SKIS_KARG(ho_stride);
                 int32_t *H = sh_hash + s * HCAP;
                 for (int t = tid; t < c; t += BLOCK) {
                     const int32_t u = src[t];
@@ -624,7 +630,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                     } else {
                         const int32_t x = list_node(sl, s_ifirst[sl] + t - s_irp[sl]);
                         if ((uint32_t)x >= (uint32_t)n) { // bounds guard: report, never index
-                            atomicOr(a.overflow, 4);
+                            atomicOr(SKIS_KARG(overflow), 4);
                             xs[k] = -1;
                         } else {
                             xs[k] = x;
@@ -734,7 +740,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                 if (!GLOBAL && (s_flags[sl] & F_DEFER)) continue;
                 const int q = (it_beg[lo] >> 2) + (idx - it_pb[lo]);
                 if (q < 0 || (int64_t)q >= a.nquads) { // bounds guard: report, never index
-                    atomicOr(a.overflow, 2);
+                    atomicOr(SKIS_KARG(overflow), 2);
                     continue;
                 }
                 ps[g] = sl;
@@ -787,7 +793,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                 const uint64_t j = a.j0 + s_idx[g1 ? ps[QPL - 1] : ps[0]];
                 // the coin's high half equals the threshold's
                 const uint32_t hw = (c & 1) ? q.w : q.y;
-                if (coin_live(a.wbits[e], coin_with_low_half(hw, (uint32_t)e, j, a.seed_lo, a.seed_hi)))
+                if (coin_live(SKIS_KARG(wbits)[e], coin_with_low_half(hw, (uint32_t)e, j, a.seed_lo, a.seed_hi)))
                     live |= 1u << c;
             }
             while (live) {
@@ -808,19 +814,21 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
         block_sync<BLOCK>();
         if (!s_alive) break;
     }
-    if (tid < 64 && a.tier_stats) {
+    if (tid < 64 && SKIS_KARG(tier_stats)) {
         st_fin = wave_sum(st_fin);
         st_ent = wave_sum(st_ent);
         st_prb = wave_sum(st_prb);
         if (tid == 0 && st_fin) {
-            atomicAdd(a.tier_stats + 0, st_fin);
-            atomicAdd(a.tier_stats + 1, st_ent);
-            atomicAdd(a.tier_stats + 2, st_prb);
+            atomicAdd(SKIS_KARG(tier_stats) + 0, st_fin);
+            atomicAdd(SKIS_KARG(tier_stats) + 1, st_ent);
+            atomicAdd(SKIS_KARG(tier_stats) + 2, st_prb);
         }
     }
 }
 
 // ---------------------------------------------------------------------------------------
+#undef SKIS_KARG
+
 // Compaction: sort each sample and write it at sample_ptr[i].
 // ---------------------------------------------------------------------------------------
 template <int NT>
