@@ -1180,7 +1180,7 @@ static const Variant kTier0[] = {
 };
 // second tier: samples that outgrew the first, slots of 1024 nodes in LDS
 static const Variant kTierMidV[] = {
-    {64, 2, 1024, 1, k_sample<64, 2, 1024, 1368, 128, 1, 1>},
+    {64, 1, 1024, 1, k_sample<64, 1, 1024, 1368, 64, 1, 1>},
     {256, 8, 1024, 2, k_sample<256, 8, 1024, 1368, 1024, 2, 1>},
 };
 // One sample per workgroup: the samples that reach this tier are few and large, so the
@@ -1569,6 +1569,23 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
         if (ran_mid && hc.n_deferred > 0) {
             // tier 2: what is left, a bitmap and a node list of n entries per slot in HBM
             const uint64_t nd = hc.n_deferred;
+            if (nd > 1) {
+                // a fixed pseudo-random order (Fisher-Yates, a 64-bit LCG): the largest samples
+                // bound this tier's time.  In tier 1's hand-on order they can bunch up at the
+                // end and run alone; all of them first (by pending nodes) ran 2.5x slower, as
+                // their HBM visited sets then compete for the caches.
+                std::vector<uint32_t> keys(nd);
+                SKIS_HIP_TRY(hipMemcpyAsync(keys.data(), deferred2.ptr, sizeof(uint32_t) * nd, hipMemcpyDeviceToHost, s));
+                SKIS_HIP_TRY(hipStreamSynchronize(s));
+                uint64_t x = 0x9E3779B97F4A7C15ull;
+                for (uint64_t k = nd - 1; k > 0; --k) {
+                    x = x * 6364136223846793005ull + 1442695040888963407ull;
+                    const uint64_t r = (uint64_t)(((unsigned __int128)(x >> 11) * (k + 1)) >> 53);
+                    std::swap(keys[k], keys[r]);
+                }
+                SKIS_HIP_TRY(hipMemcpyAsync(deferred2.ptr, keys.data(), sizeof(uint32_t) * nd, hipMemcpyHostToDevice, s));
+                SKIS_HIP_TRY(hipStreamSynchronize(s));
+            }
             sk.deferred_global = nd;
             const uint64_t slots = (uint64_t)nbg * TIERG_SLOTS;
             DevBuf<uint32_t> gbits;
