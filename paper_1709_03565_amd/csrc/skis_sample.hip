@@ -155,7 +155,8 @@ struct SampleArgs {
 // TIER: 0 the first LDS tier (hands its overflowing samples on with their state), 1 the
 // second LDS tier (resumes them), 2 the HBM tier (visited sets in global memory).
 // Arguments used once per pass or less are read from the argument segment where they are used
-// (see karg_at); the ones the edge sweep uses every pass stay in scalar registers.
+// (see karg_at); the ones the edge sweep uses every pass stay in scalar registers.  SampleArgs is
+// k_sample's only parameter, so it starts the segment and a field's offset is its offsetof.
 #define SKIS_KARG(f) karg_at<decltype(SampleArgs::f)>(offsetof(SampleArgs, f))
 static_assert(std::is_standard_layout<SampleArgs>::value, "argument offsets need a standard layout");
 
