@@ -85,7 +85,7 @@ __global__ __launch_bounds__(EST_BLOCK) void k_estimate(const int64_t *__restric
 
     double sq = 0.0, cq = 0.0;
     unsigned long long local = 0;
-    int nu = 0;
+    int nu = 0, maxnu = 0; // maxnu: threads at or past it never took a member (their sums are +0)
     int64_t E = 0;
     unsigned parked = EST_NSPLIT; // < EST_NSPLIT: the walk was handed to k_est_split_walk
     for (int64_t c0 = a; c0 < b; c0 += EST_MAX_SET) {
@@ -136,6 +136,7 @@ __global__ __launch_bounds__(EST_BLOCK) void k_estimate(const int64_t *__restric
         __syncthreads();
 
         for (int t = tid; t < nu; t += EST_BLOCK) neumaier_add(sq, cq, qv[buf[t]]);
+        maxnu = nu > maxnu ? nu : maxnu;
         int64_t dl[IPT];
         int64_t acc = 0;
 #pragma unroll
@@ -202,7 +203,9 @@ __global__ __launch_bounds__(EST_BLOCK) void k_estimate(const int64_t *__restric
         unsigned long long c = 0;
         for (int w = 0; w < EST_BLOCK / 64; ++w) c += s_cov[w];
         double s = 0.0, cc = 0.0;
-        for (int t = 0; t < EST_BLOCK; ++t) {
+        // adding the +0 partials of the threads past maxnu would change neither s nor cc
+        const int tq = maxnu < EST_BLOCK ? maxnu : EST_BLOCK;
+        for (int t = 0; t < tq; ++t) {
             neumaier_add(s, cc, ps[t]);
             neumaier_add(s, cc, pc[t]);
         }
