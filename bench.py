@@ -15,6 +15,7 @@ import math
 import os
 import sys
 import time
+import types
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -249,15 +250,26 @@ def main():
 
     wl = inputs.WORKLOADS[args.workload]
     T = args.samples or wl["T"]
+    build_only = bool(wl.get("build_only"))
     log("workload", args.workload, wl, "T", T)
     t = time.perf_counter()
-    g = inputs.workload_graph(args.workload)
-    log("graph ready in %.1fs: n=%d m=%d" % (time.perf_counter() - t, g.n, g.m))
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    rp = torch.from_numpy(g.row_ptr).to(dev)
-    col = torch.from_numpy(g.col).to(dev)
-    w = torch.from_numpy(g.w).to(dev)
+    if wl.get("device_graph"):
+        # drawn on the GPU: a host build of this size takes minutes
+        rp, col, w = inputs.chung_lu_graph_device(wl["n"], wl["m"], wl["beta"], wl["seed"], wl["model"], dev)
+        torch.cuda.synchronize()
+        g = types.SimpleNamespace(n=wl["n"], m=wl["m"])
+    else:
+        g = inputs.workload_graph(args.workload)
+        rp = torch.from_numpy(g.row_ptr).to(dev)
+        col = torch.from_numpy(g.col).to(dev)
+        w = torch.from_numpy(g.w).to(dev)
+    log("graph ready in %.1fs: n=%d m=%d" % (time.perf_counter() - t, g.n, g.m))
+    if build_only:
+        # the build alone is the step: no autotuning sweep, no plain or captured comparison
+        # builds and no oracle baseline at this size
+        args.no_autotune = args.no_plain_compare = args.no_cpu_baseline = True
     sets = inputs.random_sets(g.n, args.queries, 50, seed=7)
     set_ptr_np, set_nodes_np = inputs.sets_to_csr(sets)
     set_ptr = torch.from_numpy(set_ptr_np).to(dev)
@@ -285,6 +297,11 @@ def main():
     torch.cuda.synchronize()
 
     def step():
+        if build_only:
+            sk = skis.build_sketch(rp, col, w, T, inputs.SAMPLE_SEED, build_inverse_index=0, **opts)
+            inf = sk.info()
+            sk.free()
+            return inf, None, None
         sk = skis.build_sketch(rp, col, w, T, inputs.SAMPLE_SEED, **opts)
         sk.estimate(set_ptr, set_nodes)
         seeds, marg, cov, est = sk.greedy(args.k)
@@ -332,9 +349,10 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": "%s: directed Chung-Lu n=%d m=%d beta=%g, %s weights fp32, T=%d IIS samples, Philox seed %d; "
-                        "step = build_sketch + inverse index + %d estimates (|S| 1-50) + greedy k=%d"
-                        % (args.workload, g.n, g.m, wl["beta"], wl["model"].upper(), T, inputs.SAMPLE_SEED,
-                           args.queries, args.k),
+                        % (args.workload, g.n, g.m, wl["beta"], wl["model"].upper(), T, inputs.SAMPLE_SEED)
+                        + ("graph drawn on the GPU; step = build_sketch without the inverse index" if build_only else
+                           "step = build_sketch + inverse index + %d estimates (|S| 1-50) + greedy k=%d"
+                           % (args.queries, args.k)),
             "T": T, "n": g.n, "m": g.m,
         },
         "edges_probed_per_s": inf.probed_total * args.steps / elapsed,

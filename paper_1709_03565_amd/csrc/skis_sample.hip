@@ -16,6 +16,7 @@
 // discovered changes nothing, because the coins are keyed by (j, edge id) and the sample
 // is the set of nodes that reach the root through live edges.
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 
 #include "skis_internal.h"
@@ -1190,7 +1191,7 @@ static const Variant kTierMidV[] = {
 constexpr int TIERG_SLOTS = 1;
 constexpr int TIERG_BLOCK = 1024; // sixteen waves per sample: the largest samples bound the tier's time
 constexpr int TIERG_PER_CU = TIERG_BLOCK >= 512 ? 1 : 512 / TIERG_BLOCK;
-constexpr uint64_t TIERG_BUDGET = 8ull << 30;
+constexpr uint64_t TIERG_BUDGET = 32ull << 30;
 static SampleKernel const kTierGlobal = k_sample<TIERG_BLOCK, TIERG_SLOTS, 1, 1, 8 * TIERG_BLOCK, 2, 2>;
 
 static const Variant &pick_variant(const Variant *vs, size_t nv, uint32_t threads, uint32_t slots, uint32_t visited,
@@ -1210,6 +1211,25 @@ static int occupancy_blocks(SampleKernel fn, int block)
         nb < 1)
         nb = 1;
     return nb;
+}
+
+// Entries per sample of the last build on a graph of the same (n, m), per process: sizes the
+// next build's staging, so that a graph whose samples outgrow the default guess (48 entries
+// a sample) pays the staging-overflow retry (a second sampling pass) only once.
+static std::mutex g_hint_mu;
+static std::map<std::pair<int32_t, int64_t>, double> g_entries_hint;
+
+static double entries_per_sample_hint(int32_t n, int64_t m)
+{
+    std::lock_guard<std::mutex> lk(g_hint_mu);
+    const auto it = g_entries_hint.find({n, m});
+    return it == g_entries_hint.end() ? 48.0 : std::max(48.0, it->second * 1.05);
+}
+
+static void set_entries_per_sample_hint(int32_t n, int64_t m, double v)
+{
+    std::lock_guard<std::mutex> lk(g_hint_mu);
+    g_entries_hint[{n, m}] = v;
 }
 
 void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, uint64_t T, uint64_t seed,
@@ -1294,7 +1314,8 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
     auto staging_bound = [&](uint64_t entries, uint64_t launches) {
         return entries + entries / 7 + 1 + launches * slack + (1ull << 20);
     };
-    uint64_t cap = cfg.staging_entries ? cfg.staging_entries : staging_bound((uint64_t)count * 48ull, 1);
+    const double per_sample = entries_per_sample_hint(n, m);
+    uint64_t cap = cfg.staging_entries ? cfg.staging_entries : staging_bound((uint64_t)((double)count * per_sample), 1);
     const uint64_t words = ((uint64_t)n + 31) / 32;
     // global tier: every slot holds a bitmap of n bits and a node list of n entries
     const uint64_t slot_bytes = (uint64_t)n * 4ull + words * 4ull;
@@ -1322,7 +1343,7 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
     auto sample_chain_graph = [&]() {
         const uint64_t chunk = std::min<uint64_t>(count, cfg.chunk ? cfg.chunk : (1ull << 22));
         const uint64_t replays = (count + chunk - 1) / chunk;
-        if (!cfg.staging_entries) cap = staging_bound((uint64_t)count * 48ull, replays);
+        if (!cfg.staging_entries) cap = staging_bound((uint64_t)((double)count * per_sample), replays);
         DevBuf<ChainCtl> gc;
         gc.alloc(arena, 1);
         const uint64_t nbg_g = (uint64_t)nbg;
@@ -1649,6 +1670,7 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
     SKIS_HIP_TRY(hipMemcpyAsync(&total, sk.sample_ptr.ptr + count, sizeof(total), hipMemcpyDeviceToHost, s));
     SKIS_HIP_TRY(hipStreamSynchronize(s));
     sk.entries = (uint64_t)total;
+    if (count && !cfg.staging_entries) set_entries_per_sample_hint(n, m, (double)total / (double)count);
     sk.nodes.alloc(arena, (size_t)total);
     if (cfg.owners) sk.owner.alloc(arena, (size_t)total);
     else sk.owner.reset();

@@ -147,6 +147,80 @@ def chung_lu_graph(n: int, m: int, beta: float, seed: int, model: str, cache: bo
     return Graph(n, m, row_ptr, col, w, name)
 
 
+def chung_lu_graph_device(n: int, m: int, beta: float, seed: int, model: str, device="cuda"):
+    """The Chung-Lu recipe above drawn on the GPU with torch, for graphs whose host build
+    would take minutes (1.4B edges): the same expected-degree weights and node permutations,
+    balls as i.i.d. (source, target) draws by inverse CDF over the cumulative weights, self-
+    loops and repeated pairs rejected, a uniform random subset kept when a round yields more
+    than are missing, rounds until exactly m distinct edges exist, rows by (target, source).
+    torch's generators (seeded with `seed`) replace PCG64, so the graph is another draw of the
+    same recipe, not the host function's graph.  The weights, permutations and cumulative sums
+    are formed on the CPU: a floating-point scan on the GPU may add its partial sums in an
+    order that depends on timing, and one rounding changes which node some draws land on.
+    Returns (row_ptr int32[n+1], col int32[m], w fp32[m]) as device tensors."""
+    import torch
+    if m > n * (n - 1):
+        raise ValueError("m exceeds the number of possible directed edges")
+    dev = torch.device(device)
+    gh = torch.Generator(device="cpu")
+    gh.manual_seed(seed)
+    x = torch.arange(1, n + 1, dtype=torch.float64) ** (-1.0 / (beta - 1.0))
+    x *= m / x.sum()
+    cdf = []
+    for _ in range(2): # out-weights, then in-weights, each through its own permutation
+        wv = torch.empty(n, dtype=torch.float64)
+        wv[torch.randperm(n, generator=gh)] = x
+        c = torch.cumsum(wv, 0)
+        cdf.append((c / c[-1]).to(dev))
+    del x, wv, c
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    keys = torch.zeros(0, dtype=torch.int64, device=dev)
+    chunk = 1 << 27
+    while keys.numel() < m:
+        need = m - keys.numel()
+        B = int(need * 1.05) + 4096
+        parts = []
+        for b0 in range(0, B, chunk):
+            b = min(chunk, B - b0)
+            src = torch.searchsorted(cdf[0], torch.rand(b, dtype=torch.float64, generator=g, device=dev), right=True)
+            dst = torch.searchsorted(cdf[1], torch.rand(b, dtype=torch.float64, generator=g, device=dev), right=True)
+            src.clamp_(max=n - 1)
+            dst.clamp_(max=n - 1)
+            ok = src != dst
+            parts.append(torch.unique(src[ok] * n + dst[ok]))
+            del src, dst, ok
+        cand = torch.unique(torch.cat(parts))
+        del parts
+        if keys.numel():
+            cand = cand[~torch.isin(cand, keys)]
+        if cand.numel() > need:
+            pick = torch.randperm(cand.numel(), generator=g, device=dev)[:need]
+            cand = torch.sort(cand[pick]).values
+        keys = torch.sort(torch.cat([keys, cand])).values
+        del cand
+    src = keys // n
+    dst = keys % n
+    del keys
+    order = torch.sort(dst * n + src).values
+    del src, dst
+    col = (order % n).to(torch.int32)
+    dsts = order // n
+    del order
+    deg = torch.bincount(dsts, minlength=n)
+    row_ptr = torch.zeros(n + 1, dtype=torch.int64, device=dev)
+    torch.cumsum(deg, 0, out=row_ptr[1:])
+    if model == "wc":
+        w = (1.0 / deg.clamp(min=1).to(torch.float64)).to(torch.float32)[dsts]
+    elif model == "tri":
+        vals = torch.tensor(TRI_VALUES, device=dev)
+        w = vals[torch.randint(0, 3, (m,), generator=g, device=dev)]
+    else:
+        raise ValueError("unknown weight model %r" % model)
+    del dsts, deg
+    return row_ptr.to(torch.int32), col, w
+
+
 def random_sets(n: int, count: int, max_size: int, seed: int):
     """`count` seed sets, sizes uniform in {1..max_size}, members uniform without
     replacement."""
@@ -208,7 +282,9 @@ WORKLOADS = {
     "cl15k_wc": dict(n=15_000, m=60_000, beta=2.3, seed=101, model="wc", T=200_000),
     "cl1m_wc": dict(n=1_000_000, m=20_000_000, beta=2.1, seed=102, model="wc", T=1 << 24),
     "cl4m_tri": dict(n=4_000_000, m=70_000_000, beta=2.0, seed=103, model="tri", T=1 << 25),
-    "cl40m_wc": dict(n=40_000_000, m=1_400_000_000, beta=2.2, seed=104, model="wc", T=1 << 26),
+    # built on the GPU (chung_lu_graph_device); the step there is the build alone
+    "cl40m_wc": dict(n=40_000_000, m=1_400_000_000, beta=2.2, seed=104, model="wc", T=1 << 26,
+                     device_graph=True, build_only=True),
 }
 SAMPLE_SEED = 1
 

@@ -1,0 +1,48 @@
+"""Parity at the 1.4B-edge shape (cl40m_wc: 40M nodes, 1.4B edges, T = 2^26): three ranges of
+1024 sample ids of the GPU sketch against the CPU oracle on the same graph, bit for bit.
+Opt-in (SKIS_FULL_SCALE=1): the oracle's preprocessing of 1.4B edges takes minutes of host
+time, too long for the default GPU run."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1709_03565_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[full-scale]", *a, flush=True)
+
+
+@pytest.mark.skipif(os.environ.get("SKIS_FULL_SCALE") != "1",
+                    reason="1.4B-edge parity takes minutes of host work; run with SKIS_FULL_SCALE=1")
+def test_cl40m_sample_ranges_match_oracle():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1709_03565_amd import skis
+    wl = inputs.WORKLOADS["cl40m_wc"]
+    T = wl["T"]
+    _say("graph n=%d m=%d" % (wl["n"], wl["m"]))
+    rp, col, w = inputs.chung_lu_graph_device(wl["n"], wl["m"], wl["beta"], wl["seed"], wl["model"], "cuda")
+    # the generator is reproducible: a second draw gives the same graph
+    rp2, col2, w2 = inputs.chung_lu_graph_device(wl["n"], wl["m"], wl["beta"], wl["seed"], wl["model"], "cuda")
+    assert torch.equal(rp, rp2) and torch.equal(col, col2) and torch.equal(w, w2)
+    del rp2, col2, w2
+    _say("build T=%d" % T)
+    sk = skis.build_sketch(rp, col, w, T, inputs.SAMPLE_SEED, build_inverse_index=0)
+    sp, nodes, roots, probed = sk.export()
+    _say("entries", int(sp[-1]))
+    hrp, hcol, hw = rp.cpu().numpy(), col.cpu().numpy(), w.cpu().numpy()
+    for j0 in (0, T // 2 + 12345, T - 1024):
+        j1 = j0 + 1024
+        _say("oracle ids", j0, j1)
+        ora = oracle.build_sketch(hrp, hcol, hw, seed=inputs.SAMPLE_SEED, j0=j0, j1=j1, nthreads=16)
+        a, b = int(sp[j0]), int(sp[j1])
+        assert np.array_equal((sp[j0:j1 + 1] - a).cpu().numpy(), ora.sample_ptr)
+        assert np.array_equal(nodes[a:b].cpu().numpy(), ora.nodes)
+        assert np.array_equal(roots[j0:j1].cpu().numpy(), ora.roots)
+        assert np.array_equal(probed[j0:j1].cpu().numpy().astype(np.uint64), ora.probed)

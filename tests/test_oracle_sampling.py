@@ -298,3 +298,22 @@ def test_degenerate_gamma_zero():
     _, q = oracle.row_prefix(row_ptr, w)
     cov, est = oracle.estimate(3, sk.sample_ptr, sk.nodes, q, sk.Gamma, sets=[[0, 1], [2]])
     assert list(cov) == [0, 0] and list(est) == [2.0, 1.0]
+
+
+def test_device_chung_lu_recipe_on_cpu():
+    # the GPU generator of the 1.4B-edge workload, run on the CPU at a small size: exactly m
+    # distinct non-loop edges, rows by (target, source), WC weights 1/d_in in fp32
+    import torch
+    rp, col, w = inputs.chung_lu_graph_device(3000, 30000, 2.2, 9, "wc", device="cpu")
+    rp, col, w = rp.numpy(), col.numpy(), w.numpy()
+    assert rp[0] == 0 and rp[-1] == 30000 and len(col) == 30000
+    dst = np.repeat(np.arange(3000), np.diff(rp))
+    keys = dst.astype(np.int64) * 3000 + col
+    assert np.all(np.diff(keys) > 0)
+    assert np.all(col != dst) and np.all((col >= 0) & (col < 3000))
+    deg = np.diff(rp)
+    assert np.array_equal(w, (1.0 / np.repeat(np.maximum(deg, 1), deg).astype(np.float64)).astype(np.float32))
+    # heavy-tailed in-degrees, as the recipe's power-law weights give
+    assert deg.max() > 20 * deg.mean()
+    _, _, w2 = inputs.chung_lu_graph_device(3000, 30000, 2.2, 9, "tri", device="cpu")
+    assert set(np.unique(w2.numpy()).tolist()) <= set(inputs.TRI_VALUES.tolist())
