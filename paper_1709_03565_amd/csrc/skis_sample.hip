@@ -136,15 +136,18 @@ struct SampleArgs {
     int32_t *glist;             // global tier: [slots][n]
     uint64_t words;
     // handover to the next tier: sample k of `deferred` (k < ho_cap_out) leaves its state in
-    // ho_state_out[k] and its nodes in ho_nodes_out[k * ho_stride ...]
+    // ho_state_out[k] and its nodes in ho_nodes_out[k * ho_stride_out ...]
     Handover *ho_state_out;
     int32_t *ho_nodes_out;
     uint64_t ho_cap_out;
-    // handover from the previous tier: id k of id_list (k < ho_cap_in) resumes from it
+    int32_t ho_stride_out;
+    // handover from the previous tier: the id at position p of id_list resumes from record
+    // ho_slot_in[p] (p itself when ho_slot_in is null) if that is below ho_cap_in
     const Handover *ho_state_in;
     const int32_t *ho_nodes_in;
+    const uint32_t *ho_slot_in;
     uint64_t ho_cap_in;
-    int32_t ho_stride;
+    int32_t ho_stride_in;
 };
 
 // RCAP: nodes a slot holds before its sample moves on (the visited threshold); HCAP: size
@@ -165,7 +168,7 @@ template <int BLOCK, int S, int RCAP, int HCAP, int ICAP, int QPL, int TIER>
 __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
 {
     constexpr bool GLOBAL = TIER == 2;
-    constexpr bool HO_OUT = TIER == 0, HO_IN = TIER == 1;
+    constexpr bool HO_OUT = TIER <= 1, HO_IN = TIER >= 1;
     constexpr int IDBATCH = id_batch<S>();
     static_assert(GLOBAL || HCAP > RCAP, "the hash must be larger than the node list");
     static_assert(GLOBAL || HCAP <= 65535, "list entries are 8- or 16-bit hash slot indexes");
@@ -365,7 +368,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                 if (cnt < 0) { // a sample handed on: its nodes to the handover, then a full clear
                     if (HO_OUT && cnt == -2) {
                         const int c = s_snap[s].count;
-                        int32_t *dst = SKIS_KARG(ho_nodes_out) + (size_t)off * (size_t)SKIS_KARG(ho_stride);
+                        int32_t *dst = SKIS_KARG(ho_nodes_out) + (size_t)off * (size_t)SKIS_KARG(ho_stride_out);
                         for (int t = tid; t < c; t += BLOCK) dst[t] = sh_hash[s * HCAP + sh_lidx[s * RCAP + t]];
                         block_sync<BLOCK>();
                     }
@@ -487,18 +490,21 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                     if (!GLOBAL && (uint32_t)(r.w - r.z) > a.big_row) nf |= F_DEFER;
                     bool resumed = false;
                     if constexpr (HO_IN) {
-                        if (SKIS_KARG(ho_state_in) && myid < SKIS_KARG(ho_cap_in)) {
-                            const Handover h = SKIS_KARG(ho_state_in)[myid];
+                        const uint32_t *hs = SKIS_KARG(ho_slot_in);
+                        const unsigned long long rec_k = hs ? (unsigned long long)hs[myid] : myid;
+                        if (SKIS_KARG(ho_state_in) && rec_k < SKIS_KARG(ho_cap_in)) {
+                            const Handover h = SKIS_KARG(ho_state_in)[rec_k];
                             const int cur = h.cursor_rp >> 1;
-                            if (h.count >= 2 && h.count <= RCAP && cur >= 1 && cur <= h.count) {
-                                // its nodes are put back into the hash and list in phase B1r
+                            const int cap = GLOBAL ? n : RCAP; // the HBM tier's list holds n nodes
+                            if (h.count >= 2 && h.count <= cap && cur >= 1 && cur <= h.count) {
+                                // its nodes are put back into the visited set and list in phase B1r
                                 resumed = true;
                                 s_count[s] = h.count;
                                 s_cursor[s] = cur;
                                 s_probed[s] = h.probed;
                                 nf = F_ACTIVE | F_RESUME | ((h.cursor_rp & 1) ? F_ROOTPEND : 0);
-                                if ((uint32_t)(r.w - r.z) > a.big_row) nf |= F_DEFER;
-                                s_wo_off[s] = myid;
+                                if (!GLOBAL && (uint32_t)(r.w - r.z) > a.big_row) nf |= F_DEFER;
+                                s_wo_off[s] = rec_k;
                             }
                         }
                     }
@@ -587,14 +593,24 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
             for (int s = 0; s < S; ++s) {
                 if (!(s_flags[s] & F_RESUME)) continue;
                 const int c = s_count[s];
-                const int32_t *src = SKIS_KARG(ho_nodes_in) + (size_t)s_wo_off[s] * (size_t)SKIS_KARG(ho_stride);
-                int32_t *H = sh_hash + s * HCAP;
-                for (int t = tid; t < c; t += BLOCK) {
-                    const int32_t u = src[t];
-                    uint32_t h = hash_slot(u);
-                    for (int k = 0; k < HCAP && atomicCAS(&H[h], -1, u) != -1; ++k)
-                        h = h + 1 == (uint32_t)HCAP ? 0u : h + 1;
-                    sh_lidx[s * RCAP + t] = (LIdx)h;
+                const int32_t *src = SKIS_KARG(ho_nodes_in) + (size_t)s_wo_off[s] * (size_t)SKIS_KARG(ho_stride_in);
+                if constexpr (GLOBAL) {
+                    int32_t *L = list_ptr(s);
+                    uint32_t *B = bits_ptr(s);
+                    for (int t = tid; t < c; t += BLOCK) {
+                        const int32_t u = src[t];
+                        L[t] = u;
+                        atomicOr(B + (u >> 5), 1u << (u & 31));
+                    }
+                } else {
+                    int32_t *H = sh_hash + s * HCAP;
+                    for (int t = tid; t < c; t += BLOCK) {
+                        const int32_t u = src[t];
+                        uint32_t h = hash_slot(u);
+                        for (int k = 0; k < HCAP && atomicCAS(&H[h], -1, u) != -1; ++k)
+                            h = h + 1 == (uint32_t)HCAP ? 0u : h + 1;
+                        sh_lidx[s * RCAP + t] = (LIdx)h;
+                    }
                 }
             }
             block_sync<BLOCK>();
@@ -1434,7 +1450,7 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
             A1.ho_state_in = ho_state.ptr;
             A1.ho_nodes_in = ho_nodes.ptr;
             A1.ho_cap_in = ho_cap;
-            A0.ho_stride = A1.ho_stride = ho_stride;
+            A0.ho_stride_out = A1.ho_stride_in = ho_stride;
 
             SKIS_HIP_TRY(hipStreamBeginCapture(gg.cs, hipStreamCaptureModeThreadLocal));
             gg.capturing = true;
@@ -1550,7 +1566,7 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
         A.ho_state_out = ho_state.ptr;
         A.ho_nodes_out = ho_nodes.ptr;
         A.ho_cap_out = ho_cap;
-        A.ho_stride = ho_stride;
+        A.ho_stride_out = ho_stride;
         for (const void *p : {(const void *)A.row_ptr, (const void *)A.pairs, (const void *)A.rec, (const void *)A.u1,
                               (const void *)A.next, (const void *)A.staging, (const void *)A.stage_used,
                               (const void *)A.out_size, (const void *)A.out_off, (const void *)A.out_probed,
@@ -1566,21 +1582,34 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
         sk.deferred = hc.n_deferred;
         sk.deferred_global = 0;
         ran_mid = ran_global = false;
+        // handover from tier 1 to the HBM tier, for a quarter of tier 1's samples (the first
+        // ones it hands on; about 1 % of the samples outgrow tier 1 on the TRI and 1.4B-edge
+        // workloads, 15 % of tier 1's)
+        DevBuf<Handover> ho2_state;
+        DevBuf<int32_t> ho2_nodes;
+        DevBuf<uint32_t> ho2_slot;
+        uint64_t ho2_cap = 0;
+        const int ho2_stride = (int)vm.visited;
         if (hc.n_deferred > 0) {
             // tier 1: the samples that outgrew tier 0, LDS visited sets of 1024 nodes
             const uint64_t nd = hc.n_deferred;
+            ho2_cap = std::min<uint64_t>(nd, std::max<uint64_t>(1024, nd / 4));
+            ho2_state.alloc(arena, ho2_cap);
+            ho2_nodes.alloc(arena, ho2_cap * (uint64_t)ho2_stride);
             reset_ids();
             A.id_list = deferred.ptr;
             A.id_count = nd;
             A.deferred = deferred2.ptr;
             A.big_row = std::max<uint32_t>(cfg.big_row, 1u << 20);
             A.tier_stats = ctr.ptr->tier[1];
-            A.ho_state_out = nullptr;
-            A.ho_nodes_out = nullptr;
-            A.ho_cap_out = 0;
+            A.ho_state_out = ho2_state.ptr;
+            A.ho_nodes_out = ho2_nodes.ptr;
+            A.ho_cap_out = ho2_cap;
+            A.ho_stride_out = ho2_stride;
             A.ho_state_in = ho_state.ptr;
             A.ho_nodes_in = ho_nodes.ptr;
             A.ho_cap_in = ho_cap;
+            A.ho_stride_in = ho_stride;
             SKIS_HIP_TRY(hipEventRecord(ev[6], s));
             hipLaunchKernelGGL(vm.fn, dim3(nbm), dim3(vm.threads), 0, s, A);
             SKIS_HIP_TRY(hipGetLastError());
@@ -1596,16 +1625,25 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
                 // bound this tier's time.  In tier 1's hand-on order they can bunch up at the
                 // end and run alone; all of them first (by pending nodes) ran 2.5x slower, as
                 // their HBM visited sets then compete for the caches.
-                std::vector<uint32_t> keys(nd);
-                SKIS_HIP_TRY(hipMemcpyAsync(keys.data(), deferred2.ptr, sizeof(uint32_t) * nd, hipMemcpyDeviceToHost, s));
+                // Each sample keeps its handover record: the record of new position q is the
+                // old position perm[q] (records exist below ho2_cap).
+                std::vector<uint32_t> ids(nd), perm(nd), moved(nd), slot(nd);
+                SKIS_HIP_TRY(hipMemcpyAsync(ids.data(), deferred2.ptr, sizeof(uint32_t) * nd, hipMemcpyDeviceToHost, s));
                 SKIS_HIP_TRY(hipStreamSynchronize(s));
+                for (uint64_t k = 0; k < nd; ++k) perm[k] = (uint32_t)k;
                 uint64_t x = 0x9E3779B97F4A7C15ull;
                 for (uint64_t k = nd - 1; k > 0; --k) {
                     x = x * 6364136223846793005ull + 1442695040888963407ull;
                     const uint64_t r = (uint64_t)(((unsigned __int128)(x >> 11) * (k + 1)) >> 53);
-                    std::swap(keys[k], keys[r]);
+                    std::swap(perm[k], perm[r]);
                 }
-                SKIS_HIP_TRY(hipMemcpyAsync(deferred2.ptr, keys.data(), sizeof(uint32_t) * nd, hipMemcpyHostToDevice, s));
+                for (uint64_t q = 0; q < nd; ++q) {
+                    moved[q] = ids[perm[q]];
+                    slot[q] = perm[q] < ho2_cap ? perm[q] : 0xFFFFFFFFu;
+                }
+                ho2_slot.alloc(arena, nd);
+                SKIS_HIP_TRY(hipMemcpyAsync(deferred2.ptr, moved.data(), sizeof(uint32_t) * nd, hipMemcpyHostToDevice, s));
+                SKIS_HIP_TRY(hipMemcpyAsync(ho2_slot.ptr, slot.data(), sizeof(uint32_t) * nd, hipMemcpyHostToDevice, s));
                 SKIS_HIP_TRY(hipStreamSynchronize(s));
             }
             sk.deferred_global = nd;
@@ -1623,9 +1661,14 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
             A.gbits = gbits.ptr;
             A.glist = glist.ptr;
             A.tier_stats = ctr.ptr->tier[2];
-            A.ho_state_in = nullptr; // the HBM tier starts its samples over
-            A.ho_nodes_in = nullptr;
-            A.ho_cap_in = 0;
+            A.ho_state_out = nullptr; // the HBM tier finishes every sample
+            A.ho_nodes_out = nullptr;
+            A.ho_cap_out = 0;
+            A.ho_state_in = ho2_state.ptr; // and resumes those tier 1 handed over
+            A.ho_nodes_in = ho2_nodes.ptr;
+            A.ho_slot_in = ho2_slot.ptr;   // null when there was nothing to shuffle
+            A.ho_cap_in = ho2_cap;
+            A.ho_stride_in = ho2_stride;
             need(A.gbits, "gbits");
             need(A.glist, "glist");
             SKIS_HIP_TRY(hipEventRecord(ev[8], s));
