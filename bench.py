@@ -267,8 +267,8 @@ def main():
         w = torch.from_numpy(g.w).to(dev)
     log("graph ready in %.1fs: n=%d m=%d" % (time.perf_counter() - t, g.n, g.m))
     if build_only:
-        # the build alone is the step: no autotuning sweep, no plain or captured comparison
-        # builds and no oracle baseline at this size
+        # the build alone is the step: no autotuning sweep, no plain comparison build (the
+        # captured form is built once beside it) and no oracle baseline at this size
         args.no_autotune = args.no_plain_compare = args.no_cpu_baseline = True
     sets = inputs.random_sets(g.n, args.queries, 50, seed=7)
     set_ptr_np, set_nodes_np = inputs.sets_to_csr(sets)
@@ -391,10 +391,10 @@ def main():
                               "speedup_persistent_over_plain": pinf.ms_tier0 / sampler_ms}
         log("plain form: sampler %.1f ms over %d level launches; persistent %.1f ms" %
             (pinf.ms_tier0, pinf.plain_levels, sampler_ms))
-    if not args.no_plain_compare and args.form == 0:
+    if (build_only or not args.no_plain_compare) and args.form == 0:
         # the captured form: the same chain captured into a HIP graph, replayed per chunk
         cinfs = []
-        for _ in range(2):
+        for _ in range(1 if build_only else 2):
             sk = skis.build_sketch(rp, col, w, T, inputs.SAMPLE_SEED, form=2, build_inverse_index=0,
                                    **{k: v for k, v in opts.items() if k != "form"})
             cinfs.append(sk.info())

@@ -1373,6 +1373,16 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
         need(gc.ptr, "chain control");
         need(gbits.ptr, "gbits");
         need(glist.ptr, "glist");
+        // handover from tier 1 to the HBM tier for the first ho2_cap samples tier 1 hands on
+        // in a chunk; tier 2 takes them in that order, so position p resumes from record p
+        const uint64_t ho2_cap = std::min<uint64_t>(chunk, std::max<uint64_t>(1024, chunk / 32));
+        const int ho2_stride = (int)vm.visited;
+        DevBuf<Handover> ho2_state;
+        DevBuf<int32_t> ho2_nodes;
+        ho2_state.alloc(arena, ho2_cap);
+        ho2_nodes.alloc(arena, ho2_cap * (uint64_t)ho2_stride);
+        need(ho2_state.ptr, "handover");
+        need(ho2_nodes.ptr, "handover nodes");
         struct GraphGuard {
             hipStream_t cs = nullptr;
             hipGraph_t g = nullptr;
@@ -1444,13 +1454,21 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
             A2.n_deferred = &ctr.ptr->n_deferred; // unused for the same reason
             A2.gbits = gbits.ptr;
             A2.glist = glist.ptr;
-            A0.ho_state_out = ho_state.ptr; // tier 0 hands over, tier 1 resumes, tier 2 starts over
-            A0.ho_nodes_out = ho_nodes.ptr;
+            A0.ho_state_out = ho_state.ptr; // tier 0 hands over, tier 1 resumes and hands over,
+            A0.ho_nodes_out = ho_nodes.ptr; // tier 2 resumes
             A0.ho_cap_out = ho_cap;
             A1.ho_state_in = ho_state.ptr;
             A1.ho_nodes_in = ho_nodes.ptr;
             A1.ho_cap_in = ho_cap;
             A0.ho_stride_out = A1.ho_stride_in = ho_stride;
+            A1.ho_state_out = ho2_state.ptr;
+            A1.ho_nodes_out = ho2_nodes.ptr;
+            A1.ho_cap_out = ho2_cap;
+            A2.ho_state_in = ho2_state.ptr;
+            A2.ho_nodes_in = ho2_nodes.ptr;
+            A2.ho_slot_in = nullptr;
+            A2.ho_cap_in = ho2_cap;
+            A1.ho_stride_out = A2.ho_stride_in = ho2_stride;
 
             SKIS_HIP_TRY(hipStreamBeginCapture(gg.cs, hipStreamCaptureModeThreadLocal));
             gg.capturing = true;

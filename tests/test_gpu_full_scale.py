@@ -1,5 +1,6 @@
 """Parity at the 1.4B-edge shape (cl40m_wc: 40M nodes, 1.4B edges, T = 2^26): three ranges of
-1024 sample ids of the GPU sketch against the CPU oracle on the same graph, bit for bit.
+1024 sample ids of the GPU sketch against the CPU oracle on the same graph, bit for bit, and the
+captured form's whole sketch against the eager form's.
 Opt-in (SKIS_FULL_SCALE=1): the oracle's preprocessing of 1.4B edges takes minutes of host
 time, too long for the default GPU run."""
 import os
@@ -36,6 +37,16 @@ def test_cl40m_sample_ranges_match_oracle():
     sk = skis.build_sketch(rp, col, w, T, inputs.SAMPLE_SEED, build_inverse_index=0)
     sp, nodes, roots, probed = sk.export()
     _say("entries", int(sp[-1]))
+    sk.free()
+    # the captured form (16 replays of its chain over chunks of 2^22 ids) writes the same sketch
+    _say("captured form")
+    cap = skis.build_sketch(rp, col, w, T, inputs.SAMPLE_SEED, form=2, build_inverse_index=0)
+    cinf = cap.info()
+    _say("captured info", cinf)
+    assert cinf.graph_replays == T >> 22 and cinf.deferred_global > 0
+    for x, y in zip(cap.export(), (sp, nodes, roots, probed)):
+        assert torch.equal(x, y)
+    cap.free()
     hrp, hcol, hw = rp.cpu().numpy(), col.cpu().numpy(), w.cpu().numpy()
     for j0 in (0, T // 2 + 12345, T - 1024):
         j1 = j0 + 1024
