@@ -43,6 +43,34 @@ _TIER0 = {(64, 4, 192, 2): (256, 128), (64, 4, 192, 1): (256, 64), (64, 4, 256, 
           (256, 16, 128, 2): (172, 1024), (256, 32, 128, 2): (172, 1024), (256, 16, 256, 2): (344, 1024)}
 
 
+def random_access_probe(dev, table_log2=33, reps=5):
+    """Achievable random-access HBM bandwidth: the library's probe reads 2^26 rows at uniformly
+    random positions of an 8 GiB table, far above the last-level caches, for the sampler's two
+    random granules, 8-byte row bounds and 32-byte edge quads.  Bytes counted: the rows read.
+    Best of `reps`, timed with events on torch's stream (where the probe is launched)."""
+    import torch
+
+    from paper_1709_03565_amd import skis
+    table = torch.zeros(1 << table_log2, dtype=torch.uint8, device=dev)
+    sink = torch.zeros(1, dtype=torch.int32, device=dev)
+    reads = 1 << 26
+    res = {"probe": "skis_probe_random_read: 2^26 uniformly random rows of an 8 GiB table, bytes of the rows read"}
+    for rb in (8, 32):
+        best = float("inf")
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            skis.probe_random_read(table, rb, reads, sink)
+            e1.record()
+            e1.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        res["rows_%dB_ms" % rb] = best
+        res["rows_%dB_gbs" % rb] = reads * rb / (best * 1e-3) / 1e9
+    del table, sink
+    torch.cuda.empty_cache()
+    return res
+
+
 def tier0_kernel_name(opts) -> str:
     key = (opts.get("threads_per_block", 64), opts.get("slots_per_block", 4), opts.get("visited_threshold", 192),
            opts.get("quads_per_lane", 1))
@@ -405,6 +433,16 @@ def main():
                                  "persistent_sampler_ms": sampler_ms}
         log("captured form: sampler %.1f ms over %d graph replays; persistent %.1f ms" %
             (cinf.ms_tier0, cinf.graph_replays, sampler_ms))
+    # the tier-0 launch's algorithmic bandwidth against what random 32-byte reads reach
+    try:
+        ra = random_access_probe(dev)
+        ra["tier0_frac_of_32B"] = achieved / ra["rows_32B_gbs"]
+        log("random-access probe: %.0f GB/s in 8-B rows, %.0f GB/s in 32-B rows; tier 0 at %.2f of the latter" %
+            (ra["rows_8B_gbs"], ra["rows_32B_gbs"], ra["tier0_frac_of_32B"]))
+    except Exception as ex:  # a measurement aid: its failure does not void the step's numbers
+        ra = {"error": str(ex).splitlines()[0]}
+        log("random-access probe failed:", ra["error"])
+    line["random_access"] = ra
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(g, wl, (set_ptr_np, set_nodes_np), args.k, T)
     print(json.dumps(line), flush=True)

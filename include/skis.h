@@ -184,6 +184,17 @@ void skis_sketch_free(skis_sketch *sk);
 /* Message for the last failing call on this thread ("" if none). */
 const char *skis_last_error(void);
 
+/* Measurement aid, not a step of the method: reads `reads` rows of `row_bytes` bytes (8, 16,
+ * 32 or 64) at uniformly random positions of a device table of `rows` rows (1 <= rows < 2^32,
+ * the table 16-byte aligned and at least rows * row_bytes bytes; reads < 2^32), stream-ordered
+ * on `stream` and asynchronous.  It measures the achievable bandwidth of random reads of one
+ * size, the ceiling for the sampler's random row-bound (8 B) and edge-quad (32 B) reads; the
+ * caller times it.  `sink` is one device uint32 that is written only if the folded row words
+ * equal a fixed constant.  SKIS_EINVAL for NULL pointers, an unsupported row size or sizes out
+ * of range. */
+int skis_probe_random_read(const void *table, uint64_t rows, uint32_t row_bytes, uint64_t reads, uint32_t seed,
+                           uint32_t *sink, hipStream_t stream);
+
 /*
  * Estimate service over a resident sketch: Alg. 2 answers any seed set from the one
  * sketch (Eq. eq21), so a stream of influence queries is served without touching the

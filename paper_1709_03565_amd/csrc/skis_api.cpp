@@ -500,6 +500,15 @@ void skis_sketch_free(skis_sketch *h)
     delete h;
 }
 
+int skis_probe_random_read(const void *table, uint64_t rows, uint32_t row_bytes, uint64_t reads, uint32_t seed,
+                           uint32_t *sink, hipStream_t stream)
+{
+    return guarded([&]() -> int {
+        skis::probe_random_read(table, rows, row_bytes, reads, seed, sink, stream);
+        return SKIS_OK;
+    });
+}
+
 const char *skis_last_error(void) { return skis::get_error().c_str(); }
 
 } // extern "C"

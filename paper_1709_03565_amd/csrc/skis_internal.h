@@ -181,4 +181,10 @@ void excl_scan_u32_to_i64(Arena &arena, const uint32_t *in, int64_t *out, int64_
 // Launch-shape helper: number of compute units of the current device.
 int device_cu_count();
 
+// Random-read probe (measurement aid): `reads` uniformly random rows of row_bytes bytes
+// from a table of `rows` rows, stream-ordered on s; sink is one device word it almost never
+// writes.
+void probe_random_read(const void *table, uint64_t rows, uint32_t row_bytes, uint64_t reads, uint32_t seed,
+                       uint32_t *sink, hipStream_t s);
+
 } // namespace skis

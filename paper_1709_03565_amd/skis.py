@@ -23,7 +23,7 @@ EXPORTED = ("skis_default_options", "skis_preprocess", "skis_build_sketch", "ski
             "skis_estimate", "skis_greedy_max_cover", "skis_sketch_export", "skis_inverse_export",
             "skis_node_q", "skis_sketch_free", "skis_last_error", "skis_server_default_options",
             "skis_server_create", "skis_server_submit", "skis_server_wait", "skis_server_replay",
-            "skis_server_get_stats", "skis_server_destroy")
+            "skis_server_get_stats", "skis_server_destroy", "skis_probe_random_read")
 
 
 class SkisError(RuntimeError):
@@ -94,6 +94,8 @@ def lib():
         L.skis_sketch_export.restype = ctypes.c_int
         L.skis_inverse_export.argtypes = [P, P, P, P]
         L.skis_inverse_export.restype = ctypes.c_int
+        L.skis_probe_random_read.argtypes = [P, u64, ctypes.c_uint32, u64, ctypes.c_uint32, P, P]
+        L.skis_probe_random_read.restype = ctypes.c_int
         L.skis_node_q.argtypes = [P, P, P]
         L.skis_node_q.restype = ctypes.c_int
         L.skis_sketch_free.argtypes = [P]
@@ -331,3 +333,13 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def probe_random_read(table: torch.Tensor, row_bytes: int, reads: int, sink: torch.Tensor, seed: int = 1) -> None:
+    """Reads `reads` rows of row_bytes bytes at uniformly random positions of the device
+    tensor `table` (its bytes split into rows) on torch's current stream; a measurement aid
+    for the random-access ceiling, timed by the caller.  sink: one int32 on the device."""
+    if not (table.is_cuda and sink.is_cuda and table.is_contiguous()):
+        raise ValueError("table and sink must be contiguous device tensors")
+    rows = table.numel() * table.element_size() // row_bytes if row_bytes > 0 else 0
+    _check(lib().skis_probe_random_read(_ptr(table), rows, row_bytes, reads, seed, _ptr(sink), _stream()))
