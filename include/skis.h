@@ -67,7 +67,7 @@ typedef struct skis_options {
                                      (64,16,64,2), (256,16,128,2), (256,32,128,2), (256,16,256,2) */
     uint64_t max_device_bytes;    /* 0 = unlimited; larger total allocation -> SKIS_ENOMEM */
     uint64_t staging_entries;     /* initial staging capacity in node entries (0 = auto) */
-    uint64_t chunk_samples;       /* captured form: sample ids per graph replay (0 = 2^22) */
+    uint64_t chunk_samples;       /* captured form: sample ids per graph replay (0 = 2^24) */
     uint32_t quads_per_lane;      /* first tier: most edge quads (aligned groups of four edges)
                                      a lane takes per sweep, 1 (default: fewer registers, more
                                      workgroups resident) or 2 */

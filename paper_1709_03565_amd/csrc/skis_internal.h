@@ -154,7 +154,7 @@ struct SampleConfig {
     uint32_t visited = 192;
     uint32_t big_row = 16384;
     uint64_t staging_entries = 0;
-    uint64_t chunk = 0; // captured form: samples per replay of the chain (0: 2^22)
+    uint64_t chunk = 0; // captured form: samples per replay of the chain (0: 2^24)
     uint32_t qpl = 1;   // edge quads per lane per sweep in the first tier
     bool owners = false; // also write the sample id of every entry (Sketch::owner) for the transpose
 };

@@ -38,12 +38,12 @@ def test_cl40m_sample_ranges_match_oracle():
     sp, nodes, roots, probed = sk.export()
     _say("entries", int(sp[-1]))
     sk.free()
-    # the captured form (16 replays of its chain over chunks of 2^22 ids) writes the same sketch
+    # the captured form (4 replays of its chain over chunks of 2^24 ids) writes the same sketch
     _say("captured form")
     cap = skis.build_sketch(rp, col, w, T, inputs.SAMPLE_SEED, form=2, build_inverse_index=0)
     cinf = cap.info()
     _say("captured info", cinf)
-    assert cinf.graph_replays == T >> 22 and cinf.deferred_global > 0
+    assert cinf.graph_replays == T >> 24 and cinf.deferred_global > 0
     for x, y in zip(cap.export(), (sp, nodes, roots, probed)):
         assert torch.equal(x, y)
     cap.free()

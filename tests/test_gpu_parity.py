@@ -218,7 +218,7 @@ def test_captured_form_matches_oracle_and_persistent(skis, which, chunk):
         cap = skis.build_sketch(rp, c, w, T, 13, form=2, chunk_samples=chunk)
         inf = cap.info()
         _say("captured info", rep, inf)
-        eff = min(chunk or (1 << 22), T)
+        eff = min(chunk or (1 << 24), T)
         assert inf.graph_replays == (T + eff - 1) // eff
         _assert_tiers_add_up(inf)
         assert list(inf.tier_samples) == list(pers.info().tier_samples)
