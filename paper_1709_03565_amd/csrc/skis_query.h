@@ -8,6 +8,7 @@ namespace skis {
 
 constexpr int EST_BLOCK = 1024;   // threads per query in k_estimate
 constexpr int EST_MAX_SET = 4096; // largest seed set one estimate workgroup holds in LDS
+constexpr int EST_WALK = 4;       // sample-list entries a thread walks per round, loads issued together
 
 constexpr int GREEDY_HOT = 2048;  // hot nodes decremented in LDS
 

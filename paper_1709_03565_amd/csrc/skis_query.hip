@@ -42,6 +42,37 @@ __device__ void bitonic_sort_lds(int32_t *buf, int P)
     }
 }
 
+// Flips the bit of sample j in bm for every lane of the wave with in = true and returns the
+// bits this lane flipped; every lane of the wave must call it.  A sample list is sorted by
+// sample id and a wave walks consecutive entries, so on a dense list (a hub's) neighbouring
+// lanes often share a bitmap word.  When any do, the bits of lanes with the same word are
+// OR-ed within aligned groups of 8 lanes by a segmented scan (a lane takes the running OR of
+// lane - d in its group when their words agree; a run of equal words is contiguous, and lanes
+// of another run with the same word only add bits of that word), and the last lane of each
+// run in a group sets them with one atomicOr.  Atomics on one word are serialised, so every
+// flip is counted once.  When no neighbours share a word, each lane flips its own bit.
+__device__ __forceinline__ unsigned long long flip_bits_wave(uint32_t *bm, int32_t j, bool in)
+{
+    const int lane = threadIdx.x & 63;
+    const uint32_t w = (uint32_t)j >> 5;
+    uint32_t acc = in ? 1u << (j & 31) : 0u;
+    // the shuffle runs on every lane: under a mask it would read 0 from the masked lane 63
+    const uint32_t nw = __shfl_down(w, 1, 64);
+    const bool same_next = lane < 63 && nw == w;
+    bool last = true;
+    if (__ballot(same_next) != 0ull) { // wave-uniform
+#pragma unroll
+        for (int d = 1; d < 8; d <<= 1) {
+            const uint32_t ow = __shfl_up(w, d, 64), oa = __shfl_up(acc, d, 64);
+            if ((lane & 7) >= d && ow == w) acc |= oa;
+        }
+        last = (lane & 7) == 7 || !same_next;
+    }
+    if (!last || !acc) return 0ull;
+    const uint32_t old = atomicOr(&bm[w], acc);
+    return (unsigned long long)__popc(acc & ~old);
+}
+
 // One workgroup per query.  The set is taken in chunks of EST_MAX_SET entries; each chunk is
 // sorted and deduplicated in LDS.  LARGE workgroups (sets above one chunk) also keep a
 // bitmap of n bits that drops ids already met in an earlier chunk.  The distinct members'
@@ -179,17 +210,32 @@ __global__ __launch_bounds__(EST_BLOCK) void k_estimate(const int64_t *__restric
                 E = 0; // nothing to walk here
             }
         }
-        for (int64_t idx = tid; idx < E; idx += EST_BLOCK) {
-            int lo = 0, hi = nu - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (dbase[mid] <= idx) lo = mid; else hi = mid - 1;
+        // EST_WALK entries per thread and round, their loads issued together; a wave takes 64
+        // consecutive entries and flips their bits with one atomic per bitmap word it meets.
+        // The rounds are the same for the whole wave (the flips shuffle across it); a lane past
+        // E repeats entry E - 1 (in bounds) and flips no bit.
+        for (int64_t i0 = tid; i0 - (tid & 63) < E; i0 += (int64_t)EST_BLOCK * EST_WALK) { // wave-uniform
+            int64_t ix[EST_WALK];
+            int lv[EST_WALK];
+#pragma unroll
+            for (int u = 0; u < EST_WALK; ++u) {
+                const int64_t idx = i0 + (int64_t)u * EST_BLOCK;
+                ix[u] = idx < E ? idx : E - 1;
+                int lo = 0, hi = nu - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (dbase[mid] <= ix[u]) lo = mid; else hi = mid - 1;
+                }
+                lv[u] = lo;
             }
-            const int32_t v = buf[lo];
-            const int32_t j = node_samples[node_ptr[v] + (idx - dbase[lo])];
-            const uint32_t bit = 1u << (j & 31);
-            const uint32_t old = atomicOr(&bm[j >> 5], bit);
-            if (!(old & bit)) ++local;
+            int64_t np[EST_WALK];
+#pragma unroll
+            for (int u = 0; u < EST_WALK; ++u) np[u] = node_ptr[buf[lv[u]]];
+            int32_t jv[EST_WALK];
+#pragma unroll
+            for (int u = 0; u < EST_WALK; ++u) jv[u] = node_samples[np[u] + (ix[u] - dbase[lv[u]])];
+#pragma unroll
+            for (int u = 0; u < EST_WALK; ++u) local += flip_bits_wave(bm, jv[u], i0 + (int64_t)u * EST_BLOCK < E);
         }
         __syncthreads();
     }
@@ -222,15 +268,33 @@ __global__ __launch_bounds__(EST_BLOCK) void k_estimate(const int64_t *__restric
         for (uint64_t w = tid; w < wordsT; w += EST_BLOCK) bm[w] = 0u;
         for (int64_t t = a + tid; t < b; t += EST_BLOCK) nb[set_nodes[t] >> 5] = 0u;
     } else {
-        for (int64_t idx = tid; idx < E; idx += EST_BLOCK) { // one chunk: buf and dbase still hold it
-            int lo = 0, hi = nu - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (dbase[mid] <= idx) lo = mid; else hi = mid - 1;
+        // one chunk: buf and dbase still hold it; the same rounds as the walk (a lane past E
+        // clears the word of entry E - 1 once more)
+        for (int64_t i0 = tid; i0 - (tid & 63) < E; i0 += (int64_t)EST_BLOCK * EST_WALK) { // wave-uniform
+            int64_t ix[EST_WALK];
+            int lv[EST_WALK];
+#pragma unroll
+            for (int u = 0; u < EST_WALK; ++u) {
+                const int64_t idx = i0 + (int64_t)u * EST_BLOCK;
+                ix[u] = idx < E ? idx : E - 1;
+                int lo = 0, hi = nu - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (dbase[mid] <= ix[u]) lo = mid; else hi = mid - 1;
+                }
+                lv[u] = lo;
             }
-            const int32_t v = buf[lo];
-            const int32_t j = node_samples[node_ptr[v] + (idx - dbase[lo])];
-            bm[j >> 5] = 0u;
+            int64_t np[EST_WALK];
+#pragma unroll
+            for (int u = 0; u < EST_WALK; ++u) np[u] = node_ptr[buf[lv[u]]];
+            int32_t jv[EST_WALK];
+#pragma unroll
+            for (int u = 0; u < EST_WALK; ++u) jv[u] = node_samples[np[u] + (ix[u] - dbase[lv[u]])];
+#pragma unroll
+            for (int u = 0; u < EST_WALK; ++u) { // the last lane of each run of equal words clears it
+                const uint32_t w = (uint32_t)jv[u] >> 5, nw = __shfl_down(w, 1, 64);
+                if ((threadIdx.x & 63) == 63 || nw != w) bm[w] = 0u;
+            }
         }
     }
 }
