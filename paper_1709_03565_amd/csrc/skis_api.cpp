@@ -112,6 +112,27 @@ static void cache_put(void *p, size_t size, bool pooled)
     }
 }
 
+// Under memory pressure: every idle block of this device's cache goes back, and the
+// stream-ordered pool gives what it holds back to the device (after the device is idle), so
+// that a failed allocation can be retried on memory the process is only keeping.
+static void release_idle_memory()
+{
+    int d = 0;
+    if (hipGetDevice(&d) != hipSuccess || d < 0 || d >= CACHE_DEVICES) return;
+    (void)hipDeviceSynchronize();
+    {
+        BlockCache &c = block_cache(d);
+        std::lock_guard<std::mutex> lk(c.mu);
+        for (auto &b : c.blocks) free_block(b.second.p, b.second.pooled);
+        c.blocks.clear();
+        c.bytes = 0;
+    }
+    (void)hipDeviceSynchronize();
+    hipMemPool_t pool = nullptr;
+    if (hipDeviceGetDefaultMemPool(&pool, d) == hipSuccess) (void)hipMemPoolTrimTo(pool, 0);
+    (void)hipGetLastError();
+}
+
 // A released block is kept and handed to a later request of at least half its size: the
 // stages of one build (sampler, compaction, transpose) allocate and release buffers of a few
 // GB each, and reusing them avoids a driver call per buffer.  Kept blocks go back to the
@@ -146,9 +167,10 @@ void *Arena::alloc(size_t bytes)
     void *p = nullptr;
     const bool pooled = pool_ready();
     hipError_t e = pooled ? hipMallocAsync(&p, need, stream) : hipMalloc(&p, need);
-    if (e != hipSuccess && !free_blocks.empty()) { // give the kept blocks back and try once more
+    if (e != hipSuccess) { // give the kept and the idle blocks back and try once more
         (void)hipGetLastError();
         trim();
+        release_idle_memory();
         e = pooled ? hipMallocAsync(&p, need, stream) : hipMalloc(&p, need);
     }
     if (e != hipSuccess) {
