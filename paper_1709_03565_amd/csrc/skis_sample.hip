@@ -103,6 +103,10 @@ struct __align__(16) Handover {
     unsigned long long probed;
 };
 
+// The largest prime below 2^32: for every count below it k -> k * P mod count permutes
+// [0, count) (P and count are coprime), and k * P fits in 64 bits for k < 2^32.
+constexpr unsigned long long ID_PERM_PRIME = 4294967291ull;
+
 struct SampleArgs {
     int32_t n;
     const int32_t *row_ptr;
@@ -119,6 +123,9 @@ struct SampleArgs {
     uint64_t id_count;
     const unsigned long long *id_count_dev; // when set, id_count is read from here at launch
     const unsigned long long *id_base_dev;  // when set, id_base is read from here (else 0)
+    // nonzero: the k-th id taken is id_list[(k * ID_PERM_PRIME) mod id_count], a fixed
+    // scramble of the list's order (a bijection for counts below the prime); 0: id_list[k]
+    uint32_t id_perm;
     uint32_t big_row;
     int32_t *staging;
     unsigned long long stage_cap;
@@ -218,6 +225,11 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
     const int32_t n = a.n;
     // the work of this launch; in a captured chain the previous kernel has written it
     const unsigned long long id_count = SKIS_KARG(id_count_dev) ? *SKIS_KARG(id_count_dev) : SKIS_KARG(id_count);
+    // position in id_list (and in the handover records) of the k-th id taken
+    const bool perm = SKIS_KARG(id_perm) && id_count < ID_PERM_PRIME;
+    auto list_pos = [&](unsigned long long k) -> unsigned long long {
+        return perm ? (k * ID_PERM_PRIME) % id_count : k;
+    };
     const unsigned long long id_base = SKIS_KARG(id_base_dev) ? *SKIS_KARG(id_base_dev) : 0ull;
 
     auto list_ptr = [&](int s) -> int32_t * { return a.glist + ((size_t)blockIdx.x * S + s) * (size_t)n; };
@@ -443,7 +455,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                     if (s < IDBATCH) {
                         const unsigned long long id = nb + (unsigned long long)s;
                         if (id < id_count) {
-                            const uint32_t i = SKIS_KARG(id_list) ? SKIS_KARG(id_list)[id] : (uint32_t)(id_base + id);
+                            const uint32_t i = SKIS_KARG(id_list) ? SKIS_KARG(id_list)[list_pos(id)] : (uint32_t)(id_base + id);
                             s_cidx[cur][s] = i;
                             s_crec[cur][s] = SKIS_KARG(rec)[i];
                             s_cu1[cur][s] = SKIS_KARG(u1)[i];
@@ -491,7 +503,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                     bool resumed = false;
                     if constexpr (HO_IN) {
                         const uint32_t *hs = SKIS_KARG(ho_slot_in);
-                        const unsigned long long rec_k = hs ? (unsigned long long)hs[myid] : myid;
+                        const unsigned long long rec_k = hs ? (unsigned long long)hs[myid] : list_pos(myid);
                         if (SKIS_KARG(ho_state_in) && rec_k < SKIS_KARG(ho_cap_in)) {
                             const Handover h = SKIS_KARG(ho_state_in)[rec_k];
                             const int cur = h.cursor_rp >> 1;
@@ -1452,6 +1464,7 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
             A2.next = &gc.ptr->next2;
             A2.id_list = deferred2.ptr;
             A2.id_count_dev = &gc.ptr->nd1;
+            A2.id_perm = 1; // the eager form shuffles on the host; here the order is scrambled in place
             A2.deferred = deferred.ptr; // unused: the HBM tier finishes every sample
             A2.n_deferred = &ctr.ptr->n_deferred; // unused for the same reason
             A2.gbits = gbits.ptr;
