@@ -264,7 +264,7 @@ def main():
 
     if args.gpus != 1:
         print("bench.py measures one GPU only: the sketch shards by sample id with no communication, "
-              "and this build runs and reports a single GPU (got --gpus %d)" % args.gpus, file=sys.stderr)
+              "and this benchmark runs and reports a single GPU (got --gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
