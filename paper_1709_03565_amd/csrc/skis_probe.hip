@@ -1,6 +1,6 @@
 // skis_probe.hip -- random-read bandwidth probe: the achievable HBM bandwidth of uniformly
 // random reads of one row size, the ceiling against which the sampler's random-access
-// kernels are judged (they read 8-byte row bounds and 32-byte edge quads at random).
+// kernels are measured (they read 8-byte row bounds and 32-byte edge quads at random).
 #include <hip/hip_runtime.h>
 
 #include "skis_internal.h"
