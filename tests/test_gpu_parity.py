@@ -467,3 +467,29 @@ def test_full_size_windows(skis, name):
     gains = (deg.astype(np.float64) * inf.Gamma) / float(T) + q
     assert int(seeds[0]) == int(np.argmax(gains)) and marg[0] == deg[seeds[0]]
     _say("greedy", name, "first picks", seeds[:4].tolist(), "marg", marg[:4].tolist())
+
+
+def test_estimate_dense_list_every_lane_boundary(skis):
+    # a centre node c = n - 1 with a certain edge into every other node: every sample, rooted at
+    # a leaf, is {leaf, c}, so H(c) holds every sample id and a wave of the walk meets runs of
+    # 32 lanes on one bitmap word.  Sets {0 .. k-1, c} start c's list at every lane of a wave
+    # (their leaf lists come first), including lanes 62 and 63 and word 0 of the bitmap.
+    n, T, seed = 97, 6000, 5
+    rp = np.concatenate([np.arange(n, dtype=np.int32), np.array([n - 1], np.int32)])
+    col = np.full(n - 1, n - 1, np.int32)
+    w = np.ones(n - 1, np.float32)
+    _say("dense list: star n=%d T=%d" % (n, T))
+    ora = oracle.build_sketch(rp, col, w, seed=seed, j0=0, j1=T, nthreads=4)
+    sk = skis.build_sketch(rp, col, w, T, seed)
+    _assert_sketch_equal(sk, ora)
+    sets = [np.array(list(range(k)) + [n - 1], np.int32) for k in range(0, n - 1)]
+    sets += [np.array([n - 1], np.int32), np.arange(n, dtype=np.int32), np.array([0, 1, 2], np.int32)]
+    set_ptr, set_nodes = inputs.sets_to_csr(sets)
+    cov, est = sk.estimate(set_ptr, set_nodes)
+    _, q = oracle.row_prefix(rp, w)
+    ocov, oest = oracle.estimate(n, ora.sample_ptr, ora.nodes, q, ora.Gamma, set_ptr=set_ptr, set_nodes=set_nodes)
+    assert np.array_equal(_np(cov).astype(np.uint64), ocov)
+    assert int(ocov[0]) == T  # {c} alone covers every sample
+    e = _np(est)
+    assert np.all(np.abs(e - oest) <= REL * np.maximum(np.abs(oest), 1e-300))
+    sk.free()
