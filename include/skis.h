@@ -80,8 +80,8 @@ void skis_default_options(skis_options *opt);
 /*
  * Preprocessing alone (rows a1-a3 of the hot path), into caller buffers:
  *   Eq. (gamma_v):  P[e] = prod of (1 - w) over row v up to and including edge e, in row
- *                   order, fp64, one rounding per product (the bucket masses of
- *                   Eq. probn are P[e-1] - P[e] / gamma_v);  q[v] = P of the last edge of
+ *                   order, left to right, fp64, one rounding per product (the bucket
+ *                   masses of Eq. probn are (P[e-1] - P[e]) / gamma_v);  q[v] = P of the last edge of
  *                   row v (1 for an empty row) = 1 - gamma_v.
  *   Eq. (probu):    root weights W[v] = ceil(gamma_v * 2^s), s = 62 - ceil(log2 n), so the
  *                   root is v with probability W[v]/C, C = sum W (*C_out, host);
@@ -135,6 +135,10 @@ typedef struct skis_info {
                                     plain form counts everything in tier 0 */
     uint64_t tier_entries[3];    /* sum of |R_j| over those samples */
     uint64_t tier_probed[3];     /* edges probed for those samples */
+    uint64_t tier_swept[3];      /* in-edges each tier's launch expanded (the work of that launch:
+                                    a sample resumed from an earlier tier is not counted again for
+                                    the nodes that tier expanded) */
+    uint64_t tier_items[3];      /* nodes (and root items) each tier's launch expanded */
 } skis_info;
 
 /* Sketch facts (host out-param). */
@@ -172,7 +176,7 @@ int skis_sketch_export(const skis_sketch *sk, int64_t *sample_ptr, int32_t *node
                        uint64_t *probed, hipStream_t stream);
 
 /* Copies the node->samples transpose: node_ptr int64[n+1] and node_samples int32[entries]
- * (each list holds the ids j with v in R_j, in no particular order).  Either may be NULL. */
+ * (each list holds the ids j with v in R_j in ascending order).  Either may be NULL. */
 int skis_inverse_export(const skis_sketch *sk, int64_t *node_ptr, int32_t *node_samples, hipStream_t stream);
 
 /* Copies q[v] = 1 - gamma_v (fp64, n entries). */
@@ -185,13 +189,13 @@ void skis_sketch_free(skis_sketch *sk);
 const char *skis_last_error(void);
 
 /* Measurement aid, not a step of the method: reads `reads` rows of `row_bytes` bytes (8, 16,
- * 32 or 64) at uniformly random positions of a device table of `rows` rows (1 <= rows < 2^32,
- * the table 16-byte aligned and at least rows * row_bytes bytes; reads < 2^32), stream-ordered
- * on `stream` and asynchronous.  It measures the achievable bandwidth of random reads of one
- * size, the ceiling for the sampler's random row-bound (8 B) and edge-quad (32 B) reads; the
- * caller times it.  `sink` is one device uint32 that is written only if the folded row words
- * equal a fixed constant.  SKIS_EINVAL for NULL pointers, an unsupported row size or sizes out
- * of range. */
+ * 32, 64 or 128) at uniformly random positions of a device table of `rows` rows
+ * (1 <= rows < 2^32, the table 16-byte aligned and at least rows * row_bytes bytes;
+ * reads < 2^32), stream-ordered on `stream` and asynchronous.  It measures the achievable
+ * bandwidth of random reads of one size, the ceiling for the sampler's random row-bound (8 B)
+ * and edge-quad (32 B) reads and for whole cache lines (64 and 128 B); the caller times it.
+ * `sink` is one device uint32 that is written only if the folded row words equal a fixed
+ * constant.  SKIS_EINVAL for NULL pointers, an unsupported row size or sizes out of range. */
 int skis_probe_random_read(const void *table, uint64_t rows, uint32_t row_bytes, uint64_t reads, uint32_t seed,
                            uint32_t *sink, hipStream_t stream);
 

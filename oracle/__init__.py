@@ -67,6 +67,18 @@ def lib():
         L.ora_alias_build.restype = ctypes.c_int
         L.ora_build.argtypes = [i32, i64, P, P, P, u64, u64, u64, ctypes.c_int, ctypes.c_int]
         L.ora_build.restype = P
+        L.ora_prepare.argtypes = [i32, i64, P, P, P]
+        L.ora_prepare.restype = P
+        L.ora_prep_status.argtypes = [P]
+        L.ora_prep_status.restype = ctypes.c_int
+        L.ora_prep_scalars.argtypes = [P, P, P]
+        L.ora_prep_scalars.restype = None
+        L.ora_prep_copy.argtypes = [P, P, P, P, P, P]
+        L.ora_prep_copy.restype = None
+        L.ora_prep_free.argtypes = [P]
+        L.ora_prep_free.restype = None
+        L.ora_sample.argtypes = [P, u64, u64, u64, ctypes.c_int, ctypes.c_int]
+        L.ora_sample.restype = P
         L.ora_sketch_status.argtypes = [P]
         L.ora_sketch_status.restype = ctypes.c_int
         L.ora_sketch_info.argtypes = [P, P, P, P, P, P]
@@ -122,8 +134,8 @@ def validate(row_ptr, col, w) -> int:
 
 
 def row_prefix(row_ptr, w):
-    """(P[m], q[n]) of Eq. (gamma_v) / Eq. (probn): per row, products in blocks of 64
-    in-edges with a carried block product (a plain left-to-right product up to 64)."""
+    """(P[m], q[n]) of Eq. (gamma_v) / Eq. (probn): per row, the left-to-right running
+    product of (1 - w) in binary64."""
     row_ptr, w = _c(row_ptr, np.int32), _c(w, np.float32)
     n = len(row_ptr) - 1
     P = np.zeros(max(len(w), 1), np.float64)
@@ -178,12 +190,7 @@ class Sketch:
         return self.nodes[self.sample_ptr[i]:self.sample_ptr[i + 1]]
 
 
-def build_sketch(row_ptr, col, w, seed: int, j0: int, j1: int, nthreads: int = 1,
-                 ris_mode: bool = False) -> Sketch:
-    row_ptr, col, w = _c(row_ptr, np.int32), _c(col, np.int32), _c(w, np.float32)
-    n, m = len(row_ptr) - 1, len(col)
-    L = lib()
-    h = L.ora_build(n, m, _p(row_ptr), _p(col), _p(w), seed, j0, j1, nthreads, int(ris_mode))
+def _take_sketch(L, h, j0) -> Sketch:
     if not h:
         raise OracleError(ENOMEM)
     try:
@@ -203,6 +210,54 @@ def build_sketch(row_ptr, col, w, seed: int, j0: int, j1: int, nthreads: int = 1
                       G.value, C.value, j0)
     finally:
         L.ora_sketch_free(h)
+
+
+def build_sketch(row_ptr, col, w, seed: int, j0: int, j1: int, nthreads: int = 1,
+                 ris_mode: bool = False) -> Sketch:
+    row_ptr, col, w = _c(row_ptr, np.int32), _c(col, np.int32), _c(w, np.float32)
+    n, m = len(row_ptr) - 1, len(col)
+    L = lib()
+    return _take_sketch(L, L.ora_build(n, m, _p(row_ptr), _p(col), _p(w), seed, j0, j1, nthreads,
+                                       int(ris_mode)), j0)
+
+
+class Prepared:
+    """Alg. 2's preprocessing of one graph, done once (validation, P, q, Gamma, root weights,
+    alias table); any number of sample-id ranges are then drawn from it.  Holds the graph
+    arrays for as long as it lives."""
+
+    def __init__(self, row_ptr, col, w):
+        self.row_ptr, self.col, self.w = _c(row_ptr, np.int32), _c(col, np.int32), _c(w, np.float32)
+        self.n, self.m = len(self.row_ptr) - 1, len(self.col)
+        L = lib()
+        self._h = L.ora_prepare(self.n, self.m, _p(self.row_ptr), _p(self.col), _p(self.w))
+        if not self._h:
+            raise OracleError(ENOMEM)
+        self.status = L.ora_prep_status(self._h)
+        if self.status < 0:
+            st = self.status
+            self.close()
+            raise OracleError(st)
+        G, C = ctypes.c_double(), ctypes.c_uint64()
+        L.ora_prep_scalars(self._h, ctypes.byref(G), ctypes.byref(C))
+        self.Gamma, self.C = G.value, C.value
+
+    def sample(self, seed: int, j0: int, j1: int, nthreads: int = 1, ris_mode: bool = False) -> Sketch:
+        L = lib()
+        return _take_sketch(L, L.ora_sample(self._h, seed, j0, j1, nthreads, int(ris_mode)), j0)
+
+    def q(self) -> np.ndarray:
+        q = np.zeros(self.n, np.float64)
+        lib().ora_prep_copy(self._h, None, _p(q), None, None, None)
+        return q
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ora_prep_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
 
 
 def inverse(n: int, sample_ptr, nodes):

@@ -115,31 +115,20 @@ int ora_validate(int32_t n, int64_t m, const int32_t *row_ptr, const int32_t *co
  * Eq. (gamma_v) and the bucket probabilities of Eq. (probn): per row v, the product P_e
  * of (1 - w) over the in-edges up to and including e, in CSR order.  q_v = P of the last
  * in-edge (1 for an empty row) is the singular probability, and gamma_v = 1 - q_v.
- * The paper defines these products over the reals; in binary64 they are formed in blocks
- * of ORA_PREFIX_BLOCK consecutive in-edges of the row: a running product within the
- * block (starting from the block's first factor), a carry that multiplies in each
- * finished block's total, and P_e = carry * (running product of e's block up to e), one
- * rounding per product.  A row of at most ORA_PREFIX_BLOCK in-edges is the plain
- * left-to-right product.
+ * The paper defines these products over the reals; in binary64 they are formed left to
+ * right, P_e = P_{e-1} * (1 - w_e) with P before the row's first edge equal to 1, one
+ * rounding per product.
  * ---------------------------------------------------------------------------------- */
-#define ORA_PREFIX_BLOCK 64
-
 void ora_row_prefix(int32_t n, const int32_t *row_ptr, const float *w, double *P, double *q)
 {
     for (int32_t v = 0; v < n; ++v) {
         const int32_t a = row_ptr[v], b = row_ptr[v + 1];
-        double carry = 1.0, local = 1.0;
+        double run = 1.0;
         for (int32_t e = a; e < b; ++e) {
-            const double f = 1.0 - (double)w[e];
-            if ((e - a) % ORA_PREFIX_BLOCK == 0) {
-                if (e > a) carry = carry * local; /* the finished block's total */
-                local = f;
-            } else {
-                local = local * f;
-            }
-            P[e] = carry * local;
+            run = run * (1.0 - (double)w[e]);
+            P[e] = run;
         }
-        q[v] = b > a ? P[b - 1] : 1.0;
+        q[v] = run;
     }
 }
 
@@ -400,50 +389,102 @@ void ora_sketch_free(ora_sketch *s)
     free(s);
 }
 
-/* Builds samples [j0, j1) with `nthreads` threads over contiguous id ranges; the result
- * does not depend on the thread count because sample j depends only on (graph, seed, j).
+/* ------------------------------------------------------------------------------------
+ * Alg. 2's preprocessing, done once per graph: validation, the prefix products P and q
+ * (Eq. gamma_v), Gamma, the integer root weights and the alias table (Eq. probu).  The
+ * graph arrays are borrowed and must outlive the object.
+ * ---------------------------------------------------------------------------------- */
+typedef struct {
+    int32_t n;
+    int64_t m;
+    const int32_t *row_ptr, *col;
+    const float *w;
+    double *P, *q;
+    uint64_t *W, *thr;
+    int32_t *alias;
+    double Gamma;
+    uint64_t C;
+    int status; /* ORA_OK, ORA_WDEGENERATE (Gamma = 0) or a negative error */
+} ora_prep;
+
+void ora_prep_free(ora_prep *p)
+{
+    if (!p) return;
+    free(p->P); free(p->q); free(p->W); free(p->thr); free(p->alias);
+    free(p);
+}
+
+ora_prep *ora_prepare(int32_t n, int64_t m, const int32_t *row_ptr, const int32_t *col, const float *w)
+{
+    ora_prep *p = (ora_prep *)calloc(1, sizeof(ora_prep));
+    if (!p) return NULL;
+    p->n = n; p->m = m; p->row_ptr = row_ptr; p->col = col; p->w = w;
+    p->status = ora_validate(n, m, row_ptr, col, w);
+    if (p->status) return p;
+    p->P = (double *)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
+    p->q = (double *)malloc(sizeof(double) * (size_t)n);
+    p->W = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
+    p->thr = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
+    p->alias = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    if (!p->P || !p->q || !p->W || !p->thr || !p->alias) { p->status = ORA_ENOMEM; return p; }
+    ora_row_prefix(n, row_ptr, w, p->P, p->q);
+    p->Gamma = ora_gamma_total(n, p->q);
+    p->C = ora_root_weights(n, p->q, p->W);
+    if (p->C == 0) { p->status = ORA_WDEGENERATE; return p; } /* no non-singular sample exists */
+    if (ora_alias_build(n, p->W, p->C, p->thr, p->alias)) p->status = ORA_ENOMEM;
+    return p;
+}
+
+int ora_prep_status(const ora_prep *p) { return p ? p->status : ORA_ENOMEM; }
+
+void ora_prep_scalars(const ora_prep *p, double *Gamma, uint64_t *C)
+{
+    *Gamma = p->Gamma;
+    *C = p->C;
+}
+
+/* Copies P[m], q[n], W[n], thr[n], alias[n] out of the preprocessing (any may be NULL). */
+void ora_prep_copy(const ora_prep *p, double *P, double *q, uint64_t *W, uint64_t *thr, int32_t *alias)
+{
+    const size_t n = (size_t)p->n, m = (size_t)p->m;
+    if (P && m) memcpy(P, p->P, sizeof(double) * m);
+    if (q) memcpy(q, p->q, sizeof(double) * n);
+    if (W) memcpy(W, p->W, sizeof(uint64_t) * n);
+    if (thr && p->C) memcpy(thr, p->thr, sizeof(uint64_t) * n);
+    if (alias && p->C) memcpy(alias, p->alias, sizeof(int32_t) * n);
+}
+
+/* Samples [j0, j1) with `nthreads` threads over contiguous id ranges; the result does not
+ * depend on the thread count because sample j depends only on (graph, seed, j).
  * ris_mode = 1 draws plain RIS samples instead (singular ones included). */
-ora_sketch *ora_build(int32_t n, int64_t m, const int32_t *row_ptr, const int32_t *col,
-                      const float *w, uint64_t seed, uint64_t j0, uint64_t j1, int nthreads,
-                      int ris_mode)
+ora_sketch *ora_sample(const ora_prep *p, uint64_t seed, uint64_t j0, uint64_t j1, int nthreads, int ris_mode)
 {
     ora_sketch *sk = (ora_sketch *)calloc(1, sizeof(ora_sketch));
     if (!sk) return NULL;
     sk->j0 = j0;
     sk->j1 = j1;
-    int st = ora_validate(n, m, row_ptr, col, w);
-    if (st) { sk->status = st; return sk; }
-
-    double *P = (double *)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
-    double *q = (double *)malloc(sizeof(double) * (size_t)n);
-    uint64_t *W = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
-    uint64_t *thr = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
-    int32_t *alias = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    if (p->status < 0) { sk->status = p->status; return sk; }
+    sk->Gamma = p->Gamma;
+    sk->C = p->C;
     uint64_t count = j1 > j0 ? j1 - j0 : 0;
+    int64_t *sizes = NULL;
     sk->sample_ptr = (int64_t *)calloc((size_t)count + 1, sizeof(int64_t));
     sk->roots = (int32_t *)malloc(sizeof(int32_t) * (size_t)(count ? count : 1));
     sk->probed = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(count ? count : 1));
-    int64_t *sizes = (int64_t *)malloc(sizeof(int64_t) * (size_t)(count ? count : 1));
-    if (!P || !q || !W || !thr || !alias || !sk->sample_ptr || !sk->roots || !sk->probed || !sizes) {
+    sizes = (int64_t *)malloc(sizeof(int64_t) * (size_t)(count ? count : 1));
+    if (!sk->sample_ptr || !sk->roots || !sk->probed || !sizes) {
         sk->status = ORA_ENOMEM;
         goto done;
     }
-    ora_row_prefix(n, row_ptr, w, P, q);
-    sk->Gamma = ora_gamma_total(n, q);
-    sk->C = ora_root_weights(n, q, W);
-    if (sk->C == 0 && !ris_mode) {
+    if (p->status == ORA_WDEGENERATE && !ris_mode) {
         /* No non-singular sample exists (Gamma = 0): an empty sketch. */
         sk->status = ORA_WDEGENERATE;
         sk->j1 = sk->j0;
         sk->nodes = (int32_t *)malloc(sizeof(int32_t));
         goto done;
     }
-    if (!ris_mode && ora_alias_build(n, W, sk->C, thr, alias)) {
-        sk->status = ORA_ENOMEM;
-        goto done;
-    }
     {
-        ora_ctx ctx = {n, row_ptr, col, w, P, q, thr, alias, sk->C, seed, ris_mode};
+        ora_ctx ctx = {p->n, p->row_ptr, p->col, p->w, p->P, p->q, p->thr, p->alias, p->C, seed, ris_mode};
         if (nthreads < 1) nthreads = 1;
         if ((uint64_t)nthreads > count && count > 0) nthreads = (int)count;
         ora_worker *wks = (ora_worker *)calloc((size_t)nthreads, sizeof(ora_worker));
@@ -487,7 +528,19 @@ ora_sketch *ora_build(int32_t n, int64_t m, const int32_t *row_ptr, const int32_
         free(tids);
     }
 done:
-    free(P); free(q); free(W); free(thr); free(alias); free(sizes);
+    free(sizes);
+    return sk;
+}
+
+/* Preprocessing and samples [j0, j1) in one call. */
+ora_sketch *ora_build(int32_t n, int64_t m, const int32_t *row_ptr, const int32_t *col,
+                      const float *w, uint64_t seed, uint64_t j0, uint64_t j1, int nthreads,
+                      int ris_mode)
+{
+    ora_prep *p = ora_prepare(n, m, row_ptr, col, w);
+    if (!p) return NULL;
+    ora_sketch *sk = ora_sample(p, seed, j0, j1, nthreads, ris_mode);
+    ora_prep_free(p);
     return sk;
 }
 

@@ -421,6 +421,8 @@ int skis_sketch_info(const skis_sketch *h, skis_info *info)
             info->tier_samples[t] = sk.tier_stats[t][0];
             info->tier_entries[t] = sk.tier_stats[t][1];
             info->tier_probed[t] = sk.tier_stats[t][2];
+            info->tier_swept[t] = sk.tier_stats[t][3];
+            info->tier_items[t] = sk.tier_stats[t][4];
         }
         return SKIS_OK;
     });

@@ -120,7 +120,8 @@ struct Sketch {
     uint64_t deferred_global = 0;                    // samples that reached the HBM tier
     uint32_t plain_levels = 0;                       // BFS level launches of the plain form
     uint32_t graph_replays = 0;                      // replays of the captured chain (captured form)
-    uint64_t tier_stats[3][3] = {};                  // per sampler tier: samples, entries, edges probed
+    uint64_t tier_stats[3][5] = {};                  // per sampler tier: samples, entries, edges probed,
+                                                     // edges and nodes the tier's launch expanded
 };
 
 // ---------------------------------------------------------------------------------

@@ -7,7 +7,7 @@ namespace skis {
 
 enum : int { ERR_ROWPTR = 1, ERR_COL = 2, ERR_SELFLOOP = 4, ERR_WEIGHT = 8 };
 
-constexpr int32_t LONG_ROW = 256; // rows above this length are taken by a whole wave
+constexpr int32_t LONG_ROW = 256; // rows above this length are taken by a whole workgroup
 
 __device__ __forceinline__ int check_edge(int32_t u, float wf, int64_t v, int32_t n)
 {
@@ -18,13 +18,11 @@ __device__ __forceinline__ int check_edge(int32_t u, float wf, int64_t v, int32_
     return bad;
 }
 
-// The products of a row (Eq. gamma_v / Eq. probn) are formed in blocks of PREFIX_BLOCK
-// consecutive in-edges: a running product within the block starting from its first factor
-// (1 - w), a carry that multiplies in each finished block's total, and
-// P[e] = carry * (running product of e's block up to e), one rounding per product (the
-// build disables contraction; __dmul_rn / __dsub_rn pin the operations).  A row of at most
-// PREFIX_BLOCK in-edges is the plain left-to-right product.  q[v] = the row's last P.
-constexpr int PREFIX_BLOCK = 64;
+// The products of a row (Eq. gamma_v / Eq. probn) are formed left to right:
+// P[e] = P[e-1] * (1 - w[e]) with 1 before the row's first edge, one rounding per product
+// (the build disables contraction; __dmul_rn / __dsub_rn pin the operations), and
+// q[v] = the row's last P (1 for an empty row).  A row's products are one dependent chain
+// of multiplies, so a long row is bound by the latency of that chain, not by bandwidth.
 
 // One thread per row: validates the row, writes the interleaved (col, w) records, P and q.
 // Rows longer than LONG_ROW are listed for k_prep_long.
@@ -52,7 +50,7 @@ __global__ __launch_bounds__(256) void k_prep_rows(int32_t n, int64_t m, const i
             if (bad) atomicOr(err, bad);
             continue;
         }
-        double carry = 1.0, local = 1.0, last = 1.0;
+        double run = 1.0;
         for (int32_t e = a; e < b; ++e) {
             const int32_t u = col[e];
             float wf = w[e];
@@ -60,33 +58,24 @@ __global__ __launch_bounds__(256) void k_prep_rows(int32_t n, int64_t m, const i
             if (wf == 0.0f) wf = 0.0f; // -0 -> +0: the coin reads the bits
             edges[e] = make_uint2((uint32_t)u, coin_threshold_hi(__float_as_uint(wf)));
             wbits[e] = __float_as_uint(wf);
-            const double f = __dsub_rn(1.0, (double)wf);
-            if ((e - a) % PREFIX_BLOCK == 0) {
-                if (e > a) carry = __dmul_rn(carry, local);
-                local = f;
-            } else {
-                local = __dmul_rn(local, f);
-            }
-            last = __dmul_rn(carry, local);
-            P[e] = last;
+            run = __dmul_rn(run, __dsub_rn(1.0, (double)wf));
+            P[e] = run;
         }
-        q[v] = last;
+        q[v] = run;
         if (bad) atomicOr(err, bad);
     }
 }
 
-// One 256-thread workgroup per long row, LONG_CHUNK blocks of PREFIX_BLOCK in-edges (LONG_EDGES
-// edges) at a time, every global access coalesced: (1) each thread loads, validates and writes
-// LONG_PER edges and puts their factors (1 - w) in LDS; (2) thread b < LONG_CHUNK replaces the
-// factors of block b by the running product within the block; (3) thread 0 carries the product
-// through the chunk's block totals in row order; (4) each thread writes P = carry * running
-// product for its LONG_PER edges.  The carry after the last block is q[v].  LDS rows of
-// PREFIX_BLOCK doubles are padded by one so that the threads of (2) do not share banks.
-constexpr int LONG_CHUNK = 64;
-constexpr int LONG_EDGES = LONG_CHUNK * PREFIX_BLOCK; // 4096
+// One 256-thread workgroup per long row, LONG_EDGES in-edges at a time, every global access
+// coalesced: (1) each thread loads, validates and writes LONG_PER edges and puts their
+// factors (1 - w) in LDS (1.0 past the row's end: a multiply by 1 is exact); (2) lane 0
+// carries the row's running product through the chunk, CHAIN_BATCH factors at a time held
+// in registers with the next batch's LDS reads issued before the multiplies, so that the
+// loop's critical path is the dependent multiplies alone; (3) every thread writes its
+// LONG_PER products out.  The next chunk's edge loads are in flight during (2).
+constexpr int LONG_EDGES = 4096;
 constexpr int LONG_PER = LONG_EDGES / 256;
-
-__device__ __forceinline__ int long_slot(int i) { return i + i / PREFIX_BLOCK; }
+constexpr int CHAIN_BATCH = 16;
 
 __global__ __launch_bounds__(256) void k_prep_long(int32_t n, const int32_t *__restrict__ row_ptr,
                                                    const int32_t *__restrict__ col, const float *__restrict__ w,
@@ -95,11 +84,12 @@ __global__ __launch_bounds__(256) void k_prep_long(int32_t n, const int32_t *__r
                                                    const int32_t *__restrict__ long_rows,
                                                    const unsigned int *__restrict__ n_long)
 {
-    __shared__ double s_f[LONG_EDGES + LONG_CHUNK];
-    __shared__ double s_tot[LONG_CHUNK], s_carry[LONG_CHUNK];
+    __shared__ double s_f[LONG_EDGES + CHAIN_BATCH]; // factors of the chunk (+ one batch read ahead)
+    __shared__ double s_p[LONG_EDGES];               // their running products
     __shared__ double s_run;
     const int t = threadIdx.x;
     const unsigned int cnt = *n_long;
+    if (t < CHAIN_BATCH) s_f[LONG_EDGES + t] = 1.0;
     for (unsigned int r = blockIdx.x; r < cnt; r += gridDim.x) {
         const int32_t v = long_rows[r];
         const int32_t a = row_ptr[v], b = row_ptr[v + 1];
@@ -117,85 +107,59 @@ __global__ __launch_bounds__(256) void k_prep_long(int32_t n, const int32_t *__r
             wc[k] = w[e];
         }
         for (int32_t c0 = a; c0 < b; c0 += LONG_EDGES) {
-            // (1) this chunk's edges, then the next chunk's loads
-            int32_t un[LONG_PER];
-            float wn[LONG_PER];
+            // (1) this chunk's edges and factors, then the next chunk's loads
 #pragma unroll
             for (int k = 0; k < LONG_PER; ++k) {
                 const int32_t e = c0 + k * 256 + t;
+                double f = 1.0;
                 if (e < b) {
                     float wf = wc[k];
                     bad |= check_edge(uc[k], wf, v, n);
                     if (wf == 0.0f) wf = 0.0f; // -0 -> +0: the coin reads the bits
                     edges[e] = make_uint2((uint32_t)uc[k], coin_threshold_hi(__float_as_uint(wf)));
                     wbits[e] = __float_as_uint(wf);
-                    s_f[long_slot(k * 256 + t)] = __dsub_rn(1.0, (double)wf);
+                    f = __dsub_rn(1.0, (double)wf);
                 }
+                s_f[k * 256 + t] = f;
             }
 #pragma unroll
             for (int k = 0; k < LONG_PER; ++k) {
                 const int32_t e = min(c0 + LONG_EDGES + k * 256 + t, b - 1);
-                un[k] = col[e];
-                wn[k] = w[e];
+                uc[k] = col[e];
+                wc[k] = w[e];
             }
             __syncthreads();
             const int len = min(b - c0, LONG_EDGES);
-            const int nb = (len + PREFIX_BLOCK - 1) / PREFIX_BLOCK;
-            // (2) running products within the blocks
-            if (t < nb) { // the block's factors go to registers first: only the multiplies chain
-                const int i0 = t * PREFIX_BLOCK, cntb = min(len - i0, PREFIX_BLOCK);
-                double f[PREFIX_BLOCK];
-#pragma unroll
-                for (int i = 0; i < PREFIX_BLOCK; ++i) f[i] = i < cntb ? s_f[long_slot(i0 + i)] : 1.0;
-                double local = f[0];
-#pragma unroll
-                for (int i = 1; i < PREFIX_BLOCK; ++i) {
-                    if (i < cntb) local = __dmul_rn(local, f[i]);
-                    f[i] = local;
-                }
-#pragma unroll
-                for (int i = 1; i < PREFIX_BLOCK; ++i)
-                    if (i < cntb) s_f[long_slot(i0 + i)] = f[i];
-                s_tot[t] = local;
-            }
-            __syncthreads();
-            // (3) carries; the row's block 0 has carry 1 (its products are final)
+            // (2) the chain, in row order
             if (t == 0) {
-                double tot[LONG_CHUNK];
-#pragma unroll
-                for (int k = 0; k < LONG_CHUNK; ++k) tot[k] = k < nb ? s_tot[k] : 1.0;
                 double run = s_run;
+                double fc[CHAIN_BATCH];
 #pragma unroll
-                for (int k = 0; k < LONG_CHUNK; ++k) {
-                    if (k < nb) {
-                        const double c = run;
-                        run = (c0 == a && k == 0) ? tot[0] : __dmul_rn(run, tot[k]);
-                        tot[k] = c;
+                for (int k = 0; k < CHAIN_BATCH; ++k) fc[k] = s_f[k];
+                for (int i0 = 0; i0 < len; i0 += CHAIN_BATCH) {
+                    double fn[CHAIN_BATCH];
+#pragma unroll
+                    for (int k = 0; k < CHAIN_BATCH; ++k) fn[k] = s_f[i0 + CHAIN_BATCH + k];
+#pragma unroll
+                    for (int k = 0; k < CHAIN_BATCH; ++k) {
+                        run = __dmul_rn(run, fc[k]);
+                        s_p[i0 + k] = run;
                     }
-                }
 #pragma unroll
-                for (int k = 0; k < LONG_CHUNK; ++k)
-                    if (k < nb) s_carry[k] = tot[k];
+                    for (int k = 0; k < CHAIN_BATCH; ++k) fc[k] = fn[k];
+                }
                 s_run = run;
             }
             __syncthreads();
-            // (4) P = carry * running product
+            // (3) the products out (s_f is rewritten by the next chunk's (1) only after every
+            // lane has passed the barrier above; s_p by its (2) only after the next barrier)
 #pragma unroll
             for (int k = 0; k < LONG_PER; ++k) {
                 const int i = k * 256 + t;
-                if (i < len) {
-                    const double l = s_f[long_slot(i)];
-                    const int blk = i / PREFIX_BLOCK;
-                    P[c0 + i] = (c0 == a && blk == 0) ? l : __dmul_rn(s_carry[blk], l);
-                }
-            }
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < LONG_PER; ++k) {
-                uc[k] = un[k];
-                wc[k] = wn[k];
+                if (i < len) P[c0 + i] = s_p[i];
             }
         }
+        __syncthreads();
         if (t == 0) q[v] = s_run;
         if (bad) atomicOr(err, bad);
         __syncthreads();

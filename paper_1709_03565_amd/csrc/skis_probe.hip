@@ -1,6 +1,7 @@
 // skis_probe.hip -- random-read bandwidth probe: the achievable HBM bandwidth of uniformly
 // random reads of one row size, the ceiling against which the sampler's random-access
-// kernels are measured (they read 8-byte row bounds and 32-byte edge quads at random).
+// kernels are measured (they read 8-byte row bounds and 32-byte edge quads at random; a
+// cache line is 128 bytes).
 #include <hip/hip_runtime.h>
 
 #include "skis_internal.h"
@@ -46,24 +47,25 @@ __device__ __forceinline__ uint32_t probe_read(const unsigned char *table, uint3
 // Each thread takes reads i = gid, gid + stride, ...; four independent rows are in flight
 // per thread and iteration.  The rows' words are folded into one value that is stored only
 // if it equals a fixed constant, which keeps the loads without writing anything in practice.
+// The read index is 64-bit, so the loop ends for every accepted count (reads < 2^32).
 template <int ROWB>
 __global__ __launch_bounds__(256) void k_probe_random_read(const unsigned char *table, uint32_t rows,
-                                                           uint32_t reads, uint32_t seed, uint32_t *sink)
+                                                           uint64_t reads, uint32_t seed, uint32_t *sink)
 {
-    constexpr uint32_t U = 4;
-    const uint32_t stride = gridDim.x * blockDim.x;
-    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    constexpr uint64_t U = 4;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t acc = 0u;
-    for (; (uint64_t)i + (U - 1) * (uint64_t)stride < reads; i += U * stride) {
+    for (; i + (U - 1) * stride < reads; i += U * stride) {
         uint32_t r[U], v[U];
 #pragma unroll
-        for (uint32_t k = 0; k < U; ++k) r[k] = probe_row(i + k * stride, seed, rows);
+        for (uint32_t k = 0; k < U; ++k) r[k] = probe_row((uint32_t)(i + k * stride), seed, rows);
 #pragma unroll
         for (uint32_t k = 0; k < U; ++k) v[k] = probe_read<ROWB>(table, r[k]);
 #pragma unroll
         for (uint32_t k = 0; k < U; ++k) acc ^= v[k];
     }
-    for (; i < reads; i += stride) acc ^= probe_read<ROWB>(table, probe_row(i, seed, rows));
+    for (; i < reads; i += stride) acc ^= probe_read<ROWB>(table, probe_row((uint32_t)i, seed, rows));
     if (acc == 0x9E3779B9u) sink[0] = acc;
 }
 
@@ -76,14 +78,16 @@ void probe_random_read(const void *table, uint64_t rows, uint32_t row_bytes, uin
     if ((reinterpret_cast<uintptr_t>(table) & 15u) != 0) throw Error{SKIS_EINVAL, "table must be 16-byte aligned"};
     if (reads == 0) return;
     const unsigned grid = (unsigned)device_cu_count() * 16u;
-    const uint32_t nr = (uint32_t)rows, nreads = (uint32_t)reads;
+    const uint32_t nr = (uint32_t)rows;
+    const uint64_t nreads = reads;
     const unsigned char *t = static_cast<const unsigned char *>(table);
     switch (row_bytes) {
     case 8: hipLaunchKernelGGL(k_probe_random_read<8>, dim3(grid), dim3(256), 0, s, t, nr, nreads, seed, sink); break;
     case 16: hipLaunchKernelGGL(k_probe_random_read<16>, dim3(grid), dim3(256), 0, s, t, nr, nreads, seed, sink); break;
     case 32: hipLaunchKernelGGL(k_probe_random_read<32>, dim3(grid), dim3(256), 0, s, t, nr, nreads, seed, sink); break;
     case 64: hipLaunchKernelGGL(k_probe_random_read<64>, dim3(grid), dim3(256), 0, s, t, nr, nreads, seed, sink); break;
-    default: throw Error{SKIS_EINVAL, "row_bytes must be 8, 16, 32 or 64"};
+    case 128: hipLaunchKernelGGL(k_probe_random_read<128>, dim3(grid), dim3(256), 0, s, t, nr, nreads, seed, sink); break;
+    default: throw Error{SKIS_EINVAL, "row_bytes must be 8, 16, 32, 64 or 128"};
     }
     SKIS_HIP_TRY(hipGetLastError());
 }

@@ -12,40 +12,6 @@ constexpr int EST_WALK = 4;       // sample-list entries a thread walks per roun
 
 constexpr int GREEDY_HOT = 2048;  // hot nodes decremented in LDS
 
-// Heavy sets: a set whose sample lists hold more than EST_SPLIT entries in all is walked by
-// many workgroups in chunks of EST_CHUNK entries; at most EST_NSPLIT such sets per launch
-// (the others walk in their own workgroup).
-// The split walk is switched off: a test run through it stopped making progress and the
-// cause has not been found, so every set walks in its own workgroup until it is.
-constexpr bool EST_SPLIT_ENABLED = false;
-constexpr int64_t EST_SPLIT = 32768;
-constexpr int64_t EST_CHUNK = 16384;
-constexpr int EST_NSPLIT = 64;
-
-struct SplitRec {
-    int64_t qi;                 // the set's index in the launch's CSR
-    int64_t E;                  // entries to walk
-    unsigned long long cov;     // flips counted so far
-    double qsum;                // compensated sum of q over the distinct members
-    int32_t nu;                 // distinct members
-    uint32_t bitmap;            // index of the set's bitmap
-};
-
-struct EstSplit {
-    unsigned count;                 // sets parked in this launch
-    unsigned done;                  // workgroups of k_est_split_finish that have finished
-    unsigned long long next_unit;   // next chunk to take
-    int32_t *members;               // [EST_NSPLIT][EST_MAX_SET] distinct members, ascending
-    int64_t *dbase;                 // [EST_NSPLIT][EST_MAX_SET + 1] prefix of their deg_H
-    SplitRec rec[EST_NSPLIT];
-};
-
-struct SplitScratch {
-    DevBuf<EstSplit> hdr;
-    DevBuf<int32_t> members;
-    DevBuf<int64_t> dbase;
-};
-
 struct GreedyState {
     unsigned done;              // blocks of k_greedy_argmax that have finished
     int32_t vstar;              // this round's pick (-1: none left)
@@ -68,7 +34,6 @@ struct QueryScratch {
     DevBuf<uint32_t> bitmaps;
     uint64_t bitmap_words = 0;
     DevBuf<int> err;
-    SplitScratch split;
 };
 
 void estimate_batch(const Sketch &sk, QueryScratch &qs, int32_t Q, const int64_t *set_ptr, const int32_t *set_nodes,
@@ -78,18 +43,18 @@ void estimate_batch(const Sketch &sk, QueryScratch &qs, int32_t Q, const int64_t
 // indexes into the CSR) take the chunked path with one node bitmap of n bits each in
 // nodebits.  bitmaps holds a zeroed bitmap of bitmap_words words for every workgroup
 // (max(nq, nlarge) of them) and is left zeroed.  Stream-ordered; no host synchronisation.
-// With split non-null, heavy sets are parked by the per-set launch and walked by
-// walk_blocks workgroups of k_est_split_walk, then finished (two more launches); with
-// split null every set walks in its own workgroup.
 void estimate_launch(const Sketch &sk, int32_t nq, const int64_t *set_ptr, const int32_t *set_nodes,
                      const int64_t *large, int32_t nlarge, uint32_t *bitmaps, uint64_t bitmap_words,
-                     uint32_t *nodebits, unsigned long long *cov, double *est, int *err, EstSplit *split,
-                     unsigned walk_blocks, hipStream_t s);
-// Allocates the split scratch (zeroed counters) on the arena.
-void split_init(Arena &arena, SplitScratch &sc, hipStream_t s);
-// The walk and finish launches for the sets parked by the preceding k_estimate launch.
-void split_launch(const Sketch &sk, EstSplit *split, unsigned walk_blocks, uint32_t *bitmaps, uint64_t bitmap_words,
-                  unsigned long long *cov, double *est, hipStream_t s);
+                     uint32_t *nodebits, unsigned long long *cov, double *est, int *err, hipStream_t s);
+// The two launches of estimate_launch on their own: sets q0 .. q0+nq-1 of the CSR (those of
+// at most EST_MAX_SET entries; set q0+b uses bitmap b), and the ng large sets listed in
+// qlist[g0 .. g0+ng) (set qlist[g0+b] uses bitmap b and node bitmap b).  Stream-ordered.
+void estimate_launch_small(const Sketch &sk, int64_t q0, int32_t nq, const int64_t *set_ptr,
+                           const int32_t *set_nodes, uint32_t *bitmaps, uint64_t bitmap_words,
+                           unsigned long long *cov, double *est, int *err, hipStream_t s);
+void estimate_launch_large(const Sketch &sk, const int64_t *qlist, int64_t g0, int32_t ng, const int64_t *set_ptr,
+                           const int32_t *set_nodes, uint32_t *bitmaps, uint64_t bitmap_words, uint32_t *nodebits,
+                           unsigned long long *cov, double *est, int *err, hipStream_t s);
 // Zero-fills count words with a kernel (capturable, unlike a memset node).
 void fill_u32(uint32_t *p, uint64_t count, hipStream_t s);
 void greedy(const Sketch &sk, QueryScratch &qs, int32_t k, int32_t *seeds, uint64_t *marg, uint64_t *cov_out,

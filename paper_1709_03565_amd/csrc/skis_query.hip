@@ -89,8 +89,7 @@ __global__ __launch_bounds__(EST_BLOCK) void k_estimate(const int64_t *__restric
                                                         uint32_t *__restrict__ bitmaps, uint64_t wordsT,
                                                         uint32_t *__restrict__ nodebits, uint64_t wordsN,
                                                         unsigned long long *__restrict__ cov_out,
-                                                        double *__restrict__ est_out, int *__restrict__ err,
-                                                        EstSplit *__restrict__ split)
+                                                        double *__restrict__ est_out, int *__restrict__ err)
 {
     __shared__ int32_t buf[EST_MAX_SET];
     __shared__ int64_t dbase[EST_MAX_SET + 1];
@@ -99,7 +98,6 @@ __global__ __launch_bounds__(EST_BLOCK) void k_estimate(const int64_t *__restric
     __shared__ double ps[EST_BLOCK], pc[EST_BLOCK];
     __shared__ unsigned long long s_cov[EST_BLOCK / 64];
     __shared__ int s_bad;
-    __shared__ unsigned s_split;
 
     const int64_t qi = LARGE ? qlist[q0 + blockIdx.x] : q0 + blockIdx.x;
     const int tid = threadIdx.x;
@@ -118,7 +116,6 @@ __global__ __launch_bounds__(EST_BLOCK) void k_estimate(const int64_t *__restric
     unsigned long long local = 0;
     int nu = 0, maxnu = 0; // maxnu: threads at or past it never took a member (their sums are +0)
     int64_t E = 0;
-    unsigned parked = EST_NSPLIT; // < EST_NSPLIT: the walk was handed to k_est_split_walk
     for (int64_t c0 = a; c0 < b; c0 += EST_MAX_SET) {
         const int kc = (int)((b - c0) < EST_MAX_SET ? (b - c0) : EST_MAX_SET);
         if (tid == 0) s_bad = 0;
@@ -189,27 +186,6 @@ __global__ __launch_bounds__(EST_BLOCK) void k_estimate(const int64_t *__restric
         }
         if (tid == 0) dbase[nu] = E;
         __syncthreads();
-        if (!LARGE && split && E > EST_SPLIT) {
-            // a heavy set: park its members and prefix so that many workgroups walk it
-            if (tid == 0) s_split = atomicAdd(&split->count, 1u);
-            __syncthreads();
-            parked = s_split;
-            if (parked < EST_NSPLIT) {
-                int32_t *pm = split->members + (size_t)parked * EST_MAX_SET;
-                int64_t *pd = split->dbase + (size_t)parked * (EST_MAX_SET + 1);
-                for (int t = tid; t < nu; t += EST_BLOCK) pm[t] = buf[t];
-                for (int t = tid; t <= nu; t += EST_BLOCK) pd[t] = dbase[t];
-                if (tid == 0) {
-                    SplitRec &r = split->rec[parked];
-                    r.qi = qi;
-                    r.nu = nu;
-                    r.E = E;
-                    r.bitmap = blockIdx.x;
-                    r.cov = 0ull;
-                }
-                E = 0; // nothing to walk here
-            }
-        }
         // EST_WALK entries per thread and round, their loads issued together; a wave takes 64
         // consecutive entries and flips their bits with one atomic per bitmap word it meets.
         // The rounds are the same for the whole wave (the flips shuffle across it); a lane past
@@ -255,13 +231,9 @@ __global__ __launch_bounds__(EST_BLOCK) void k_estimate(const int64_t *__restric
             neumaier_add(s, cc, ps[t]);
             neumaier_add(s, cc, pc[t]);
         }
-        if (parked < EST_NSPLIT) {
-            split->rec[parked].qsum = __dadd_rn(s, cc); // k_est_split_finish writes the outputs
-        } else {
-            const double first = T > 0 ? __ddiv_rn(__dmul_rn((double)c, Gamma), (double)T) : 0.0;
-            cov_out[qi] = c;
-            est_out[qi] = __dadd_rn(first, __dadd_rn(s, cc));
-        }
+        const double first = T > 0 ? __ddiv_rn(__dmul_rn((double)c, Gamma), (double)T) : 0.0;
+        cov_out[qi] = c;
+        est_out[qi] = __dadd_rn(first, __dadd_rn(s, cc));
     }
     // leave the bitmaps clear for the next query
     if (LARGE) {
@@ -296,110 +268,6 @@ __global__ __launch_bounds__(EST_BLOCK) void k_estimate(const int64_t *__restric
                 if ((threadIdx.x & 63) == 63 || nw != w) bm[w] = 0u;
             }
         }
-    }
-}
-
-// ---------------------------------------------------------------------------------------
-// Heavy sets: the parked sets' sample lists, Sum deg_H(v) entries each, are cut into
-// chunks of EST_CHUNK entries; workgroups take chunks from a counter until none is left and
-// flip the set's bitmap bits, adding the flips to the set's count.  Each entry is tested by
-// one atomicOr, so a sample is counted once however the chunks are spread.
-// ---------------------------------------------------------------------------------------
-__global__ __launch_bounds__(EST_BLOCK) void k_est_split_walk(EstSplit *__restrict__ sp,
-                                                              const int64_t *__restrict__ node_ptr,
-                                                              const int32_t *__restrict__ node_samples,
-                                                              uint32_t *__restrict__ bitmaps, uint64_t wordsT)
-{
-    __shared__ int64_t ubase[EST_NSPLIT + 1];
-    __shared__ int64_t db[EST_MAX_SET + 1];
-    __shared__ int32_t mem[EST_MAX_SET];
-    __shared__ long long s_u;
-    __shared__ int s_cur;
-    __shared__ unsigned long long s_cov[EST_BLOCK / 64];
-    static_assert(EST_NSPLIT < EST_BLOCK, "one thread per parked set");
-    const int tid = threadIdx.x;
-    const int ns = (int)min(sp->count, (unsigned)EST_NSPLIT);
-    if (tid < ns) ubase[tid + 1] = (sp->rec[tid].E + EST_CHUNK - 1) / EST_CHUNK; // chunks of set tid
-    __syncthreads();
-    if (tid == 0) {
-        ubase[0] = 0;
-        for (int k = 0; k < ns; ++k) ubase[k + 1] += ubase[k];
-        s_cur = -1;
-    }
-    __syncthreads();
-    for (;;) {
-        if (tid == 0) s_u = (long long)atomicAdd(&sp->next_unit, 1ull);
-        __syncthreads();
-        const int64_t u = s_u;
-        if (u >= ubase[ns]) break;
-        int k = 0;
-        while (ubase[k + 1] <= u) ++k;
-        const SplitRec &r = sp->rec[k];
-        const int nu = r.nu;
-        if (s_cur != k) { // this set's members and prefix into LDS
-            for (int t = tid; t < nu; t += EST_BLOCK) mem[t] = sp->members[(size_t)k * EST_MAX_SET + t];
-            for (int t = tid; t <= nu; t += EST_BLOCK) db[t] = sp->dbase[(size_t)k * (EST_MAX_SET + 1) + t];
-        }
-        __syncthreads();
-        if (tid == 0) s_cur = k;
-        const int64_t e0 = (u - ubase[k]) * EST_CHUNK;
-        const int64_t e1 = min(r.E, e0 + (int64_t)EST_CHUNK);
-        uint32_t *bm = bitmaps + (uint64_t)r.bitmap * wordsT;
-        unsigned long long local = 0;
-        for (int64_t idx = e0 + tid; idx < e1; idx += EST_BLOCK) {
-            int lo = 0, hi = nu - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (db[mid] <= idx) lo = mid; else hi = mid - 1;
-            }
-            const int32_t v = mem[lo];
-            const int32_t j = node_samples[node_ptr[v] + (idx - db[lo])];
-            const uint32_t bit = 1u << (j & 31);
-            if (!(atomicOr(&bm[j >> 5], bit) & bit)) ++local;
-        }
-        local = wave_sum(local);
-        if ((tid & 63) == 0) s_cov[tid >> 6] = local;
-        __syncthreads();
-        if (tid == 0) {
-            unsigned long long c = 0;
-            for (int w = 0; w < EST_BLOCK / 64; ++w) c += s_cov[w];
-            if (c) atomicAdd(&sp->rec[k].cov, c);
-        }
-    }
-}
-
-// Outputs of the parked sets (the same roundings as k_estimate), their bitmaps zeroed
-// whole, and the split record reset by the last workgroup for the next launch.
-__global__ __launch_bounds__(256) void k_est_split_finish(EstSplit *__restrict__ sp, uint64_t T, double Gamma,
-                                                          uint32_t *__restrict__ bitmaps, uint64_t wordsT,
-                                                          unsigned long long *__restrict__ cov_out,
-                                                          double *__restrict__ est_out)
-{
-    __shared__ bool last;
-    const unsigned ns = min(sp->count, (unsigned)EST_NSPLIT);
-    for (unsigned k = 0; k < ns; ++k) {
-        uint32_t *bm = bitmaps + (uint64_t)sp->rec[k].bitmap * wordsT;
-        for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < wordsT; w += (uint64_t)gridDim.x * blockDim.x)
-            bm[w] = 0u;
-    }
-    if (blockIdx.x == 0)
-        for (unsigned k = threadIdx.x; k < ns; k += blockDim.x) {
-            const SplitRec &r = sp->rec[k];
-            const unsigned long long c = __hip_atomic_load(&sp->rec[k].cov, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const double first = T > 0 ? __ddiv_rn(__dmul_rn((double)c, Gamma), (double)T) : 0.0;
-            cov_out[r.qi] = c;
-            est_out[r.qi] = __dadd_rn(first, r.qsum);
-        }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        last = atomicAdd(&sp->done, 1u) == gridDim.x - 1;
-    }
-    __syncthreads();
-    if (last && threadIdx.x == 0) {
-        sp->count = 0u;
-        sp->next_unit = 0ull;
-        sp->done = 0u;
     }
 }
 
@@ -804,19 +672,14 @@ void estimate_batch(const Sketch &sk, QueryScratch &qs, int32_t Q, const int64_t
         SKIS_HIP_TRY(hipGetLastError());
     }
     if (!qs.err.ptr) qs.err.alloc(arena, 1);
-    if (EST_SPLIT_ENABLED && !qs.split.hdr.ptr) split_init(arena, qs.split, s);
     hipLaunchKernelGGL(k_fill_q<int>, dim3(1), dim3(64), 0, s, (uint64_t)1, qs.err.ptr, 0);
     for (int64_t q0 = 0; q0 < Q; q0 += (int64_t)batch) {
         const int64_t nq = (Q - q0) < (int64_t)batch ? (Q - q0) : (int64_t)batch;
         hipLaunchKernelGGL(k_estimate<false>, dim3((unsigned)nq), dim3(EST_BLOCK), 0, s, (const int64_t *)nullptr, q0,
                            set_ptr, set_nodes, sk.n, sk.T, sk.Gamma, sk.q.ptr, sk.node_ptr.ptr, sk.node_samples.ptr,
                            qs.bitmaps.ptr, per, (uint32_t *)nullptr, (uint64_t)0,
-                           reinterpret_cast<unsigned long long *>(cov), est, qs.err.ptr,
-                           EST_SPLIT_ENABLED ? qs.split.hdr.ptr : nullptr);
+                           reinterpret_cast<unsigned long long *>(cov), est, qs.err.ptr);
         SKIS_HIP_TRY(hipGetLastError());
-        if (EST_SPLIT_ENABLED)
-            split_launch(sk, qs.split.hdr.ptr, gridq(1ull << 30, EST_BLOCK, 2), qs.bitmaps.ptr, per,
-                         reinterpret_cast<unsigned long long *>(cov), est, s);
     }
     if (!large.empty()) {
         const uint64_t wordsN = ((uint64_t)sk.n + 31) / 32;
@@ -833,8 +696,7 @@ void estimate_batch(const Sketch &sk, QueryScratch &qs, int32_t Q, const int64_t
             hipLaunchKernelGGL(k_estimate<true>, dim3((unsigned)ng), dim3(EST_BLOCK), 0, s,
                                (const int64_t *)qlist.ptr, (int64_t)g0, set_ptr, set_nodes, sk.n, sk.T, sk.Gamma,
                                sk.q.ptr, sk.node_ptr.ptr, sk.node_samples.ptr, qs.bitmaps.ptr, per, nodebits.ptr,
-                               wordsN, reinterpret_cast<unsigned long long *>(cov), est, qs.err.ptr,
-                               (EstSplit *)nullptr);
+                               wordsN, reinterpret_cast<unsigned long long *>(cov), est, qs.err.ptr);
             SKIS_HIP_TRY(hipGetLastError());
         }
         SKIS_HIP_TRY(hipStreamSynchronize(s));
@@ -852,51 +714,47 @@ void estimate_batch(const Sketch &sk, QueryScratch &qs, int32_t Q, const int64_t
     if (herr & 4) throw Error{SKIS_EINVAL, "a seed set holds a node id outside [0, n)"};
 }
 
-void split_init(Arena &arena, SplitScratch &sc, hipStream_t s)
-{
-    sc.members.alloc(arena, (size_t)EST_NSPLIT * EST_MAX_SET);
-    sc.dbase.alloc(arena, (size_t)EST_NSPLIT * (EST_MAX_SET + 1));
-    sc.hdr.alloc(arena, 1);
-    EstSplit h{};
-    h.members = sc.members.ptr;
-    h.dbase = sc.dbase.ptr;
-    SKIS_HIP_TRY(hipMemcpyAsync(sc.hdr.ptr, &h, sizeof(h), hipMemcpyHostToDevice, s));
-    SKIS_HIP_TRY(hipStreamSynchronize(s));
-}
-
-void split_launch(const Sketch &sk, EstSplit *split, unsigned walk_blocks, uint32_t *bitmaps, uint64_t bitmap_words,
-                  unsigned long long *cov, double *est, hipStream_t s)
-{
-    if (!split) return;
-    hipLaunchKernelGGL(k_est_split_walk, dim3(walk_blocks ? walk_blocks : 1), dim3(EST_BLOCK), 0, s, split,
-                       sk.node_ptr.ptr, sk.node_samples.ptr, bitmaps, bitmap_words);
-    SKIS_HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_est_split_finish, dim3(gridq(1ull << 30, 256, 1)), dim3(256), 0, s, split, sk.T, sk.Gamma,
-                       bitmaps, bitmap_words, cov, est);
-    SKIS_HIP_TRY(hipGetLastError());
-}
-
 void estimate_launch(const Sketch &sk, int32_t nq, const int64_t *set_ptr, const int32_t *set_nodes,
                      const int64_t *large, int32_t nlarge, uint32_t *bitmaps, uint64_t bitmap_words,
-                     uint32_t *nodebits, unsigned long long *cov, double *est, int *err, EstSplit *split,
-                     unsigned walk_blocks, hipStream_t s)
+                     uint32_t *nodebits, unsigned long long *cov, double *est, int *err, hipStream_t s)
 {
     const uint64_t per = bitmap_words;
-    if (!EST_SPLIT_ENABLED) split = nullptr;
     if (nq > 0) {
         hipLaunchKernelGGL(k_estimate<false>, dim3((unsigned)nq), dim3(EST_BLOCK), 0, s, (const int64_t *)nullptr,
                            (int64_t)0, set_ptr, set_nodes, sk.n, sk.T, sk.Gamma, sk.q.ptr, sk.node_ptr.ptr,
-                           sk.node_samples.ptr, bitmaps, per, (uint32_t *)nullptr, (uint64_t)0, cov, est, err, split);
+                           sk.node_samples.ptr, bitmaps, per, (uint32_t *)nullptr, (uint64_t)0, cov, est, err);
         SKIS_HIP_TRY(hipGetLastError());
-        split_launch(sk, split, walk_blocks, bitmaps, per, cov, est, s);
     }
     if (nlarge > 0) {
         const uint64_t wordsN = ((uint64_t)sk.n + 31) / 32;
         hipLaunchKernelGGL(k_estimate<true>, dim3((unsigned)nlarge), dim3(EST_BLOCK), 0, s, large, (int64_t)0,
                            set_ptr, set_nodes, sk.n, sk.T, sk.Gamma, sk.q.ptr, sk.node_ptr.ptr, sk.node_samples.ptr,
-                           bitmaps, per, nodebits, wordsN, cov, est, err, (EstSplit *)nullptr);
+                           bitmaps, per, nodebits, wordsN, cov, est, err);
         SKIS_HIP_TRY(hipGetLastError());
     }
+}
+
+void estimate_launch_small(const Sketch &sk, int64_t q0, int32_t nq, const int64_t *set_ptr,
+                           const int32_t *set_nodes, uint32_t *bitmaps, uint64_t bitmap_words,
+                           unsigned long long *cov, double *est, int *err, hipStream_t s)
+{
+    if (nq <= 0) return;
+    hipLaunchKernelGGL(k_estimate<false>, dim3((unsigned)nq), dim3(EST_BLOCK), 0, s, (const int64_t *)nullptr, q0,
+                       set_ptr, set_nodes, sk.n, sk.T, sk.Gamma, sk.q.ptr, sk.node_ptr.ptr, sk.node_samples.ptr,
+                       bitmaps, bitmap_words, (uint32_t *)nullptr, (uint64_t)0, cov, est, err);
+    SKIS_HIP_TRY(hipGetLastError());
+}
+
+void estimate_launch_large(const Sketch &sk, const int64_t *qlist, int64_t g0, int32_t ng, const int64_t *set_ptr,
+                           const int32_t *set_nodes, uint32_t *bitmaps, uint64_t bitmap_words, uint32_t *nodebits,
+                           unsigned long long *cov, double *est, int *err, hipStream_t s)
+{
+    if (ng <= 0) return;
+    const uint64_t wordsN = ((uint64_t)sk.n + 31) / 32;
+    hipLaunchKernelGGL(k_estimate<true>, dim3((unsigned)ng), dim3(EST_BLOCK), 0, s, qlist, g0, set_ptr, set_nodes,
+                       sk.n, sk.T, sk.Gamma, sk.q.ptr, sk.node_ptr.ptr, sk.node_samples.ptr, bitmaps, bitmap_words,
+                       nodebits, wordsN, cov, est, err);
+    SKIS_HIP_TRY(hipGetLastError());
 }
 
 void fill_u32(uint32_t *p, uint64_t count, hipStream_t s)

@@ -26,8 +26,8 @@ namespace skis {
 
 constexpr uint32_t DEFERRED = 0xFFFFFFFFu;
 constexpr int SMALL_SORT = 1024;   // sizes up to this are sorted in registers by k_gather_sort
-constexpr int SORT_LDS_MAX = 8192; // sizes up to this are sorted in LDS by k_gather_medium;
-                                   // larger ones are written already sorted by the global tier
+constexpr int SORT_LDS_MAX = 8192; // sizes up to this are sorted in LDS by k_gather_medium,
+                                   // larger ones through a node bitmap by k_gather_large
 // sample ids taken from the global counter at a time: at least the slots of a workgroup
 template <int S>
 constexpr int id_batch() { return S <= 16 ? 16 : 32; }
@@ -138,7 +138,8 @@ struct SampleArgs {
     uint32_t *medium;
     unsigned long long *n_medium;
     int *overflow;
-    unsigned long long *tier_stats; // [3]: samples finished by this launch, their entries, edges probed
+    unsigned long long *tier_stats; // [5]: samples finished by this launch, their entries, their edges
+                                    // probed; the edges and the nodes (items) this launch expanded
     uint32_t *gbits;            // global tier: [slots][words]
     int32_t *glist;             // global tier: [slots][n]
     uint64_t words;
@@ -276,6 +277,8 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
 
     // lane s of wave 0 counts what slot s finishes; summed once when the workgroup exits
     unsigned long long st_fin = 0, st_ent = 0, st_prb = 0;
+    // every lane counts the edges and items it sets up (the work of this launch)
+    unsigned long long st_swp = 0, st_itm = 0;
     if constexpr (!GLOBAL)
         for (int i = tid; i < HSZ; i += BLOCK) sh_hash[i] = -1;
     if (tid < S) {
@@ -398,32 +401,9 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
             } else {
                 int32_t *L = list_ptr(s);
                 uint32_t *B = bits_ptr(s);
-                if (cnt > SORT_LDS_MAX) {
-                    // a very large sample: write it sorted straight from the bitmap
-                    unsigned long long run = off;
-                    for (uint64_t w0 = 0; w0 < a.words; w0 += BLOCK) {
-                        const uint64_t wi = w0 + tid;
-                        const uint32_t word = wi < a.words ? B[wi] : 0u;
-                        int tot;
-                        const int ex = block_excl_scan<BLOCK, int>(__popc(word), s_scan, &tot);
-                        if (word) {
-                            uint32_t x = word;
-                            int k = 0;
-                            while (x) {
-                                const int b = __ffs(x) - 1;
-                                x &= x - 1u;
-                                SKIS_KARG(staging)[run + ex + k] = (int32_t)(wi * 32u + (uint64_t)b);
-                                ++k;
-                            }
-                            B[wi] = 0u;
-                        }
-                        run += (unsigned long long)tot;
-                    }
-                } else {
-                    for (int t = tid; t < cnt; t += BLOCK) SKIS_KARG(staging)[off + t] = L[t];
-                    const int rc = s_count[s];
-                    for (int t = tid; t < rc; t += BLOCK) B[L[t] >> 5] = 0u;
-                }
+                for (int t = tid; t < cnt; t += BLOCK) SKIS_KARG(staging)[off + t] = L[t];
+                const int rc = s_count[s];
+                for (int t = tid; t < rc; t += BLOCK) B[L[t] >> 5] = 0u;
             }
         }
         block_sync<BLOCK>();
@@ -693,6 +673,8 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                         end = beg;
                     }
                 }
+                st_swp += (unsigned long long)(end - beg);
+                st_itm += 1;
                 it_slot[it] = (uint8_t)sl;
                 it_beg[it] = beg;
                 it_end[it] = end;
@@ -844,14 +826,22 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
         block_sync<BLOCK>();
         if (!s_alive) break;
     }
-    if (tid < 64 && SKIS_KARG(tier_stats)) {
-        st_fin = wave_sum(st_fin);
-        st_ent = wave_sum(st_ent);
-        st_prb = wave_sum(st_prb);
-        if (tid == 0 && st_fin) {
-            atomicAdd(SKIS_KARG(tier_stats) + 0, st_fin);
-            atomicAdd(SKIS_KARG(tier_stats) + 1, st_ent);
-            atomicAdd(SKIS_KARG(tier_stats) + 2, st_prb);
+    if (SKIS_KARG(tier_stats)) {
+        if (tid < 64) {
+            st_fin = wave_sum(st_fin);
+            st_ent = wave_sum(st_ent);
+            st_prb = wave_sum(st_prb);
+            if (tid == 0 && st_fin) {
+                atomicAdd(SKIS_KARG(tier_stats) + 0, st_fin);
+                atomicAdd(SKIS_KARG(tier_stats) + 1, st_ent);
+                atomicAdd(SKIS_KARG(tier_stats) + 2, st_prb);
+            }
+        }
+        st_swp = wave_sum(st_swp);
+        st_itm = wave_sum(st_itm);
+        if ((tid & 63) == 0 && st_itm) {
+            atomicAdd(SKIS_KARG(tier_stats) + 3, st_swp);
+            atomicAdd(SKIS_KARG(tier_stats) + 4, st_itm);
         }
     }
 }
@@ -1058,20 +1048,80 @@ __global__ __launch_bounds__(256) void k_gather_medium(uint64_t count, const uin
     for (uint64_t k = blockIdx.x; k < count; k += gridDim.x) {
         const uint32_t i = list[k];
         const int sz = (int)size[i];
+        if (sz > SORT_LDS_MAX) continue; // k_gather_large's
         const int32_t *src = staging + off[i];
         int32_t *dst = nodes + sptr[i];
         if (owner)
             for (int t = threadIdx.x; t < sz; t += 256) owner[sptr[i] + t] = (int32_t)i;
-        if (sz > SORT_LDS_MAX) { // written sorted by the global tier
-            for (int t = threadIdx.x; t < sz; t += 256) dst[t] = src[t];
-            continue;
-        }
         int P = 512;
         while (P < sz) P <<= 1;
         for (int t = threadIdx.x; t < P; t += 256) buf[t] = t < sz ? src[t] : INT32_MAX;
         __syncthreads();
         bitonic_lds<256>(buf, P);
         for (int t = threadIdx.x; t < sz; t += 256) dst[t] = buf[t];
+        __syncthreads();
+    }
+}
+
+// Samples above SORT_LDS_MAX nodes, one at a time per workgroup: the sample's nodes set
+// their bits in the workgroup's bitmap of n bits and in a summary of one bit per bitmap word;
+// a walk over the summary, in node order, visits only the bitmap words that hold nodes,
+// writes those nodes in ascending order and clears both levels (every sample leaves its
+// bitmaps zero).  Work per sample: its nodes plus n / 1024 summary words.
+constexpr int LARGE_BLOCK = 256;
+constexpr uint64_t LARGE_BITMAP_BUDGET = 2ull << 30;
+
+__global__ __launch_bounds__(LARGE_BLOCK) void k_gather_large(uint64_t count, const uint32_t *__restrict__ list,
+                                                              const uint32_t *__restrict__ size,
+                                                              const unsigned long long *__restrict__ off,
+                                                              const int64_t *__restrict__ sptr,
+                                                              const int32_t *__restrict__ staging,
+                                                              int32_t *__restrict__ nodes, int32_t *__restrict__ owner,
+                                                              uint32_t *__restrict__ bits, uint32_t *__restrict__ summ,
+                                                              uint64_t words, uint64_t swords, int *err)
+{
+    __shared__ int32_t s_scan[LARGE_BLOCK / 64 + 1];
+    uint32_t *B = bits + (size_t)blockIdx.x * words;
+    uint32_t *Sm = summ + (size_t)blockIdx.x * swords;
+    const int tid = threadIdx.x;
+    for (uint64_t k = blockIdx.x; k < count; k += gridDim.x) {
+        const uint32_t i = list[k];
+        const int64_t sz = (int64_t)size[i];
+        if (sz <= SORT_LDS_MAX) continue; // k_gather_medium's
+        const int32_t *src = staging + off[i];
+        int32_t *dst = nodes + sptr[i];
+        for (int64_t t = tid; t < sz; t += LARGE_BLOCK) {
+            const uint32_t u = (uint32_t)src[t];
+            if ((uint64_t)(u >> 5) >= words) { // bounds guard: report, never index
+                atomicOr(err, 1);
+                continue;
+            }
+            atomicOr(B + (u >> 5), 1u << (u & 31));
+            atomicOr(Sm + (u >> 10), 1u << ((u >> 5) & 31));
+            if (owner) owner[sptr[i] + t] = (int32_t)i;
+        }
+        __syncthreads();
+        int64_t run = 0;
+        for (uint64_t s0 = 0; s0 < swords; s0 += LARGE_BLOCK) {
+            const uint64_t sw = s0 + tid;
+            const uint32_t sm = sw < swords ? Sm[sw] : 0u;
+            int c = 0;
+            for (uint32_t x = sm; x; x &= x - 1u) c += __popc(B[sw * 32u + (uint64_t)(__ffs(x) - 1)]);
+            int tot;
+            const int ex = block_excl_scan<LARGE_BLOCK, int>(c, s_scan, &tot);
+            int64_t pos = run + ex;
+            for (uint32_t x = sm; x; x &= x - 1u) {
+                const uint64_t wi = sw * 32u + (uint64_t)(__ffs(x) - 1);
+                for (uint32_t y = B[wi]; y; y &= y - 1u) {
+                    if (pos < sz) dst[pos] = (int32_t)(wi * 32u + (uint64_t)(__ffs(y) - 1));
+                    ++pos;
+                }
+                B[wi] = 0u;
+            }
+            if (sm) Sm[sw] = 0u;
+            run += tot;
+        }
+        if (tid == 0 && run != sz) atomicOr(err, 2); // a repeated node: the sample is broken
         __syncthreads();
     }
 }
@@ -1095,6 +1145,17 @@ __global__ __launch_bounds__(256) void k_count_value(uint64_t count, const uint3
     unsigned long long acc = 0;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (uint64_t)gridDim.x * blockDim.x)
         acc += x[i] == v ? 1ull : 0ull;
+    block_add_to(acc, out);
+}
+
+// *out += #{ k < count : x[list[k]] > v }
+__global__ __launch_bounds__(256) void k_count_listed_above(uint64_t count, const uint32_t *__restrict__ list,
+                                                            const uint32_t *__restrict__ x, uint32_t v,
+                                                            unsigned long long *__restrict__ out)
+{
+    unsigned long long acc = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (uint64_t)gridDim.x * blockDim.x)
+        acc += x[list[i]] > v ? 1ull : 0ull;
     block_add_to(acc, out);
 }
 
@@ -1175,7 +1236,8 @@ struct Counters {
     unsigned long long n_medium;
     int overflow;
     int pad;
-    unsigned long long tier[3][3]; // per tier: samples finished, their entries, edges probed
+    unsigned long long tier[3][5]; // per tier: samples finished, their entries, their edges probed,
+                                   // edges and nodes the launch expanded
 };
 
 typedef void (*SampleKernel)(SampleArgs);
@@ -1725,18 +1787,25 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
     }
     SKIS_HIP_TRY(hipEventRecord(ev[2], s));
     for (int t = 0; t < 3; ++t)
-        for (int k = 0; k < 3; ++k) sk.tier_stats[t][k] = hc.tier[t][k];
+        for (int k = 0; k < 5; ++k) sk.tier_stats[t][k] = hc.tier[t][k];
 
-    // every sample must have finished in one of the tiers
-    hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(1), dim3(64), 0, s, (uint64_t)1, &ctr.ptr->next, 0ull);
+    // every sample must have finished in one of the tiers; the samples above SORT_LDS_MAX
+    // nodes (all listed in `medium`) are counted for k_gather_large
+    DevBuf<unsigned long long> tally;
+    tally.alloc(arena, 2);
+    hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(1), dim3(64), 0, s, (uint64_t)2, tally.ptr, 0ull);
     hipLaunchKernelGGL(k_count_value, dim3(grid_cap(count, 256, 1)), dim3(256), 0, s, (uint64_t)count, out_size.ptr,
-                       DEFERRED, &ctr.ptr->next);
+                       DEFERRED, tally.ptr);
+    if (hc.n_medium > 0)
+        hipLaunchKernelGGL(k_count_listed_above, dim3(grid_cap(hc.n_medium, 256, 1)), dim3(256), 0, s,
+                           (uint64_t)hc.n_medium, medium.ptr, out_size.ptr, (uint32_t)SORT_LDS_MAX, tally.ptr + 1);
     SKIS_HIP_TRY(hipGetLastError());
-    unsigned long long unfinished = 0;
-    SKIS_HIP_TRY(hipMemcpyAsync(&unfinished, &ctr.ptr->next, sizeof(unfinished), hipMemcpyDeviceToHost, s));
+    unsigned long long htally[2] = {0, 0};
+    SKIS_HIP_TRY(hipMemcpyAsync(htally, tally.ptr, sizeof(htally), hipMemcpyDeviceToHost, s));
     SKIS_HIP_TRY(hipStreamSynchronize(s));
-    if (unfinished)
-        throw Error{SKIS_EHIP, "internal error: " + std::to_string(unfinished) + " samples did not finish"};
+    if (htally[0])
+        throw Error{SKIS_EHIP, "internal error: " + std::to_string(htally[0]) + " samples did not finish"};
+    const uint64_t n_large = htally[1];
 
     // CSR: sample_ptr = exclusive scan of sizes, then sorted copies
     sk.T = count;
@@ -1784,11 +1853,36 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
                            sk.sample_ptr.ptr, staging.ptr, sk.nodes.ptr, owner_p);
         SKIS_HIP_TRY(hipGetLastError());
     }
-    if (hc.n_medium > 0) {
+    if (hc.n_medium > n_large) {
         hipLaunchKernelGGL(k_gather_medium, dim3(grid_cap(hc.n_medium, 1, 4)), dim3(256), 0, s,
                            (uint64_t)hc.n_medium, medium.ptr, out_size.ptr, out_off.ptr, sk.sample_ptr.ptr,
                            staging.ptr, sk.nodes.ptr, owner_p);
         SKIS_HIP_TRY(hipGetLastError());
+    }
+    if (n_large > 0) {
+        // one bitmap of n bits and one summary bit per bitmap word for each workgroup, at
+        // most LARGE_BITMAP_BUDGET bytes of them
+        const uint64_t words = ((uint64_t)n + 31) / 32, swords = (words + 31) / 32;
+        const uint64_t per_wg = (words + swords) * 4;
+        uint64_t g = std::min<uint64_t>({n_large, (uint64_t)device_cu_count() * 2,
+                                         std::max<uint64_t>(1, LARGE_BITMAP_BUDGET / per_wg)});
+        DevBuf<uint32_t> lbits, lsumm;
+        DevBuf<int> lerr;
+        lbits.alloc(arena, g * words);
+        lsumm.alloc(arena, g * swords);
+        lerr.alloc(arena, 1);
+        hipLaunchKernelGGL(k_fill<uint32_t>, dim3(grid_cap(g * words, 256)), dim3(256), 0, s, g * words, lbits.ptr, 0u);
+        hipLaunchKernelGGL(k_fill<uint32_t>, dim3(grid_cap(g * swords, 256)), dim3(256), 0, s, g * swords, lsumm.ptr, 0u);
+        hipLaunchKernelGGL(k_fill<int>, dim3(1), dim3(64), 0, s, (uint64_t)1, lerr.ptr, 0);
+        hipLaunchKernelGGL(k_gather_large, dim3((unsigned)g), dim3(LARGE_BLOCK), 0, s, (uint64_t)hc.n_medium,
+                           medium.ptr, out_size.ptr, out_off.ptr, sk.sample_ptr.ptr, staging.ptr, sk.nodes.ptr,
+                           owner_p, lbits.ptr, lsumm.ptr, words, swords, lerr.ptr);
+        SKIS_HIP_TRY(hipGetLastError());
+        int herr = 0;
+        SKIS_HIP_TRY(hipMemcpyAsync(&herr, lerr.ptr, sizeof(int), hipMemcpyDeviceToHost, s));
+        SKIS_HIP_TRY(hipStreamSynchronize(s));
+        if (herr) throw Error{SKIS_EHIP, "internal error: a large sample failed its sort (flags " +
+                                             std::to_string(herr) + ")"};
     }
     sk.roots.alloc(arena, count);
     hipLaunchKernelGGL(k_roots_out, dim3(grid_cap(count, 256)), dim3(256), 0, s, count, rec.ptr, sk.roots.ptr);
@@ -1806,6 +1900,8 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
         sk.tier_stats[0][0] = count;
         sk.tier_stats[0][1] = (uint64_t)total;
         sk.tier_stats[0][2] = ptot;
+        sk.tier_stats[0][3] = ptot;            // every probed edge is swept once
+        sk.tier_stats[0][4] = (uint64_t)total; // and every node expanded once
     }
     float ms = 0;
     SKIS_HIP_TRY(hipEventElapsedTime(&ms, ev[0], ev[1]));

@@ -76,9 +76,7 @@ struct Slot {
     skis::DevBuf<int> d_err;
     skis::DevBuf<uint32_t> bitmaps;  // max_batch_queries bitmaps of T bits
     skis::DevBuf<uint32_t> nodebits; // max_large node bitmaps of n bits
-    skis::SplitScratch split;        // heavy sets of the batch, walked by many workgroups
     std::vector<Pending> batch;
-    uint64_t heavy_units = 0;        // chunks of the batch's heavy sets (upper bound; 0: none)
     bool busy = false;
 };
 
@@ -89,8 +87,6 @@ struct skis_server {
     skis_server_options opt{};
     int device = 0;
     uint64_t wordsT = 1, wordsN = 1;
-    std::vector<int64_t> node_ptr; // host copy of the transpose's offsets: deg_H per node
-    int cus = 1;
     skis::Arena arena;
     std::vector<std::unique_ptr<Slot>> slots;
     std::thread worker;
@@ -141,11 +137,8 @@ void skis_server::launch(Slot &sl)
     if (nl > 0)
         SKIS_HIP_TRY(hipMemcpyAsync(sl.d_large.ptr, sl.h_large.ptr, sizeof(int64_t) * (size_t)nl,
                                     hipMemcpyHostToDevice, s));
-    // the split launches only when a set may be heavy (the bound counts duplicates)
-    const unsigned walk = (unsigned)std::min<uint64_t>(sl.heavy_units, (uint64_t)4 * cus);
     skis::estimate_launch(k, nq, sl.d_ptr.ptr, sl.d_nodes.ptr, sl.d_large.ptr, nl, sl.bitmaps.ptr, wordsT,
-                          sl.nodebits.ptr, sl.d_cov.ptr, sl.d_est.ptr, sl.d_err.ptr,
-                          sl.heavy_units ? sl.split.hdr.ptr : nullptr, walk, s);
+                          sl.nodebits.ptr, sl.d_cov.ptr, sl.d_est.ptr, sl.d_err.ptr, s);
     SKIS_HIP_TRY(hipMemcpyAsync(sl.h_cov.ptr, sl.d_cov.ptr, sizeof(unsigned long long) * (size_t)nq,
                                 hipMemcpyDeviceToHost, s));
     SKIS_HIP_TRY(hipMemcpyAsync(sl.h_est.ptr, sl.d_est.ptr, sizeof(double) * (size_t)nq, hipMemcpyDeviceToHost, s));
@@ -203,7 +196,6 @@ void skis_server::run()
                     Slot &sl = *free_slot;
                     uint64_t entries = 0;
                     uint32_t large = 0;
-                    sl.heavy_units = 0;
                     while (!queue.empty() && sl.batch.size() < opt.max_batch_queries) {
                         const uint64_t e = queue.front().nodes.size();
                         const bool is_large = e > (uint64_t)skis::EST_MAX_SET;
@@ -211,11 +203,6 @@ void skis_server::run()
                         if (is_large && large >= opt.max_large_sets) break;
                         entries += e;
                         large += is_large ? 1u : 0u;
-                        if (skis::EST_SPLIT_ENABLED && !is_large && !node_ptr.empty()) {
-                            int64_t w = 0;
-                            for (int32_t v : queue.front().nodes) w += node_ptr[v + 1] - node_ptr[v];
-                            if (w > skis::EST_SPLIT) sl.heavy_units += (uint64_t)((w + skis::EST_CHUNK - 1) / skis::EST_CHUNK);
-                        }
                         sl.batch.push_back(std::move(queue.front()));
                         queue.pop_front();
                     }
@@ -354,12 +341,6 @@ int skis_server_create(const skis_sketch *sk, const skis_server_options *opt_in,
         sv->arena.cap = opt.max_device_bytes;
         sv->wordsT = sk->core.T ? (sk->core.T + 31) / 32 : 1;
         sv->wordsN = ((uint64_t)sk->core.n + 31) / 32;
-        sv->cus = skis::device_cu_count();
-        if (sk->core.T > 0) {
-            sv->node_ptr.resize((size_t)sk->core.n + 1);
-            SKIS_HIP_TRY(hipMemcpy(sv->node_ptr.data(), sk->core.node_ptr.ptr, sizeof(int64_t) * sv->node_ptr.size(),
-                                   hipMemcpyDeviceToHost));
-        }
         const uint64_t nb = std::max<uint64_t>(opt.max_batch_queries, opt.max_large_sets);
         sv->arena.stream = nullptr; // allocations complete before any slot stream uses them (below)
         for (uint32_t i = 0; i < opt.pipeline_depth; ++i) {
@@ -385,7 +366,6 @@ int skis_server_create(const skis_sketch *sk, const skis_server_options *opt_in,
             skis::fill_u32(s.bitmaps.ptr, nb * sv->wordsT, s.stream);
             skis::fill_u32(s.nodebits.ptr, (uint64_t)opt.max_large_sets * sv->wordsN, s.stream);
             skis::fill_u32(reinterpret_cast<uint32_t *>(s.d_err.ptr), 1, s.stream);
-            if (skis::EST_SPLIT_ENABLED) skis::split_init(sv->arena, s.split, s.stream);
             SKIS_HIP_TRY(hipStreamSynchronize(s.stream));
         }
         skis_server *raw = sv.get();

@@ -63,7 +63,8 @@ class Info(ctypes.Structure):
                 ("ms_tier2", ctypes.c_double), ("deferred_global", ctypes.c_uint64),
                 ("plain_levels", ctypes.c_uint32), ("graph_replays", ctypes.c_uint32),
                 ("tier_samples", ctypes.c_uint64 * 3), ("tier_entries", ctypes.c_uint64 * 3),
-                ("tier_probed", ctypes.c_uint64 * 3)]
+                ("tier_probed", ctypes.c_uint64 * 3), ("tier_swept", ctypes.c_uint64 * 3),
+                ("tier_items", ctypes.c_uint64 * 3)]
 
 
 _lib = None
@@ -191,6 +192,8 @@ class SketchInfo:
     tier_samples: tuple = (0, 0, 0)
     tier_entries: tuple = (0, 0, 0)
     tier_probed: tuple = (0, 0, 0)
+    tier_swept: tuple = (0, 0, 0)
+    tier_items: tuple = (0, 0, 0)
 
 
 class Sketch:
@@ -218,7 +221,7 @@ class Sketch:
                           i.ms_preprocess, i.ms_roots, i.ms_sample, i.ms_compact, i.ms_inverse,
                           i.ms_tier0, i.ms_tier1, i.ms_tier2, i.deferred_global,
                           i.plain_levels, i.graph_replays, tuple(i.tier_samples), tuple(i.tier_entries),
-                          tuple(i.tier_probed))
+                          tuple(i.tier_probed), tuple(i.tier_swept), tuple(i.tier_items))
 
     def estimate(self, set_ptr, set_nodes):
         """(cov uint64[Q], est float64[Q]) device tensors for seed sets in CSR form."""

@@ -19,7 +19,7 @@ def skis():
     return s
 
 
-@pytest.mark.parametrize("row_bytes", [8, 16, 32, 64])
+@pytest.mark.parametrize("row_bytes", [8, 16, 32, 64, 128])
 def test_probe_reads_the_rows(skis, row_bytes):
     print("[gpu-probe] row_bytes", row_bytes, flush=True)
     rows = 1 << 14
@@ -45,7 +45,7 @@ def test_probe_reads_the_rows(skis, row_bytes):
 def test_probe_refuses_bad_arguments(skis):
     t = torch.zeros(4096, dtype=torch.uint8, device="cuda")
     sink = torch.zeros(1, dtype=torch.int32, device="cuda")
-    for rb in (0, 4, 12, 128):
+    for rb in (0, 4, 12, 256):
         with pytest.raises(skis.SkisError):
             skis.probe_random_read(t, rb, 10, sink)
     with pytest.raises(skis.SkisError):  # fewer bytes than one row: no rows

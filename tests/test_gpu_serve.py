@@ -93,9 +93,9 @@ def test_replay_mix_equals_alone(skis, sketch):
     assert np.all(lat > 0)
 
 
-@pytest.mark.skip(reason="a GPU run of this case stopped making progress (killed for silence) while the "
-                         "split walk for heavy sets was on; the cause is not found and the split walk is "
-                         "switched off in the library; the case stays off the GPU until a cause is shown")
+@pytest.mark.skip(reason="a GPU run of this case stopped making progress (killed for silence) while a split walk "
+                         "for heavy sets was in the library; reading the code found no cause, the split walk was "
+                         "removed, and the case stays off the GPU until a cause is shown")
 def test_server_heavy_sets(skis, sketch):
     # sets holding hubs inside the server, compared with skis_estimate and the oracle
     g, sk, ora, q = sketch

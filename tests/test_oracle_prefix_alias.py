@@ -3,6 +3,7 @@ Eq. probn), Gamma (Table 1), integer root weights and the alias table (Eq. probu
 import json
 import math
 import os
+import zlib
 from fractions import Fraction
 
 import numpy as np
@@ -52,28 +53,43 @@ def _rows_graph(rows):
     return inputs.edges_to_in_csr(n, src, dst, np.array(ws, np.float32))
 
 
-def test_prefix_short_rows_are_the_plain_running_product():
-    # a row of at most 64 in-edges: P is itertools.accumulate's left-to-right product
+def _running_product(ws):
+    """P_e of a row by Python's own binary64 arithmetic: a plain loop over the factors."""
+    out, run = [], 1.0
+    for x in ws:
+        run = run * (1.0 - float(x))
+        out.append(run)
+    return out
+
+
+def test_prefix_rows_are_the_plain_running_product():
+    # every row, short or long (up to a 1.2M-edge hub row, the size of the TRI workload's
+    # largest), equals Python's left-to-right product bit for bit; compared with
+    # itertools.accumulate as well on the short rows
     import itertools
     import operator
     rng = np.random.Generator(np.random.PCG64(12))
-    rows = [rng.choice(np.array([0.1, 0.01, 0.001, 0.5, 0.0], np.float32), size=d) for d in (1, 2, 17, 63, 64)]
+    vals = np.array([0.1, 0.01, 0.001, 0.5, 0.0, 0.999], np.float32)
+    rows = [rng.choice(vals, size=d) for d in (1, 2, 17, 63, 64, 65, 257, 4097, 40000)]
+    rows.append(rng.choice(np.array([0.1, 0.01, 0.001], np.float32), size=1_200_000))
+    rows.append(np.full(50000, np.float32(1.0) / np.float32(50000), np.float32))
     row_ptr, col, ww = _rows_graph(rows)
     P, q = oracle.row_prefix(row_ptr, ww)
     for v in range(len(rows)):
         a, b = row_ptr[v], row_ptr[v + 1]
-        f = [1.0 - float(x) for x in ww[a:b]]
-        assert P[a:b].tolist() == list(itertools.accumulate(f, operator.mul))
+        want = _running_product(ww[a:b])
+        assert P[a:b].tolist() == want, v
+        if b - a <= 64:
+            f = [1.0 - float(x) for x in ww[a:b]]
+            assert want == list(itertools.accumulate(f, operator.mul))
         assert q[v] == P[b - 1]
 
 
 def test_prefix_long_rows_within_rounding_bound_of_exact_products():
-    # every P_e against the exact rational product of its factors.  Counting the roundings
-    # behind the i-th product of a row (0-based): 63 in each earlier block, the carries
-    # after the first (which multiplies 1.0 exactly), i mod 64 in its own block and the
-    # final product (exact in block 0): i in all, as for a left-to-right product.  So
-    # |P_e - exact| <= i u / (1 - i u) * exact; a dropped, repeated or misplaced factor
-    # is off by orders of magnitude more
+    # every P_e against the exact rational product of its factors: the i-th product of a
+    # row (0-based) takes i roundings (the first, 1.0 times the first factor, is exact), so
+    # |P_e - exact| <= i u / (1 - i u) * exact; a dropped, repeated or misplaced factor is
+    # off by orders of magnitude more
     rng = np.random.Generator(np.random.PCG64(13))
     u = Fraction(1, 1 << 53)
     rows = [rng.choice(np.array([0.1, 0.01, 0.001], np.float32), size=d) for d in (65, 128, 129, 1000, 4097)]
@@ -152,7 +168,7 @@ def _alias_mass(thr, alias, C):
 
 @pytest.mark.parametrize("case", ["random", "equal", "one_heavy", "zeros", "tiny", "skewed"])
 def test_alias_exact_mass(case):
-    rng = np.random.Generator(np.random.PCG64(abs(hash(case)) % 1000))
+    rng = np.random.Generator(np.random.PCG64(zlib.crc32(case.encode())))
     if case == "random":
         W = rng.integers(0, 1 << 40, 3000).astype(np.uint64)
     elif case == "equal":
