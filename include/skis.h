@@ -71,11 +71,35 @@ typedef struct skis_options {
     uint32_t quads_per_lane;      /* first tier: most edge quads (aligned groups of four edges)
                                      a lane takes per sweep, 1 (default: fewer registers, more
                                      workgroups resident) or 2 */
-    uint32_t reserved_opt;
+    uint64_t entry_budget;        /* 0 (default): num_samples samples.  Otherwise a size-budgeted sketch
+                                     (the stopping rule of Sec. 7, samples until their total size
+                                     reaches h * n * log n): the sketch holds samples 0 .. T-1 for the
+                                     smallest T <= num_samples whose sizes sum to at least entry_budget
+                                     (T = num_samples if none does).  Samples are drawn in rounds that
+                                     overshoot and the sketch is then cut at T, so T and every sample are
+                                     the same whatever the rounds; the tier and time counters of
+                                     skis_info describe the last round */
+    uint32_t ris_mode;            /* 0 (default): IIS samples (Alg. 1); 1: plain RIS samples of Sec. 2.3.1
+                                     -- a root uniform over V, independent coins on all its in-edges,
+                                     singular samples {root} kept -- for comparisons with IIS.  A RIS
+                                     sketch answers estimate with n * Cov / T (Eq. ris_prob) and runs
+                                     the greedy on gains n * Delta / T; it is built even when Gamma = 0 */
+    uint32_t reserved_opt;        /* set to 0 */
 } skis_options;
 
 /* Fills *opt with the defaults. */
 void skis_default_options(skis_options *opt);
+
+/*
+ * Lemma lem:monte: a sketch of at least T = ceil((2 Gamma / n + 2 eps / 3) ln(2 / delta) n /
+ * (I_lower eps^2)) samples gives an (eps, delta)-estimate of I(S) for every set S with
+ * I(S) >= I_lower (the Lemma states it for I(S); any lower bound of it, such as |S|, keeps the
+ * guarantee).  Host arithmetic only (binary64), no device work.  *T_out (host) receives T.
+ * Errors: SKIS_EINVAL for n <= 0, Gamma outside [0, n], I_lower <= 0, eps <= 0, delta outside
+ * (0, 1), or a T of 2^63 or more.
+ */
+int skis_samples_for_estimate(int32_t n, double Gamma, double I_lower, double eps, double delta,
+                              uint64_t *T_out /* host */);
 
 /*
  * Preprocessing alone (rows a1-a3 of the hot path), into caller buffers:
@@ -125,20 +149,21 @@ typedef struct skis_info {
     double Gamma;                /* sum of gamma_v */
     uint64_t device_bytes;       /* bytes the sketch holds on the device */
     double ms_preprocess, ms_roots, ms_sample, ms_compact, ms_inverse; /* stage times (events) */
-    double ms_tier0, ms_tier1, ms_tier2; /* the three sampler tiers' launches alone; the plain
-                                            and the captured form report their whole sampler
+    double ms_tier0, ms_tier1, ms_tier2, ms_tier3; /* the four sampler tiers' launches alone; the
+                                            plain and the captured form report their whole sampler
                                             in ms_tier0 */
-    uint64_t deferred_global;    /* samples that reached the HBM tier */
+    uint64_t deferred_global;    /* samples that outgrew the second tier (reached the HBM hash tier) */
+    uint64_t deferred_bitmap;    /* samples that outgrew the HBM hash tier (reached the bitmap tier) */
     uint32_t plain_levels;       /* plain form: BFS level launches (0 for the persistent form) */
     uint32_t graph_replays;      /* captured form: replays of the captured chain (0 otherwise) */
-    uint64_t tier_samples[3];    /* samples finished by each sampler tier (LDS, LDS 1024, HBM); the
-                                    plain form counts everything in tier 0 */
-    uint64_t tier_entries[3];    /* sum of |R_j| over those samples */
-    uint64_t tier_probed[3];     /* edges probed for those samples */
-    uint64_t tier_swept[3];      /* in-edges each tier's launch expanded (the work of that launch:
+    uint64_t tier_samples[4];    /* samples finished by each sampler tier (LDS 192-ish, LDS 1024, HBM
+                                    hash, HBM bitmap); the plain form counts everything in tier 0 */
+    uint64_t tier_entries[4];    /* sum of |R_j| over those samples */
+    uint64_t tier_probed[4];     /* edges probed for those samples */
+    uint64_t tier_swept[4];      /* in-edges each tier's launch expanded (the work of that launch:
                                     a sample resumed from an earlier tier is not counted again for
                                     the nodes that tier expanded) */
-    uint64_t tier_items[3];      /* nodes (and root items) each tier's launch expanded */
+    uint64_t tier_items[4];      /* nodes (and root items) each tier's launch expanded */
 } skis_info;
 
 /* Sketch facts (host out-param). */
@@ -184,6 +209,20 @@ int skis_node_q(const skis_sketch *sk, double *q, hipStream_t stream);
 
 /* Frees the sketch and every device buffer it owns (NULL is a no-op). */
 void skis_sketch_free(skis_sketch *sk);
+
+/* Device memory the library keeps for reuse, process-wide.  Blocks that a finished call no longer
+ * uses go to a cache of idle blocks (per device, at most cache_keep_bytes, default 32 GiB; the
+ * largest leave first) from which later calls take buffers without a driver call, and the device's
+ * stream-ordered pool keeps up to pool_keep_bytes (default 64 GiB) of released memory.  Lower limits
+ * leave more memory to other users of the GPU (a PyTorch caching allocator, another library);
+ * the call trims the current device's cache to the new limit at once.  Sketches and servers keep
+ * the buffers they own.  Errors: SKIS_EHIP. */
+int skis_set_memory_limits(uint64_t cache_keep_bytes, uint64_t pool_keep_bytes);
+
+/* Gives every idle cached block of the current device back and trims its stream-ordered pool to
+ * nothing, after a device synchronisation.  Memory owned by live sketches and servers stays.
+ * Errors: SKIS_EHIP. */
+int skis_release_cached_memory(void);
 
 /* Message for the last failing call on this thread ("" if none). */
 const char *skis_last_error(void);

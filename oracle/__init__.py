@@ -260,6 +260,23 @@ class Prepared:
         self.close()
 
 
+def first_T_reaching(prep: Prepared, seed: int, budget: int, T_max: int, chunk: int = 1 << 15,
+                     nthreads: int = 1, ris_mode: bool = False) -> int:
+    """The size-budgeted sample count (Sec. 7: samples until their total size reaches a budget):
+    the smallest T <= T_max with |R_0| + ... + |R_{T-1}| >= budget, T_max if there is none.
+    Samples are drawn in id order, chunk ids at a time."""
+    total, j = 0, 0
+    while j < T_max:
+        sk = prep.sample(seed, j, min(j + chunk, T_max), nthreads=nthreads, ris_mode=ris_mode)
+        cum = total + np.cumsum(np.diff(sk.sample_ptr))
+        hit = int(np.searchsorted(cum, budget))  # first position with cum >= budget
+        if hit < len(cum):
+            return j + hit + 1
+        total = int(cum[-1]) if len(cum) else total
+        j += len(cum)
+    return T_max
+
+
 def inverse(n: int, sample_ptr, nodes):
     sample_ptr, nodes = _c(sample_ptr, np.int64), _c(nodes, np.int32)
     T = len(sample_ptr) - 1

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <cmath>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -22,7 +24,7 @@ const std::string &get_error() { return g_err; }
 // POOL_KEEP bytes of released memory for reuse: a build then takes its buffers from what the
 // previous one released instead of going back to the driver.  Buffers are released on the
 // arena's stream, after the work queued there that uses them.
-constexpr uint64_t POOL_KEEP = 64ull << 30;
+static std::atomic<uint64_t> g_pool_keep{64ull << 30};
 
 static bool pool_ready()
 {
@@ -36,7 +38,7 @@ static bool pool_ready()
         ok = hipDeviceGetAttribute(&supported, hipDeviceAttributeMemoryPoolsSupported, d) == hipSuccess && supported;
         if (ok) {
             hipMemPool_t pool = nullptr;
-            uint64_t keep = POOL_KEEP;
+            uint64_t keep = g_pool_keep.load();
             ok = hipDeviceGetDefaultMemPool(&pool, d) == hipSuccess &&
                  hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep) == hipSuccess;
         }
@@ -50,7 +52,7 @@ static bool pool_ready()
 // device synchronisation), so an arena on any stream may take it as it is.  Taking one costs
 // no driver call; the stream-ordered free and allocation cost tens to hundreds of microseconds
 // of host time each.
-constexpr uint64_t CACHE_KEEP = 32ull << 30;
+static std::atomic<uint64_t> g_cache_keep{32ull << 30};
 constexpr int CACHE_DEVICES = 64;
 
 struct CachedBlock {
@@ -96,7 +98,8 @@ static void *cache_take(size_t need, size_t *size, bool *pooled)
 static void cache_put(void *p, size_t size, bool pooled)
 {
     int d = 0;
-    if (hipGetDevice(&d) != hipSuccess || d < 0 || d >= CACHE_DEVICES || size > CACHE_KEEP) {
+    const uint64_t keep = g_cache_keep.load();
+    if (hipGetDevice(&d) != hipSuccess || d < 0 || d >= CACHE_DEVICES || size > keep) {
         free_block(p, pooled);
         return;
     }
@@ -104,7 +107,22 @@ static void cache_put(void *p, size_t size, bool pooled)
     std::lock_guard<std::mutex> lk(c.mu);
     c.blocks.emplace(size, CachedBlock{p, pooled});
     c.bytes += size;
-    while (c.bytes > CACHE_KEEP) { // the largest blocks leave first
+    while (c.bytes > keep) { // the largest blocks leave first
+        auto it = std::prev(c.blocks.end());
+        c.bytes -= it->first;
+        free_block(it->second.p, it->second.pooled);
+        c.blocks.erase(it);
+    }
+}
+
+// Frees idle blocks of the current device's cache, largest first, until it holds at most keep bytes.
+static void trim_idle_cache(uint64_t keep)
+{
+    int d = 0;
+    if (hipGetDevice(&d) != hipSuccess || d < 0 || d >= CACHE_DEVICES) return;
+    BlockCache &c = block_cache(d);
+    std::lock_guard<std::mutex> lk(c.mu);
+    while (c.bytes > keep && !c.blocks.empty()) {
         auto it = std::prev(c.blocks.end());
         c.bytes -= it->first;
         free_block(it->second.p, it->second.pooled);
@@ -325,7 +343,10 @@ int skis_build_sketch(int32_t n, int64_t m, const int32_t *row_ptr, const int32_
             opt.staging_entries = opt_in->staging_entries;
             opt.chunk_samples = opt_in->chunk_samples;
             if (opt_in->quads_per_lane) opt.quads_per_lane = opt_in->quads_per_lane;
+            opt.ris_mode = opt_in->ris_mode;
+            opt.entry_budget = opt_in->entry_budget;
         }
+        if (opt.ris_mode > 1) throw skis::Error{SKIS_EINVAL, "ris_mode must be 0 or 1"};
         if (opt.form > 2) throw skis::Error{SKIS_EINVAL, "unknown sampler form"};
         skis_sketch *h = new skis_sketch;
         try {
@@ -348,7 +369,8 @@ int skis_build_sketch(int32_t n, int64_t m, const int32_t *row_ptr, const int32_
                 sk.ms_preprocess = ms;
                 sk.Gamma = prep.Gamma;
                 sk.C = prep.C;
-                if (prep.C == 0) {
+                sk.ris = opt.ris_mode != 0;
+                if (prep.C == 0 && !sk.ris) {
                     status = SKIS_WDEGENERATE;
                     sk.T = 0;
                     sk.sample_ptr.alloc(sk.arena, 1);
@@ -364,7 +386,24 @@ int skis_build_sketch(int32_t n, int64_t m, const int32_t *row_ptr, const int32_
                     cfg.chunk = opt.chunk_samples;
                     cfg.qpl = opt.quads_per_lane;
                     cfg.owners = opt.build_inverse_index != 0;
-                    skis::sample_and_compact(sk.arena, prep, n, m, num_samples, seed, cfg, sk, stream);
+                    cfg.ris = sk.ris;
+                    if (!opt.entry_budget) {
+                        skis::sample_and_compact(sk.arena, prep, n, m, num_samples, seed, cfg, sk, stream);
+                    } else {
+                        // size-budgeted: rounds from a pilot of 2^16 ids, each sized from the mean
+                        // sample size so far with 5 % to spare (at least doubling), until the
+                        // samples hold the budget or the cap is reached; then the cut
+                        uint64_t T_try = std::min<uint64_t>(num_samples, 1ull << 16);
+                        for (;;) {
+                            skis::sample_and_compact(sk.arena, prep, n, m, T_try, seed, cfg, sk, stream);
+                            if (sk.entries >= opt.entry_budget || T_try == num_samples) break;
+                            const double mean = std::max(1.0, (double)sk.entries / (double)T_try);
+                            const double want = (double)opt.entry_budget / mean * 1.05 + 1024.0;
+                            const uint64_t next = want >= (double)num_samples ? num_samples : (uint64_t)want;
+                            T_try = std::min<uint64_t>(num_samples, std::max<uint64_t>(2 * T_try, next));
+                        }
+                        skis::truncate_to_budget(sk, opt.entry_budget, stream);
+                    }
                 }
                 // q moves into the sketch only after every kernel that reads prep.q has run
                 sk.q.swap(prep.q);
@@ -414,10 +453,12 @@ int skis_sketch_info(const skis_sketch *h, skis_info *info)
         info->ms_tier0 = sk.ms_tier0;
         info->ms_tier1 = sk.ms_tier1;
         info->ms_tier2 = sk.ms_tier2;
+        info->ms_tier3 = sk.ms_tier3;
         info->deferred_global = sk.deferred_global;
+        info->deferred_bitmap = sk.deferred_bitmap;
         info->plain_levels = sk.plain_levels;
         info->graph_replays = sk.graph_replays;
-        for (int t = 0; t < 3; ++t) {
+        for (int t = 0; t < 4; ++t) {
             info->tier_samples[t] = sk.tier_stats[t][0];
             info->tier_entries[t] = sk.tier_stats[t][1];
             info->tier_probed[t] = sk.tier_stats[t][2];
@@ -529,6 +570,52 @@ int skis_probe_random_read(const void *table, uint64_t rows, uint32_t row_bytes,
 {
     return guarded([&]() -> int {
         skis::probe_random_read(table, rows, row_bytes, reads, seed, sink, stream);
+        return SKIS_OK;
+    });
+}
+
+int skis_samples_for_estimate(int32_t n, double Gamma, double I_lower, double eps, double delta, uint64_t *T_out)
+{
+    return guarded([&]() -> int {
+        if (!T_out) throw skis::Error{SKIS_EINVAL, "T_out must not be NULL"};
+        if (n <= 0) throw skis::Error{SKIS_EINVAL, "n must be positive"};
+        if (!(Gamma >= 0.0 && Gamma <= (double)n)) throw skis::Error{SKIS_EINVAL, "Gamma must be in [0, n]"};
+        if (!(I_lower > 0.0)) throw skis::Error{SKIS_EINVAL, "I_lower must be positive"};
+        if (!(eps > 0.0)) throw skis::Error{SKIS_EINVAL, "eps must be positive"};
+        if (!(delta > 0.0 && delta < 1.0)) throw skis::Error{SKIS_EINVAL, "delta must be in (0, 1)"};
+        // Lemma lem:monte: (2 Gamma / n + 2 eps / 3) ln(2 / delta) (n / I(S)) eps^-2 samples
+        const double T = (2.0 * Gamma / (double)n + 2.0 * eps / 3.0) * std::log(2.0 / delta) * ((double)n / I_lower) /
+                         (eps * eps);
+        if (!(T < 9.2e18)) throw skis::Error{SKIS_EINVAL, "the sample count does not fit 63 bits"};
+        *T_out = (uint64_t)std::ceil(T);
+        return SKIS_OK;
+    });
+}
+
+int skis_set_memory_limits(uint64_t cache_keep_bytes, uint64_t pool_keep_bytes)
+{
+    return guarded([&]() -> int {
+        skis::g_cache_keep.store(cache_keep_bytes);
+        skis::g_pool_keep.store(pool_keep_bytes);
+        int d = 0;
+        SKIS_HIP_TRY(hipGetDevice(&d));
+        int supported = 0;
+        if (hipDeviceGetAttribute(&supported, hipDeviceAttributeMemoryPoolsSupported, d) == hipSuccess && supported) {
+            hipMemPool_t pool = nullptr;
+            uint64_t keep = pool_keep_bytes;
+            if (hipDeviceGetDefaultMemPool(&pool, d) == hipSuccess)
+                (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+        }
+        (void)hipGetLastError();
+        skis::trim_idle_cache(cache_keep_bytes);
+        return SKIS_OK;
+    });
+}
+
+int skis_release_cached_memory(void)
+{
+    return guarded([&]() -> int {
+        skis::release_idle_memory();
         return SKIS_OK;
     });
 }

@@ -104,6 +104,7 @@ struct Sketch {
     uint64_t C = 0;
     double Gamma = 0.0;
     bool has_inverse = false;
+    bool ris = false;             // plain RIS samples: estimates n * Cov / T, no q term
     DevBuf<double> q;             // [n]
     DevBuf<int64_t> sample_ptr;   // [T+1]
     DevBuf<int32_t> nodes;        // [entries]
@@ -116,12 +117,17 @@ struct Sketch {
     DevBuf<int32_t> hot_node;     // [nhot]
     int nhot = 0;
     double ms_preprocess = 0, ms_roots = 0, ms_sample = 0, ms_compact = 0, ms_inverse = 0;
-    double ms_tier0 = 0, ms_tier1 = 0, ms_tier2 = 0; // the sampler launches alone
-    uint64_t deferred_global = 0;                    // samples that reached the HBM tier
+    double ms_tier0 = 0, ms_tier1 = 0, ms_tier2 = 0, ms_tier3 = 0; // the sampler launches alone
+    uint64_t deferred_global = 0;                    // samples that reached the HBM hash tier
+    uint64_t deferred_bitmap = 0;                    // samples that reached the HBM bitmap tier
     uint32_t plain_levels = 0;                       // BFS level launches of the plain form
     uint32_t graph_replays = 0;                      // replays of the captured chain (captured form)
-    uint64_t tier_stats[3][5] = {};                  // per sampler tier: samples, entries, edges probed,
+    uint64_t tier_stats[4][5] = {};                  // per sampler tier: samples, entries, edges probed,
                                                      // edges and nodes the tier's launch expanded
+    // the estimator's scale and per-node term: Gamma and q for IIS (Eq. eq21), n and none
+    // for RIS (Eq. ris_prob)
+    double est_scale() const { return ris ? (double)n : Gamma; }
+    const double *est_q() const { return ris ? nullptr : q.ptr; }
 };
 
 // ---------------------------------------------------------------------------------
@@ -158,12 +164,17 @@ struct SampleConfig {
     uint64_t chunk = 0; // captured form: samples per replay of the chain (0: 2^24)
     uint32_t qpl = 1;   // edge quads per lane per sweep in the first tier
     bool owners = false; // also write the sample id of every entry (Sketch::owner) for the transpose
+    bool ris = false;    // plain RIS samples (uniform root, no conditioning) instead of IIS
 };
 
 void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, uint64_t T, uint64_t seed,
                         const SampleConfig &cfg, Sketch &sk, hipStream_t s);
 
 void build_inverse(Sketch &sk, hipStream_t s);
+
+// Cuts a built sketch, before its transpose, to the smallest number of leading samples whose
+// sizes sum to at least budget.
+void truncate_to_budget(Sketch &sk, uint64_t budget, hipStream_t s);
 
 // node_ptr[n+1] and node_samples[N] (each list ascending) of the N-entry sketch.
 // owner: the sample id of every entry (written by the compaction), or null to have them

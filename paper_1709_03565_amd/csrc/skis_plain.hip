@@ -101,7 +101,8 @@ __global__ __launch_bounds__(PLAIN_BLOCK) void k_plain_init(uint32_t count, uint
             if (k < c.items_cap) c.items_out[k] = make_int4((int32_t)t, r.y + 1, r.w, (int32_t)np);
             else atomicOr(c.err, 2);
         }
-        plain_visit(c, t, u1[i0 + t]);
+        const int32_t u = u1[i0 + t];
+        if (u >= 0) plain_visit(c, t, u); // -1: a RIS sample, no first live in-edge
     }
 }
 

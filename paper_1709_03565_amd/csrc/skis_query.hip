@@ -163,7 +163,8 @@ __global__ __launch_bounds__(EST_BLOCK) void k_estimate(const int64_t *__restric
             if (flags >> r & 1) buf[pos++] = mine[r];
         __syncthreads();
 
-        for (int t = tid; t < nu; t += EST_BLOCK) neumaier_add(sq, cq, qv[buf[t]]);
+        if (qv)
+            for (int t = tid; t < nu; t += EST_BLOCK) neumaier_add(sq, cq, qv[buf[t]]);
         maxnu = nu > maxnu ? nu : maxnu;
         int64_t dl[IPT];
         int64_t acc = 0;
@@ -379,7 +380,7 @@ __global__ __launch_bounds__(256) void k_greedy_argmax(int32_t n, int round, uin
             const bool in = v < n;
             c[u] = in ? chosen[v] : (uint8_t)1;
             d[u] = in ? delta[v] : 0;
-            q[u] = in ? qv[v] : 0.0;
+            q[u] = in && qv ? qv[v] : 0.0;
             if (recounted && in) spare[v] = 0;
         }
 #pragma unroll
@@ -611,7 +612,8 @@ __global__ __launch_bounds__(256) void k_greedy_final(int32_t k, uint64_t T, dou
 {
     __shared__ double ps[256], pc[256];
     double s = 0.0, c = 0.0;
-    for (int32_t r = threadIdx.x; r < k; r += 256) neumaier_add(s, c, qv[seeds[r]]);
+    if (qv)
+        for (int32_t r = threadIdx.x; r < k; r += 256) neumaier_add(s, c, qv[seeds[r]]);
     ps[threadIdx.x] = s;
     pc[threadIdx.x] = c;
     __syncthreads();
@@ -676,7 +678,7 @@ void estimate_batch(const Sketch &sk, QueryScratch &qs, int32_t Q, const int64_t
     for (int64_t q0 = 0; q0 < Q; q0 += (int64_t)batch) {
         const int64_t nq = (Q - q0) < (int64_t)batch ? (Q - q0) : (int64_t)batch;
         hipLaunchKernelGGL(k_estimate<false>, dim3((unsigned)nq), dim3(EST_BLOCK), 0, s, (const int64_t *)nullptr, q0,
-                           set_ptr, set_nodes, sk.n, sk.T, sk.Gamma, sk.q.ptr, sk.node_ptr.ptr, sk.node_samples.ptr,
+                           set_ptr, set_nodes, sk.n, sk.T, sk.est_scale(), sk.est_q(), sk.node_ptr.ptr, sk.node_samples.ptr,
                            qs.bitmaps.ptr, per, (uint32_t *)nullptr, (uint64_t)0,
                            reinterpret_cast<unsigned long long *>(cov), est, qs.err.ptr);
         SKIS_HIP_TRY(hipGetLastError());
@@ -694,8 +696,8 @@ void estimate_batch(const Sketch &sk, QueryScratch &qs, int32_t Q, const int64_t
         for (uint64_t g0 = 0; g0 < large.size(); g0 += group) {
             const uint64_t ng = std::min<uint64_t>(group, large.size() - g0);
             hipLaunchKernelGGL(k_estimate<true>, dim3((unsigned)ng), dim3(EST_BLOCK), 0, s,
-                               (const int64_t *)qlist.ptr, (int64_t)g0, set_ptr, set_nodes, sk.n, sk.T, sk.Gamma,
-                               sk.q.ptr, sk.node_ptr.ptr, sk.node_samples.ptr, qs.bitmaps.ptr, per, nodebits.ptr,
+                               (const int64_t *)qlist.ptr, (int64_t)g0, set_ptr, set_nodes, sk.n, sk.T, sk.est_scale(),
+                               sk.est_q(), sk.node_ptr.ptr, sk.node_samples.ptr, qs.bitmaps.ptr, per, nodebits.ptr,
                                wordsN, reinterpret_cast<unsigned long long *>(cov), est, qs.err.ptr);
             SKIS_HIP_TRY(hipGetLastError());
         }
@@ -721,14 +723,14 @@ void estimate_launch(const Sketch &sk, int32_t nq, const int64_t *set_ptr, const
     const uint64_t per = bitmap_words;
     if (nq > 0) {
         hipLaunchKernelGGL(k_estimate<false>, dim3((unsigned)nq), dim3(EST_BLOCK), 0, s, (const int64_t *)nullptr,
-                           (int64_t)0, set_ptr, set_nodes, sk.n, sk.T, sk.Gamma, sk.q.ptr, sk.node_ptr.ptr,
+                           (int64_t)0, set_ptr, set_nodes, sk.n, sk.T, sk.est_scale(), sk.est_q(), sk.node_ptr.ptr,
                            sk.node_samples.ptr, bitmaps, per, (uint32_t *)nullptr, (uint64_t)0, cov, est, err);
         SKIS_HIP_TRY(hipGetLastError());
     }
     if (nlarge > 0) {
         const uint64_t wordsN = ((uint64_t)sk.n + 31) / 32;
         hipLaunchKernelGGL(k_estimate<true>, dim3((unsigned)nlarge), dim3(EST_BLOCK), 0, s, large, (int64_t)0,
-                           set_ptr, set_nodes, sk.n, sk.T, sk.Gamma, sk.q.ptr, sk.node_ptr.ptr, sk.node_samples.ptr,
+                           set_ptr, set_nodes, sk.n, sk.T, sk.est_scale(), sk.est_q(), sk.node_ptr.ptr, sk.node_samples.ptr,
                            bitmaps, per, nodebits, wordsN, cov, est, err);
         SKIS_HIP_TRY(hipGetLastError());
     }
@@ -740,7 +742,7 @@ void estimate_launch_small(const Sketch &sk, int64_t q0, int32_t nq, const int64
 {
     if (nq <= 0) return;
     hipLaunchKernelGGL(k_estimate<false>, dim3((unsigned)nq), dim3(EST_BLOCK), 0, s, (const int64_t *)nullptr, q0,
-                       set_ptr, set_nodes, sk.n, sk.T, sk.Gamma, sk.q.ptr, sk.node_ptr.ptr, sk.node_samples.ptr,
+                       set_ptr, set_nodes, sk.n, sk.T, sk.est_scale(), sk.est_q(), sk.node_ptr.ptr, sk.node_samples.ptr,
                        bitmaps, bitmap_words, (uint32_t *)nullptr, (uint64_t)0, cov, est, err);
     SKIS_HIP_TRY(hipGetLastError());
 }
@@ -752,7 +754,7 @@ void estimate_launch_large(const Sketch &sk, const int64_t *qlist, int64_t g0, i
     if (ng <= 0) return;
     const uint64_t wordsN = ((uint64_t)sk.n + 31) / 32;
     hipLaunchKernelGGL(k_estimate<true>, dim3((unsigned)ng), dim3(EST_BLOCK), 0, s, qlist, g0, set_ptr, set_nodes,
-                       sk.n, sk.T, sk.Gamma, sk.q.ptr, sk.node_ptr.ptr, sk.node_samples.ptr, bitmaps, bitmap_words,
+                       sk.n, sk.T, sk.est_scale(), sk.est_q(), sk.node_ptr.ptr, sk.node_samples.ptr, bitmaps, bitmap_words,
                        nodebits, wordsN, cov, est, err);
     SKIS_HIP_TRY(hipGetLastError());
 }
@@ -818,8 +820,8 @@ void greedy(const Sketch &sk, QueryScratch &qs, int32_t k, int32_t *seeds, uint6
     }
     const unsigned gr = gridq(nit * RECOUNT_LANES, 256, 8);
     for (int32_t r = 0; r < k; ++r) {
-        hipLaunchKernelGGL(k_greedy_argmax, dim3(ga), dim3(256), 0, s, n, (int)r, sk.T, sk.Gamma, delta.ptr,
-                           delta_spare.ptr, sk.q.ptr, chosen.ptr, pg.ptr, pv.ptr, st.ptr, seeds,
+        hipLaunchKernelGGL(k_greedy_argmax, dim3(ga), dim3(256), 0, s, n, (int)r, sk.T, sk.est_scale(), delta.ptr,
+                           delta_spare.ptr, sk.est_q(), chosen.ptr, pg.ptr, pv.ptr, st.ptr, seeds,
                            reinterpret_cast<unsigned long long *>(marg));
         if (sk.T) {
             // the cover lowers delta itself unless the round recounts, decided on the device
@@ -831,7 +833,7 @@ void greedy(const Sketch &sk, QueryScratch &qs, int32_t k, int32_t *seeds, uint6
         }
     }
     SKIS_HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_greedy_final, dim3(1), dim3(256), 0, s, k, sk.T, sk.Gamma, seeds, sk.q.ptr, st.ptr);
+    hipLaunchKernelGGL(k_greedy_final, dim3(1), dim3(256), 0, s, k, sk.T, sk.est_scale(), seeds, sk.est_q(), st.ptr);
     SKIS_HIP_TRY(hipGetLastError());
     GreedyState hs;
     SKIS_HIP_TRY(hipMemcpyAsync(&hs, st.ptr, sizeof(hs), hipMemcpyDeviceToHost, s));

@@ -6,10 +6,12 @@
 //                  with its visited set and node list; the unexpanded nodes of all slots
 //                  form one flat list of (slot, edge range) items, and the lanes sweep the
 //                  edges of all items four at a time (two 16-byte loads and one Philox call
-//                  per aligned edge quad).  GLOBAL=false keeps the visited set in LDS (an
-//                  open-addressing hash) and hands a sample to the global tier when it
-//                  outgrows the hash or meets an in-degree above big_row; GLOBAL=true keeps
-//                  a bitmap of n bits and a node list of n entries per slot in HBM.
+//                  per aligned edge quad).  Tiers 0 and 1 keep the visited set in LDS (an
+//                  open-addressing hash) and hand a sample to the next tier when it outgrows
+//                  the hash or meets an in-degree above big_row; tier 2 keeps a hash and a
+//                  node list sized to the sample in HBM (one sample per one-wave workgroup,
+//                  thousands in flight); tier 3 keeps a bitmap of n bits and a node list of
+//                  n entries per sample in HBM (one sample per 1024-thread workgroup).
 //   k_gather_*     sorts each sample's nodes and writes the CSR in sample order.
 //
 // Sample j is a pure function of (graph, seed, j): the order in which a sample's nodes are
@@ -38,6 +40,9 @@ enum : int { F_ACTIVE = 1, F_ROOTPEND = 2, F_DEFER = 4, F_CLEAR = 8, F_RESUME = 
 // ---------------------------------------------------------------------------------------
 // Root and first live in-edge of every sample.
 //   rec[i] = (root, i*, row begin, row end), u1[i] = col[i*], for sample j = j0 + i.
+//   With ris set (plain RIS samples, Sec. 2.3.1): root = the bucket drawn uniformly,
+//   rec[i] = (root, row begin - 1, row begin, row end) and u1[i] = -1 -- no first live
+//   in-edge, every in-edge of the root flips its own coin.
 // ---------------------------------------------------------------------------------------
 //   range (device, may be null): {base, count} of a chunk read at launch; the thread then
 //   covers i = base .. base+count-1 instead of 0 .. count-1.
@@ -46,7 +51,8 @@ __global__ __launch_bounds__(256) void k_roots(uint64_t j0, uint32_t count, cons
                                                int32_t n, uint64_t C, const AliasEntry *__restrict__ alias,
                                                const int32_t *__restrict__ row_ptr, const double *__restrict__ q,
                                                const double *__restrict__ P, const uint2 *__restrict__ edges,
-                                               const uint32_t *__restrict__ wbits, int4 *__restrict__ rec, int32_t *__restrict__ u1, int *__restrict__ err)
+                                               const uint32_t *__restrict__ wbits, int4 *__restrict__ rec, int32_t *__restrict__ u1, int *__restrict__ err,
+                                               int ris)
 {
     const uint32_t base = range ? (uint32_t)range[0] : 0u;
     const uint32_t cnt = range ? (uint32_t)range[1] : count;
@@ -57,6 +63,13 @@ __global__ __launch_bounds__(256) void k_roots(uint64_t j0, uint32_t count, cons
         uint64_t X, Y;
         philox2x64(0u, jl, jh, TAG_ROOT, seed_lo, seed_hi, X, Y);
         const uint64_t b = __umul64hi(X, (uint64_t)n);
+        if (ris) {
+            const int32_t root = (int32_t)b; // b < n
+            const int32_t rb = row_ptr[root], re = row_ptr[root + 1];
+            rec[i] = make_int4(root, rb - 1, rb, re);
+            u1[i] = -1;
+            continue;
+        }
         const uint64_t r = __umul64hi(Y, C);
         const AliasEntry ae = alias[b];
         const int32_t root = r < ae.thr ? (int32_t)b : ae.alias;
@@ -140,9 +153,11 @@ struct SampleArgs {
     int *overflow;
     unsigned long long *tier_stats; // [5]: samples finished by this launch, their entries, their edges
                                     // probed; the edges and the nodes (items) this launch expanded
-    uint32_t *gbits;            // global tier: [slots][words]
-    int32_t *glist;             // global tier: [slots][n]
+    uint32_t *gbits;            // bitmap tier: [slots][words]
+    int32_t *glist;             // bitmap tier: [slots][n]
     uint64_t words;
+    int32_t *ghash;             // hash tier: [slots][HCAP], -1 = empty (every launch leaves it so)
+    uint2 *glist2;              // hash tier: [slots][RCAP] (node id, its hash slot) in discovery order
     // handover to the next tier: sample k of `deferred` (k < ho_cap_out) leaves its state in
     // ho_state_out[k] and its nodes in ho_nodes_out[k * ho_stride_out ...]
     Handover *ho_state_out;
@@ -165,7 +180,9 @@ struct SampleArgs {
 // groups of four edges, one Philox call) a lane takes per sweep (2 keeps more loads in
 // flight, 1 needs fewer registers).
 // TIER: 0 the first LDS tier (hands its overflowing samples on with their state), 1 the
-// second LDS tier (resumes them), 2 the HBM tier (visited sets in global memory).
+// second LDS tier (resumes them and hands its own on), 2 the HBM hash tier (a hash of HCAP
+// slots and a list of RCAP nodes per sample in global memory; resumes and hands on), 3 the
+// HBM bitmap tier (a bitmap of n bits and a list of n nodes per sample; finishes every sample).
 // Arguments used once per pass or less are read from the argument segment where they are used
 // (see karg_at); the ones the edge sweep uses every pass stay in scalar registers.  SampleArgs is
 // k_sample's only parameter, so it starts the segment and a field's offset is its offsetof.
@@ -175,13 +192,16 @@ static_assert(std::is_standard_layout<SampleArgs>::value, "argument offsets need
 template <int BLOCK, int S, int RCAP, int HCAP, int ICAP, int QPL, int TIER>
 __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
 {
-    constexpr bool GLOBAL = TIER == 2;
-    constexpr bool HO_OUT = TIER <= 1, HO_IN = TIER >= 1;
+    constexpr bool GLOBAL = TIER == 3; // bitmap visited sets: a sample never outgrows them
+    constexpr bool GHASH = TIER == 2;  // hash visited sets in global memory
+    constexpr bool LDSV = TIER <= 1;   // hash visited sets in LDS
+    constexpr bool HO_OUT = TIER <= 2, HO_IN = TIER >= 1;
     constexpr int IDBATCH = id_batch<S>();
     static_assert(GLOBAL || HCAP > RCAP, "the hash must be larger than the node list");
-    static_assert(GLOBAL || HCAP <= 65535, "list entries are 8- or 16-bit hash slot indexes");
-    constexpr int HSZ = GLOBAL ? 1 : S * HCAP;
-    constexpr int LSZ = GLOBAL ? 1 : S * RCAP;
+    static_assert(!LDSV || HCAP <= 65535, "list entries are 8- or 16-bit hash slot indexes");
+    static_assert(!GHASH || BLOCK == 64, "the hash tier's workgroups are one wave");
+    constexpr int HSZ = LDSV ? S * HCAP : 1;
+    constexpr int LSZ = LDSV ? S * RCAP : 1;
     constexpr int IPT = (ICAP + BLOCK - 1) / BLOCK;
     static_assert(S <= 64, "slots are owned by the lanes of wave 0");
     static_assert(IDBATCH >= S, "one refill must cover every empty slot");
@@ -234,12 +254,27 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
     const unsigned long long id_base = SKIS_KARG(id_base_dev) ? *SKIS_KARG(id_base_dev) : 0ull;
 
     auto list_ptr = [&](int s) -> int32_t * { return a.glist + ((size_t)blockIdx.x * S + s) * (size_t)n; };
+    auto ghash_ptr = [&](int s) -> int32_t * { return a.ghash + ((size_t)blockIdx.x * S + s) * (size_t)HCAP; };
+    auto glist2_ptr = [&](int s) -> uint2 * { return a.glist2 + ((size_t)blockIdx.x * S + s) * (size_t)RCAP; };
     // node at position t of slot s's list
     auto list_node = [&](int s, int t) -> int32_t {
         if constexpr (GLOBAL) return list_ptr(s)[t];
+        else if constexpr (GHASH) return (int32_t)glist2_ptr(s)[t].x;
         else return sh_hash[s * HCAP + sh_lidx[s * RCAP + t]];
     };
     auto bits_ptr = [&](int s) -> uint32_t * { return a.gbits + ((size_t)blockIdx.x * S + s) * a.words; };
+    // The hash tier keeps its visited sets and lists in global memory, written by some lanes
+    // and read by others after a barrier: its barriers order global memory at workgroup scope
+    // (the stores have completed before any lane goes on).  The LDS tiers need LDS order only.
+    auto bsync = [&]() {
+        if constexpr (GHASH) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        } else {
+            block_sync<BLOCK>();
+        }
+    };
 
     // Home slot of node u in an HCAP-entry hash: multiplicative hashing, then the high
     // half of the product with HCAP maps the 32-bit hash onto [0, HCAP).
@@ -247,9 +282,34 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
         return (uint32_t)(((uint64_t)((uint32_t)u * 0x9E3779B1u) * (uint64_t)HCAP) >> 32);
     };
 
+    // Inserts u into an HCAP-slot hash in global memory (linear probing from its home slot);
+    // returns the slot it took, -1 if u was there already, -2 if the hash is full.
+    auto ghash_insert = [&](int32_t *H, int32_t u) -> int {
+        uint32_t h = hash_slot(u);
+#pragma unroll 1
+        for (int k = 0; k < HCAP; ++k) {
+            const int32_t old = atomicCAS(&H[h], -1, u);
+            if (old == -1) return (int)h;
+            if (old == u) return -1;
+            h = h + 1 == (uint32_t)HCAP ? 0u : h + 1;
+        }
+        return -2;
+    };
+
     // Adds u to slot s's sample if it is not there yet.
     auto visit = [&](int s, int32_t u) {
-        if constexpr (GLOBAL) {
+        if constexpr (GHASH) {
+            // a sample already handed on restarts from its snapshot in the next tier
+            if (s_flags[s] & F_DEFER) return;
+            const int h = ghash_insert(ghash_ptr(s), u);
+            if (h >= 0) {
+                const int pos = atomicAdd(&s_count[s], 1);
+                if (pos < RCAP) glist2_ptr(s)[pos] = make_uint2((uint32_t)u, (uint32_t)h);
+                else atomicOr(&s_flags[s], F_DEFER);
+            } else if (h == -2) {
+                atomicOr(&s_flags[s], F_DEFER);
+            }
+        } else if constexpr (GLOBAL) {
             const uint32_t bit = 1u << (u & 31);
             const uint32_t old = atomicOr(bits_ptr(s) + (u >> 5), bit);
             if (!(old & bit)) {
@@ -292,10 +352,10 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
         s_ccur = 0;
     }
     // staging space is reserved STAGE_CHUNK entries at a time per workgroup (lane 0 of
-    // wave 0 keeps the open chunk [st_base, st_end)); the HBM tier reserves exactly
-    constexpr unsigned long long STAGE_CHUNK = GLOBAL ? 0ull : 8ull * S * RCAP;
+    // wave 0 keeps the open chunk [st_base, st_end)); the HBM tiers reserve exactly
+    constexpr unsigned long long STAGE_CHUNK = LDSV ? 8ull * S * RCAP : 0ull;
     unsigned long long st_base = 0, st_end = 0;
-    block_sync<BLOCK>();
+    bsync();
 
     for (;;) {
         // ---- A1: wave 0, lane s owns slot s: finished and handed-on samples -----------------
@@ -370,7 +430,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                 }
             }
         }
-        block_sync<BLOCK>();
+        bsync();
 
         // ---- B1: write out finished samples, clear their visited sets ----------------------
         // (before admission, so that a slot finished in this pass takes its next sample now)
@@ -379,13 +439,32 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
             if (fs != F_CLEAR) continue;
             const int cnt = s_wo_cnt[s];
             const unsigned long long off = s_wo_off[s];
-            if constexpr (!GLOBAL) {
+            if constexpr (GHASH) {
+                int32_t *H = ghash_ptr(s);
+                const uint2 *GL = glist2_ptr(s);
+                if (cnt < 0) { // a sample handed on: its nodes to the handover, then a full clear
+                    if (cnt == -2) {
+                        const int c = s_snap[s].count;
+                        int32_t *dst = SKIS_KARG(ho_nodes_out) + (size_t)off * (size_t)SKIS_KARG(ho_stride_out);
+                        for (int t = tid; t < c; t += BLOCK) dst[t] = (int32_t)GL[t].x;
+                    }
+                    for (int t = tid; t < HCAP; t += BLOCK) H[t] = -1;
+                } else {
+                    // a finished sample holds every key in its list: write them and clear their slots
+                    const int rc = s_count[s];
+                    for (int t = tid; t < rc; t += BLOCK) {
+                        const uint2 e = GL[t];
+                        if (t < cnt) SKIS_KARG(staging)[off + t] = (int32_t)e.x;
+                        H[e.y] = -1;
+                    }
+                }
+            } else if constexpr (!GLOBAL) {
                 if (cnt < 0) { // a sample handed on: its nodes to the handover, then a full clear
                     if (HO_OUT && cnt == -2) {
                         const int c = s_snap[s].count;
                         int32_t *dst = SKIS_KARG(ho_nodes_out) + (size_t)off * (size_t)SKIS_KARG(ho_stride_out);
                         for (int t = tid; t < c; t += BLOCK) dst[t] = sh_hash[s * HCAP + sh_lidx[s * RCAP + t]];
-                        block_sync<BLOCK>();
+                        bsync();
                     }
                     for (int t = tid; t < HCAP; t += BLOCK) sh_hash[s * HCAP + t] = -1;
                 } else {
@@ -406,7 +485,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                 for (int t = tid; t < rc; t += BLOCK) B[L[t] >> 5] = 0u;
             }
         }
-        block_sync<BLOCK>();
+        bsync();
         if (tid < S && s_flags[tid] == F_CLEAR) {
             s_flags[tid] = 0;
             s_wo_cnt[tid] = 0;
@@ -467,8 +546,11 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                     const uint32_t i = s_cidx[b][c];
                     const int4 r = s_crec[b][c];
                     const int32_t u = s_cu1[b][c];
+                    // a RIS record has no first live in-edge: u = -1 and i* = row begin - 1
+                    const bool ris_rec = u == -1;
                     if (cd >= (unsigned long long)IDBATCH || i >= (uint32_t)(id_base + (SKIS_KARG(id_list) ? 0x7FFFFFFFull : id_count)) ||
-                        (uint32_t)r.x >= (uint32_t)n || (uint32_t)u >= (uint32_t)n || r.y < r.z || r.w <= r.y ||
+                        (uint32_t)r.x >= (uint32_t)n ||
+                        (ris_rec ? (r.y != r.z - 1 || r.w < r.z) : ((uint32_t)u >= (uint32_t)n || r.y < r.z || r.w <= r.y)) ||
                         (int64_t)r.w > 4 * a.nquads) {
                         atomicOr(SKIS_KARG(overflow), 8); // bounds guard: the sample is left out
                     } else {
@@ -476,7 +558,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                     s_rib[s] = r.y + 1;
                     s_rie[s] = r.w;
                     s_probed[s] = (unsigned long long)(r.w - r.z);
-                    s_count[s] = 2;
+                    s_count[s] = ris_rec ? 1 : 2;
                     s_cursor[s] = 1;
                     int nf = F_ACTIVE | (r.y + 1 < r.w ? F_ROOTPEND : 0);
                     if (!GLOBAL && (uint32_t)(r.w - r.z) > a.big_row) nf |= F_DEFER;
@@ -487,8 +569,8 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                         if (SKIS_KARG(ho_state_in) && rec_k < SKIS_KARG(ho_cap_in)) {
                             const Handover h = SKIS_KARG(ho_state_in)[rec_k];
                             const int cur = h.cursor_rp >> 1;
-                            const int cap = GLOBAL ? n : RCAP; // the HBM tier's list holds n nodes
-                            if (h.count >= 2 && h.count <= cap && cur >= 1 && cur <= h.count) {
+                            const int cap = GLOBAL ? n : RCAP; // the bitmap tier's list holds n nodes
+                            if (h.count >= 1 && h.count <= cap && cur >= 1 && cur <= h.count) {
                                 // its nodes are put back into the visited set and list in phase B1r
                                 resumed = true;
                                 s_count[s] = h.count;
@@ -501,18 +583,27 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                         }
                     }
                     if (resumed) {
+                    } else if constexpr (GHASH) {
+                        // root and u1 differ (no self-loops), so they take two slots
+                        int32_t *H = ghash_ptr(s);
+                        uint2 *GL = glist2_ptr(s);
+                        const int32_t keys[2] = {r.x, u};
+                        for (int t = 0; t < (ris_rec ? 1 : 2); ++t)
+                            GL[t] = make_uint2((uint32_t)keys[t], (uint32_t)ghash_insert(H, keys[t]));
                     } else if constexpr (GLOBAL) {
                         int32_t *L = list_ptr(s);
-                        L[0] = r.x;
-                        L[1] = u;
                         uint32_t *B = bits_ptr(s);
+                        L[0] = r.x;
                         atomicOr(B + (r.x >> 5), 1u << (r.x & 31));
-                        atomicOr(B + (u >> 5), 1u << (u & 31));
+                        if (!ris_rec) {
+                            L[1] = u;
+                            atomicOr(B + (u >> 5), 1u << (u & 31));
+                        }
                     } else {
                         // root and u1 differ (no self-loops), so they take two slots
                         int32_t *H = sh_hash + s * HCAP;
                         const int32_t keys[2] = {r.x, u};
-                        for (int t = 0; t < 2; ++t) {
+                        for (int t = 0; t < (ris_rec ? 1 : 2); ++t) {
                             uint32_t h = hash_slot(keys[t]);
                             while (H[h] != -1) h = h + 1 == (uint32_t)HCAP ? 0u : h + 1;
                             H[h] = keys[t];
@@ -578,7 +669,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                 s_alive = amask != 0ull;
             }
         }
-        block_sync<BLOCK>();
+        bsync();
 
         // ---- B1r: resumed samples (admitted above) put their nodes back into hash and list ---
         if constexpr (HO_IN) {
@@ -594,6 +685,14 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                         L[t] = u;
                         atomicOr(B + (u >> 5), 1u << (u & 31));
                     }
+                } else if constexpr (GHASH) {
+                    // distinct nodes, fewer than HCAP: each finds an empty slot
+                    int32_t *H = ghash_ptr(s);
+                    uint2 *GL = glist2_ptr(s);
+                    for (int t = tid; t < c; t += BLOCK) {
+                        const int32_t u = src[t];
+                        GL[t] = make_uint2((uint32_t)u, (uint32_t)ghash_insert(H, u));
+                    }
                 } else {
                     int32_t *H = sh_hash + s * HCAP;
                     for (int t = tid; t < c; t += BLOCK) {
@@ -605,7 +704,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                     }
                 }
             }
-            block_sync<BLOCK>();
+            bsync();
         }
 
         // ---- B2: item edge ranges ----------------------------------------------------------
@@ -681,7 +780,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                 it_pb[it] = end > beg ? ((end - 1) >> 2) - (beg >> 2) + 1 : 0;
             }
         }
-        block_sync<BLOCK>();
+        bsync();
 
         // ---- B3: prefix sum of edge quads over the items -----------------------------------
         {
@@ -716,7 +815,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                 }
             }
         }
-        block_sync<BLOCK>();
+        bsync();
 
         // ---- B4: live-edge coins for every edge quad, visits ------------------------------
         // Each lane takes qpl consecutive quads (qpl = the fewest, up to QPL, that cover the
@@ -823,7 +922,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                 visit(sl, (int32_t)((c & 1) ? q.z : q.x));
             }
         }
-        block_sync<BLOCK>();
+        bsync();
         if (!s_alive) break;
     }
     if (SKIS_KARG(tier_stats)) {
@@ -1189,9 +1288,9 @@ __global__ __launch_bounds__(256) void k_fill(uint64_t count, T *__restrict__ p,
 struct ChainCtl {
     unsigned long long cursor;            // first sample id not yet handed to a chunk
     unsigned long long base, count;       // the current chunk: ids [base, base + count)
-    unsigned long long next0, next1, next2; // id counters of the three tiers
-    unsigned long long nd0, nd1;          // samples handed on by tier 0 / tier 1 in this chunk
-    unsigned long long tot0, tot1;        // the same, summed over chunks
+    unsigned long long next0, next1, next2, next3; // id counters of the four tiers
+    unsigned long long nd0, nd1, nd2;     // samples handed on by tiers 0, 1, 2 in this chunk
+    unsigned long long tot0, tot1, tot2;  // the same, summed over chunks
     unsigned long long replays;
 };
 
@@ -1206,8 +1305,10 @@ __global__ __launch_bounds__(64) void k_chain_begin(ChainCtl *c, uint64_t T, uin
     c->next0 = 0;
     c->next1 = 0;
     c->next2 = 0;
+    c->next3 = 0;
     c->nd0 = 0;
     c->nd1 = 0;
+    c->nd2 = 0;
 }
 
 __global__ __launch_bounds__(64) void k_chain_end(ChainCtl *c)
@@ -1215,7 +1316,21 @@ __global__ __launch_bounds__(64) void k_chain_end(ChainCtl *c)
     if (threadIdx.x != 0) return;
     c->tot0 += c->nd0;
     c->tot1 += c->nd1;
+    c->tot2 += c->nd2;
     c->replays += 1;
+}
+
+// out[0] = the smallest t in [1, T] with sptr[t] >= budget (T if there is none); one thread.
+__global__ void k_first_reaching(const int64_t *__restrict__ sptr, uint64_t T, int64_t budget,
+                                 unsigned long long *__restrict__ out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    uint64_t lo = 1, hi = T;
+    while (lo < hi) {
+        const uint64_t mid = lo + ((hi - lo) >> 1);
+        if (sptr[mid] >= budget) hi = mid; else lo = mid + 1;
+    }
+    out[0] = lo;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1236,7 +1351,7 @@ struct Counters {
     unsigned long long n_medium;
     int overflow;
     int pad;
-    unsigned long long tier[3][5]; // per tier: samples finished, their entries, their edges probed,
+    unsigned long long tier[4][5]; // per tier: samples finished, their entries, their edges probed,
                                    // edges and nodes the launch expanded
 };
 
@@ -1275,14 +1390,21 @@ static const Variant kTierMidV[] = {
     {64, 1, 1024, 1, k_sample<64, 1, 1024, 1368, 64, 1, 1>},
     {256, 8, 1024, 2, k_sample<256, 8, 1024, 1368, 1024, 2, 1>},
 };
-// One sample per workgroup: the samples that reach this tier are few and large, so the
-// chip is filled with workgroups rather than slots; the HBM buffers of all slots are kept
-// within TIERG_BUDGET bytes.
+// Third tier: one sample per one-wave workgroup, its visited set a hash of TIERH_HCAP slots
+// and its node list TIERH_RCAP entries in HBM, so that every compute unit holds as many
+// samples as waves fit (the samples that outgrow 1024 nodes number about 1 % on the 1.4B-edge
+// workload, and each takes many passes).
+constexpr int TIERH_RCAP = 12288;
+constexpr int TIERH_HCAP = 16384;
+static SampleKernel const kTierHash = k_sample<64, 1, TIERH_RCAP, TIERH_HCAP, 64, 1, 2>;
+// Fourth tier: one sample per workgroup with a bitmap of n bits and a node list of n entries;
+// the few samples that outgrow the hash tier or meet an in-degree above 2^20 take sixteen waves
+// each; the HBM buffers of all slots are kept within TIERG_BUDGET bytes.
 constexpr int TIERG_SLOTS = 1;
-constexpr int TIERG_BLOCK = 1024; // sixteen waves per sample: the largest samples bound the tier's time
+constexpr int TIERG_BLOCK = 1024;
 constexpr int TIERG_PER_CU = TIERG_BLOCK >= 512 ? 1 : 512 / TIERG_BLOCK;
 constexpr uint64_t TIERG_BUDGET = 32ull << 30;
-static SampleKernel const kTierGlobal = k_sample<TIERG_BLOCK, TIERG_SLOTS, 1, 1, 8 * TIERG_BLOCK, 2, 2>;
+static SampleKernel const kTierGlobal = k_sample<TIERG_BLOCK, TIERG_SLOTS, 1, 1, 8 * TIERG_BLOCK, 2, 3>;
 
 static const Variant &pick_variant(const Variant *vs, size_t nv, uint32_t threads, uint32_t slots, uint32_t visited,
                                    uint32_t qpl)
@@ -1329,7 +1451,7 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
     if (T >= (1ull << 31)) throw Error{SKIS_EINVAL, "num_samples must be below 2^31"};
     const uint32_t count = (uint32_t)T;
     const uint32_t seed_lo = (uint32_t)seed, seed_hi = (uint32_t)(seed >> 32);
-    constexpr int NEV = 10;
+    constexpr int NEV = 12;
     hipEvent_t ev[NEV];
     for (auto &e : ev) SKIS_HIP_TRY(hipEventCreate(&e));
     struct EvGuard {
@@ -1339,13 +1461,13 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
             for (int i = 0; i < NEV; ++i) (void)hipEventDestroy(e[i]);
         }
     } evg{ev};
-    bool ran_mid = false, ran_global = false;
+    bool ran_mid = false, ran_hash = false, ran_global = false;
 
     // every device buffer a kernel below dereferences must exist (checked on the host)
     auto need = [](const void *p, const char *what) {
         if (!p) throw Error{SKIS_EHIP, std::string("internal error: null device buffer ") + what};
     };
-    need(prep.alias.ptr, "alias");
+    if (!cfg.ris) need(prep.alias.ptr, "alias");
     need(prep.row_ptr.ptr, "row_ptr");
     need(prep.q.ptr, "q");
     need(prep.P.ptr, "P");
@@ -1363,7 +1485,8 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
     if (cfg.form != 2) { // the captured form draws the roots inside its chain, chunk by chunk
         hipLaunchKernelGGL(k_roots, dim3(grid_cap(count, 256, 64)), dim3(256), 0, s, (uint64_t)0, count,
                            (const unsigned long long *)nullptr, seed_lo, seed_hi, n, prep.C, prep.alias.ptr,
-                           prep.row_ptr.ptr, prep.q.ptr, prep.P.ptr, prep.edges.ptr, prep.wbits.ptr, rec.ptr, u1.ptr, rerr.ptr);
+                           prep.row_ptr.ptr, prep.q.ptr, prep.P.ptr, prep.edges.ptr, prep.wbits.ptr, rec.ptr, u1.ptr, rerr.ptr,
+                           (int)cfg.ris);
         SKIS_HIP_TRY(hipGetLastError());
     }
     SKIS_HIP_TRY(hipEventRecord(ev[1], s));
@@ -1407,13 +1530,19 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
     const double per_sample = entries_per_sample_hint(n, m);
     uint64_t cap = cfg.staging_entries ? cfg.staging_entries : staging_bound((uint64_t)((double)count * per_sample), 1);
     const uint64_t words = ((uint64_t)n + 31) / 32;
-    // global tier: every slot holds a bitmap of n bits and a node list of n entries
+    // bitmap tier: every slot holds a bitmap of n bits and a node list of n entries
     const uint64_t slot_bytes = (uint64_t)n * 4ull + words * 4ull;
     uint64_t nbg_mem = TIERG_BUDGET / (slot_bytes * TIERG_SLOTS);
     if (nbg_mem < 1) nbg_mem = 1;
     const int nbg = (int)std::min<uint64_t>((uint64_t)TIERG_PER_CU * cus, nbg_mem);
+    // hash tier: as many one-wave workgroups as are resident at once, each with its own hash
+    // and list
+    const int nbh = occupancy_blocks(kTierHash, 64) * cus;
     DevBuf<uint32_t> deferred2;
     deferred2.alloc(arena, count);
+    const int ho2_stride = (int)vm.visited; // tier 1 -> hash tier records
+    const int ho3_stride = TIERH_RCAP;      // hash tier -> bitmap tier records
+    constexpr uint64_t HO3_MAX = 4096;      // records of the samples that outgrow the hash tier
 
     auto read_counters = [&]() {
         SKIS_HIP_TRY(hipMemcpyAsync(&hc, ctr.ptr, sizeof(hc), hipMemcpyDeviceToHost, s));
@@ -1423,13 +1552,25 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
         hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(1), dim3(64), 0, s, (uint64_t)1, &ctr.ptr->next, 0ull);
         hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(1), dim3(64), 0, s, (uint64_t)1, &ctr.ptr->n_deferred, 0ull);
     };
+    // the hash tier's hashes start empty (-1) and every launch leaves them so
+    DevBuf<int32_t> ghash;
+    DevBuf<uint2> glist2;
+    auto alloc_hash_tier = [&]() {
+        ghash.alloc(arena, (uint64_t)nbh * TIERH_HCAP);
+        glist2.alloc(arena, (uint64_t)nbh * TIERH_RCAP);
+        hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_cap((uint64_t)nbh * TIERH_HCAP, 256)), dim3(256), 0, s,
+                           (uint64_t)nbh * TIERH_HCAP, ghash.ptr, -1);
+        SKIS_HIP_TRY(hipGetLastError());
+        need(ghash.ptr, "hash tier hashes");
+        need(glist2.ptr, "hash tier lists");
+    };
 
-    // Captured form: the whole chain for one chunk of ids -- chunk bounds, roots, the three
+    // Captured form: the whole chain for one chunk of ids -- chunk bounds, roots, the four
     // tiers, each reading its work count from device memory -- is captured once into a HIP
     // graph on a private stream and replayed ceil(T / chunk) times on s with no host
-    // round trip in between.  The HBM tier cannot be skipped on the host's word here, so
-    // its buffers are always allocated (each slot clears its own bits when its sample
-    // finishes, so they stay zero across replays).
+    // round trip in between.  The HBM tiers cannot be skipped on the host's word here, so
+    // their buffers are always allocated (each slot clears what its sample used when the
+    // sample leaves, so they stay clear across replays).
     auto sample_chain_graph = [&]() {
         // 2^24 ids by default: every chunk waits for its own largest samples, so fewer chunks
         // finish sooner (2^22 took 44 / 115 ms on the 1M-node WC / 4M-node TRI graphs, 2^24 37 / 67)
@@ -1446,19 +1587,25 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
         glist.alloc(arena, gslots * (uint64_t)n);
         hipLaunchKernelGGL(k_fill<uint32_t>, dim3(grid_cap(gslots * words, 256)), dim3(256), 0, s, gslots * words,
                            gbits.ptr, 0u);
+        alloc_hash_tier();
         need(gc.ptr, "chain control");
         need(gbits.ptr, "gbits");
         need(glist.ptr, "glist");
-        // handover from tier 1 to the HBM tier for the first ho2_cap samples tier 1 hands on
-        // in a chunk; tier 2 takes them in that order, so position p resumes from record p
+        // handover from tier 1 to the hash tier for the first ho2_cap samples tier 1 hands on
+        // in a chunk, and from the hash tier to the bitmap tier for the first ho3_cap; each
+        // tier takes its list in a scrambled order, and position p resumes from record p
         const uint64_t ho2_cap = std::min<uint64_t>(chunk, std::max<uint64_t>(1024, chunk / 64));
-        const int ho2_stride = (int)vm.visited;
-        DevBuf<Handover> ho2_state;
-        DevBuf<int32_t> ho2_nodes;
+        const uint64_t ho3_cap = std::min<uint64_t>(chunk, HO3_MAX);
+        DevBuf<Handover> ho2_state, ho3_state;
+        DevBuf<int32_t> ho2_nodes, ho3_nodes;
         ho2_state.alloc(arena, ho2_cap);
         ho2_nodes.alloc(arena, ho2_cap * (uint64_t)ho2_stride);
+        ho3_state.alloc(arena, ho3_cap);
+        ho3_nodes.alloc(arena, ho3_cap * (uint64_t)ho3_stride);
         need(ho2_state.ptr, "handover");
         need(ho2_nodes.ptr, "handover nodes");
+        need(ho3_state.ptr, "handover");
+        need(ho3_nodes.ptr, "handover nodes");
         struct GraphGuard {
             hipStream_t cs = nullptr;
             hipGraph_t g = nullptr;
@@ -1506,10 +1653,11 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
             A.overflow = &ctr.ptr->overflow;
             A.words = words;
             need(A.staging, "staging");
-            SampleArgs A0 = A, A1 = A, A2 = A;
+            SampleArgs A0 = A, A1 = A, A2 = A, A3 = A;
             A0.tier_stats = ctr.ptr->tier[0];
             A1.tier_stats = ctr.ptr->tier[1];
             A2.tier_stats = ctr.ptr->tier[2];
+            A3.tier_stats = ctr.ptr->tier[3];
             A0.next = &gc.ptr->next0;
             A0.id_list = nullptr;
             A0.id_count_dev = &gc.ptr->count;
@@ -1527,12 +1675,21 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
             A2.id_list = deferred2.ptr;
             A2.id_count_dev = &gc.ptr->nd1;
             A2.id_perm = 1; // the eager form shuffles on the host; here the order is scrambled in place
-            A2.deferred = deferred.ptr; // unused: the HBM tier finishes every sample
-            A2.n_deferred = &ctr.ptr->n_deferred; // unused for the same reason
-            A2.gbits = gbits.ptr;
-            A2.glist = glist.ptr;
-            A0.ho_state_out = ho_state.ptr; // tier 0 hands over, tier 1 resumes and hands over,
-            A0.ho_nodes_out = ho_nodes.ptr; // tier 2 resumes
+            A2.big_row = std::max<uint32_t>(cfg.big_row, 1u << 20);
+            A2.deferred = deferred.ptr; // tier 1 has read tier 0's list by now
+            A2.n_deferred = &gc.ptr->nd2;
+            A2.ghash = ghash.ptr;
+            A2.glist2 = glist2.ptr;
+            A3.next = &gc.ptr->next3;
+            A3.id_list = deferred.ptr;
+            A3.id_count_dev = &gc.ptr->nd2;
+            A3.id_perm = 1;
+            A3.deferred = deferred2.ptr;          // unused: the bitmap tier finishes every sample
+            A3.n_deferred = &ctr.ptr->n_deferred; // unused for the same reason
+            A3.gbits = gbits.ptr;
+            A3.glist = glist.ptr;
+            A0.ho_state_out = ho_state.ptr; // tiers 0-2 hand over, tiers 1-3 resume
+            A0.ho_nodes_out = ho_nodes.ptr;
             A0.ho_cap_out = ho_cap;
             A1.ho_state_in = ho_state.ptr;
             A1.ho_nodes_in = ho_nodes.ptr;
@@ -1546,6 +1703,14 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
             A2.ho_slot_in = nullptr;
             A2.ho_cap_in = ho2_cap;
             A1.ho_stride_out = A2.ho_stride_in = ho2_stride;
+            A2.ho_state_out = ho3_state.ptr;
+            A2.ho_nodes_out = ho3_nodes.ptr;
+            A2.ho_cap_out = ho3_cap;
+            A3.ho_state_in = ho3_state.ptr;
+            A3.ho_nodes_in = ho3_nodes.ptr;
+            A3.ho_slot_in = nullptr;
+            A3.ho_cap_in = ho3_cap;
+            A2.ho_stride_out = A3.ho_stride_in = ho3_stride;
 
             SKIS_HIP_TRY(hipStreamBeginCapture(gg.cs, hipStreamCaptureModeThreadLocal));
             gg.capturing = true;
@@ -1553,10 +1718,11 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
             hipLaunchKernelGGL(k_roots, dim3(grid_cap(chunk, 256, 64)), dim3(256), 0, gg.cs, (uint64_t)0, 0u,
                                (const unsigned long long *)&gc.ptr->base, seed_lo, seed_hi, n, prep.C,
                                prep.alias.ptr, prep.row_ptr.ptr, prep.q.ptr, prep.P.ptr, prep.edges.ptr, prep.wbits.ptr, rec.ptr,
-                               u1.ptr, rerr.ptr);
+                               u1.ptr, rerr.ptr, (int)cfg.ris);
             hipLaunchKernelGGL(v0.fn, dim3(nb0), dim3(v0.threads), 0, gg.cs, A0);
             hipLaunchKernelGGL(vm.fn, dim3(nbm), dim3(vm.threads), 0, gg.cs, A1);
-            hipLaunchKernelGGL(kTierGlobal, dim3((unsigned)nbg_g), dim3(TIERG_BLOCK), 0, gg.cs, A2);
+            hipLaunchKernelGGL(kTierHash, dim3((unsigned)nbh), dim3(64), 0, gg.cs, A2);
+            hipLaunchKernelGGL(kTierGlobal, dim3((unsigned)nbg_g), dim3(TIERG_BLOCK), 0, gg.cs, A3);
             hipLaunchKernelGGL(k_chain_end, dim3(1), dim3(64), 0, gg.cs, gc.ptr);
             const hipError_t launch_err = hipGetLastError();
             gg.capturing = false;
@@ -1580,6 +1746,7 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
                                            " of " + std::to_string(count) + " samples"};
             sk.deferred = hg.tot0;
             sk.deferred_global = hg.tot1;
+            sk.deferred_bitmap = hg.tot2;
             sk.graph_replays = (uint32_t)replays;
             (void)hipGraphExecDestroy(gg.x);
             (void)hipGraphDestroy(gg.g);
@@ -1587,7 +1754,7 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
             gg.g = nullptr;
             if (!hc.overflow) return;
             // every size is known now: a bound that holds whatever order the chunks took
-            cap = staging_bound(hc.tier[0][1] + hc.tier[1][1] + hc.tier[2][1], replays);
+            cap = staging_bound(hc.tier[0][1] + hc.tier[1][1] + hc.tier[2][1] + hc.tier[3][1], replays);
             staging.reset();
             if (attempt == 1) throw Error{SKIS_ENOMEM, "staging overflow after resize"};
         }
@@ -1623,6 +1790,7 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
         read_counters();
         sk.deferred = 0;
         sk.deferred_global = 0;
+        sk.deferred_bitmap = 0;
         sk.plain_levels = po.levels;
     }
     if (cfg.form == 2) sample_chain_graph();
@@ -1676,15 +1844,15 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
         read_counters();
         sk.deferred = hc.n_deferred;
         sk.deferred_global = 0;
-        ran_mid = ran_global = false;
-        // handover from tier 1 to the HBM tier, for a quarter of tier 1's samples (the first
+        sk.deferred_bitmap = 0;
+        ran_mid = ran_hash = ran_global = false;
+        // handover from tier 1 to the hash tier, for a quarter of tier 1's samples (the first
         // ones it hands on; about 1 % of the samples outgrow tier 1 on the TRI and 1.4B-edge
         // workloads, 15 % of tier 1's)
-        DevBuf<Handover> ho2_state;
-        DevBuf<int32_t> ho2_nodes;
+        DevBuf<Handover> ho2_state, ho3_state;
+        DevBuf<int32_t> ho2_nodes, ho3_nodes;
         DevBuf<uint32_t> ho2_slot;
-        uint64_t ho2_cap = 0;
-        const int ho2_stride = (int)vm.visited;
+        uint64_t ho2_cap = 0, ho3_cap = 0;
         if (hc.n_deferred > 0) {
             // tier 1: the samples that outgrew tier 0, LDS visited sets of 1024 nodes
             const uint64_t nd = hc.n_deferred;
@@ -1713,15 +1881,13 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
             read_counters();
         }
         if (ran_mid && hc.n_deferred > 0) {
-            // tier 2: what is left, a bitmap and a node list of n entries per slot in HBM
+            // tier 2: the samples that outgrew tier 1, hashes and lists sized to them in HBM
             const uint64_t nd = hc.n_deferred;
             if (nd > 1) {
-                // a fixed pseudo-random order (Fisher-Yates, a 64-bit LCG): the largest samples
-                // bound this tier's time.  In tier 1's hand-on order they can bunch up at the
-                // end and run alone; all of them first (by pending nodes) ran 2.5x slower, as
-                // their HBM visited sets then compete for the caches.
-                // Each sample keeps its handover record: the record of new position q is the
-                // old position perm[q] (records exist below ho2_cap).
+                // a fixed pseudo-random order (Fisher-Yates, a 64-bit LCG): in tier 1's hand-on
+                // order the largest samples can bunch up and start last.  Each sample keeps its
+                // handover record: the record of new position q is the old position perm[q]
+                // (records exist below ho2_cap).
                 std::vector<uint32_t> ids(nd), perm(nd), moved(nd), slot(nd);
                 SKIS_HIP_TRY(hipMemcpyAsync(ids.data(), deferred2.ptr, sizeof(uint32_t) * nd, hipMemcpyDeviceToHost, s));
                 SKIS_HIP_TRY(hipStreamSynchronize(s));
@@ -1742,6 +1908,38 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
                 SKIS_HIP_TRY(hipStreamSynchronize(s));
             }
             sk.deferred_global = nd;
+            alloc_hash_tier();
+            ho3_cap = std::min<uint64_t>(nd, HO3_MAX);
+            ho3_state.alloc(arena, ho3_cap);
+            ho3_nodes.alloc(arena, ho3_cap * (uint64_t)ho3_stride);
+            reset_ids();
+            A.id_list = deferred2.ptr;
+            A.id_count = nd;
+            A.deferred = deferred.ptr; // tier 1 has read tier 0's list by now
+            A.ghash = ghash.ptr;
+            A.glist2 = glist2.ptr;
+            A.big_row = std::max<uint32_t>(cfg.big_row, 1u << 20);
+            A.tier_stats = ctr.ptr->tier[2];
+            A.ho_state_out = ho3_state.ptr;
+            A.ho_nodes_out = ho3_nodes.ptr;
+            A.ho_cap_out = ho3_cap;
+            A.ho_stride_out = ho3_stride;
+            A.ho_state_in = ho2_state.ptr;
+            A.ho_nodes_in = ho2_nodes.ptr;
+            A.ho_slot_in = ho2_slot.ptr; // null when there was nothing to shuffle
+            A.ho_cap_in = ho2_cap;
+            A.ho_stride_in = ho2_stride;
+            SKIS_HIP_TRY(hipEventRecord(ev[8], s));
+            hipLaunchKernelGGL(kTierHash, dim3((unsigned)nbh), dim3(64), 0, s, A);
+            SKIS_HIP_TRY(hipGetLastError());
+            SKIS_HIP_TRY(hipEventRecord(ev[9], s));
+            ran_hash = true;
+            read_counters();
+        }
+        if (ran_hash && hc.n_deferred > 0) {
+            // tier 3: what is left, a bitmap and a node list of n entries per slot in HBM
+            const uint64_t nd = hc.n_deferred;
+            sk.deferred_bitmap = nd;
             const uint64_t slots = (uint64_t)nbg * TIERG_SLOTS;
             DevBuf<uint32_t> gbits;
             DevBuf<int32_t> glist;
@@ -1750,26 +1948,27 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
             hipLaunchKernelGGL(k_fill<uint32_t>, dim3(grid_cap(slots * words, 256)), dim3(256), 0, s, slots * words,
                                gbits.ptr, 0u);
             reset_ids();
-            A.id_list = deferred2.ptr;
+            A.id_list = deferred.ptr;
             A.id_count = nd;
-            A.deferred = deferred.ptr; // unused: the global tier finishes every sample
+            A.id_perm = 1;              // a fixed scramble of the hand-on order
+            A.deferred = deferred2.ptr; // unused: the bitmap tier finishes every sample
             A.gbits = gbits.ptr;
             A.glist = glist.ptr;
-            A.tier_stats = ctr.ptr->tier[2];
-            A.ho_state_out = nullptr; // the HBM tier finishes every sample
+            A.tier_stats = ctr.ptr->tier[3];
+            A.ho_state_out = nullptr;
             A.ho_nodes_out = nullptr;
             A.ho_cap_out = 0;
-            A.ho_state_in = ho2_state.ptr; // and resumes those tier 1 handed over
-            A.ho_nodes_in = ho2_nodes.ptr;
-            A.ho_slot_in = ho2_slot.ptr;   // null when there was nothing to shuffle
-            A.ho_cap_in = ho2_cap;
-            A.ho_stride_in = ho2_stride;
+            A.ho_state_in = ho3_state.ptr; // records follow the list position
+            A.ho_nodes_in = ho3_nodes.ptr;
+            A.ho_slot_in = nullptr;
+            A.ho_cap_in = ho3_cap;
+            A.ho_stride_in = ho3_stride;
             need(A.gbits, "gbits");
             need(A.glist, "glist");
-            SKIS_HIP_TRY(hipEventRecord(ev[8], s));
+            SKIS_HIP_TRY(hipEventRecord(ev[10], s));
             hipLaunchKernelGGL(kTierGlobal, dim3(nbg), dim3(TIERG_BLOCK), 0, s, A);
             SKIS_HIP_TRY(hipGetLastError());
-            SKIS_HIP_TRY(hipEventRecord(ev[9], s));
+            SKIS_HIP_TRY(hipEventRecord(ev[11], s));
             ran_global = true;
             read_counters();
         }
@@ -1781,12 +1980,12 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
                                        std::to_string(hc.overflow | herr) + ")"};
         if (!hc.overflow) break;
         // every size is known now: a bound that holds whatever order the chunks took
-        cap = staging_bound(hc.tier[0][1] + hc.tier[1][1] + hc.tier[2][1], 1);
+        cap = staging_bound(hc.tier[0][1] + hc.tier[1][1] + hc.tier[2][1] + hc.tier[3][1], 1);
         staging.reset();
         if (attempt == 1) throw Error{SKIS_ENOMEM, "staging overflow after resize"};
     }
     SKIS_HIP_TRY(hipEventRecord(ev[2], s));
-    for (int t = 0; t < 3; ++t)
+    for (int t = 0; t < 4; ++t)
         for (int k = 0; k < 5; ++k) sk.tier_stats[t][k] = hc.tier[t][k];
 
     // every sample must have finished in one of the tiers; the samples above SORT_LDS_MAX
@@ -1914,14 +2113,47 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
     sk.ms_tier0 = ms;
     sk.ms_tier1 = 0;
     sk.ms_tier2 = 0;
+    sk.ms_tier3 = 0;
     if (ran_mid) {
         SKIS_HIP_TRY(hipEventElapsedTime(&ms, ev[6], ev[7]));
         sk.ms_tier1 = ms;
     }
-    if (ran_global) {
+    if (ran_hash) {
         SKIS_HIP_TRY(hipEventElapsedTime(&ms, ev[8], ev[9]));
         sk.ms_tier2 = ms;
     }
+    if (ran_global) {
+        SKIS_HIP_TRY(hipEventElapsedTime(&ms, ev[10], ev[11]));
+        sk.ms_tier3 = ms;
+    }
+}
+
+// Cuts a built sketch (before its transpose) to its first T' samples, T' the smallest count
+// whose sizes sum to at least budget (T' = T when all of them together hold fewer entries).
+void truncate_to_budget(Sketch &sk, uint64_t budget, hipStream_t s)
+{
+    if (sk.T == 0 || sk.entries < budget) return;
+    DevBuf<unsigned long long> t;
+    t.alloc(sk.arena, 2);
+    hipLaunchKernelGGL(k_first_reaching, dim3(1), dim3(64), 0, s, sk.sample_ptr.ptr, (uint64_t)sk.T, (int64_t)budget,
+                       t.ptr);
+    hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(1), dim3(64), 0, s, (uint64_t)1, t.ptr + 1, 0ull);
+    SKIS_HIP_TRY(hipGetLastError());
+    unsigned long long T2 = 0;
+    SKIS_HIP_TRY(hipMemcpyAsync(&T2, t.ptr, sizeof(T2), hipMemcpyDeviceToHost, s));
+    SKIS_HIP_TRY(hipStreamSynchronize(s));
+    if (T2 < 1 || T2 > sk.T) throw Error{SKIS_EHIP, "internal error: budget cut outside the sketch"};
+    hipLaunchKernelGGL(k_sum_u64, dim3(grid_cap(T2, 256, 1)), dim3(256), 0, s, (uint64_t)T2,
+                       reinterpret_cast<const unsigned long long *>(sk.probed.ptr), t.ptr + 1);
+    SKIS_HIP_TRY(hipGetLastError());
+    int64_t ent = 0;
+    unsigned long long ptot = 0;
+    SKIS_HIP_TRY(hipMemcpyAsync(&ent, sk.sample_ptr.ptr + T2, sizeof(ent), hipMemcpyDeviceToHost, s));
+    SKIS_HIP_TRY(hipMemcpyAsync(&ptot, t.ptr + 1, sizeof(ptot), hipMemcpyDeviceToHost, s));
+    SKIS_HIP_TRY(hipStreamSynchronize(s));
+    sk.T = T2;
+    sk.entries = (uint64_t)ent;
+    sk.probed_total = ptot;
 }
 
 } // namespace skis

@@ -23,7 +23,8 @@ EXPORTED = ("skis_default_options", "skis_preprocess", "skis_build_sketch", "ski
             "skis_estimate", "skis_greedy_max_cover", "skis_sketch_export", "skis_inverse_export",
             "skis_node_q", "skis_sketch_free", "skis_last_error", "skis_server_default_options",
             "skis_server_create", "skis_server_submit", "skis_server_wait", "skis_server_replay",
-            "skis_server_get_stats", "skis_server_destroy", "skis_probe_random_read")
+            "skis_server_get_stats", "skis_server_destroy", "skis_probe_random_read", "skis_set_memory_limits",
+            "skis_release_cached_memory", "skis_samples_for_estimate")
 
 
 class SkisError(RuntimeError):
@@ -38,7 +39,7 @@ class Options(ctypes.Structure):
                 ("build_inverse_index", ctypes.c_uint32), ("threads_per_block", ctypes.c_uint32),
                 ("max_device_bytes", ctypes.c_uint64), ("staging_entries", ctypes.c_uint64),
                 ("chunk_samples", ctypes.c_uint64), ("quads_per_lane", ctypes.c_uint32),
-                ("reserved_opt", ctypes.c_uint32)]
+                ("entry_budget", ctypes.c_uint64), ("ris_mode", ctypes.c_uint32), ("reserved_opt", ctypes.c_uint32)]
 
 
 class ServerOptions(ctypes.Structure):
@@ -60,11 +61,12 @@ class Info(ctypes.Structure):
                 ("ms_roots", ctypes.c_double), ("ms_sample", ctypes.c_double),
                 ("ms_compact", ctypes.c_double), ("ms_inverse", ctypes.c_double),
                 ("ms_tier0", ctypes.c_double), ("ms_tier1", ctypes.c_double),
-                ("ms_tier2", ctypes.c_double), ("deferred_global", ctypes.c_uint64),
+                ("ms_tier2", ctypes.c_double), ("ms_tier3", ctypes.c_double),
+                ("deferred_global", ctypes.c_uint64), ("deferred_bitmap", ctypes.c_uint64),
                 ("plain_levels", ctypes.c_uint32), ("graph_replays", ctypes.c_uint32),
-                ("tier_samples", ctypes.c_uint64 * 3), ("tier_entries", ctypes.c_uint64 * 3),
-                ("tier_probed", ctypes.c_uint64 * 3), ("tier_swept", ctypes.c_uint64 * 3),
-                ("tier_items", ctypes.c_uint64 * 3)]
+                ("tier_samples", ctypes.c_uint64 * 4), ("tier_entries", ctypes.c_uint64 * 4),
+                ("tier_probed", ctypes.c_uint64 * 4), ("tier_swept", ctypes.c_uint64 * 4),
+                ("tier_items", ctypes.c_uint64 * 4)]
 
 
 _lib = None
@@ -118,6 +120,13 @@ def lib():
         L.skis_server_get_stats.restype = ctypes.c_int
         L.skis_server_destroy.argtypes = [P]
         L.skis_server_destroy.restype = None
+        L.skis_set_memory_limits.argtypes = [u64, u64]
+        L.skis_set_memory_limits.restype = ctypes.c_int
+        L.skis_release_cached_memory.argtypes = []
+        L.skis_release_cached_memory.restype = ctypes.c_int
+        L.skis_samples_for_estimate.argtypes = [i32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                                ctypes.c_double, ctypes.POINTER(u64)]
+        L.skis_samples_for_estimate.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -186,14 +195,16 @@ class SketchInfo:
     ms_tier0: float
     ms_tier1: float
     ms_tier2: float
+    ms_tier3: float
     deferred_global: int
+    deferred_bitmap: int
     plain_levels: int
     graph_replays: int
-    tier_samples: tuple = (0, 0, 0)
-    tier_entries: tuple = (0, 0, 0)
-    tier_probed: tuple = (0, 0, 0)
-    tier_swept: tuple = (0, 0, 0)
-    tier_items: tuple = (0, 0, 0)
+    tier_samples: tuple = (0, 0, 0, 0)
+    tier_entries: tuple = (0, 0, 0, 0)
+    tier_probed: tuple = (0, 0, 0, 0)
+    tier_swept: tuple = (0, 0, 0, 0)
+    tier_items: tuple = (0, 0, 0, 0)
 
 
 class Sketch:
@@ -219,7 +230,7 @@ class Sketch:
         _check(lib().skis_sketch_info(self._h, ctypes.byref(i)))
         return SketchInfo(i.n, i.T, i.entries, i.probed_total, i.deferred, i.C, i.Gamma, i.device_bytes,
                           i.ms_preprocess, i.ms_roots, i.ms_sample, i.ms_compact, i.ms_inverse,
-                          i.ms_tier0, i.ms_tier1, i.ms_tier2, i.deferred_global,
+                          i.ms_tier0, i.ms_tier1, i.ms_tier2, i.ms_tier3, i.deferred_global, i.deferred_bitmap,
                           i.plain_levels, i.graph_replays, tuple(i.tier_samples), tuple(i.tier_entries),
                           tuple(i.tier_probed), tuple(i.tier_swept), tuple(i.tier_items))
 
@@ -263,6 +274,23 @@ class Sketch:
         q = torch.empty(inf.n, dtype=torch.float64, device="cuda")
         _check(lib().skis_node_q(self._h, _ptr(q), _stream()))
         return q
+
+
+def samples_for_estimate(n: int, Gamma: float, I_lower: float, eps: float, delta: float) -> int:
+    """Samples an (eps, delta)-estimate of every set with I(S) >= I_lower needs (Lemma lem:monte)."""
+    T = ctypes.c_uint64()
+    _check(lib().skis_samples_for_estimate(n, Gamma, I_lower, eps, delta, ctypes.byref(T)))
+    return T.value
+
+
+def set_memory_limits(cache_keep_bytes: int, pool_keep_bytes: int) -> None:
+    """Limits on the device memory the library keeps for reuse (idle-block cache, pool)."""
+    _check(lib().skis_set_memory_limits(cache_keep_bytes, pool_keep_bytes))
+
+
+def release_cached_memory() -> None:
+    """Gives the library's idle device memory back (after a device synchronisation)."""
+    _check(lib().skis_release_cached_memory())
 
 
 def build_sketch(row_ptr, col, w, num_samples: int, seed: int, options: Options | None = None, **kw) -> Sketch:

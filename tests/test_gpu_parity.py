@@ -157,15 +157,16 @@ def test_sketch_identical_across_sampler_shapes(skis, threads, slots, visited, q
     _assert_sketch_equal(sk, ora)
 
 
-@pytest.mark.parametrize("scale", [2.5, 4.0])
-def test_large_cascades_global_tier(skis, scale):
-    # heavier weights give samples of thousands of nodes: LDS overflow -> global tier;
+@pytest.mark.parametrize("scale,n,m", [(2.5, 30000, 300000), (4.0, 30000, 300000), (4.0, 60000, 600000)])
+def test_large_cascades_global_tier(skis, scale, n, m):
+    # heavier weights give samples of thousands of nodes: LDS overflow -> the HBM hash tier;
     # at scale 4 most samples exceed the LDS sort limit (8192 nodes) and are sorted through
-    # the compaction's node bitmap
-    g = inputs.chung_lu_graph(30000, 300000, 2.1, 77, "wc", cache=False)
+    # the compaction's node bitmap; on the 60k-node graph most also exceed the hash tier's
+    # 12288 nodes and finish in the bitmap tier, resumed from the hash tier's handover
+    g = inputs.chung_lu_graph(n, m, 2.1, 77, "wc", cache=False)
     w = np.minimum(g.w * scale, 1.0).astype(np.float32)
     T = 2000
-    _say("large cascades", scale)
+    _say("large cascades", scale, n)
     ora = oracle.build_sketch(g.row_ptr, g.col, w, seed=5, j0=0, j1=T, nthreads=8)
     sizes = np.diff(ora.sample_ptr)
     if scale > 3:
@@ -175,9 +176,13 @@ def test_large_cascades_global_tier(skis, scale):
     sk = skis.build_sketch(g.row_ptr, g.col, w, T, 5)
     inf = sk.info()
     _say("large cascades info", inf)
-    assert inf.deferred > 0 and inf.deferred_global > 0  # samples above 1024 nodes reach the HBM tier
+    assert inf.deferred > 0 and inf.deferred_global > 0  # samples above 1024 nodes reach the HBM tiers
     _assert_tiers_add_up(inf)
-    assert inf.tier_samples[2] == inf.deferred_global
+    assert inf.tier_samples[2] + inf.tier_samples[3] == inf.deferred_global
+    assert inf.tier_samples[3] == inf.deferred_bitmap
+    assert (inf.deferred_bitmap > 0) == bool((sizes > 12288).any())
+    if n > 30000:
+        assert (sizes > 12288).mean() > 0.5
     _assert_sketch_equal(sk, ora)
 
 
@@ -205,7 +210,8 @@ def test_plain_form_matches_oracle_and_persistent(skis, which):
         assert torch.equal(x, y)
 
 
-@pytest.mark.parametrize("which,chunk", [("cl15k", 0), ("cl15k", 4096), ("cl15k", 1000), ("large", 300)])
+@pytest.mark.parametrize("which,chunk", [("cl15k", 0), ("cl15k", 4096), ("cl15k", 1000), ("large", 300),
+                                         ("large4", 700)])
 def test_captured_form_matches_oracle_and_persistent(skis, which, chunk):
     # the captured chain (chunk bounds, roots, three tiers) replayed once per chunk of ids,
     # the last chunk ragged, gives the same sketch bit for bit; two builds in a row
@@ -214,8 +220,9 @@ def test_captured_form_matches_oracle_and_persistent(skis, which, chunk):
         g = inputs.workload_graph("cl15k_wc")
         rp, c, w, T = g.row_ptr, g.col, g.w, 30000
     else:
-        g = inputs.chung_lu_graph(30000, 300000, 2.1, 77, "wc", cache=False)
-        rp, c, w, T = g.row_ptr, g.col, np.minimum(g.w * 2.5, 1.0).astype(np.float32), 2000
+        scale, gn = (2.5, 30000) if which == "large" else (4.0, 60000)
+        g = inputs.chung_lu_graph(gn, 10 * gn, 2.1, 77, "wc", cache=False)
+        rp, c, w, T = g.row_ptr, g.col, np.minimum(g.w * scale, 1.0).astype(np.float32), 2000
     _say("captured form", which, chunk)
     ora = oracle.build_sketch(rp, c, w, seed=13, j0=0, j1=T, nthreads=8)
     pers = skis.build_sketch(rp, c, w, T, 13)
@@ -231,8 +238,12 @@ def test_captured_form_matches_oracle_and_persistent(skis, which, chunk):
         for x, y in zip(cap.export(), pers.export()):
             assert torch.equal(x, y)
         assert inf.deferred == pers.info().deferred
+        assert inf.deferred_global == pers.info().deferred_global
+        assert inf.deferred_bitmap == pers.info().deferred_bitmap
         if which == "large":
             assert inf.deferred_global > 0
+        if which == "large4":
+            assert inf.deferred_bitmap > 0
 
 
 def test_tiny_and_degenerate_shapes(skis):

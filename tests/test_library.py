@@ -88,6 +88,14 @@ def test_bench_kernel_names_match_the_library_table():
     for r in rows:
         th, sl, vi, pl, th2, sl2, vi2, hcap, icap, pl2 = map(int, r)
         assert (th, sl, vi, pl) == (th2, sl2, vi2, pl2)
-        name = bench.tier0_kernel_name(dict(threads_per_block=th, slots_per_block=sl, visited_threshold=vi,
-                                            quads_per_lane=pl))
+        name = bench.tier_kernel_names(dict(threads_per_block=th, slots_per_block=sl, visited_threshold=vi,
+                                            quads_per_lane=pl))[0]
         assert name == "k_sample<%d, %d, %d, %d, %d, %d, 0>" % (th, sl, vi, hcap, icap, pl)
+    # the later tiers' names as the library instantiates them
+    names = bench.tier_kernel_names({})
+    mid = re.search(r"kTierMidV\[\] = \{\s*\{64, 1, 1024, 1, (k_sample<[^>]*>)\}", src).group(1)
+    assert names[1] == mid
+    assert "kTierHash = %s;" % names[2].replace("12288", "TIERH_RCAP").replace("16384", "TIERH_HCAP") in src
+    assert "kTierGlobal = k_sample<TIERG_BLOCK, TIERG_SLOTS, 1, 1, 8 * TIERG_BLOCK, 2, 3>;" in src
+    assert names[3] == "k_sample<1024, 1, 1, 1, 8192, 2, 3>" and "constexpr int TIERG_BLOCK = 1024;" in src
+    assert "constexpr int TIERH_RCAP = 12288;" in src and "constexpr int TIERH_HCAP = 16384;" in src
