@@ -185,6 +185,22 @@ int skis_estimate(const skis_sketch *sk, int32_t num_sets, const int64_t *set_pt
                   uint64_t *cov, double *est, hipStream_t stream);
 
 /*
+ * skis_estimate without device allocation, for callers that cannot allocate (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the same sets, the
+ * same results bit for bit, the same errors as skis_estimate.  Its scratch (an error word,
+ * the list of large sets and the per-set bitmaps) is one file-scope device array of 32 MiB
+ * that every GPU the library runs on holds until the process ends; the call clears the part
+ * it uses and allocates nothing.  Every call on a GPU shares that GPU's array: calls that
+ * overlap on one GPU (from several threads or streams) race and must be serialised by the
+ * caller.  Sets are taken in rounds of 1024 (set_ptr read to the host, stack staging); each
+ * launch holds as many T-bit bitmaps as fit in the array, so T may be at most about 2^28.
+ * Sets above 4096 entries also need a node bitmap of n bits beside their T-bit bitmap;
+ * SKIS_EINVAL when one of those does not fit, or when T-bit bitmaps alone do not.  Blocking.
+ */
+int skis_estimate_noalloc(const skis_sketch *sk, int32_t num_sets, const int64_t *set_ptr, const int32_t *set_nodes,
+                          uint64_t *cov, double *est, hipStream_t stream);
+
+/*
  * Greedy max-cover of Alg. 3: k rounds, each adding the node v outside the current set
  * with the largest gain fl(fl(Delta(v) * Gamma) / T) + q_v (Eq. margin), Delta(v) being
  * the number of samples containing v not yet covered; ties go to the smallest id.

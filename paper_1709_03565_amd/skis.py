@@ -24,7 +24,7 @@ EXPORTED = ("skis_default_options", "skis_preprocess", "skis_build_sketch", "ski
             "skis_node_q", "skis_sketch_free", "skis_last_error", "skis_server_default_options",
             "skis_server_create", "skis_server_submit", "skis_server_wait", "skis_server_replay",
             "skis_server_get_stats", "skis_server_destroy", "skis_probe_random_read", "skis_set_memory_limits",
-            "skis_release_cached_memory", "skis_samples_for_estimate")
+            "skis_release_cached_memory", "skis_samples_for_estimate", "skis_estimate_noalloc")
 
 
 class SkisError(RuntimeError):
@@ -91,6 +91,8 @@ def lib():
         L.skis_sketch_info.restype = ctypes.c_int
         L.skis_estimate.argtypes = [P, i32, P, P, P, P, P]
         L.skis_estimate.restype = ctypes.c_int
+        L.skis_estimate_noalloc.argtypes = [P, i32, P, P, P, P, P]
+        L.skis_estimate_noalloc.restype = ctypes.c_int
         L.skis_greedy_max_cover.argtypes = [P, i32, P, P, P, P, P]
         L.skis_greedy_max_cover.restype = ctypes.c_int
         L.skis_sketch_export.argtypes = [P, P, P, P, P, P]
@@ -241,6 +243,16 @@ class Sketch:
         cov = torch.empty(max(Q, 1), dtype=torch.int64, device="cuda")
         est = torch.empty(max(Q, 1), dtype=torch.float64, device="cuda")
         _check(lib().skis_estimate(self._h, Q, _ptr(set_ptr), _ptr(set_nodes), _ptr(cov), _ptr(est), _stream()))
+        return cov[:Q], est[:Q]
+
+    def estimate_noalloc(self, set_ptr, set_nodes):
+        """As estimate(), through skis_estimate_noalloc (no device allocation inside the call)."""
+        set_ptr, set_nodes = _dev(set_ptr, torch.int64), _dev(set_nodes, torch.int32)
+        Q = set_ptr.numel() - 1
+        cov = torch.empty(max(Q, 1), dtype=torch.int64, device="cuda")
+        est = torch.empty(max(Q, 1), dtype=torch.float64, device="cuda")
+        _check(lib().skis_estimate_noalloc(self._h, Q, _ptr(set_ptr), _ptr(set_nodes), _ptr(cov), _ptr(est),
+                                           _stream()))
         return cov[:Q], est[:Q]
 
     def greedy(self, k: int):
