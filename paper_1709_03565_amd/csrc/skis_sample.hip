@@ -1396,6 +1396,9 @@ static const Variant kTierMidV[] = {
 // workload, and each takes many passes).
 constexpr int TIERH_RCAP = 12288;
 constexpr int TIERH_HCAP = 16384;
+// in-degree above which the hash tier hands a sample on: a hub row is swept faster by the
+// bitmap tier's sixteen waves than by one
+constexpr uint32_t TIERH_BIG_ROW = 65536;
 static SampleKernel const kTierHash = k_sample<64, 1, TIERH_RCAP, TIERH_HCAP, 64, 1, 2>;
 // Fourth tier: one sample per workgroup with a bitmap of n bits and a node list of n entries;
 // the few samples that outgrow the hash tier or meet an in-degree above 2^20 take sixteen waves
@@ -1675,7 +1678,7 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
             A2.id_list = deferred2.ptr;
             A2.id_count_dev = &gc.ptr->nd1;
             A2.id_perm = 1; // the eager form shuffles on the host; here the order is scrambled in place
-            A2.big_row = std::max<uint32_t>(cfg.big_row, 1u << 20);
+            A2.big_row = std::max<uint32_t>(cfg.big_row, TIERH_BIG_ROW);
             A2.deferred = deferred.ptr; // tier 1 has read tier 0's list by now
             A2.n_deferred = &gc.ptr->nd2;
             A2.ghash = ghash.ptr;
@@ -1918,7 +1921,7 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
             A.deferred = deferred.ptr; // tier 1 has read tier 0's list by now
             A.ghash = ghash.ptr;
             A.glist2 = glist2.ptr;
-            A.big_row = std::max<uint32_t>(cfg.big_row, 1u << 20);
+            A.big_row = std::max<uint32_t>(cfg.big_row, TIERH_BIG_ROW);
             A.tier_stats = ctr.ptr->tier[2];
             A.ho_state_out = ho3_state.ptr;
             A.ho_nodes_out = ho3_nodes.ptr;
