@@ -357,7 +357,8 @@ def ris_comparison(g, rp, col, w, T, set_ptr, set_nodes):
     return res
 
 
-def full_step_workload(name, dev, steps, warmup, k, queries, plain_compare, serve_args=None, ris_compare=False):
+def full_step_workload(name, dev, steps, warmup, k, queries, plain_compare, serve_args=None, ris_compare=False,
+                       dssa_k=0):
     """A whole-path step (build with inverse index, estimates, greedy) on a host-generated
     workload, with the tier lines; optionally the plain form and a serving run."""
     import torch
@@ -391,6 +392,16 @@ def full_step_workload(name, dev, steps, warmup, k, queries, plain_compare, serv
             (name, pinf.ms_tier0, pinf.plain_levels, pers))
     if ris_compare:
         res["ris_comparison"] = ris_comparison(g, rp, col, w, T, set_ptr, set_nodes)
+    if dssa_k:
+        # D-SSA on SKIS sketches with the paper's IM settings (eps = 0.5, delta = 1/n)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        seeds, dinfo, _ = skis.im_dssa(rp, col, w, dssa_k, 0.5, 1.0 / g.n, inputs.SAMPLE_SEED)
+        torch.cuda.synchronize()
+        res["im_dssa"] = dict(dinfo, k=dssa_k, eps=0.5, delta=1.0 / g.n, seconds=time.perf_counter() - t)
+        log("%s D-SSA k=%d: %.3f s, T=%d, %d iterations, stopped %d, I_hat %.1f" %
+            (name, dssa_k, res["im_dssa"]["seconds"], dinfo["T"], dinfo["iterations"], dinfo["stopped"],
+             dinfo["est_check"]))
     if serve_args is not None:
         sk = skis.build_sketch(rp, col, w, T, inputs.SAMPLE_SEED)
         res["serving"] = serving_run(sk, g.n, T, name, *serve_args)
@@ -573,7 +584,8 @@ def main():
             serve_args = (args.rate, args.duration or 3.0) if other == "cl4m_tri" else None
             extras[other] = full_step_workload(other, dev, args.steps, args.warmup, args.k, args.queries,
                                                plain_compare=(other == "cl1m_wc"), serve_args=serve_args,
-                                               ris_compare=(other == "cl1m_wc"))
+                                               ris_compare=(other == "cl1m_wc"),
+                                               dssa_k=100 if other == "cl4m_tri" else 0)
         line["workloads"] = extras
         if "cl4m_tri" in extras:
             line["serving"] = extras["cl4m_tri"].pop("serving")

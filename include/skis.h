@@ -211,6 +211,46 @@ int skis_estimate_noalloc(const skis_sketch *sk, int32_t num_sets, const int64_t
 int skis_greedy_max_cover(const skis_sketch *sk, int32_t k, int32_t *seeds, uint64_t *marg,
                           uint64_t *cov_out /* host */, double *est_out /* host */, hipStream_t stream);
 
+/*
+ * Influence maximisation with the SKIS sketch: D-SSA (stop-and-stare, doubling) run on IIS
+ * samples, as the paper's Sec. 5 and its appendix on D-SSA with SKIS describe.  The graph is
+ * preprocessed once.  Iteration t (t = 1, 2, ...) draws the sketch R of sample ids [0, T) and,
+ * when needed, the check sketch R^c of ids [T, 2T) from the stream of `seed`; T starts at
+ * ceil(Lambda) and doubles each iteration.  The seeds are the greedy of Alg. 3 on R; when
+ * Cov_R(seeds) >= Lambda they are estimated on R^c by Eq. (eq21), and the run stops when
+ *   eps_t = (eps1 + eps2 + eps1 eps2)(1 - 1/e - eps) + (1 - 1/e) eps3 <= eps, with
+ *   eps1 = I_R / I_Rc - 1,  eps2 = eps sqrt(n (1 + eps) / (2^(t-1) I_Rc)),
+ *   eps3 = eps sqrt(n (1 + eps)(1 - 1/e - eps) / ((1 + eps/3) 2^(t-1) I_Rc)),
+ * or when T reaches N_max (then the last seeds are returned, stopped = 0).  The bounds are
+ * D-SSA's with the SKIS coverage threshold of the appendix:
+ *   Upsilon(eps, d) = (2 + 2 eps/3) ln(1/d) / eps^2,
+ *   N_max = 8 (1 - 1/e) / (2 + 2 eps/3) Upsilon(eps, delta / (6 C(n, k))) n / k,
+ *   t_max = ceil(log2(2 N_max / Upsilon(eps, delta / 3))),
+ *   Lambda = 1 + (1 + eps)(2 Gamma/n + 2 eps/3) ln(3 t_max / delta) / eps^2.
+ * Graph buffers as for skis_build_sketch; seeds (host) receives k node ids in pick order;
+ * *info (host) the run's figures.  opt may be NULL (sampler shape and max_device_bytes are
+ * used; form, inverse index, RIS and budget options are not).  Blocking.  Errors: SKIS_EINVAL
+ * (k outside [1, n], eps outside (0, 1 - 1/e), delta outside (0, 1), a malformed graph, or
+ * sketches that would need 2^31 ids), SKIS_ENOMEM, SKIS_EHIP.  Gamma = 0 returns
+ * SKIS_WDEGENERATE with seeds 0 .. k-1 (I(S) = |S| for every S).
+ */
+typedef struct skis_dssa_info {
+    uint64_t T;                 /* samples in R at the end (R^c holds as many more) */
+    uint32_t iterations;        /* iterations run */
+    uint32_t stopped;           /* 1: the error condition held; 0: T reached N_max */
+    uint64_t cov_select;        /* Cov_R(seeds) */
+    uint64_t cov_check;         /* Cov_Rc(seeds) of the last check (0 if none ran) */
+    double est_select;          /* I_hat_R(seeds), Eq. eq21 */
+    double est_check;           /* I_hat_Rc(seeds) of the last check */
+    double eps1, eps2, eps3, eps_t; /* the last check's error terms */
+    double Lambda, N_max, t_max; /* the bounds */
+    double Gamma;
+} skis_dssa_info;
+
+int skis_im_dssa(int32_t n, int64_t m, const int32_t *row_ptr, const int32_t *col, const float *w, int32_t k,
+                 double eps, double delta, uint64_t seed, const skis_options *opt, hipStream_t stream,
+                 int32_t *seeds /* host [k] */, skis_dssa_info *info /* host */);
+
 /* Copies the sketch into caller buffers: sample_ptr int64[T+1], nodes int32[entries],
  * roots int32[T], probed uint64[T].  Any pointer may be NULL. */
 int skis_sketch_export(const skis_sketch *sk, int64_t *sample_ptr, int32_t *nodes, int32_t *roots,

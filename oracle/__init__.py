@@ -16,6 +16,7 @@ Contents
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -325,3 +326,60 @@ def greedy(n: int, sample_ptr, nodes, q, Gamma: float, k: int):
     if st:
         raise OracleError(st)
     return seeds[:k], marg[:k], cov.value, est.value
+
+
+def dssa(row_ptr, col, w, k: int, eps: float, delta: float, seed: int, nthreads: int = 1):
+    """D-SSA on IIS sketches (Sec. 5 and the appendix on D-SSA with SKIS), step by step:
+    iteration t takes the sketch R of sample ids [0, T) and the check sketch R^c of ids
+    [T, 2T), runs the greedy of Alg. 3 on R, and, once Cov_R(seeds) reaches Lambda, estimates
+    the seeds on R^c by Eq. (eq21) and stops when the combined error eps_t is at most eps; T
+    starts at ceil(Lambda) and doubles, up to N_max.  Returns (seeds, info dict)."""
+    prep = Prepared(row_ptr, col, w)
+    n, G = prep.n, prep.Gamma
+    info = {"Gamma": G}
+    if prep.status == WDEGENERATE:
+        prep.close()
+        return np.arange(k, dtype=np.int32), dict(info, est_select=float(k), est_check=float(k))
+    q = prep.q()
+    e1 = 1.0 - 1.0 / math.exp(1.0)
+    lnC = 0.0
+    for i in range(1, k + 1):
+        lnC += math.log(float(n - k + i)) - math.log(float(i))
+    a = 2.0 + 2.0 * eps / 3.0
+    ups_nk = a * (math.log(6.0 / delta) + lnC) / (eps * eps)
+    ups_3 = a * math.log(3.0 / delta) / (eps * eps)
+    N_max = 8.0 * e1 / a * ups_nk * float(n) / float(k)
+    t_max = max(float(math.ceil(math.log2(2.0 * N_max / ups_3))), 1.0)
+    Lam = 1.0 + (1.0 + eps) * (2.0 * G / float(n) + 2.0 * eps / 3.0) * math.log(3.0 * t_max / delta) / (eps * eps)
+    info.update(Lambda=Lam, N_max=N_max, t_max=t_max, stopped=0, cov_check=0, est_check=0.0,
+                eps1=0.0, eps2=0.0, eps3=0.0, eps_t=0.0)
+    T = max(1, int(math.ceil(Lam)))
+    t = 1
+    while True:
+        R = prep.sample(seed, 0, T, nthreads=nthreads)
+        seeds, marg, cov_R, est_R = greedy(n, R.sample_ptr, R.nodes, q, G, k)
+        info.update(iterations=t, T=T, cov_select=int(cov_R), est_select=float(est_R))
+        done = False
+        if cov_R >= Lam:
+            Rc = prep.sample(seed, T, 2 * T, nthreads=nthreads)
+            sp, sn = _sets_csr([seeds])
+            cc, ec = estimate(n, Rc.sample_ptr, Rc.nodes, q, G, set_ptr=sp, set_nodes=sn)
+            cov_c, est_c = int(cc[0]), float(ec[0])
+            p2 = float(1 << (t - 1))
+            eps1 = est_R / est_c - 1.0
+            eps2 = eps * math.sqrt(float(n) * (1.0 + eps) / (p2 * est_c))
+            eps3 = eps * math.sqrt(float(n) * (1.0 + eps) * (e1 - eps) / ((1.0 + eps / 3.0) * p2 * est_c))
+            eps_t = (eps1 + eps2 + eps1 * eps2) * (e1 - eps) + e1 * eps3
+            info.update(cov_check=cov_c, est_check=est_c, eps1=eps1, eps2=eps2, eps3=eps3, eps_t=eps_t)
+            if eps_t <= eps:
+                info["stopped"] = 1
+                done = True
+        if not done and float(T) >= N_max:
+            done = True
+        if done:
+            break
+        T *= 2
+        t += 1
+    prep.close()
+    return np.asarray(seeds, np.int32), info
+

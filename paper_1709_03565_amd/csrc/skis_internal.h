@@ -165,6 +165,7 @@ struct SampleConfig {
     uint32_t qpl = 1;   // edge quads per lane per sweep in the first tier
     bool owners = false; // also write the sample id of every entry (Sketch::owner) for the transpose
     bool ris = false;    // plain RIS samples (uniform root, no conditioning) instead of IIS
+    uint64_t first_id = 0; // sample i of the build is sample id first_id + i of the stream
 };
 
 void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, uint64_t T, uint64_t seed,

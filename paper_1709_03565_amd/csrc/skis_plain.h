@@ -13,6 +13,7 @@ struct PlainInputs {
     const int4 *rec;
     const int32_t *u1;
     uint32_t seed_lo, seed_hi;
+    uint64_t first_id;              // sample i of the chunk series is sample id first_id + i
     uint64_t expected_size;         // expected |R_j|, sizes the chunk buffers
     DevBuf<int32_t> *staging;       // grown (contents kept) when a chunk does not fit
     uint32_t *out_size;

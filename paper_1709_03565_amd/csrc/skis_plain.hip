@@ -318,7 +318,7 @@ void sample_plain(Arena &arena, const PlainInputs &in, PlainOutputs &out, hipStr
                 const unsigned ge =
                     (unsigned)std::min<uint64_t>(std::max<uint64_t>(wins, 1), (uint64_t)device_cu_count() * 16);
                 hipLaunchKernelGGL(k_plain_expand, dim3(ge), dim3(PLAIN_BLOCK), 0, s, (uint64_t)n_items, cur,
-                                   pbase.ptr, total, in.seed_lo, in.seed_hi, (uint64_t)i0, c);
+                                   pbase.ptr, total, in.seed_lo, in.seed_hi, in.first_id + (uint64_t)i0, c);
                 SKIS_HIP_TRY(hipGetLastError());
                 std::swap(cur, nxt);
             }

@@ -1486,7 +1486,7 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
     hipLaunchKernelGGL(k_fill<int>, dim3(1), dim3(64), 0, s, (uint64_t)1, rerr.ptr, 0);
     SKIS_HIP_TRY(hipEventRecord(ev[0], s));
     if (cfg.form != 2) { // the captured form draws the roots inside its chain, chunk by chunk
-        hipLaunchKernelGGL(k_roots, dim3(grid_cap(count, 256, 64)), dim3(256), 0, s, (uint64_t)0, count,
+        hipLaunchKernelGGL(k_roots, dim3(grid_cap(count, 256, 64)), dim3(256), 0, s, (uint64_t)cfg.first_id, count,
                            (const unsigned long long *)nullptr, seed_lo, seed_hi, n, prep.C, prep.alias.ptr,
                            prep.row_ptr.ptr, prep.q.ptr, prep.P.ptr, prep.edges.ptr, prep.wbits.ptr, rec.ptr, u1.ptr, rerr.ptr,
                            (int)cfg.ris);
@@ -1642,7 +1642,7 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
             A.wbits = prep.wbits.ptr;
             A.rec = rec.ptr;
             A.u1 = u1.ptr;
-            A.j0 = 0;
+            A.j0 = cfg.first_id;
             A.seed_lo = seed_lo;
             A.seed_hi = seed_hi;
             A.staging = staging.ptr;
@@ -1718,7 +1718,7 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
             SKIS_HIP_TRY(hipStreamBeginCapture(gg.cs, hipStreamCaptureModeThreadLocal));
             gg.capturing = true;
             hipLaunchKernelGGL(k_chain_begin, dim3(1), dim3(64), 0, gg.cs, gc.ptr, (uint64_t)count, chunk);
-            hipLaunchKernelGGL(k_roots, dim3(grid_cap(chunk, 256, 64)), dim3(256), 0, gg.cs, (uint64_t)0, 0u,
+            hipLaunchKernelGGL(k_roots, dim3(grid_cap(chunk, 256, 64)), dim3(256), 0, gg.cs, (uint64_t)cfg.first_id, 0u,
                                (const unsigned long long *)&gc.ptr->base, seed_lo, seed_hi, n, prep.C,
                                prep.alias.ptr, prep.row_ptr.ptr, prep.q.ptr, prep.P.ptr, prep.edges.ptr, prep.wbits.ptr, rec.ptr,
                                u1.ptr, rerr.ptr, (int)cfg.ris);
@@ -1778,6 +1778,7 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
         in.u1 = u1.ptr;
         in.seed_lo = seed_lo;
         in.seed_hi = seed_hi;
+        in.first_id = cfg.first_id;
         in.expected_size = 48;
         in.staging = &staging;
         in.out_size = out_size.ptr;
@@ -1809,7 +1810,7 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
         A.wbits = prep.wbits.ptr;
         A.rec = rec.ptr;
         A.u1 = u1.ptr;
-        A.j0 = 0;
+        A.j0 = cfg.first_id;
         A.seed_lo = seed_lo;
         A.seed_hi = seed_hi;
         A.next = &ctr.ptr->next;

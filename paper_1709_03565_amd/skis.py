@@ -24,7 +24,7 @@ EXPORTED = ("skis_default_options", "skis_preprocess", "skis_build_sketch", "ski
             "skis_node_q", "skis_sketch_free", "skis_last_error", "skis_server_default_options",
             "skis_server_create", "skis_server_submit", "skis_server_wait", "skis_server_replay",
             "skis_server_get_stats", "skis_server_destroy", "skis_probe_random_read", "skis_set_memory_limits",
-            "skis_release_cached_memory", "skis_samples_for_estimate", "skis_estimate_noalloc")
+            "skis_release_cached_memory", "skis_samples_for_estimate", "skis_estimate_noalloc", "skis_im_dssa")
 
 
 class SkisError(RuntimeError):
@@ -40,6 +40,14 @@ class Options(ctypes.Structure):
                 ("max_device_bytes", ctypes.c_uint64), ("staging_entries", ctypes.c_uint64),
                 ("chunk_samples", ctypes.c_uint64), ("quads_per_lane", ctypes.c_uint32),
                 ("entry_budget", ctypes.c_uint64), ("ris_mode", ctypes.c_uint32), ("reserved_opt", ctypes.c_uint32)]
+
+
+class DssaInfo(ctypes.Structure):
+    _fields_ = [("T", ctypes.c_uint64), ("iterations", ctypes.c_uint32), ("stopped", ctypes.c_uint32),
+                ("cov_select", ctypes.c_uint64), ("cov_check", ctypes.c_uint64), ("est_select", ctypes.c_double),
+                ("est_check", ctypes.c_double), ("eps1", ctypes.c_double), ("eps2", ctypes.c_double),
+                ("eps3", ctypes.c_double), ("eps_t", ctypes.c_double), ("Lambda", ctypes.c_double),
+                ("N_max", ctypes.c_double), ("t_max", ctypes.c_double), ("Gamma", ctypes.c_double)]
 
 
 class ServerOptions(ctypes.Structure):
@@ -129,6 +137,9 @@ def lib():
         L.skis_samples_for_estimate.argtypes = [i32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                                 ctypes.c_double, ctypes.POINTER(u64)]
         L.skis_samples_for_estimate.restype = ctypes.c_int
+        L.skis_im_dssa.argtypes = [i32, i64, P, P, P, i32, ctypes.c_double, ctypes.c_double, u64,
+                                   ctypes.POINTER(Options), P, P, ctypes.POINTER(DssaInfo)]
+        L.skis_im_dssa.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -286,6 +297,19 @@ class Sketch:
         q = torch.empty(inf.n, dtype=torch.float64, device="cuda")
         _check(lib().skis_node_q(self._h, _ptr(q), _stream()))
         return q
+
+
+def im_dssa(row_ptr, col, w, k: int, eps: float, delta: float, seed: int, **kw):
+    """D-SSA on SKIS sketches (skis_im_dssa): (seeds int32 numpy [k], info dict, status)."""
+    import numpy as np
+    row_ptr, col, w = _dev(row_ptr, torch.int32), _dev(col, torch.int32), _dev(w, torch.float32)
+    n, m = row_ptr.numel() - 1, col.numel()
+    opt = default_options(**kw)
+    seeds = np.zeros(max(k, 1), np.int32)
+    info = DssaInfo()
+    st = _check(lib().skis_im_dssa(n, m, _ptr(row_ptr), _ptr(col), _ptr(w), k, eps, delta, seed, ctypes.byref(opt),
+                                   _stream(), seeds.ctypes.data_as(ctypes.c_void_p), ctypes.byref(info)))
+    return seeds[:k], {f: getattr(info, f) for f, _ in DssaInfo._fields_}, st
 
 
 def samples_for_estimate(n: int, Gamma: float, I_lower: float, eps: float, delta: float) -> int:
