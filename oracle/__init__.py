@@ -11,7 +11,8 @@ Contents
     (Alg. 3).  Loaded here through ctypes.
   * ``philox.py``      a pure-Python Philox4x32-10 (independent of the C one).
   * ``tiny.py``        exact enumeration of live-edge graphs for graphs of <= 12 edges:
-    I(S) by its definition (Sec. 2.1) and the exact IIS sample distribution (Lemma 2).
+    I(S) by its definition (Sec. 2.1) and the exact IIS sample distribution (Lemma 2), for
+    the independent cascade and the linear threshold model (Sec. 6).
 """
 from __future__ import annotations
 
@@ -70,6 +71,10 @@ def lib():
         L.ora_build.restype = P
         L.ora_prepare.argtypes = [i32, i64, P, P, P]
         L.ora_prepare.restype = P
+        L.ora_prepare_model.argtypes = [i32, i64, P, P, P, ctypes.c_int]
+        L.ora_prepare_model.restype = P
+        L.ora_row_sums_lt.argtypes = [i32, P, P, P, P]
+        L.ora_row_sums_lt.restype = ctypes.c_int
         L.ora_prep_status.argtypes = [P]
         L.ora_prep_status.restype = ctypes.c_int
         L.ora_prep_scalars.argtypes = [P, P, P]
@@ -145,6 +150,18 @@ def row_prefix(row_ptr, w):
     return P[:len(w)], q
 
 
+def row_sums_lt(row_ptr, w):
+    """(S[m], q[n], status) of the linear threshold model (Sec. 6): per row, the left-to-right
+    running sum of w in binary64; q_v = 1 - the row's sum (0 if the sum rounds above 1);
+    status ORA_EINVAL (-1) if a row's sum exceeds 1 + 2^-20."""
+    row_ptr, w = _c(row_ptr, np.int32), _c(w, np.float32)
+    n = len(row_ptr) - 1
+    S = np.zeros(max(len(w), 1), np.float64)
+    q = np.zeros(n, np.float64)
+    st = lib().ora_row_sums_lt(n, _p(row_ptr), _p(w), _p(S), _p(q))
+    return S[:len(w)], q, st
+
+
 def gamma_total(q) -> float:
     q = _c(q, np.float64)
     return lib().ora_gamma_total(len(q), _p(q))
@@ -214,7 +231,14 @@ def _take_sketch(L, h, j0) -> Sketch:
 
 
 def build_sketch(row_ptr, col, w, seed: int, j0: int, j1: int, nthreads: int = 1,
-                 ris_mode: bool = False) -> Sketch:
+                 ris_mode: bool = False, model: int = 0) -> Sketch:
+    """Samples [j0, j1); model 0: independent cascade (Alg. 1), 1: linear threshold (Sec. 6)."""
+    if model:
+        prep = Prepared(row_ptr, col, w, model=model)
+        try:
+            return prep.sample(seed, j0, j1, nthreads=nthreads, ris_mode=ris_mode)
+        finally:
+            prep.close()
     row_ptr, col, w = _c(row_ptr, np.int32), _c(col, np.int32), _c(w, np.float32)
     n, m = len(row_ptr) - 1, len(col)
     L = lib()
@@ -225,13 +249,15 @@ def build_sketch(row_ptr, col, w, seed: int, j0: int, j1: int, nthreads: int = 1
 class Prepared:
     """Alg. 2's preprocessing of one graph, done once (validation, P, q, Gamma, root weights,
     alias table); any number of sample-id ranges are then drawn from it.  Holds the graph
-    arrays for as long as it lives."""
+    arrays for as long as it lives.  model 1: the linear threshold model of Sec. 6 (row sums
+    in place of the products, gamma_v = sum of w)."""
 
-    def __init__(self, row_ptr, col, w):
+    def __init__(self, row_ptr, col, w, model: int = 0):
         self.row_ptr, self.col, self.w = _c(row_ptr, np.int32), _c(col, np.int32), _c(w, np.float32)
         self.n, self.m = len(self.row_ptr) - 1, len(self.col)
+        self.model = model
         L = lib()
-        self._h = L.ora_prepare(self.n, self.m, _p(self.row_ptr), _p(self.col), _p(self.w))
+        self._h = L.ora_prepare_model(self.n, self.m, _p(self.row_ptr), _p(self.col), _p(self.w), model)
         if not self._h:
             raise OracleError(ENOMEM)
         self.status = L.ora_prep_status(self._h)
@@ -328,13 +354,14 @@ def greedy(n: int, sample_ptr, nodes, q, Gamma: float, k: int):
     return seeds[:k], marg[:k], cov.value, est.value
 
 
-def dssa(row_ptr, col, w, k: int, eps: float, delta: float, seed: int, nthreads: int = 1):
+def dssa(row_ptr, col, w, k: int, eps: float, delta: float, seed: int, nthreads: int = 1, model: int = 0):
     """D-SSA on IIS sketches (Sec. 5 and the appendix on D-SSA with SKIS), step by step:
     iteration t takes the sketch R of sample ids [0, T) and the check sketch R^c of ids
     [T, 2T), runs the greedy of Alg. 3 on R, and, once Cov_R(seeds) reaches Lambda, estimates
     the seeds on R^c by Eq. (eq21) and stops when the combined error eps_t is at most eps; T
-    starts at ceil(Lambda) and doubles, up to N_max.  Returns (seeds, info dict)."""
-    prep = Prepared(row_ptr, col, w)
+    starts at ceil(Lambda) and doubles, up to N_max.  model 1 draws linear threshold samples
+    (Sec. 6).  Returns (seeds, info dict)."""
+    prep = Prepared(row_ptr, col, w, model=model)
     n, G = prep.n, prep.Gamma
     info = {"Gamma": G}
     if prep.status == WDEGENERATE:

@@ -12,7 +12,7 @@ MASK32 = 0xFFFFFFFF
 M0, M1 = 0xD2511F53, 0xCD9E8D57
 W0, W1 = 0x9E3779B9, 0xBB67AE85
 
-TAG_ROOT, TAG_FIRST, TAG_EDGE, TAG_EDGE_LOW = 0, 1, 2, 3
+TAG_ROOT, TAG_FIRST, TAG_EDGE, TAG_EDGE_LOW, TAG_LT = 0, 1, 2, 3, 4
 
 
 def philox4x32_10(ctr, key):

@@ -22,6 +22,9 @@ uint64_t ora_root_weights(int32_t n, const double *q, uint64_t *W);
 int ora_alias_build(int32_t n, const uint64_t *W, uint64_t C, uint64_t *thr, int32_t *alias);
 int ora_validate(int32_t n, int64_t m, const int32_t *row_ptr, const int32_t *col, const float *w);
 void *ora_prepare(int32_t n, int64_t m, const int32_t *row_ptr, const int32_t *col, const float *w);
+void *ora_prepare_model(int32_t n, int64_t m, const int32_t *row_ptr, const int32_t *col, const float *w,
+                        int model);
+int ora_row_sums_lt(int32_t n, const int32_t *row_ptr, const float *w, double *S, double *q);
 int ora_prep_status(const void *p);
 void ora_prep_free(void *p);
 void *ora_sample(const void *p, uint64_t seed, uint64_t j0, uint64_t j1, int nthreads, int ris_mode);
@@ -82,6 +85,46 @@ static void random_graph(int32_t n, int32_t m, int wc, int32_t **rp_out, int32_t
     }
     free(deg); free(src); free(dst); free(fill);
     *rp_out = rp; *col_out = col; *w_out = w; *m_out = k;
+}
+
+/* The linear threshold sampler (Sec. 6): WC weights (rows sum to 1, long walks that end on
+ * cycles) and WC weights scaled by a per-node factor in (0, 1) (short walks). */
+static void run_lt(int32_t n, int32_t m, int scaled)
+{
+    int32_t *rp, *col;
+    float *w;
+    int64_t mm;
+    random_graph(n, m, 1, &rp, &col, &w, &mm);
+    if (scaled)
+        for (int32_t v = 0; v < n; ++v) {
+            const float f = (float)(1 + rnd(1000)) / 1001.0f;
+            for (int32_t e = rp[v]; e < rp[v + 1]; ++e) w[e] *= f;
+        }
+    double *S = malloc(sizeof(double) * (size_t)(mm ? mm : 1)), *q = malloc(sizeof(double) * (size_t)n);
+    CHECK(ora_row_sums_lt(n, rp, w, S, q) == 0);
+    void *prep = ora_prepare_model(n, mm, rp, col, w, 1);
+    CHECK(prep && ora_prep_status(prep) >= 0);
+    void *sk = ora_sample(prep, 11, 0, 4000, 3, 0);
+    CHECK(sk && ora_sketch_status(sk) >= 0);
+    uint64_t cnt, ptot, CC;
+    int64_t ent;
+    double GG;
+    ora_sketch_info(sk, &cnt, &ent, &ptot, &GG, &CC);
+    int64_t *sp = malloc(sizeof(int64_t) * (cnt + 1));
+    int32_t *nodes = malloc(sizeof(int32_t) * (size_t)(ent ? ent : 1));
+    int32_t *roots = malloc(sizeof(int32_t) * (cnt ? cnt : 1));
+    uint64_t *probed = malloc(sizeof(uint64_t) * (cnt ? cnt : 1));
+    ora_sketch_copy(sk, sp, nodes, roots, probed);
+    for (uint64_t j = 0; j < cnt; ++j) {
+        CHECK(sp[j + 1] - sp[j] >= 2);
+        for (int64_t t = sp[j] + 1; t < sp[j + 1]; ++t) CHECK(nodes[t - 1] < nodes[t]);
+    }
+    void *bad = ora_sample(prep, 11, 0, 10, 1, 1); /* RIS mode is not defined for LT */
+    CHECK(bad && ora_sketch_status(bad) < 0);
+    ora_sketch_free(bad);
+    ora_sketch_free(sk);
+    ora_prep_free(prep);
+    free(sp); free(nodes); free(roots); free(probed); free(S); free(q); free(rp); free(col); free(w);
 }
 
 static void run_graph(int32_t n, int32_t m, int wc, int ris)
@@ -179,6 +222,9 @@ int main(void)
     run_graph(300, 2000, 0, 1);
     run_graph(5, 8, 1, 0);
     run_graph(3, 2, 0, 1);
+    run_lt(300, 2000, 0);
+    run_lt(300, 2000, 1);
+    run_lt(4, 5, 0);
     printf("sanitized oracle run ok\n");
     return 0;
 }

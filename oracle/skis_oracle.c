@@ -21,6 +21,8 @@
  *     tag 3 (edge coin, low):  sub = e;      word y0 is the low half of edge e's coin
  *                              the coin is the 64-bit word high:low; the edge is live iff
  *                              w >= 1 or coin < floor(w * 2^64)
+ *     tag 4 (LT selection):    sub = x;      U = (X >> 11) * 2^-53 picks node x's in-neighbour in
+ *                              the linear threshold model (none when U >= the row's weight sum)
  */
 #include <math.h>
 #include <pthread.h>
@@ -132,6 +134,27 @@ void ora_row_prefix(int32_t n, const int32_t *row_ptr, const float *w, double *P
     }
 }
 
+/* The linear threshold model (Sec. 6): node v picks at most one in-neighbour, u with probability
+ * w(u,v), none with probability 1 - sum_u w(u,v), so gamma_v = sum_u w(u,v) (the weights of a
+ * row must sum to at most 1).  Per row, S_e = S_{e-1} + w_e left to right in binary64 (S before
+ * the first edge is 0), and q_v = 1 - S of the last edge (1 for an empty row), 0 if the sum
+ * exceeds 1 by rounding.  Returns ORA_EINVAL if a row's sum exceeds 1 + 2^-20. */
+int ora_row_sums_lt(int32_t n, const int32_t *row_ptr, const float *w, double *S, double *q)
+{
+    int st = ORA_OK;
+    for (int32_t v = 0; v < n; ++v) {
+        const int32_t a = row_ptr[v], b = row_ptr[v + 1];
+        double run = 0.0;
+        for (int32_t e = a; e < b; ++e) {
+            run = run + (double)w[e];
+            S[e] = run;
+        }
+        if (run > 1.0 + 0x1p-20) st = ORA_EINVAL;
+        q[v] = run < 1.0 ? 1.0 - run : 0.0;
+    }
+    return st;
+}
+
 /* Gamma = sum_v gamma_v (Table 1), rounded once.  Each gamma_v = 1 - q_v with q_v in
  * [0,1] lies on the grid 2^-53 Z, so the sum is exact in a 128-bit integer. */
 double ora_gamma_total(int32_t n, const double *q)
@@ -229,6 +252,7 @@ typedef struct {
     uint64_t C;
     uint64_t seed;
     int ris_mode; /* 1: plain RIS sample (uniform root, no conditioning), Sec. 2.3.1 */
+    int model;    /* 0: independent cascade; 1: linear threshold (P holds the row sums S) */
 } ora_ctx;
 
 static int cmp_i32(const void *a, const void *b)
@@ -335,6 +359,63 @@ static int64_t ora_one_sample(const ora_ctx *g, uint64_t j, unsigned char *mark,
     return size;
 }
 
+/* The first in-edge e of [a, b) with S_e > theta, or b if there is none. */
+static int32_t ora_first_above(const double *S, int32_t a, int32_t b, double theta)
+{
+    for (int32_t e = a; e < b; ++e)
+        if (S[e] > theta) return e;
+    return b;
+}
+
+/* One IIS sample under the linear threshold model (Sec. 6): the root as in Alg. 1 (weights
+ * gamma_v / Gamma), exactly one of its in-neighbours, u with probability w(u, root) / gamma_root
+ * (theta = U * gamma_root against the row sums), then the RIS walk of the model: the last node
+ * added picks at most one in-neighbour (tag-4 draw of that node), until it picks none or picks a
+ * node already in the sample.  Appends R_j (sorted) to out; returns its size. */
+static int64_t ora_one_sample_lt(const ora_ctx *g, uint64_t j, unsigned char *mark, ora_vec *out,
+                                 int32_t *root_out, uint64_t *probed_out)
+{
+    const int64_t base = out->len;
+    uint64_t X, Y;
+    draw2(g->seed, 0u, j, 0u, &X, &Y);
+    const uint64_t b = mulhi64(X, (uint64_t)g->n);
+    const uint64_t r = mulhi64(Y, g->C);
+    const int32_t root = r < g->thr[b] ? (int32_t)b : g->alias[b];
+    if (vec_push(out, root)) return ORA_ENOMEM;
+    mark[root] = 1;
+    const int32_t rs = g->row_ptr[root], re = g->row_ptr[root + 1];
+    draw2(g->seed, 0u, j, 1u, &X, &Y);
+    const double U = (double)(X >> 11) * 0x1p-53;
+    const double theta = U * (1.0 - g->q[root]);
+    int32_t e = ora_first_above(g->P, rs, re, theta);
+    if (e >= re) { /* theta rounded up to the row's sum: the last in-edge of positive weight */
+        for (e = re - 1; e > rs && g->w[e] <= 0.0f; --e) {
+        }
+    }
+    int32_t x = g->col[e];
+    while (!mark[x]) {
+        mark[x] = 1;
+        if (vec_push(out, x)) return ORA_ENOMEM;
+        draw2(g->seed, (uint32_t)x, j, 4u, &X, &Y);
+        const double V = (double)(X >> 11) * 0x1p-53;
+        const int32_t xs = g->row_ptr[x], xe = g->row_ptr[x + 1];
+        const int32_t f = ora_first_above(g->P, xs, xe, V);
+        if (f >= xe) break; /* x picks no in-neighbour */
+        x = g->col[f];
+    }
+    uint64_t probed = 0;
+    for (int64_t i = base; i < out->len; ++i) {
+        const int32_t y = out->nodes[i];
+        probed += (uint64_t)(g->row_ptr[y + 1] - g->row_ptr[y]);
+        mark[y] = 0;
+    }
+    const int64_t size = out->len - base;
+    qsort(out->nodes + base, (size_t)size, sizeof(int32_t), cmp_i32);
+    *root_out = root;
+    *probed_out = probed;
+    return size;
+}
+
 /* ------------------------------------------------------------------------------------
  * A sketch over sample ids [j0, j1): Alg. 2's preprocessing, kept as a CSR hypergraph.
  * ---------------------------------------------------------------------------------- */
@@ -369,7 +450,8 @@ static void *ora_worker_run(void *arg)
     for (uint64_t j = wk->j0; j < wk->j1; ++j) {
         int32_t root;
         uint64_t probed;
-        int64_t s = ora_one_sample(wk->g, j, mark, &wk->out, &root, &probed);
+        int64_t s = wk->g->model == 1 ? ora_one_sample_lt(wk->g, j, mark, &wk->out, &root, &probed)
+                                      : ora_one_sample(wk->g, j, mark, &wk->out, &root, &probed);
         if (s < 0) { wk->status = (int)s; break; }
         wk->sizes[j - wk->j0] = s;
         wk->roots[j - wk->j0] = root;
@@ -404,6 +486,7 @@ typedef struct {
     int32_t *alias;
     double Gamma;
     uint64_t C;
+    int model;  /* 0: independent cascade (P = prefix products); 1: linear threshold (P = row sums) */
     int status; /* ORA_OK, ORA_WDEGENERATE (Gamma = 0) or a negative error */
 } ora_prep;
 
@@ -414,12 +497,14 @@ void ora_prep_free(ora_prep *p)
     free(p);
 }
 
-ora_prep *ora_prepare(int32_t n, int64_t m, const int32_t *row_ptr, const int32_t *col, const float *w)
+ora_prep *ora_prepare_model(int32_t n, int64_t m, const int32_t *row_ptr, const int32_t *col, const float *w,
+                            int model)
 {
     ora_prep *p = (ora_prep *)calloc(1, sizeof(ora_prep));
     if (!p) return NULL;
-    p->n = n; p->m = m; p->row_ptr = row_ptr; p->col = col; p->w = w;
+    p->n = n; p->m = m; p->row_ptr = row_ptr; p->col = col; p->w = w; p->model = model;
     p->status = ora_validate(n, m, row_ptr, col, w);
+    if (!p->status && (model < 0 || model > 1)) p->status = ORA_EINVAL;
     if (p->status) return p;
     p->P = (double *)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
     p->q = (double *)malloc(sizeof(double) * (size_t)n);
@@ -427,12 +512,22 @@ ora_prep *ora_prepare(int32_t n, int64_t m, const int32_t *row_ptr, const int32_
     p->thr = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
     p->alias = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
     if (!p->P || !p->q || !p->W || !p->thr || !p->alias) { p->status = ORA_ENOMEM; return p; }
-    ora_row_prefix(n, row_ptr, w, p->P, p->q);
+    if (model == 1) {
+        p->status = ora_row_sums_lt(n, row_ptr, w, p->P, p->q);
+        if (p->status) return p;
+    } else {
+        ora_row_prefix(n, row_ptr, w, p->P, p->q);
+    }
     p->Gamma = ora_gamma_total(n, p->q);
     p->C = ora_root_weights(n, p->q, p->W);
     if (p->C == 0) { p->status = ORA_WDEGENERATE; return p; } /* no non-singular sample exists */
     if (ora_alias_build(n, p->W, p->C, p->thr, p->alias)) p->status = ORA_ENOMEM;
     return p;
+}
+
+ora_prep *ora_prepare(int32_t n, int64_t m, const int32_t *row_ptr, const int32_t *col, const float *w)
+{
+    return ora_prepare_model(n, m, row_ptr, col, w, 0);
 }
 
 int ora_prep_status(const ora_prep *p) { return p ? p->status : ORA_ENOMEM; }
@@ -464,6 +559,7 @@ ora_sketch *ora_sample(const ora_prep *p, uint64_t seed, uint64_t j0, uint64_t j
     sk->j0 = j0;
     sk->j1 = j1;
     if (p->status < 0) { sk->status = p->status; return sk; }
+    if (p->model == 1 && ris_mode) { sk->status = ORA_EINVAL; return sk; }
     sk->Gamma = p->Gamma;
     sk->C = p->C;
     uint64_t count = j1 > j0 ? j1 - j0 : 0;
@@ -484,7 +580,7 @@ ora_sketch *ora_sample(const ora_prep *p, uint64_t seed, uint64_t j0, uint64_t j
         goto done;
     }
     {
-        ora_ctx ctx = {p->n, p->row_ptr, p->col, p->w, p->P, p->q, p->thr, p->alias, p->C, seed, ris_mode};
+        ora_ctx ctx = {p->n, p->row_ptr, p->col, p->w, p->P, p->q, p->thr, p->alias, p->C, seed, ris_mode, p->model};
         if (nthreads < 1) nthreads = 1;
         if ((uint64_t)nthreads > count && count > 0) nthreads = (int)count;
         ora_worker *wks = (ora_worker *)calloc((size_t)nthreads, sizeof(ora_worker));

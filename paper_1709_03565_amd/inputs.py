@@ -6,7 +6,11 @@ evaluates on six SNAP / Kwak graphs (Sec. 7, Table 2) that are not available her
 power-law Chung-Lu graphs of the stated shapes stand in for them, with the two edge
 probability models of Sec. 7 ("Weight Settings"):
   * weighted cascade (WC): w(u,v) = 1 / d_in(v), computed in fp32;
-  * trivalency (TRI):      w(u,v) drawn uniformly from {0.1, 0.01, 0.001} (fp32).
+  * trivalency (TRI):      w(u,v) drawn uniformly from {0.1, 0.01, 0.001} (fp32);
+  * linear threshold (LT): the in-weights of v normalised and scaled by one number U_v
+    uniform in [0,1) per node, w(u,v) = U_v / d_in(v) (binary64, rounded once to fp32), the
+    setting of the paper's LT experiment (Sec. 7); a row's weights then sum to at most
+    U_v (1 + 2^-24).
 
 Chung-Lu recipe (directed): expected-degree weights x_i = (i+1)^(-1/(beta-1)), scaled to
 sum to m, are assigned to nodes through two independent random permutations (one for
@@ -124,8 +128,17 @@ def tri_weights(m: int, seed: int) -> np.ndarray:
     return TRI_VALUES[rng.integers(0, 3, size=m)]
 
 
+def lt_weights(row_ptr, seed: int) -> np.ndarray:
+    """Linear threshold: w(u,v) = U_v / d_in(v), U_v uniform in [0,1) per node (PCG64)."""
+    deg = np.diff(np.asarray(row_ptr, np.int64))
+    rng = np.random.Generator(np.random.PCG64(seed))
+    U = rng.random(len(deg))
+    per_row = U / np.maximum(deg, 1).astype(np.float64)
+    return np.repeat(per_row, deg).astype(np.float32)
+
+
 def chung_lu_graph(n: int, m: int, beta: float, seed: int, model: str, cache: bool = True) -> Graph:
-    """Directed Chung-Lu graph with WC or TRI probabilities; weight seed = graph seed + 1000."""
+    """Directed Chung-Lu graph with WC, TRI or LT weights; weight seed = graph seed + 1000."""
     name = "cl_n%d_m%d_b%g_s%d_%s_v%d" % (n, m, beta, seed, model, RECIPE_VERSION)
     path = os.path.join(_cache_dir(), name + ".npz") if cache else None
     if path and os.path.exists(path):
@@ -138,6 +151,8 @@ def chung_lu_graph(n: int, m: int, beta: float, seed: int, model: str, cache: bo
         w = wc_weights(row_ptr)
     elif model == "tri":
         w = tri_weights(m, seed + 1000)
+    elif model == "lt":
+        w = lt_weights(row_ptr, seed + 1000)
     else:
         raise ValueError("unknown weight model %r" % model)
     if path:
@@ -215,6 +230,10 @@ def chung_lu_graph_device(n: int, m: int, beta: float, seed: int, model: str, de
     elif model == "tri":
         vals = torch.tensor(TRI_VALUES, device=dev)
         w = vals[torch.randint(0, 3, (m,), generator=g, device=dev)]
+    elif model == "lt":
+        U = torch.rand(n, dtype=torch.float64, generator=g, device=dev)
+        w = (U / deg.clamp(min=1).to(torch.float64)).to(torch.float32)[dsts]
+        del U
     else:
         raise ValueError("unknown weight model %r" % model)
     del dsts, deg
@@ -277,6 +296,30 @@ def random_tiny_graph(rng, n: int, m: int, wset=None):
     return Graph(n, m, row_ptr, col, ww, "tiny")
 
 
+def random_tiny_lt_graph(rng, n: int, m: int, full_rows: bool = False):
+    """A random graph on n nodes with m distinct non-loop edges and linear threshold weights
+    that are multiples of 1/64 (so every sum is exact): row v's weights sum to at most 1, to
+    exactly 1 when full_rows is set."""
+    pairs = [(u, v) for u in range(n) for v in range(n) if u != v]
+    idx = rng.choice(len(pairs), size=m, replace=False)
+    src = np.array([pairs[i][0] for i in idx], np.int64)
+    dst = np.array([pairs[i][1] for i in idx], np.int64)
+    w = np.zeros(m, np.float32)
+    for v in range(n):
+        es = np.nonzero(dst == v)[0]
+        if len(es) == 0:
+            continue
+        # d + 1 parts of 64 (the last one is the "no in-neighbour" share), each at least 1
+        cuts = np.sort(rng.choice(np.arange(1, 64), size=len(es), replace=False))
+        parts = np.diff(np.concatenate([[0], cuts, [64]]))
+        k = parts[:-1].copy()
+        if full_rows:
+            k[-1] += parts[-1]
+        w[es] = k.astype(np.float32) / np.float32(64)
+    row_ptr, col, ww = edges_to_in_csr(n, src, dst, w)
+    return Graph(n, m, row_ptr, col, ww, "tiny_lt")
+
+
 # Workloads (sizes of the synthetic stand-ins).  Sample seed 1 everywhere.
 WORKLOADS = {
     "cl15k_wc": dict(n=15_000, m=60_000, beta=2.3, seed=101, model="wc", T=200_000),
@@ -284,6 +327,11 @@ WORKLOADS = {
     "cl4m_tri": dict(n=4_000_000, m=70_000_000, beta=2.0, seed=103, model="tri", T=1 << 25),
     # built on the GPU (chung_lu_graph_device); the step there is the build alone
     "cl40m_wc": dict(n=40_000_000, m=1_400_000_000, beta=2.2, seed=104, model="wc", T=1 << 26,
+                     device_graph=True, build_only=True),
+    # linear threshold model (Sec. 6) with the LT experiment's weights (Sec. 7)
+    "cl15k_lt": dict(n=15_000, m=60_000, beta=2.3, seed=101, model="lt", T=200_000),
+    "cl1m_lt": dict(n=1_000_000, m=20_000_000, beta=2.1, seed=102, model="lt", T=1 << 24),
+    "cl40m_lt": dict(n=40_000_000, m=1_400_000_000, beta=2.2, seed=104, model="lt", T=1 << 26,
                      device_graph=True, build_only=True),
 }
 SAMPLE_SEED = 1
