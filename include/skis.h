@@ -84,7 +84,15 @@ typedef struct skis_options {
                                      singular samples {root} kept -- for comparisons with IIS.  A RIS
                                      sketch answers estimate with n * Cov / T (Eq. ris_prob) and runs
                                      the greedy on gains n * Delta / T; it is built even when Gamma = 0 */
-    uint32_t reserved_opt;        /* set to 0 */
+    uint32_t model;               /* diffusion model: 0 (default) independent cascade (Alg. 1); 1 linear
+                                     threshold (Sec. 6): every node's in-weights must sum to at most 1 (up
+                                     to 2^-20 of rounding), gamma_v = sum of v's in-weights, the root picks
+                                     exactly one in-neighbour u with probability w(u, root) / gamma_root
+                                     and the sample follows the model's reverse walk (the node added last
+                                     picks at most one in-neighbour u with probability w(u, x)) until a node
+                                     picks none or one already in the sample.  Persistent form only (form
+                                     0), no RIS mode; skis_info's tier 0 is the walk kernel, tier 1 the
+                                     kernel of walks longer than 32 nodes, *_swept count the picks drawn */
 } skis_options;
 
 /* Fills *opt with the defaults. */
@@ -121,6 +129,17 @@ int skis_samples_for_estimate(int32_t n, double Gamma, double I_lower, double ep
 int skis_preprocess(int32_t n, int64_t m, const int32_t *row_ptr, const int32_t *col, const float *w,
                     double *P, double *q, uint64_t *W, uint64_t *thr, int32_t *alias,
                     uint64_t *C_out /* host */, double *Gamma_out /* host */, hipStream_t stream);
+
+/*
+ * skis_preprocess for the linear threshold model (Sec. 6): S[e] = the running sum of w over row
+ * v up to and including edge e, left to right in fp64 (S before the row's first edge is 0);
+ * q[v] = 1 - the row's sum (1 for an empty row, 0 when the sum rounds past 1), so gamma_v =
+ * 1 - q[v] is the sum of v's in-weights; W, thr, alias, C and Gamma as for skis_preprocess.
+ * Errors: SKIS_EINVAL also when a row's weights sum to more than 1 + 2^-20.
+ */
+int skis_preprocess_lt(int32_t n, int64_t m, const int32_t *row_ptr, const int32_t *col, const float *w,
+                       double *S, double *q, uint64_t *W, uint64_t *thr, int32_t *alias,
+                       uint64_t *C_out /* host */, double *Gamma_out /* host */, hipStream_t stream);
 
 /*
  * Builds the sketch of num_samples IIS samples (Alg. 1 repeated, Alg. 2 preprocessing).
@@ -228,7 +247,7 @@ int skis_greedy_max_cover(const skis_sketch *sk, int32_t k, int32_t *seeds, uint
  *   t_max = ceil(log2(2 N_max / Upsilon(eps, delta / 3))),
  *   Lambda = 1 + (1 + eps)(2 Gamma/n + 2 eps/3) ln(3 t_max / delta) / eps^2.
  * Graph buffers as for skis_build_sketch; seeds (host) receives k node ids in pick order;
- * *info (host) the run's figures.  opt may be NULL (sampler shape and max_device_bytes are
+ * *info (host) the run's figures.  opt may be NULL (sampler shape, model and max_device_bytes are
  * used; form, inverse index, RIS and budget options are not).  Blocking.  Errors: SKIS_EINVAL
  * (k outside [1, n], eps outside (0, 1 - 1/e), delta outside (0, 1), a malformed graph, or
  * sketches that would need 2^31 ids), SKIS_ENOMEM, SKIS_EHIP.  Gamma = 0 returns

@@ -287,16 +287,16 @@ void skis_default_options(skis_options *opt)
     opt->quads_per_lane = 1;
 }
 
-int skis_preprocess(int32_t n, int64_t m, const int32_t *row_ptr, const int32_t *col, const float *w, double *P,
-                    double *q, uint64_t *W, uint64_t *thr, int32_t *alias, uint64_t *C_out, double *Gamma_out,
-                    hipStream_t stream)
+static int preprocess_model(int32_t n, int64_t m, const int32_t *row_ptr, const int32_t *col, const float *w,
+                            double *P, double *q, uint64_t *W, uint64_t *thr, int32_t *alias, uint64_t *C_out,
+                            double *Gamma_out, hipStream_t stream, int model)
 {
     return guarded([&]() -> int {
         check_graph_args(n, m, row_ptr, col, w);
         skis::Arena arena;
         arena.stream = stream;
         skis::Prep prep;
-        skis::preprocess(arena, n, m, row_ptr, col, w, thr || alias, prep, stream);
+        skis::preprocess(arena, n, m, row_ptr, col, w, thr || alias, prep, stream, model);
         if (P && m > 0)
             SKIS_HIP_TRY(hipMemcpyAsync(P, prep.P.ptr, sizeof(double) * (size_t)m, hipMemcpyDeviceToDevice, stream));
         if (q) SKIS_HIP_TRY(hipMemcpyAsync(q, prep.q.ptr, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, stream));
@@ -317,6 +317,20 @@ int skis_preprocess(int32_t n, int64_t m, const int32_t *row_ptr, const int32_t 
         if (Gamma_out) *Gamma_out = prep.Gamma;
         return prep.C == 0 ? SKIS_WDEGENERATE : SKIS_OK;
     });
+}
+
+int skis_preprocess(int32_t n, int64_t m, const int32_t *row_ptr, const int32_t *col, const float *w, double *P,
+                    double *q, uint64_t *W, uint64_t *thr, int32_t *alias, uint64_t *C_out, double *Gamma_out,
+                    hipStream_t stream)
+{
+    return preprocess_model(n, m, row_ptr, col, w, P, q, W, thr, alias, C_out, Gamma_out, stream, skis::MODEL_IC);
+}
+
+int skis_preprocess_lt(int32_t n, int64_t m, const int32_t *row_ptr, const int32_t *col, const float *w, double *S,
+                       double *q, uint64_t *W, uint64_t *thr, int32_t *alias, uint64_t *C_out, double *Gamma_out,
+                       hipStream_t stream)
+{
+    return preprocess_model(n, m, row_ptr, col, w, S, q, W, thr, alias, C_out, Gamma_out, stream, skis::MODEL_LT);
 }
 
 int skis_build_sketch(int32_t n, int64_t m, const int32_t *row_ptr, const int32_t *col, const float *w,
@@ -345,8 +359,12 @@ int skis_build_sketch(int32_t n, int64_t m, const int32_t *row_ptr, const int32_
             if (opt_in->quads_per_lane) opt.quads_per_lane = opt_in->quads_per_lane;
             opt.ris_mode = opt_in->ris_mode;
             opt.entry_budget = opt_in->entry_budget;
+            opt.model = opt_in->model;
         }
         if (opt.ris_mode > 1) throw skis::Error{SKIS_EINVAL, "ris_mode must be 0 or 1"};
+        if (opt.model > 1) throw skis::Error{SKIS_EINVAL, "model must be 0 (independent cascade) or 1 (linear threshold)"};
+        if (opt.model == 1 && (opt.ris_mode || opt.form != 0))
+            throw skis::Error{SKIS_EINVAL, "the linear threshold sampler has the persistent form only and no RIS mode"};
         if (opt.form > 2) throw skis::Error{SKIS_EINVAL, "unknown sampler form"};
         skis_sketch *h = new skis_sketch;
         try {
@@ -361,7 +379,7 @@ int skis_build_sketch(int32_t n, int64_t m, const int32_t *row_ptr, const int32_
             int status = SKIS_OK;
             {
                 skis::Prep prep;
-                skis::preprocess(sk.arena, n, m, row_ptr, col, w, true, prep, stream);
+                skis::preprocess(sk.arena, n, m, row_ptr, col, w, true, prep, stream, (int)opt.model);
                 SKIS_HIP_TRY(hipEventRecord(e1, stream));
                 SKIS_HIP_TRY(hipEventSynchronize(e1));
                 float ms = 0;
@@ -387,6 +405,7 @@ int skis_build_sketch(int32_t n, int64_t m, const int32_t *row_ptr, const int32_
                     cfg.qpl = opt.quads_per_lane;
                     cfg.owners = opt.build_inverse_index != 0;
                     cfg.ris = sk.ris;
+                    cfg.model = (int)opt.model;
                     if (!opt.entry_budget) {
                         skis::sample_and_compact(sk.arena, prep, n, m, num_samples, seed, cfg, sk, stream);
                     } else {

@@ -12,6 +12,7 @@ constexpr uint32_t TAG_ROOT = 0u;   // Philox tag: root draw
 constexpr uint32_t TAG_FIRST = 1u;  // Philox tag: first live in-edge of the root
 constexpr uint32_t TAG_EDGE = 2u;   // Philox tag: high halves of the live-edge coins, four edges per call
 constexpr uint32_t TAG_EDGE_LOW = 3u; // Philox tag: low half of one edge's coin
+constexpr uint32_t TAG_LT = 4u;    // Philox tag: the in-neighbour a node picks under the linear threshold model
 
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32->64-bit
 // multiplications with Weyl-bumped keys.  Returns the two 64-bit halves X = y1:y0 and

@@ -87,13 +87,15 @@ extern "C" int skis_im_dssa(int32_t n, int64_t m, const int32_t *row_ptr, const 
             if (opt_in->threads_per_block) opt.threads_per_block = opt_in->threads_per_block;
             if (opt_in->quads_per_lane) opt.quads_per_lane = opt_in->quads_per_lane;
             opt.max_device_bytes = opt_in->max_device_bytes;
+            opt.model = opt_in->model;
         }
+        if (opt.model > 1) throw skis::Error{SKIS_EINVAL, "model must be 0 (independent cascade) or 1 (linear threshold)"};
         std::memset(info, 0, sizeof(*info));
         skis::Arena arena;
         arena.cap = opt.max_device_bytes;
         arena.stream = stream;
         skis::Prep prep;
-        skis::preprocess(arena, n, m, row_ptr, col, w, true, prep, stream);
+        skis::preprocess(arena, n, m, row_ptr, col, w, true, prep, stream, (int)opt.model);
         info->Gamma = prep.Gamma;
         if (prep.C == 0) {
             // Gamma = 0: no edge can be live, I(S) = |S| for every S; the greedy's tie rule picks 0..k-1
@@ -113,6 +115,7 @@ extern "C" int skis_im_dssa(int32_t n, int64_t m, const int32_t *row_ptr, const 
         cfg.visited = opt.visited_threshold;
         cfg.big_row = opt.big_row;
         cfg.qpl = opt.quads_per_lane;
+        cfg.model = (int)opt.model;
         skis::DevBuf<int32_t> d_seeds;
         skis::DevBuf<uint64_t> d_marg;
         skis::DevBuf<int64_t> d_ptr;

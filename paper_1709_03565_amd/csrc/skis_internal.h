@@ -133,12 +133,16 @@ struct Sketch {
 // ---------------------------------------------------------------------------------
 // Preprocessing (rows a1-a3).
 // ---------------------------------------------------------------------------------
+// Diffusion models: independent cascade (Alg. 1) and linear threshold (Sec. 6)
+enum : int { MODEL_IC = 0, MODEL_LT = 1 };
+
 struct Prep {
+    int model = MODEL_IC;
     DevBuf<int32_t> row_ptr;    // private copy [n+1]
     DevBuf<uint2> edges;        // interleaved (col, coin_threshold_hi(w)) per edge, padded with
                                 // (0, 0) records to a multiple of four edges
     DevBuf<uint32_t> wbits;     // [m] w bits per edge (+0 for -0): coin ties and the roots' fallback
-    DevBuf<double> P;           // [m]
+    DevBuf<double> P;           // [m] prefix products (IC) or running sums of w (LT)
     DevBuf<double> q;           // [n]
     DevBuf<uint64_t> W;         // [n]
     DevBuf<AliasEntry> alias;   // [n]
@@ -149,7 +153,7 @@ struct Prep {
 // Validates the graph, copies row_ptr, interleaves (col, coin threshold), keeps the w bits,
 // computes P, q, W, C, Gamma and (if build_alias) the alias table.  Throws Error on failure.
 void preprocess(Arena &arena, int32_t n, int64_t m, const int32_t *row_ptr, const int32_t *col,
-                const float *w, bool build_alias, Prep &out, hipStream_t s);
+                const float *w, bool build_alias, Prep &out, hipStream_t s, int model = MODEL_IC);
 
 // ---------------------------------------------------------------------------------
 // Sampling (rows a4-a7, a11) and compaction.
@@ -166,6 +170,7 @@ struct SampleConfig {
     bool owners = false; // also write the sample id of every entry (Sketch::owner) for the transpose
     bool ris = false;    // plain RIS samples (uniform root, no conditioning) instead of IIS
     uint64_t first_id = 0; // sample i of the build is sample id first_id + i of the stream
+    int model = MODEL_IC;  // MODEL_LT: the linear threshold sampler (Sec. 6); prep must match
 };
 
 void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, uint64_t T, uint64_t seed,

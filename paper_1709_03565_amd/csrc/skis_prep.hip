@@ -1,11 +1,20 @@
 // skis_prep.hip -- preprocessing for the root draw and the first live in-edge:
 // validation, per-row prefix products P and q (Eq. gamma_v / Eq. probn), integer root
 // weights W, the weight total C, Gamma (exactly rounded) and the alias table (Eq. probu).
+// Under the linear threshold model (Sec. 6) the same kernels form per-row running sums of w
+// in place of the products (gamma_v is the sum of v's in-weights).
 #include "skis_internal.h"
 
 namespace skis {
 
-enum : int { ERR_ROWPTR = 1, ERR_COL = 2, ERR_SELFLOOP = 4, ERR_WEIGHT = 8 };
+enum : int { ERR_ROWPTR = 1, ERR_COL = 2, ERR_SELFLOOP = 4, ERR_WEIGHT = 8, ERR_LTSUM = 16 };
+
+// Linear threshold model: a row's weights may sum to at most 1 (Sec. 6); rounding may take the
+// sum past 1 by this much, no more.
+constexpr double LT_SUM_SLACK = 0x1p-20;
+
+// q of a row under the linear threshold model from its sum of weights
+__device__ __forceinline__ double lt_q(double sum) { return sum < 1.0 ? __dsub_rn(1.0, sum) : 0.0; }
 
 constexpr int32_t LONG_ROW = 256; // rows above this length are taken by a whole workgroup
 
@@ -25,13 +34,15 @@ __device__ __forceinline__ int check_edge(int32_t u, float wf, int64_t v, int32_
 // of multiplies, so a long row is bound by the latency of that chain, not by bandwidth.
 
 // One thread per row: validates the row, writes the interleaved (col, w) records, P and q.
-// Rows longer than LONG_ROW are listed for k_prep_long.
+// Rows longer than LONG_ROW are listed for k_prep_long.  lt: running sums S in P (S[e] =
+// S[e-1] + w[e], 0 before the row's first edge) and q = 1 - the row's sum.
 __global__ __launch_bounds__(256) void k_prep_rows(int32_t n, int64_t m, const int32_t *__restrict__ row_ptr,
                                                    const int32_t *__restrict__ col, const float *__restrict__ w,
                                                    int32_t *__restrict__ rp_copy, uint2 *__restrict__ edges,
                                                    uint32_t *__restrict__ wbits, double *__restrict__ P,
                                                    double *__restrict__ q, int *err,
-                                                   int32_t *__restrict__ long_rows, unsigned int *__restrict__ n_long)
+                                                   int32_t *__restrict__ long_rows, unsigned int *__restrict__ n_long,
+                                                   int lt)
 {
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
         const int32_t a = row_ptr[v], b = row_ptr[v + 1];
@@ -50,7 +61,7 @@ __global__ __launch_bounds__(256) void k_prep_rows(int32_t n, int64_t m, const i
             if (bad) atomicOr(err, bad);
             continue;
         }
-        double run = 1.0;
+        double run = lt ? 0.0 : 1.0;
         for (int32_t e = a; e < b; ++e) {
             const int32_t u = col[e];
             float wf = w[e];
@@ -58,10 +69,15 @@ __global__ __launch_bounds__(256) void k_prep_rows(int32_t n, int64_t m, const i
             if (wf == 0.0f) wf = 0.0f; // -0 -> +0: the coin reads the bits
             edges[e] = make_uint2((uint32_t)u, coin_threshold_hi(__float_as_uint(wf)));
             wbits[e] = __float_as_uint(wf);
-            run = __dmul_rn(run, __dsub_rn(1.0, (double)wf));
+            run = lt ? __dadd_rn(run, (double)wf) : __dmul_rn(run, __dsub_rn(1.0, (double)wf));
             P[e] = run;
         }
-        q[v] = run;
+        if (lt) {
+            if (run > 1.0 + LT_SUM_SLACK) bad |= ERR_LTSUM;
+            q[v] = lt_q(run);
+        } else {
+            q[v] = run;
+        }
         if (bad) atomicOr(err, bad);
     }
 }
@@ -72,7 +88,8 @@ __global__ __launch_bounds__(256) void k_prep_rows(int32_t n, int64_t m, const i
 // carries the row's running product through the chunk, CHAIN_BATCH factors at a time held
 // in registers with the next batch's LDS reads issued before the multiplies, so that the
 // loop's critical path is the dependent multiplies alone; (3) every thread writes its
-// LONG_PER products out.  The next chunk's edge loads are in flight during (2).
+// LONG_PER products out.  The next chunk's edge loads are in flight during (2).  lt: the
+// terms are w (0 past the row's end: adding 0 is exact) and the chain adds.
 constexpr int LONG_EDGES = 4096;
 constexpr int LONG_PER = LONG_EDGES / 256;
 constexpr int CHAIN_BATCH = 16;
@@ -82,19 +99,20 @@ __global__ __launch_bounds__(256) void k_prep_long(int32_t n, const int32_t *__r
                                                    uint2 *__restrict__ edges, uint32_t *__restrict__ wbits,
                                                    double *__restrict__ P, double *__restrict__ q, int *err,
                                                    const int32_t *__restrict__ long_rows,
-                                                   const unsigned int *__restrict__ n_long)
+                                                   const unsigned int *__restrict__ n_long, int lt)
 {
     __shared__ double s_f[LONG_EDGES + CHAIN_BATCH]; // factors of the chunk (+ one batch read ahead)
     __shared__ double s_p[LONG_EDGES];               // their running products
     __shared__ double s_run;
     const int t = threadIdx.x;
     const unsigned int cnt = *n_long;
-    if (t < CHAIN_BATCH) s_f[LONG_EDGES + t] = 1.0;
+    const double ident = lt ? 0.0 : 1.0;
+    if (t < CHAIN_BATCH) s_f[LONG_EDGES + t] = ident;
     for (unsigned int r = blockIdx.x; r < cnt; r += gridDim.x) {
         const int32_t v = long_rows[r];
         const int32_t a = row_ptr[v], b = row_ptr[v + 1];
         int bad = 0;
-        if (t == 0) s_run = 1.0;
+        if (t == 0) s_run = ident;
         // element k of a thread's share of a chunk is edge c0 + k * 256 + t (coalesced per k);
         // the loads are unconditional (an index past the row reads its last edge, unused), so
         // that the compiler can keep the next chunk's loads in flight across a chunk
@@ -111,14 +129,14 @@ __global__ __launch_bounds__(256) void k_prep_long(int32_t n, const int32_t *__r
 #pragma unroll
             for (int k = 0; k < LONG_PER; ++k) {
                 const int32_t e = c0 + k * 256 + t;
-                double f = 1.0;
+                double f = ident;
                 if (e < b) {
                     float wf = wc[k];
                     bad |= check_edge(uc[k], wf, v, n);
                     if (wf == 0.0f) wf = 0.0f; // -0 -> +0: the coin reads the bits
                     edges[e] = make_uint2((uint32_t)uc[k], coin_threshold_hi(__float_as_uint(wf)));
                     wbits[e] = __float_as_uint(wf);
-                    f = __dsub_rn(1.0, (double)wf);
+                    f = lt ? (double)wf : __dsub_rn(1.0, (double)wf);
                 }
                 s_f[k * 256 + t] = f;
             }
@@ -140,10 +158,18 @@ __global__ __launch_bounds__(256) void k_prep_long(int32_t n, const int32_t *__r
                     double fn[CHAIN_BATCH];
 #pragma unroll
                     for (int k = 0; k < CHAIN_BATCH; ++k) fn[k] = s_f[i0 + CHAIN_BATCH + k];
+                    if (lt) {
 #pragma unroll
-                    for (int k = 0; k < CHAIN_BATCH; ++k) {
-                        run = __dmul_rn(run, fc[k]);
-                        s_p[i0 + k] = run;
+                        for (int k = 0; k < CHAIN_BATCH; ++k) {
+                            run = __dadd_rn(run, fc[k]);
+                            s_p[i0 + k] = run;
+                        }
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < CHAIN_BATCH; ++k) {
+                            run = __dmul_rn(run, fc[k]);
+                            s_p[i0 + k] = run;
+                        }
                     }
 #pragma unroll
                     for (int k = 0; k < CHAIN_BATCH; ++k) fc[k] = fn[k];
@@ -160,7 +186,14 @@ __global__ __launch_bounds__(256) void k_prep_long(int32_t n, const int32_t *__r
             }
         }
         __syncthreads();
-        if (t == 0) q[v] = s_run;
+        if (t == 0) {
+            if (lt) {
+                if (s_run > 1.0 + LT_SUM_SLACK) bad |= ERR_LTSUM;
+                q[v] = lt_q(s_run);
+            } else {
+                q[v] = s_run;
+            }
+        }
         if (bad) atomicOr(err, bad);
         __syncthreads();
     }
@@ -337,8 +370,11 @@ static int root_shift(int32_t n)
 }
 
 void preprocess(Arena &arena, int32_t n, int64_t m, const int32_t *row_ptr, const int32_t *col, const float *w,
-                bool build_alias, Prep &out, hipStream_t s)
+                bool build_alias, Prep &out, hipStream_t s, int model)
 {
+    if (model != MODEL_IC && model != MODEL_LT) throw Error{SKIS_EINVAL, "model must be 0 (IC) or 1 (LT)"};
+    out.model = model;
+    const int lt = model == MODEL_LT ? 1 : 0;
     out.row_ptr.alloc(arena, (size_t)n + 1);
     const size_t m_quad = (size_t)((m + 3) & ~(int64_t)3);
     out.edges.alloc(arena, m_quad > 0 ? m_quad : 4);
@@ -354,10 +390,10 @@ void preprocess(Arena &arena, int32_t n, int64_t m, const int32_t *row_ptr, cons
     long_rows.alloc(arena, (size_t)n);
     unsigned int *n_long = reinterpret_cast<unsigned int *>(err.ptr + 1);
     hipLaunchKernelGGL(k_prep_rows, dim3(grid_for(n)), dim3(256), 0, s, n, m, row_ptr, col, w, out.row_ptr.ptr,
-                       out.edges.ptr, out.wbits.ptr, out.P.ptr, out.q.ptr, err.ptr, long_rows.ptr, n_long);
+                       out.edges.ptr, out.wbits.ptr, out.P.ptr, out.q.ptr, err.ptr, long_rows.ptr, n_long, lt);
     SKIS_HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_prep_long, dim3((unsigned)device_cu_count() * 4), dim3(256), 0, s, n, row_ptr, col, w,
-                       out.edges.ptr, out.wbits.ptr, out.P.ptr, out.q.ptr, err.ptr, long_rows.ptr, n_long);
+                       out.edges.ptr, out.wbits.ptr, out.P.ptr, out.q.ptr, err.ptr, long_rows.ptr, n_long, lt);
     SKIS_HIP_TRY(hipGetLastError());
     int herr = 0;
     SKIS_HIP_TRY(hipMemcpyAsync(&herr, err.ptr, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -368,6 +404,7 @@ void preprocess(Arena &arena, int32_t n, int64_t m, const int32_t *row_ptr, cons
         if (herr & ERR_COL) msg += " col entries must lie in [0, n);";
         if (herr & ERR_SELFLOOP) msg += " self-loops are not allowed;";
         if (herr & ERR_WEIGHT) msg += " w must be in [0, 1] (no NaN);";
+        if (herr & ERR_LTSUM) msg += " linear threshold model: a node's in-weights must sum to at most 1;";
         throw Error{SKIS_EINVAL, msg};
     }
     const unsigned gw = grid_for(n);

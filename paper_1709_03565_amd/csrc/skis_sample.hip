@@ -22,6 +22,7 @@
 #include <type_traits>
 
 #include "skis_internal.h"
+#include "skis_lt.h"
 #include "skis_plain.h"
 
 namespace skis {
@@ -1470,6 +1471,10 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
     auto need = [](const void *p, const char *what) {
         if (!p) throw Error{SKIS_EHIP, std::string("internal error: null device buffer ") + what};
     };
+    const bool lt = cfg.model == MODEL_LT;
+    if (lt && (cfg.ris || cfg.form != 0))
+        throw Error{SKIS_EINVAL, "the linear threshold sampler has the persistent form only and no RIS mode"};
+    if (lt != (prep.model == MODEL_LT)) throw Error{SKIS_EHIP, "internal error: sampler and preprocessing models differ"};
     if (!cfg.ris) need(prep.alias.ptr, "alias");
     need(prep.row_ptr.ptr, "row_ptr");
     need(prep.q.ptr, "q");
@@ -1485,7 +1490,7 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
     rerr.alloc(arena, 1);
     hipLaunchKernelGGL(k_fill<int>, dim3(1), dim3(64), 0, s, (uint64_t)1, rerr.ptr, 0);
     SKIS_HIP_TRY(hipEventRecord(ev[0], s));
-    if (cfg.form != 2) { // the captured form draws the roots inside its chain, chunk by chunk
+    if (cfg.form != 2 && !lt) { // the captured form draws the roots inside its chain, chunk by chunk
         hipLaunchKernelGGL(k_roots, dim3(grid_cap(count, 256, 64)), dim3(256), 0, s, (uint64_t)cfg.first_id, count,
                            (const unsigned long long *)nullptr, seed_lo, seed_hi, n, prep.C, prep.alias.ptr,
                            prep.row_ptr.ptr, prep.q.ptr, prep.P.ptr, prep.edges.ptr, prep.wbits.ptr, rec.ptr, u1.ptr, rerr.ptr,
@@ -1763,7 +1768,35 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
         }
     };
 
-    if (cfg.form == 1) {
+    LtStats lts;
+    if (lt) {
+        // linear threshold model: the walk kernel and the long-walk kernel fill the same staging,
+        // sizes, offsets and roots that the compaction below reads
+        hipLaunchKernelGGL(k_fill<unsigned char>, dim3(1), dim3(64), 0, s, (uint64_t)sizeof(Counters),
+                           reinterpret_cast<unsigned char *>(ctr.ptr), (unsigned char)0);
+        LtIo io;
+        io.count = count;
+        io.first_id = cfg.first_id;
+        io.seed_lo = seed_lo;
+        io.seed_hi = seed_hi;
+        io.rec = rec.ptr;
+        io.out_size = out_size.ptr;
+        io.out_off = out_off.ptr;
+        io.out_probed = reinterpret_cast<unsigned long long *>(sk.probed.ptr);
+        io.medium = medium.ptr;
+        io.n_medium = &ctr.ptr->n_medium;
+        io.small_sort = SMALL_SORT;
+        io.staging = &staging;
+        io.staging_entries = cfg.staging_entries;
+        SKIS_HIP_TRY(hipEventRecord(ev[4], s));
+        sample_lt(arena, prep, n, io, lts, s);
+        SKIS_HIP_TRY(hipEventRecord(ev[5], s));
+        read_counters();
+        sk.deferred = lts.long_samples;
+        sk.deferred_global = 0;
+        sk.deferred_bitmap = 0;
+    }
+    if (cfg.form == 1 && !lt) {
         // plain form: one launch per BFS level over all samples of a chunk
         staging.alloc(arena, cap);
         hipLaunchKernelGGL(k_fill<unsigned char>, dim3(1), dim3(64), 0, s, (uint64_t)sizeof(Counters),
@@ -1798,7 +1831,7 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
         sk.plain_levels = po.levels;
     }
     if (cfg.form == 2) sample_chain_graph();
-    for (int attempt = 0; attempt < 2 && cfg.form == 0; ++attempt) {
+    for (int attempt = 0; attempt < 2 && cfg.form == 0 && !lt; ++attempt) {
         staging.alloc(arena, cap);
         hipLaunchKernelGGL(k_fill<unsigned char>, dim3(1), dim3(64), 0, s, (uint64_t)sizeof(Counters),
                            reinterpret_cast<unsigned char *>(ctr.ptr), (unsigned char)0);
@@ -1991,6 +2024,12 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
     SKIS_HIP_TRY(hipEventRecord(ev[2], s));
     for (int t = 0; t < 4; ++t)
         for (int k = 0; k < 5; ++k) sk.tier_stats[t][k] = hc.tier[t][k];
+    if (lt) { // stage 0: the walk kernel, stage 1: the long walks; picks drawn in place of swept edges
+        const uint64_t ts[2][5] = {{lts.walk_samples, lts.walk_entries, lts.walk_probed, lts.walk_picks, lts.walk_entries},
+                                   {lts.long_samples, lts.long_entries, lts.long_probed, lts.long_picks, lts.long_entries}};
+        for (int t = 0; t < 4; ++t)
+            for (int k = 0; k < 5; ++k) sk.tier_stats[t][k] = t < 2 ? ts[t][k] : 0;
+    }
 
     // every sample must have finished in one of the tiers; the samples above SORT_LDS_MAX
     // nodes (all listed in `medium`) are counted for k_gather_large
@@ -2114,8 +2153,8 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
     SKIS_HIP_TRY(hipEventElapsedTime(&ms, ev[2], ev[3]));
     sk.ms_compact = ms;
     SKIS_HIP_TRY(hipEventElapsedTime(&ms, ev[4], ev[5]));
-    sk.ms_tier0 = ms;
-    sk.ms_tier1 = 0;
+    sk.ms_tier0 = lt ? lts.ms_walk : ms;
+    sk.ms_tier1 = lt ? lts.ms_long : 0;
     sk.ms_tier2 = 0;
     sk.ms_tier3 = 0;
     if (ran_mid) {

@@ -24,7 +24,8 @@ EXPORTED = ("skis_default_options", "skis_preprocess", "skis_build_sketch", "ski
             "skis_node_q", "skis_sketch_free", "skis_last_error", "skis_server_default_options",
             "skis_server_create", "skis_server_submit", "skis_server_wait", "skis_server_replay",
             "skis_server_get_stats", "skis_server_destroy", "skis_probe_random_read", "skis_set_memory_limits",
-            "skis_release_cached_memory", "skis_samples_for_estimate", "skis_estimate_noalloc", "skis_im_dssa")
+            "skis_release_cached_memory", "skis_samples_for_estimate", "skis_estimate_noalloc", "skis_im_dssa",
+            "skis_preprocess_lt")
 
 
 class SkisError(RuntimeError):
@@ -39,7 +40,7 @@ class Options(ctypes.Structure):
                 ("build_inverse_index", ctypes.c_uint32), ("threads_per_block", ctypes.c_uint32),
                 ("max_device_bytes", ctypes.c_uint64), ("staging_entries", ctypes.c_uint64),
                 ("chunk_samples", ctypes.c_uint64), ("quads_per_lane", ctypes.c_uint32),
-                ("entry_budget", ctypes.c_uint64), ("ris_mode", ctypes.c_uint32), ("reserved_opt", ctypes.c_uint32)]
+                ("entry_budget", ctypes.c_uint64), ("ris_mode", ctypes.c_uint32), ("model", ctypes.c_uint32)]
 
 
 class DssaInfo(ctypes.Structure):
@@ -92,6 +93,8 @@ def lib():
         L.skis_default_options.restype = None
         L.skis_preprocess.argtypes = [i32, i64, P, P, P, P, P, P, P, P, P, P, P]
         L.skis_preprocess.restype = ctypes.c_int
+        L.skis_preprocess_lt.argtypes = [i32, i64, P, P, P, P, P, P, P, P, P, P, P]
+        L.skis_preprocess_lt.restype = ctypes.c_int
         L.skis_build_sketch.argtypes = [i32, i64, P, P, P, u64, u64, ctypes.POINTER(Options), P,
                                         ctypes.POINTER(P)]
         L.skis_build_sketch.restype = ctypes.c_int
@@ -174,8 +177,9 @@ def default_options(**kw) -> Options:
     return o
 
 
-def preprocess(row_ptr, col, w):
-    """Rows a1-a3 into new device tensors: dict(P, q, W, thr, alias, C, Gamma, status)."""
+def preprocess(row_ptr, col, w, model: int = 0):
+    """Rows a1-a3 into new device tensors: dict(P, q, W, thr, alias, C, Gamma, status).  model 1:
+    the linear threshold model (skis_preprocess_lt), P holds the running sums S."""
     row_ptr, col, w = _dev(row_ptr, torch.int32), _dev(col, torch.int32), _dev(w, torch.float32)
     n, m = row_ptr.numel() - 1, col.numel()
     P = torch.empty(max(m, 1), dtype=torch.float64, device="cuda")
@@ -185,8 +189,9 @@ def preprocess(row_ptr, col, w):
     alias = torch.empty(n, dtype=torch.int32, device="cuda")
     C = ctypes.c_uint64()
     G = ctypes.c_double()
-    st = _check(lib().skis_preprocess(n, m, _ptr(row_ptr), _ptr(col), _ptr(w), _ptr(P), _ptr(q), _ptr(W),
-                                      _ptr(thr), _ptr(alias), ctypes.byref(C), ctypes.byref(G), _stream()))
+    fn = lib().skis_preprocess_lt if model else lib().skis_preprocess
+    st = _check(fn(n, m, _ptr(row_ptr), _ptr(col), _ptr(w), _ptr(P), _ptr(q), _ptr(W),
+                   _ptr(thr), _ptr(alias), ctypes.byref(C), ctypes.byref(G), _stream()))
     return dict(P=P[:m], q=q, W=W, thr=thr, alias=alias, C=C.value, Gamma=G.value, status=st)
 
 
