@@ -9,8 +9,9 @@ index, 100 estimates and a greedy k = 100.
 
 Beside the headline the same JSON line carries (unless --no-extras): the full steps of the
 1M-node WC and 4M-node TRI workloads, a short open-loop serving run over the TRI sketch
-(p50/p99 latency, achieved queries/s, alone-vs-mix identity), and the random-read probe at 8,
-32, 64 and 128-byte rows.
+(p50/p99 latency, achieved queries/s, alone-vs-mix identity), the build of the same 40M-node
+graph with linear threshold weights and the LT sampler (Sec. 6), and the random-read probe at
+8, 32, 64 and 128-byte rows.
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -41,11 +42,17 @@ def sample_bytes(T: int, entries: int, probed: int) -> int:
     return 40 * T + 12 * entries + 8 * probed
 
 
-def launch_bytes(inf, t: int) -> int:
+def launch_bytes(inf, t: int, lt: bool = False) -> int:
     """Bytes one sampler tier's launch must move for the work it did: the root record and
     result meta of every sample it finished (40 B) and their staged ids (4 B a node), the row
     bounds of every node it expanded (8 B) and the record of every in-edge it swept (8 B).
-    A sample resumed from an earlier tier is charged only for what this launch expanded."""
+    A sample resumed from an earlier tier is charged only for what this launch expanded.
+    Linear threshold kernels (lt): per sample the alias entry (16 B), the root's row bounds
+    (8 B), q (8 B), one running sum (8 B), the picked id (4 B) and the result meta (36 B); per
+    further node of R_j its row bounds, one running sum and the picked id (20 B); per node its
+    staged id (4 B): 60 B a sample + 24 B a node."""
+    if lt:
+        return 60 * inf.tier_samples[t] + 24 * inf.tier_entries[t]
     return 40 * inf.tier_samples[t] + 4 * inf.tier_entries[t] + 8 * inf.tier_items[t] + 8 * inf.tier_swept[t]
 
 
@@ -147,20 +154,25 @@ def load_graph(name, dev):
     return g, rp, col, w
 
 
-def tier_lines(infos, names, workload):
+LT_KERNELS = ["k_lt_walk", "k_lt_long"]
+
+
+def tier_lines(infos, names, workload, lt=False):
     """Per sampler tier: the launch's algorithmic bytes over its HIP-event time (mean over
-    the timed steps), against the HBM peak."""
+    the timed steps), against the HBM peak.  Linear threshold: the walk and long-walk kernels."""
     out = []
-    for t in range(4):
+    for t in range(2 if lt else 4):
         ms = sum(getattr(x, "ms_tier%d" % t) for x in infos) / len(infos)
         inf = infos[-1]
-        b = launch_bytes(inf, t)
+        b = launch_bytes(inf, t, lt)
         gbs = b / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
         out.append({"tier": t, "kernel": names[t], "launch_ms": ms, "alg_bytes_per_launch": b,
                     "achieved_gbs": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS,
                     "samples_finished": inf.tier_samples[t], "entries_finished": inf.tier_entries[t],
                     "edges_swept": inf.tier_swept[t], "nodes_expanded": inf.tier_items[t],
                     "traffic": measured_traffic(names[t], workload)})
+        if lt:
+            out[-1]["picks_drawn"] = out[-1].pop("edges_swept")
     return out
 
 
@@ -201,7 +213,7 @@ def stage_means(infos):
     return {k: round(sum(getattr(x, k) for x in infos) / len(infos), 3) for k in keys}
 
 
-def oracle_baseline(g, rp, col, w, T, budget_s=20.0, build_only=True, sets=None, k=100):
+def oracle_baseline(g, rp, col, w, T, budget_s=20.0, build_only=True, sets=None, k=100, model=0):
     """The oracle (plain C, test infrastructure) on a bounded prefix of the same workload's
     sample ids, with every host thread the process may use and with one: preprocessing is
     timed once, sampling per sample, and the rate is extrapolated to the T samples of a step.
@@ -217,7 +229,7 @@ def oracle_baseline(g, rp, col, w, T, budget_s=20.0, build_only=True, sets=None,
         hrp, hcol, hw = g.row_ptr, g.col, g.w
     log("cpu baseline: oracle preprocessing (one thread)")
     t = time.perf_counter()
-    prep = oracle.Prepared(hrp, hcol, hw)
+    prep = oracle.Prepared(hrp, hcol, hw, model=model)
     t_prep = time.perf_counter() - t
     # size the prefix for about budget_s seconds of sampling with every thread
     n0 = 1 << 13
@@ -366,21 +378,28 @@ def full_step_workload(name, dev, steps, warmup, k, queries, plain_compare, serv
     from paper_1709_03565_amd import inputs, skis
     wl = inputs.WORKLOADS[name]
     T = wl["T"]
+    lt = wl["model"] == "lt"
+    build_only = bool(wl.get("build_only"))
+    opts = {"model": 1} if lt else {}
     t = time.perf_counter()
     g, rp, col, w = load_graph(name, dev)
     log("%s graph ready in %.1fs" % (name, time.perf_counter() - t))
     sets = inputs.random_sets(g.n, queries, 50, seed=7)
     sp_np, sn_np = inputs.sets_to_csr(sets)
     set_ptr, set_nodes = torch.from_numpy(sp_np).to(dev), torch.from_numpy(sn_np).to(dev)
-    infos, elapsed = run_steps(name, rp, col, w, T, {}, steps, warmup, set_ptr, set_nodes, k)
+    infos, elapsed = run_steps(name, rp, col, w, T, opts, steps, warmup, set_ptr, set_nodes, k, build_only)
     inf = infos[-1]
     samp_ms = sum(x.ms_roots + x.ms_sample + x.ms_compact for x in infos) / len(infos)
-    res = {"workload": "%s: n=%d m=%d beta=%g %s, T=%d; step = build_sketch + inverse index + %d estimates + greedy k=%d"
-                       % (name, g.n, g.m, wl["beta"], wl["model"].upper(), T, queries, k),
+    step_text = ("build_sketch without the inverse index" if build_only else
+                 "build_sketch + inverse index + %d estimates + greedy k=%d" % (queries, k))
+    res = {"workload": "%s: n=%d m=%d beta=%g %s weights, %s sampler, T=%d%s; step = %s"
+                       % (name, g.n, g.m, wl["beta"], wl["model"].upper(),
+                          "linear threshold (Sec. 6)" if lt else "independent cascade", T,
+                          ", graph drawn on the GPU" if wl.get("device_graph") else "", step_text),
            "ms_per_step": elapsed * 1000.0 / steps, "samples_per_s": T * steps / elapsed,
            "sampling_samples_per_s": T / (samp_ms * 1e-3), "edges_probed_per_s": inf.probed_total * steps / elapsed,
            "entries": inf.entries, "probed_total": inf.probed_total, "stages_ms": stage_means(infos),
-           "tiers": tier_lines(infos, tier_kernel_names({}), name)}
+           "tiers": tier_lines(infos, LT_KERNELS if lt else tier_kernel_names({}), name, lt)}
     if plain_compare:
         sk = skis.build_sketch(rp, col, w, T, inputs.SAMPLE_SEED, form=1, build_inverse_index=0)
         pinf = sk.info()
@@ -481,6 +500,7 @@ def main():
     wl = inputs.WORKLOADS[name]
     T = args.samples or wl["T"]
     build_only = bool(wl.get("build_only"))
+    lt = wl["model"] == "lt"
     log("workload", name, wl, "T", T)
     t = time.perf_counter()
     g, rp, col, w = load_graph(name, dev)
@@ -491,8 +511,10 @@ def main():
                      ("form", args.form)):
         if val:
             opts[key] = val
+    if lt:
+        opts["model"] = 1
     tuned = None
-    if args.autotune and args.form == 0:
+    if args.autotune and args.form == 0 and not lt:
         from paper_1709_03565_amd import autotune
         tuned = autotune.autotune(rp, col, w, pilot_samples=T, log=log)
         opts.update(autotune.options_from(tuned))
@@ -506,12 +528,12 @@ def main():
     inf = infos[-1]
     ms_step = elapsed * 1000.0 / args.steps
     value = T * args.steps / elapsed
-    names = tier_kernel_names(opts)
-    tiers = tier_lines(infos, names, name)
+    names = LT_KERNELS if lt else tier_kernel_names(opts)
+    tiers = tier_lines(infos, names, name, lt)
     dom = max(tiers, key=lambda x: x["launch_ms"])
     samp_ms = sum(x.ms_roots + x.ms_sample + x.ms_compact for x in infos) / len(infos)
     sampler_ms = sum(x.ms_tier0 + x.ms_tier1 + x.ms_tier2 + x.ms_tier3 for x in infos) / len(infos)
-    b_chain = sample_bytes(T, inf.entries, inf.probed_total)
+    b_chain = 60 * T + 24 * inf.entries if lt else sample_bytes(T, inf.entries, inf.probed_total)
     line = {
         "metric": "SKIS samples/s",
         "value": value,
@@ -526,8 +548,9 @@ def main():
         "dtype": "u64/f64",
         "data": "synthetic",
         "config": {
-            "workload": "%s: directed Chung-Lu n=%d m=%d beta=%g, %s weights fp32, T=%d IIS samples, Philox seed %d; "
-                        % (name, g.n, g.m, wl["beta"], wl["model"].upper(), T, inputs.SAMPLE_SEED)
+            "workload": "%s: directed Chung-Lu n=%d m=%d beta=%g, %s weights fp32, T=%d %s IIS samples, Philox seed %d; "
+                        % (name, g.n, g.m, wl["beta"], wl["model"].upper(), T,
+                           "linear threshold" if lt else "independent cascade", inputs.SAMPLE_SEED)
                         + ("graph drawn on the GPU; step = build_sketch without the inverse index" if build_only else
                            "step = build_sketch + inverse index + %d estimates (|S| 1-50) + greedy k=%d"
                            % (args.queries, args.k)),
@@ -552,8 +575,9 @@ def main():
             "traffic": dom["traffic"],
             "alg_bytes_per_launch": dom["alg_bytes_per_launch"],
             "launch_ms": dom["launch_ms"],
-            "note": "the sampler tier with the longest launch; bytes = 40 per finished sample + 4 per staged "
-                    "node + 8 per expanded node + 8 per swept in-edge of that launch",
+            "note": ("the LT walk kernel with the longest launch; bytes = 60 per sample + 24 per node" if lt else
+                     "the sampler tier with the longest launch; bytes = 40 per finished sample + 4 per staged "
+                     "node + 8 per expanded node + 8 per swept in-edge of that launch"),
             "sampler_alg_bytes": b_chain,
             "sampler_ms": sampler_ms,
             "sampler_gbs": b_chain / (sampler_ms * 1e-3) / 1e9,
@@ -562,7 +586,7 @@ def main():
     }
     if tuned is not None:
         line["config"]["sampler_options"] = autotune.options_from(tuned)
-    if args.form == 0:
+    if args.form == 0 and not lt:
         # the captured form: the same chain captured into a HIP graph, replayed per chunk
         sk = skis.build_sketch(rp, col, w, T, inputs.SAMPLE_SEED, form=2, build_inverse_index=0, **opts)
         cinf = sk.info()
@@ -573,12 +597,12 @@ def main():
             (cinf.ms_tier0, cinf.graph_replays, sampler_ms))
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = oracle_baseline(g, rp, col, w, T, build_only=build_only,
-                                               sets=(sp_np, sn_np), k=args.k)
+                                               sets=(sp_np, sn_np), k=args.k, model=1 if lt else 0)
     del rp, col, w
     torch.cuda.empty_cache()
     if not args.no_extras:
         extras = {}
-        for other in ("cl1m_wc", "cl4m_tri"):
+        for other in ("cl1m_wc", "cl4m_tri", "cl40m_lt"):
             if other == name:
                 continue
             serve_args = (args.rate, args.duration or 3.0) if other == "cl4m_tri" else None
