@@ -228,6 +228,18 @@ void Arena::trim(bool idle)
 
 Arena::~Arena() { trim(idle_on_destroy); }
 
+hipStream_t side_stream()
+{
+    static std::mutex mu;
+    static hipStream_t streams[64] = {};
+    int d = 0;
+    SKIS_HIP_TRY(hipGetDevice(&d));
+    if (d < 0 || d >= 64) throw Error{SKIS_EHIP, "device index out of range"};
+    std::lock_guard<std::mutex> lk(mu);
+    if (!streams[d]) SKIS_HIP_TRY(hipStreamCreateWithFlags(&streams[d], hipStreamNonBlocking));
+    return streams[d];
+}
+
 int device_cu_count()
 {
     static thread_local int cached_dev = -1, cached_cus = 0;

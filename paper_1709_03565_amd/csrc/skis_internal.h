@@ -199,6 +199,11 @@ void excl_scan_u32_to_i64(Arena &arena, const uint32_t *in, int64_t *out, int64_
 // Launch-shape helper: number of compute units of the current device.
 int device_cu_count();
 
+// A second stream of the current device (non-blocking, default priority, created once and kept
+// until the process ends) for work that runs beside the caller's stream between an event
+// recorded on it and one the caller's stream waits on.
+hipStream_t side_stream();
+
 // Random-read probe (measurement aid): `reads` uniformly random rows of row_bytes bytes
 // from a table of `rows` rows, stream-ordered on s; sink is one device word it almost never
 // writes.

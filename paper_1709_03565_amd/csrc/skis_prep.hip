@@ -33,16 +33,25 @@ __device__ __forceinline__ int check_edge(int32_t u, float wf, int64_t v, int32_
 // q[v] = the row's last P (1 for an empty row).  A row's products are one dependent chain
 // of multiplies, so a long row is bound by the latency of that chain, not by bandwidth.
 
+// Rows longer than LONG_ROW (with bounds inside [0, m]), listed first so that k_prep_long can
+// run beside k_prep_rows.
+__global__ __launch_bounds__(256) void k_find_long(int32_t n, int64_t m, const int32_t *__restrict__ row_ptr,
+                                                   int32_t *__restrict__ long_rows, unsigned int *__restrict__ n_long)
+{
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t a = row_ptr[v], b = row_ptr[v + 1];
+        if (a >= 0 && (int64_t)b <= m && b - a > LONG_ROW) long_rows[atomicAdd(n_long, 1u)] = (int32_t)v;
+    }
+}
+
 // One thread per row: validates the row, writes the interleaved (col, w) records, P and q.
-// Rows longer than LONG_ROW are listed for k_prep_long.  lt: running sums S in P (S[e] =
-// S[e-1] + w[e], 0 before the row's first edge) and q = 1 - the row's sum.
+// Rows longer than LONG_ROW are k_prep_long's.  lt: running sums S in P (S[e] = S[e-1] + w[e],
+// 0 before the row's first edge) and q = 1 - the row's sum.
 __global__ __launch_bounds__(256) void k_prep_rows(int32_t n, int64_t m, const int32_t *__restrict__ row_ptr,
                                                    const int32_t *__restrict__ col, const float *__restrict__ w,
                                                    int32_t *__restrict__ rp_copy, uint2 *__restrict__ edges,
                                                    uint32_t *__restrict__ wbits, double *__restrict__ P,
-                                                   double *__restrict__ q, int *err,
-                                                   int32_t *__restrict__ long_rows, unsigned int *__restrict__ n_long,
-                                                   int lt)
+                                                   double *__restrict__ q, int *err, int lt)
 {
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
         const int32_t a = row_ptr[v], b = row_ptr[v + 1];
@@ -56,8 +65,7 @@ __global__ __launch_bounds__(256) void k_prep_rows(int32_t n, int64_t m, const i
             q[v] = 1.0;
             continue;
         }
-        if (b - a > LONG_ROW) {
-            long_rows[atomicAdd(n_long, 1u)] = (int32_t)v;
+        if (b - a > LONG_ROW) { // listed by k_find_long
             if (bad) atomicOr(err, bad);
             continue;
         }
@@ -82,33 +90,42 @@ __global__ __launch_bounds__(256) void k_prep_rows(int32_t n, int64_t m, const i
     }
 }
 
-// One 256-thread workgroup per long row, LONG_EDGES in-edges at a time, every global access
-// coalesced: (1) each thread loads, validates and writes LONG_PER edges and puts their
-// factors (1 - w) in LDS (1.0 past the row's end: a multiply by 1 is exact); (2) lane 0
-// carries the row's running product through the chunk, CHAIN_BATCH factors at a time held
-// in registers with the next batch's LDS reads issued before the multiplies, so that the
-// loop's critical path is the dependent multiplies alone; (3) every thread writes its
-// LONG_PER products out.  The next chunk's edge loads are in flight during (2).  lt: the
-// terms are w (0 past the row's end: adding 0 is exact) and the chain adds.
+// One 256-thread workgroup per long row (the next row of the list taken with one atomic, so
+// that the workgroup holding the longest row takes no other), LONG_EDGES in-edges at a time,
+// every global access coalesced: (1) each thread loads, validates and writes LONG_PER edges and
+// puts their factors (1 - w) in LDS (1.0 past the row's end: a multiply by 1 is exact); (2)
+// lane 0 carries the row's running product through the chunk, CHAIN_BATCH factors at a time
+// held in registers, two register batches in turn: while one batch is multiplied in, the
+// other is read from LDS, so that the loop's critical path is the dependent multiplies alone
+// and no register copies sit on it; (3) every thread writes its LONG_PER products out.  The
+// next chunk's edge loads are in flight during (2).  lt: the terms are w (0 past the row's
+// end: adding 0 is exact) and the chain adds.
 constexpr int LONG_EDGES = 4096;
 constexpr int LONG_PER = LONG_EDGES / 256;
 constexpr int CHAIN_BATCH = 16;
+static_assert(LONG_EDGES % (2 * CHAIN_BATCH) == 0, "a chunk is whole trips of two batches");
 
 __global__ __launch_bounds__(256) void k_prep_long(int32_t n, const int32_t *__restrict__ row_ptr,
                                                    const int32_t *__restrict__ col, const float *__restrict__ w,
                                                    uint2 *__restrict__ edges, uint32_t *__restrict__ wbits,
                                                    double *__restrict__ P, double *__restrict__ q, int *err,
                                                    const int32_t *__restrict__ long_rows,
-                                                   const unsigned int *__restrict__ n_long, int lt)
+                                                   const unsigned int *__restrict__ n_long,
+                                                   unsigned int *__restrict__ next_row, int lt)
 {
     __shared__ double s_f[LONG_EDGES + CHAIN_BATCH]; // factors of the chunk (+ one batch read ahead)
     __shared__ double s_p[LONG_EDGES];               // their running products
     __shared__ double s_run;
+    __shared__ unsigned int s_r;
     const int t = threadIdx.x;
     const unsigned int cnt = *n_long;
     const double ident = lt ? 0.0 : 1.0;
     if (t < CHAIN_BATCH) s_f[LONG_EDGES + t] = ident;
-    for (unsigned int r = blockIdx.x; r < cnt; r += gridDim.x) {
+    for (;;) {
+        if (t == 0) s_r = atomicAdd(next_row, 1u);
+        __syncthreads();
+        const unsigned int r = s_r;
+        if (r >= cnt) break;
         const int32_t v = long_rows[r];
         const int32_t a = row_ptr[v], b = row_ptr[v + 1];
         int bad = 0;
@@ -150,29 +167,46 @@ __global__ __launch_bounds__(256) void k_prep_long(int32_t n, const int32_t *__r
             const int len = min(b - c0, LONG_EDGES);
             // (2) the chain, in row order
             if (t == 0) {
+                // batches i0 .. i0 + 2 CHAIN_BATCH - 1 per trip; entries from len to the end of
+                // the trip hold the identity (phase (1) and the read-ahead pad), so running
+                // through them leaves the product as it is
                 double run = s_run;
-                double fc[CHAIN_BATCH];
+                double fa[CHAIN_BATCH], fb[CHAIN_BATCH];
 #pragma unroll
-                for (int k = 0; k < CHAIN_BATCH; ++k) fc[k] = s_f[k];
-                for (int i0 = 0; i0 < len; i0 += CHAIN_BATCH) {
-                    double fn[CHAIN_BATCH];
+                for (int k = 0; k < CHAIN_BATCH; ++k) fa[k] = s_f[k];
+                for (int i0 = 0; i0 < len; i0 += 2 * CHAIN_BATCH) {
 #pragma unroll
-                    for (int k = 0; k < CHAIN_BATCH; ++k) fn[k] = s_f[i0 + CHAIN_BATCH + k];
+                    for (int k = 0; k < CHAIN_BATCH; ++k) fb[k] = s_f[i0 + CHAIN_BATCH + k];
                     if (lt) {
 #pragma unroll
                         for (int k = 0; k < CHAIN_BATCH; ++k) {
-                            run = __dadd_rn(run, fc[k]);
+                            run = __dadd_rn(run, fa[k]);
                             s_p[i0 + k] = run;
                         }
                     } else {
 #pragma unroll
                         for (int k = 0; k < CHAIN_BATCH; ++k) {
-                            run = __dmul_rn(run, fc[k]);
+                            run = __dmul_rn(run, fa[k]);
                             s_p[i0 + k] = run;
                         }
                     }
+                    // the next trip's first batch (past the chunk: the pad, never used)
+                    const int nx = i0 + 2 * CHAIN_BATCH < LONG_EDGES ? i0 + 2 * CHAIN_BATCH : LONG_EDGES;
 #pragma unroll
-                    for (int k = 0; k < CHAIN_BATCH; ++k) fc[k] = fn[k];
+                    for (int k = 0; k < CHAIN_BATCH; ++k) fa[k] = s_f[nx + k];
+                    if (lt) {
+#pragma unroll
+                        for (int k = 0; k < CHAIN_BATCH; ++k) {
+                            run = __dadd_rn(run, fb[k]);
+                            s_p[i0 + CHAIN_BATCH + k] = run;
+                        }
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < CHAIN_BATCH; ++k) {
+                            run = __dmul_rn(run, fb[k]);
+                            s_p[i0 + CHAIN_BATCH + k] = run;
+                        }
+                    }
                 }
                 s_run = run;
             }
@@ -384,17 +418,39 @@ void preprocess(Arena &arena, int32_t n, int64_t m, const int32_t *row_ptr, cons
     out.W.alloc(arena, (size_t)n);
     SKIS_HIP_TRY(hipMemsetAsync(out.edges.ptr, 0, out.edges.bytes(), s));
     DevBuf<int> err;
-    err.alloc(arena, 2);
-    SKIS_HIP_TRY(hipMemsetAsync(err.ptr, 0, 2 * sizeof(int), s));
+    err.alloc(arena, 4);
+    SKIS_HIP_TRY(hipMemsetAsync(err.ptr, 0, 4 * sizeof(int), s));
     DevBuf<int32_t> long_rows;
     long_rows.alloc(arena, (size_t)n);
     unsigned int *n_long = reinterpret_cast<unsigned int *>(err.ptr + 1);
+    unsigned int *next_long = reinterpret_cast<unsigned int *>(err.ptr + 2);
+    // the long rows' chains (bound by their length) run on a second stream beside the short rows
+    hipLaunchKernelGGL(k_find_long, dim3(grid_for(n)), dim3(256), 0, s, n, m, row_ptr, long_rows.ptr, n_long);
+    SKIS_HIP_TRY(hipGetLastError());
+    hipStream_t s2 = side_stream();
+    hipEvent_t fork = nullptr, join = nullptr;
+    SKIS_HIP_TRY(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+    struct EvGuard {
+        hipEvent_t *a, *b;
+        ~EvGuard()
+        {
+            if (*a) (void)hipEventDestroy(*a);
+            if (*b) (void)hipEventDestroy(*b);
+        }
+    } evg{&fork, &join};
+    SKIS_HIP_TRY(hipEventCreateWithFlags(&join, hipEventDisableTiming));
+    SKIS_HIP_TRY(hipEventRecord(fork, s));
+    SKIS_HIP_TRY(hipStreamWaitEvent(s2, fork, 0));
+    hipLaunchKernelGGL(k_prep_long, dim3((unsigned)device_cu_count() * 4), dim3(256), 0, s2, n, row_ptr, col, w,
+                       out.edges.ptr, out.wbits.ptr, out.P.ptr, out.q.ptr, err.ptr, long_rows.ptr, n_long, next_long,
+                       lt);
+    const hipError_t long_err = hipGetLastError();
+    SKIS_HIP_TRY(hipEventRecord(join, s2));
     hipLaunchKernelGGL(k_prep_rows, dim3(grid_for(n)), dim3(256), 0, s, n, m, row_ptr, col, w, out.row_ptr.ptr,
-                       out.edges.ptr, out.wbits.ptr, out.P.ptr, out.q.ptr, err.ptr, long_rows.ptr, n_long, lt);
+                       out.edges.ptr, out.wbits.ptr, out.P.ptr, out.q.ptr, err.ptr, lt);
     SKIS_HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_prep_long, dim3((unsigned)device_cu_count() * 4), dim3(256), 0, s, n, row_ptr, col, w,
-                       out.edges.ptr, out.wbits.ptr, out.P.ptr, out.q.ptr, err.ptr, long_rows.ptr, n_long, lt);
-    SKIS_HIP_TRY(hipGetLastError());
+    SKIS_HIP_TRY(hipStreamWaitEvent(s, join, 0));
+    SKIS_HIP_TRY(long_err);
     int herr = 0;
     SKIS_HIP_TRY(hipMemcpyAsync(&herr, err.ptr, sizeof(int), hipMemcpyDeviceToHost, s));
     SKIS_HIP_TRY(hipStreamSynchronize(s));
