@@ -17,6 +17,7 @@ constexpr double LT_SUM_SLACK = 0x1p-20;
 __device__ __forceinline__ double lt_q(double sum) { return sum < 1.0 ? __dsub_rn(1.0, sum) : 0.0; }
 
 constexpr int32_t LONG_ROW = 256; // rows above this length are taken by a whole workgroup
+constexpr int ROW_BATCH = 8;      // edges a row thread loads at a time
 
 __device__ __forceinline__ int check_edge(int32_t u, float wf, int64_t v, int32_t n)
 {
@@ -35,12 +36,27 @@ __device__ __forceinline__ int check_edge(int32_t u, float wf, int64_t v, int32_
 
 // Rows longer than LONG_ROW (with bounds inside [0, m]), listed first so that k_prep_long can
 // run beside k_prep_rows.
+// One atomic per wave: a ballot of the wave's long rows, then each takes its rank.
 __global__ __launch_bounds__(256) void k_find_long(int32_t n, int64_t m, const int32_t *__restrict__ row_ptr,
                                                    int32_t *__restrict__ long_rows, unsigned int *__restrict__ n_long)
 {
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t a = row_ptr[v], b = row_ptr[v + 1];
-        if (a >= 0 && (int64_t)b <= m && b - a > LONG_ROW) long_rows[atomicAdd(n_long, 1u)] = (int32_t)v;
+    const int lane = threadIdx.x & 63;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    // every lane runs the same trip count, so the whole wave takes part in each ballot
+    for (int64_t v0 = (int64_t)blockIdx.x * blockDim.x; v0 < n; v0 += stride) {
+        const int64_t v = v0 + threadIdx.x;
+        bool is_long = false;
+        if (v < n) {
+            const int32_t a = row_ptr[v], b = row_ptr[v + 1];
+            is_long = a >= 0 && (int64_t)b <= m && b - a > LONG_ROW;
+        }
+        const unsigned long long mask = __ballot(is_long);
+        if (mask) {
+            unsigned int base = 0;
+            if (lane == 0) base = atomicAdd(n_long, (unsigned int)__popcll(mask));
+            base = (unsigned int)__builtin_amdgcn_readfirstlane((int)base);
+            if (is_long) long_rows[base + (unsigned int)__popcll(mask & ((1ull << lane) - 1ull))] = (int32_t)v;
+        }
     }
 }
 
@@ -69,16 +85,46 @@ __global__ __launch_bounds__(256) void k_prep_rows(int32_t n, int64_t m, const i
             if (bad) atomicOr(err, bad);
             continue;
         }
+        // ROW_BATCH edges at a time, the next batch's loads issued (clamped to the row's last
+        // edge, so unconditionally) before this batch is used: one memory latency per batch
         double run = lt ? 0.0 : 1.0;
-        for (int32_t e = a; e < b; ++e) {
-            const int32_t u = col[e];
-            float wf = w[e];
-            bad |= check_edge(u, wf, v, n);
-            if (wf == 0.0f) wf = 0.0f; // -0 -> +0: the coin reads the bits
-            edges[e] = make_uint2((uint32_t)u, coin_threshold_hi(__float_as_uint(wf)));
-            wbits[e] = __float_as_uint(wf);
-            run = lt ? __dadd_rn(run, (double)wf) : __dmul_rn(run, __dsub_rn(1.0, (double)wf));
-            P[e] = run;
+        if (b > a) {
+            int32_t uc[ROW_BATCH];
+            float wc[ROW_BATCH];
+#pragma unroll
+            for (int k = 0; k < ROW_BATCH; ++k) {
+                const int32_t e = min(a + k, b - 1);
+                uc[k] = col[e];
+                wc[k] = w[e];
+            }
+            for (int32_t e0 = a; e0 < b; e0 += ROW_BATCH) {
+                int32_t un[ROW_BATCH];
+                float wn[ROW_BATCH];
+#pragma unroll
+                for (int k = 0; k < ROW_BATCH; ++k) {
+                    const int32_t e = min(e0 + ROW_BATCH + k, b - 1);
+                    un[k] = col[e];
+                    wn[k] = w[e];
+                }
+#pragma unroll
+                for (int k = 0; k < ROW_BATCH; ++k) {
+                    const int32_t e = e0 + k;
+                    if (e >= b) break;
+                    const int32_t u = uc[k];
+                    float wf = wc[k];
+                    bad |= check_edge(u, wf, v, n);
+                    if (wf == 0.0f) wf = 0.0f; // -0 -> +0: the coin reads the bits
+                    edges[e] = make_uint2((uint32_t)u, coin_threshold_hi(__float_as_uint(wf)));
+                    wbits[e] = __float_as_uint(wf);
+                    run = lt ? __dadd_rn(run, (double)wf) : __dmul_rn(run, __dsub_rn(1.0, (double)wf));
+                    P[e] = run;
+                }
+#pragma unroll
+                for (int k = 0; k < ROW_BATCH; ++k) {
+                    uc[k] = un[k];
+                    wc[k] = wn[k];
+                }
+            }
         }
         if (lt) {
             if (run > 1.0 + LT_SUM_SLACK) bad |= ERR_LTSUM;
@@ -91,19 +137,26 @@ __global__ __launch_bounds__(256) void k_prep_rows(int32_t n, int64_t m, const i
 }
 
 // One 256-thread workgroup per long row (the next row of the list taken with one atomic, so
-// that the workgroup holding the longest row takes no other), LONG_EDGES in-edges at a time,
-// every global access coalesced: (1) each thread loads, validates and writes LONG_PER edges and
-// puts their factors (1 - w) in LDS (1.0 past the row's end: a multiply by 1 is exact); (2)
-// lane 0 carries the row's running product through the chunk, CHAIN_BATCH factors at a time
-// held in registers, two register batches in turn: while one batch is multiplied in, the
-// other is read from LDS, so that the loop's critical path is the dependent multiplies alone
-// and no register copies sit on it; (3) every thread writes its LONG_PER products out.  The
-// next chunk's edge loads are in flight during (2).  lt: the terms are w (0 past the row's
-// end: adding 0 is exact) and the chain adds.
+// that the workgroup holding the longest row takes no other), LONG_EDGES in-edges at a time.
+// A row's products are one dependent chain; on the longest row that chain bounds the whole
+// preprocessing, so lane 0 of wave 0 does nothing but run it: it reads two fp64 factors per
+// LDS read (the reads of one trip of 32 in flight while the other trip's multiplies run) and
+// keeps, every LONG_BLK products, the running product before the block (a checkpoint).  The
+// other three waves, at the same time, load chunk c + 1 (coalesced), validate it, write its
+// edge records and w bits and put its factors 1 - w into LDS (1 past the row's end: a multiply
+// by 1 leaves the chain as it is), and rebuild the products of chunk c - 1: each thread takes
+// a block, starts from its checkpoint and multiplies the same factors in the same order, so
+// every product is the chain's own, and writes them out.  Lane 0 thus issues no store and one
+// LDS read per two factors: a single lane's LDS and global stores had made the chain up to
+// four times slower than its multiplies.  Three factor buffers rotate (chained, fed, rebuilt).
+// lt: the terms are w (0 past the row's end) and the chain adds.
 constexpr int LONG_EDGES = 4096;
-constexpr int LONG_PER = LONG_EDGES / 256;
-constexpr int CHAIN_BATCH = 16;
-static_assert(LONG_EDGES % (2 * CHAIN_BATCH) == 0, "a chunk is whole trips of two batches");
+constexpr int LONG_TRIP = 32;                  // factors per trip of the chain
+constexpr int LONG_PAD = 2 * LONG_TRIP;        // read-ahead past a chunk
+constexpr int LONG_BLK = 64;                   // products per checkpoint
+constexpr int LONG_FEED = 192;                 // threads of waves 1-3
+static_assert(LONG_EDGES % LONG_BLK == 0 && LONG_BLK == 2 * LONG_TRIP, "checkpoints fall on trip pairs");
+static_assert(LONG_EDGES / LONG_BLK <= LONG_FEED, "one rebuilt block per feeding thread");
 
 __global__ __launch_bounds__(256) void k_prep_long(int32_t n, const int32_t *__restrict__ row_ptr,
                                                    const int32_t *__restrict__ col, const float *__restrict__ w,
@@ -113,14 +166,32 @@ __global__ __launch_bounds__(256) void k_prep_long(int32_t n, const int32_t *__r
                                                    const unsigned int *__restrict__ n_long,
                                                    unsigned int *__restrict__ next_row, int lt)
 {
-    __shared__ double s_f[LONG_EDGES + CHAIN_BATCH]; // factors of the chunk (+ one batch read ahead)
-    __shared__ double s_p[LONG_EDGES];               // their running products
-    __shared__ double s_run;
+    __shared__ __align__(16) double s_f[3][LONG_EDGES + LONG_PAD]; // factors of three chunks (+ read-ahead pad)
+    __shared__ double s_ck[2][LONG_EDGES / LONG_BLK];               // checkpoints of two chunks
     __shared__ unsigned int s_r;
     const int t = threadIdx.x;
     const unsigned int cnt = *n_long;
     const double ident = lt ? 0.0 : 1.0;
-    if (t < CHAIN_BATCH) s_f[LONG_EDGES + t] = ident;
+    for (int i = t; i < LONG_PAD; i += 256) s_f[0][LONG_EDGES + i] = s_f[1][LONG_EDGES + i] = s_f[2][LONG_EDGES + i] = ident;
+    // waves 1-3 put chunk c0 of row v (edges [c0, b)) into buffer `buf`; returns their flags
+    auto feed = [&](int32_t v, int32_t c0, int32_t b, int buf) -> int {
+        int bad = 0;
+        for (int i = t - 64; i < LONG_EDGES; i += LONG_FEED) {
+            const int32_t e = c0 + i;
+            double f = ident;
+            if (e < b) {
+                const int32_t u = col[e];
+                float wf = w[e];
+                bad |= check_edge(u, wf, v, n);
+                if (wf == 0.0f) wf = 0.0f; // -0 -> +0: the coin reads the bits
+                edges[e] = make_uint2((uint32_t)u, coin_threshold_hi(__float_as_uint(wf)));
+                wbits[e] = __float_as_uint(wf);
+                f = lt ? (double)wf : __dsub_rn(1.0, (double)wf);
+            }
+            s_f[buf][i] = f;
+        }
+        return bad;
+    };
     for (;;) {
         if (t == 0) s_r = atomicAdd(next_row, 1u);
         __syncthreads();
@@ -128,104 +199,69 @@ __global__ __launch_bounds__(256) void k_prep_long(int32_t n, const int32_t *__r
         if (r >= cnt) break;
         const int32_t v = long_rows[r];
         const int32_t a = row_ptr[v], b = row_ptr[v + 1];
+        const int nchunks = (b - a + LONG_EDGES - 1) / LONG_EDGES;
         int bad = 0;
-        if (t == 0) s_run = ident;
-        // element k of a thread's share of a chunk is edge c0 + k * 256 + t (coalesced per k);
-        // the loads are unconditional (an index past the row reads its last edge, unused), so
-        // that the compiler can keep the next chunk's loads in flight across a chunk
-        int32_t uc[LONG_PER];
-        float wc[LONG_PER];
-#pragma unroll
-        for (int k = 0; k < LONG_PER; ++k) {
-            const int32_t e = min(a + k * 256 + t, b - 1);
-            uc[k] = col[e];
-            wc[k] = w[e];
-        }
-        for (int32_t c0 = a; c0 < b; c0 += LONG_EDGES) {
-            // (1) this chunk's edges and factors, then the next chunk's loads
-#pragma unroll
-            for (int k = 0; k < LONG_PER; ++k) {
-                const int32_t e = c0 + k * 256 + t;
-                double f = ident;
-                if (e < b) {
-                    float wf = wc[k];
-                    bad |= check_edge(uc[k], wf, v, n);
-                    if (wf == 0.0f) wf = 0.0f; // -0 -> +0: the coin reads the bits
-                    edges[e] = make_uint2((uint32_t)uc[k], coin_threshold_hi(__float_as_uint(wf)));
-                    wbits[e] = __float_as_uint(wf);
-                    f = lt ? (double)wf : __dsub_rn(1.0, (double)wf);
-                }
-                s_f[k * 256 + t] = f;
-            }
-#pragma unroll
-            for (int k = 0; k < LONG_PER; ++k) {
-                const int32_t e = min(c0 + LONG_EDGES + k * 256 + t, b - 1);
-                uc[k] = col[e];
-                wc[k] = w[e];
-            }
-            __syncthreads();
-            const int len = min(b - c0, LONG_EDGES);
-            // (2) the chain, in row order
-            if (t == 0) {
-                // batches i0 .. i0 + 2 CHAIN_BATCH - 1 per trip; entries from len to the end of
-                // the trip hold the identity (phase (1) and the read-ahead pad), so running
-                // through them leaves the product as it is
-                double run = s_run;
-                double fa[CHAIN_BATCH], fb[CHAIN_BATCH];
-#pragma unroll
-                for (int k = 0; k < CHAIN_BATCH; ++k) fa[k] = s_f[k];
-                for (int i0 = 0; i0 < len; i0 += 2 * CHAIN_BATCH) {
-#pragma unroll
-                    for (int k = 0; k < CHAIN_BATCH; ++k) fb[k] = s_f[i0 + CHAIN_BATCH + k];
-                    if (lt) {
-#pragma unroll
-                        for (int k = 0; k < CHAIN_BATCH; ++k) {
-                            run = __dadd_rn(run, fa[k]);
-                            s_p[i0 + k] = run;
-                        }
-                    } else {
-#pragma unroll
-                        for (int k = 0; k < CHAIN_BATCH; ++k) {
-                            run = __dmul_rn(run, fa[k]);
-                            s_p[i0 + k] = run;
-                        }
-                    }
-                    // the next trip's first batch (past the chunk: the pad, never used)
-                    const int nx = i0 + 2 * CHAIN_BATCH < LONG_EDGES ? i0 + 2 * CHAIN_BATCH : LONG_EDGES;
-#pragma unroll
-                    for (int k = 0; k < CHAIN_BATCH; ++k) fa[k] = s_f[nx + k];
-                    if (lt) {
-#pragma unroll
-                        for (int k = 0; k < CHAIN_BATCH; ++k) {
-                            run = __dadd_rn(run, fb[k]);
-                            s_p[i0 + CHAIN_BATCH + k] = run;
-                        }
-                    } else {
-#pragma unroll
-                        for (int k = 0; k < CHAIN_BATCH; ++k) {
-                            run = __dmul_rn(run, fb[k]);
-                            s_p[i0 + CHAIN_BATCH + k] = run;
-                        }
-                    }
-                }
-                s_run = run;
-            }
-            __syncthreads();
-            // (3) the products out (s_f is rewritten by the next chunk's (1) only after every
-            // lane has passed the barrier above; s_p by its (2) only after the next barrier)
-#pragma unroll
-            for (int k = 0; k < LONG_PER; ++k) {
-                const int i = k * 256 + t;
-                if (i < len) P[c0 + i] = s_p[i];
-            }
-        }
+        if (t >= 64) bad |= feed(v, a, b, 0);
         __syncthreads();
+        double run = ident; // lane 0's chain
+        for (int c = 0; c <= nchunks; ++c) {
+            if (t == 0) {
+                if (c < nchunks) {
+                    const double *F = s_f[c % 3];
+                    double *CK = s_ck[c & 1];
+                    const int len = min(b - (a + c * LONG_EDGES), LONG_EDGES);
+                    double2 xa[LONG_TRIP / 2], xb[LONG_TRIP / 2];
+#pragma unroll
+                    for (int k = 0; k < LONG_TRIP / 2; ++k) xa[k] = reinterpret_cast<const double2 *>(F)[k];
+                    for (int i0 = 0; i0 < len; i0 += LONG_BLK) {
+                        CK[i0 / LONG_BLK] = run; // the product before element i0
+#pragma unroll
+                        for (int k = 0; k < LONG_TRIP / 2; ++k)
+                            xb[k] = reinterpret_cast<const double2 *>(F + i0 + LONG_TRIP)[k];
+                        if (lt) {
+#pragma unroll
+                            for (int k = 0; k < LONG_TRIP / 2; ++k) run = __dadd_rn(__dadd_rn(run, xa[k].x), xa[k].y);
+                        } else {
+#pragma unroll
+                            for (int k = 0; k < LONG_TRIP / 2; ++k) run = __dmul_rn(__dmul_rn(run, xa[k].x), xa[k].y);
+                        }
+#pragma unroll
+                        for (int k = 0; k < LONG_TRIP / 2; ++k)
+                            xa[k] = reinterpret_cast<const double2 *>(F + i0 + LONG_BLK)[k];
+                        if (lt) {
+#pragma unroll
+                            for (int k = 0; k < LONG_TRIP / 2; ++k) run = __dadd_rn(__dadd_rn(run, xb[k].x), xb[k].y);
+                        } else {
+#pragma unroll
+                            for (int k = 0; k < LONG_TRIP / 2; ++k) run = __dmul_rn(__dmul_rn(run, xb[k].x), xb[k].y);
+                        }
+                    }
+                }
+            } else if (t >= 64) {
+                if (c + 1 < nchunks) bad |= feed(v, a + (c + 1) * LONG_EDGES, b, (c + 1) % 3);
+                if (c >= 1) { // rebuild chunk c - 1 from its checkpoints, one block per thread
+                    const int32_t cp0 = a + (c - 1) * LONG_EDGES;
+                    const int lenp = min(b - cp0, LONG_EDGES);
+                    const double *F = s_f[(c - 1) % 3];
+                    const int blk = t - 64;
+                    if (blk * LONG_BLK < lenp) {
+                        double x = s_ck[(c - 1) & 1][blk];
+                        const int i1 = min(lenp, (blk + 1) * LONG_BLK);
+                        for (int i = blk * LONG_BLK; i < i1; ++i) {
+                            x = lt ? __dadd_rn(x, F[i]) : __dmul_rn(x, F[i]);
+                            P[cp0 + i] = x;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
         if (t == 0) {
             if (lt) {
-                if (s_run > 1.0 + LT_SUM_SLACK) bad |= ERR_LTSUM;
-                q[v] = lt_q(s_run);
+                if (run > 1.0 + LT_SUM_SLACK) bad |= ERR_LTSUM;
+                q[v] = lt_q(run);
             } else {
-                q[v] = s_run;
+                q[v] = run;
             }
         }
         if (bad) atomicOr(err, bad);
@@ -424,6 +460,7 @@ void preprocess(Arena &arena, int32_t n, int64_t m, const int32_t *row_ptr, cons
     long_rows.alloc(arena, (size_t)n);
     unsigned int *n_long = reinterpret_cast<unsigned int *>(err.ptr + 1);
     unsigned int *next_long = reinterpret_cast<unsigned int *>(err.ptr + 2);
+    if (reinterpret_cast<uintptr_t>(out.P.ptr) & 15) throw Error{SKIS_EHIP, "internal error: P is not 16-byte aligned"};
     // the long rows' chains (bound by their length) run on a second stream beside the short rows
     hipLaunchKernelGGL(k_find_long, dim3(grid_for(n)), dim3(256), 0, s, n, m, row_ptr, long_rows.ptr, n_long);
     SKIS_HIP_TRY(hipGetLastError());
@@ -441,7 +478,7 @@ void preprocess(Arena &arena, int32_t n, int64_t m, const int32_t *row_ptr, cons
     SKIS_HIP_TRY(hipEventCreateWithFlags(&join, hipEventDisableTiming));
     SKIS_HIP_TRY(hipEventRecord(fork, s));
     SKIS_HIP_TRY(hipStreamWaitEvent(s2, fork, 0));
-    hipLaunchKernelGGL(k_prep_long, dim3((unsigned)device_cu_count() * 4), dim3(256), 0, s2, n, row_ptr, col, w,
+    hipLaunchKernelGGL(k_prep_long, dim3((unsigned)device_cu_count()), dim3(256), 0, s2, n, row_ptr, col, w,
                        out.edges.ptr, out.wbits.ptr, out.P.ptr, out.q.ptr, err.ptr, long_rows.ptr, n_long, next_long,
                        lt);
     const hipError_t long_err = hipGetLastError();
