@@ -1049,6 +1049,40 @@ __global__ __launch_bounds__(256) void k_class_fill(uint64_t T, const uint32_t *
     }
 }
 
+// Bitonic network over the W * R values of a segment of W lanes, element e = t * R + r in v[r]
+// of lane t: exchanges at distance d < R stay in the lane, the others are shuffles at lane
+// distance d / R within the segment.  Every lane of the wave runs it.
+template <int W, int R>
+__device__ __forceinline__ void bitonic_regs(int32_t (&v)[R], int t)
+{
+    constexpr int P = W * R;
+#pragma unroll
+    for (int k = 2; k <= P; k <<= 1) {
+#pragma unroll
+        for (int d = k >> 1; d > 0; d >>= 1) {
+            if (d < R) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    if (r & d) continue;
+                    const bool asc = ((t * R + r) & k) == 0;
+                    const int32_t x = v[r], y = v[r | d];
+                    v[r] = asc ? min(x, y) : max(x, y);
+                    v[r | d] = asc ? max(x, y) : min(x, y);
+                }
+            } else {
+                const int ld = d / R;
+                const bool low = (t & ld) == 0;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const bool asc = ((t * R + r) & k) == 0;
+                    const int32_t y = __shfl_xor(v[r], ld, 64);
+                    v[r] = (low == asc) ? min(v[r], y) : max(v[r], y);
+                }
+            }
+        }
+    }
+}
+
 // Segments of W lanes each sort one sample of up to W * R nodes in registers (64 / W samples
 // per wave and step).  Node slot r * W + t of the sample is loaded by lane t of the segment
 // into v[r] (coalesced; padding INT32_MAX), then a bitonic network sorts the W * R values
@@ -1064,7 +1098,7 @@ __global__ __launch_bounds__(64) void k_gather_sort(int cls, const unsigned long
                                                     const int32_t *__restrict__ staging, int32_t *__restrict__ nodes,
                                                     int32_t *__restrict__ owner)
 {
-    constexpr int G = 64 / W, P = W * R;
+    constexpr int G = 64 / W;
     const int lane = threadIdx.x, seg = lane / W, t = lane % W;
     unsigned long long base = 0;
     for (int k = 0; k < cls; ++k) base += counts[k];
@@ -1096,31 +1130,7 @@ __global__ __launch_bounds__(64) void k_gather_sort(int cls, const unsigned long
             v[r] = staging[o + (x < (int)sz ? x : 0)];
             if (x >= (int)sz) v[r] = INT32_MAX;
         }
-#pragma unroll
-        for (int k = 2; k <= P; k <<= 1) {
-#pragma unroll
-            for (int d = k >> 1; d > 0; d >>= 1) {
-                if (d < R) {
-#pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        if (r & d) continue;
-                        const bool asc = ((t * R + r) & k) == 0;
-                        const int32_t x = v[r], y = v[r | d];
-                        v[r] = asc ? min(x, y) : max(x, y);
-                        v[r | d] = asc ? max(x, y) : min(x, y);
-                    }
-                } else {
-                    const int ld = d / R;
-                    const bool low = (t & ld) == 0;
-#pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        const bool asc = ((t * R + r) & k) == 0;
-                        const int32_t y = __shfl_xor(v[r], ld, 64);
-                        v[r] = (low == asc) ? min(v[r], y) : max(v[r], y);
-                    }
-                }
-            }
-        }
+        bitonic_regs<W, R>(v, t);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int e = t * R + r;
@@ -1137,6 +1147,54 @@ __global__ __launch_bounds__(64) void k_gather_sort(int cls, const unsigned long
     }
 }
 
+// Listed samples of (32 R, 64 R] nodes, one per wave, sorted in registers by the network above
+// (R nodes a lane); the next sample's list entry and bounds are loaded before the sort.
+template <int R>
+__global__ __launch_bounds__(64) void k_gather_medium_regs(uint64_t count, const uint32_t *__restrict__ list,
+                                                           const uint32_t *__restrict__ size,
+                                                           const unsigned long long *__restrict__ off,
+                                                           const int64_t *__restrict__ sptr,
+                                                           const int32_t *__restrict__ staging,
+                                                           int32_t *__restrict__ nodes, int32_t *__restrict__ owner)
+{
+    constexpr int LO = 32 * R, HI = 64 * R;
+    const int t = threadIdx.x;
+    uint64_t k = blockIdx.x;
+    if (k >= count) return;
+    uint32_t id = list[k];
+    uint32_t sz = size[id];
+    for (; k < count; k += gridDim.x) {
+        const uint64_t kn = k + gridDim.x < count ? k + gridDim.x : k;
+        const uint32_t idn = list[kn];
+        const uint32_t szn = size[idn];
+        if (sz > (uint32_t)LO && sz <= (uint32_t)HI) {
+            const unsigned long long o = off[id];
+            const int64_t dp = sptr[id];
+            int32_t v[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int x = r * 64 + t;
+                v[r] = x < (int)sz ? staging[o + x] : INT32_MAX;
+            }
+            bitonic_regs<64, R>(v, t);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int e = t * R + r;
+                if (e < (int)sz) {
+                    nodes[dp + e] = v[r];
+                    if (owner) owner[dp + e] = (int32_t)id;
+                }
+            }
+        }
+        id = idn;
+        sz = szn;
+    }
+}
+
+// Listed samples of (MEDIUM_REGS_MAX, SORT_LDS_MAX] nodes: a bitonic sort in LDS per workgroup.
+constexpr int MEDIUM_REGS_MAX = 2048; // sizes up to this are sorted in registers by k_gather_medium_regs<32>
+// (64 values a lane spill to scratch: the network is too large to unroll)
+
 __global__ __launch_bounds__(256) void k_gather_medium(uint64_t count, const uint32_t *__restrict__ list,
                                                        const uint32_t *__restrict__ size,
                                                        const unsigned long long *__restrict__ off,
@@ -1148,7 +1206,7 @@ __global__ __launch_bounds__(256) void k_gather_medium(uint64_t count, const uin
     for (uint64_t k = blockIdx.x; k < count; k += gridDim.x) {
         const uint32_t i = list[k];
         const int sz = (int)size[i];
-        if (sz > SORT_LDS_MAX) continue; // k_gather_large's
+        if (sz > SORT_LDS_MAX || sz <= MEDIUM_REGS_MAX) continue; // k_gather_large or k_gather_medium_regs takes it
         const int32_t *src = staging + off[i];
         int32_t *dst = nodes + sptr[i];
         if (owner)
@@ -2096,6 +2154,9 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
         SKIS_HIP_TRY(hipGetLastError());
     }
     if (hc.n_medium > n_large) {
+        const unsigned gm = grid_cap(hc.n_medium, 1, 16);
+        hipLaunchKernelGGL((k_gather_medium_regs<32>), dim3(gm), dim3(64), 0, s, (uint64_t)hc.n_medium, medium.ptr,
+                           out_size.ptr, out_off.ptr, sk.sample_ptr.ptr, staging.ptr, sk.nodes.ptr, owner_p);
         hipLaunchKernelGGL(k_gather_medium, dim3(grid_cap(hc.n_medium, 1, 4)), dim3(256), 0, s,
                            (uint64_t)hc.n_medium, medium.ptr, out_size.ptr, out_off.ptr, sk.sample_ptr.ptr,
                            staging.ptr, sk.nodes.ptr, owner_p);
