@@ -63,7 +63,7 @@ _TIER0 = {(64, 4, 192, 2): (256, 128), (64, 4, 192, 1): (256, 64), (64, 4, 256, 
           (64, 8, 192, 2): (256, 256), (64, 8, 192, 1): (256, 256), (64, 8, 256, 2): (344, 256),
           (64, 12, 192, 2): (256, 384), (64, 16, 128, 2): (172, 512), (64, 16, 64, 2): (88, 512),
           (256, 16, 128, 2): (172, 1024), (256, 32, 128, 2): (172, 1024), (256, 16, 256, 2): (344, 1024)}
-TIER1_KERNEL = "k_sample<64, 1, 1024, 1368, 64, 1, 1>"
+TIER1_KERNEL = "k_sample<64, 1, 1024, 1368, 64, 2, 1>"
 TIER2_KERNEL = "k_sample<64, 1, 12288, 16384, 64, 1, 2>"
 TIER3_KERNEL = "k_sample<1024, 1, 1, 1, 8192, 2, 3>"
 
@@ -449,6 +449,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="the headline workload only (no other workloads, serving run or random-read probe)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-captured", action="store_true",
+                    help="skip the captured-form build beside the headline (profiling runs: only the timed launches)")
     ap.add_argument("--serve", action="store_true",
                     help="serving benchmark alone: open-loop Poisson query stream against a resident sketch")
     ap.add_argument("--rate", type=float, default=50000.0, help="serving: offered queries per second")
@@ -586,7 +588,7 @@ def main():
     }
     if tuned is not None:
         line["config"]["sampler_options"] = autotune.options_from(tuned)
-    if args.form == 0 and not lt:
+    if args.form == 0 and not lt and not args.no_captured:
         # the captured form: the same chain captured into a HIP graph, replayed per chunk
         sk = skis.build_sketch(rp, col, w, T, inputs.SAMPLE_SEED, form=2, build_inverse_index=0, **opts)
         cinf = sk.info()

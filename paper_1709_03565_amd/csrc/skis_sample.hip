@@ -1445,8 +1445,10 @@ static const Variant kTier0[] = {
     {256, 16, 256, 2, k_sample<256, 16, 256, 344, 1024, 2, 0>},
 };
 // second tier: samples that outgrew the first, slots of 1024 nodes in LDS
+// (64 items a pass and two quads a lane: 341 ms at 1.4B edges against 350 with one quad,
+// 345 with 128 items, 399 and 469 with 128 and 256 items and one quad)
 static const Variant kTierMidV[] = {
-    {64, 1, 1024, 1, k_sample<64, 1, 1024, 1368, 64, 1, 1>},
+    {64, 1, 1024, 2, k_sample<64, 1, 1024, 1368, 64, 2, 1>},
     {256, 8, 1024, 2, k_sample<256, 8, 1024, 1368, 1024, 2, 1>},
 };
 // Third tier: one sample per one-wave workgroup, its visited set a hash of TIERH_HCAP slots

@@ -93,7 +93,7 @@ def test_bench_kernel_names_match_the_library_table():
         assert name == "k_sample<%d, %d, %d, %d, %d, %d, 0>" % (th, sl, vi, hcap, icap, pl)
     # the later tiers' names as the library instantiates them
     names = bench.tier_kernel_names({})
-    mid = re.search(r"kTierMidV\[\] = \{\s*\{64, 1, 1024, 1, (k_sample<[^>]*>)\}", src).group(1)
+    mid = re.search(r"kTierMidV\[\] = \{\s*\{64, 1, 1024, \d, (k_sample<[^>]*>)\}", src).group(1)
     assert names[1] == mid
     assert "kTierHash = %s;" % names[2].replace("12288", "TIERH_RCAP").replace("16384", "TIERH_HCAP") in src
     assert "kTierGlobal = k_sample<TIERG_BLOCK, TIERG_SLOTS, 1, 1, 8 * TIERG_BLOCK, 2, 3>;" in src
