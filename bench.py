@@ -449,6 +449,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="the headline workload only (no other workloads, serving run or random-read probe)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cache-gib", type=float, default=0.0,
+                    help="the library's idle-block cache and pool limits in GiB (0: its defaults)")
     ap.add_argument("--no-captured", action="store_true",
                     help="skip the captured-form build beside the headline (profiling runs: only the timed launches)")
     ap.add_argument("--serve", action="store_true",
@@ -484,6 +486,8 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     skis.lib()  # fails loudly if the HIP library is missing
+    if args.cache_gib > 0:
+        skis.set_memory_limits(int(args.cache_gib * (1 << 30)), int(args.cache_gib * (1 << 30)))
 
     if args.serve:
         name = "cl4m_tri" if inputs.WORKLOADS[args.workload].get("build_only") else args.workload
@@ -506,6 +510,7 @@ def main():
     log("workload", name, wl, "T", T)
     t = time.perf_counter()
     g, rp, col, w = load_graph(name, dev)
+    torch.cuda.empty_cache()  # the graph generator's temporaries go back to the device
     log("graph ready in %.1fs: n=%d m=%d" % (time.perf_counter() - t, g.n, g.m))
     opts = {}
     for key, val in (("slots_per_block", args.slots), ("visited_threshold", args.visited),
