@@ -383,6 +383,7 @@ def full_step_workload(name, dev, steps, warmup, k, queries, plain_compare, serv
     opts = {"model": 1} if lt else {}
     t = time.perf_counter()
     g, rp, col, w = load_graph(name, dev)
+    torch.cuda.empty_cache()
     log("%s graph ready in %.1fs" % (name, time.perf_counter() - t))
     sets = inputs.random_sets(g.n, queries, 50, seed=7)
     sp_np, sn_np = inputs.sets_to_csr(sets)
