@@ -357,13 +357,33 @@ def ris_comparison(g, rp, col, w, T, set_ptr, set_nodes):
     vz = ii.Gamma ** 2 * ci * (1 - ci)
     vy = float(g.n) ** 2 * cr * (1 - cr)
     ratio = vz / np.maximum(vy, 1e-300)
-    iis.free()
     ris.free()
+    # greedy identifiability (the synthetic analogue of the paper's Fig. 3): k seeds picked on
+    # small IIS and RIS sketches (5 sample seeds each), each seed set judged by Eq. eq21 on the
+    # large IIS sketch of the step's seed
+    import torch
+    k = 50
+    ptr = torch.tensor([0, k], dtype=torch.int64, device="cuda")
+    quality = []
+    for Ts in (1000, 10000, 100000):
+        got = {"iis": [], "ris": []}
+        for r in range(5):
+            for mode in ("iis", "ris"):
+                sk = skis.build_sketch(rp, col, w, Ts, 1000 + 10 * r + (mode == "ris"), ris_mode=int(mode == "ris"))
+                seeds = sk.greedy(k)[0]
+                sk.free()
+                got[mode].append(float(iis.estimate(ptr, seeds.to(torch.int32))[1][0]))
+        quality.append({"T": Ts, "k": k, "iis_mean": float(np.mean(got["iis"])), "ris_mean": float(np.mean(got["ris"])),
+                        "iis": got["iis"], "ris": got["ris"]})
+        log("greedy on T=%d: I_hat(seeds) IIS %.0f, RIS %.0f (judged on the T=%d IIS sketch)" %
+            (Ts, quality[-1]["iis_mean"], quality[-1]["ris_mean"], T))
+    iis.free()
     res = {"T": T, "singular_fraction": singular, "one_minus_gamma_over_n": 1.0 - ii.Gamma / g.n,
            "var_ratio_z_over_y_median": float(np.median(ratio)), "var_ratio_z_over_y_max": float(ratio.max()),
            "queries_var_z_le_var_y": int((vz <= vy).sum()), "queries": int(len(ci)),
            "ris_sampler_ms": ri.ms_tier0 + ri.ms_tier1 + ri.ms_tier2 + ri.ms_tier3, "ris_entries": ri.entries,
-           "iis_sampler_ms": ii.ms_tier0 + ii.ms_tier1 + ii.ms_tier2 + ii.ms_tier3, "iis_entries": ii.entries}
+           "iis_sampler_ms": ii.ms_tier0 + ii.ms_tier1 + ii.ms_tier2 + ii.ms_tier3, "iis_entries": ii.entries,
+           "greedy_quality": quality}
     log("RIS vs IIS: singular %.4f (1 - Gamma/n %.4f), Var[Z]/Var[Y] median %.3f max %.3f" %
         (singular, res["one_minus_gamma_over_n"], res["var_ratio_z_over_y_median"], res["var_ratio_z_over_y_max"]))
     return res
