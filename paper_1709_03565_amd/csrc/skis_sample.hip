@@ -31,6 +31,7 @@ constexpr uint32_t DEFERRED = 0xFFFFFFFFu;
 constexpr int SMALL_SORT = 1024;   // sizes up to this are sorted in registers by k_gather_sort
 constexpr int SORT_LDS_MAX = 8192; // sizes up to this are sorted in LDS by k_gather_medium,
                                    // larger ones through a node bitmap by k_gather_large
+constexpr int VQ_CAP = 64;        // live edges a wave queues before visiting them
 // sample ids taken from the global counter at a time: at least the slots of a workgroup
 template <int S>
 constexpr int id_batch() { return S <= 16 ? 16 : 32; }
@@ -242,6 +243,9 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
     constexpr bool WMAP_QUAD = BLOCK == 64 && QPL == 1;
     __shared__ uint32_t s_imap[WMAP_SLOT ? 64 : 1];
     __shared__ uint32_t s_qmap[WMAP_QUAD ? 64 : 1];
+    // per wave: the live edges of the pass's sweeps not yet visited (node, slot)
+    __shared__ int32_t s_vq_node[(BLOCK / 64) * VQ_CAP];
+    __shared__ uint8_t s_vq_slot[(BLOCK / 64) * VQ_CAP];
 
     const int tid = threadIdx.x;
     const int32_t n = a.n;
@@ -828,7 +832,28 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
         const int total = it_pb[nitems];
         const int qpl = total >= BLOCK * QPL ? QPL : (total + BLOCK - 1) / BLOCK;
         const int first_item = WMAP_QUAD ? (int)wave_incl_max_dpp(s_qmap[tid]) - 1 : 0;
-        for (int base = tid * qpl; base < total; base += BLOCK * qpl) {
+        // The live edges a sweep finds join the wave's queue, and the queue is visited (the
+        // visited-set inserts, one entry a lane) when it could not take the next sweep's and
+        // after the last sweep: the inserts run with most lanes busy instead of with the few
+        // lanes that hold a live edge in a sweep.  The nodes a pass adds are expanded in later
+        // passes only, so when they are inserted within the pass does not matter.  Every lane
+        // of a wave runs the same number of sweeps (the wave-level scan needs them all).
+        int32_t *const vq_node = s_vq_node + (tid >> 6) * VQ_CAP;
+        uint8_t *const vq_slot = s_vq_slot + (tid >> 6) * VQ_CAP;
+        uint32_t vq_n = 0; // entries in the wave's queue (the same in every lane)
+        auto vq_flush = [&]() {
+            if (vq_n == 0) return;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            for (uint32_t i = (uint32_t)(tid & 63); i < vq_n; i += 64) visit((int)vq_slot[i], vq_node[i]);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            vq_n = 0;
+        };
+        for (int base0 = 0; base0 < total; base0 += BLOCK * qpl) {
+            const int base = base0 + tid * qpl; // past total: no quad (the lane still takes part)
             int lo = 0, hi = nitems - 1; // last item whose first quad index is <= base
             if (WMAP_QUAD && base < BLOCK) {
                 lo = first_item; // the first sweep: quad base = tid
@@ -908,6 +933,14 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                 if (coin_live(SKIS_KARG(wbits)[e], coin_with_low_half(hw, (uint32_t)e, j, a.seed_lo, a.seed_hi)))
                     live |= 1u << c;
             }
+            // the sweep's live edges into the queue (visited at once when a sweep alone holds
+            // more than the queue can)
+            const uint32_t nl = (uint32_t)__popc(live);
+            const uint32_t incl = wave_incl_scan(nl);
+            const uint32_t tot = lane_value(incl, 63);
+            const bool direct = tot > (uint32_t)VQ_CAP;
+            if (tot && (direct || vq_n + tot > (uint32_t)VQ_CAP)) vq_flush();
+            uint32_t pos = vq_n + incl - nl;
             while (live) {
                 const int c = __ffs(live) - 1;
                 live &= live - 1u;
@@ -920,9 +953,18 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                 case 2: q = pr[QPL > 1 ? 2 : 0]; sl = ps[QPL > 1 ? 1 : 0]; break;
                 default: q = pr[QPL > 1 ? 3 : 0]; sl = ps[QPL > 1 ? 1 : 0]; break;
                 }
-                visit(sl, (int32_t)((c & 1) ? q.z : q.x));
+                const int32_t u = (int32_t)((c & 1) ? q.z : q.x);
+                if (direct) {
+                    visit(sl, u);
+                } else {
+                    vq_node[pos] = u;
+                    vq_slot[pos] = (uint8_t)sl;
+                    ++pos;
+                }
             }
+            if (!direct) vq_n += tot;
         }
+        vq_flush();
         bsync();
         if (!s_alive) break;
     }
