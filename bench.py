@@ -466,6 +466,7 @@ def main():
     ap.add_argument("--big-row", type=int, default=0)
     ap.add_argument("--qpl", type=int, default=0, help="edge quads per lane per sweep in the first tier (1 or 2)")
     ap.add_argument("--form", type=int, default=0, help="0: persistent sampler, 1: plain, 2: captured")
+    ap.add_argument("--chunk", type=int, default=0, help="captured form: sample ids per graph replay (0: the library's)")
     ap.add_argument("--autotune", action="store_true", help="autotune the first tier's shape on the workload first")
     ap.add_argument("--no-extras", action="store_true",
                     help="the headline workload only (no other workloads, serving run or random-read probe)")
@@ -536,7 +537,7 @@ def main():
     opts = {}
     for key, val in (("slots_per_block", args.slots), ("visited_threshold", args.visited),
                      ("threads_per_block", args.threads), ("big_row", args.big_row), ("quads_per_lane", args.qpl),
-                     ("form", args.form)):
+                     ("form", args.form), ("chunk_samples", args.chunk)):
         if val:
             opts[key] = val
     if lt:

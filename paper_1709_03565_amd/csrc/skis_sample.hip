@@ -1510,6 +1510,9 @@ constexpr int TIERG_SLOTS = 1;
 constexpr int TIERG_BLOCK = 1024;
 constexpr int TIERG_PER_CU = TIERG_BLOCK >= 512 ? 1 : 512 / TIERG_BLOCK;
 constexpr uint64_t TIERG_BUDGET = 32ull << 30;
+// captured form: sample ids per graph replay unless the caller names another count (every chunk
+// waits for its own largest samples, so fewer chunks finish sooner)
+constexpr uint64_t CHAIN_CHUNK_DEFAULT = 1ull << 24;
 static SampleKernel const kTierGlobal = k_sample<TIERG_BLOCK, TIERG_SLOTS, 1, 1, 8 * TIERG_BLOCK, 2, 3>;
 
 static const Variant &pick_variant(const Variant *vs, size_t nv, uint32_t threads, uint32_t slots, uint32_t visited,
@@ -1617,8 +1620,12 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
         pick_variant(kTier0, sizeof(kTier0) / sizeof(kTier0[0]), cfg.threads, cfg.slots, cfg.visited, cfg.qpl);
     const Variant &vm = kTierMidV[cfg.threads == 64 ? 0 : 1];
     // handover from tier 0 to tier 1 for the first ho_cap samples a launch hands on (the rest
-    // start over in tier 1): about 3 % of the samples at the default shape
-    const uint64_t ho_cap = std::min<uint64_t>(count, std::max<uint64_t>(1024, count / 32));
+    // start over in tier 1): an eighth of the ids one tier-0 launch takes (784 B a record at the
+    // default shape; 8.2 % of the samples outgrow tier 0 on the 1.4B-edge WC graph)
+    const uint64_t per_launch0 =
+        cfg.form == 2 ? std::min<uint64_t>(count, cfg.chunk ? cfg.chunk : CHAIN_CHUNK_DEFAULT) : count;
+    const bool tiered = !lt && cfg.form != 1;
+    const uint64_t ho_cap = tiered ? std::min<uint64_t>(per_launch0, std::max<uint64_t>(1024, per_launch0 / 8)) : 0;
     const int ho_stride = (int)v0.visited;
     if (v0.visited > vm.visited) throw Error{SKIS_EHIP, "internal error: tier 1 smaller than tier 0"};
     DevBuf<Handover> ho_state;
@@ -1652,7 +1659,7 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
     deferred2.alloc(arena, count);
     const int ho2_stride = (int)vm.visited; // tier 1 -> hash tier records
     const int ho3_stride = TIERH_RCAP;      // hash tier -> bitmap tier records
-    constexpr uint64_t HO3_MAX = 4096;      // records of the samples that outgrow the hash tier
+    constexpr uint64_t HO3_MAX = 8192;      // records of the samples that outgrow the hash tier (384 MiB)
 
     auto read_counters = [&]() {
         SKIS_HIP_TRY(hipMemcpyAsync(&hc, ctr.ptr, sizeof(hc), hipMemcpyDeviceToHost, s));
@@ -1684,7 +1691,7 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
     auto sample_chain_graph = [&]() {
         // 2^24 ids by default: every chunk waits for its own largest samples, so fewer chunks
         // finish sooner (2^22 took 44 / 115 ms on the 1M-node WC / 4M-node TRI graphs, 2^24 37 / 67)
-        const uint64_t chunk = std::min<uint64_t>(count, cfg.chunk ? cfg.chunk : (1ull << 24));
+        const uint64_t chunk = std::min<uint64_t>(count, cfg.chunk ? cfg.chunk : CHAIN_CHUNK_DEFAULT);
         const uint64_t replays = (count + chunk - 1) / chunk;
         if (!cfg.staging_entries) cap = staging_bound((uint64_t)((double)count * per_sample), replays);
         DevBuf<ChainCtl> gc;
