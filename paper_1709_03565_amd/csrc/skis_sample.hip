@@ -191,8 +191,15 @@ struct SampleArgs {
 #define SKIS_KARG(f) karg_at<decltype(SampleArgs::f)>(offsetof(SampleArgs, f))
 static_assert(std::is_standard_layout<SampleArgs>::value, "argument offsets need a standard layout");
 
+// Five waves a SIMD for the default tier-0 shape: its registers fit in 96 (one value spilled,
+// reloaded once a pass); left to itself the compiler takes 98 and four waves.
+template <int S, int RCAP, int QPL, int TIER> constexpr int sample_min_waves()
+{
+    return TIER == 0 && S <= 4 && RCAP <= 192 && QPL == 1 ? 5 : 1;
+}
+
 template <int BLOCK, int S, int RCAP, int HCAP, int ICAP, int QPL, int TIER>
-__global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
+__global__ __launch_bounds__(BLOCK, (sample_min_waves<S, RCAP, QPL, TIER>())) void k_sample(SampleArgs a)
 {
     constexpr bool GLOBAL = TIER == 3; // bitmap visited sets: a sample never outgrows them
     constexpr bool GHASH = TIER == 2;  // hash visited sets in global memory
@@ -235,12 +242,14 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
     __shared__ unsigned long long s_cbase[2];
     __shared__ int s_ccur;
     __shared__ int32_t s_scan[BLOCK / 64 + 1];
-    // one-wave workgroups find an item's slot (one item per lane) and a lane's item in the
-    // first sweep (one quad per lane) by a prefix maximum over the lanes instead of a binary
-    // search: s_imap[i] = slot + 1 of the slot whose items start at i, s_qmap[p] = item + 1
-    // of the non-empty item whose quads start at p, 0 elsewhere
+    // one-wave workgroups find an item's slot (one item per lane) and, in every sweep, a lane's
+    // item (lane i holding item i's quad range) by a prefix maximum over the lanes instead of
+    // a binary search: s_imap[i] = slot + 1 of the slot whose items start at i, s_qmap[p] =
+    // item + 1 of the non-empty item whose quads start at position p of the sweep (or before
+    // it, at p = 0), 0 elsewhere
     constexpr bool WMAP_SLOT = BLOCK == 64 && IPT == 1;
-    constexpr bool WMAP_QUAD = BLOCK == 64 && QPL == 1;
+    // (one quad a lane only: with two, the marks cost tier 1 more than its searches)
+    constexpr bool WMAP_QUAD = BLOCK == 64 && ICAP <= 64 && QPL == 1;
     __shared__ uint32_t s_imap[WMAP_SLOT ? 64 : 1];
     __shared__ uint32_t s_qmap[WMAP_QUAD ? 64 : 1];
     // per wave: the live edges of the pass's sweeps not yet visited (node, slot)
@@ -807,18 +816,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
                 if (idx < nitems) it_pb[idx] = ex + loc[k];
             }
             if (tid == 0) it_pb[nitems] = tot;
-            if constexpr (WMAP_QUAD) {
-                s_qmap[tid] = 0u;
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll
-                for (int k = 0; k < IPT; ++k) {
-                    const int idx = tid * IPT + k;
-                    const int st = ex + loc[k];
-                    if (idx < nitems && cnt[k] > 0 && st < 64) s_qmap[st] = (uint32_t)idx + 1u;
-                }
-            }
+            if constexpr (WMAP_QUAD) s_qmap[tid] = 0u;
         }
         bsync();
 
@@ -831,7 +829,14 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
         // settled on the whole coin after the sweep.
         const int total = it_pb[nitems];
         const int qpl = total >= BLOCK * QPL ? QPL : (total + BLOCK - 1) / BLOCK;
-        const int first_item = WMAP_QUAD ? (int)wave_incl_max_dpp(s_qmap[tid]) - 1 : 0;
+        // one-wave workgroups: this lane's item's quads [my_qb, my_qe) (empty past nitems)
+        int my_qb = 0, my_qe = 0;
+        if constexpr (WMAP_QUAD) {
+            if (tid < nitems) {
+                my_qb = it_pb[tid];
+                my_qe = it_pb[tid + 1];
+            }
+        }
         // The live edges a sweep finds join the wave's queue, and the queue is visited (the
         // visited-set inserts, one entry a lane) when it could not take the next sweep's and
         // after the last sweep: the inserts run with most lanes busy instead of with the few
@@ -854,10 +859,22 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs a)
         };
         for (int base0 = 0; base0 < total; base0 += BLOCK * qpl) {
             const int base = base0 + tid * qpl; // past total: no quad (the lane still takes part)
-            int lo = 0, hi = nitems - 1; // last item whose first quad index is <= base
-            if (WMAP_QUAD && base < BLOCK) {
-                lo = first_item; // the first sweep: quad base = tid
+            int lo = 0; // last item whose first quad index is <= base
+            if constexpr (WMAP_QUAD) {
+                // every item that overlaps the sweep marks where it starts in it (0 if before);
+                // the largest mark at or before a lane's quad is its item
+                if (my_qe > my_qb && my_qb < base0 + 64 && my_qe > base0)
+                    s_qmap[max(my_qb - base0, 0)] = (uint32_t)tid + 1u;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                lo = max((int)wave_incl_max_dpp(s_qmap[tid]) - 1, 0);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                s_qmap[tid] = 0u;
             } else {
+                int hi = nitems - 1;
                 while (lo < hi) {
                     const int mid = (lo + hi + 1) >> 1;
                     if (it_pb[mid] <= base) lo = mid; else hi = mid - 1;
