@@ -37,7 +37,8 @@ struct LtCounters {
     unsigned long long walk_samples, walk_entries, walk_probed, walk_picks;
     unsigned long long long_entries, long_probed, long_picks;
     int overflow;                       // a reservation ran past the capacity
-    int err;                            // 1: a root without in-edges or out of range; 2: a walk past its guard
+    int err;                            // 1: a root without in-edges or out of range; 2: a walk past its
+                                        // guard; 4: more samples listed for compaction than there are
 };
 
 struct LtArgs {
@@ -302,7 +303,11 @@ __global__ __launch_bounds__(LT_LONG_BLOCK) void k_lt_long(LtArgs a)
         a.out_off[i] = off;
         a.out_probed[i] = probed;
         a.rec[i] = make_int4(root, 0, 0, 0);
-        if (size > (unsigned long long)a.small_sort) a.medium[atomicAdd(a.n_medium, 1ull)] = i;
+        if (size > (unsigned long long)a.small_sort) {
+            const unsigned long long k = atomicAdd(a.n_medium, 1ull);
+            if (k < a.count) a.medium[k] = i; // bounds guard: report, never index
+            else atomicOr(&a.ctr->err, 4);
+        }
         n_ent += size;
         n_prb += probed;
     }
@@ -316,9 +321,14 @@ __global__ __launch_bounds__(LT_LONG_BLOCK) void k_lt_long(LtArgs a)
     }
 }
 
-__global__ void k_lt_zero(LtCounters *c)
+// Clears the counters and the compaction's list count before every attempt (a retry after a
+// staging overflow lists its samples again).
+__global__ void k_lt_zero(LtCounters *c, unsigned long long *n_medium)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *c = LtCounters{};
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        *c = LtCounters{};
+        *n_medium = 0ull;
+    }
 }
 
 void sample_lt(Arena &arena, const Prep &prep, int32_t n, const LtIo &io, LtStats &st, hipStream_t s)
@@ -355,7 +365,7 @@ void sample_lt(Arena &arena, const Prep &prep, int32_t n, const LtIo &io, LtStat
     for (int attempt = 0;; ++attempt) {
         io.staging->reset();
         io.staging->alloc(arena, cap);
-        hipLaunchKernelGGL(k_lt_zero, dim3(1), dim3(64), 0, s, ctr.ptr);
+        hipLaunchKernelGGL(k_lt_zero, dim3(1), dim3(64), 0, s, ctr.ptr, io.n_medium);
         LtArgs A{};
         A.n = n;
         A.count = count;

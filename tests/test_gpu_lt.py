@@ -181,6 +181,19 @@ def test_lt_staging_overflow_retry(skis):
     _equal(skis.build_sketch(g.row_ptr, g.col, g.w, T, 4, model=1, staging_entries=1000), ora)
 
 
+def test_lt_retry_lists_large_samples_once(skis):
+    # every sample of a weight-1 cycle of 1500 nodes is the cycle, above the 1024 nodes that
+    # the compaction sorts in registers, so each is listed for the larger sorts; a first
+    # staging of 1000 entries overflows, and the retry must list each sample once
+    L = 1500
+    rp, col, w = _csr(L, list(range(L)), [(v + 1) % L for v in range(L)], [1.0] * L)
+    for T in (700, 3000):
+        _say("retry", L, T)
+        ora = oracle.build_sketch(rp, col, w, seed=5, j0=0, j1=T, nthreads=4, model=1)
+        sk = skis.build_sketch(rp, col, w, T, 5, model=1, staging_entries=1000)
+        _equal(sk, ora)
+
+
 def test_lt_budgeted_sketch(skis):
     g = inputs.workload_graph("cl15k_lt")
     budget = int(math.ceil(2 * g.n * math.log(g.n)))
