@@ -653,6 +653,21 @@ def main():
             log("random-access probe failed:", ra["error"])
         line["random_access"] = ra
     print(json.dumps(line), flush=True)
+    release_device_memory()
+
+
+def release_device_memory():
+    """Hands the library's idle blocks and pool and torch's cached blocks back to the driver
+    before the process ends: a process started right after one that exits holding them (about
+    130 GB at 1.4B edges) met memory the driver was still reclaiming and took 150 ms more a
+    step."""
+    import torch
+
+    from paper_1709_03565_amd import skis
+    torch.cuda.synchronize()
+    skis.release_cached_memory()
+    torch.cuda.empty_cache()
+    torch.cuda.synchronize()
 
 
 if __name__ == "__main__":

@@ -286,12 +286,13 @@ int skis_node_q(const skis_sketch *sk, double *q, hipStream_t stream);
 void skis_sketch_free(skis_sketch *sk);
 
 /* Device memory the library keeps for reuse, process-wide.  Blocks that a finished call no longer
- * uses go to a cache of idle blocks (per device, at most cache_keep_bytes, default 32 GiB; the
- * largest leave first) from which later calls take buffers without a driver call, and the device's
- * stream-ordered pool keeps up to pool_keep_bytes (default 64 GiB) of released memory.  Lower limits
- * leave more memory to other users of the GPU (a PyTorch caching allocator, another library);
- * the call trims the current device's cache to the new limit at once.  Sketches and servers keep
- * the buffers they own.  Errors: SKIS_EHIP. */
+ * uses go to a cache of idle blocks (per device, at most cache_keep_bytes; the largest leave first)
+ * from which later calls take buffers without a driver call, and the device's stream-ordered pool
+ * keeps up to pool_keep_bytes of released memory.  Until this is called each limit is half of the
+ * device's memory (a build of 2^26 samples at 1.4B edges uses about 100 GB of transient buffers).
+ * Lower limits leave more memory to other users of the GPU (a PyTorch caching allocator, another
+ * library); the call trims the current device's cache to the new limit at once.  Sketches and
+ * servers keep the buffers they own.  Errors: SKIS_EHIP. */
 int skis_set_memory_limits(uint64_t cache_keep_bytes, uint64_t pool_keep_bytes);
 
 /* Gives every idle cached block of the current device back and trims its stream-ordered pool to

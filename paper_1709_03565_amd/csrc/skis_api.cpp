@@ -20,11 +20,37 @@ static thread_local std::string g_err;
 void set_error(const std::string &msg) { g_err = msg; }
 const std::string &get_error() { return g_err; }
 
-// Stream-ordered allocation from the device's default memory pool, which keeps up to
-// POOL_KEEP bytes of released memory for reuse: a build then takes its buffers from what the
+// Limits on the memory kept for reuse (the pool's release threshold and the idle-block cache
+// below).  Unless the caller sets them, each is half the device's memory: one build of 2^26
+// samples at 1.4B edges allocates about 100 GB of transient buffers, and with smaller limits
+// every build handed part of them back to the driver and mapped them again (150 ms a build
+// once another process had used that memory, which the driver then clears first).
+constexpr uint64_t KEEP_UNSET = ~0ull;
+constexpr int CACHE_DEVICES = 64;
+static std::atomic<uint64_t> g_pool_keep{KEEP_UNSET};
+static std::atomic<uint64_t> g_cache_keep{KEEP_UNSET};
+
+static uint64_t keep_limit(const std::atomic<uint64_t> &limit, int d)
+{
+    const uint64_t set = limit.load();
+    if (set != KEEP_UNSET) return set;
+    static std::atomic<uint64_t> half[CACHE_DEVICES];
+    const int k = d >= 0 && d < CACHE_DEVICES ? d : 0;
+    uint64_t h = half[k].load();
+    if (h == 0) {
+        size_t total = 0;
+        if (hipDeviceTotalMem(&total, d) != hipSuccess || total == 0) total = 64ull << 30;
+        (void)hipGetLastError();
+        h = (uint64_t)total / 2;
+        half[k].store(h);
+    }
+    return h;
+}
+
+// Stream-ordered allocation from the device's default memory pool, which keeps up to its
+// release threshold of released memory for reuse: a build then takes its buffers from what the
 // previous one released instead of going back to the driver.  Buffers are released on the
 // arena's stream, after the work queued there that uses them.
-static std::atomic<uint64_t> g_pool_keep{64ull << 30};
 
 static bool pool_ready()
 {
@@ -38,7 +64,7 @@ static bool pool_ready()
         ok = hipDeviceGetAttribute(&supported, hipDeviceAttributeMemoryPoolsSupported, d) == hipSuccess && supported;
         if (ok) {
             hipMemPool_t pool = nullptr;
-            uint64_t keep = g_pool_keep.load();
+            uint64_t keep = keep_limit(g_pool_keep, d);
             ok = hipDeviceGetDefaultMemPool(&pool, d) == hipSuccess &&
                  hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep) == hipSuccess;
         }
@@ -47,13 +73,11 @@ static bool pool_ready()
     return ok;
 }
 
-// Idle device blocks shared by every arena of the process (per device, up to CACHE_KEEP
-// bytes): a block enters only when no queued work can use it any more (after a stream or
-// device synchronisation), so an arena on any stream may take it as it is.  Taking one costs
-// no driver call; the stream-ordered free and allocation cost tens to hundreds of microseconds
-// of host time each.
-static std::atomic<uint64_t> g_cache_keep{32ull << 30};
-constexpr int CACHE_DEVICES = 64;
+// Idle device blocks shared by every arena of the process (per device, up to the cache limit):
+// a block enters only when no queued work can use it any more (after a stream or device
+// synchronisation), so an arena on any stream may take it as it is.  Taking one costs no
+// driver call; the stream-ordered free and allocation cost tens to hundreds of microseconds of
+// host time each.
 
 struct CachedBlock {
     void *p;
@@ -98,8 +122,12 @@ static void *cache_take(size_t need, size_t *size, bool *pooled)
 static void cache_put(void *p, size_t size, bool pooled)
 {
     int d = 0;
-    const uint64_t keep = g_cache_keep.load();
-    if (hipGetDevice(&d) != hipSuccess || d < 0 || d >= CACHE_DEVICES || size > keep) {
+    if (hipGetDevice(&d) != hipSuccess || d < 0 || d >= CACHE_DEVICES) {
+        free_block(p, pooled);
+        return;
+    }
+    const uint64_t keep = keep_limit(g_cache_keep, d);
+    if (size > keep) {
         free_block(p, pooled);
         return;
     }
