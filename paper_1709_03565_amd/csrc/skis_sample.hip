@@ -29,8 +29,9 @@ namespace skis {
 
 constexpr uint32_t DEFERRED = 0xFFFFFFFFu;
 constexpr int SMALL_SORT = 1024;   // sizes up to this are sorted in registers by k_gather_sort
-constexpr int SORT_LDS_MAX = 8192; // sizes up to this are sorted in LDS by k_gather_medium,
-                                   // larger ones through a node bitmap by k_gather_large
+constexpr int SORT_LDS_MAX = 8192; // sizes up to this are sorted by k_gather_medium_regs and
+                                   // k_gather_block, larger ones through a node bitmap by
+                                   // k_gather_large
 constexpr int VQ_CAP = 64;        // live edges a wave queues before visiting them
 // sample ids taken from the global counter at a time: at least the slots of a workgroup
 template <int S>
@@ -1010,27 +1011,6 @@ __global__ __launch_bounds__(BLOCK, (sample_min_waves<S, RCAP, QPL, TIER>())) vo
 
 // Compaction: sort each sample and write it at sample_ptr[i].
 // ---------------------------------------------------------------------------------------
-template <int NT>
-__device__ void bitonic_lds(int32_t *buf, int P)
-{
-    for (int k = 2; k <= P; k <<= 1) {
-        for (int d = k >> 1; d > 0; d >>= 1) {
-            for (int i = threadIdx.x; i < P; i += NT) {
-                const int ixj = i ^ d;
-                if (ixj > i) {
-                    const int32_t x = buf[i], y = buf[ixj];
-                    const bool asc = (i & k) == 0;
-                    if ((x > y) == asc) {
-                        buf[i] = y;
-                        buf[ixj] = x;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-    }
-}
-
 // Size classes for the segmented sorts: class c holds sizes up to 8 << c; classes 0 .. 3 use
 // segments of 8, 16, 32 or 64 lanes with one node per lane, classes 4 .. 7 a whole wave with
 // 2, 4, 8 or 16 nodes per lane (up to SMALL_SORT).
@@ -1254,28 +1234,90 @@ __global__ __launch_bounds__(64) void k_gather_medium_regs(uint64_t count, const
 constexpr int MEDIUM_REGS_MAX = 2048; // sizes up to this are sorted in registers by k_gather_medium_regs<32>
 // (64 values a lane spill to scratch: the network is too large to unroll)
 
-__global__ __launch_bounds__(256) void k_gather_medium(uint64_t count, const uint32_t *__restrict__ list,
-                                                       const uint32_t *__restrict__ size,
-                                                       const unsigned long long *__restrict__ off,
-                                                       const int64_t *__restrict__ sptr,
-                                                       const int32_t *__restrict__ staging,
-                                                       int32_t *__restrict__ nodes, int32_t *__restrict__ owner)
+// Samples of MEDIUM_REGS_MAX + 1 .. SORT_LDS_MAX nodes, one at a time per workgroup of NT
+// threads, in registers: element e = t * R + r of the padded sample (P = NT R values) lives in
+// v[r] of thread t.  Bitonic stages at distance d < R stay in the thread, those with d < 64 R
+// are shuffles within the wave, and only the d >= 64 R stages (three per sample at 4096
+// values, six at 8192) exchange through LDS; the LDS network it replaces took a barrier at
+// every one of its 78-91 stages.  R = 16 values a thread keeps the network fully unrolled (at
+// 32 the compiler indexed the registers at run time); 256 threads take the samples up to 4096
+// nodes, 512 the rest.  The load is coalesced (any assignment of the sample's nodes to
+// elements sorts the same) and the sorted values go out coalesced through LDS, one pad word
+// per R values keeping the strided writes free of bank conflicts.
+constexpr int BLOCK_SORT_R = 16;
+constexpr int BLOCK_SORT_BUF = SORT_LDS_MAX + SORT_LDS_MAX / BLOCK_SORT_R;
+__device__ __forceinline__ int pad_idx(int e) { return e + e / BLOCK_SORT_R; }
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_gather_block(uint64_t count, const uint32_t *__restrict__ list,
+                                                     const uint32_t *__restrict__ size,
+                                                     const unsigned long long *__restrict__ off,
+                                                     const int64_t *__restrict__ sptr,
+                                                     const int32_t *__restrict__ staging,
+                                                     int32_t *__restrict__ nodes, int32_t *__restrict__ owner)
 {
-    __shared__ int32_t buf[SORT_LDS_MAX];
+    constexpr int R = BLOCK_SORT_R;
+    constexpr int P = NT * R;
+    constexpr int LO = NT == 256 ? MEDIUM_REGS_MAX : P / 2; // sizes in (LO, P] are this kernel's
+    static_assert(P <= SORT_LDS_MAX && (NT == 256 || NT == 512), "one workgroup size per half of the range");
+    __shared__ int32_t buf[BLOCK_SORT_BUF];
+    const int t = threadIdx.x;
     for (uint64_t k = blockIdx.x; k < count; k += gridDim.x) {
         const uint32_t i = list[k];
         const int sz = (int)size[i];
-        if (sz > SORT_LDS_MAX || sz <= MEDIUM_REGS_MAX) continue; // k_gather_large or k_gather_medium_regs takes it
+        if (sz <= LO || sz > P) continue; // another kernel's sample
         const int32_t *src = staging + off[i];
         int32_t *dst = nodes + sptr[i];
         if (owner)
-            for (int t = threadIdx.x; t < sz; t += 256) owner[sptr[i] + t] = (int32_t)i;
-        int P = 512;
-        while (P < sz) P <<= 1;
-        for (int t = threadIdx.x; t < P; t += 256) buf[t] = t < sz ? src[t] : INT32_MAX;
+            for (int x = t; x < sz; x += NT) owner[sptr[i] + x] = (int32_t)i;
+        int32_t v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int x = r * NT + t;
+            v[r] = x < sz ? src[x] : INT32_MAX;
+        }
+#pragma unroll
+        for (int kk = 2; kk <= P; kk <<= 1) {
+#pragma unroll
+            for (int d = kk >> 1; d > 0; d >>= 1) {
+                if (d < R) {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        if (r & d) continue;
+                        const bool asc = ((t * R + r) & kk) == 0;
+                        const int32_t x = v[r], y = v[r | d];
+                        v[r] = asc ? min(x, y) : max(x, y);
+                        v[r | d] = asc ? max(x, y) : min(x, y);
+                    }
+                } else if (d < 64 * R) {
+                    const int ld = d / R;
+                    const bool low = (t & ld) == 0;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const bool asc = ((t * R + r) & kk) == 0;
+                        const int32_t y = __shfl_xor(v[r], ld, 64);
+                        v[r] = (low == asc) ? min(v[r], y) : max(v[r], y);
+                    }
+                } else { // partner in another wave: through LDS
+                    const int ld = d / R;
+                    const bool low = (t & ld) == 0;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) buf[pad_idx(t * R + r)] = v[r];
+                    __syncthreads();
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const bool asc = ((t * R + r) & kk) == 0;
+                        const int32_t y = buf[pad_idx((t ^ ld) * R + r)];
+                        v[r] = (low == asc) ? min(v[r], y) : max(v[r], y);
+                    }
+                    __syncthreads();
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) buf[pad_idx(t * R + r)] = v[r];
         __syncthreads();
-        bitonic_lds<256>(buf, P);
-        for (int t = threadIdx.x; t < sz; t += 256) dst[t] = buf[t];
+        for (int x = t; x < sz; x += NT) dst[x] = buf[pad_idx(x)];
         __syncthreads();
     }
 }
@@ -1304,7 +1346,7 @@ __global__ __launch_bounds__(LARGE_BLOCK) void k_gather_large(uint64_t count, co
     for (uint64_t k = blockIdx.x; k < count; k += gridDim.x) {
         const uint32_t i = list[k];
         const int64_t sz = (int64_t)size[i];
-        if (sz <= SORT_LDS_MAX) continue; // k_gather_medium's
+        if (sz <= SORT_LDS_MAX) continue; // k_gather_block's
         const int32_t *src = staging + off[i];
         int32_t *dst = nodes + sptr[i];
         for (int64_t t = tid; t < sz; t += LARGE_BLOCK) {
@@ -2225,7 +2267,10 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
         const unsigned gm = grid_cap(hc.n_medium, 1, 16);
         hipLaunchKernelGGL((k_gather_medium_regs<32>), dim3(gm), dim3(64), 0, s, (uint64_t)hc.n_medium, medium.ptr,
                            out_size.ptr, out_off.ptr, sk.sample_ptr.ptr, staging.ptr, sk.nodes.ptr, owner_p);
-        hipLaunchKernelGGL(k_gather_medium, dim3(grid_cap(hc.n_medium, 1, 4)), dim3(256), 0, s,
+        hipLaunchKernelGGL(k_gather_block<256>, dim3(grid_cap(hc.n_medium, 1, 4)), dim3(256), 0, s,
+                           (uint64_t)hc.n_medium, medium.ptr, out_size.ptr, out_off.ptr, sk.sample_ptr.ptr,
+                           staging.ptr, sk.nodes.ptr, owner_p);
+        hipLaunchKernelGGL(k_gather_block<512>, dim3(grid_cap(hc.n_medium, 1, 2)), dim3(512), 0, s,
                            (uint64_t)hc.n_medium, medium.ptr, out_size.ptr, out_off.ptr, sk.sample_ptr.ptr,
                            staging.ptr, sk.nodes.ptr, owner_p);
         SKIS_HIP_TRY(hipGetLastError());
