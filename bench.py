@@ -64,7 +64,7 @@ _TIER0 = {(64, 4, 192, 2): (256, 128), (64, 4, 192, 1): (256, 64), (64, 4, 256, 
           (64, 12, 192, 2): (256, 384), (64, 16, 128, 2): (172, 512), (64, 16, 64, 2): (88, 512),
           (256, 16, 128, 2): (172, 1024), (256, 32, 128, 2): (172, 1024), (256, 16, 256, 2): (344, 1024)}
 TIER1_KERNEL = "k_sample<64, 1, 1024, 1368, 64, 2, 1>"
-TIER2_KERNEL = "k_sample<64, 1, 12288, 16384, 64, 1, 2>"
+TIER2_KERNEL = "k_sample<64, 1, 6144, 8192, 64, 1, 2>"
 TIER3_KERNEL = "k_sample<1024, 1, 1, 1, 8192, 2, 3>"
 
 

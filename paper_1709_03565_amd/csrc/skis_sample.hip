@@ -1555,9 +1555,12 @@ static const Variant kTierMidV[] = {
 // Third tier: one sample per one-wave workgroup, its visited set a hash of TIERH_HCAP slots
 // and its node list TIERH_RCAP entries in HBM, so that every compute unit holds as many
 // samples as waves fit (the samples that outgrow 1024 nodes number about 1 % on the 1.4B-edge
-// workload, and each takes many passes).
-constexpr int TIERH_RCAP = 12288;
-constexpr int TIERH_HCAP = 16384;
+// workload, and each takes many passes).  The hashes of the 5,120 samples in flight are the
+// tier's working set: at 16384 slots (335 MB) the tier took 67 ms at 1.4B edges, at 8192
+// 62 ms, and at 4096 slots the samples sent on to the bitmap tier cost more than the hash saved
+// (71 ms); the samples that leave it mostly meet a hub row rather than outgrow it.
+constexpr int TIERH_RCAP = 6144;
+constexpr int TIERH_HCAP = 8192;
 // in-degree above which the hash tier hands a sample on: a hub row is swept faster by the
 // bitmap tier's sixteen waves than by one
 constexpr uint32_t TIERH_BIG_ROW = 65536;
@@ -1718,7 +1721,7 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
     deferred2.alloc(arena, count);
     const int ho2_stride = (int)vm.visited; // tier 1 -> hash tier records
     const int ho3_stride = TIERH_RCAP;      // hash tier -> bitmap tier records
-    constexpr uint64_t HO3_MAX = 8192;      // records of the samples that outgrow the hash tier (384 MiB)
+    constexpr uint64_t HO3_MAX = 8192;      // records of the samples that outgrow the hash tier (192 MiB)
 
     auto read_counters = [&]() {
         SKIS_HIP_TRY(hipMemcpyAsync(&hc, ctr.ptr, sizeof(hc), hipMemcpyDeviceToHost, s));

@@ -162,7 +162,7 @@ def test_large_cascades_global_tier(skis, scale, n, m):
     # heavier weights give samples of thousands of nodes: LDS overflow -> the HBM hash tier;
     # at scale 4 most samples exceed the LDS sort limit (8192 nodes) and are sorted through
     # the compaction's node bitmap; on the 60k-node graph most also exceed the hash tier's
-    # 12288 nodes and finish in the bitmap tier, resumed from the hash tier's handover
+    # 6144 nodes and finish in the bitmap tier, resumed from the hash tier's handover
     g = inputs.chung_lu_graph(n, m, 2.1, 77, "wc", cache=False)
     w = np.minimum(g.w * scale, 1.0).astype(np.float32)
     T = 2000
@@ -180,9 +180,9 @@ def test_large_cascades_global_tier(skis, scale, n, m):
     _assert_tiers_add_up(inf)
     assert inf.tier_samples[2] + inf.tier_samples[3] == inf.deferred_global
     assert inf.tier_samples[3] == inf.deferred_bitmap
-    assert (inf.deferred_bitmap > 0) == bool((sizes > 12288).any())
+    assert (inf.deferred_bitmap > 0) == bool((sizes > 6144).any())
     if n > 30000:
-        assert (sizes > 12288).mean() > 0.5
+        assert (sizes > 6144).mean() > 0.5
     _assert_sketch_equal(sk, ora)
 
 

@@ -95,7 +95,7 @@ def test_bench_kernel_names_match_the_library_table():
     names = bench.tier_kernel_names({})
     mid = re.search(r"kTierMidV\[\] = \{\s*\{64, 1, 1024, \d, (k_sample<[^>]*>)\}", src).group(1)
     assert names[1] == mid
-    assert "kTierHash = %s;" % names[2].replace("12288", "TIERH_RCAP").replace("16384", "TIERH_HCAP") in src
+    assert "kTierHash = %s;" % names[2].replace("6144", "TIERH_RCAP").replace("8192", "TIERH_HCAP") in src
     assert "kTierGlobal = k_sample<TIERG_BLOCK, TIERG_SLOTS, 1, 1, 8 * TIERG_BLOCK, 2, 3>;" in src
     assert names[3] == "k_sample<1024, 1, 1, 1, 8192, 2, 3>" and "constexpr int TIERG_BLOCK = 1024;" in src
-    assert "constexpr int TIERH_RCAP = 12288;" in src and "constexpr int TIERH_HCAP = 16384;" in src
+    assert "constexpr int TIERH_RCAP = 6144;" in src and "constexpr int TIERH_HCAP = 8192;" in src
