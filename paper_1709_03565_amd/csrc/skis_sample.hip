@@ -1091,6 +1091,16 @@ __global__ __launch_bounds__(256) void k_class_fill(uint64_t T, const uint32_t *
 // Bitonic network over the W * R values of a segment of W lanes, element e = t * R + r in v[r]
 // of lane t: exchanges at distance d < R stay in the lane, the others are shuffles at lane
 // distance d / R within the segment.  Every lane of the wave runs it.
+// v of lane (this lane ^ ld) for ld < 64: lane distances 1 and 2 by a DPP quad permutation (a
+// plain VALU move), the others through the LDS crossbar.  In the unrolled networks below ld is
+// a constant, so the choice costs nothing; distances 1 and 2 are about half of their shuffles.
+__device__ __forceinline__ int32_t shfl_xor_lanes(int32_t v, int ld)
+{
+    if (ld == 1) return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false); // quad_perm [1,0,3,2]
+    if (ld == 2) return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false); // quad_perm [2,3,0,1]
+    return __shfl_xor(v, ld, 64);
+}
+
 template <int W, int R>
 __device__ __forceinline__ void bitonic_regs(int32_t (&v)[R], int t)
 {
@@ -1114,7 +1124,8 @@ __device__ __forceinline__ void bitonic_regs(int32_t (&v)[R], int t)
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const bool asc = ((t * R + r) & k) == 0;
-                    const int32_t y = __shfl_xor(v[r], ld, 64);
+                    // (32 values a lane: the DPP form makes the network too large to unroll)
+                    const int32_t y = R >= 32 ? __shfl_xor(v[r], ld, 64) : shfl_xor_lanes(v[r], ld);
                     v[r] = (low == asc) ? min(v[r], y) : max(v[r], y);
                 }
             }
@@ -1230,7 +1241,6 @@ __global__ __launch_bounds__(64) void k_gather_medium_regs(uint64_t count, const
     }
 }
 
-// Listed samples of (MEDIUM_REGS_MAX, SORT_LDS_MAX] nodes: a bitonic sort in LDS per workgroup.
 constexpr int MEDIUM_REGS_MAX = 2048; // sizes up to this are sorted in registers by k_gather_medium_regs<32>
 // (64 values a lane spill to scratch: the network is too large to unroll)
 
@@ -1295,7 +1305,8 @@ __global__ __launch_bounds__(NT) void k_gather_block(uint64_t count, const uint3
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
                         const bool asc = ((t * R + r) & kk) == 0;
-                        const int32_t y = __shfl_xor(v[r], ld, 64);
+                        // (at 512 threads the DPP form makes the network too large to unroll)
+                        const int32_t y = NT == 512 ? __shfl_xor(v[r], ld, 64) : shfl_xor_lanes(v[r], ld);
                         v[r] = (low == asc) ? min(v[r], y) : max(v[r], y);
                     }
                 } else { // partner in another wave: through LDS
