@@ -2244,6 +2244,48 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
     if (cfg.owners) sk.owner.alloc(arena, (size_t)total);
     else sk.owner.reset();
     int32_t *const owner_p = cfg.owners ? sk.owner.ptr : nullptr;
+    // The register sorts of the 1025-8192-node samples (bound by their ALU work) run on a
+    // second stream beside the size classes (bound by memory), dispatched first; the caller's
+    // stream waits for them before the large samples and everything after (also when an
+    // error leaves this function early: the buffers they use are released on that stream).
+    const bool mid_side = hc.n_medium > n_large;
+    hipEvent_t mfork = nullptr, mjoin = nullptr;
+    bool mid_pending = false;
+    hipError_t mid_err = hipSuccess;
+    struct MidEvents {
+        hipStream_t s;
+        hipEvent_t *a, *b;
+        bool *pending;
+        ~MidEvents()
+        {
+            if (*pending) (void)hipStreamWaitEvent(s, *b, 0);
+            if (*a) (void)hipEventDestroy(*a);
+            if (*b) (void)hipEventDestroy(*b);
+        }
+    } mid_events{s, &mfork, &mjoin, &mid_pending};
+    if (mid_side) {
+        hipStream_t s2 = side_stream();
+        SKIS_HIP_TRY(hipEventCreateWithFlags(&mfork, hipEventDisableTiming));
+        SKIS_HIP_TRY(hipEventCreateWithFlags(&mjoin, hipEventDisableTiming));
+        SKIS_HIP_TRY(hipEventRecord(mfork, s));
+        hipError_t e = hipStreamWaitEvent(s2, mfork, 0);
+        if (e == hipSuccess) {
+            const unsigned gm = grid_cap(hc.n_medium, 1, 16);
+            hipLaunchKernelGGL((k_gather_medium_regs<32>), dim3(gm), dim3(64), 0, s2, (uint64_t)hc.n_medium,
+                               medium.ptr, out_size.ptr, out_off.ptr, sk.sample_ptr.ptr, staging.ptr, sk.nodes.ptr,
+                               owner_p);
+            hipLaunchKernelGGL(k_gather_block<256>, dim3(grid_cap(hc.n_medium, 1, 4)), dim3(256), 0, s2,
+                               (uint64_t)hc.n_medium, medium.ptr, out_size.ptr, out_off.ptr, sk.sample_ptr.ptr,
+                               staging.ptr, sk.nodes.ptr, owner_p);
+            hipLaunchKernelGGL(k_gather_block<512>, dim3(grid_cap(hc.n_medium, 1, 2)), dim3(512), 0, s2,
+                               (uint64_t)hc.n_medium, medium.ptr, out_size.ptr, out_off.ptr, sk.sample_ptr.ptr,
+                               staging.ptr, sk.nodes.ptr, owner_p);
+            e = hipGetLastError();
+        }
+        SKIS_HIP_TRY(hipEventRecord(mjoin, s2));
+        mid_pending = true;
+        mid_err = e;
+    }
     {
         // samples by size class, then one segmented sort per class
         DevBuf<unsigned long long> cls;
@@ -2277,17 +2319,10 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
                            sk.sample_ptr.ptr, staging.ptr, sk.nodes.ptr, owner_p);
         SKIS_HIP_TRY(hipGetLastError());
     }
-    if (hc.n_medium > n_large) {
-        const unsigned gm = grid_cap(hc.n_medium, 1, 16);
-        hipLaunchKernelGGL((k_gather_medium_regs<32>), dim3(gm), dim3(64), 0, s, (uint64_t)hc.n_medium, medium.ptr,
-                           out_size.ptr, out_off.ptr, sk.sample_ptr.ptr, staging.ptr, sk.nodes.ptr, owner_p);
-        hipLaunchKernelGGL(k_gather_block<256>, dim3(grid_cap(hc.n_medium, 1, 4)), dim3(256), 0, s,
-                           (uint64_t)hc.n_medium, medium.ptr, out_size.ptr, out_off.ptr, sk.sample_ptr.ptr,
-                           staging.ptr, sk.nodes.ptr, owner_p);
-        hipLaunchKernelGGL(k_gather_block<512>, dim3(grid_cap(hc.n_medium, 1, 2)), dim3(512), 0, s,
-                           (uint64_t)hc.n_medium, medium.ptr, out_size.ptr, out_off.ptr, sk.sample_ptr.ptr,
-                           staging.ptr, sk.nodes.ptr, owner_p);
-        SKIS_HIP_TRY(hipGetLastError());
+    if (mid_pending) {
+        SKIS_HIP_TRY(hipStreamWaitEvent(s, mjoin, 0));
+        mid_pending = false;
+        SKIS_HIP_TRY(mid_err);
     }
     if (n_large > 0) {
         // one bitmap of n bits and one summary bit per bitmap word for each workgroup, at
