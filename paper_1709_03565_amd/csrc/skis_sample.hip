@@ -193,10 +193,13 @@ struct SampleArgs {
 static_assert(std::is_standard_layout<SampleArgs>::value, "argument offsets need a standard layout");
 
 // Five waves a SIMD for the default tier-0 shape: its registers fit in 96 (one value spilled,
-// reloaded once a pass); left to itself the compiler takes 98 and four waves.
+// reloaded once a pass); left to itself the compiler takes 98 and four waves.  Six for the
+// HBM hash tier, whose samples wait on memory more than on anything else: 80 registers and a
+// few spilled values (59 ms at 1.4B edges against 62-65 with five waves, 61 with eight; with
+// a half or a quarter of the workgroups in flight it took 98 and 148 ms).
 template <int S, int RCAP, int QPL, int TIER> constexpr int sample_min_waves()
 {
-    return TIER == 0 && S <= 4 && RCAP <= 192 && QPL == 1 ? 5 : 1;
+    return TIER == 0 && S <= 4 && RCAP <= 192 && QPL == 1 ? 5 : TIER == 2 ? 6 : 1;
 }
 
 template <int BLOCK, int S, int RCAP, int HCAP, int ICAP, int QPL, int TIER>
@@ -1566,9 +1569,9 @@ static const Variant kTierMidV[] = {
 // Third tier: one sample per one-wave workgroup, its visited set a hash of TIERH_HCAP slots
 // and its node list TIERH_RCAP entries in HBM, so that every compute unit holds as many
 // samples as waves fit (the samples that outgrow 1024 nodes number about 1 % on the 1.4B-edge
-// workload, and each takes many passes).  The hashes of the 5,120 samples in flight are the
-// tier's working set: at 16384 slots (335 MB) the tier took 67 ms at 1.4B edges, at 8192
-// 62 ms, and at 4096 slots the samples sent on to the bitmap tier cost more than the hash saved
+// workload, and each takes many passes).  The hashes of the samples in flight (6,144 at six
+// waves a SIMD) are the tier's working set: with five waves, at 16384 slots (335 MB) the tier
+// took 67 ms at 1.4B edges, at 8192 62 ms, and at 4096 slots the samples sent on to the bitmap tier cost more than the hash saved
 // (71 ms); the samples that leave it mostly meet a hub row rather than outgrow it.
 constexpr int TIERH_RCAP = 6144;
 constexpr int TIERH_HCAP = 8192;
