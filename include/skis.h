@@ -321,11 +321,14 @@ int skis_probe_random_read(const void *table, uint64_t rows, uint32_t row_bytes,
  * of pipeline_depth batch slots is free, every waiting query it admits (by count, by total
  * entries, and by sets above 4096 entries) is packed into pinned host memory and sent
  * through copy-in, the estimate kernels and copy-out on the slot's own HIP stream, while
- * the next batch is being formed.  Results are identical to skis_estimate's for the same
- * set, alone or in any mix: every set has its own workgroup, bitmap and summation order.
- * The sketch must outlive the server; the server does not lock it, and other calls on
- * the sketch (estimate, greedy, export) may run at the same time.  Memory: each slot holds
- * max_batch_queries bitmaps of T bits and max_large_sets bitmaps of n bits on the device.
+ * the next batch is being formed.  A set whose members' sample lists hold more than 2^18
+ * entries in all (a set with a hub) goes in a batch of its own, so that it does not hold
+ * the light sets it would have been batched with.  Results are identical to skis_estimate's
+ * for the same set, alone or in any mix: every set has its own workgroup, bitmap and
+ * summation order.  The sketch must outlive the server; the server does not lock it, and
+ * other calls on the sketch (estimate, greedy, export) may run at the same time.  Memory:
+ * each slot holds max_batch_queries bitmaps of T bits and max_large_sets bitmaps of n bits
+ * on the device; the host keeps a copy of the inverse index's n + 1 offsets.
  */
 typedef struct skis_server skis_server;
 

@@ -6,7 +6,10 @@
 // `depth` pipeline slots, each with its own HIP stream, pinned host staging, device CSR
 // buffers and zeroed bitmap scratch.  Whenever a slot is free and queries are waiting, the
 // worker takes as many as the slot admits (by count, by total entries and by large sets),
-// packs them into the slot's pinned CSR, and enqueues copy-in, the estimate kernels and
+// except that a heavy set (one whose members' sample lists hold more than HEAVY_WORK entries,
+// a hub's set) runs in a batch of its own: a batch completes when its slowest set does, so a
+// hub set among light ones would hold them all for milliseconds, while alone it holds one
+// slot and the other slots keep serving.  It packs them into the slot's pinned CSR, and enqueues copy-in, the estimate kernels and
 // copy-out on the slot's stream without waiting.  It polls the slots' completion events,
 // and when a batch is done it stores each query's (Cov, I_hat) and completion time and
 // wakes the waiters.  A query's result does not depend on the batch it ran in: each set
@@ -32,8 +35,14 @@ using Clock = std::chrono::steady_clock;
 struct Pending {
     uint64_t ticket;
     std::vector<int32_t> nodes;
+    uint64_t work = 0; // sum of |H(v)| over the members (from the inverse index's offsets)
     Clock::time_point arrive;
 };
+
+// A set whose members' lists hold more entries than this is batched alone (about a
+// millisecond of walking for one workgroup; a set of 1000 uniform members on the 4M-node TRI
+// sketch holds about 60 thousand, its top hub 3 million).
+constexpr uint64_t HEAVY_WORK = 1ull << 18;
 
 struct Done {
     uint64_t cov;
@@ -88,6 +97,7 @@ struct skis_server {
     int device = 0;
     uint64_t wordsT = 1, wordsN = 1;
     skis::Arena arena;
+    std::vector<int64_t> node_ptr; // host copy of the inverse index's offsets (n + 1), for the work of a set
     std::vector<std::unique_ptr<Slot>> slots;
     std::thread worker;
     std::mutex mu;
@@ -199,12 +209,15 @@ void skis_server::run()
                     while (!queue.empty() && sl.batch.size() < opt.max_batch_queries) {
                         const uint64_t e = queue.front().nodes.size();
                         const bool is_large = e > (uint64_t)skis::EST_MAX_SET;
+                        const bool heavy = queue.front().work > HEAVY_WORK;
+                        if (heavy && !sl.batch.empty()) break; // it goes alone, in the next free slot
                         if (entries + e > opt.max_batch_entries) break;
                         if (is_large && large >= opt.max_large_sets) break;
                         entries += e;
                         large += is_large ? 1u : 0u;
                         sl.batch.push_back(std::move(queue.front()));
                         queue.pop_front();
+                        if (heavy) break;
                     }
                 } else {
                     free_slot = nullptr;
@@ -273,6 +286,8 @@ int submit_one(skis_server *sv, const int32_t *nodes, int32_t count, Clock::time
         if (nodes[i] < 0 || nodes[i] >= n) throw skis::Error{SKIS_EINVAL, "a seed set holds a node id outside [0, n)"};
     Pending p;
     p.nodes.assign(nodes, nodes + count);
+    if (!sv->node_ptr.empty())
+        for (int32_t i = 0; i < count; ++i) p.work += (uint64_t)(sv->node_ptr[nodes[i] + 1] - sv->node_ptr[nodes[i]]);
     p.arrive = arrive;
     {
         std::lock_guard<std::mutex> g(sv->mu);
@@ -341,6 +356,11 @@ int skis_server_create(const skis_sketch *sk, const skis_server_options *opt_in,
         sv->arena.cap = opt.max_device_bytes;
         sv->wordsT = sk->core.T ? (sk->core.T + 31) / 32 : 1;
         sv->wordsN = ((uint64_t)sk->core.n + 31) / 32;
+        if (sk->core.T > 0 && sk->core.node_ptr.ptr) {
+            sv->node_ptr.resize((size_t)sk->core.n + 1);
+            SKIS_HIP_TRY(hipMemcpy(sv->node_ptr.data(), sk->core.node_ptr.ptr, sizeof(int64_t) * ((size_t)sk->core.n + 1),
+                                   hipMemcpyDeviceToHost));
+        }
         const uint64_t nb = std::max<uint64_t>(opt.max_batch_queries, opt.max_large_sets);
         sv->arena.stream = nullptr; // allocations complete before any slot stream uses them (below)
         for (uint32_t i = 0; i < opt.pipeline_depth; ++i) {
