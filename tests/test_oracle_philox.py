@@ -79,6 +79,17 @@ def test_edge_coin_definition():
     assert abs(hits / 40000 - p) < 5 * np.sqrt(p * (1 - p) / 40000)
 
 
+@pytest.mark.parametrize("w", [0.01, 0.1, 1.0 / 7.0, 1.0 / 3.0, 0.5, 0.9, 0.999])
+def test_edge_coin_frequency_is_w(w):
+    # P(live) = w for each of the four words of a Philox call (e mod 4) and for low and high
+    # edge indices, over independent sample ids
+    p = float(np.float32(w))
+    N = 6000
+    for e in (0, 1, 2, 3, 4097, (1 << 30) + 2):
+        hits = sum(oracle.edge_coin(7, j, e, p) for j in range(N))
+        assert abs(hits / N - p) < 5 * np.sqrt(p * (1 - p) / N), (w, e, hits)
+
+
 def test_edge_coin_high_words_share_one_call():
     # four consecutive edges 4c..4c+3 take their high halves from the four words of one call
     seed, j = 0x1234_5678_9ABC, 77
