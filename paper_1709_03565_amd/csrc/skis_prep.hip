@@ -627,6 +627,7 @@ void preprocess(Arena &arena, int32_t n, int64_t m, const int32_t *row_ptr, cons
         side_err = hipGetLastError();
     }
     const hipError_t rec_err = hipEventRecord(join, s2);
+    if (rec_err != hipSuccess) (void)hipStreamSynchronize(s2); // no event to wait on: drain it here
     SKIS_HIP_TRY(rec_err);
     SKIS_HIP_TRY(hipStreamWaitEvent(s, join, 0));
     SKIS_HIP_TRY(long_err);

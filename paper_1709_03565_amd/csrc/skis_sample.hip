@@ -1091,9 +1091,6 @@ __global__ __launch_bounds__(256) void k_class_fill(uint64_t T, const uint32_t *
     }
 }
 
-// Bitonic network over the W * R values of a segment of W lanes, element e = t * R + r in v[r]
-// of lane t: exchanges at distance d < R stay in the lane, the others are shuffles at lane
-// distance d / R within the segment.  Every lane of the wave runs it.
 // v of lane (this lane ^ ld) for ld < 64: lane distances 1 and 2 by a DPP quad permutation (a
 // plain VALU move), the others through the LDS crossbar.  In the unrolled networks below ld is
 // a constant, so the choice costs nothing; distances 1 and 2 are about half of their shuffles.
@@ -1104,6 +1101,9 @@ __device__ __forceinline__ int32_t shfl_xor_lanes(int32_t v, int ld)
     return __shfl_xor(v, ld, 64);
 }
 
+// Bitonic network over the W * R values of a segment of W lanes, element e = t * R + r in v[r]
+// of lane t: exchanges at distance d < R stay in the lane, the others are shuffles at lane
+// distance d / R within the segment.  Every lane of the wave runs it.
 template <int W, int R>
 __device__ __forceinline__ void bitonic_regs(int32_t (&v)[R], int t)
 {
@@ -1571,8 +1571,9 @@ static const Variant kTierMidV[] = {
 // samples as waves fit (the samples that outgrow 1024 nodes number about 1 % on the 1.4B-edge
 // workload, and each takes many passes).  The hashes of the samples in flight (6,144 at six
 // waves a SIMD) are the tier's working set: with five waves, at 16384 slots (335 MB) the tier
-// took 67 ms at 1.4B edges, at 8192 62 ms, and at 4096 slots the samples sent on to the bitmap tier cost more than the hash saved
-// (71 ms); the samples that leave it mostly meet a hub row rather than outgrow it.
+// took 67 ms at 1.4B edges, at 8192 62 ms, and at 4096 slots the samples sent on to the
+// bitmap tier cost more than the hash saved (71 ms); the samples that leave it mostly meet a
+// hub row rather than outgrow it.
 constexpr int TIERH_RCAP = 6144;
 constexpr int TIERH_HCAP = 8192;
 // in-degree above which the hash tier hands a sample on: a hub row is swept faster by the
@@ -2285,7 +2286,9 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
                                staging.ptr, sk.nodes.ptr, owner_p);
             e = hipGetLastError();
         }
-        SKIS_HIP_TRY(hipEventRecord(mjoin, s2));
+        const hipError_t rec = hipEventRecord(mjoin, s2);
+        if (rec != hipSuccess) (void)hipStreamSynchronize(s2); // no event to wait on: drain it here
+        SKIS_HIP_TRY(rec);
         mid_pending = true;
         mid_err = e;
     }
