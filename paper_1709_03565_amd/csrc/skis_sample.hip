@@ -2248,29 +2248,35 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
     if (cfg.owners) sk.owner.alloc(arena, (size_t)total);
     else sk.owner.reset();
     int32_t *const owner_p = cfg.owners ? sk.owner.ptr : nullptr;
+    // samples by size class (the lists live until the side stream below has joined)
+    DevBuf<unsigned long long> cls;
+    DevBuf<uint32_t> lists;
     // The register sorts of the 1025-8192-node samples (bound by their ALU work) run on a
-    // second stream beside the size classes (bound by memory), dispatched first; the caller's
-    // stream waits for them before the large samples and everything after (also when an
-    // error leaves this function early: the buffers they use are released on that stream).
+    // second stream beside the size classes (bound by memory), dispatched first, and the
+    // largest size class (513-1024 nodes) follows them there; the caller's stream waits for
+    // them before the large samples and everything after (also when an error leaves this
+    // function early: the buffers they use are released on that stream).
     const bool mid_side = hc.n_medium > n_large;
-    hipEvent_t mfork = nullptr, mjoin = nullptr;
+    hipEvent_t mfork = nullptr, mjoin = nullptr, mcls = nullptr;
     bool mid_pending = false;
     hipError_t mid_err = hipSuccess;
     struct MidEvents {
         hipStream_t s;
-        hipEvent_t *a, *b;
+        hipEvent_t *a, *b, *c;
         bool *pending;
         ~MidEvents()
         {
             if (*pending) (void)hipStreamWaitEvent(s, *b, 0);
             if (*a) (void)hipEventDestroy(*a);
             if (*b) (void)hipEventDestroy(*b);
+            if (*c) (void)hipEventDestroy(*c);
         }
-    } mid_events{s, &mfork, &mjoin, &mid_pending};
+    } mid_events{s, &mfork, &mjoin, &mcls, &mid_pending};
     if (mid_side) {
         hipStream_t s2 = side_stream();
         SKIS_HIP_TRY(hipEventCreateWithFlags(&mfork, hipEventDisableTiming));
         SKIS_HIP_TRY(hipEventCreateWithFlags(&mjoin, hipEventDisableTiming));
+        SKIS_HIP_TRY(hipEventCreateWithFlags(&mcls, hipEventDisableTiming));
         SKIS_HIP_TRY(hipEventRecord(mfork, s));
         hipError_t e = hipStreamWaitEvent(s2, mfork, 0);
         if (e == hipSuccess) {
@@ -2293,9 +2299,7 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
         mid_err = e;
     }
     {
-        // samples by size class, then one segmented sort per class
-        DevBuf<unsigned long long> cls;
-        DevBuf<uint32_t> lists;
+        // one segmented sort per class
         cls.alloc(arena, 2 * GATHER_CLASSES);
         lists.alloc(arena, count);
         hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(1), dim3(64), 0, s, (uint64_t)(2 * GATHER_CLASSES),
@@ -2307,6 +2311,20 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
         const unsigned gg = grid_cap(count, 8, 64);
         const uint32_t *const sz_p = out_size.ptr;
         const unsigned long long *const off_p = out_off.ptr;
+        bool last_class_side = false;
+        if (mid_pending) {
+            hipStream_t s2 = side_stream();
+            SKIS_HIP_TRY(hipEventRecord(mcls, s));
+            SKIS_HIP_TRY(hipStreamWaitEvent(s2, mcls, 0));
+            hipLaunchKernelGGL((k_gather_sort<64, 16>), dim3(gg), dim3(64), 0, s2, 7, cls.ptr, lists.ptr, sz_p, off_p,
+                               sk.sample_ptr.ptr, staging.ptr, sk.nodes.ptr, owner_p);
+            const hipError_t e7 = hipGetLastError();
+            const hipError_t rec = hipEventRecord(mjoin, s2); // the join now follows this class too
+            if (rec != hipSuccess) (void)hipStreamSynchronize(s2);
+            SKIS_HIP_TRY(rec);
+            if (mid_err == hipSuccess) mid_err = e7;
+            last_class_side = true;
+        }
         hipLaunchKernelGGL((k_gather_sort<8, 1>), dim3(gg), dim3(64), 0, s, 0, cls.ptr, lists.ptr, sz_p, off_p,
                            sk.sample_ptr.ptr, staging.ptr, sk.nodes.ptr, owner_p);
         hipLaunchKernelGGL((k_gather_sort<16, 1>), dim3(gg), dim3(64), 0, s, 1, cls.ptr, lists.ptr, sz_p, off_p,
@@ -2321,8 +2339,9 @@ void sample_and_compact(Arena &arena, const Prep &prep, int32_t n, int64_t m, ui
                            sk.sample_ptr.ptr, staging.ptr, sk.nodes.ptr, owner_p);
         hipLaunchKernelGGL((k_gather_sort<64, 8>), dim3(gg), dim3(64), 0, s, 6, cls.ptr, lists.ptr, sz_p, off_p,
                            sk.sample_ptr.ptr, staging.ptr, sk.nodes.ptr, owner_p);
-        hipLaunchKernelGGL((k_gather_sort<64, 16>), dim3(gg), dim3(64), 0, s, 7, cls.ptr, lists.ptr, sz_p, off_p,
-                           sk.sample_ptr.ptr, staging.ptr, sk.nodes.ptr, owner_p);
+        if (!last_class_side)
+            hipLaunchKernelGGL((k_gather_sort<64, 16>), dim3(gg), dim3(64), 0, s, 7, cls.ptr, lists.ptr, sz_p, off_p,
+                               sk.sample_ptr.ptr, staging.ptr, sk.nodes.ptr, owner_p);
         SKIS_HIP_TRY(hipGetLastError());
     }
     if (mid_pending) {
