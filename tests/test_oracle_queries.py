@@ -144,6 +144,12 @@ def test_inverse_index_is_transpose():
             assert v in set(sk.sample(int(j)).tolist())
     cnt = np.bincount(sk.nodes, minlength=g.n)
     assert np.array_equal(np.diff(node_ptr), cnt)
+    # every entry: the (node, sample) pairs of the sketch, ordered by node then sample with a
+    # numpy sort, are the inverse lists in order
+    sizes = np.diff(np.asarray(sk.sample_ptr, np.int64))
+    owner = np.repeat(np.arange(len(sizes), dtype=np.int64), sizes)
+    order = np.lexsort((owner, np.asarray(sk.nodes, np.int64)))
+    assert np.array_equal(np.asarray(ns, np.int64), owner[order])
 
 
 def _naive_greedy(n, samples, q, Gamma, T, k):
